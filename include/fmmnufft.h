@@ -1,0 +1,145 @@
+/*
+ * fmmnufft.h -- C ABI of the MI355X (gfx950) FMM-based NUFFT / INUFFT.
+ *
+ * Method: N. A. Gumerov and R. Duraiswami, "Fast Multipole Method based
+ * filtering of non-uniformly sampled data" (arXiv:1611.09379).
+ *
+ * Problems (Section 2).  A 2 pi-periodic band-limited function
+ *     f(x) = sum_{n=0}^{N-1} c_n e^{inx}                       (Eq. p1)
+ * is sampled at the N equispaced points x_k = 2 pi k / N, f_k = f(x_k).
+ *   (i)  forward:  given f_k, find g_j = f(y_j) at M arbitrary points y_j;
+ *        g = K f with K_jk = (1/N) sum_n e^{-i n x_k} e^{i n y_j}  (Eq. p2)
+ *        = F_j G(y_j - x_k), F_j = (e^{iNy_j} - 1)/N,
+ *        G(t) = 1/(e^{it} - 1) = -(1 + i cot(t/2))/2           (Eq. p4-p5)
+ *  (ii)  inverse (M = N): given g_j at the y_j, find f_k;
+ *        f = L g, L_kj = C_k G(x_k - y_j) D_j                   (Eq. p6)
+ *        with C_k, D_j the products of sines of Eq. (p8).
+ * Both reduce to the matrix-vector product with the kernel cot(t/2), which
+ * the library evaluates with the multilevel FMM of Section 2.1-2.4 on the
+ * circular binary tree; C_k and D_j come from the same FMM applied to the
+ * kernel log|2 sin(t/2)| (the logarithms of the products of Eq. p8).
+ *
+ * Conventions shared by every entry point:
+ *   - Every array argument is DEVICE memory (hipMalloc / a PyTorch CUDA
+ *     tensor) owned by the caller; the library never frees it.  y is always
+ *     binary64 radians.  f and g are interleaved complex (re, im): binary64
+ *     pairs for FN_C128, binary32 pairs for FN_C64.
+ *   - y may hold any finite value with |y| <= FN_Y_MAX; it is reduced modulo
+ *     2 pi exactly (in grid units N y / 2 pi, formed in double-double).
+ *   - Outputs are in the order of the inputs (g_j in the order of y_j, f_k
+ *     for k = 0..N-1).
+ *   - eps is the target relative l2 error ||out - exact|| / ||exact||.  It
+ *     sets the truncation numbers p, q and the tree depth (Eq. 18, 18.2, 25).
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; a call returns when the work is enqueued,
+ *     except where noted ("synchronises").
+ *   - Every function returns an fn_status.  Nothing throws.  On a non-OK
+ *     status nufft_last_error() returns a message (thread-local, valid until
+ *     the next call on the same thread).  Scalar argument errors are
+ *     reported before any GPU work is enqueued.
+ */
+#ifndef FMMNUFFT_H
+#define FMMNUFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FN_OK = 0,
+    FN_EINVAL = 1,    /* bad scalar argument, NULL pointer, non-finite or
+                         out-of-range y                                    */
+    FN_ENOMEM = 2,    /* device workspace allocation failed                */
+    FN_EHIP = 3,      /* a HIP runtime call failed (message has details)   */
+    FN_ESINGULAR = 4, /* inverse: two y_j coincide on the circle            */
+    FN_ERANGE = 5,    /* inverse: |C_k| or |D_j| leaves the binary64 range
+                         (the point set is too ill-conditioned)            */
+    FN_EPREC = 6      /* eps below what the precision path can deliver     */
+} fn_status;
+
+typedef enum {
+    FN_C128 = 0, /* binary64 throughout                                    */
+    FN_C64 = 1   /* mixed: binary32 data, expansions and translations;
+                    binary64 phase reduction, near-field differences and
+                    the log-sums of the inverse                           */
+} fn_dtype;
+
+/* Largest accepted |y| (radians). */
+#define FN_Y_MAX 1024.0
+
+typedef struct fn_plan fn_plan;
+
+/* Parameters a plan uses (for reporting and tests). */
+typedef struct {
+    int64_t N, M;
+    int32_t kind;  /* 0 forward, 1 inverse                                */
+    int32_t dtype; /* fn_dtype                                            */
+    int32_t p;     /* multipole / local expansion terms of the 1/t FMM    */
+    int32_t q;     /* Bernoulli terms of the regular part (Eq. 10, 11)    */
+    int32_t lmax;  /* finest tree level (2^lmax leaves)                   */
+    int32_t nterms;/* terms stored per expansion (>= p and >= 2q)         */
+    double eps;
+} fn_plan_info;
+
+/* Forward interpolation (problem i): g_j = sum_k K_jk f_k, Eq. (p2).
+ * y: M doubles; f: N complex; g: M complex (written).  N >= 1, M >= 1,
+ * N, M < 2^31.  One-shot: plan + execute + destroy; synchronises the stream
+ * once (to size the tree). */
+int nufft_fwd(int64_t N, int64_t M, const double *y, const void *f, void *g,
+              double eps, int dtype, void *stream);
+
+/* Inverse interpolation (problem ii, M = N): f = L g, Eq. (p6)/(p8).
+ * y: N doubles, pairwise distinct modulo 2 pi; g: N complex; f: N complex
+ * (written).  One-shot; synchronises the stream. */
+int inufft(int64_t N, const double *y, const void *g, void *f, double eps,
+           int dtype, void *stream);
+
+/* Setup step of Section 3.3 ("setting the data structure"): everything that
+ * depends on the points only.  Forward plan: reduction of y to grid units
+ * and the sort of the targets into the leaves of the tree.  Inverse plan:
+ * the same for the sources y_j, plus C_k and D_j of Eq. (p8) by the
+ * log-kernel FMM.  The plan owns its device workspace, allocated here.
+ * Synchronises the stream.  y is read during the call only. */
+int nufft_plan_fwd(fn_plan **plan, int64_t N, int64_t M, const double *y,
+                   double eps, int dtype, void *stream);
+int nufft_plan_inv(fn_plan **plan, int64_t N, const double *y, double eps,
+                   int dtype, void *stream);
+
+/* Evaluation step of Section 3.3: out = K in (forward plan) or out = L in
+ * (inverse plan).  in/out sizes: forward N -> M, inverse N -> N, complex of
+ * the plan's dtype.  Enqueues kernels only: no allocation, no
+ * synchronisation. */
+int nufft_execute(fn_plan *plan, const void *in, void *out, void *stream);
+
+/* Releases the plan and its workspace (NULL is accepted).  Synchronises the
+ * device. */
+int nufft_destroy(fn_plan *plan);
+
+/* Reports the parameters of a plan. */
+int nufft_plan_get_info(const fn_plan *plan, fn_plan_info *info);
+
+/* Parameters the library would choose for (N, M, eps, dtype): the
+ * truncation numbers of Eq. (18.2) and the depth of Eq. (25).  Host only;
+ * no GPU work.  Any output pointer may be NULL. */
+int nufft_select_params(int64_t N, int64_t M, double eps, int dtype,
+                        int32_t *p, int32_t *q, int32_t *lmax);
+
+/* Like nufft_plan_fwd / nufft_plan_inv with p, q and lmax given explicitly
+ * (values <= 0 mean "choose as nufft_select_params").  For tuning and tests. */
+int nufft_plan_fwd_ex(fn_plan **plan, int64_t N, int64_t M, const double *y,
+                      double eps, int dtype, int32_t p, int32_t q,
+                      int32_t lmax, void *stream);
+int nufft_plan_inv_ex(fn_plan **plan, int64_t N, const double *y, double eps,
+                      int dtype, int32_t p, int32_t q, int32_t lmax,
+                      void *stream);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char *nufft_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMMNUFFT_H */

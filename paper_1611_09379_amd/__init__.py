@@ -1,0 +1,222 @@
+"""MI355X (gfx950) FMM-based NUFFT / INUFFT of Gumerov & Duraiswami.
+
+Thin ctypes binding over libfmmnufft.so (C ABI in include/fmmnufft.h).  It
+only marshals arguments: every step of the transforms runs in the library's
+HIP kernels.  Tensors are PyTorch CUDA tensors (ROCm): y float64, data
+complex128 (plain FP64 path) or complex64 (mixed path).  If the library is
+missing, importing the binding's functions raises: there is no fallback.
+
+    g = nufft_fwd(y, f, eps)        # forward, Eq. (p2): g_j = f(y_j)
+    f = inufft(y, g, eps)           # inverse, Eq. (p6), M = N
+    plan = Plan.forward(N, y, eps)  # setup once per point set (Section 3.3)
+    g = plan(f)                     # evaluation, repeated per input
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfmmnufft.so")
+
+FN_OK, FN_EINVAL, FN_ENOMEM, FN_EHIP, FN_ESINGULAR, FN_ERANGE, FN_EPREC = range(7)
+FN_C128, FN_C64 = 0, 1
+STATUS_NAMES = {0: "FN_OK", 1: "FN_EINVAL", 2: "FN_ENOMEM", 3: "FN_EHIP",
+                4: "FN_ESINGULAR", 5: "FN_ERANGE", 6: "FN_EPREC"}
+
+ABI_SYMBOLS = (
+    "nufft_fwd", "inufft", "nufft_plan_fwd", "nufft_plan_inv",
+    "nufft_plan_fwd_ex", "nufft_plan_inv_ex", "nufft_execute",
+    "nufft_destroy", "nufft_plan_get_info", "nufft_select_params",
+    "nufft_last_error",
+)
+
+
+class NufftError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("M", ctypes.c_int64),
+                ("kind", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("p", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("lmax", ctypes.c_int32), ("nterms", ctypes.c_int32),
+                ("eps", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libfmmnufft.so and declares the C signatures.  Raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it first "
+            "(python -m paper_1611_09379_amd.build); there is no fallback path")
+    lib = ctypes.CDLL(path)
+    i64, i32, dbl, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    pi32 = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "nufft_fwd": [i64, i64, vp, vp, vp, dbl, ctypes.c_int, vp],
+        "inufft": [i64, vp, vp, vp, dbl, ctypes.c_int, vp],
+        "nufft_plan_fwd": [pp, i64, i64, vp, dbl, ctypes.c_int, vp],
+        "nufft_plan_inv": [pp, i64, vp, dbl, ctypes.c_int, vp],
+        "nufft_plan_fwd_ex": [pp, i64, i64, vp, dbl, ctypes.c_int, i32, i32, i32, vp],
+        "nufft_plan_inv_ex": [pp, i64, vp, dbl, ctypes.c_int, i32, i32, i32, vp],
+        "nufft_execute": [vp, vp, vp, vp],
+        "nufft_destroy": [vp],
+        "nufft_plan_get_info": [vp, ctypes.POINTER(PlanInfo)],
+        "nufft_select_params": [i64, i64, dbl, ctypes.c_int, pi32, pi32, pi32],
+        "nufft_last_error": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name == "nufft_last_error" else ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != FN_OK:
+        msg = load_library().nufft_last_error().decode(errors="replace")
+        raise NufftError(status, msg)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.complex128:
+        return FN_C128
+    if t.dtype == torch.complex64:
+        return FN_C64
+    raise TypeError(f"data must be complex128 or complex64, got {t.dtype}")
+
+
+def _dev_ptr(t, name):
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_y(y):
+    torch = _torch()
+    if y.dtype != torch.float64 or y.dim() != 1:
+        raise TypeError("y must be a 1-D float64 tensor (radians)")
+
+
+def select_params(N: int, M: int, eps: float, dtype: int = FN_C128):
+    """(p, q, lmax) the library chooses: Eq. (18.2) and Eq. (25)."""
+    p, q, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().nufft_select_params(N, M, eps, dtype, ctypes.byref(p),
+                                              ctypes.byref(q), ctypes.byref(l)))
+    return p.value, q.value, l.value
+
+
+class Plan:
+    """A plan: the setup step (points only) of Section 3.3."""
+
+    def __init__(self, handle, kind: int, N: int, M: int, dtype: int):
+        self._h = handle
+        self.kind, self.N, self.M, self.dtype = kind, N, M, dtype
+
+    @classmethod
+    def forward(cls, N: int, y, eps: float, dtype: int = FN_C128,
+                p: int = 0, q: int = 0, lmax: int = 0):
+        _check_y(y)
+        h = ctypes.c_void_p()
+        _check(load_library().nufft_plan_fwd_ex(
+            ctypes.byref(h), N, y.shape[0], _dev_ptr(y, "y"), eps, dtype,
+            p, q, lmax, _stream()))
+        return cls(h, 0, N, y.shape[0], dtype)
+
+    @classmethod
+    def inverse(cls, y, eps: float, dtype: int = FN_C128, p: int = 0,
+                q: int = 0, lmax: int = 0):
+        _check_y(y)
+        h = ctypes.c_void_p()
+        N = y.shape[0]
+        _check(load_library().nufft_plan_inv_ex(
+            ctypes.byref(h), N, _dev_ptr(y, "y"), eps, dtype, p, q, lmax,
+            _stream()))
+        return cls(h, 1, N, N, dtype)
+
+    def info(self) -> PlanInfo:
+        out = PlanInfo()
+        _check(load_library().nufft_plan_get_info(self._h, ctypes.byref(out)))
+        return out
+
+    def execute(self, x, out=None):
+        torch = _torch()
+        if self._h is None:
+            raise RuntimeError("plan was destroyed")
+        if _dtype_code(x) != self.dtype:
+            raise TypeError("input dtype does not match the plan")
+        n_in = self.N
+        n_out = self.M if self.kind == 0 else self.N
+        if x.shape != (n_in,):
+            raise ValueError(f"input must have shape ({n_in},)")
+        if out is None:
+            out = torch.empty(n_out, dtype=x.dtype, device=x.device)
+        elif out.shape != (n_out,) or out.dtype != x.dtype:
+            raise ValueError("bad output tensor")
+        _check(load_library().nufft_execute(self._h, _dev_ptr(x, "input"),
+                                            _dev_ptr(out, "output"), _stream()))
+        return out
+
+    __call__ = execute
+
+    def destroy(self):
+        if self._h is not None:
+            _check(load_library().nufft_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def nufft_fwd(y, f, eps: float, out=None):
+    """g_j = sum_k K_jk f_k (Eq. p2) at the points y (radians), one shot."""
+    torch = _torch()
+    _check_y(y)
+    dt = _dtype_code(f)
+    N, M = f.shape[0], y.shape[0]
+    if out is None:
+        out = torch.empty(M, dtype=f.dtype, device=f.device)
+    _check(load_library().nufft_fwd(N, M, _dev_ptr(y, "y"), _dev_ptr(f, "f"),
+                                    _dev_ptr(out, "g"), eps, dt, _stream()))
+    return out
+
+
+def inufft(y, g, eps: float, out=None):
+    """f = L g (Eq. p6), M = N, one shot."""
+    torch = _torch()
+    _check_y(y)
+    dt = _dtype_code(g)
+    N = y.shape[0]
+    if g.shape != (N,):
+        raise ValueError("g must have the shape of y (M = N)")
+    if out is None:
+        out = torch.empty(N, dtype=g.dtype, device=g.device)
+    _check(load_library().inufft(N, _dev_ptr(y, "y"), _dev_ptr(g, "g"),
+                                 _dev_ptr(out, "f"), eps, dt, _stream()))
+    return out

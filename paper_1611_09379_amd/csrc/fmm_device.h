@@ -1,0 +1,90 @@
+// Device-side building blocks of the circular-tree FMM (gfx950).
+//
+// Geometry is kept in grid units: a point y in radians is s = N y / (2 pi),
+// stored as an exact integer part m and a binary64 fraction th in
+// [-1/2, 1/2], with the representative s = m + th in [0, N) (m may equal N
+// when th < 0).  The uniform points x_k = 2 pi k / N are s = k.  Level L of
+// the binary tree (Section 2.1) splits [0, N) into 2^L equal arcs; box b of
+// level L has centre c = (b + 1/2) N / 2^L and half-width r = N / 2^(L+1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fn {
+
+template <typename R>
+struct cx {
+    R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// First multipole / local coefficient of level L in the packed per-level
+// arrays (levels 2..lmax, 2^L boxes each).
+__host__ __device__ __forceinline__ int64_t lev_off(int L, int P)
+{
+    return ((int64_t(1) << L) - 4) * (int64_t)P;
+}
+
+// floor((m + th) 2^L / N): the level-L box of the point s = m + th.
+__device__ __forceinline__ int64_t box_of(int64_t m, double th, int L,
+                                          int64_t N)
+{
+    int64_t A = m << L;
+    int64_t q0 = A / N;
+    double t = (double)(A - q0 * N) + ldexp(th, L);
+    q0 += (int64_t)floor(t / (double)N);
+    int64_t nb = int64_t(1) << L;
+    return q0 < 0 ? 0 : (q0 >= nb ? nb - 1 : q0);
+}
+
+// (s - c) / r for the point s = m + th and box b of level L.
+__device__ __forceinline__ double rel_coord(int64_t m, double th, int64_t b,
+                                            int L, int64_t N)
+{
+    int64_t num = (m << (L + 1)) - (2 * b + 1) * N;
+    return ((double)num + ldexp(th, L + 1)) / (double)N;
+}
+
+// First uniform point k of box b at level L: ceil(b N / 2^L).
+__device__ __forceinline__ int64_t uni_start(int64_t b, int L, int64_t N)
+{
+    return (b * N + (int64_t(1) << L) - 1) >> L;
+}
+
+// Integer power by squaring (v^e, e >= 0).
+template <typename R>
+__device__ __forceinline__ R ipow(R v, int e)
+{
+    R r = R(1);
+    while (e) {
+        if (e & 1)
+            r *= v;
+        v *= v;
+        e >>= 1;
+    }
+    return r;
+}
+
+// d = n + (a - b) with one rounding (a, b in [-1/2, 1/2]); the difference
+// a - b is carried as an exact two-term sum.
+__device__ __forceinline__ double grid_diff(int64_t n, double a, double b)
+{
+    double hi = a - b;
+    double bb = hi - a;
+    double lo = (a - (hi - bb)) + (-b - bb);
+    return ((double)n + hi) + lo;
+}
+
+// Antiderivative of log|u|: u log|u| - u (0 at u = 0).
+__device__ __forceinline__ double xlogx_m_x(double u)
+{
+    return u == 0.0 ? 0.0 : u * log(fabs(u)) - u;
+}
+
+} // namespace fn

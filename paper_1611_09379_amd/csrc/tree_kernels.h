@@ -1,0 +1,186 @@
+// Setup step ("setting the data structure", Section 3.3): reduction of the
+// points to grid units, the sort of the points into the leaves of the
+// circular binary tree (Section 2.1), and for the inverse the assembly of
+// C_k and D_j of Eq. (p8) from their log-sums.
+#pragma once
+
+#include "fmm_device.h"
+
+namespace fn {
+
+enum { FLAG_BAD_Y = 1, FLAG_DUP = 2, FLAG_RANGE = 4 };
+
+// y -> (m, th, leaf).  s = y N / (2 pi) is formed in double-double from the
+// double-double constant N/(2 pi) = c_hi + c_lo; m = nearest integer mod N,
+// th = s - nearest integer in [-1/2, 1/2]; the representative in [0, N)
+// uses m = N when m = 0 and th < 0.  Counts the points of every leaf and, if
+// hit is given, records the index of a point that lies exactly on x_m.
+__global__ void k_reduce(int64_t M, const double *__restrict__ y, double c_hi,
+                         double c_lo, int64_t N, int l, double ymax,
+                         int32_t *um, double *uth, int32_t *ukey,
+                         int32_t *count, int32_t *hit, int *flags)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < M;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        double yy = y[j];
+        if (!(fabs(yy) <= ymax)) { // also catches NaN
+            atomicOr(flags, FLAG_BAD_Y);
+            um[j] = 0;
+            uth[j] = 0.25;
+            ukey[j] = 0;
+            atomicAdd(&count[0], 1);
+            continue;
+        }
+        double p = yy * c_hi;
+        double e = fma(yy, c_hi, -p);
+        e = fma(yy, c_lo, e);
+        double n = rint(p);
+        double th = (p - n) + e;
+        if (th > 0.5) {
+            th -= 1.0;
+            n += 1.0;
+        } else if (th < -0.5) {
+            th += 1.0;
+            n -= 1.0;
+        }
+        int64_t m = (int64_t)n % N;
+        if (m < 0)
+            m += N;
+        if (m == 0 && th < 0.0)
+            m = N;
+        int64_t key = box_of(m, th, l, N);
+        um[j] = (int32_t)m;
+        uth[j] = th;
+        ukey[j] = (int32_t)key;
+        atomicAdd(&count[key], 1);
+        if (hit && th == 0.0)
+            atomicExch(&hit[m], (int32_t)j);
+    }
+}
+
+// Exclusive scan of the leaf counts (one workgroup of 1024 threads).
+__global__ void __launch_bounds__(1024)
+    k_scan(const int32_t *count, int32_t *off, int32_t *cursor, int64_t n)
+{
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t b0 = tid * per;
+    const int64_t b1 = b0 + per < n ? b0 + per : n;
+    int64_t s = 0;
+    for (int64_t i = b0; i < b1; ++i)
+        s += count[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        int64_t v = tid >= d ? part[tid - d] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = tid == 0 ? 0 : part[tid - 1];
+    for (int64_t i = b0; i < b1; ++i) {
+        off[i] = (int32_t)run;
+        if (cursor)
+            cursor[i] = (int32_t)run;
+        run += count[i];
+    }
+    if (tid == 1023)
+        off[n] = (int32_t)part[1023];
+}
+
+// Counting-sort scatter: each point takes the next slot of its leaf.  The
+// order inside a leaf is arbitrary (the forward results do not depend on it).
+__global__ void k_scatter(int64_t M, const int32_t *um, const double *uth,
+                          const int32_t *ukey, int32_t *cursor, int32_t *sm,
+                          double *sth, int32_t *sperm, int32_t *skey)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < M;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        int32_t key = ukey[j];
+        int32_t pos = atomicAdd(&cursor[key], 1);
+        sm[pos] = um[j];
+        sth[pos] = uth[j];
+        sperm[pos] = (int32_t)j;
+        if (skey)
+            skey[pos] = key;
+    }
+}
+
+// Orders the points of every leaf by position (so the whole set is sorted
+// along the circle); two points at the same position raise FLAG_DUP.
+__global__ void k_rank(int64_t n, const int32_t *gm, const double *gth,
+                       const int32_t *gperm, const int32_t *gkey,
+                       const int32_t *off, int32_t *sm, double *sth,
+                       int32_t *sperm, int *flags)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = gkey[t];
+        const int32_t t0 = off[b], t1 = off[b + 1];
+        const int32_t mt = gm[t];
+        const double tht = gth[t];
+        int32_t rank = 0;
+        for (int32_t u = t0; u < t1; ++u) {
+            if (u == t)
+                continue;
+            double d = grid_diff((int64_t)gm[u] - mt, gth[u], tht);
+            if (d < 0.0)
+                ++rank;
+            else if (d == 0.0) {
+                atomicOr(flags, FLAG_DUP);
+                if (u < t)
+                    ++rank;
+            }
+        }
+        const int32_t pos = t0 + rank;
+        sm[pos] = mt;
+        sth[pos] = tht;
+        sperm[pos] = gperm[t];
+    }
+}
+
+// Eq. (p8), rescaled by 2^N (the scale cancels in C_k D_j):
+//   Chat_k = (-1)^k prod_j 2 sin((x_k - y_j)/2)
+//          = (-1)^(k + #{j: s_j > k}) exp(logC_k),
+//   Dhat_j = i e^{-i N y_j / 2} / prod_{i != j} 2 sin((y_j - y_i)/2)
+//          = i (-1)^(m_j) e^{-i pi th_j} (-1)^(#{i: s_i > s_j}) exp(logD_j),
+// with the points sorted along the circle, so #{i: s_i > s_j} = N - 1 - rank.
+__global__ void k_coeffs(int64_t N, const double *logc, const double *logd,
+                         const int32_t *sm, const double *sth,
+                         const int32_t *hit, double *chat, cx<double> *dhat,
+                         int *flags)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < N;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        // #{j : s_j <= k} by binary search over the sorted positions
+        int64_t lo = 0, hi = N;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            bool le = sm[mid] < k || (sm[mid] == k && sth[mid] <= 0.0);
+            if (le)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        const int64_t neg = N - lo;
+        const double lc = logc[k];
+        if (hit[k] >= 0) {
+            chat[k] = 0.0;
+        } else {
+            if (!(fabs(lc) <= 700.0))
+                atomicOr(flags, FLAG_RANGE);
+            chat[k] = (((k + neg) & 1) ? -1.0 : 1.0) * exp(lc);
+        }
+        // Dhat for the k-th point in sorted order
+        const double ld = logd[k];
+        if (!(fabs(ld) <= 700.0))
+            atomicOr(flags, FLAG_RANGE);
+        const int64_t negd = N - 1 - k;
+        const double sg = (((sm[k] + negd) & 1) ? -1.0 : 1.0) * exp(ld);
+        const double th = sth[k];
+        dhat[k] = {sg * sinpi(th), sg * cospi(th)};
+    }
+}
+
+} // namespace fn

@@ -1,0 +1,59 @@
+"""The C-ABI library loads on the host, exports every symbol of
+include/fmmnufft.h, and rejects bad scalar arguments before any GPU work.
+Host logic: the truncation numbers of Eq. (18.2) and the depth of Eq. (25)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1611_09379_amd as fn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "fmmnufft.h")).read()
+    return set(re.findall(r"^\s*(?:int|const char \*)\s*(\w+)\s*\(", txt, re.M))
+
+
+def test_exports_every_header_symbol():
+    lib = fn.load_library()
+    syms = header_symbols()
+    assert syms == set(fn.ABI_SYMBOLS)
+    for s in syms:
+        assert getattr(lib, s) is not None
+
+
+def test_scalar_errors_before_gpu_work():
+    lib = fn.load_library()
+    h = ctypes.c_void_p()
+    y = ctypes.c_void_p(1)  # never dereferenced: the checks come first
+    assert lib.nufft_plan_fwd(ctypes.byref(h), 0, 5, y, 1e-12, 0, None) == fn.FN_EINVAL
+    assert lib.nufft_plan_fwd(ctypes.byref(h), 5, 0, y, 1e-12, 0, None) == fn.FN_EINVAL
+    assert lib.nufft_plan_fwd(ctypes.byref(h), 5, 5, y, float("nan"), 0, None) == fn.FN_EINVAL
+    assert lib.nufft_plan_fwd(ctypes.byref(h), 5, 5, y, 1e-12, 7, None) == fn.FN_EINVAL
+    assert lib.nufft_plan_fwd(ctypes.byref(h), 5, 5, y, 1e-17, 0, None) == fn.FN_EPREC
+    assert lib.nufft_plan_fwd(ctypes.byref(h), 5, 5, y, 1e-9, 1, None) == fn.FN_EPREC
+    assert lib.nufft_plan_fwd(ctypes.byref(h), 5, 5, None, 1e-12, 0, None) == fn.FN_EINVAL
+    assert b"NULL" in lib.nufft_last_error()
+    assert lib.nufft_execute(None, y, y, None) == fn.FN_EINVAL
+    assert lib.nufft_destroy(None) == fn.FN_OK
+    assert lib.nufft_fwd(5, 5, y, None, y, 1e-12, 0, None) == fn.FN_EINVAL
+
+
+def load_golden(name):
+    rows = []
+    for line in open(os.path.join(ROOT, "tests", "golden", name)):
+        line = line.split("#")[0].strip()
+        if line:
+            rows.append(line.split())
+    return rows
+
+
+def test_truncation_numbers_eq_18_2():
+    """q and p of Eq. (18.2) (the larger of the printed fraction and the one
+    that balances Eq. 18), depth from Eq. (25) with the paper's offset."""
+    for row in load_golden("eq18_params.txt"):
+        eps, N, q, p, l = float(row[0]), int(row[1]), int(row[2]), int(row[3]), int(row[4])
+        assert fn.select_params(N, N, eps) == (p, q, l), row

@@ -1,0 +1,150 @@
+"""Forward transform on the GPU against the CPU oracle (Eq. p2 / p4).
+
+Tolerances: the stated relative l2 targets (1e-12 for the plain FP64 path,
+1e-6 for the mixed path), at sizes that span several tree levels, leaves and
+ragged tails, plus sampled targets at 2^20."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import dev, host, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+fn = pytest.importorskip("paper_1611_09379_amd")
+
+
+def run_fwd(N, y, f, eps, dtype=np.complex128, **kw):
+    say(f"fwd N={N} M={y.shape[0]} eps={eps} dtype={np.dtype(dtype).name} {kw}")
+    fd = dev(f.astype(dtype))
+    yd = dev(y)
+    if kw:
+        plan = fn.Plan.forward(N, yd, eps, fn.FN_C128 if dtype == np.complex128 else fn.FN_C64, **kw)
+        g = plan(fd)
+        out = host(g)
+        plan.destroy()
+        return out
+    return host(fn.nufft_fwd(yd, fd, eps))
+
+
+@pytest.mark.parametrize("N,M,dist", [(1024, 1024, "uniform"),
+                                      (1000, 777, "uniform"),
+                                      (3000, 5001, "uniform"),
+                                      (4096, 8192, "clustered"),
+                                      (1024, 3000, "clustered")])
+def test_fwd_fp64_full(N, M, dist):
+    y, f, c = workloads.forward_case(N, M, dist, seed=0)
+    g = run_fwd(N, y, f, 1e-12)
+    ref = oracle.fwd(N, y, f)
+    err = rel_l2(g, ref)
+    say("rel l2", err)
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 8, 17, 64, 255])
+def test_fwd_tiny(N):
+    rng = np.random.default_rng(N)
+    y = workloads.points_uniform(33, rng)
+    f = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    g = run_fwd(N, y, f, 1e-12)
+    assert rel_l2(g, oracle.fwd(N, y, f)) < 1e-12
+
+
+@pytest.mark.parametrize("lmax", [2, 3, 4, 6, 9])
+def test_fwd_depths(lmax):
+    N, M = 2048, 1500
+    y, f, c = workloads.forward_case(N, M, "uniform", seed=lmax)
+    g = run_fwd(N, y, f, 1e-12, lmax=lmax)
+    assert rel_l2(g, oracle.fwd(N, y, f)) < 1e-12
+
+
+def test_fwd_constant_and_hits():
+    """Section 3.1: f = 1 gives g = 1; exact and near hits of the grid."""
+    N = 4096
+    rng = np.random.default_rng(3)
+    y = np.concatenate([workloads.points_uniform(5000, rng),
+                        [0.0, 2 * np.pi * 7 / N, 2 * np.pi * 4095 / N,
+                         np.nextafter(2 * np.pi, 0), -1e-300, 2 * np.pi * 1e-15]])
+    g = run_fwd(N, y, np.ones(N), 1e-12)
+    assert np.abs(g - 1).max() < 1e-12
+    f = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    g = run_fwd(N, y, f, 1e-12)
+    ref = oracle.fwd(N, y, f)
+    assert rel_l2(g, ref) < 1e-12
+    assert g[5000] == f[0]
+    assert np.abs(g - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_fwd_single_frequency():
+    N, n0 = 8192, 1234
+    rng = np.random.default_rng(11)
+    c = np.zeros(N, complex)
+    c[n0] = 1.0
+    y = workloads.points_uniform(4000, rng)
+    g = run_fwd(N, y, workloads.samples_from_coefficients(c), 1e-12)
+    assert rel_l2(g, np.exp(1j * n0 * y)) < 1e-12
+
+
+@pytest.mark.parametrize("N,M,dist", [(4096, 4096, "uniform"),
+                                      (8192, 5000, "clustered")])
+def test_fwd_mixed(N, M, dist):
+    y, f, c = workloads.forward_case(N, M, dist, seed=1)
+    f32 = f.astype(np.complex64)
+    g = run_fwd(N, y, f32, 1e-6, dtype=np.complex64)
+    ref = oracle.fwd(N, y, f32.astype(np.complex128))
+    err = rel_l2(g, ref)
+    say("mixed rel l2", err, "vs complex128 input", rel_l2(g, oracle.fwd(N, y, f)))
+    assert err < 1e-6
+
+
+def test_plan_reuse():
+    N, M = 5000, 6000
+    y, f, c = workloads.forward_case(N, M, "uniform", seed=2)
+    yd = dev(y)
+    plan = fn.Plan.forward(N, yd, 1e-12)
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        f = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        g = host(plan(dev(f)))
+        assert rel_l2(g, oracle.fwd(N, y, f)) < 1e-12
+    info = plan.info()
+    assert info.N == N and info.M == M and info.lmax >= 2
+    plan.destroy()
+
+
+@pytest.mark.parametrize("dist,dtype,eps", [("uniform", np.complex128, 1e-12),
+                                            ("clustered", np.complex128, 1e-12),
+                                            ("clustered", np.complex64, 1e-6),
+                                            ("uniform", np.complex64, 1e-6)])
+def test_fwd_2p20_sampled(dist, dtype, eps):
+    """Full size (N = M = 2^20), checked on 1024 targets against the oracle."""
+    N = M = 1 << 20
+    y, f, c = workloads.forward_case(N, M, dist, seed=0)
+    fin = f.astype(dtype)
+    g = run_fwd(N, y, fin, eps, dtype=dtype)
+    rng = np.random.default_rng(5)
+    sel = rng.choice(M, 1024, replace=False)
+    ref = oracle.fwd_at(N, y, fin.astype(np.complex128), sel)
+    err = rel_l2(g[sel], ref)
+    say(dist, np.dtype(dtype).name, "sampled rel l2", err)
+    assert err < eps
+    # f = 1 at full size: g = 1 everywhere (Section 3.1)
+    g1 = run_fwd(N, y, np.ones(N, dtype=dtype), eps, dtype=dtype)
+    assert np.abs(g1 - 1).max() < 10 * eps
+
+
+def test_errors():
+    import torch
+    y = dev(np.array([0.1, np.nan, 0.3]))
+    f = dev(np.ones(8, complex))
+    with pytest.raises(fn.NufftError) as e:
+        fn.nufft_fwd(y, f, 1e-12)
+    assert e.value.status == fn.FN_EINVAL
+    y = dev(np.array([0.1, 0.2]))
+    with pytest.raises(fn.NufftError) as e:
+        fn.nufft_fwd(y, f, 1e-20)
+    assert e.value.status == fn.FN_EPREC
+    with pytest.raises(fn.NufftError) as e:
+        fn.nufft_fwd(y, f.to(torch.complex64), 1e-9)
+    assert e.value.status == fn.FN_EPREC

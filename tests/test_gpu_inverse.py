@@ -1,0 +1,98 @@
+"""Inverse transform (M = N) on the GPU against the CPU oracle (Eq. p6/p8)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import dev, host, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+fn = pytest.importorskip("paper_1611_09379_amd")
+
+
+def run_inv(y, g, eps, dtype=np.complex128):
+    say(f"inv N={y.shape[0]} eps={eps} dtype={np.dtype(dtype).name}")
+    return host(fn.inufft(dev(y), dev(g.astype(dtype)), eps))
+
+
+@pytest.mark.parametrize("N,amp", [(1024, 0.4), (1000, 0.3), (8192, 0.4),
+                                   (4097, 0.1)])
+def test_inv_fp64_full(N, amp):
+    y, c = workloads.inverse_case(N, amp, seed=0)
+    rng = np.random.default_rng(1)
+    g = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    f = run_inv(y, g, 1e-12)
+    ref = oracle.inv(N, y, g)
+    err = rel_l2(f, ref)
+    say("rel l2", err)
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 16, 100])
+def test_inv_tiny(N):
+    y, c = workloads.inverse_case(N, 0.3, seed=N)
+    rng = np.random.default_rng(N)
+    g = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    assert rel_l2(run_inv(y, g, 1e-12), oracle.inv(N, y, g)) < 1e-12
+
+
+def test_inv_uniform_shift():
+    """y_j = x_j + 2 pi delta / N: the inverse undoes the fractional shift.
+    g_j = f(y_j) is evaluated from the coefficients at the binary64 points
+    (Eq. p1), so the inverse must return the samples f_k themselves."""
+    N, delta = 4096, 0.37
+    y = 2 * np.pi * (np.arange(N) + delta) / N
+    rng = np.random.default_rng(2)
+    c = workloads.coefficients(N, rng)
+    f = workloads.samples_from_coefficients(c)
+    g = oracle.eval_series(N, y, c)
+    f2 = run_inv(y, g, 1e-12)
+    err = rel_l2(f2, f)
+    say("shift rel l2", err)
+    assert err < 1e-12
+
+
+def test_inv_hits_and_errors():
+    N = 512
+    y, c = workloads.inverse_case(N, 0.3, seed=4)
+    y[0] = 0.0
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    f = run_inv(y, g, 1e-12)
+    assert f[0] == g[0]
+    assert rel_l2(f, oracle.inv(N, y, g)) < 1e-12
+    y2 = y.copy()
+    y2[5] = y2[9]
+    with pytest.raises(fn.NufftError) as e:
+        run_inv(y2, g, 1e-12)
+    assert e.value.status == fn.FN_ESINGULAR
+
+
+@pytest.mark.parametrize("N,amp,dtype,eps", [(1 << 16, 0.4, np.complex128, 1e-12),
+                                             (1 << 16, 0.4, np.complex64, 1e-6),
+                                             (1 << 20, 0.4, np.complex128, 1e-12),
+                                             (1 << 20, 0.4, np.complex64, 1e-6)])
+def test_round_trip(N, amp, dtype, eps):
+    """INUFFT(NUFFT(f)) = f (Eq. p6 inverts Eq. p2), within cond * eps."""
+    y, c = workloads.inverse_case(N, amp, seed=0)
+    f = workloads.samples_from_coefficients(c).astype(dtype)
+    fd, yd = dev(f), dev(y)
+    say(f"round trip N={N} dtype={np.dtype(dtype).name}")
+    g = fn.nufft_fwd(yd, fd, eps)
+    f2 = host(fn.inufft(yd, g, eps))
+    err = rel_l2(f2, f)
+    say("round trip rel l2", err)
+    assert err < 10 * eps
+
+
+def test_inv_mixed():
+    N = 8192
+    y, c = workloads.inverse_case(N, 0.4, seed=6)
+    rng = np.random.default_rng(6)
+    g = (rng.standard_normal(N) + 1j * rng.standard_normal(N)).astype(np.complex64)
+    f = run_inv(y, g, 1e-6, dtype=np.complex64)
+    ref = oracle.inv(N, y, g.astype(np.complex128))
+    err = rel_l2(f, ref)
+    say("mixed inv rel l2", err)
+    assert err < 1e-6
