@@ -344,6 +344,7 @@ static const double ONE_OVER_2PI_LO = -0x1.6b01ec5417056p-57;
 
 static void n_over_2pi(int64_t N, double *hi, double *lo)
 {
+#pragma clang fp contract(off)
     const double n = (double)N;
     double p = n * ONE_OVER_2PI_HI;
     double e = std::fma(n, ONE_OVER_2PI_HI, -p);

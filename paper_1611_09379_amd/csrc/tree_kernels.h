@@ -10,6 +10,21 @@ namespace fn {
 
 enum { FLAG_BAD_Y = 1, FLAG_DUP = 2, FLAG_RANGE = 4 };
 
+// s = y (c_hi + c_lo) in double-double, split into the nearest integer n
+// and the remainder th.  Contraction stays off: fusing p - n with
+// p = y c_hi into one fma would count the rounding error of y c_hi twice.
+__device__ __noinline__ void grid_units(double y, double c_hi, double c_lo,
+                                        double *n_out, double *th_out)
+{
+#pragma clang fp contract(off)
+    double p = y * c_hi;
+    double e = fma(y, c_hi, -p);
+    e = fma(y, c_lo, e);
+    double n = rint(p);
+    *n_out = n;
+    *th_out = (p - n) + e;
+}
+
 // y -> (m, th, leaf).  s = y N / (2 pi) is formed in double-double from the
 // double-double constant N/(2 pi) = c_hi + c_lo; m = nearest integer mod N,
 // th = s - nearest integer in [-1/2, 1/2]; the representative in [0, N)
@@ -31,11 +46,8 @@ __global__ void k_reduce(int64_t M, const double *__restrict__ y, double c_hi,
             atomicAdd(&count[0], 1);
             continue;
         }
-        double p = yy * c_hi;
-        double e = fma(yy, c_hi, -p);
-        e = fma(yy, c_lo, e);
-        double n = rint(p);
-        double th = (p - n) + e;
+        double n, th;
+        grid_units(yy, c_hi, c_lo, &n, &th);
         if (th > 0.5) {
             th -= 1.0;
             n += 1.0;
