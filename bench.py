@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Throughput of the FMM-based NUFFT + INUFFT on one MI355X.
+
+One step = one forward transform (problem i, N = M = 2^20, y iid uniform on
+[0, 2 pi)) plus one inverse transform (problem ii, N = M = 2^20, jittered
+grid y_j = 2 pi (j + u_j)/N, u_j ~ U(-0.4, 0.4)), each one-shot: setup of
+the data structure (Section 3.3) and evaluation.  Inputs are resident in HBM
+before the timed region.  value = (N + M) / step time, i.e. points per
+second for the forward + inverse pair.  The plain FP64 path (eps 1e-12) is
+the headline; the mixed path (eps 1e-6) is timed on the same inputs.
+
+Prints one JSON line.  Options: --steps K --warmup W --gpus 1.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "(N+M)/s at rel-ℓ2 1e-12 (FP64) vs 1e-6 (mixed), N=M=2^20 fwd+inv"
+PEAK_FP64 = 78.6e12      # MI355X FP64 vector (and matrix) FLOP/s
+PEAK_FP32 = 157.3e12     # MI355X FP32 vector FLOP/s
+PEAK_HBM = 8.0e12        # B/s
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle sample")
+    ap.add_argument("--no-mixed", action="store_true")
+    return ap.parse_args()
+
+
+def down_eval_flops(info, n_targets, n_sources):
+    """Algorithmic flops of one k_down_eval launch (forward or inverse cot FMM):
+    L2L (triangular) + 3 M2L per box of levels 3..lmax on complex data
+    (2 flops per real FMA), 3 N M / 2^lmax near-field pairs (Eq. 23) at 6 flops
+    (difference, reciprocal, complex-by-real FMA), and a P-term complex Horner
+    L2P (4 flops per term) per target."""
+    P, l = info.nterms, info.lmax
+    boxes = (1 << (l + 1)) - 8 if l >= 3 else 0
+    trans = boxes * (2 * P * (P + 1) + 12 * P * P)
+    p2p = 3.0 * n_targets * n_sources / (1 << l) * 6.0
+    l2p = n_targets * 4.0 * P
+    return trans + p2p + l2p
+
+
+def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
+    """Times `steps` one-shot fwd + inv pairs; per-kernel events for phase 1."""
+    dt = f.dtype
+    g = torch.empty(M, dtype=dt, device="cuda")
+    fo = torch.empty(N, dtype=dt, device="cuda")
+    dtc = fn.FN_C128 if dt == torch.complex128 else fn.FN_C64
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    k_f, k_i, up_f, up_i = [], [], [], []
+    info_f = info_i = None
+
+    def one_step(record):
+        nonlocal info_f, info_i
+        pf = fn.Plan.forward(N, yu, eps, dtc)
+        ev[0].record()
+        pf.execute_phase(f, g, 0)
+        ev[1].record()
+        pf.execute_phase(f, g, 1)
+        ev[2].record()
+        info_f = pf.info()
+        pf.destroy()
+        pi = fn.Plan.inverse(yj, eps, dtc)
+        ev[3].record()
+        pi.execute_phase(gj, fo, 0)
+        ev[4].record()
+        pi.execute_phase(gj, fo, 1)
+        ev[5].record()
+        info_i = pi.info()
+        pi.destroy()
+        if record:
+            up_f.append(ev[0].elapsed_time(ev[1]))
+            k_f.append(ev[1].elapsed_time(ev[2]))
+            up_i.append(ev[3].elapsed_time(ev[4]))
+            k_i.append(ev[4].elapsed_time(ev[5]))
+
+    for _ in range(warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    # evaluation only (plan reused, Section 3.3), outside the headline
+    pf = fn.Plan.forward(N, yu, eps, dtc)
+    pi = fn.Plan.inverse(yj, eps, dtc)
+    for _ in range(2):
+        pf(f, g)
+        pi(gj, fo)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        pf(f, g)
+        pi(gj, fo)
+    torch.cuda.synchronize()
+    exec_wall = time.perf_counter() - t1
+    pf.destroy()
+    pi.destroy()
+    return {
+        "wall_s": wall, "ms_per_step": 1e3 * wall / steps,
+        "exec_ms_per_step": 1e3 * exec_wall / steps,
+        "fwd_up_ms": float(np.mean(up_f)), "fwd_down_ms": float(np.mean(k_f)),
+        "inv_up_ms": float(np.mean(up_i)), "inv_down_ms": float(np.mean(k_i)),
+        "info_f": info_f, "info_i": info_i, "g": g, "fo": fo,
+    }
+
+
+def cpu_baseline(N, M, yu, f, yj, seconds):
+    """The oracle (direct sums, unchanged) on a bounded sample of the same
+    workload, extrapolated to the full transforms: forward cost per target
+    = one O(N) direct sum (Eq. p4); inverse cost per output = the two O(N)
+    log-sums behind Eq. (p8) plus one O(N) cot sum (Eq. p6)."""
+    import oracle
+    cores = oracle.threads()
+    rng = np.random.default_rng(7)
+    # calibrate on a small sample, then size the sample to ~seconds of work
+    s0 = max(cores, 32)
+    t = time.perf_counter()
+    oracle.fwd_at(N, yu, f, rng.choice(M, s0, replace=False))
+    per_f = (time.perf_counter() - t) / s0
+    t = time.perf_counter()
+    oracle.logsums(N, yj, ks=rng.choice(N, s0, replace=False),
+                   js=rng.choice(N, s0, replace=False))
+    per_i = (time.perf_counter() - t) / s0 + per_f
+    S = int(max(s0, min(M, seconds / (per_f + per_i))))
+    sel_f = rng.choice(M, S, replace=False)
+    sel_i = rng.choice(N, S, replace=False)
+    t = time.perf_counter()
+    oracle.fwd_at(N, yu, f, sel_f)
+    tf = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.logsums(N, yj, ks=sel_i, js=sel_i)
+    oracle.fwd_at(N, yj, f, sel_i)      # same O(N) cot sum per output
+    ti = time.perf_counter() - t
+    t_pair = tf * M / S + ti * N / S
+    return {"value": (N + M) / t_pair, "unit": "points/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{S} forward targets + {S} inverse outputs (log-sums "
+                      f"and cot sum) of the N=M=2^{int(np.log2(N))} workload, "
+                      f"{tf + ti:.1f} s measured, extrapolated linearly to all "
+                      f"N + M outputs ({t_pair:.0f} s per fwd+inv pair)"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md, 'How the path would shard'); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1611_09379_amd as fn
+    import workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    fn.load_library()
+    N = M = 1 << args.log2n
+    yu_h, f_h, c_h = workloads.forward_case(N, M, "uniform", seed=0)
+    yj_h, cj_h = workloads.inverse_case(N, 0.4, seed=1)
+    yu = torch.from_numpy(yu_h).cuda()
+    yj = torch.from_numpy(yj_h).cuda()
+    f64 = torch.from_numpy(f_h).cuda()
+    # inverse input: samples of the same band-limited function at the jittered
+    # points (computed once, before timing)
+    gj64 = fn.nufft_fwd(yj, f64, 1e-12)
+    torch.cuda.synchronize()
+
+    res = run_path(fn, torch, N, M, yu, f64, yj, gj64, 1e-12, args.steps, args.warmup)
+    # accuracy of the timed outputs (outside the timed region)
+    sel = np.random.default_rng(3).choice(M, 64, replace=False)
+    g_h = res["g"].cpu().numpy()
+    fo_h = res["fo"].cpu().numpy()
+    acc = {"inv_roundtrip_rel_l2": float(np.linalg.norm(fo_h - f_h) / np.linalg.norm(f_h))}
+    if not args.no_cpu_baseline:
+        import oracle
+        ref = oracle.fwd_at(N, yu_h, f_h, sel)
+        acc["fwd_rel_l2_vs_oracle_64"] = float(np.linalg.norm(g_h[sel] - ref) / np.linalg.norm(ref))
+
+    info_f, info_i = res["info_f"], res["info_i"]
+    fl_f = down_eval_flops(info_f, M, N)
+    fl_i = down_eval_flops(info_i, N, N)
+    kf = res["fwd_down_ms"] * 1e-3
+    ki = res["inv_down_ms"] * 1e-3
+    # dominant kernel: the forward or inverse downward pass, whichever is longer
+    if kf >= ki:
+        dom, fl, dur = "k_down_eval<double,cot,uniform sources,forward>", fl_f, kf
+    else:
+        dom, fl, dur = "k_down_eval<double,cot,sorted sources,inverse>", fl_i, ki
+    roof = {"bound": "alu", "achieved": fl / dur / 1e12, "peak": PEAK_FP64 / 1e12,
+            "unit": "TFLOP/s", "frac": fl / dur / PEAK_FP64, "traffic": None,
+            "kernel": dom, "flops_per_launch": fl, "avg_launch_ms": dur * 1e3}
+
+    out = {
+        "metric": METRIC,
+        "value": (N + M) / (res["ms_per_step"] * 1e-3),
+        "unit": "points/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"fwd uniform y + inv jittered grid (u~U(-0.4,0.4)), "
+                               f"N=M=2^{args.log2n}, one-shot, FP64 eps=1e-12",
+                   "N": N, "M": M, "eps": 1e-12,
+                   "fwd": {"p": info_f.p, "q": info_f.q, "lmax": info_f.lmax,
+                           "nterms": info_f.nterms},
+                   "inv": {"p": info_i.p, "q": info_i.q, "lmax": info_i.lmax,
+                           "nterms": info_i.nterms}},
+        "phases_ms": {k: round(res[k], 4) for k in
+                      ("fwd_up_ms", "fwd_down_ms", "inv_up_ms", "inv_down_ms")},
+        "exec_only": {"ms_per_step": res["exec_ms_per_step"],
+                      "value": (N + M) / (res["exec_ms_per_step"] * 1e-3)},
+        "accuracy": acc,
+        "roofline": roof,
+    }
+    if not args.no_mixed:
+        f32 = f64.to(torch.complex64)
+        gj32 = gj64.to(torch.complex64)
+        rm = run_path(fn, torch, N, M, yu, f32, yj, gj32, 1e-6, args.steps, args.warmup)
+        fo_m = rm["fo"].cpu().numpy()
+        mixed = {"value": (N + M) / (rm["ms_per_step"] * 1e-3),
+                 "ms_per_step": rm["ms_per_step"], "dtype": "mixed f32/f64",
+                 "eps": 1e-6,
+                 "speedup_vs_f64": res["ms_per_step"] / rm["ms_per_step"],
+                 "exec_only_ms_per_step": rm["exec_ms_per_step"],
+                 "phases_ms": {k: round(rm[k], 4) for k in
+                               ("fwd_up_ms", "fwd_down_ms", "inv_up_ms", "inv_down_ms")},
+                 "inv_roundtrip_rel_l2": float(np.linalg.norm(fo_m - f_h) / np.linalg.norm(f_h))}
+        if not args.no_cpu_baseline:
+            import oracle
+            gm = rm["g"].cpu().numpy()
+            ref = oracle.fwd_at(N, yu_h, f32.cpu().numpy().astype(np.complex128), sel)
+            mixed["fwd_rel_l2_vs_oracle_64"] = float(np.linalg.norm(gm[sel] - ref) / np.linalg.norm(ref))
+        out["mixed"] = mixed
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(N, M, yu_h, f_h, yj_h, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

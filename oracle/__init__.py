@@ -50,6 +50,8 @@ def _load():
                                   ctypes.c_int]
     lib.or_inv.argtypes = [i64, vp, vp, vp, ctypes.c_int]
     lib.or_inv.restype = ctypes.c_int
+    lib.or_max_threads.argtypes = [ctypes.c_int]
+    lib.or_max_threads.restype = ctypes.c_int
     del dp, ip
     _lib = lib
     return lib
@@ -57,6 +59,11 @@ def _load():
 
 def _threads() -> int:
     return int(os.environ.get("ORACLE_THREADS", "0"))
+
+
+def threads() -> int:
+    """Threads the oracle's parallel loops use."""
+    return int(_load().or_max_threads(_threads()))
 
 
 def _f64(a):

@@ -79,6 +79,13 @@ static void set_threads(int nthreads)
         omp_set_num_threads(nthreads);
 }
 
+/* Threads a parallel region of the oracle uses (for reporting). */
+int or_max_threads(int nthreads)
+{
+    set_threads(nthreads);
+    return omp_get_max_threads();
+}
+
 /* ------------------------------------------------------------ grid units */
 
 /* s_j = N y_j / (2 pi) in binary128; m_j = nearest integer mod N,

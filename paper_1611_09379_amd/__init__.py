@@ -27,6 +27,7 @@ STATUS_NAMES = {0: "FN_OK", 1: "FN_EINVAL", 2: "FN_ENOMEM", 3: "FN_EHIP",
 ABI_SYMBOLS = (
     "nufft_fwd", "inufft", "nufft_plan_fwd", "nufft_plan_inv",
     "nufft_plan_fwd_ex", "nufft_plan_inv_ex", "nufft_execute",
+    "nufft_execute_phase",
     "nufft_destroy", "nufft_plan_get_info", "nufft_select_params",
     "nufft_last_error",
 )
@@ -70,6 +71,7 @@ def load_library(path: str = LIB_PATH):
         "nufft_plan_fwd_ex": [pp, i64, i64, vp, dbl, ctypes.c_int, i32, i32, i32, vp],
         "nufft_plan_inv_ex": [pp, i64, vp, dbl, ctypes.c_int, i32, i32, i32, vp],
         "nufft_execute": [vp, vp, vp, vp],
+        "nufft_execute_phase": [vp, vp, vp, ctypes.c_int, vp],
         "nufft_destroy": [vp],
         "nufft_plan_get_info": [vp, ctypes.POINTER(PlanInfo)],
         "nufft_select_params": [i64, i64, dbl, ctypes.c_int, pi32, pi32, pi32],
@@ -181,6 +183,14 @@ class Plan:
         return out
 
     __call__ = execute
+
+    def execute_phase(self, x, out, phase: int):
+        """One kernel of execute (0: upward pass, 1: downward pass and
+        evaluation); both must be enqueued in order with the same x."""
+        _check(load_library().nufft_execute_phase(
+            self._h, _dev_ptr(x, "input"), _dev_ptr(out, "output"), phase,
+            _stream()))
+        return out
 
     def destroy(self):
         if self._h is not None:

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -141,125 +142,168 @@ static long double bernoulli_abs(int m)
     return r;
 }
 
-static long double binom(int n, int k)
-{
-    if (k < 0 || k > n)
-        return 0;
-    long double r = 1;
-    for (int i = 1; i <= k; ++i)
-        r = r * (n - k + i) / i;
-    return r;
-}
-
-static long double factl(int n)
-{
-    long double r = 1;
-    for (int i = 2; i <= n; ++i)
-        r *= i;
-    return r;
-}
-
 struct Tables {
-    std::vector<long double> m2m, l2l, m2l, bin, reg1, reg2;
+    std::vector<long double> m2m, l2l, m2l4, m2l6, bin, reg1, reg2;
 };
 
 // M2M (child at c_p + s r_p/2 -> parent):  a^P_n = sum_{m<=n} C(n,m) 2^-n s^(n-m) a^C_m
 // L2L (parent -> child):                   b^C_m = sum_{n>=m} C(n,m) 2^-n s^(n-m) b^P_n
+// Only the left child (s = -1) is stored; the right one differs by (-1)^(n-m).
 // M2L cot (1/t kernel, delta = (c_t - c_s)/r):
 //                    b_n = sum_m (-1)^n C(m+n, n) delta^-(m+n+1) a_m
 // M2L log (log|t| kernel):
 //                    b_0 = a_0 log|delta| - sum_{m>=1} (a_m/m) delta^-m
 //                    b_n = a_0 (-1)^(n+1) / (n delta^n)
 //                          - sum_{m>=1} (a_m/m) C(m+n-1, n) (-1)^n delta^-(m+n)
+// Only delta = +4 and +6 are stored; delta < 0 follows from the sign pattern.
 // Regular part at level 2 (Eq. p20 and its log analogue) in the variable
 // u = (y - x_c)/(pi/4), with A_t the moments of Omega_1 (reg1) or of the
 // opposite quarter (reg2) about the centre x_c in units of pi/4.
 static void build_tables(int P, int q, int kernel, Tables &T)
 {
     const int PP = P * P;
-    T.m2m.assign(2 * PP, 0);
-    T.l2l.assign(2 * PP, 0);
-    T.m2l.assign(4 * PP, 0);
+    T.m2m.assign(PP, 0);
+    T.l2l.assign(PP, 0);
+    T.m2l4.assign(PP, 0);
+    T.m2l6.assign(PP, 0);
     T.bin.assign(PP, 0);
     T.reg1.assign(PP, 0);
     T.reg2.assign(PP, 0);
-    for (int c = 0; c < 2; ++c) {
-        const long double s = c == 0 ? -1 : 1;
-        for (int n = 0; n < P; ++n)
-            for (int m = 0; m <= n; ++m) {
-                long double v = binom(n, m) * powl(2.0L, -n) * powl(s, n - m);
-                T.m2m[c * PP + m * P + n] = v; // [in m][out n]
-                T.l2l[c * PP + n * P + m] = v; // [in n][out m]
-            }
+    // Pascal triangle and powers, exact in long double for these sizes
+    std::vector<long double> C((2 * P) * (2 * P), 0);
+    for (int n = 0; n < 2 * P; ++n) {
+        C[n * 2 * P] = 1;
+        for (int k = 1; k <= n; ++k)
+            C[n * 2 * P + k] = C[(n - 1) * 2 * P + k - 1] + (k < n ? C[(n - 1) * 2 * P + k] : 0);
     }
-    const int deltas[4] = {-6, -4, 4, 6};
-    for (int di = 0; di < 4; ++di) {
-        const long double d = deltas[di];
+    auto binom = [&](int n, int k) -> long double {
+        return (k < 0 || k > n) ? 0 : C[n * 2 * P + k];
+    };
+    for (int n = 0; n < P; ++n)
+        for (int m = 0; m <= n; ++m) {
+            long double v = binom(n, m) * ldexpl(1.0L, -n) * (((n - m) & 1) ? -1 : 1);
+            T.m2m[m * P + n] = v; // [in m][out n]
+            T.l2l[n * P + m] = v; // [in n][out m]
+        }
+    for (int di = 0; di < 2; ++di) {
+        const long double d = di == 0 ? 4 : 6;
+        std::vector<long double> &M = di == 0 ? T.m2l4 : T.m2l6;
+        std::vector<long double> ip(2 * P + 2, 1);
+        for (int j = 1; j < 2 * P + 2; ++j)
+            ip[j] = ip[j - 1] / d; // d^-j
         for (int m = 0; m < P; ++m)
             for (int n = 0; n < P; ++n) {
                 long double v;
                 if (kernel == KER_COT) {
-                    v = ((n & 1) ? -1 : 1) * binom(m + n, n) * powl(d, -(m + n + 1));
+                    v = ((n & 1) ? -1 : 1) * binom(m + n, n) * ip[m + n + 1];
                 } else if (m == 0 && n == 0) {
-                    v = logl(fabsl(d));
+                    v = logl(d);
                 } else if (n == 0) {
-                    v = -powl(d, -m) / m;
+                    v = -ip[m] / m;
                 } else if (m == 0) {
-                    v = ((n & 1) ? 1 : -1) / (n * powl(d, n));
+                    v = ((n & 1) ? 1 : -1) * ip[n] / n;
                 } else {
-                    v = -binom(m + n - 1, n) * ((n & 1) ? -1 : 1) * powl(d, -(m + n)) / m;
+                    v = -binom(m + n - 1, n) * ((n & 1) ? -1 : 1) * ip[m + n] / m;
                 }
-                T.m2l[di * PP + m * P + n] = v;
+                M[m * P + n] = v;
             }
     }
     for (int t = 0; t < P; ++t)
         for (int j = 0; j <= t; ++j)
             T.bin[t * P + j] = binom(t, j);
     const long double qpi = 0.785398163397448309615660845819875721L; // pi/4
+    std::vector<long double> fac(2 * P + 2, 1);
+    for (int i = 1; i < 2 * P + 2; ++i)
+        fac[i] = fac[i - 1] * i;
     for (int m = 1; m <= q; ++m) {
         const long double B = bernoulli_abs(m);
         const long double four_m = powl(4.0L, m) - 1;
         const int top = kernel == KER_COT ? 2 * m - 1 : 2 * m;
         for (int lo = 0; lo <= top; ++lo) {
-            const int t = (kernel == KER_COT ? 2 * m - 1 : 2 * m) - lo;
+            const int t = top - lo;
             if (lo >= P || t >= P)
                 continue;
             const long double w = kernel == KER_COT ? B / m : B / (2 * m);
-            const long double kap = -(powl(qpi, lo) / factl(lo)) * w *
-                                    (powl(-qpi, t) / factl(t));
+            const long double kap = -(powl(qpi, lo) / fac[lo]) * w *
+                                    (powl(-qpi, t) / fac[t]);
             T.reg1[t * P + lo] = kap;
             T.reg2[t * P + lo] = kap * four_m;
         }
     }
 }
 
+// Device copies of the tables, built once per (precision, kernel, P, q,
+// device) and kept for the life of the process.
+struct TableSet {
+    void *base = nullptr;
+    size_t off[7] = {0};
+};
+
+static std::mutex g_tab_mu;
+static std::map<std::tuple<int, int, int, int, int>, TableSet> g_tab_cache;
+
+template <typename R>
+static int get_tables(int kernel, int Pn, int q, OpTables<R> *out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    const auto key = std::make_tuple((int)sizeof(R), kernel, Pn, q, dev);
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    auto it = g_tab_cache.find(key);
+    if (it == g_tab_cache.end()) {
+        Tables T;
+        build_tables(Pn, q, kernel, T);
+        std::vector<R> h;
+        TableSet ts;
+        const std::vector<long double> *parts[7] = {&T.m2m, &T.l2l, &T.m2l4, &T.m2l6,
+                                                    &T.bin, &T.reg1, &T.reg2};
+        for (int i = 0; i < 7; ++i) {
+            ts.off[i] = h.size();
+            for (long double x : *parts[i])
+                h.push_back((R)x);
+        }
+        HIPCHK(hipMalloc(&ts.base, h.size() * sizeof(R)));
+        HIPCHK(hipMemcpy(ts.base, h.data(), h.size() * sizeof(R), hipMemcpyHostToDevice));
+        it = g_tab_cache.emplace(key, ts).first;
+    }
+    const R *b = (const R *)it->second.base;
+    const size_t *o = it->second.off;
+    *out = {b + o[0], b + o[1], b + o[2], b + o[3], b + o[4], b + o[5], b + o[6]};
+    return FN_OK;
+}
+
 // ------------------------------------------------------------------ plan
+
+// Workspace and launch shapes of one FMM (cot or log kernel) on a tree.
+struct FmmSetup {
+    int Pn = 0, q = 0;
+    Buf mp, loc2, S, cnt;
+    int nbands = 0;
+    int band_lo[MAX_BANDS] = {0}, band_d[MAX_BANDS] = {0};
+    int cnt_off[MAX_BANDS + 1] = {0};
+    int up_grid = 0;
+    size_t up_smem = 0, dn_smem = 0;
+    int nbuf = 0, near_cap = 0;
+};
 
 struct fn_plan {
     int kind = 0, dtype = 0;
     int64_t N = 0, M = 0;
     int p = 0, q = 0, l = 0, P = 0;
     double eps = 0;
-    int lr = 2;                   // subtree root level of k_down_eval
-    // sorted point set (targets of the forward, sources of the inverse)
+    int lr = 2; // subtree root level of k_down_eval
+    // points sorted into the leaves (targets of the forward, sources of the
+    // inverse)
     Buf off, sm, sth, sperm;
     Buf work;
     int nwork = 0;
-    // k_up band structure
-    UpArgs<float, cx<float>> bands_f; // only the band fields are used
-    int up_grid = 0;
-    size_t up_smem = 0, dn_smem = 0;
-    Buf cnt;
-    // cot expansions and operators (element type R = double or float)
-    Buf mp, loc2, S, tabs;
-    size_t tab_m2m = 0, tab_l2l = 0, tab_m2l = 0, tab_bin = 0, tab_reg1 = 0,
-           tab_reg2 = 0;
+    FmmSetup cot;
     // inverse
     Buf hit, chat, dhat, wsorted;
     std::vector<Buf *> all()
     {
-        return {&off, &sm, &sth, &sperm, &work, &cnt, &mp, &loc2, &S, &tabs,
-                &hit, &chat, &dhat, &wsorted};
+        return {&off, &sm, &sth, &sperm, &work, &cot.mp, &cot.loc2, &cot.S,
+                &cot.cnt, &hit, &chat, &dhat, &wsorted};
     }
 };
 
@@ -283,59 +327,125 @@ static void release_plan(fn_plan *P)
         release(*b);
 }
 
+static constexpr int UP_DMAX = 4; // levels per band of k_up
+static constexpr int DN_S = 4;    // subtree depth of k_down_eval
+
 // Bands of k_up: climbs of at most dmax levels from the leaves to level 2.
-template <typename BandArgs>
-static void make_bands(int l, int dmax, BandArgs &a, int *grid, int *ncnt)
+static void make_bands(int l, FmmSetup &F, int *ncnt)
 {
     int nb = 0, lo = l;
     while (true) {
-        int d = std::min(dmax, lo - 2);
-        a.band_lo[nb] = lo;
-        a.band_d[nb] = d;
+        int d = std::min(UP_DMAX, lo - 2);
+        F.band_lo[nb] = lo;
+        F.band_d[nb] = d;
         ++nb;
         lo -= d;
         if (lo == 2)
             break;
     }
-    a.nbands = nb;
-    // counters: band k (k >= 1) has 2^(band_lo[k] - band_d[k]) nodes; the
-    // final stage has one.
+    F.nbands = nb;
+    // band k (k >= 1) has 2^(band_lo[k] - band_d[k]) nodes; the final stage one
     int off = 0;
-    a.cnt_off[0] = 0;
     for (int k = 1; k < nb; ++k) {
-        a.cnt_off[k] = off;
-        off += 1 << (a.band_lo[k] - a.band_d[k]);
+        F.cnt_off[k] = off;
+        off += 1 << (F.band_lo[k] - F.band_d[k]);
     }
-    a.cnt_off[nb] = off;
-    off += 1;
-    *ncnt = off;
-    *grid = 1 << (l - a.band_d[0]);
+    F.cnt_off[nb] = off;
+    *ncnt = off + 1;
+    F.up_grid = 1 << (l - F.band_d[0]);
 }
 
-template <typename R>
-static int upload_tables(fn_plan *P, int kernel, int Pn, int q, hipStream_t st)
+template <typename R, typename V>
+static size_t down_smem(int Pn, int s, int nbuf)
 {
-    Tables T;
-    build_tables(Pn, q, kernel, T);
-    std::vector<R> h;
-    auto push = [&](const std::vector<long double> &v) {
-        size_t o = h.size();
-        for (long double x : v)
-            h.push_back((R)x);
-        return o;
-    };
-    P->tab_m2m = push(T.m2m);
-    P->tab_l2l = push(T.l2l);
-    P->tab_m2l = push(T.m2l);
-    P->tab_bin = push(T.bin);
-    P->tab_reg1 = push(T.reg1);
-    P->tab_reg2 = push(T.reg2);
-    if (!alloc(P->tabs, h.size() * sizeof(R)))
-        return fail(FN_ENOMEM, "table allocation failed");
-    HIPCHK(hipMemcpyAsync(P->tabs.p, h.data(), h.size() * sizeof(R),
-                          hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st)); // h goes out of scope
+    return 3 * (size_t)Pn * Pn * sizeof(R) + 2 * (size_t)nbuf * Pn * sizeof(V) +
+           (((size_t)1 << s) + 6) * Pn * sizeof(V);
+}
+
+static size_t lds_limit()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v <= 0)
+        return 64 * 1024;
+    return (size_t)v;
+}
+
+// Subtree root level: the deepest subtrees (at most DN_S levels) whose
+// k_down_eval workspace fits in LDS for both expansion lengths used.
+template <typename R, typename V>
+static int choose_lr(int l, int Pn)
+{
+    const size_t lim = lds_limit();
+    for (int s = std::min(DN_S, l - 2); s >= 0; --s) {
+        const int lr = l - s;
+        const int nbuf = std::max(1 << s, lr);
+        if (down_smem<R, V>(Pn, s, nbuf) <= lim)
+            return lr;
+    }
+    return l;
+}
+
+template <typename R, typename V>
+static int setup_fmm(fn_plan *P, int kernel, int Pn, int q, bool near_stage,
+                     FmmSetup &F, hipStream_t st)
+{
+    F.Pn = Pn;
+    F.q = q;
+    int ncnt = 0;
+    make_bands(P->l, F, &ncnt);
+    const int64_t nmp = lev_off(P->l + 1, Pn);
+    if (!alloc(F.mp, nmp * sizeof(V)) || !alloc(F.loc2, 4 * Pn * sizeof(V)) ||
+        !alloc(F.S, sizeof(V)) || !alloc(F.cnt, ncnt * 4))
+        return fail(FN_ENOMEM, "expansion allocation failed");
+    HIPCHK(hipMemsetAsync(F.cnt.p, 0, ncnt * 4, st));
+    const int nbot = 1 << std::max(F.band_d[0], 0);
+    F.up_smem = (size_t)Pn * Pn * sizeof(R) +
+                (size_t)std::max(nbot + std::max(nbot / 2, 1), 8) * Pn * sizeof(V);
+    const int s = P->l - P->lr;
+    F.nbuf = std::max(1 << s, P->lr);
+    F.dn_smem = down_smem<R, V>(Pn, s, F.nbuf);
+    F.near_cap = near_stage ? (int)((((size_t)1 << s) + 6) * Pn * sizeof(V) / sizeof(cx<R>)) : 0;
+    if (F.dn_smem > lds_limit())
+        return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", Pn, F.dn_smem);
+    (void)kernel;
     return FN_OK;
+}
+
+template <typename R, typename V>
+static void fill_up(const fn_plan *P, const FmmSetup &F, const OpTables<R> &T,
+                    UpArgs<R, V> &ua)
+{
+    ua.N = P->N;
+    ua.l = P->l;
+    ua.P = F.Pn;
+    ua.nbands = F.nbands;
+    std::memcpy(ua.band_lo, F.band_lo, sizeof ua.band_lo);
+    std::memcpy(ua.band_d, F.band_d, sizeof ua.band_d);
+    std::memcpy(ua.cnt_off, F.cnt_off, sizeof ua.cnt_off);
+    ua.cnt = (int *)F.cnt.p;
+    ua.mp = (V *)F.mp.p;
+    ua.loc2 = (V *)F.loc2.p;
+    ua.S = (V *)F.S.p;
+    ua.T = T;
+}
+
+template <typename R, typename V>
+static void fill_down(const fn_plan *P, const FmmSetup &F, const OpTables<R> &T,
+                      DownArgs<R, V> &da)
+{
+    da.N = P->N;
+    da.l = P->l;
+    da.P = F.Pn;
+    da.lr = P->lr;
+    da.nbuf = F.nbuf;
+    da.near_cap = F.near_cap;
+    da.work = (const WorkItem *)P->work.p;
+    da.mp = (const V *)F.mp.p;
+    da.loc2 = (const V *)F.loc2.p;
+    da.S = (const V *)F.S.p;
+    da.T = T;
 }
 
 // Double-double N / (2 pi): 1/(2 pi) = ONE_OVER_2PI_HI + ONE_OVER_2PI_LO.
@@ -497,31 +607,6 @@ static int build_work(fn_plan *P, bool sorted_targets, bool uniform_targets,
     return FN_OK;
 }
 
-static constexpr int UP_DMAX = 4;
-static constexpr int DN_S = 4;
-
-// Expansion storage and k_up / k_down_eval launch shapes for one FMM.
-template <typename R, typename V>
-static int setup_fmm(fn_plan *P, int kernel, int Pn, int q, Buf &mp, Buf &loc2,
-                     Buf &S, Buf &cnt, UpArgs<R, V> &ua, int *up_grid,
-                     size_t *up_smem, size_t *dn_smem, hipStream_t st)
-{
-    int ncnt = 0;
-    make_bands(P->l, UP_DMAX, ua, up_grid, &ncnt);
-    const int64_t nmp = lev_off(P->l + 1, Pn);
-    if (!alloc(mp, nmp * sizeof(V)) || !alloc(loc2, 4 * Pn * sizeof(V)) ||
-        !alloc(S, sizeof(V)) || !alloc(cnt, ncnt * 4))
-        return fail(FN_ENOMEM, "expansion allocation failed");
-    HIPCHK(hipMemsetAsync(cnt.p, 0, ncnt * 4, st));
-    const int d0 = ua.band_d[0];
-    const int nbot = 1 << std::max(d0, 0);
-    *up_smem = (size_t)std::max(nbot + std::max(nbot / 2, 1), 8) * Pn * sizeof(V);
-    *dn_smem = (size_t)2 * ((size_t)1 << (P->l - P->lr)) * Pn * sizeof(V);
-    (void)kernel;
-    (void)q;
-    return FN_OK;
-}
-
 // --------------------------------------------------------- forward plan
 
 template <typename R>
@@ -530,77 +615,49 @@ static int plan_fwd_impl(fn_plan *P, const double *y, hipStream_t st)
     int rc = build_tree(P, P->M, y, false, false, st);
     if (rc)
         return rc;
-    P->lr = std::max(2, P->l - DN_S);
+    P->lr = choose_lr<R, cx<R>>(P->l, P->P);
     rc = build_work(P, true, false, st);
     if (rc)
         return rc;
-    rc = upload_tables<R>(P, KER_COT, P->P, P->q, st);
+    rc = setup_fmm<R, cx<R>>(P, KER_COT, P->P, P->q, true, P->cot, st);
     if (rc)
         return rc;
-    UpArgs<R, cx<R>> ua{};
-    rc = setup_fmm<R, cx<R>>(P, KER_COT, P->P, P->q, P->mp, P->loc2, P->S, P->cnt,
-                             ua, &P->up_grid, &P->up_smem, &P->dn_smem, st);
+    OpTables<R> T;
+    rc = get_tables<R>(KER_COT, P->P, P->q, &T);
     if (rc)
         return rc;
-    std::memcpy(P->bands_f.band_lo, ua.band_lo, sizeof ua.band_lo);
-    std::memcpy(P->bands_f.band_d, ua.band_d, sizeof ua.band_d);
-    std::memcpy(P->bands_f.cnt_off, ua.cnt_off, sizeof ua.cnt_off);
-    P->bands_f.nbands = ua.nbands;
     HIPCHK(hipStreamSynchronize(st));
     return FN_OK;
 }
 
-template <typename R, typename A>
-static void copy_bands(const fn_plan *P, A &a)
-{
-    std::memcpy(a.band_lo, P->bands_f.band_lo, sizeof a.band_lo);
-    std::memcpy(a.band_d, P->bands_f.band_d, sizeof a.band_d);
-    std::memcpy(a.cnt_off, P->bands_f.cnt_off, sizeof a.cnt_off);
-    a.nbands = P->bands_f.nbands;
-}
-
 template <typename R>
-static int exec_fwd(fn_plan *P, const void *in, void *out, hipStream_t st)
+static int exec_fwd(fn_plan *P, const void *in, void *out, int phase,
+                    hipStream_t st)
 {
     using V = cx<R>;
-    const R *tabs = (const R *)P->tabs.p;
-    UpArgs<R, V> ua{};
-    copy_bands<R>(P, ua);
-    ua.N = P->N;
-    ua.l = P->l;
-    ua.P = P->P;
-    ua.cnt = (int *)P->cnt.p;
-    ua.f_uniform = (const cx<R> *)in;
-    ua.mp = (V *)P->mp.p;
-    ua.loc2 = (V *)P->loc2.p;
-    ua.S = (V *)P->S.p;
-    ua.m2m = tabs + P->tab_m2m;
-    ua.bin = tabs + P->tab_bin;
-    ua.reg1 = tabs + P->tab_reg1;
-    ua.reg2 = tabs + P->tab_reg2;
-    hipLaunchKernelGGL((k_up<R, V, KER_COT, SET_UNIFORM>), dim3(P->up_grid),
-                       dim3(BLOCK), P->up_smem, st, ua);
-    HIPCHK(hipGetLastError());
-    if (P->nwork == 0)
+    OpTables<R> T;
+    int rc = get_tables<R>(KER_COT, P->P, P->q, &T);
+    if (rc)
+        return rc;
+    if (phase != 1) {
+        UpArgs<R, V> ua{};
+        fill_up(P, P->cot, T, ua);
+        ua.f_uniform = (const cx<R> *)in;
+        hipLaunchKernelGGL((k_up<R, V, KER_COT, SET_UNIFORM>), dim3(P->cot.up_grid),
+                           dim3(BLOCK), P->cot.up_smem, st, ua);
+        HIPCHK(hipGetLastError());
+    }
+    if (P->nwork == 0 || phase == 0)
         return FN_OK;
     DownArgs<R, V> da{};
-    da.N = P->N;
-    da.l = P->l;
-    da.P = P->P;
-    da.lr = P->lr;
-    da.work = (const WorkItem *)P->work.p;
-    da.mp = (const V *)P->mp.p;
-    da.loc2 = (const V *)P->loc2.p;
-    da.l2l = tabs + P->tab_l2l;
-    da.m2l = tabs + P->tab_m2l;
+    fill_down(P, P->cot, T, da);
     da.f_uniform = (const cx<R> *)in;
     da.tgt = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
               (const double *)P->sth.p, (const int32_t *)P->sperm.p};
     da.out = (cx<R> *)out;
-    da.S = (const V *)P->S.p;
     da.f_hit = (const cx<R> *)in;
     hipLaunchKernelGGL((k_down_eval<R, V, KER_COT, SET_UNIFORM, EPI_FWD>),
-                       dim3(P->nwork), dim3(BLOCK), P->dn_smem, st, da);
+                       dim3(P->nwork), dim3(BLOCK), P->cot.dn_smem, st, da);
     HIPCHK(hipGetLastError());
     return FN_OK;
 }
@@ -613,72 +670,49 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
 {
     using R = double;
     using V = double;
-    // parameters of the log FMM: the log-sums are absolute errors of log|C|,
-    // log|D|, i.e. relative errors of f, so they get a tenth of eps.
+    // the log-sums are absolute errors of log|C|, log|D|, i.e. relative
+    // errors of f, so they get a tenth of eps
     const double eps_log = std::max(P->eps * 0.1, 1e-15);
     int plog, qlog;
     trunc_numbers(eps_log, P->l, &plog, &qlog);
     const int Plog = round8(std::max(plog, 2 * qlog + 1));
-    fn_plan tmp; // tables of the log kernel
-    int rc = upload_tables<R>(&tmp, KER_LOG, Plog, qlog, st);
-    if (rc) {
-        release_plan(&tmp);
+    OpTables<R> T;
+    int rc = get_tables<R>(KER_LOG, Plog, qlog, &T);
+    if (rc)
         return rc;
-    }
-    Buf mp, loc2, S, cnt, logc, logd, flags;
-    UpArgs<R, V> ua{};
-    int up_grid;
-    size_t up_smem, dn_smem;
+    FmmSetup F;
+    Buf logc, logd, flags;
     auto cleanup = [&]() {
-        for (Buf *b : {&mp, &loc2, &S, &cnt, &logc, &logd, &flags})
+        for (Buf *b : {&F.mp, &F.loc2, &F.S, &F.cnt, &logc, &logd, &flags})
             release(*b);
-        release_plan(&tmp);
     };
-    rc = setup_fmm<R, V>(P, KER_LOG, Plog, qlog, mp, loc2, S, cnt, ua, &up_grid,
-                         &up_smem, &dn_smem, st);
+    rc = setup_fmm<R, V>(P, KER_LOG, Plog, qlog, false, F, st);
     if (!rc && !(alloc(logc, P->N * 8) && alloc(logd, P->N * 8) && alloc(flags, 4)))
         rc = fail(FN_ENOMEM, "log-sum allocation failed");
     if (rc) {
         cleanup();
         return rc;
     }
-    const R *tabs = (const R *)tmp.tabs.p;
-    ua.N = P->N;
-    ua.l = P->l;
-    ua.P = Plog;
-    ua.cnt = (int *)cnt.p;
-    ua.src = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
-              (const double *)P->sth.p, (const int32_t *)P->sperm.p};
-    ua.mp = (V *)mp.p;
-    ua.loc2 = (V *)loc2.p;
-    ua.S = (V *)S.p;
-    ua.m2m = tabs + tmp.tab_m2m;
-    ua.bin = tabs + tmp.tab_bin;
-    ua.reg1 = tabs + tmp.tab_reg1;
-    ua.reg2 = tabs + tmp.tab_reg2;
+    const SortedSet src = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
+                           (const double *)P->sth.p, (const int32_t *)P->sperm.p};
+    UpArgs<R, V> ua{};
+    fill_up(P, F, T, ua);
+    ua.src = src;
     ua.logc1 = std::log(2.0 * M_PI / (double)P->N);
     ua.logc2 = std::log(2.0);
-    hipLaunchKernelGGL((k_up<R, V, KER_LOG, SET_SORTED>), dim3(up_grid),
-                       dim3(BLOCK), up_smem, st, ua);
+    hipLaunchKernelGGL((k_up<R, V, KER_LOG, SET_SORTED>), dim3(F.up_grid),
+                       dim3(BLOCK), F.up_smem, st, ua);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
         DownArgs<R, V> da{};
-        da.N = P->N;
-        da.l = P->l;
-        da.P = Plog;
-        da.lr = P->lr;
-        da.work = (const WorkItem *)P->work.p;
-        da.mp = (const V *)mp.p;
-        da.loc2 = (const V *)loc2.p;
-        da.l2l = tabs + tmp.tab_l2l;
-        da.m2l = tabs + tmp.tab_m2l;
-        da.src = ua.src;
-        da.tgt = ua.src;
+        fill_down(P, F, T, da);
+        da.src = src;
+        da.tgt = src;
         da.logc = (double *)logc.p;
         da.logd = (double *)logd.p;
         da.logself = std::log(2.0 * M_PI / (double)P->N);
         hipLaunchKernelGGL((k_down_eval<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>),
-                           dim3(P->nwork), dim3(BLOCK), dn_smem, st, da);
+                           dim3(P->nwork), dim3(BLOCK), F.dn_smem, st, da);
         e = hipGetLastError();
     }
     if (e == hipSuccess)
@@ -711,7 +745,9 @@ static int plan_inv_impl(fn_plan *P, const double *y, hipStream_t st)
     int rc = build_tree(P, P->N, y, true, true, st);
     if (rc)
         return rc;
-    P->lr = std::max(2, P->l - DN_S);
+    // one subtree level serves the log FMM (double, at most 64 terms) and
+    // the cot FMM
+    P->lr = std::max(choose_lr<R, cx<R>>(P->l, P->P), choose_lr<double, double>(P->l, 64));
     rc = build_work(P, true, true, st);
     if (rc)
         return rc;
@@ -721,67 +757,51 @@ static int plan_inv_impl(fn_plan *P, const double *y, hipStream_t st)
     rc = plan_inv_logs(P, st);
     if (rc)
         return rc;
-    rc = upload_tables<R>(P, KER_COT, P->P, P->q, st);
+    rc = setup_fmm<R, cx<R>>(P, KER_COT, P->P, P->q, false, P->cot, st);
     if (rc)
         return rc;
-    UpArgs<R, cx<R>> ua{};
-    rc = setup_fmm<R, cx<R>>(P, KER_COT, P->P, P->q, P->mp, P->loc2, P->S, P->cnt,
-                             ua, &P->up_grid, &P->up_smem, &P->dn_smem, st);
+    OpTables<R> T;
+    rc = get_tables<R>(KER_COT, P->P, P->q, &T);
     if (rc)
         return rc;
-    std::memcpy(P->bands_f.band_lo, ua.band_lo, sizeof ua.band_lo);
-    std::memcpy(P->bands_f.band_d, ua.band_d, sizeof ua.band_d);
-    std::memcpy(P->bands_f.cnt_off, ua.cnt_off, sizeof ua.cnt_off);
-    P->bands_f.nbands = ua.nbands;
     HIPCHK(hipStreamSynchronize(st));
     return FN_OK;
 }
 
 template <typename R>
-static int exec_inv(fn_plan *P, const void *in, void *out, hipStream_t st)
+static int exec_inv(fn_plan *P, const void *in, void *out, int phase,
+                    hipStream_t st)
 {
     using V = cx<R>;
-    const R *tabs = (const R *)P->tabs.p;
-    UpArgs<R, V> ua{};
-    copy_bands<R>(P, ua);
-    ua.N = P->N;
-    ua.l = P->l;
-    ua.P = P->P;
-    ua.cnt = (int *)P->cnt.p;
-    ua.src = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
-              (const double *)P->sth.p, (const int32_t *)P->sperm.p};
-    ua.dhat = (const cx<double> *)P->dhat.p;
-    ua.gin = (const cx<R> *)in;
-    ua.w_out = (cx<R> *)P->wsorted.p;
-    ua.mp = (V *)P->mp.p;
-    ua.loc2 = (V *)P->loc2.p;
-    ua.S = (V *)P->S.p;
-    ua.m2m = tabs + P->tab_m2m;
-    ua.bin = tabs + P->tab_bin;
-    ua.reg1 = tabs + P->tab_reg1;
-    ua.reg2 = tabs + P->tab_reg2;
-    hipLaunchKernelGGL((k_up<R, V, KER_COT, SET_SORTED>), dim3(P->up_grid),
-                       dim3(BLOCK), P->up_smem, st, ua);
-    HIPCHK(hipGetLastError());
+    OpTables<R> T;
+    int rc = get_tables<R>(KER_COT, P->P, P->q, &T);
+    if (rc)
+        return rc;
+    const SortedSet src = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
+                           (const double *)P->sth.p, (const int32_t *)P->sperm.p};
+    if (phase != 1) {
+        UpArgs<R, V> ua{};
+        fill_up(P, P->cot, T, ua);
+        ua.src = src;
+        ua.dhat = (const cx<double> *)P->dhat.p;
+        ua.gin = (const cx<R> *)in;
+        ua.w_out = (cx<R> *)P->wsorted.p;
+        hipLaunchKernelGGL((k_up<R, V, KER_COT, SET_SORTED>), dim3(P->cot.up_grid),
+                           dim3(BLOCK), P->cot.up_smem, st, ua);
+        HIPCHK(hipGetLastError());
+    }
+    if (phase == 0)
+        return FN_OK;
     DownArgs<R, V> da{};
-    da.N = P->N;
-    da.l = P->l;
-    da.P = P->P;
-    da.lr = P->lr;
-    da.work = (const WorkItem *)P->work.p;
-    da.mp = (const V *)P->mp.p;
-    da.loc2 = (const V *)P->loc2.p;
-    da.l2l = tabs + P->tab_l2l;
-    da.m2l = tabs + P->tab_m2l;
-    da.src = ua.src;
+    fill_down(P, P->cot, T, da);
+    da.src = src;
     da.w_sorted = (const cx<R> *)P->wsorted.p;
     da.out = (cx<R> *)out;
-    da.S = (const V *)P->S.p;
     da.chat = (const double *)P->chat.p;
     da.hit = (const int32_t *)P->hit.p;
     da.gin = (const cx<R> *)in;
     hipLaunchKernelGGL((k_down_eval<R, V, KER_COT, SET_SORTED, EPI_INV>),
-                       dim3(P->nwork), dim3(BLOCK), P->dn_smem, st, da);
+                       dim3(P->nwork), dim3(BLOCK), P->cot.dn_smem, st, da);
     HIPCHK(hipGetLastError());
     return FN_OK;
 }
@@ -884,7 +904,8 @@ int nufft_plan_inv(fn_plan **plan, int64_t N, const double *y, double eps,
     return plan_common(plan, 1, N, N, y, eps, dtype, 0, 0, 0, stream);
 }
 
-int nufft_execute(fn_plan *plan, const void *in, void *out, void *stream)
+static int execute(fn_plan *plan, const void *in, void *out, int phase,
+                   void *stream)
 {
     if (!plan)
         return fail(FN_EINVAL, "plan is NULL");
@@ -892,10 +913,23 @@ int nufft_execute(fn_plan *plan, const void *in, void *out, void *stream)
         return fail(FN_EINVAL, "input or output pointer is NULL");
     hipStream_t st = (hipStream_t)stream;
     if (plan->kind == 0)
-        return plan->dtype == FN_C128 ? exec_fwd<double>(plan, in, out, st)
-                                      : exec_fwd<float>(plan, in, out, st);
-    return plan->dtype == FN_C128 ? exec_inv<double>(plan, in, out, st)
-                                  : exec_inv<float>(plan, in, out, st);
+        return plan->dtype == FN_C128 ? exec_fwd<double>(plan, in, out, phase, st)
+                                      : exec_fwd<float>(plan, in, out, phase, st);
+    return plan->dtype == FN_C128 ? exec_inv<double>(plan, in, out, phase, st)
+                                  : exec_inv<float>(plan, in, out, phase, st);
+}
+
+int nufft_execute(fn_plan *plan, const void *in, void *out, void *stream)
+{
+    return execute(plan, in, out, -1, stream);
+}
+
+int nufft_execute_phase(fn_plan *plan, const void *in, void *out, int phase,
+                        void *stream)
+{
+    if (phase != 0 && phase != 1)
+        return fail(FN_EINVAL, "phase must be 0 or 1");
+    return execute(plan, in, out, phase, stream);
 }
 
 int nufft_destroy(fn_plan *plan)

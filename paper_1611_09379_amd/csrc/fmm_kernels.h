@@ -80,6 +80,21 @@ __device__ __forceinline__ void vadd(R &a, R b) { a += b; }
 
 // ------------------------------------------------------------------ k_up
 
+// Operator tables (type R) shared by all plans with the same (P, q, kernel):
+//   m2m  [P in m][P out n]  M2M for the left child (centre c_p - r_p/2):
+//                           C(n,m) 2^-n (-1)^(n-m); the right child differs
+//                           by (-1)^(n-m)
+//   l2l  [P in n][P out m]  L2L to the left child, same coefficients
+//   m2l4, m2l6 [P in m][P out n]  M2L for delta = (c_t - c_s)/r = +4, +6;
+//                           delta = -4, -6 differ by (-1)^(m+n+1) (cot
+//                           kernel) or (-1)^(m+n) (log kernel)
+//   bin  [P][P]             C(t, j) at [t][j]
+//   reg1, reg2 [P t][P lo]  level-2 regular part (Eq. p20 and its log analogue)
+template <typename R>
+struct OpTables {
+    const R *m2m, *l2l, *m2l4, *m2l6, *bin, *reg1, *reg2;
+};
+
 template <typename R, typename V>
 struct UpArgs {
     int64_t N;
@@ -98,10 +113,7 @@ struct UpArgs {
     V *mp;                       // multipoles, levels 2..l
     V *loc2;                     // level-2 local polynomials, 4 x P
     V *S;                        // sum of the weights (cot kernel)
-    // operators
-    const R *m2m;                // [2][P in][P out]
-    const R *bin;                // [P][P] binomial C(t, j) at [t][j]
-    const R *reg1, *reg2;        // [P t][P lo]
+    OpTables<R> T;
     double logc1, logc2;         // log kernel: log(2 pi / N), log 2
 };
 
@@ -168,12 +180,16 @@ template <typename R, typename V, int KER, int SRC>
 __global__ void __launch_bounds__(BLOCK) k_up(UpArgs<R, V> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    V *buf0 = reinterpret_cast<V *>(smem_raw);
-    __shared__ int s_last;
     const int P = a.P;
+    R *tm2m = reinterpret_cast<R *>(smem_raw);
+    V *buf0 = reinterpret_cast<V *>(tm2m + P * P);
+    __shared__ int s_last;
     const int tid = threadIdx.x;
     int band = 0;
     int64_t node = blockIdx.x;
+
+    for (int i = tid; i < P * P; i += BLOCK)
+        tm2m[i] = a.T.m2m[i];
 
     for (;;) {
         const int lb = a.band_lo[band];
@@ -209,15 +225,22 @@ __global__ void __launch_bounds__(BLOCK) k_up(UpArgs<R, V> a)
             V *g = a.mp + lev_off(lev, P) + pfirst * P;
             for (int idx = tid; idx < n * P; idx += BLOCK) {
                 const int i = idx / P, nn = idx - i * P;
-                V acc = vzero<V>();
-                for (int c = 0; c < 2; ++c) {
-                    const R *T = a.m2m + (size_t)c * P * P;
-                    const V *ch = cur + (size_t)(2 * i + c) * P;
-                    for (int m = 0; m <= nn; ++m)
-                        vfma(acc, T[m * P + nn], ch[m]);
+                const V *cl = cur + (size_t)(2 * i) * P;
+                const V *cr = cl + P;
+                V al = vzero<V>(), ar = vzero<V>();
+                for (int m = nn; m >= 0; m -= 2) {   // n - m even
+                    const R t = tm2m[m * P + nn];
+                    vfma(al, t, cl[m]);
+                    vfma(ar, t, cr[m]);
                 }
-                nxt[idx] = acc;
-                g[idx] = acc;
+                for (int m = nn - 1; m >= 0; m -= 2) { // n - m odd
+                    const R t = tm2m[m * P + nn];
+                    vfma(al, t, cl[m]);
+                    vfma(ar, -t, cr[m]);
+                }
+                vadd(al, ar);
+                nxt[idx] = al;
+                g[idx] = al;
             }
             __syncthreads();
             V *t = cur;
@@ -262,7 +285,7 @@ __global__ void __launch_bounds__(BLOCK) k_up(UpArgs<R, V> a)
         const V *rgt = a2 + ((q + 1) & 3) * P;
         R pw = R(1);
         for (int j = t; j >= 0; --j) {
-            R cb = a.bin[t * P + j] * pw;
+            R cb = a.T.bin[t * P + j] * pw;
             vfma(acc, cb, rgt[j]);
             vfma(acc, ((t - j) & 1) ? -cb : cb, lft[j]);
             pw *= R(2);
@@ -276,8 +299,8 @@ __global__ void __launch_bounds__(BLOCK) k_up(UpArgs<R, V> a)
         const V *n1 = A1 + q * P;
         V acc = vzero<V>();
         for (int t = 0; t < P; ++t) {
-            vfma(acc, a.reg1[t * P + lo], n1[t]);
-            vfma(acc, a.reg2[t * P + lo], o[t]);
+            vfma(acc, a.T.reg1[t * P + lo], n1[t]);
+            vfma(acc, a.T.reg2[t * P + lo], o[t]);
         }
         if constexpr (KER == KER_LOG) {
             if (lo == 0)
@@ -308,11 +331,12 @@ template <typename R, typename V>
 struct DownArgs {
     int64_t N;
     int l, P, lr;
+    int nbuf;                // rows of each LDS local buffer: max(2^s, lr)
+    int near_cap;            // LDS slots for the forward near-field sources
     const WorkItem *work;
     const V *mp;
     const V *loc2;
-    const R *l2l;     // [2][P in][P out]
-    const R *m2l;     // [4][P in][P out], offsets delta = -6, -4, 4, 6
+    OpTables<R> T;
     // sources of the near field
     SortedSet src;
     const cx<R> *f_uniform;
@@ -330,50 +354,51 @@ struct DownArgs {
     double logself;          // LOGCD: log(2 pi / N), the excluded self term
 };
 
-// Local expansion coefficient n of box B at level lev: L2L from the parent
-// local plus M2L from the interaction list (left child: source offsets
-// -2, +2, +3 boxes; right child: -3, -2, +2).  cot kernel coefficients are
-// in units of h: M2L carries (N/pi)/r = 2^(lev+1)/pi.  The log kernel adds
-// a_0 log r to the constant term (the M2L table holds log|delta|).
-template <typename R, typename V, int KER>
-__device__ __forceinline__ V down_coeff(const DownArgs<R, V> &a, int lev,
-                                        int64_t B, int n, const V *ploc)
+// M2L of the three interaction-list boxes of box B at level lev onto output
+// coefficient n (left child: source offsets -2, +2, +3 boxes, i.e. delta =
+// +4, -4, -6; right child: -3, -2, +2, i.e. delta = +6, +4, -4).  srcrow(o)
+// returns the multipole of box B + o.  cot coefficients are in units of h:
+// the 1/t M2L carries (N/pi)/r = 2^(lev+1)/pi.  The log kernel adds
+// a_0 log r to the constant term (its tables hold log|delta|).
+template <typename R, typename V, int KER, typename SrcRow>
+__device__ __forceinline__ V m2l_coeff(const R *t4, const R *t6, int P,
+                                       int lev, int64_t B, int n, int64_t N,
+                                       SrcRow srcrow)
 {
-    const int P = a.P;
-    V acc = vzero<V>();
-    const R *T = a.l2l + (size_t)(B & 1) * P * P;
-    for (int m = n; m < P; ++m)
-        vfma(acc, T[m * P + n], ploc[m]);
-    const int64_t mask = (int64_t(1) << lev) - 1;
-    int offs[3], didx[3];
-    if ((B & 1) == 0) {
-        offs[0] = -2; didx[0] = 2;  // delta = +4
-        offs[1] = 2;  didx[1] = 1;  // delta = -4
-        offs[2] = 3;  didx[2] = 0;  // delta = -6
-    } else {
-        offs[0] = -3; didx[0] = 3;  // delta = +6
-        offs[1] = -2; didx[1] = 2;  // delta = +4
-        offs[2] = 2;  didx[2] = 1;  // delta = -4
+    // sign of T_{-delta} relative to T_delta: (-1)^(m+n+1) (cot), (-1)^(m+n) (log)
+    const bool neg_odd = ((n + (KER == KER_COT ? 1 : 0)) & 1) != 0;
+    V pos = vzero<V>(), neg = vzero<V>();
+    R a0 = R(0);
+    const bool left = (B & 1) == 0;
+    const V *s_p4 = srcrow(-2);              // delta = +4: offset -2
+    const V *s_m4 = srcrow(2);               // delta = -4: offset +2
+    const V *s_6 = srcrow(left ? 3 : -3);    // delta = -6 (left) / +6 (right)
+    for (int m = 0; m < P; ++m) {
+        const R a4 = t4[m * P + n];
+        const R a6 = t6[m * P + n];
+        vfma(pos, a4, s_p4[m]);
+        // T_{-4}[m][n] = +-(-1)^m T_4[m][n]
+        const R sm = (m & 1) ? -a4 : a4;
+        vfma(neg, sm, s_m4[m]);
+        if (left) {
+            const R s6 = (m & 1) ? -a6 : a6;
+            vfma(neg, s6, s_6[m]);
+        } else {
+            vfma(pos, a6, s_6[m]);
+        }
     }
-    V far = vzero<V>();
-    R a0sum = R(0);
-    for (int i = 0; i < 3; ++i) {
-        const V *as = a.mp + lev_off(lev, P) + ((B + offs[i]) & mask) * P;
-        const R *M = a.m2l + (size_t)didx[i] * P * P;
-        for (int m = 0; m < P; ++m)
-            vfma(far, M[m * P + n], as[m]);
-        if constexpr (KER == KER_LOG)
-            a0sum += as[0];
-    }
+    if (neg_odd)
+        neg = vscale(neg, R(-1));
+    vadd(pos, neg);
     if constexpr (KER == KER_COT) {
-        const R sc = (R)(ldexp(2.0, lev) / 3.14159265358979323846);
-        vfma(acc, sc, far);
+        return vscale(pos, (R)(ldexp(2.0, lev) / 3.14159265358979323846));
     } else {
-        acc += far;
-        if (n == 0)
-            acc += a0sum * (R)log(ldexp((double)a.N, -(lev + 1)));
+        if (n == 0) {
+            a0 = (R)((double)s_p4[0] + (double)s_m4[0] + (double)s_6[0]);
+            pos += a0 * (R)log(ldexp((double)N, -(lev + 1)));
+        }
+        return pos;
     }
-    return acc;
 }
 
 template <typename R, typename V>
@@ -388,15 +413,52 @@ __device__ __forceinline__ V horner(const V *c, int P, R u)
     return acc;
 }
 
+// 1/d to full binary64 (or binary32) precision: hardware reciprocal refined
+// by Newton steps.
+__device__ __forceinline__ double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float d)
+{
+    float r = __builtin_amdgcn_rcpf(d);
+    float e = fmaf(-d, r, 1.0f);
+    return fmaf(r, e, r);
+}
+
 // Near field of the cot kernel: sum over the sources of leaves b-1, b, b+1
 // (unwrapped around the circle) of w / (tau - sigma~).
 template <typename R, typename V, int SRC>
 __device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
-                                          double tth, int64_t leaf)
+                                          double tth, int64_t leaf,
+                                          const cx<R> *fs, int64_t K0)
 {
     const int64_t N = a.N;
     const int64_t nleaf = int64_t(1) << a.l;
     cx<R> acc = {R(0), R(0)};
+    if constexpr (SRC == SET_UNIFORM) {
+        if (fs) { // sources staged in LDS from unwrapped index K0 on
+            auto ustart = [&](int64_t b) {
+                if (b < 0)
+                    return uni_start(b + nleaf, a.l, N) - N;
+                if (b > nleaf)
+                    return uni_start(b - nleaf, a.l, N) + N;
+                return uni_start(b, a.l, N);
+            };
+            const int64_t k0 = ustart(leaf - 1), k1 = ustart(leaf + 2);
+            for (int64_t k = k0; k < k1; ++k) {
+                const R rd = recip((R)((double)(tm - k) + tth));
+                const cx<R> w = fs[k - K0];
+                acc.re = fma(w.re, rd, acc.re);
+                acc.im = fma(w.im, rd, acc.im);
+            }
+            return acc;
+        }
+    }
     for (int dl = -1; dl <= 1; ++dl) {
         int64_t b = leaf + dl, shift = 0;
         if (b < 0) {
@@ -409,18 +471,17 @@ __device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
         if constexpr (SRC == SET_UNIFORM) {
             const int64_t k0 = uni_start(b, a.l, N), k1 = uni_start(b + 1, a.l, N);
             for (int64_t k = k0; k < k1; ++k) {
-                double d = (double)(tm - k - shift) + tth;
-                R rd = R(1) / (R)d;
-                cx<R> w = a.f_uniform[k];
+                const R rd = recip((R)((double)(tm - k - shift) + tth));
+                const cx<R> w = a.f_uniform[k];
                 acc.re = fma(w.re, rd, acc.re);
                 acc.im = fma(w.im, rd, acc.im);
             }
         } else {
             const int32_t t0 = a.src.off[b], t1 = a.src.off[b + 1];
             for (int32_t t = t0; t < t1; ++t) {
-                double d = grid_diff(tm - a.src.m[t] - shift, tth, a.src.th[t]);
-                R rd = R(1) / (R)d;
-                cx<R> w = a.w_sorted[t];
+                const double d = grid_diff(tm - a.src.m[t] - shift, tth, a.src.th[t]);
+                const R rd = recip((R)d);
+                const cx<R> w = a.w_sorted[t];
                 acc.re = fma(w.re, rd, acc.re);
                 acc.im = fma(w.im, rd, acc.im);
             }
@@ -471,35 +532,111 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int P = a.P;
     const int s = a.l - a.lr;
-    V *bufA = reinterpret_cast<V *>(smem_raw);
-    V *bufB = bufA + ((size_t)1 << s) * P;
+    const int PP = P * P;
+    R *t4 = reinterpret_cast<R *>(smem_raw);
+    R *t6 = t4 + PP;
+    R *tll = t6 + PP;
+    V *bufA = reinterpret_cast<V *>(tll + PP);
+    V *bufB = bufA + (size_t)a.nbuf * P;
+    V *srcs = bufB + (size_t)a.nbuf * P;       // (2^s + 6) x P
+    // near-field staging reuses the source buffer once the translations are
+    // done (near_cap slots of cx<R>)
+    cx<R> *fs = reinterpret_cast<cx<R> *>(srcs);
     const int tid = threadIdx.x;
     const WorkItem w = a.work[blockIdx.x];
     const int64_t R0 = w.root;
     const int lr = a.lr;
+    const int64_t N = a.N;
 
-    // local of the subtree root, from level 2 down
-    for (int n = tid; n < P; n += BLOCK)
-        bufA[n] = a.loc2[(R0 >> (lr - 2)) * P + n];
+    for (int i = tid; i < PP; i += BLOCK) {
+        t4[i] = a.T.m2l4[i];
+        t6[i] = a.T.m2l6[i];
+        tll[i] = a.T.l2l[i];
+    }
+    __syncthreads();
+
+    // ---- local expansion of the subtree root R0 (level lr).  The local of
+    // a box is the sum over its ancestors A_L (L = 2..lr) of the M2L result
+    // at A_L (the regular-part polynomial for L = 2) shifted straight from
+    // the centre of A_L to the centre of R0:
+    //   u_A = rho u_R + delta,  b^R_n = sum_{n'>=n} C(n',n) rho^n delta^(n'-n) b^A_n'.
+    const int nL = lr - 1; // levels 2..lr
+    V *X = bufA;           // X[L-2][n]
+    V *Y = bufB;
+    for (int idx = tid; idx < nL * P; idx += BLOCK) {
+        const int li = idx / P, n = idx - li * P;
+        const int L = li + 2;
+        const int64_t A = R0 >> (lr - L);
+        if (L == 2) {
+            X[idx] = a.loc2[A * P + n];
+        } else {
+            const int64_t mask = (int64_t(1) << L) - 1;
+            const V *base = a.mp + lev_off(L, P);
+            X[idx] = m2l_coeff<R, V, KER>(t4, t6, P, L, A, n, N, [&](int o) {
+                return base + ((A + o) & mask) * P;
+            });
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nL * P; idx += BLOCK) {
+        const int li = idx / P, n = idx - li * P;
+        const int L = li + 2;
+        const int64_t A = R0 >> (lr - L);
+        const int sh = lr - L;
+        // rho = 2^-sh; delta = ((2 R0 + 1) - (2A + 1) 2^sh) / 2^sh
+        const R rho2 = (R)ldexp(2.0, -sh);                     // 2 rho
+        const R md2 = (R)(-2.0 * ldexp((double)((2 * R0 + 1) - ((2 * A + 1) << sh)), -sh));
+        // C(n',n) = tll[n'][n] 2^n' (-1)^(n'-n) = tll[n'][n] 2^n (-2)^(n'-n)
+        const V *x = X + li * P;
+        V acc = vzero<V>();
+        R pw = R(1);
+        for (int np = n; np < P; ++np) {
+            vfma(acc, tll[np * P + n] * pw, x[np]);
+            pw *= md2;
+        }
+        Y[idx] = vscale(acc, ipow(rho2, n));
+    }
     __syncthreads();
     V *cur = bufA, *nxt = bufB;
-    for (int lev = 3; lev <= lr; ++lev) {
-        const int64_t B = R0 >> (lr - lev);
-        for (int n = tid; n < P; n += BLOCK)
-            nxt[n] = down_coeff<R, V, KER>(a, lev, B, n, cur);
-        __syncthreads();
-        V *t = cur;
-        cur = nxt;
-        nxt = t;
+    for (int n = tid; n < P; n += BLOCK) {
+        V acc = Y[n];
+        for (int li = 1; li < nL; ++li)
+            vadd(acc, Y[li * P + n]);
+        cur[n] = acc; // X is no longer needed
     }
-    // the subtree's levels
+    __syncthreads();
+
+    // ---- the subtree's levels: L2L from the parent + M2L from the level's
+    // interaction lists (sources staged in LDS)
     for (int lev = lr + 1; lev <= a.l; ++lev) {
         const int nb = 1 << (lev - lr);
         const int64_t first = R0 << (lev - lr);
+        const int64_t mask = (int64_t(1) << lev) - 1;
+        const V *base = a.mp + lev_off(lev, P);
+        for (int idx = tid; idx < (nb + 6) * P; idx += BLOCK) {
+            const int i = idx / P, m = idx - i * P;
+            srcs[idx] = base[((first - 3 + i) & mask) * P + m];
+        }
+        __syncthreads();
         for (int idx = tid; idx < nb * P; idx += BLOCK) {
             const int i = idx / P, n = idx - i * P;
-            nxt[idx] = down_coeff<R, V, KER>(a, lev, first + i, n,
-                                             cur + (size_t)(i >> 1) * P);
+            const int64_t B = first + i;
+            const V *par = cur + (size_t)(i >> 1) * P;
+            V acc = vzero<V>();
+            if ((B & 1) == 0) {
+                for (int m = n; m < P; ++m)
+                    vfma(acc, tll[m * P + n], par[m]);
+            } else {
+                for (int m = n; m < P; ++m) {
+                    const R t = tll[m * P + n];
+                    vfma(acc, ((m - n) & 1) ? -t : t, par[m]);
+                }
+            }
+            V far = m2l_coeff<R, V, KER>(t4, t6, P, lev, B, n, N, [&](int o) {
+                return srcs + (size_t)(i + 3 + o) * P;
+            });
+            vadd(acc, far);
+            nxt[idx] = acc;
         }
         __syncthreads();
         V *t = cur;
@@ -508,9 +645,32 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
     }
     const V *leafloc = cur;
     const int64_t leaf0 = R0 << s;
-    const int64_t N = a.N;
 
     if constexpr (EPI == EPI_FWD) {
+        // stage the near-field sources of the subtree (uniform sources)
+        const cx<R> *fsp = nullptr;
+        int64_t K0 = 0;
+        if constexpr (SRC == SET_UNIFORM) {
+            const int64_t nleaf = int64_t(1) << a.l;
+            auto ustart = [&](int64_t b) {
+                if (b < 0)
+                    return uni_start(b + nleaf, a.l, N) - N;
+                if (b > nleaf)
+                    return uni_start(b - nleaf, a.l, N) + N;
+                return uni_start(b, a.l, N);
+            };
+            K0 = ustart(leaf0 - 1);
+            const int64_t K1 = ustart(leaf0 + (1 << s) + 1);
+            if (K1 - K0 <= a.near_cap) {
+                for (int64_t i = tid; i < K1 - K0; i += BLOCK) {
+                    int64_t k = K0 + i;
+                    k = k < 0 ? k + N : (k >= N ? k - N : k);
+                    fs[i] = a.f_uniform[k];
+                }
+                fsp = fs;
+            }
+            __syncthreads();
+        }
         const V S = *a.S;
         const double hscale = (double)N / 3.14159265358979323846;
         for (int32_t t = w.t0 + tid; t < w.t1; t += BLOCK) {
@@ -524,7 +684,7 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
             const int64_t leaf = box_of(tm, th, a.l, N);
             const R u = (R)rel_coord(tm, th, leaf, a.l, N);
             V h = horner<R, V>(leafloc + (leaf - leaf0) * P, P, u);
-            cx<R> nr = near_cot<R, V, SRC>(a, tm, th, leaf);
+            cx<R> nr = near_cot<R, V, SRC>(a, tm, th, leaf, fsp, K0);
             double hr = (double)h.re + hscale * (double)nr.re;
             double hi = (double)h.im + hscale * (double)nr.im;
             // g = -(F/2)(S + i h), F = 2i sin(pi th) e^{i pi th} / N
@@ -546,7 +706,7 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
             const int64_t leaf = box_of(k, 0.0, a.l, N);
             const R u = (R)rel_coord(k, 0.0, leaf, a.l, N);
             V h = horner<R, V>(leafloc + (leaf - leaf0) * P, P, u);
-            cx<R> nr = near_cot<R, V, SRC>(a, k, 0.0, leaf);
+            cx<R> nr = near_cot<R, V, SRC>(a, k, 0.0, leaf, nullptr, 0);
             double hr = (double)h.re + hscale * (double)nr.re;
             double hi = (double)h.im + hscale * (double)nr.im;
             // f = -(C/2)(W + i h)
