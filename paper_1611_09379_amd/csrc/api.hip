@@ -110,7 +110,6 @@ static int default_depth(int64_t N, int64_t M, int dtype)
     return std::min(24, std::max(2, l));
 }
 
-static int round8(int x) { return (x + 7) & ~7; }
 
 static double eps_floor(int dtype) { return dtype == FN_C64 ? 1e-7 : 1e-15; }
 
@@ -159,40 +158,43 @@ struct Tables {
 // Regular part at level 2 (Eq. p20 and its log analogue) in the variable
 // u = (y - x_c)/(pi/4), with A_t the moments of Omega_1 (reg1) or of the
 // opposite quarter (reg2) about the centre x_c in units of pi/4.
-static void build_tables(int P, int q, int kernel, Tables &T)
+// Multipole sizes are PU, local sizes PD.
+static void build_tables(int PU, int PD, int q, int kernel, Tables &T)
 {
-    const int PP = P * P;
-    T.m2m.assign(PP, 0);
-    T.l2l.assign(PP, 0);
-    T.m2l4.assign(PP, 0);
-    T.m2l6.assign(PP, 0);
-    T.bin.assign(PP, 0);
-    T.reg1.assign(PP, 0);
-    T.reg2.assign(PP, 0);
-    // Pascal triangle and powers, exact in long double for these sizes
-    std::vector<long double> C((2 * P) * (2 * P), 0);
-    for (int n = 0; n < 2 * P; ++n) {
-        C[n * 2 * P] = 1;
+    T.m2m.assign(PU * PU, 0);
+    T.bin.assign(PU * PU, 0);
+    T.l2l.assign(PD * PD, 0);
+    T.m2l4.assign(PD * PD, 0);
+    T.m2l6.assign(PD * PD, 0);
+    T.reg1.assign(PU * PD, 0);
+    T.reg2.assign(PU * PD, 0);
+    const int NB = 2 * std::max(PU, PD) + 2;
+    std::vector<long double> C(NB * NB, 0);
+    for (int n = 0; n < NB; ++n) {
+        C[n * NB] = 1;
         for (int k = 1; k <= n; ++k)
-            C[n * 2 * P + k] = C[(n - 1) * 2 * P + k - 1] + (k < n ? C[(n - 1) * 2 * P + k] : 0);
+            C[n * NB + k] = C[(n - 1) * NB + k - 1] + (k < n ? C[(n - 1) * NB + k] : 0);
     }
     auto binom = [&](int n, int k) -> long double {
-        return (k < 0 || k > n) ? 0 : C[n * 2 * P + k];
+        return (k < 0 || k > n) ? 0 : C[n * NB + k];
     };
-    for (int n = 0; n < P; ++n)
-        for (int m = 0; m <= n; ++m) {
-            long double v = binom(n, m) * ldexpl(1.0L, -n) * (((n - m) & 1) ? -1 : 1);
-            T.m2m[m * P + n] = v; // [in m][out n]
-            T.l2l[n * P + m] = v; // [in n][out m]
-        }
+    auto shiftc = [&](int n, int m) -> long double { // C(n,m) 2^-n (-1)^(n-m)
+        return binom(n, m) * ldexpl(1.0L, -n) * (((n - m) & 1) ? -1 : 1);
+    };
+    for (int n = 0; n < PU; ++n)
+        for (int m = 0; m <= n; ++m)
+            T.m2m[m * PU + n] = shiftc(n, m); // [in m][out n]
+    for (int n = 0; n < PD; ++n)
+        for (int m = 0; m <= n; ++m)
+            T.l2l[n * PD + m] = shiftc(n, m); // [in n][out m]
     for (int di = 0; di < 2; ++di) {
         const long double d = di == 0 ? 4 : 6;
-        std::vector<long double> &M = di == 0 ? T.m2l4 : T.m2l6;
-        std::vector<long double> ip(2 * P + 2, 1);
-        for (int j = 1; j < 2 * P + 2; ++j)
+        std::vector<long double> &Mt = di == 0 ? T.m2l4 : T.m2l6;
+        std::vector<long double> ip(2 * PD + 2, 1);
+        for (int j = 1; j < 2 * PD + 2; ++j)
             ip[j] = ip[j - 1] / d; // d^-j
-        for (int m = 0; m < P; ++m)
-            for (int n = 0; n < P; ++n) {
+        for (int m = 0; m < PD; ++m)
+            for (int n = 0; n < PD; ++n) {
                 long double v;
                 if (kernel == KER_COT) {
                     v = ((n & 1) ? -1 : 1) * binom(m + n, n) * ip[m + n + 1];
@@ -205,15 +207,15 @@ static void build_tables(int P, int q, int kernel, Tables &T)
                 } else {
                     v = -binom(m + n - 1, n) * ((n & 1) ? -1 : 1) * ip[m + n] / m;
                 }
-                M[m * P + n] = v;
+                Mt[m * PD + n] = v;
             }
     }
-    for (int t = 0; t < P; ++t)
+    for (int t = 0; t < PU; ++t)
         for (int j = 0; j <= t; ++j)
-            T.bin[t * P + j] = binom(t, j);
+            T.bin[t * PU + j] = binom(t, j);
     const long double qpi = 0.785398163397448309615660845819875721L; // pi/4
-    std::vector<long double> fac(2 * P + 2, 1);
-    for (int i = 1; i < 2 * P + 2; ++i)
+    std::vector<long double> fac(2 * PU + 4, 1);
+    for (int i = 1; i < (int)fac.size(); ++i)
         fac[i] = fac[i - 1] * i;
     for (int m = 1; m <= q; ++m) {
         const long double B = bernoulli_abs(m);
@@ -221,38 +223,38 @@ static void build_tables(int P, int q, int kernel, Tables &T)
         const int top = kernel == KER_COT ? 2 * m - 1 : 2 * m;
         for (int lo = 0; lo <= top; ++lo) {
             const int t = top - lo;
-            if (lo >= P || t >= P)
+            if (lo >= PD || t >= PU)
                 continue;
             const long double w = kernel == KER_COT ? B / m : B / (2 * m);
             const long double kap = -(powl(qpi, lo) / fac[lo]) * w *
                                     (powl(-qpi, t) / fac[t]);
-            T.reg1[t * P + lo] = kap;
-            T.reg2[t * P + lo] = kap * four_m;
+            T.reg1[t * PD + lo] = kap;
+            T.reg2[t * PD + lo] = kap * four_m;
         }
     }
 }
 
-// Device copies of the tables, built once per (precision, kernel, P, q,
-// device) and kept for the life of the process.
+// Device copies of the tables, built once per (precision, kernel, PU, PD,
+// q, device) and kept for the life of the process.
 struct TableSet {
     void *base = nullptr;
     size_t off[7] = {0};
 };
 
 static std::mutex g_tab_mu;
-static std::map<std::tuple<int, int, int, int, int>, TableSet> g_tab_cache;
+static std::map<std::tuple<int, int, int, int, int, int>, TableSet> g_tab_cache;
 
 template <typename R>
-static int get_tables(int kernel, int Pn, int q, OpTables<R> *out)
+static int get_tables(int kernel, int PU, int PD, int q, OpTables<R> *out)
 {
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
-    const auto key = std::make_tuple((int)sizeof(R), kernel, Pn, q, dev);
+    const auto key = std::make_tuple((int)sizeof(R), kernel, PU, PD, q, dev);
     std::lock_guard<std::mutex> lk(g_tab_mu);
     auto it = g_tab_cache.find(key);
     if (it == g_tab_cache.end()) {
         Tables T;
-        build_tables(Pn, q, kernel, T);
+        build_tables(PU, PD, q, kernel, T);
         std::vector<R> h;
         TableSet ts;
         const std::vector<long double> *parts[7] = {&T.m2m, &T.l2l, &T.m2l4, &T.m2l6,
@@ -274,22 +276,30 @@ static int get_tables(int kernel, int Pn, int q, OpTables<R> *out)
 
 // ------------------------------------------------------------------ plan
 
+static constexpr int MAX_BANDS = 8;
+
+struct Band {
+    int lb, d, first, grid;
+    size_t smem;
+};
+
 // Workspace and launch shapes of one FMM (cot or log kernel) on a tree.
 struct FmmSetup {
-    int Pn = 0, q = 0;
-    Buf mp, loc2, S, cnt;
+    int PU = 0, PD = 0, q = 0;
+    int RSu = 0, RSd = 0;          // LDS row strides (elements of R)
+    Buf mp, loc2, S;
     int nbands = 0;
-    int band_lo[MAX_BANDS] = {0}, band_d[MAX_BANDS] = {0};
-    int cnt_off[MAX_BANDS + 1] = {0};
-    int up_grid = 0;
-    size_t up_smem = 0, dn_smem = 0;
-    int nbuf = 0, near_cap = 0;
+    Band band[MAX_BANDS];
+    int top_lb = 2;
+    size_t top_smem = 0;
+    size_t dn_smem = 0;
+    int rows_buf = 0, rows_src = 0, near_cap = 0;
 };
 
 struct fn_plan {
     int kind = 0, dtype = 0;
     int64_t N = 0, M = 0;
-    int p = 0, q = 0, l = 0, P = 0;
+    int p = 0, q = 0, l = 0;
     double eps = 0;
     int lr = 2; // subtree root level of k_down_eval
     // points sorted into the leaves (targets of the forward, sources of the
@@ -303,7 +313,7 @@ struct fn_plan {
     std::vector<Buf *> all()
     {
         return {&off, &sm, &sth, &sperm, &work, &cot.mp, &cot.loc2, &cot.S,
-                &cot.cnt, &hit, &chat, &dhat, &wsorted};
+                &hit, &chat, &dhat, &wsorted};
     }
 };
 
@@ -327,40 +337,7 @@ static void release_plan(fn_plan *P)
         release(*b);
 }
 
-static constexpr int UP_DMAX = 4; // levels per band of k_up
-static constexpr int DN_S = 4;    // subtree depth of k_down_eval
-
-// Bands of k_up: climbs of at most dmax levels from the leaves to level 2.
-static void make_bands(int l, FmmSetup &F, int *ncnt)
-{
-    int nb = 0, lo = l;
-    while (true) {
-        int d = std::min(UP_DMAX, lo - 2);
-        F.band_lo[nb] = lo;
-        F.band_d[nb] = d;
-        ++nb;
-        lo -= d;
-        if (lo == 2)
-            break;
-    }
-    F.nbands = nb;
-    // band k (k >= 1) has 2^(band_lo[k] - band_d[k]) nodes; the final stage one
-    int off = 0;
-    for (int k = 1; k < nb; ++k) {
-        F.cnt_off[k] = off;
-        off += 1 << (F.band_lo[k] - F.band_d[k]);
-    }
-    F.cnt_off[nb] = off;
-    *ncnt = off + 1;
-    F.up_grid = 1 << (l - F.band_d[0]);
-}
-
-template <typename R, typename V>
-static size_t down_smem(int Pn, int s, int nbuf)
-{
-    return 3 * (size_t)Pn * Pn * sizeof(R) + 2 * (size_t)nbuf * Pn * sizeof(V) +
-           (((size_t)1 << s) + 6) * Pn * sizeof(V);
-}
+static int round16(int x) { return std::min(64, std::max(16, (x + 15) & ~15)); }
 
 static size_t lds_limit()
 {
@@ -372,44 +349,90 @@ static size_t lds_limit()
     return (size_t)v;
 }
 
-// Subtree root level: the deepest subtrees (at most DN_S levels) whose
-// k_down_eval workspace fits in LDS for both expansion lengths used.
-template <typename R, typename V>
-static int choose_lr(int l, int Pn)
+// LDS row stride: nc * P elements of size es, padded so that a row's start
+// moves by 4 nc banks (of 64) from one row to the next: the matrix-core
+// B-operand loads of a wavefront then hit distinct banks.
+static int row_stride(int nc, int P, int es)
+{
+    const int w0 = nc * P * es / 4;
+    const int pad_w = ((4 * nc - w0) % 64 + 64) % 64;
+    return nc * P + pad_w * 4 / es;
+}
+
+static size_t down_lds(int s, int lr, int RS, int es, int *rows_buf, int *rows_src)
+{
+    const int nA = lr - 2;
+    *rows_buf = std::max(1 << s, nA + 1);
+    *rows_src = std::max((1 << s) + 6, 3 * nA);
+    return (size_t)(2 * *rows_buf + *rows_src) * RS * es;
+}
+
+// Subtree root level of k_down_eval: subtrees of at most 4 levels whose
+// workspace fits in LDS.
+static int choose_lr(int l, int nc, int PD, int es)
 {
     const size_t lim = lds_limit();
-    for (int s = std::min(DN_S, l - 2); s >= 0; --s) {
-        const int lr = l - s;
-        const int nbuf = std::max(1 << s, lr);
-        if (down_smem<R, V>(Pn, s, nbuf) <= lim)
-            return lr;
+    const int RS = row_stride(nc, PD, es);
+    for (int s = std::min(4, l - 2); s >= 0; --s) {
+        int rb, rsrc;
+        if (down_lds(s, l - s, RS, es, &rb, &rsrc) <= lim)
+            return l - s;
     }
     return l;
 }
 
 template <typename R, typename V>
-static int setup_fmm(fn_plan *P, int kernel, int Pn, int q, bool near_stage,
+static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool near_stage,
                      FmmSetup &F, hipStream_t st)
 {
-    F.Pn = Pn;
+    constexpr int NC = ncomp<V>::value;
+    const int es = sizeof(R);
+    F.PU = PU;
+    F.PD = PD;
     F.q = q;
-    int ncnt = 0;
-    make_bands(P->l, F, &ncnt);
-    const int64_t nmp = lev_off(P->l + 1, Pn);
-    if (!alloc(F.mp, nmp * sizeof(V)) || !alloc(F.loc2, 4 * Pn * sizeof(V)) ||
-        !alloc(F.S, sizeof(V)) || !alloc(F.cnt, ncnt * 4))
-        return fail(FN_ENOMEM, "expansion allocation failed");
-    HIPCHK(hipMemsetAsync(F.cnt.p, 0, ncnt * 4, st));
-    const int nbot = 1 << std::max(F.band_d[0], 0);
-    F.up_smem = (size_t)Pn * Pn * sizeof(R) +
-                (size_t)std::max(nbot + std::max(nbot / 2, 1), 8) * Pn * sizeof(V);
+    F.RSu = row_stride(NC, PU, es);
+    F.RSd = row_stride(NC, PD, es);
+    const size_t lim = lds_limit();
+    // bands of the upward pass: the leaves' band (at most 4 levels), then
+    // bands of at most 5 levels down to the top level handled by one
+    // workgroup (at most 7, as long as its multipoles fit in LDS)
+    int ttop = std::min(7, P->l);
+    while (ttop > 2 && (size_t)((1 << ttop) + std::max(1 << (ttop - 1), 4)) * F.RSu * es > lim)
+        --ttop;
+    F.nbands = 0;
+    int lb = P->l;
+    {
+        const int d = std::min(4, std::max(0, lb - std::max(ttop, 2)));
+        const int d0 = lb - d < 2 ? lb - 2 : d;
+        F.band[F.nbands++] = {lb, d0, 1, 1 << (lb - d0),
+                              (size_t)((1 << d0) + std::max((1 << d0) / 2, 1)) * F.RSu * es};
+        lb -= d0;
+    }
+    while (lb > ttop) {
+        const int d = std::min(5, lb - ttop);
+        F.band[F.nbands++] = {lb, d, 0, 1 << (lb - d),
+                              (size_t)((1 << d) + std::max((1 << d) / 2, 1)) * F.RSu * es};
+        lb -= d;
+    }
+    F.top_lb = lb;
+    F.top_smem = (size_t)((1 << lb) + std::max(1 << (lb - 1), 4)) * F.RSu * es;
+    if (F.top_smem > lim)
+        return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PU, F.top_smem);
+    for (int b = 0; b < F.nbands; ++b)
+        if (F.band[b].smem > lim)
+            return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PU,
+                        F.band[b].smem);
     const int s = P->l - P->lr;
-    F.nbuf = std::max(1 << s, P->lr);
-    F.dn_smem = down_smem<R, V>(Pn, s, F.nbuf);
-    F.near_cap = near_stage ? (int)((((size_t)1 << s) + 6) * Pn * sizeof(V) / sizeof(cx<R>)) : 0;
-    if (F.dn_smem > lds_limit())
-        return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", Pn, F.dn_smem);
+    F.dn_smem = down_lds(s, P->lr, F.RSd, es, &F.rows_buf, &F.rows_src);
+    if (F.dn_smem > lim)
+        return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PD, F.dn_smem);
+    F.near_cap = near_stage ? (int)((size_t)F.rows_src * F.RSd * es / sizeof(cx<R>)) : 0;
+    const int64_t nmp = lev_off(P->l + 1, PU);
+    if (!alloc(F.mp, nmp * sizeof(V)) || !alloc(F.loc2, 4 * PD * sizeof(V)) ||
+        !alloc(F.S, sizeof(V)))
+        return fail(FN_ENOMEM, "expansion allocation failed");
     (void)kernel;
+    (void)st;
     return FN_OK;
 }
 
@@ -419,12 +442,8 @@ static void fill_up(const fn_plan *P, const FmmSetup &F, const OpTables<R> &T,
 {
     ua.N = P->N;
     ua.l = P->l;
-    ua.P = F.Pn;
-    ua.nbands = F.nbands;
-    std::memcpy(ua.band_lo, F.band_lo, sizeof ua.band_lo);
-    std::memcpy(ua.band_d, F.band_d, sizeof ua.band_d);
-    std::memcpy(ua.cnt_off, F.cnt_off, sizeof ua.cnt_off);
-    ua.cnt = (int *)F.cnt.p;
+    ua.RS = F.RSu;
+    ua.PD = F.PD;
     ua.mp = (V *)F.mp.p;
     ua.loc2 = (V *)F.loc2.p;
     ua.S = (V *)F.S.p;
@@ -437,15 +456,64 @@ static void fill_down(const fn_plan *P, const FmmSetup &F, const OpTables<R> &T,
 {
     da.N = P->N;
     da.l = P->l;
-    da.P = F.Pn;
     da.lr = P->lr;
-    da.nbuf = F.nbuf;
+    da.RS = F.RSd;
+    da.rows_buf = F.rows_buf;
+    da.rows_src = F.rows_src;
     da.near_cap = F.near_cap;
     da.work = (const WorkItem *)P->work.p;
     da.mp = (const V *)F.mp.p;
+    da.PU = F.PU;
     da.loc2 = (const V *)F.loc2.p;
     da.S = (const V *)F.S.p;
     da.T = T;
+}
+
+// Launches with the expansion lengths as template arguments.
+#define FN_DISPATCH16(val, NAME, ...)                                          \
+    switch (val) {                                                             \
+    case 16: { constexpr int NAME = 16; __VA_ARGS__; } break;                  \
+    case 32: { constexpr int NAME = 32; __VA_ARGS__; } break;                  \
+    case 48: { constexpr int NAME = 48; __VA_ARGS__; } break;                  \
+    default: { constexpr int NAME = 64; __VA_ARGS__; } break;                  \
+    }
+
+// The upward pass: the bands, then the top.  ua must be filled except for
+// the band fields.
+template <typename R, typename V, int KER, int SRC>
+static int launch_up(const FmmSetup &F, UpArgs<R, V> ua, hipStream_t st)
+{
+    for (int b = 0; b < F.nbands; ++b) {
+        ua.lb = F.band[b].lb;
+        ua.d = F.band[b].d;
+        ua.first_band = F.band[b].first;
+        FN_DISPATCH16(F.PU, PU_,
+                      hipLaunchKernelGGL((k_up_band<R, V, KER, SRC, PU_>),
+                                         dim3(F.band[b].grid), dim3(BLOCK),
+                                         F.band[b].smem, st, ua));
+        HIPCHK(hipGetLastError());
+    }
+    ua.lb = F.top_lb;
+    ua.d = F.top_lb - 2;
+    ua.first_band = 0;
+    FN_DISPATCH16(F.PU, PU_,
+                  hipLaunchKernelGGL((k_up_top<R, V, KER, PU_>), dim3(1), dim3(BLOCK),
+                                     F.top_smem, st, ua));
+    HIPCHK(hipGetLastError());
+    return FN_OK;
+}
+
+template <typename R, typename V, int KER, int SRC, int EPI>
+static int launch_down(const fn_plan *P, const FmmSetup &F, const DownArgs<R, V> &da,
+                       hipStream_t st)
+{
+    if (P->nwork == 0)
+        return FN_OK;
+    FN_DISPATCH16(F.PD, PD_,
+                  hipLaunchKernelGGL((k_down_eval<R, V, KER, SRC, EPI, PD_>),
+                                     dim3(P->nwork), dim3(BLOCK), F.dn_smem, st, da));
+    HIPCHK(hipGetLastError());
+    return FN_OK;
 }
 
 // Double-double N / (2 pi): 1/(2 pi) = ONE_OVER_2PI_HI + ONE_OVER_2PI_LO.
@@ -607,6 +675,13 @@ static int build_work(fn_plan *P, bool sorted_targets, bool uniform_targets,
     return FN_OK;
 }
 
+// Expansion lengths of the cot FMM for (p, q).
+static void cot_lengths(int p, int q, int *PU, int *PD)
+{
+    *PD = round16(p);
+    *PU = round16(std::max(*PD, 2 * q));
+}
+
 // --------------------------------------------------------- forward plan
 
 template <typename R>
@@ -615,19 +690,17 @@ static int plan_fwd_impl(fn_plan *P, const double *y, hipStream_t st)
     int rc = build_tree(P, P->M, y, false, false, st);
     if (rc)
         return rc;
-    P->lr = choose_lr<R, cx<R>>(P->l, P->P);
+    int PU, PD;
+    cot_lengths(P->p, P->q, &PU, &PD);
+    P->lr = choose_lr(P->l, 2, PD, sizeof(R));
     rc = build_work(P, true, false, st);
     if (rc)
         return rc;
-    rc = setup_fmm<R, cx<R>>(P, KER_COT, P->P, P->q, true, P->cot, st);
+    rc = setup_fmm<R, cx<R>>(P, KER_COT, PU, PD, P->q, true, P->cot, st);
     if (rc)
         return rc;
     OpTables<R> T;
-    rc = get_tables<R>(KER_COT, P->P, P->q, &T);
-    if (rc)
-        return rc;
-    HIPCHK(hipStreamSynchronize(st));
-    return FN_OK;
+    return get_tables<R>(KER_COT, PU, PD, P->q, &T);
 }
 
 template <typename R>
@@ -635,31 +708,29 @@ static int exec_fwd(fn_plan *P, const void *in, void *out, int phase,
                     hipStream_t st)
 {
     using V = cx<R>;
+    const FmmSetup &F = P->cot;
     OpTables<R> T;
-    int rc = get_tables<R>(KER_COT, P->P, P->q, &T);
+    int rc = get_tables<R>(KER_COT, F.PU, F.PD, F.q, &T);
     if (rc)
         return rc;
     if (phase != 1) {
         UpArgs<R, V> ua{};
-        fill_up(P, P->cot, T, ua);
+        fill_up(P, F, T, ua);
         ua.f_uniform = (const cx<R> *)in;
-        hipLaunchKernelGGL((k_up<R, V, KER_COT, SET_UNIFORM>), dim3(P->cot.up_grid),
-                           dim3(BLOCK), P->cot.up_smem, st, ua);
-        HIPCHK(hipGetLastError());
+        rc = launch_up<R, V, KER_COT, SET_UNIFORM>(F, ua, st);
+        if (rc)
+            return rc;
     }
-    if (P->nwork == 0 || phase == 0)
+    if (phase == 0)
         return FN_OK;
     DownArgs<R, V> da{};
-    fill_down(P, P->cot, T, da);
+    fill_down(P, F, T, da);
     da.f_uniform = (const cx<R> *)in;
     da.tgt = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
               (const double *)P->sth.p, (const int32_t *)P->sperm.p};
     da.out = (cx<R> *)out;
     da.f_hit = (const cx<R> *)in;
-    hipLaunchKernelGGL((k_down_eval<R, V, KER_COT, SET_UNIFORM, EPI_FWD>),
-                       dim3(P->nwork), dim3(BLOCK), P->cot.dn_smem, st, da);
-    HIPCHK(hipGetLastError());
-    return FN_OK;
+    return launch_down<R, V, KER_COT, SET_UNIFORM, EPI_FWD>(P, F, da, st);
 }
 
 // --------------------------------------------------------- inverse plan
@@ -675,18 +746,19 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     const double eps_log = std::max(P->eps * 0.1, 1e-15);
     int plog, qlog;
     trunc_numbers(eps_log, P->l, &plog, &qlog);
-    const int Plog = round8(std::max(plog, 2 * qlog + 1));
+    const int PD = round16(plog);
+    const int PU = round16(std::max(PD, 2 * qlog + 1));
     OpTables<R> T;
-    int rc = get_tables<R>(KER_LOG, Plog, qlog, &T);
+    int rc = get_tables<R>(KER_LOG, PU, PD, qlog, &T);
     if (rc)
         return rc;
     FmmSetup F;
     Buf logc, logd, flags;
     auto cleanup = [&]() {
-        for (Buf *b : {&F.mp, &F.loc2, &F.S, &F.cnt, &logc, &logd, &flags})
+        for (Buf *b : {&F.mp, &F.loc2, &F.S, &logc, &logd, &flags})
             release(*b);
     };
-    rc = setup_fmm<R, V>(P, KER_LOG, Plog, qlog, false, F, st);
+    rc = setup_fmm<R, V>(P, KER_LOG, PU, PD, qlog, false, F, st);
     if (!rc && !(alloc(logc, P->N * 8) && alloc(logd, P->N * 8) && alloc(flags, 4)))
         rc = fail(FN_ENOMEM, "log-sum allocation failed");
     if (rc) {
@@ -700,10 +772,8 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     ua.src = src;
     ua.logc1 = std::log(2.0 * M_PI / (double)P->N);
     ua.logc2 = std::log(2.0);
-    hipLaunchKernelGGL((k_up<R, V, KER_LOG, SET_SORTED>), dim3(F.up_grid),
-                       dim3(BLOCK), F.up_smem, st, ua);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) {
+    rc = launch_up<R, V, KER_LOG, SET_SORTED>(F, ua, st);
+    if (!rc) {
         DownArgs<R, V> da{};
         fill_down(P, F, T, da);
         da.src = src;
@@ -711,13 +781,12 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
         da.logc = (double *)logc.p;
         da.logd = (double *)logd.p;
         da.logself = std::log(2.0 * M_PI / (double)P->N);
-        hipLaunchKernelGGL((k_down_eval<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>),
-                           dim3(P->nwork), dim3(BLOCK), F.dn_smem, st, da);
-        e = hipGetLastError();
+        rc = launch_down<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>(P, F, da, st);
     }
-    if (e == hipSuccess)
+    hipError_t e = hipSuccess;
+    if (!rc)
         e = hipMemsetAsync(flags.p, 0, 4, st);
-    if (e == hipSuccess) {
+    if (!rc && e == hipSuccess) {
         hipLaunchKernelGGL(k_coeffs, dim3(grid_for(P->N)), dim3(256), 0, st, P->N,
                            (const double *)logc.p, (const double *)logd.p,
                            (const int32_t *)P->sm.p, (const double *)P->sth.p,
@@ -726,11 +795,15 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
         e = hipGetLastError();
     }
     int hflags = 0;
-    if (e == hipSuccess)
+    if (!rc && e == hipSuccess)
         e = hipMemcpyAsync(&hflags, flags.p, 4, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess)
+    if (!rc && e == hipSuccess)
         e = hipStreamSynchronize(st);
+    else if (rc)
+        (void)hipStreamSynchronize(st);
     cleanup();
+    if (rc)
+        return rc;
     if (e != hipSuccess)
         return fail(FN_EHIP, "inverse plan: %s", hipGetErrorString(e));
     if (hflags & FLAG_RANGE)
@@ -745,9 +818,11 @@ static int plan_inv_impl(fn_plan *P, const double *y, hipStream_t st)
     int rc = build_tree(P, P->N, y, true, true, st);
     if (rc)
         return rc;
-    // one subtree level serves the log FMM (double, at most 64 terms) and
-    // the cot FMM
-    P->lr = std::max(choose_lr<R, cx<R>>(P->l, P->P), choose_lr<double, double>(P->l, 64));
+    int PU, PD;
+    cot_lengths(P->p, P->q, &PU, &PD);
+    // one subtree level serves the log FMM (binary64, real, at most 64
+    // terms) and the cot FMM
+    P->lr = std::max(choose_lr(P->l, 2, PD, sizeof(R)), choose_lr(P->l, 1, 64, 8));
     rc = build_work(P, true, true, st);
     if (rc)
         return rc;
@@ -757,15 +832,11 @@ static int plan_inv_impl(fn_plan *P, const double *y, hipStream_t st)
     rc = plan_inv_logs(P, st);
     if (rc)
         return rc;
-    rc = setup_fmm<R, cx<R>>(P, KER_COT, P->P, P->q, false, P->cot, st);
+    rc = setup_fmm<R, cx<R>>(P, KER_COT, PU, PD, P->q, false, P->cot, st);
     if (rc)
         return rc;
     OpTables<R> T;
-    rc = get_tables<R>(KER_COT, P->P, P->q, &T);
-    if (rc)
-        return rc;
-    HIPCHK(hipStreamSynchronize(st));
-    return FN_OK;
+    return get_tables<R>(KER_COT, PU, PD, P->q, &T);
 }
 
 template <typename R>
@@ -773,37 +844,35 @@ static int exec_inv(fn_plan *P, const void *in, void *out, int phase,
                     hipStream_t st)
 {
     using V = cx<R>;
+    const FmmSetup &F = P->cot;
     OpTables<R> T;
-    int rc = get_tables<R>(KER_COT, P->P, P->q, &T);
+    int rc = get_tables<R>(KER_COT, F.PU, F.PD, F.q, &T);
     if (rc)
         return rc;
     const SortedSet src = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
                            (const double *)P->sth.p, (const int32_t *)P->sperm.p};
     if (phase != 1) {
         UpArgs<R, V> ua{};
-        fill_up(P, P->cot, T, ua);
+        fill_up(P, F, T, ua);
         ua.src = src;
         ua.dhat = (const cx<double> *)P->dhat.p;
         ua.gin = (const cx<R> *)in;
         ua.w_out = (cx<R> *)P->wsorted.p;
-        hipLaunchKernelGGL((k_up<R, V, KER_COT, SET_SORTED>), dim3(P->cot.up_grid),
-                           dim3(BLOCK), P->cot.up_smem, st, ua);
-        HIPCHK(hipGetLastError());
+        rc = launch_up<R, V, KER_COT, SET_SORTED>(F, ua, st);
+        if (rc)
+            return rc;
     }
     if (phase == 0)
         return FN_OK;
     DownArgs<R, V> da{};
-    fill_down(P, P->cot, T, da);
+    fill_down(P, F, T, da);
     da.src = src;
     da.w_sorted = (const cx<R> *)P->wsorted.p;
     da.out = (cx<R> *)out;
     da.chat = (const double *)P->chat.p;
     da.hit = (const int32_t *)P->hit.p;
     da.gin = (const cx<R> *)in;
-    hipLaunchKernelGGL((k_down_eval<R, V, KER_COT, SET_SORTED, EPI_INV>),
-                       dim3(P->nwork), dim3(BLOCK), P->cot.dn_smem, st, da);
-    HIPCHK(hipGetLastError());
-    return FN_OK;
+    return launch_down<R, V, KER_COT, SET_SORTED, EPI_INV>(P, F, da, st);
 }
 
 // ------------------------------------------------------------------ ABI
@@ -855,10 +924,10 @@ static int plan_common(fn_plan **out, int kind, int64_t N, int64_t M,
     P->M = M;
     P->eps = eps;
     choose(N, M, eps, dtype, p_in, q_in, l_in, &P->p, &P->q, &P->l);
-    P->P = round8(std::max(P->p, 2 * P->q));
-    if (P->P > 64) {
+    if (P->p > 64 || 2 * P->q > 64) {
+        const int p = P->p, q = P->q;
         delete P;
-        return fail(FN_EINVAL, "expansion length %d exceeds 64", P->P);
+        return fail(FN_EINVAL, "truncation numbers p = %d, q = %d need more than 64 terms", p, q);
     }
     hipStream_t st = (hipStream_t)stream;
     if (kind == 0)
@@ -955,7 +1024,7 @@ int nufft_plan_get_info(const fn_plan *plan, fn_plan_info *info)
     info->p = plan->p;
     info->q = plan->q;
     info->lmax = plan->l;
-    info->nterms = plan->P;
+    info->nterms = plan->cot.PD;
     info->eps = plan->eps;
     return FN_OK;
 }

@@ -12,16 +12,22 @@
 //        the MLFMM, and the term-wise integrals of Eq. (10) and (11) (divided
 //        by 2) as the regular part.
 //
+// Expansions: multipoles carry PU terms (PU >= 2q: the level-2 moments feed
+// the regular part up to degree 2q - 1); locals and translations carry
+// PD <= PU terms (the MLFMM truncation p, rounded up to the 16-row tiles of
+// the matrix cores).  Coefficients live in LDS as rows of RS elements of
+// type R (complex data interleaved re, im), RS padded so that the matrix-core
+// operand loads are free of bank conflicts.
+//
 // Kernels:
-//   k_up         P2M at the leaves and M2M to level 2, by bands of levels;
-//                the last workgroup to finish a band's subtree carries on
-//                with the parent subtree (no grid-wide wait), and the last
-//                one overall turns the level-2 moments into the level-2
-//                local polynomial of the regular part (Eq. p20).
-//   k_down_eval  for one subtree of the finest levels: the local expansion
-//                of its root from level 2 down (L2L + M2L over interaction
-//                lists), the subtree's locals, then every target in it:
-//                L2P + near-field P2P + the transform's epilogue.
+//   k_up_band    P2M at the leaves (first band) or a load of the band's
+//                bottom multipoles, then M2M up the band (matrix cores).
+//   k_up_top     one workgroup: M2M of the last levels down to level 2 and
+//                the level-2 local polynomial of the regular part (Eq. p20).
+//   k_down_eval  one subtree of the finest levels: the local of its root as
+//                the sum of the ancestors' M2L results shifted straight to
+//                the root, the subtree's L2L + M2L (matrix cores), then every
+//                target in it: L2P + near-field P2P + the transform epilogue.
 #pragma once
 
 #include "fmm_device.h"
@@ -32,16 +38,15 @@ enum { KER_COT = 0, KER_LOG = 1 };
 enum { SET_UNIFORM = 0, SET_SORTED = 1 };
 enum { EPI_FWD = 0, EPI_INV = 1, EPI_LOGCD = 2 };
 
-constexpr int MAX_BANDS = 16;
-constexpr int CH = 8;          // moments per thread in P2M
-constexpr int BLOCK = 256;
+constexpr int CH = 8;      // moments per thread in P2M
+constexpr int BLOCK = 256; // 4 wavefronts of 64
 
 // Points sorted by leaf: off[b]..off[b+1] index the points of leaf b.
 struct SortedSet {
     const int32_t *off;
-    const int32_t *m;   // integer part of the representative (0..N)
-    const double *th;   // fraction in [-1/2, 1/2]
-    const int32_t *perm;// sorted position -> input index
+    const int32_t *m;    // integer part of the representative (0..N)
+    const double *th;    // fraction in [-1/2, 1/2]
+    const int32_t *perm; // sorted position -> input index
 };
 
 template <typename V>
@@ -78,49 +83,119 @@ __device__ __forceinline__ void vadd(cx<R> &a, cx<R> b)
 template <typename R>
 __device__ __forceinline__ void vadd(R &a, R b) { a += b; }
 
-// ------------------------------------------------------------------ k_up
+// Number of real components of a coefficient type.
+template <typename V>
+struct ncomp { static constexpr int value = 1; };
+template <typename R>
+struct ncomp<cx<R>> { static constexpr int value = 2; };
 
-// Operator tables (type R) shared by all plans with the same (P, q, kernel):
-//   m2m  [P in m][P out n]  M2M for the left child (centre c_p - r_p/2):
-//                           C(n,m) 2^-n (-1)^(n-m); the right child differs
-//                           by (-1)^(n-m)
-//   l2l  [P in n][P out m]  L2L to the left child, same coefficients
-//   m2l4, m2l6 [P in m][P out n]  M2L for delta = (c_t - c_s)/r = +4, +6;
-//                           delta = -4, -6 differ by (-1)^(m+n+1) (cot
-//                           kernel) or (-1)^(m+n) (log kernel)
-//   bin  [P][P]             C(t, j) at [t][j]
-//   reg1, reg2 [P t][P lo]  level-2 regular part (Eq. p20 and its log analogue)
+// Coefficient n of row `row` of an LDS coefficient array.
+template <typename R, typename V>
+__device__ __forceinline__ V ld_coef(const R *base, int RS, int row, int n)
+{
+    if constexpr (ncomp<V>::value == 2) {
+        const R *p = base + (size_t)row * RS + 2 * n;
+        return V{p[0], p[1]};
+    } else {
+        return base[(size_t)row * RS + n];
+    }
+}
+template <typename R, typename V>
+__device__ __forceinline__ void st_coef(R *base, int RS, int row, int n, V v)
+{
+    if constexpr (ncomp<V>::value == 2) {
+        R *p = base + (size_t)row * RS + 2 * n;
+        p[0] = v.re;
+        p[1] = v.im;
+    } else {
+        base[(size_t)row * RS + n] = v;
+    }
+}
+
+// ------------------------------------------------------------ matrix cores
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <typename R>
+struct acc_t;
+template <>
+struct acc_t<double> { typedef d4 type; };
+template <>
+struct acc_t<float> { typedef f4 type; };
+
+// D(16x16) += A(16x4) B(4x16).  Lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; it receives D rows out_row(l, r), r = 0..3, of column
+// l % 16 (binary64 interleaves the rows, binary32 blocks them).
+__device__ __forceinline__ d4 mma(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mma(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename R>
+__device__ __forceinline__ int out_row(int lane, int r)
+{
+    if constexpr (sizeof(R) == 8)
+        return 4 * r + (lane >> 4);
+    else
+        return 4 * (lane >> 4) + r;
+}
+
+// Operator tables (type R) shared by all plans with the same (PU, PD, q,
+// kernel), each stored [input index][output index]:
+//   m2m  PU x PU   M2M from the left child (centre c_p - r_p/2):
+//                  C(n,m) 2^-n (-1)^(n-m); the right child differs by (-1)^(n-m)
+//   l2l  PD x PD   L2L to the left child, same coefficients
+//   m2l4, m2l6 PD x PD  M2L for delta = (c_t - c_s)/r = +4, +6; delta = -4, -6
+//                  differ by (-1)^(m+n+1) (cot kernel) or (-1)^(m+n) (log)
+//   bin  PU x PU   C(t, j) at [t][j]
+//   reg1, reg2 PU x PD  level-2 regular part (Eq. p20 and its log analogue)
 template <typename R>
 struct OpTables {
     const R *m2m, *l2l, *m2l4, *m2l6, *bin, *reg1, *reg2;
 };
 
+// A-operands of one 16-row tile of a square operator, held in registers:
+// a[ks] = T[row = 16 rt + lane % 16][k = 4 ks + lane / 16] = tab[k][row].
+template <typename R, int K>
+__device__ __forceinline__ void load_tile(R (&a)[K / 4], const R *tab, int rt,
+                                          int lane)
+{
+    const int row = 16 * rt + (lane & 15);
+#pragma unroll
+    for (int ks = 0; ks < K / 4; ++ks)
+        a[ks] = tab[(4 * ks + (lane >> 4)) * K + row];
+}
+
+// ------------------------------------------------------------------ k_up
+
 template <typename R, typename V>
 struct UpArgs {
     int64_t N;
-    int l, P, nbands;
-    int band_lo[MAX_BANDS]; // bottom level of each band
-    int band_d[MAX_BANDS];  // levels the band climbs
-    int cnt_off[MAX_BANDS + 1];
-    int *cnt;               // arrival counters, zero between launches
-    // sources
+    int l;         // leaf level
+    int lb, d;     // this launch: bottom level and levels climbed
+    int RS;        // LDS row stride (elements of R)
+    int PD;        // local expansion terms (level-2 polynomial)
+    int first_band;
+    // sources (first band)
     SortedSet src;
-    const cx<R> *f_uniform;      // forward: f_k at the uniform points
-    const cx<double> *dhat;      // inverse: Dhat_j in sorted order
-    const cx<R> *gin;            // inverse: g_j in input order
-    cx<R> *w_out;                // inverse: w_j = Dhat_j g_j (sorted)
+    const cx<R> *f_uniform;  // forward: f_k at the uniform points
+    const cx<double> *dhat;  // inverse: Dhat_j in sorted order
+    const cx<R> *gin;        // inverse: g_j in input order
+    cx<R> *w_out;            // inverse: w_j = Dhat_j g_j (sorted)
     // outputs
-    V *mp;                       // multipoles, levels 2..l
-    V *loc2;                     // level-2 local polynomials, 4 x P
-    V *S;                        // sum of the weights (cot kernel)
+    V *mp;                   // multipoles, levels 2..l, PU per box
+    V *loc2;                 // level-2 local polynomials, 4 x PD
+    V *S;                    // sum of the weights (cot kernel)
     OpTables<R> T;
-    double logc1, logc2;         // log kernel: log(2 pi / N), log 2
+    double logc1, logc2;     // log kernel: log(2 pi / N), log 2
 };
 
-// P2M at leaf b (cot or log kernel) for CH consecutive moments m0..m0+CH-1.
-// Moments are a_m = sum w (sigma - c)^m / r^m over the leaf's sources; the
-// log kernel takes unit weights minus the uniform density of one point per
-// grid unit (whose moments are 2r/(m+1) for even m).
+// P2M at leaf b for CH consecutive moments m0..m0+CH-1: a_m = sum w v^m with
+// v = (sigma - c)/r.  The log kernel takes unit weights minus the uniform
+// density of one point per grid unit (moments 2r/(m+1) for even m).
 template <typename R, typename V, int KER, int SRC>
 __device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, int64_t b,
                                           int m0, V *acc, bool store_w)
@@ -176,144 +251,176 @@ __device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, int64_t b,
     }
 }
 
-template <typename R, typename V, int KER, int SRC>
-__global__ void __launch_bounds__(BLOCK) k_up(UpArgs<R, V> a)
+// M2M of one level inside LDS: np parents from 2 np children (rows of cur),
+// written to nxt (LDS) and g (global, PU per box).  Each wave takes 16-row
+// tiles of the parents' moments; its operator tile sits in registers.
+template <typename R, typename V, int PU>
+__device__ __forceinline__ void m2m_level(const R (&am)[PU / 4], int rt,
+                                          int ct0, int ctstep, int lane, int np,
+                                          const R *cur, R *nxt, int RS, V *g)
+{
+    constexpr int NC = ncomp<V>::value;
+    using A = typename acc_t<R>::type;
+    const int nct = (NC * np + 15) / 16;
+    for (int ct = ct0; ct < nct; ct += ctstep) {
+        const int j = 16 * ct + (lane & 15);
+        const int p = j / NC, c = j % NC;
+        const bool valid = p < np;
+        const int pc = valid ? p : 0;
+        const R *cl = cur + (size_t)(2 * pc) * RS + c;
+        const R *cr = cl + RS;
+        A al = {0, 0, 0, 0}, ar = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < PU / 4; ++ks) {
+            const int m = 4 * ks + (lane >> 4);
+            R bl = cl[m * NC], br = cr[m * NC];
+            if (!valid) {
+                bl = R(0);
+                br = R(0);
+            }
+            if (m & 1)
+                br = -br;
+            al = mma(am[ks], bl, al);
+            ar = mma(am[ks], br, ar);
+        }
+        if (valid) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * rt + out_row<R>(lane, r);
+                const R v = al[r] + ((n & 1) ? -ar[r] : ar[r]);
+                nxt[(size_t)p * RS + n * NC + c] = v;
+                reinterpret_cast<R *>(g)[((size_t)p * PU + n) * NC + c] = v;
+            }
+        }
+    }
+}
+
+// One launch of the upward pass: 2^d boxes of level lb (the leaves, by P2M,
+// in the first band) up to level lb - d.
+template <typename R, typename V, int KER, int SRC, int PU>
+__global__ void __launch_bounds__(BLOCK) k_up_band(UpArgs<R, V> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int P = a.P;
-    R *tm2m = reinterpret_cast<R *>(smem_raw);
-    V *buf0 = reinterpret_cast<V *>(tm2m + P * P);
-    __shared__ int s_last;
-    const int tid = threadIdx.x;
-    int band = 0;
-    int64_t node = blockIdx.x;
-
-    for (int i = tid; i < P * P; i += BLOCK)
-        tm2m[i] = a.T.m2m[i];
-
-    for (;;) {
-        const int lb = a.band_lo[band];
-        const int d = a.band_d[band];
-        const int nbot = 1 << d;
-        const int64_t first = node << d;
-        V *buf1 = buf0 + (size_t)nbot * P;
-        if (band == 0) {
-            const int nch = P / CH;
-            V *g = a.mp + lev_off(lb, P);
-            for (int idx = tid; idx < nbot * nch; idx += BLOCK) {
-                const int i = idx / nch, ch = idx - i * nch;
-                V acc[CH];
-                p2m_chunk<R, V, KER, SRC>(a, first + i, ch * CH, acc, ch == 0);
-                for (int c = 0; c < CH; ++c) {
-                    buf0[i * P + ch * CH + c] = acc[c];
-                    g[(first + i) * P + ch * CH + c] = acc[c];
-                }
+    R *buf0 = reinterpret_cast<R *>(smem_raw);
+    const int RS = a.RS;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lb = a.lb, d = a.d;
+    const int nbot = 1 << d;
+    const int64_t first = (int64_t)blockIdx.x << d;
+    R *buf1 = buf0 + (size_t)nbot * RS;
+    if (a.first_band) {
+        constexpr int nch = PU / CH;
+        V *g = a.mp + lev_off(lb, PU);
+        for (int idx = tid; idx < nbot * nch; idx += BLOCK) {
+            const int i = idx / nch, ch = idx - i * nch;
+            V acc[CH];
+            p2m_chunk<R, V, KER, SRC>(a, first + i, ch * CH, acc, ch == 0);
+            for (int c = 0; c < CH; ++c) {
+                st_coef<R, V>(buf0, RS, i, ch * CH + c, acc[c]);
+                g[(first + i) * PU + ch * CH + c] = acc[c];
             }
-        } else {
-            const V *g = a.mp + lev_off(lb, P) + first * P;
-            for (int idx = tid; idx < nbot * P; idx += BLOCK)
-                buf0[idx] = g[idx];
         }
-        __syncthreads();
-
-        // M2M up the band: a^parent_n = sum_c sum_{m<=n} M2M_c[m][n] a^c_m
-        V *cur = buf0, *nxt = buf1;
-        int n = nbot;
-        for (int lev = lb - 1; lev >= lb - d; --lev) {
-            n >>= 1;
-            const int64_t pfirst = first >> (lb - lev);
-            V *g = a.mp + lev_off(lev, P) + pfirst * P;
-            for (int idx = tid; idx < n * P; idx += BLOCK) {
-                const int i = idx / P, nn = idx - i * P;
-                const V *cl = cur + (size_t)(2 * i) * P;
-                const V *cr = cl + P;
-                V al = vzero<V>(), ar = vzero<V>();
-                for (int m = nn; m >= 0; m -= 2) {   // n - m even
-                    const R t = tm2m[m * P + nn];
-                    vfma(al, t, cl[m]);
-                    vfma(ar, t, cr[m]);
-                }
-                for (int m = nn - 1; m >= 0; m -= 2) { // n - m odd
-                    const R t = tm2m[m * P + nn];
-                    vfma(al, t, cl[m]);
-                    vfma(ar, -t, cr[m]);
-                }
-                vadd(al, ar);
-                nxt[idx] = al;
-                g[idx] = al;
-            }
-            __syncthreads();
-            V *t = cur;
-            cur = nxt;
-            nxt = t;
-        }
-
-        // hand the subtree root to the parent band
-        __threadfence();
-        __syncthreads();
-        const int nb1 = band + 1;
-        const int dn = (nb1 < a.nbands) ? a.band_d[nb1] : 2;
-        const int64_t parent = node >> dn;
-        if (tid == 0) {
-            int *c = a.cnt + a.cnt_off[nb1] + parent;
-            int old = atomicAdd(c, 1);
-            s_last = (old == (1 << dn) - 1);
-            if (s_last)
-                atomicExch(c, 0);
-        }
-        __syncthreads();
-        if (!s_last)
-            return;
-        __threadfence();
-        node = parent;
-        band = nb1;
-        if (band == a.nbands)
-            break;
+    } else {
+        const V *g = a.mp + lev_off(lb, PU) + first * PU;
+        for (int idx = tid; idx < nbot * PU; idx += BLOCK)
+            st_coef<R, V>(buf0, RS, idx / PU, idx % PU, g[idx]);
     }
-
-    // ---- level 2: regular part of Eq. (p20) as the level-2 local polynomial
-    V *a2 = buf0;          // [4][P] level-2 moments about the quarter centres
-    V *A1 = buf0 + 4 * P;  // [4][P] moments of Omega_1(P_n) about c_n
-    for (int idx = tid; idx < 4 * P; idx += BLOCK)
-        a2[idx] = a.mp[idx];
+    if (d == 0)
+        return;
+    constexpr int nrt = PU / 16;
+    const int used = (4 / nrt) * nrt;
+    R am[PU / 4];
+    const int rt = wave % nrt;
+    if (wave < used)
+        load_tile<R, PU>(am, a.T.m2m, rt, lane);
     __syncthreads();
-    for (int idx = tid; idx < 4 * P; idx += BLOCK) {
-        const int q = idx / P, t = idx - q * P;
-        // (v + 2i)^t expanded, i = -1, 0, +1 (unwrapped neighbours)
-        V acc = a2[q * P + t];
-        const V *lft = a2 + ((q + 3) & 3) * P;
-        const V *rgt = a2 + ((q + 1) & 3) * P;
+    R *cur = buf0, *nxt = buf1;
+    int n = nbot;
+    for (int lev = lb - 1; lev >= lb - d; --lev) {
+        n >>= 1;
+        if (wave < used)
+            m2m_level<R, V, PU>(am, rt, wave / nrt, 4 / nrt, lane, n, cur, nxt, RS,
+                                a.mp + lev_off(lev, PU) + (first >> (lb - lev)) * PU);
+        __syncthreads();
+        R *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+}
+
+// Last launch of the upward pass (one workgroup): the 2^lb multipoles of
+// level lb up to level 2, then the level-2 local polynomial of the regular
+// part of Eq. (p20) and the sum of the weights.
+template <typename R, typename V, int KER, int PU>
+__global__ void __launch_bounds__(BLOCK) k_up_top(UpArgs<R, V> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    R *buf0 = reinterpret_cast<R *>(smem_raw);
+    const int RS = a.RS;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lb = a.lb;
+    const int nbot = 1 << lb;
+    R *buf1 = buf0 + (size_t)nbot * RS; // max(nbot / 2, 4) rows
+    {
+        const V *g = a.mp + lev_off(lb, PU);
+        for (int idx = tid; idx < nbot * PU; idx += BLOCK)
+            st_coef<R, V>(buf0, RS, idx / PU, idx % PU, g[idx]);
+    }
+    constexpr int nrt = PU / 16;
+    const int used = (4 / nrt) * nrt;
+    R am[PU / 4];
+    const int rt = wave % nrt;
+    if (wave < used)
+        load_tile<R, PU>(am, a.T.m2m, rt, lane);
+    __syncthreads();
+    R *cur = buf0, *nxt = buf1;
+    int n = nbot;
+    for (int lev = lb - 1; lev >= 2; --lev) {
+        n >>= 1;
+        if (wave < used)
+            m2m_level<R, V, PU>(am, rt, wave / nrt, 4 / nrt, lane, n, cur, nxt, RS,
+                                a.mp + lev_off(lev, PU));
+        __syncthreads();
+        R *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    // level 2: A1 = moments of Omega_1(P_n) about c_n, the three quarters
+    // unwrapped around P_n: (v + 2i)^t expanded for i = -1, 0, +1
+    R *A1 = nxt; // 4 rows (the other buffer is free)
+    for (int idx = tid; idx < 4 * PU; idx += BLOCK) {
+        const int q = idx / PU, t = idx - q * PU;
+        V acc = ld_coef<R, V>(cur, RS, q, t);
         R pw = R(1);
         for (int j = t; j >= 0; --j) {
-            R cb = a.T.bin[t * P + j] * pw;
-            vfma(acc, cb, rgt[j]);
-            vfma(acc, ((t - j) & 1) ? -cb : cb, lft[j]);
+            const R cb = a.T.bin[t * PU + j] * pw;
+            vfma(acc, cb, ld_coef<R, V>(cur, RS, (q + 1) & 3, j));
+            vfma(acc, ((t - j) & 1) ? -cb : cb, ld_coef<R, V>(cur, RS, (q + 3) & 3, j));
             pw *= R(2);
         }
-        A1[idx] = acc;
+        st_coef<R, V>(A1, RS, q, t, acc);
     }
     __syncthreads();
-    for (int idx = tid; idx < 4 * P; idx += BLOCK) {
-        const int q = idx / P, lo = idx - q * P;
-        const V *o = a2 + ((q + 2) & 3) * P;
-        const V *n1 = A1 + q * P;
+    const int PD = a.PD;
+    for (int idx = tid; idx < 4 * PD; idx += BLOCK) {
+        const int q = idx / PD, lo = idx - q * PD;
         V acc = vzero<V>();
-        for (int t = 0; t < P; ++t) {
-            vfma(acc, a.T.reg1[t * P + lo], n1[t]);
-            vfma(acc, a.T.reg2[t * P + lo], o[t]);
+        for (int t = 0; t < PU; ++t) {
+            vfma(acc, a.T.reg1[t * PD + lo], ld_coef<R, V>(A1, RS, q, t));
+            vfma(acc, a.T.reg2[t * PD + lo], ld_coef<R, V>(cur, RS, (q + 2) & 3, t));
         }
         if constexpr (KER == KER_LOG) {
             if (lo == 0)
-                acc += (R)(a.logc1 * (double)n1[0] + a.logc2 * (double)o[0]);
+                acc += (R)(a.logc1 * (double)ld_coef<R, V>(A1, RS, q, 0) +
+                           a.logc2 * (double)ld_coef<R, V>(cur, RS, (q + 2) & 3, 0));
         }
         a.loc2[idx] = acc;
     }
     if constexpr (KER == KER_COT) {
         if (tid == 0) {
-            V s = a2[0];
-            vadd(s, a2[P]);
-            vadd(s, a2[2 * P]);
-            vadd(s, a2[3 * P]);
+            V s = ld_coef<R, V>(cur, RS, 0, 0);
+            for (int q = 1; q < 4; ++q)
+                vadd(s, ld_coef<R, V>(cur, RS, q, 0));
             *a.S = s;
         }
     }
@@ -322,20 +429,22 @@ __global__ void __launch_bounds__(BLOCK) k_up(UpArgs<R, V> a)
 // ------------------------------------------------------------ k_down_eval
 
 struct WorkItem {
-    int64_t root;      // subtree root at level lr
-    int32_t t0, t1;    // sorted-target range
-    int32_t u0, u1;    // uniform-target range
+    int64_t root;   // subtree root at level lr
+    int32_t t0, t1; // sorted-target range
+    int32_t u0, u1; // uniform-target range
 };
 
 template <typename R, typename V>
 struct DownArgs {
     int64_t N;
-    int l, P, lr;
-    int nbuf;                // rows of each LDS local buffer: max(2^s, lr)
-    int near_cap;            // LDS slots for the forward near-field sources
+    int l, lr;
+    int RS;                  // LDS row stride (elements of R)
+    int rows_buf, rows_src;  // rows of each local buffer / of the source buffer
+    int near_cap;            // LDS slots (cx<R>) for the forward near field
     const WorkItem *work;
-    const V *mp;
-    const V *loc2;
+    const V *mp;             // PU per box
+    int PU;
+    const V *loc2;           // 4 x PD
     OpTables<R> T;
     // sources of the near field
     SortedSet src;
@@ -354,67 +463,103 @@ struct DownArgs {
     double logself;          // LOGCD: log(2 pi / N), the excluded self term
 };
 
-// M2L of the three interaction-list boxes of box B at level lev onto output
-// coefficient n (left child: source offsets -2, +2, +3 boxes, i.e. delta =
-// +4, -4, -6; right child: -3, -2, +2, i.e. delta = +6, +4, -4).  srcrow(o)
-// returns the multipole of box B + o.  cot coefficients are in units of h:
-// the 1/t M2L carries (N/pi)/r = 2^(lev+1)/pi.  The log kernel adds
-// a_0 log r to the constant term (its tables hold log|delta|).
-template <typename R, typename V, int KER, typename SrcRow>
-__device__ __forceinline__ V m2l_coeff(const R *t4, const R *t6, int P,
-                                       int lev, int64_t B, int n, int64_t N,
-                                       SrcRow srcrow)
+// Register-held operator tiles of one wave (row tile rt of PD rows).
+template <typename R, int PD>
+struct DownOps {
+    R a4[PD / 4], a6[PD / 4], al[PD / 4];
+};
+
+// M2L (+ L2L) for up to 16/NC target boxes per column tile with matrix
+// cores.  For target column box i:
+//   out = sigma [T_4 a(i,-2) + T_-4 a(i,+2) + T_(-+6) a(i,+-3)] + L2L par(i)
+// (left child: offsets -2, +2, +3; right child: -3, -2, +2).  T_-delta and
+// the right-child L2L follow from T_delta and the left L2L by the sign
+// patterns (-1)^m on the input (applied to the B operand) and a per-row
+// sign on the output.  srcrow(i, o) -> LDS row of box i's neighbour at
+// offset o; parrow(i) -> LDS row of the parent local; isleft(i), sig(i),
+// lgr(i) per box; outrow(i) -> output row in outbase.
+template <typename R, typename V, int KER, int PD, bool WITH_L2L, typename SrcRow,
+          typename ParRow, typename IsLeft, typename Sigma, typename LogR,
+          typename OutRow>
+__device__ __forceinline__ void m2l_tiles(const DownOps<R, PD> &o, int rt, int ct0,
+                                          int ctstep, int lane, int nb,
+                                          const R *lds, const R *parbase, int RS,
+                                          SrcRow srcrow, ParRow parrow,
+                                          IsLeft isleft, Sigma sig,
+                                          LogR lgr, OutRow outrow, R *outbase)
 {
-    // sign of T_{-delta} relative to T_delta: (-1)^(m+n+1) (cot), (-1)^(m+n) (log)
-    const bool neg_odd = ((n + (KER == KER_COT ? 1 : 0)) & 1) != 0;
-    V pos = vzero<V>(), neg = vzero<V>();
-    R a0 = R(0);
-    const bool left = (B & 1) == 0;
-    const V *s_p4 = srcrow(-2);              // delta = +4: offset -2
-    const V *s_m4 = srcrow(2);               // delta = -4: offset +2
-    const V *s_6 = srcrow(left ? 3 : -3);    // delta = -6 (left) / +6 (right)
-    for (int m = 0; m < P; ++m) {
-        const R a4 = t4[m * P + n];
-        const R a6 = t6[m * P + n];
-        vfma(pos, a4, s_p4[m]);
-        // T_{-4}[m][n] = +-(-1)^m T_4[m][n]
-        const R sm = (m & 1) ? -a4 : a4;
-        vfma(neg, sm, s_m4[m]);
-        if (left) {
-            const R s6 = (m & 1) ? -a6 : a6;
-            vfma(neg, s6, s_6[m]);
-        } else {
-            vfma(pos, a6, s_6[m]);
+    constexpr int NC = ncomp<V>::value;
+    using A = typename acc_t<R>::type;
+    const int nct = (NC * nb + 15) / 16;
+    for (int ct = ct0; ct < nct; ct += ctstep) {
+        const int j = 16 * ct + (lane & 15);
+        const int i = j / NC, c = j % NC;
+        const bool valid = i < nb;
+        const int ic = valid ? i : 0;
+        const bool left = isleft(ic);
+        const R *sp4 = lds + (size_t)srcrow(ic, -2) * RS + c;
+        const R *sm4 = lds + (size_t)srcrow(ic, 2) * RS + c;
+        const R *s6 = lds + (size_t)srcrow(ic, left ? 3 : -3) * RS + c;
+        const R *sp = sp4;
+        if constexpr (WITH_L2L)
+            sp = parbase + (size_t)parrow(ic) * RS + c;
+        A p4 = {0, 0, 0, 0}, n4 = {0, 0, 0, 0}, a6 = {0, 0, 0, 0}, al = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < PD / 4; ++ks) {
+            const int m = 4 * ks + (lane >> 4);
+            const bool odd = (m & 1) != 0;
+            R b1 = sp4[m * NC], b2 = sm4[m * NC], b3 = s6[m * NC];
+            if (!valid) {
+                b1 = R(0);
+                b2 = R(0);
+                b3 = R(0);
+            }
+            if (odd) {
+                b2 = -b2;
+                if (left)
+                    b3 = -b3;
+            }
+            p4 = mma(o.a4[ks], b1, p4);
+            n4 = mma(o.a4[ks], b2, n4);
+            a6 = mma(o.a6[ks], b3, a6);
+            if constexpr (WITH_L2L) {
+                R b4 = sp[m * NC];
+                if (!valid)
+                    b4 = R(0);
+                if (odd && !left)
+                    b4 = -b4;
+                al = mma(o.al[ks], b4, al);
+            }
         }
-    }
-    if (neg_odd)
-        neg = vscale(neg, R(-1));
-    vadd(pos, neg);
-    if constexpr (KER == KER_COT) {
-        return vscale(pos, (R)(ldexp(2.0, lev) / 3.14159265358979323846));
-    } else {
-        if (n == 0) {
-            a0 = (R)((double)s_p4[0] + (double)s_m4[0] + (double)s_6[0]);
-            pos += a0 * (R)log(ldexp((double)N, -(lev + 1)));
+        if (!valid)
+            continue;
+        const R sg = sig(ic);
+        R a0 = R(0), lr0 = R(0);
+        if constexpr (KER == KER_LOG) {
+            a0 = sp4[0] + sm4[0] + s6[0];
+            lr0 = lgr(ic);
         }
-        return pos;
+        R *dst = outbase + (size_t)outrow(ic) * RS + c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * rt + out_row<R>(lane, r);
+            // output sign of the T_-delta family
+            const bool sneg = ((n + (KER == KER_COT ? 1 : 0)) & 1) != 0;
+            const R nv = sneg ? -n4[r] : n4[r];
+            const R v6 = (left && sneg) ? -a6[r] : a6[r];
+            R v = (p4[r] + nv + v6) * sg;
+            if constexpr (KER == KER_LOG) {
+                if (n == 0)
+                    v += a0 * lr0;
+            }
+            if constexpr (WITH_L2L)
+                v += (!left && (n & 1)) ? -al[r] : al[r];
+            dst[n * NC] = v;
+        }
     }
 }
 
-template <typename R, typename V>
-__device__ __forceinline__ V horner(const V *c, int P, R u)
-{
-    V acc = c[P - 1];
-    for (int n = P - 2; n >= 0; --n) {
-        V t = vscale(acc, u);
-        vadd(t, c[n]);
-        acc = t;
-    }
-    return acc;
-}
-
-// 1/d to full binary64 (or binary32) precision: hardware reciprocal refined
-// by Newton steps.
+// 1/d to full precision: hardware reciprocal refined by Newton steps.
 __device__ __forceinline__ double recip(double d)
 {
     double r = __builtin_amdgcn_rcp(d);
@@ -430,6 +575,29 @@ __device__ __forceinline__ float recip(float d)
     return fmaf(r, e, r);
 }
 
+template <typename R, typename V>
+__device__ __forceinline__ V horner(const R *base, int RS, int row, int P, R u)
+{
+    V acc = ld_coef<R, V>(base, RS, row, P - 1);
+    for (int n = P - 2; n >= 0; --n) {
+        V t = vscale(acc, u);
+        vadd(t, ld_coef<R, V>(base, RS, row, n));
+        acc = t;
+    }
+    return acc;
+}
+
+// First uniform point of leaf b for b in [-1, nleaf + 1], unwrapped.
+__device__ __forceinline__ int64_t uni_start_unwrapped(int64_t b, int l, int64_t N)
+{
+    const int64_t nleaf = int64_t(1) << l;
+    if (b < 0)
+        return uni_start(b + nleaf, l, N) - N;
+    if (b > nleaf)
+        return uni_start(b - nleaf, l, N) + N;
+    return uni_start(b, l, N);
+}
+
 // Near field of the cot kernel: sum over the sources of leaves b-1, b, b+1
 // (unwrapped around the circle) of w / (tau - sigma~).
 template <typename R, typename V, int SRC>
@@ -442,17 +610,14 @@ __device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
     cx<R> acc = {R(0), R(0)};
     if constexpr (SRC == SET_UNIFORM) {
         if (fs) { // sources staged in LDS from unwrapped index K0 on
-            auto ustart = [&](int64_t b) {
-                if (b < 0)
-                    return uni_start(b + nleaf, a.l, N) - N;
-                if (b > nleaf)
-                    return uni_start(b - nleaf, a.l, N) + N;
-                return uni_start(b, a.l, N);
-            };
-            const int64_t k0 = ustart(leaf - 1), k1 = ustart(leaf + 2);
-            for (int64_t k = k0; k < k1; ++k) {
-                const R rd = recip((R)((double)(tm - k) + tth));
-                const cx<R> w = fs[k - K0];
+            const int64_t k0 = uni_start_unwrapped(leaf - 1, a.l, N);
+            const int64_t k1 = uni_start_unwrapped(leaf + 2, a.l, N);
+            const int32_t base = (int32_t)(tm - k0);
+            const cx<R> *fp = fs + (k0 - K0);
+            const int32_t cnt = (int32_t)(k1 - k0);
+            for (int32_t i = 0; i < cnt; ++i) {
+                const R rd = recip((R)((double)(base - i) + tth));
+                const cx<R> w = fp[i];
                 acc.re = fma(w.re, rd, acc.re);
                 acc.im = fma(w.im, rd, acc.im);
             }
@@ -479,8 +644,8 @@ __device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
         } else {
             const int32_t t0 = a.src.off[b], t1 = a.src.off[b + 1];
             for (int32_t t = t0; t < t1; ++t) {
-                const double d = grid_diff(tm - a.src.m[t] - shift, tth, a.src.th[t]);
-                const R rd = recip((R)d);
+                const double dd = grid_diff(tm - a.src.m[t] - shift, tth, a.src.th[t]);
+                const R rd = recip((R)dd);
                 const cx<R> w = a.w_sorted[t];
                 acc.re = fma(w.re, rd, acc.re);
                 acc.im = fma(w.im, rd, acc.im);
@@ -515,8 +680,8 @@ __device__ __forceinline__ double near_log(const DownArgs<R, V> &a, int64_t tm,
         for (int32_t t = t0; t < t1; ++t) {
             if (t == self)
                 continue;
-            double d = grid_diff(tm - a.src.m[t] - shift, tth, a.src.th[t]);
-            acc += log(fabs(d));
+            double dd = grid_diff(tm - a.src.m[t] - shift, tth, a.src.th[t]);
+            acc += log(fabs(dd));
         }
     }
     // integral over [(leaf-1) N/2^l, (leaf+2) N/2^l) (unwrapped)
@@ -526,141 +691,133 @@ __device__ __forceinline__ double near_log(const DownArgs<R, V> &a, int64_t tm,
     return acc - (xlogx_m_x(hi) - xlogx_m_x(lo));
 }
 
-template <typename R, typename V, int KER, int SRC, int EPI>
+template <typename R, typename V, int KER, int SRC, int EPI, int PD>
 __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int P = a.P;
+    const int RS = a.RS;
     const int s = a.l - a.lr;
-    const int PP = P * P;
-    R *t4 = reinterpret_cast<R *>(smem_raw);
-    R *t6 = t4 + PP;
-    R *tll = t6 + PP;
-    V *bufA = reinterpret_cast<V *>(tll + PP);
-    V *bufB = bufA + (size_t)a.nbuf * P;
-    V *srcs = bufB + (size_t)a.nbuf * P;       // (2^s + 6) x P
-    // near-field staging reuses the source buffer once the translations are
-    // done (near_cap slots of cx<R>)
-    cx<R> *fs = reinterpret_cast<cx<R> *>(srcs);
-    const int tid = threadIdx.x;
+    R *bufA = reinterpret_cast<R *>(smem_raw);
+    R *bufB = bufA + (size_t)a.rows_buf * RS;
+    R *srcs = bufB + (size_t)a.rows_buf * RS;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const WorkItem w = a.work[blockIdx.x];
     const int64_t R0 = w.root;
     const int lr = a.lr;
     const int64_t N = a.N;
+    const int PU = a.PU;
 
-    for (int i = tid; i < PP; i += BLOCK) {
-        t4[i] = a.T.m2l4[i];
-        t6[i] = a.T.m2l6[i];
-        tll[i] = a.T.l2l[i];
+    constexpr int nrt = PD / 16;
+    const int used = (4 / nrt) * nrt;
+    const int rt = wave % nrt, ct0 = wave / nrt, ctstep = 4 / nrt;
+    DownOps<R, PD> ops;
+    if (wave < used) {
+        load_tile<R, PD>(ops.a4, a.T.m2l4, rt, lane);
+        load_tile<R, PD>(ops.a6, a.T.m2l6, rt, lane);
+        load_tile<R, PD>(ops.al, a.T.l2l, rt, lane);
+    }
+
+    // ---- local expansion of the subtree root R0 (level lr): the sum over
+    // its ancestors A_L (L = 2..lr) of the M2L result at A_L (the regular-
+    // part polynomial for L = 2) shifted from the centre of A_L to that of
+    // R0:  u_A = rho u_R + delta,
+    //      b^R_n = sum_{n' >= n} C(n', n) rho^n delta^(n'-n) b^A_n'.
+    const int nA = lr - 2; // ancestors with M2L: levels 3..lr
+    // stage the three interaction-list multipoles of every ancestor
+    for (int idx = tid; idx < 3 * nA * PD; idx += BLOCK) {
+        const int row = idx / PD, m = idx - row * PD;
+        const int ai = row / 3, which = row - ai * 3;
+        const int L = ai + 3;
+        const int64_t A = R0 >> (lr - L);
+        const int o = which == 0 ? -2 : (which == 1 ? 2 : ((A & 1) ? -3 : 3));
+        const int64_t mask = (int64_t(1) << L) - 1;
+        st_coef<R, V>(srcs, RS, row, m, a.mp[lev_off(L, PU) + ((A + o) & mask) * PU + m]);
+    }
+    // X row 0: the level-2 local of R0's quarter
+    for (int n = tid; n < PD; n += BLOCK)
+        st_coef<R, V>(bufA, RS, 0, n, a.loc2[(R0 >> (lr - 2)) * PD + n]);
+    __syncthreads();
+    if (nA > 0 && wave < used) {
+        m2l_tiles<R, V, KER, PD, false>(
+            ops, rt, ct0, ctstep, lane, nA, srcs, srcs, RS,
+            [&](int i, int o) { return 3 * i + (o == -2 ? 0 : (o == 2 ? 1 : 2)); },
+            [&](int) { return 0; },
+            [&](int i) { return ((R0 >> (lr - (i + 3))) & 1) == 0; },
+            [&](int i) {
+                return KER == KER_COT ? (R)(ldexp(2.0, i + 3) / 3.14159265358979323846) : R(1);
+            },
+            [&](int i) { return (R)log(ldexp((double)N, -(i + 4))); },
+            [&](int i) { return i + 1; }, bufA);
     }
     __syncthreads();
-
-    // ---- local expansion of the subtree root R0 (level lr).  The local of
-    // a box is the sum over its ancestors A_L (L = 2..lr) of the M2L result
-    // at A_L (the regular-part polynomial for L = 2) shifted straight from
-    // the centre of A_L to the centre of R0:
-    //   u_A = rho u_R + delta,  b^R_n = sum_{n'>=n} C(n',n) rho^n delta^(n'-n) b^A_n'.
-    const int nL = lr - 1; // levels 2..lr
-    V *X = bufA;           // X[L-2][n]
-    V *Y = bufB;
-    for (int idx = tid; idx < nL * P; idx += BLOCK) {
-        const int li = idx / P, n = idx - li * P;
-        const int L = li + 2;
-        const int64_t A = R0 >> (lr - L);
-        if (L == 2) {
-            X[idx] = a.loc2[A * P + n];
-        } else {
-            const int64_t mask = (int64_t(1) << L) - 1;
-            const V *base = a.mp + lev_off(L, P);
-            X[idx] = m2l_coeff<R, V, KER>(t4, t6, P, L, A, n, N, [&](int o) {
-                return base + ((A + o) & mask) * P;
-            });
-        }
-    }
-    __syncthreads();
-    for (int idx = tid; idx < nL * P; idx += BLOCK) {
-        const int li = idx / P, n = idx - li * P;
-        const int L = li + 2;
-        const int64_t A = R0 >> (lr - L);
-        const int sh = lr - L;
-        // rho = 2^-sh; delta = ((2 R0 + 1) - (2A + 1) 2^sh) / 2^sh
-        const R rho2 = (R)ldexp(2.0, -sh);                     // 2 rho
+    // shift every row of X to the root (bufB rows), then sum
+    for (int idx = tid; idx < (nA + 1) * PD; idx += BLOCK) {
+        const int li = idx / PD, n = idx - li * PD;
+        const int sh = nA - li; // lr - L
+        const int64_t A = R0 >> sh;
+        // 2 rho = 2^(1 - sh); -2 delta with delta = ((2 R0 + 1) - (2A + 1) 2^sh) / 2^sh;
+        // C(n',n) = l2l[n'][n] 2^n' (-1)^(n'-n) = l2l[n'][n] 2^n (-2)^(n'-n)
+        const R rho2 = (R)ldexp(2.0, -sh);
         const R md2 = (R)(-2.0 * ldexp((double)((2 * R0 + 1) - ((2 * A + 1) << sh)), -sh));
-        // C(n',n) = tll[n'][n] 2^n' (-1)^(n'-n) = tll[n'][n] 2^n (-2)^(n'-n)
-        const V *x = X + li * P;
         V acc = vzero<V>();
         R pw = R(1);
-        for (int np = n; np < P; ++np) {
-            vfma(acc, tll[np * P + n] * pw, x[np]);
+        for (int np = n; np < PD; ++np) {
+            vfma(acc, a.T.l2l[np * PD + n] * pw, ld_coef<R, V>(bufA, RS, li, np));
             pw *= md2;
         }
-        Y[idx] = vscale(acc, ipow(rho2, n));
+        st_coef<R, V>(bufB, RS, li, n, vscale(acc, ipow(rho2, n)));
     }
     __syncthreads();
-    V *cur = bufA, *nxt = bufB;
-    for (int n = tid; n < P; n += BLOCK) {
-        V acc = Y[n];
-        for (int li = 1; li < nL; ++li)
-            vadd(acc, Y[li * P + n]);
-        cur[n] = acc; // X is no longer needed
+    R *cur = bufA, *nxt = bufB;
+    for (int n = tid; n < PD; n += BLOCK) {
+        V acc = ld_coef<R, V>(bufB, RS, 0, n);
+        for (int li = 1; li <= nA; ++li)
+            vadd(acc, ld_coef<R, V>(bufB, RS, li, n));
+        st_coef<R, V>(cur, RS, 0, n, acc);
     }
     __syncthreads();
 
     // ---- the subtree's levels: L2L from the parent + M2L from the level's
-    // interaction lists (sources staged in LDS)
+    // interaction lists (sources staged in LDS, rows first - 3 ...)
     for (int lev = lr + 1; lev <= a.l; ++lev) {
         const int nb = 1 << (lev - lr);
         const int64_t first = R0 << (lev - lr);
         const int64_t mask = (int64_t(1) << lev) - 1;
-        const V *base = a.mp + lev_off(lev, P);
-        for (int idx = tid; idx < (nb + 6) * P; idx += BLOCK) {
-            const int i = idx / P, m = idx - i * P;
-            srcs[idx] = base[((first - 3 + i) & mask) * P + m];
+        const V *base = a.mp + lev_off(lev, PU);
+        for (int idx = tid; idx < (nb + 6) * PD; idx += BLOCK) {
+            const int i = idx / PD, m = idx - i * PD;
+            st_coef<R, V>(srcs, RS, i, m, base[((first - 3 + i) & mask) * PU + m]);
         }
         __syncthreads();
-        for (int idx = tid; idx < nb * P; idx += BLOCK) {
-            const int i = idx / P, n = idx - i * P;
-            const int64_t B = first + i;
-            const V *par = cur + (size_t)(i >> 1) * P;
-            V acc = vzero<V>();
-            if ((B & 1) == 0) {
-                for (int m = n; m < P; ++m)
-                    vfma(acc, tll[m * P + n], par[m]);
-            } else {
-                for (int m = n; m < P; ++m) {
-                    const R t = tll[m * P + n];
-                    vfma(acc, ((m - n) & 1) ? -t : t, par[m]);
-                }
-            }
-            V far = m2l_coeff<R, V, KER>(t4, t6, P, lev, B, n, N, [&](int o) {
-                return srcs + (size_t)(i + 3 + o) * P;
-            });
-            vadd(acc, far);
-            nxt[idx] = acc;
+        if (wave < used) {
+            const R sgl = KER == KER_COT ? (R)(ldexp(2.0, lev) / 3.14159265358979323846) : R(1);
+            const R lgl = (R)log(ldexp((double)N, -(lev + 1)));
+            m2l_tiles<R, V, KER, PD, true>(
+                ops, rt, ct0, ctstep, lane, nb, srcs, cur, RS,
+                [&](int i, int o) { return i + 3 + o; },
+                [&](int i) { return i >> 1; },
+                [&](int i) { return (i & 1) == 0; },
+                [&](int) { return sgl; },
+                [&](int) { return lgl; },
+                [&](int i) { return i; }, nxt);
         }
         __syncthreads();
-        V *t = cur;
+        R *t = cur;
         cur = nxt;
         nxt = t;
     }
-    const V *leafloc = cur;
+    const R *leafloc = cur;
     const int64_t leaf0 = R0 << s;
 
     if constexpr (EPI == EPI_FWD) {
-        // stage the near-field sources of the subtree (uniform sources)
+        // stage the near-field sources of the subtree (uniform sources),
+        // reusing the source buffer
         const cx<R> *fsp = nullptr;
         int64_t K0 = 0;
         if constexpr (SRC == SET_UNIFORM) {
-            const int64_t nleaf = int64_t(1) << a.l;
-            auto ustart = [&](int64_t b) {
-                if (b < 0)
-                    return uni_start(b + nleaf, a.l, N) - N;
-                if (b > nleaf)
-                    return uni_start(b - nleaf, a.l, N) + N;
-                return uni_start(b, a.l, N);
-            };
-            K0 = ustart(leaf0 - 1);
-            const int64_t K1 = ustart(leaf0 + (1 << s) + 1);
+            cx<R> *fs = reinterpret_cast<cx<R> *>(srcs);
+            K0 = uni_start_unwrapped(leaf0 - 1, a.l, N);
+            const int64_t K1 = uni_start_unwrapped(leaf0 + (1 << s) + 1, a.l, N);
             if (K1 - K0 <= a.near_cap) {
                 for (int64_t i = tid; i < K1 - K0; i += BLOCK) {
                     int64_t k = K0 + i;
@@ -683,7 +840,7 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
             }
             const int64_t leaf = box_of(tm, th, a.l, N);
             const R u = (R)rel_coord(tm, th, leaf, a.l, N);
-            V h = horner<R, V>(leafloc + (leaf - leaf0) * P, P, u);
+            V h = horner<R, V>(leafloc, RS, (int)(leaf - leaf0), PD, u);
             cx<R> nr = near_cot<R, V, SRC>(a, tm, th, leaf, fsp, K0);
             double hr = (double)h.re + hscale * (double)nr.re;
             double hi = (double)h.im + hscale * (double)nr.im;
@@ -705,7 +862,7 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
             }
             const int64_t leaf = box_of(k, 0.0, a.l, N);
             const R u = (R)rel_coord(k, 0.0, leaf, a.l, N);
-            V h = horner<R, V>(leafloc + (leaf - leaf0) * P, P, u);
+            V h = horner<R, V>(leafloc, RS, (int)(leaf - leaf0), PD, u);
             cx<R> nr = near_cot<R, V, SRC>(a, k, 0.0, leaf, nullptr, 0);
             double hr = (double)h.re + hscale * (double)nr.re;
             double hi = (double)h.im + hscale * (double)nr.im;
@@ -718,7 +875,7 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
         for (int32_t k = w.u0 + tid; k < w.u1; k += BLOCK) {
             const int64_t leaf = box_of(k, 0.0, a.l, N);
             const R u = (R)rel_coord(k, 0.0, leaf, a.l, N);
-            V far = horner<R, V>(leafloc + (leaf - leaf0) * P, P, u);
+            V far = horner<R, V>(leafloc, RS, (int)(leaf - leaf0), PD, u);
             a.logc[k] = (double)far + near_log<R, V>(a, k, 0.0, leaf, -1);
         }
         for (int32_t t = w.t0 + tid; t < w.t1; t += BLOCK) {
@@ -726,7 +883,7 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
             const double th = a.tgt.th[t];
             const int64_t leaf = box_of(tm, th, a.l, N);
             const R u = (R)rel_coord(tm, th, leaf, a.l, N);
-            V far = horner<R, V>(leafloc + (leaf - leaf0) * P, P, u);
+            V far = horner<R, V>(leafloc, RS, (int)(leaf - leaf0), PD, u);
             // the net count of Omega_1 carried log(2 pi / N) for the point
             // itself, whose log|t| term the near field skips
             a.logd[t] = -((double)far + near_log<R, V>(a, tm, th, leaf, t) - a.logself);
