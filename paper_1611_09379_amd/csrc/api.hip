@@ -276,7 +276,7 @@ static int get_tables(int kernel, int PU, int PD, int q, OpTables<R> *out)
 
 // ------------------------------------------------------------------ plan
 
-static constexpr int MAX_BANDS = 8;
+static constexpr int MAX_BANDS = 12;
 
 struct Band {
     int lb, d, first, grid;
@@ -290,8 +290,7 @@ struct FmmSetup {
     Buf mp, loc2, S;
     int nbands = 0;
     Band band[MAX_BANDS];
-    int top_lb = 2;
-    size_t top_smem = 0;
+    size_t reg_smem = 0;
     size_t dn_smem = 0;
     int rows_buf = 0, rows_src = 0, near_cap = 0;
 };
@@ -394,34 +393,25 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool near_st
     F.RSd = row_stride(NC, PD, es);
     const size_t lim = lds_limit();
     // bands of the upward pass: the leaves' band (at most 4 levels), then
-    // bands of at most 5 levels down to the top level handled by one
-    // workgroup (at most 7, as long as its multipoles fit in LDS)
-    int ttop = std::min(7, P->l);
-    while (ttop > 2 && (size_t)((1 << ttop) + std::max(1 << (ttop - 1), 4)) * F.RSu * es > lim)
-        --ttop;
+    // bands of at most 5 levels down to level 2 (the last one has 4
+    // workgroups, one per quarter)
     F.nbands = 0;
     int lb = P->l;
-    {
-        const int d = std::min(4, std::max(0, lb - std::max(ttop, 2)));
-        const int d0 = lb - d < 2 ? lb - 2 : d;
-        F.band[F.nbands++] = {lb, d0, 1, 1 << (lb - d0),
-                              (size_t)((1 << d0) + std::max((1 << d0) / 2, 1)) * F.RSu * es};
-        lb -= d0;
-    }
-    while (lb > ttop) {
-        const int d = std::min(5, lb - ttop);
-        F.band[F.nbands++] = {lb, d, 0, 1 << (lb - d),
+    bool first = true;
+    do {
+        const int d = std::min(first ? 4 : 5, lb - 2);
+        F.band[F.nbands++] = {lb, d, first ? 1 : 0, 1 << (lb - d),
                               (size_t)((1 << d) + std::max((1 << d) / 2, 1)) * F.RSu * es};
         lb -= d;
-    }
-    F.top_lb = lb;
-    F.top_smem = (size_t)((1 << lb) + std::max(1 << (lb - 1), 4)) * F.RSu * es;
-    if (F.top_smem > lim)
-        return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PU, F.top_smem);
+        first = false;
+    } while (lb > 2);
     for (int b = 0; b < F.nbands; ++b)
         if (F.band[b].smem > lim)
             return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PU,
                         F.band[b].smem);
+    F.reg_smem = (size_t)(PU * PU + 2 * PU * PD) * es + 8 * (size_t)PU * sizeof(V);
+    if (F.reg_smem > lim)
+        return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PU, F.reg_smem);
     const int s = P->l - P->lr;
     F.dn_smem = down_lds(s, P->lr, F.RSd, es, &F.rows_buf, &F.rows_src);
     if (F.dn_smem > lim)
@@ -444,6 +434,10 @@ static void fill_up(const fn_plan *P, const FmmSetup &F, const OpTables<R> &T,
     ua.l = P->l;
     ua.RS = F.RSu;
     ua.PD = F.PD;
+    {
+        const int64_t B = P->N >> P->l;
+        ua.leaf_pts = ((B << P->l) == P->N && B >= 4 && B % 4 == 0) ? (int)B : 0;
+    }
     ua.mp = (V *)F.mp.p;
     ua.loc2 = (V *)F.loc2.p;
     ua.S = (V *)F.S.p;
@@ -478,8 +472,8 @@ static void fill_down(const fn_plan *P, const FmmSetup &F, const OpTables<R> &T,
     default: { constexpr int NAME = 64; __VA_ARGS__; } break;                  \
     }
 
-// The upward pass: the bands, then the top.  ua must be filled except for
-// the band fields.
+// The upward pass: the bands, then the level-2 regular part.  ua must be
+// filled except for the band fields.
 template <typename R, typename V, int KER, int SRC>
 static int launch_up(const FmmSetup &F, UpArgs<R, V> ua, hipStream_t st)
 {
@@ -493,12 +487,8 @@ static int launch_up(const FmmSetup &F, UpArgs<R, V> ua, hipStream_t st)
                                          F.band[b].smem, st, ua));
         HIPCHK(hipGetLastError());
     }
-    ua.lb = F.top_lb;
-    ua.d = F.top_lb - 2;
-    ua.first_band = 0;
-    FN_DISPATCH16(F.PU, PU_,
-                  hipLaunchKernelGGL((k_up_top<R, V, KER, PU_>), dim3(1), dim3(BLOCK),
-                                     F.top_smem, st, ua));
+    hipLaunchKernelGGL((k_regular<R, V, KER>), dim3(1), dim3(BLOCK), F.reg_smem, st,
+                       ua, F.PU);
     HIPCHK(hipGetLastError());
     return FN_OK;
 }
@@ -544,14 +534,15 @@ static int build_tree(fn_plan *P, int64_t n, const double *y, bool deterministic
                       bool want_hit, hipStream_t st)
 {
     const int64_t nleaf = int64_t(1) << P->l;
-    Buf um, uth, ukey, count, cursor, flags, gm, gth, gperm, gkey;
+    Buf um, uth, ukey, count, cursor, flags, gm, gth, gperm, gkey, tsum;
     auto cleanup = [&]() {
         for (Buf *b : {&um, &uth, &ukey, &count, &cursor, &flags, &gm, &gth,
-                       &gperm, &gkey})
+                       &gperm, &gkey, &tsum})
             release(*b);
     };
     bool ok = alloc(um, n * 4) && alloc(uth, n * 8) && alloc(ukey, n * 4) &&
               alloc(count, nleaf * 4) && alloc(cursor, nleaf * 4) &&
+              alloc(tsum, ((nleaf + SCAN_TILE - 1) / SCAN_TILE) * 4) &&
               alloc(flags, 4) && alloc(P->off, (nleaf + 1) * 4) &&
               alloc(P->sm, n * 4) && alloc(P->sth, n * 8) &&
               alloc(P->sperm, n * 4);
@@ -587,10 +578,19 @@ static int build_tree(fn_plan *P, int64_t n, const double *y, bool deterministic
                            want_hit ? (int32_t *)P->hit.p : nullptr,
                            (int *)flags.p);
         TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st,
-                           (const int32_t *)count.p, (int32_t *)P->off.p,
-                           (int32_t *)cursor.p, nleaf);
-        TRY(hipGetLastError());
+        {
+            const int nt = (int)((nleaf + SCAN_TILE - 1) / SCAN_TILE);
+            hipLaunchKernelGGL(k_scan_sums, dim3(nt), dim3(256), 0, st,
+                               (const int32_t *)count.p, nleaf, (int32_t *)tsum.p);
+            TRY(hipGetLastError());
+            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st,
+                               (int32_t *)tsum.p, nt, (int32_t *)P->off.p + nleaf);
+            TRY(hipGetLastError());
+            hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(256), 0, st,
+                               (const int32_t *)count.p, nleaf, (const int32_t *)tsum.p,
+                               (int32_t *)P->off.p, (int32_t *)cursor.p);
+            TRY(hipGetLastError());
+        }
         if (!deterministic) {
             hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(256), 0, st, n,
                                (const int32_t *)um.p, (const double *)uth.p,
@@ -770,6 +770,7 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     UpArgs<R, V> ua{};
     fill_up(P, F, T, ua);
     ua.src = src;
+    ua.leaf_pts = 0;
     ua.logc1 = std::log(2.0 * M_PI / (double)P->N);
     ua.logc2 = std::log(2.0);
     rc = launch_up<R, V, KER_LOG, SET_SORTED>(F, ua, st);
@@ -855,9 +856,12 @@ static int exec_inv(fn_plan *P, const void *in, void *out, int phase,
         UpArgs<R, V> ua{};
         fill_up(P, F, T, ua);
         ua.src = src;
-        ua.dhat = (const cx<double> *)P->dhat.p;
-        ua.gin = (const cx<R> *)in;
-        ua.w_out = (cx<R> *)P->wsorted.p;
+        ua.leaf_pts = 0;
+        ua.w_sorted = (const cx<R> *)P->wsorted.p;
+        hipLaunchKernelGGL((k_weights<R>), dim3(grid_for(P->N)), dim3(256), 0, st, P->N,
+                           (const cx<double> *)P->dhat.p, (const int32_t *)P->sperm.p,
+                           (const cx<R> *)in, (cx<R> *)P->wsorted.p);
+        HIPCHK(hipGetLastError());
         rc = launch_up<R, V, KER_COT, SET_SORTED>(F, ua, st);
         if (rc)
             return rc;

@@ -21,9 +21,10 @@
 //
 // Kernels:
 //   k_up_band    P2M at the leaves (first band) or a load of the band's
-//                bottom multipoles, then M2M up the band (matrix cores).
-//   k_up_top     one workgroup: M2M of the last levels down to level 2 and
-//                the level-2 local polynomial of the regular part (Eq. p20).
+//                bottom multipoles, then M2M up the band (matrix cores); the
+//                last band ends at level 2.
+//   k_regular    one workgroup: the level-2 local polynomial of the regular
+//                part (Eq. p20) from the four level-2 multipoles.
 //   k_down_eval  one subtree of the finest levels: the local of its root as
 //                the sum of the ancestors' M2L results shifted straight to
 //                the root, the subtree's L2L + M2L (matrix cores), then every
@@ -38,7 +39,6 @@ enum { KER_COT = 0, KER_LOG = 1 };
 enum { SET_UNIFORM = 0, SET_SORTED = 1 };
 enum { EPI_FWD = 0, EPI_INV = 1, EPI_LOGCD = 2 };
 
-constexpr int CH = 8;      // moments per thread in P2M
 constexpr int BLOCK = 256; // 4 wavefronts of 64
 
 // Points sorted by leaf: off[b]..off[b+1] index the points of leaf b.
@@ -174,17 +174,18 @@ __device__ __forceinline__ void load_tile(R (&a)[K / 4], const R *tab, int rt,
 template <typename R, typename V>
 struct UpArgs {
     int64_t N;
-    int l;         // leaf level
-    int lb, d;     // this launch: bottom level and levels climbed
-    int RS;        // LDS row stride (elements of R)
-    int PD;        // local expansion terms (level-2 polynomial)
+    int l;          // leaf level
+    int lb, d;      // this launch: bottom level and levels climbed
+    int RS;         // LDS row stride (elements of R)
+    int PD;         // local expansion terms (level-2 polynomial)
     int first_band;
+    int leaf_pts;   // uniform sources: points per leaf if every leaf holds
+                    // the same number (N divisible by 2^l, a multiple of 4
+                    // up to 64), else 0
     // sources (first band)
     SortedSet src;
     const cx<R> *f_uniform;  // forward: f_k at the uniform points
-    const cx<double> *dhat;  // inverse: Dhat_j in sorted order
-    const cx<R> *gin;        // inverse: g_j in input order
-    cx<R> *w_out;            // inverse: w_j = Dhat_j g_j (sorted)
+    const cx<R> *w_sorted;   // inverse: w_j = Dhat_j g_j (sorted)
     // outputs
     V *mp;                   // multipoles, levels 2..l, PU per box
     V *loc2;                 // level-2 local polynomials, 4 x PD
@@ -193,16 +194,33 @@ struct UpArgs {
     double logc1, logc2;     // log kernel: log(2 pi / N), log 2
 };
 
-// P2M at leaf b for CH consecutive moments m0..m0+CH-1: a_m = sum w v^m with
+// Inverse: w_j = Dhat_j g_j in sorted order (Eq. p6: the weights of the cot
+// sum).
+template <typename R>
+__global__ void k_weights(int64_t n, const cx<double> *dhat, const int32_t *perm,
+                          const cx<R> *g, cx<R> *w)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const cx<double> d = dhat[t];
+        const cx<R> x = g[perm[t]];
+        w[t] = {(R)(d.re * (double)x.re - d.im * (double)x.im),
+                (R)(d.re * (double)x.im + d.im * (double)x.re)};
+    }
+}
+
+constexpr int CHS = 4; // moments per thread in the vector P2M
+
+// P2M at leaf b for CHS consecutive moments m0..: a_m = sum w v^m with
 // v = (sigma - c)/r.  The log kernel takes unit weights minus the uniform
 // density of one point per grid unit (moments 2r/(m+1) for even m).
 template <typename R, typename V, int KER, int SRC>
 __device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, int64_t b,
-                                          int m0, V *acc, bool store_w)
+                                          int m0, V *acc)
 {
     const int l = a.l;
     const int64_t N = a.N;
-    for (int c = 0; c < CH; ++c)
+    for (int c = 0; c < CHS; ++c)
         acc[c] = vzero<V>();
     if constexpr (SRC == SET_UNIFORM) {
         const int64_t k0 = uni_start(b, l, N), k1 = uni_start(b + 1, l, N);
@@ -214,7 +232,7 @@ __device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, int64_t b,
                 w = a.f_uniform[k];
             else
                 w = R(1);
-            for (int c = 0; c < CH; ++c) {
+            for (int c = 0; c < CHS; ++c) {
                 vfma(acc[c], pw, w);
                 pw *= v;
             }
@@ -225,17 +243,11 @@ __device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, int64_t b,
             R v = (R)rel_coord(a.src.m[t], a.src.th[t], b, l, N);
             R pw = ipow(v, m0);
             V w;
-            if constexpr (KER == KER_COT) {
-                cx<double> d = a.dhat[t];
-                cx<R> g = a.gin[a.src.perm[t]];
-                w = {(R)(d.re * (double)g.re - d.im * (double)g.im),
-                     (R)(d.re * (double)g.im + d.im * (double)g.re)};
-                if (store_w)
-                    a.w_out[t] = w;
-            } else {
+            if constexpr (KER == KER_COT)
+                w = a.w_sorted[t];
+            else
                 w = R(1);
-            }
-            for (int c = 0; c < CH; ++c) {
+            for (int c = 0; c < CHS; ++c) {
                 vfma(acc[c], pw, w);
                 pw *= v;
             }
@@ -243,10 +255,53 @@ __device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, int64_t b,
     }
     if constexpr (KER == KER_LOG) {
         const double r = ldexp((double)N, -(l + 1));
-        for (int c = 0; c < CH; ++c) {
+        for (int c = 0; c < CHS; ++c) {
             int m = m0 + c;
             if ((m & 1) == 0)
                 acc[c] -= (R)(2.0 * r / (double)(m + 1));
+        }
+    }
+}
+
+// P2M on the matrix cores for uniform sources with B points in every leaf:
+// a[m][(leaf, comp)] = sum_i v_i^m f[leaf B + i], v_i = (2i - B)/B, i.e. a
+// GEMM whose operator V^T (PU x B) is the same for every leaf.
+template <typename R, typename V, int PU>
+__device__ __forceinline__ void p2m_mfma(const UpArgs<R, V> &a, int64_t first,
+                                         int nbot, R *buf, int RS, V *g,
+                                         int lane, int wave)
+{
+    constexpr int NC = 2; // cot kernel: complex weights
+    using A = typename acc_t<R>::type;
+    constexpr int nrt = PU / 16;
+    const int B = a.leaf_pts;
+    const int nks = B / 4;
+    const int ntile = nrt * ((NC * nbot + 15) / 16);
+    const R *f = reinterpret_cast<const R *>(a.f_uniform);
+    for (int tile = wave; tile < ntile; tile += 4) {
+        const int rt = tile % nrt, ct = tile / nrt;
+        const int j = 16 * ct + (lane & 15);
+        const int i = j / NC, c = j % NC;
+        const bool valid = i < nbot;
+        const int m = 16 * rt + (lane & 15); // A row of this lane
+        const R *fp = f + ((first + (valid ? i : 0)) * B) * NC + c;
+        A acc = {0, 0, 0, 0};
+        for (int ks = 0; ks < nks; ++ks) {
+            const int k = 4 * ks + (lane >> 4);
+            const R v = (R)((double)(2 * k - B) / (double)B);
+            const R av = ipow(v, m);
+            R bv = fp[k * NC];
+            if (!valid)
+                bv = R(0);
+            acc = mma(av, bv, acc);
+        }
+        if (valid) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * rt + out_row<R>(lane, r);
+                buf[(size_t)i * RS + n * NC + c] = acc[r];
+                reinterpret_cast<R *>(g)[((first + i) * PU + n) * NC + c] = acc[r];
+            }
         }
     }
 }
@@ -309,15 +364,24 @@ __global__ void __launch_bounds__(BLOCK) k_up_band(UpArgs<R, V> a)
     const int64_t first = (int64_t)blockIdx.x << d;
     R *buf1 = buf0 + (size_t)nbot * RS;
     if (a.first_band) {
-        constexpr int nch = PU / CH;
         V *g = a.mp + lev_off(lb, PU);
-        for (int idx = tid; idx < nbot * nch; idx += BLOCK) {
-            const int i = idx / nch, ch = idx - i * nch;
-            V acc[CH];
-            p2m_chunk<R, V, KER, SRC>(a, first + i, ch * CH, acc, ch == 0);
-            for (int c = 0; c < CH; ++c) {
-                st_coef<R, V>(buf0, RS, i, ch * CH + c, acc[c]);
-                g[(first + i) * PU + ch * CH + c] = acc[c];
+        bool done = false;
+        if constexpr (SRC == SET_UNIFORM && KER == KER_COT) {
+            if (a.leaf_pts > 0) {
+                p2m_mfma<R, V, PU>(a, first, nbot, buf0, RS, g, lane, wave);
+                done = true;
+            }
+        }
+        if (!done) {
+            constexpr int nch = PU / CHS;
+            for (int idx = tid; idx < nbot * nch; idx += BLOCK) {
+                const int i = idx / nch, ch = idx - i * nch;
+                V acc[CHS];
+                p2m_chunk<R, V, KER, SRC>(a, first + i, ch * CHS, acc);
+                for (int c = 0; c < CHS; ++c) {
+                    st_coef<R, V>(buf0, RS, i, ch * CHS + c, acc[c]);
+                    g[(first + i) * PU + ch * CHS + c] = acc[c];
+                }
             }
         }
     } else {
@@ -348,79 +412,66 @@ __global__ void __launch_bounds__(BLOCK) k_up_band(UpArgs<R, V> a)
     }
 }
 
-// Last launch of the upward pass (one workgroup): the 2^lb multipoles of
-// level lb up to level 2, then the level-2 local polynomial of the regular
-// part of Eq. (p20) and the sum of the weights.
-template <typename R, typename V, int KER, int PU>
-__global__ void __launch_bounds__(BLOCK) k_up_top(UpArgs<R, V> a)
+// Level 2 (one workgroup): the regular part of Eq. (p20) as the level-2
+// local polynomial of every quarter, from the four level-2 multipoles, and
+// the sum of the weights.  A1 holds the moments of Omega_1(P_n) about the
+// centre of P_n: the three quarters unwrapped around it, (v + 2i)^t expanded
+// for i = -1, 0, +1.
+template <typename R, typename V, int KER>
+__global__ void __launch_bounds__(BLOCK) k_regular(UpArgs<R, V> a, int PU)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    R *buf0 = reinterpret_cast<R *>(smem_raw);
-    const int RS = a.RS;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lb = a.lb;
-    const int nbot = 1 << lb;
-    R *buf1 = buf0 + (size_t)nbot * RS; // max(nbot / 2, 4) rows
-    {
-        const V *g = a.mp + lev_off(lb, PU);
-        for (int idx = tid; idx < nbot * PU; idx += BLOCK)
-            st_coef<R, V>(buf0, RS, idx / PU, idx % PU, g[idx]);
+    const int PD = a.PD;
+    R *tb = reinterpret_cast<R *>(smem_raw);      // PU x PU
+    R *t1 = tb + PU * PU;                          // PU x PD
+    R *t2 = t1 + PU * PD;                          // PU x PD
+    V *a2 = reinterpret_cast<V *>(t2 + PU * PD);   // 4 x PU
+    V *A1 = a2 + 4 * PU;                           // 4 x PU
+    const int tid = threadIdx.x;
+    for (int i = tid; i < PU * PU; i += BLOCK)
+        tb[i] = a.T.bin[i];
+    for (int i = tid; i < PU * PD; i += BLOCK) {
+        t1[i] = a.T.reg1[i];
+        t2[i] = a.T.reg2[i];
     }
-    constexpr int nrt = PU / 16;
-    const int used = (4 / nrt) * nrt;
-    R am[PU / 4];
-    const int rt = wave % nrt;
-    if (wave < used)
-        load_tile<R, PU>(am, a.T.m2m, rt, lane);
+    for (int i = tid; i < 4 * PU; i += BLOCK)
+        a2[i] = a.mp[i]; // level 2 is the first level of mp
     __syncthreads();
-    R *cur = buf0, *nxt = buf1;
-    int n = nbot;
-    for (int lev = lb - 1; lev >= 2; --lev) {
-        n >>= 1;
-        if (wave < used)
-            m2m_level<R, V, PU>(am, rt, wave / nrt, 4 / nrt, lane, n, cur, nxt, RS,
-                                a.mp + lev_off(lev, PU));
-        __syncthreads();
-        R *t = cur;
-        cur = nxt;
-        nxt = t;
-    }
-    // level 2: A1 = moments of Omega_1(P_n) about c_n, the three quarters
-    // unwrapped around P_n: (v + 2i)^t expanded for i = -1, 0, +1
-    R *A1 = nxt; // 4 rows (the other buffer is free)
     for (int idx = tid; idx < 4 * PU; idx += BLOCK) {
         const int q = idx / PU, t = idx - q * PU;
-        V acc = ld_coef<R, V>(cur, RS, q, t);
+        V acc = a2[q * PU + t];
+        const V *lft = a2 + ((q + 3) & 3) * PU;
+        const V *rgt = a2 + ((q + 1) & 3) * PU;
         R pw = R(1);
         for (int j = t; j >= 0; --j) {
-            const R cb = a.T.bin[t * PU + j] * pw;
-            vfma(acc, cb, ld_coef<R, V>(cur, RS, (q + 1) & 3, j));
-            vfma(acc, ((t - j) & 1) ? -cb : cb, ld_coef<R, V>(cur, RS, (q + 3) & 3, j));
+            const R cb = tb[t * PU + j] * pw;
+            vfma(acc, cb, rgt[j]);
+            vfma(acc, ((t - j) & 1) ? -cb : cb, lft[j]);
             pw *= R(2);
         }
-        st_coef<R, V>(A1, RS, q, t, acc);
+        A1[idx] = acc;
     }
     __syncthreads();
-    const int PD = a.PD;
     for (int idx = tid; idx < 4 * PD; idx += BLOCK) {
         const int q = idx / PD, lo = idx - q * PD;
+        const V *o = a2 + ((q + 2) & 3) * PU;
+        const V *n1 = A1 + q * PU;
         V acc = vzero<V>();
         for (int t = 0; t < PU; ++t) {
-            vfma(acc, a.T.reg1[t * PD + lo], ld_coef<R, V>(A1, RS, q, t));
-            vfma(acc, a.T.reg2[t * PD + lo], ld_coef<R, V>(cur, RS, (q + 2) & 3, t));
+            vfma(acc, t1[t * PD + lo], n1[t]);
+            vfma(acc, t2[t * PD + lo], o[t]);
         }
         if constexpr (KER == KER_LOG) {
             if (lo == 0)
-                acc += (R)(a.logc1 * (double)ld_coef<R, V>(A1, RS, q, 0) +
-                           a.logc2 * (double)ld_coef<R, V>(cur, RS, (q + 2) & 3, 0));
+                acc += (R)(a.logc1 * (double)n1[0] + a.logc2 * (double)o[0]);
         }
         a.loc2[idx] = acc;
     }
     if constexpr (KER == KER_COT) {
         if (tid == 0) {
-            V s = ld_coef<R, V>(cur, RS, 0, 0);
+            V s = a2[0];
             for (int q = 1; q < 4; ++q)
-                vadd(s, ld_coef<R, V>(cur, RS, q, 0));
+                vadd(s, a2[q * PU]);
             *a.S = s;
         }
     }
@@ -559,7 +610,8 @@ __device__ __forceinline__ void m2l_tiles(const DownOps<R, PD> &o, int rt, int c
     }
 }
 
-// 1/d to full precision: hardware reciprocal refined by Newton steps.
+// 1/d: the binary64 hardware reciprocal is good to about 2^-24 and takes two
+// Newton steps; the binary32 one is within 1 ulp.
 __device__ __forceinline__ double recip(double d)
 {
     double r = __builtin_amdgcn_rcp(d);
@@ -570,9 +622,7 @@ __device__ __forceinline__ double recip(double d)
 }
 __device__ __forceinline__ float recip(float d)
 {
-    float r = __builtin_amdgcn_rcpf(d);
-    float e = fmaf(-d, r, 1.0f);
-    return fmaf(r, e, r);
+    return __builtin_amdgcn_rcpf(d); // within 1 ulp on gfx950
 }
 
 template <typename R, typename V>
@@ -658,6 +708,8 @@ __device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
 // Near field of the log kernel with the uniform background removed:
 // sum log|tau - sigma~| over the sources of leaves b-1..b+1 (skipping the
 // source `self`), minus the integral of log|tau - sigma| over those leaves.
+// The logarithms of the distances are summed as the logarithm of their
+// product, kept as mantissa x 2^exponent so that it cannot leave the range.
 template <typename R, typename V>
 __device__ __forceinline__ double near_log(const DownArgs<R, V> &a, int64_t tm,
                                            double tth, int64_t leaf,
@@ -666,7 +718,8 @@ __device__ __forceinline__ double near_log(const DownArgs<R, V> &a, int64_t tm,
     const int64_t N = a.N;
     const int l = a.l;
     const int64_t nleaf = int64_t(1) << l;
-    double acc = 0.0;
+    double prod = 1.0;
+    int expo = 0, cnt = 0;
     for (int dl = -1; dl <= 1; ++dl) {
         int64_t b = leaf + dl, shift = 0;
         if (b < 0) {
@@ -680,10 +733,17 @@ __device__ __forceinline__ double near_log(const DownArgs<R, V> &a, int64_t tm,
         for (int32_t t = t0; t < t1; ++t) {
             if (t == self)
                 continue;
-            double dd = grid_diff(tm - a.src.m[t] - shift, tth, a.src.th[t]);
-            acc += log(fabs(dd));
+            const double dd = grid_diff(tm - a.src.m[t] - shift, tth, a.src.th[t]);
+            prod *= fabs(dd);
+            if (++cnt == 8) { // renormalise: |dd| <= 2N, so 8 factors stay in range
+                int e;
+                prod = frexp(prod, &e);
+                expo += e;
+                cnt = 0;
+            }
         }
     }
+    const double acc = log(prod) + (double)expo * 0.69314718055994530942;
     // integral over [(leaf-1) N/2^l, (leaf+2) N/2^l) (unwrapped)
     const double sc = ldexp(1.0, -l);
     double lo = (double)((leaf - 1) * N - (tm << l)) * sc - tth;

@@ -70,35 +70,99 @@ __global__ void k_reduce(int64_t M, const double *__restrict__ y, double c_hi,
     }
 }
 
-// Exclusive scan of the leaf counts (one workgroup of 1024 threads).
-__global__ void __launch_bounds__(1024)
-    k_scan(const int32_t *count, int32_t *off, int32_t *cursor, int64_t n)
+// Exclusive scan of the leaf counts in three coalesced steps: sums of tiles
+// of SCAN_TILE counts, a scan of the tile sums (one workgroup), and the scan
+// inside every tile.
+constexpr int SCAN_TILE = 4096;
+
+__global__ void __launch_bounds__(256)
+    k_scan_sums(const int32_t *count, int64_t n, int32_t *tsum)
 {
-    __shared__ int64_t part[1024];
+    __shared__ int32_t red[256];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int32_t s = 0;
+    for (int i = threadIdx.x; i < SCAN_TILE; i += 256)
+        if (base + i < n)
+            s += count[base + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if (threadIdx.x < d)
+            red[threadIdx.x] += red[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        tsum[blockIdx.x] = red[0];
+}
+
+// In place: tsum[i] <- sum of tsum[0..i), for nt <= 4096 tiles; the total
+// goes to *total.
+__global__ void __launch_bounds__(1024)
+    k_scan_top(int32_t *tsum, int nt, int32_t *total)
+{
+    __shared__ int32_t part[1024];
     const int tid = threadIdx.x;
-    const int64_t per = (n + 1023) / 1024;
-    const int64_t b0 = tid * per;
-    const int64_t b1 = b0 + per < n ? b0 + per : n;
-    int64_t s = 0;
-    for (int64_t i = b0; i < b1; ++i)
-        s += count[i];
+    const int per = (nt + 1023) / 1024;
+    const int b0 = tid * per, b1 = b0 + per < nt ? b0 + per : nt;
+    int32_t v[4];
+    int32_t s = 0;
+    for (int i = b0; i < b1; ++i) {
+        v[i - b0] = tsum[i];
+        s += v[i - b0];
+    }
     part[tid] = s;
     __syncthreads();
     for (int d = 1; d < 1024; d <<= 1) {
-        int64_t v = tid >= d ? part[tid - d] : 0;
+        int32_t x = tid >= d ? part[tid - d] : 0;
         __syncthreads();
-        part[tid] += v;
+        part[tid] += x;
         __syncthreads();
     }
-    int64_t run = tid == 0 ? 0 : part[tid - 1];
-    for (int64_t i = b0; i < b1; ++i) {
-        off[i] = (int32_t)run;
-        if (cursor)
-            cursor[i] = (int32_t)run;
-        run += count[i];
+    int32_t run = tid == 0 ? 0 : part[tid - 1];
+    for (int i = b0; i < b1; ++i) {
+        tsum[i] = run;
+        run += v[i - b0];
     }
     if (tid == 1023)
-        off[n] = (int32_t)part[1023];
+        *total = part[1023];
+}
+
+__global__ void __launch_bounds__(256)
+    k_scan_tiles(const int32_t *count, int64_t n, const int32_t *tsum,
+                 int32_t *off, int32_t *cursor)
+{
+    __shared__ int32_t tile[SCAN_TILE];
+    __shared__ int32_t part[256];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    for (int i = tid; i < SCAN_TILE; i += 256)
+        tile[i] = base + i < n ? count[base + i] : 0;
+    __syncthreads();
+    constexpr int per = SCAN_TILE / 256;
+    int32_t s = 0;
+    for (int i = 0; i < per; ++i)
+        s += tile[tid * per + i];
+    part[tid] = s;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        int32_t x = tid >= d ? part[tid - d] : 0;
+        __syncthreads();
+        part[tid] += x;
+        __syncthreads();
+    }
+    int32_t run = tsum[blockIdx.x] + (tid == 0 ? 0 : part[tid - 1]);
+    for (int i = 0; i < per; ++i) {
+        const int32_t c = tile[tid * per + i];
+        tile[tid * per + i] = run;
+        run += c;
+    }
+    __syncthreads();
+    for (int i = tid; i < SCAN_TILE; i += 256)
+        if (base + i < n) {
+            off[base + i] = tile[i];
+            if (cursor)
+                cursor[base + i] = tile[i];
+        }
 }
 
 // Counting-sort scatter: each point takes the next slot of its leaf.  The
