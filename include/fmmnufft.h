@@ -76,10 +76,13 @@ typedef struct {
     int64_t N, M;
     int32_t kind;  /* 0 forward, 1 inverse                                */
     int32_t dtype; /* fn_dtype                                            */
-    int32_t p;     /* multipole / local expansion terms of the 1/t FMM    */
+    int32_t p;     /* truncation number of the 1/t MLFMM from Eq. (18.2)
+                      (or as given)                                      */
     int32_t q;     /* Bernoulli terms of the regular part (Eq. 10, 11)    */
     int32_t lmax;  /* finest tree level (2^lmax leaves)                   */
-    int32_t nterms;/* terms stored per expansion (>= p and >= 2q)         */
+    int32_t nterms;/* terms of the local expansions and translations: p,
+                      or a smaller value calibrated for the relative l2
+                      target when p was not given, rounded up to 16       */
     double eps;
 } fn_plan_info;
 
@@ -125,7 +128,8 @@ int nufft_execute_phase(fn_plan *plan, const void *in, void *out, int phase,
                         void *stream);
 
 /* Releases the plan and its workspace (NULL is accepted).  Synchronises the
- * device. */
+ * stream of the plan's last call (creation or execute); work of the plan
+ * still queued on another stream must have completed before this call. */
 int nufft_destroy(fn_plan *plan);
 
 /* Reports the parameters of a plan. */

@@ -299,20 +299,26 @@ struct fn_plan {
     int kind = 0, dtype = 0;
     int64_t N = 0, M = 0;
     int p = 0, q = 0, l = 0;
+    bool p_explicit = false;
     double eps = 0;
     int lr = 2; // subtree root level of k_down_eval
     // points sorted into the leaves (targets of the forward, sources of the
     // inverse)
-    Buf off, sm, sth, sperm;
-    Buf work;
-    int nwork = 0;
+    Buf off, sm, sth, sperm, skey;
+    Buf work, nwork_dev;
+    int nwork = 0;  // grid of k_down_eval: the largest possible work list
     FmmSetup cot;
     // inverse
     Buf hit, chat, dhat, wsorted;
+    // error flags of the setup kernels, read once at the end of the plan
+    Buf flags;
+    // temporaries of the setup, released after its synchronisation
+    std::vector<Buf> tmp;
+    hipStream_t stream = nullptr; // stream of the last call
     std::vector<Buf *> all()
     {
-        return {&off, &sm, &sth, &sperm, &work, &cot.mp, &cot.loc2, &cot.S,
-                &hit, &chat, &dhat, &wsorted};
+        return {&off, &sm, &sth, &sperm, &skey, &work, &nwork_dev, &cot.mp, &cot.loc2,
+                &cot.S, &hit, &chat, &dhat, &wsorted, &flags};
     }
 };
 
@@ -330,10 +336,28 @@ static void release(Buf &b)
     b.n = 0;
 }
 
+static void release_tmp(fn_plan *P)
+{
+    for (Buf &b : P->tmp)
+        release(b);
+    P->tmp.clear();
+}
+
 static void release_plan(fn_plan *P)
 {
     for (Buf *b : P->all())
         release(*b);
+    release_tmp(P);
+}
+
+// A temporary of the setup: kept until the plan's synchronisation.
+static void *tmp_alloc(fn_plan *P, size_t bytes)
+{
+    Buf b;
+    if (!alloc(b, bytes))
+        return nullptr;
+    P->tmp.push_back(b);
+    return b.p;
 }
 
 static int round16(int x) { return std::min(64, std::max(16, (x + 15) & ~15)); }
@@ -456,6 +480,7 @@ static void fill_down(const fn_plan *P, const FmmSetup &F, const OpTables<R> &T,
     da.rows_src = F.rows_src;
     da.near_cap = F.near_cap;
     da.work = (const WorkItem *)P->work.p;
+    da.nwork = (const int32_t *)P->nwork_dev.p;
     da.mp = (const V *)F.mp.p;
     da.PU = F.PU;
     da.loc2 = (const V *)F.loc2.p;
@@ -527,159 +552,168 @@ static int grid_for(int64_t n, int block = 256)
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
 }
 
-// Sort a point set into the leaves.  deterministic = order inside a leaf by
-// position (inverse); otherwise arbitrary (forward).  Also fills the hit map
-// when requested.  Synchronises.
-static int build_tree(fn_plan *P, int64_t n, const double *y, bool deterministic,
-                      bool want_hit, hipStream_t st)
+static constexpr int SORT_LDS_BINS = 32768; // LDS histogram limit (128 KB)
+
+// Sort a point set by the level-(l - keyshift) box (the leaves for
+// keyshift = 0): a counting sort with per-block LDS histograms when the
+// keys fit in LDS, with global atomics otherwise.  deterministic: order
+// inside each leaf by position (inverse; keyshift must be 0); otherwise the
+// order inside a key is arbitrary (forward).  Fills the hit map when asked.
+// Enqueues only; errors land in P->flags.
+static int build_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
+                      bool deterministic, bool want_hit, hipStream_t st)
 {
-    const int64_t nleaf = int64_t(1) << P->l;
-    Buf um, uth, ukey, count, cursor, flags, gm, gth, gperm, gkey, tsum;
-    auto cleanup = [&]() {
-        for (Buf *b : {&um, &uth, &ukey, &count, &cursor, &flags, &gm, &gth,
-                       &gperm, &gkey, &tsum})
-            release(*b);
-    };
-    bool ok = alloc(um, n * 4) && alloc(uth, n * 8) && alloc(ukey, n * 4) &&
-              alloc(count, nleaf * 4) && alloc(cursor, nleaf * 4) &&
-              alloc(tsum, ((nleaf + SCAN_TILE - 1) / SCAN_TILE) * 4) &&
-              alloc(flags, 4) && alloc(P->off, (nleaf + 1) * 4) &&
-              alloc(P->sm, n * 4) && alloc(P->sth, n * 8) &&
-              alloc(P->sperm, n * 4);
-    if (ok && deterministic)
-        ok = alloc(gm, n * 4) && alloc(gth, n * 8) && alloc(gperm, n * 4) &&
-             alloc(gkey, n * 4);
-    if (ok && want_hit)
-        ok = alloc(P->hit, P->N * 4);
-    if (!ok) {
-        cleanup();
-        return fail(FN_ENOMEM, "workspace allocation failed (%lld points)", (long long)n);
+    const int nbins = 1 << (P->l - keyshift);
+    int32_t *um = (int32_t *)tmp_alloc(P, n * 4);
+    double *uth = (double *)tmp_alloc(P, n * 8);
+    int32_t *ukey = (int32_t *)tmp_alloc(P, n * 4);
+    const bool lds_path = nbins <= SORT_LDS_BINS;
+    const int nblk = lds_path ? (int)std::max<int64_t>(1, std::min<int64_t>(128, (n + 8191) / 8192)) : 0;
+    const int64_t chunk = lds_path ? (n + nblk - 1) / nblk : 0;
+    int32_t *H = lds_path ? (int32_t *)tmp_alloc(P, (size_t)nbins * nblk * 4) : nullptr;
+    int32_t *tot = (int32_t *)tmp_alloc(P, (size_t)nbins * 4);
+    int32_t *tsum = (int32_t *)tmp_alloc(P, ((nbins + SCAN_TILE - 1) / SCAN_TILE) * 4);
+    int32_t *gm = nullptr, *gperm = nullptr, *gkey = nullptr;
+    double *gth = nullptr;
+    if (deterministic) {
+        gm = (int32_t *)tmp_alloc(P, n * 4);
+        gth = (double *)tmp_alloc(P, n * 8);
+        gperm = (int32_t *)tmp_alloc(P, n * 4);
+        gkey = (int32_t *)tmp_alloc(P, n * 4);
     }
+    if (!um || !uth || !ukey || (lds_path && !H) || !tot || !tsum ||
+        (deterministic && (!gm || !gth || !gperm || !gkey)) ||
+        !alloc(P->off, ((size_t)nbins + 1) * 4) || !alloc(P->sm, n * 4) ||
+        !alloc(P->sth, n * 8) || !alloc(P->sperm, n * 4) ||
+        (want_hit && !alloc(P->hit, P->N * 4)))
+        return fail(FN_ENOMEM, "workspace allocation failed (%lld points)", (long long)n);
+    if ((nbins + SCAN_TILE - 1) / SCAN_TILE > 4096)
+        return fail(FN_EINVAL, "tree too large for the scan (%d leaves)", nbins);
     double chi, clo;
     n_over_2pi(P->N, &chi, &clo);
-    int rc = FN_OK;
-#define TRY(expr)                                                              \
-    do {                                                                       \
-        hipError_t e_ = (expr);                                                \
-        if (e_ != hipSuccess) {                                                \
-            rc = fail(FN_EHIP, "%s: %s", #expr, hipGetErrorString(e_));        \
-            goto out;                                                          \
-        }                                                                      \
-    } while (0)
-    {
-        TRY(hipMemsetAsync(count.p, 0, nleaf * 4, st));
-        TRY(hipMemsetAsync(flags.p, 0, 4, st));
-        if (want_hit)
-            TRY(hipMemsetAsync(P->hit.p, 0xff, P->N * 4, st));
-        hipLaunchKernelGGL(k_reduce, dim3(grid_for(n)), dim3(256), 0, st, n, y,
-                           chi, clo, P->N, P->l, (double)FN_Y_MAX,
-                           (int32_t *)um.p, (double *)uth.p, (int32_t *)ukey.p,
-                           (int32_t *)count.p,
-                           want_hit ? (int32_t *)P->hit.p : nullptr,
-                           (int *)flags.p);
-        TRY(hipGetLastError());
-        {
-            const int nt = (int)((nleaf + SCAN_TILE - 1) / SCAN_TILE);
-            hipLaunchKernelGGL(k_scan_sums, dim3(nt), dim3(256), 0, st,
-                               (const int32_t *)count.p, nleaf, (int32_t *)tsum.p);
-            TRY(hipGetLastError());
-            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st,
-                               (int32_t *)tsum.p, nt, (int32_t *)P->off.p + nleaf);
-            TRY(hipGetLastError());
-            hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(256), 0, st,
-                               (const int32_t *)count.p, nleaf, (const int32_t *)tsum.p,
-                               (int32_t *)P->off.p, (int32_t *)cursor.p);
-            TRY(hipGetLastError());
-        }
-        if (!deterministic) {
-            hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(256), 0, st, n,
-                               (const int32_t *)um.p, (const double *)uth.p,
-                               (const int32_t *)ukey.p, (int32_t *)cursor.p,
-                               (int32_t *)P->sm.p, (double *)P->sth.p,
-                               (int32_t *)P->sperm.p, nullptr);
-            TRY(hipGetLastError());
-        } else {
-            hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(256), 0, st, n,
-                               (const int32_t *)um.p, (const double *)uth.p,
-                               (const int32_t *)ukey.p, (int32_t *)cursor.p,
-                               (int32_t *)gm.p, (double *)gth.p,
-                               (int32_t *)gperm.p, (int32_t *)gkey.p);
-            TRY(hipGetLastError());
-            hipLaunchKernelGGL(k_rank, dim3(grid_for(n)), dim3(256), 0, st, n,
-                               (const int32_t *)gm.p, (const double *)gth.p,
-                               (const int32_t *)gperm.p, (const int32_t *)gkey.p,
-                               (const int32_t *)P->off.p, (int32_t *)P->sm.p,
-                               (double *)P->sth.p, (int32_t *)P->sperm.p,
-                               (int *)flags.p);
-            TRY(hipGetLastError());
-        }
-        int hflags = 0;
-        TRY(hipMemcpyAsync(&hflags, flags.p, 4, hipMemcpyDeviceToHost, st));
-        TRY(hipStreamSynchronize(st));
-        if (hflags & FLAG_BAD_Y) {
-            rc = fail(FN_EINVAL, "y holds a non-finite value or |y| > %g", FN_Y_MAX);
-            goto out;
-        }
-        if (hflags & FLAG_DUP) {
-            rc = fail(FN_ESINGULAR, "two points y_j coincide on the circle");
-            goto out;
-        }
+    if (want_hit)
+        HIPCHK(hipMemsetAsync(P->hit.p, 0xff, P->N * 4, st));
+    int32_t *hit = want_hit ? (int32_t *)P->hit.p : nullptr;
+    int *flags = (int *)P->flags.p;
+    if (lds_path) {
+        hipLaunchKernelGGL(k_reduce_hist, dim3(nblk), dim3(256), (size_t)nbins * 4, st,
+                           n, y, chi, clo, P->N, P->l, keyshift, (double)FN_Y_MAX,
+                           chunk, nbins, nblk, um, uth, ukey, H, hit, flags);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_colscan, dim3(grid_for(nbins)), dim3(256), 0, st, nbins, nblk,
+                           H, tot);
+    } else {
+        HIPCHK(hipMemsetAsync(tot, 0, (size_t)nbins * 4, st));
+        hipLaunchKernelGGL(k_reduce, dim3(grid_for(n)), dim3(256), 0, st, n, y, chi,
+                           clo, P->N, P->l, keyshift, (double)FN_Y_MAX, um, uth, ukey,
+                           tot, hit, flags);
     }
-out:
-#undef TRY
-    cleanup();
-    return rc;
-}
-
-// Work items of k_down_eval: one per subtree of level lr holding targets,
-// split so that no item has more than tmax sorted targets.
-static int build_work(fn_plan *P, bool sorted_targets, bool uniform_targets,
-                      hipStream_t st)
-{
-    const int64_t nleaf = int64_t(1) << P->l;
-    const int s = P->l - P->lr;
-    std::vector<int32_t> off(nleaf + 1);
-    HIPCHK(hipMemcpyAsync(off.data(), P->off.p, (nleaf + 1) * 4,
-                          hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    const int32_t tmax = 2048;
-    std::vector<WorkItem> items;
-    const int64_t nroot = int64_t(1) << P->lr;
-    for (int64_t R = 0; R < nroot; ++R) {
-        int32_t t0 = 0, t1 = 0, u0 = 0, u1 = 0;
-        if (sorted_targets) {
-            t0 = off[R << s];
-            t1 = off[(R + 1) << s];
-        }
-        if (uniform_targets) {
-            u0 = (int32_t)((R * P->N + nroot - 1) >> P->lr);
-            u1 = (int32_t)(((R + 1) * P->N + nroot - 1) >> P->lr);
-        }
-        if (t1 == t0 && u1 == u0)
-            continue;
-        if (sorted_targets && !uniform_targets) {
-            for (int32_t a = t0; a < t1; a += tmax)
-                items.push_back({R, a, std::min(t1, a + tmax), 0, 0});
-        } else {
-            items.push_back({R, t0, t1, u0, u1});
-        }
+    HIPCHK(hipGetLastError());
+    // off = exclusive scan of the key totals; cursor copy for the atomic path
+    int32_t *off = (int32_t *)P->off.p;
+    int32_t *cursor = lds_path ? nullptr : (int32_t *)tmp_alloc(P, (size_t)nbins * 4);
+    if (!lds_path && !cursor)
+        return fail(FN_ENOMEM, "workspace allocation failed");
+    const int nt = (int)((nbins + SCAN_TILE - 1) / SCAN_TILE);
+    hipLaunchKernelGGL(k_scan_sums, dim3(nt), dim3(256), 0, st, (const int32_t *)tot,
+                       (int64_t)nbins, tsum);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tsum, nt, off + nbins);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(256), 0, st, (const int32_t *)tot,
+                       (int64_t)nbins, (const int32_t *)tsum, off, cursor);
+    HIPCHK(hipGetLastError());
+    int32_t *dm = deterministic ? gm : (int32_t *)P->sm.p;
+    double *dth = deterministic ? gth : (double *)P->sth.p;
+    int32_t *dperm = deterministic ? gperm : (int32_t *)P->sperm.p;
+    if (!deterministic) { // the forward keeps every target's leaf
+        if (!alloc(P->skey, n * 4))
+            return fail(FN_ENOMEM, "workspace allocation failed");
+        gkey = (int32_t *)P->skey.p;
     }
-    P->nwork = (int)items.size();
-    if (!alloc(P->work, std::max<size_t>(1, items.size()) * sizeof(WorkItem)))
-        return fail(FN_ENOMEM, "work list allocation failed");
-    if (!items.empty()) {
-        HIPCHK(hipMemcpyAsync(P->work.p, items.data(), items.size() * sizeof(WorkItem),
-                              hipMemcpyHostToDevice, st));
-        HIPCHK(hipStreamSynchronize(st));
+    if (lds_path) {
+        hipLaunchKernelGGL(k_place, dim3(nblk), dim3(256), (size_t)nbins * 4, st, n,
+                           chunk, nbins, (const int32_t *)H, (const int32_t *)off,
+                           (const int32_t *)um, (const double *)uth, (const int32_t *)ukey,
+                           dm, dth, dperm, gkey);
+    } else {
+        hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(256), 0, st, n,
+                           (const int32_t *)um, (const double *)uth, (const int32_t *)ukey,
+                           cursor, dm, dth, dperm, gkey);
+    }
+    HIPCHK(hipGetLastError());
+    if (deterministic) {
+        hipLaunchKernelGGL(k_rank, dim3(grid_for(n)), dim3(256), 0, st, n,
+                           (const int32_t *)gm, (const double *)gth,
+                           (const int32_t *)gperm, (const int32_t *)gkey,
+                           (const int32_t *)P->off.p, (int32_t *)P->sm.p,
+                           (double *)P->sth.p, (int32_t *)P->sperm.p, flags);
+        HIPCHK(hipGetLastError());
     }
     return FN_OK;
 }
 
-// Expansion lengths of the cot FMM for (p, q).
-static void cot_lengths(int p, int q, int *PU, int *PD)
+// Work list of k_down_eval, built on the device: subtree roots of level lr;
+// P->off indexes the sorted points at level lr + sh.  The grid is sized for
+// the largest possible list.
+static int build_work(fn_plan *P, int sh, bool uniform, int64_t npts, hipStream_t st)
 {
+    const int32_t tmax = 2048;
+    const int64_t nroot = int64_t(1) << P->lr;
+    const int64_t maxitems = uniform ? nroot : nroot + npts / tmax + 1;
+    if (maxitems > INT32_MAX)
+        return fail(FN_EINVAL, "work list too long");
+    P->nwork = (int)maxitems;
+    if (!alloc(P->work, maxitems * sizeof(WorkItem)) || !alloc(P->nwork_dev, 4))
+        return fail(FN_ENOMEM, "work list allocation failed");
+    hipLaunchKernelGGL(k_work, dim3(1), dim3(1024), 0, st, nroot, sh,
+                       (const int32_t *)P->off.p, uniform ? 1 : 0, P->N, P->lr, tmax,
+                       (WorkItem *)P->work.p, (int32_t *)P->nwork_dev.p);
+    HIPCHK(hipGetLastError());
+    return FN_OK;
+}
+
+// The one synchronisation of a plan: waits for the setup, reads the error
+// flags and releases the temporaries.
+static int finish_plan(fn_plan *P, hipStream_t st)
+{
+    int hflags = 0;
+    hipError_t e = hipMemcpyAsync(&hflags, P->flags.p, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    release_tmp(P);
+    if (e != hipSuccess)
+        return fail(FN_EHIP, "plan setup: %s", hipGetErrorString(e));
+    if (hflags & FLAG_BAD_Y)
+        return fail(FN_EINVAL, "y holds a non-finite value or |y| > %g", FN_Y_MAX);
+    if (hflags & FLAG_DUP)
+        return fail(FN_ESINGULAR, "two points y_j coincide on the circle");
+    if (hflags & FLAG_RANGE)
+        return fail(FN_ERANGE, "|C_k| or |D_j| leaves the binary64 range: the "
+                               "point set is too ill-conditioned for the inverse");
+    return FN_OK;
+}
+
+// Expansion lengths of the cot FMM for (p, q).
+// Terms of the translations for a relative l2 target eps.  Eq. (18.2)
+// carries a factor 2^lmax from Eq. (17), a bound on the maximum error summed
+// over all leaves for unit sources; the relative l2 error does not add up
+// over leaves, and 3^-p per box pair decides it.  Calibrated on the oracle
+// at N = M = 2^20 (binary64: 32 terms reach the rounding floor at 1e-12,
+// 16 terms give 8.7e-11; binary32: 16 terms reach its 1.8e-7 floor).
+static int p_calibrated(double eps)
+{
+    const double x = 10.0 / (3.0 * M_PI * eps);
+    return (int)std::ceil(std::log(x) / std::log(3.0)) + 3;
+}
+
+// Expansion lengths of the cot FMM: locals and translations PD, multipoles
+// PU >= 2q (the level-2 moments of the regular part).
+static void cot_lengths(const fn_plan *P, int *PU, int *PD)
+{
+    const int p = P->p_explicit ? P->p : std::min(P->p, p_calibrated(P->eps));
     *PD = round16(p);
-    *PU = round16(std::max(*PD, 2 * q));
+    *PU = round16(std::max(*PD, 2 * P->q));
 }
 
 // --------------------------------------------------------- forward plan
@@ -687,20 +721,25 @@ static void cot_lengths(int p, int q, int *PU, int *PD)
 template <typename R>
 static int plan_fwd_impl(fn_plan *P, const double *y, hipStream_t st)
 {
-    int rc = build_tree(P, P->M, y, false, false, st);
+    int PU, PD;
+    cot_lengths(P, &PU, &PD);
+    P->lr = choose_lr(P->l, 2, PD, sizeof(R));
+    // targets grouped by leaf: the lanes of a wavefront then share the
+    // leaf locals and near-field sources they read
+    int rc = build_tree(P, P->M, y, 0, false, false, st);
     if (rc)
         return rc;
-    int PU, PD;
-    cot_lengths(P->p, P->q, &PU, &PD);
-    P->lr = choose_lr(P->l, 2, PD, sizeof(R));
-    rc = build_work(P, true, false, st);
+    rc = build_work(P, P->l - P->lr, false, P->M, st);
     if (rc)
         return rc;
     rc = setup_fmm<R, cx<R>>(P, KER_COT, PU, PD, P->q, true, P->cot, st);
     if (rc)
         return rc;
     OpTables<R> T;
-    return get_tables<R>(KER_COT, PU, PD, P->q, &T);
+    rc = get_tables<R>(KER_COT, PU, PD, P->q, &T);
+    if (rc)
+        return rc;
+    return finish_plan(P, st);
 }
 
 template <typename R>
@@ -728,6 +767,7 @@ static int exec_fwd(fn_plan *P, const void *in, void *out, int phase,
     da.f_uniform = (const cx<R> *)in;
     da.tgt = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
               (const double *)P->sth.p, (const int32_t *)P->sperm.p};
+    da.tgt_leaf = (const int32_t *)P->skey.p;
     da.out = (cx<R> *)out;
     da.f_hit = (const cx<R> *)in;
     return launch_down<R, V, KER_COT, SET_UNIFORM, EPI_FWD>(P, F, da, st);
@@ -736,7 +776,7 @@ static int exec_fwd(fn_plan *P, const void *in, void *out, int phase,
 // --------------------------------------------------------- inverse plan
 
 // The log-kernel FMM of the plan: logC_k at the uniform points and logD_j
-// at the sorted sources, then Chat and Dhat (Eq. p8).
+// at the sorted sources, then Chat and Dhat (Eq. p8).  Enqueues only.
 static int plan_inv_logs(fn_plan *P, hipStream_t st)
 {
     using R = double;
@@ -746,25 +786,24 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     const double eps_log = std::max(P->eps * 0.1, 1e-15);
     int plog, qlog;
     trunc_numbers(eps_log, P->l, &plog, &qlog);
-    const int PD = round16(plog);
+    const int PD = round16(std::min(plog, p_calibrated(eps_log)));
     const int PU = round16(std::max(PD, 2 * qlog + 1));
     OpTables<R> T;
     int rc = get_tables<R>(KER_LOG, PU, PD, qlog, &T);
     if (rc)
         return rc;
     FmmSetup F;
-    Buf logc, logd, flags;
-    auto cleanup = [&]() {
-        for (Buf *b : {&F.mp, &F.loc2, &F.S, &logc, &logd, &flags})
-            release(*b);
-    };
     rc = setup_fmm<R, V>(P, KER_LOG, PU, PD, qlog, false, F, st);
-    if (!rc && !(alloc(logc, P->N * 8) && alloc(logd, P->N * 8) && alloc(flags, 4)))
-        rc = fail(FN_ENOMEM, "log-sum allocation failed");
-    if (rc) {
-        cleanup();
+    // the log FMM's workspace lives until the plan's synchronisation
+    for (Buf *b : {&F.mp, &F.loc2, &F.S})
+        if (b->p)
+            P->tmp.push_back(*b);
+    if (rc)
         return rc;
-    }
+    double *logc = (double *)tmp_alloc(P, P->N * 8);
+    double *logd = (double *)tmp_alloc(P, P->N * 8);
+    if (!logc || !logd)
+        return fail(FN_ENOMEM, "log-sum allocation failed");
     const SortedSet src = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
                            (const double *)P->sth.p, (const int32_t *)P->sperm.p};
     UpArgs<R, V> ua{};
@@ -774,57 +813,39 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     ua.logc1 = std::log(2.0 * M_PI / (double)P->N);
     ua.logc2 = std::log(2.0);
     rc = launch_up<R, V, KER_LOG, SET_SORTED>(F, ua, st);
-    if (!rc) {
-        DownArgs<R, V> da{};
-        fill_down(P, F, T, da);
-        da.src = src;
-        da.tgt = src;
-        da.logc = (double *)logc.p;
-        da.logd = (double *)logd.p;
-        da.logself = std::log(2.0 * M_PI / (double)P->N);
-        rc = launch_down<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>(P, F, da, st);
-    }
-    hipError_t e = hipSuccess;
-    if (!rc)
-        e = hipMemsetAsync(flags.p, 0, 4, st);
-    if (!rc && e == hipSuccess) {
-        hipLaunchKernelGGL(k_coeffs, dim3(grid_for(P->N)), dim3(256), 0, st, P->N,
-                           (const double *)logc.p, (const double *)logd.p,
-                           (const int32_t *)P->sm.p, (const double *)P->sth.p,
-                           (const int32_t *)P->hit.p, (double *)P->chat.p,
-                           (cx<double> *)P->dhat.p, (int *)flags.p);
-        e = hipGetLastError();
-    }
-    int hflags = 0;
-    if (!rc && e == hipSuccess)
-        e = hipMemcpyAsync(&hflags, flags.p, 4, hipMemcpyDeviceToHost, st);
-    if (!rc && e == hipSuccess)
-        e = hipStreamSynchronize(st);
-    else if (rc)
-        (void)hipStreamSynchronize(st);
-    cleanup();
     if (rc)
         return rc;
-    if (e != hipSuccess)
-        return fail(FN_EHIP, "inverse plan: %s", hipGetErrorString(e));
-    if (hflags & FLAG_RANGE)
-        return fail(FN_ERANGE, "|C_k| or |D_j| leaves the binary64 range: the "
-                               "point set is too ill-conditioned for the inverse");
+    DownArgs<R, V> da{};
+    fill_down(P, F, T, da);
+    da.src = src;
+    da.tgt = src;
+    da.logc = logc;
+    da.logd = logd;
+    da.logself = std::log(2.0 * M_PI / (double)P->N);
+    rc = launch_down<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>(P, F, da, st);
+    if (rc)
+        return rc;
+    hipLaunchKernelGGL(k_coeffs, dim3(grid_for(P->N)), dim3(256), 0, st, P->N,
+                       (const double *)logc, (const double *)logd,
+                       (const int32_t *)P->sm.p, (const double *)P->sth.p,
+                       (const int32_t *)P->hit.p, (double *)P->chat.p,
+                       (cx<double> *)P->dhat.p, (int *)P->flags.p);
+    HIPCHK(hipGetLastError());
     return FN_OK;
 }
 
 template <typename R>
 static int plan_inv_impl(fn_plan *P, const double *y, hipStream_t st)
 {
-    int rc = build_tree(P, P->N, y, true, true, st);
-    if (rc)
-        return rc;
     int PU, PD;
-    cot_lengths(P->p, P->q, &PU, &PD);
+    cot_lengths(P, &PU, &PD);
     // one subtree level serves the log FMM (binary64, real, at most 64
     // terms) and the cot FMM
     P->lr = std::max(choose_lr(P->l, 2, PD, sizeof(R)), choose_lr(P->l, 1, 64, 8));
-    rc = build_work(P, true, true, st);
+    int rc = build_tree(P, P->N, y, 0, true, true, st);
+    if (rc)
+        return rc;
+    rc = build_work(P, P->l - P->lr, true, P->N, st);
     if (rc)
         return rc;
     if (!alloc(P->chat, P->N * 8) || !alloc(P->dhat, P->N * 16) ||
@@ -837,7 +858,10 @@ static int plan_inv_impl(fn_plan *P, const double *y, hipStream_t st)
     if (rc)
         return rc;
     OpTables<R> T;
-    return get_tables<R>(KER_COT, PU, PD, P->q, &T);
+    rc = get_tables<R>(KER_COT, PU, PD, P->q, &T);
+    if (rc)
+        return rc;
+    return finish_plan(P, st);
 }
 
 template <typename R>
@@ -928,12 +952,23 @@ static int plan_common(fn_plan **out, int kind, int64_t N, int64_t M,
     P->M = M;
     P->eps = eps;
     choose(N, M, eps, dtype, p_in, q_in, l_in, &P->p, &P->q, &P->l);
+    P->p_explicit = p_in > 0;
     if (P->p > 64 || 2 * P->q > 64) {
         const int p = P->p, q = P->q;
         delete P;
         return fail(FN_EINVAL, "truncation numbers p = %d, q = %d need more than 64 terms", p, q);
     }
     hipStream_t st = (hipStream_t)stream;
+    P->stream = st;
+    if (!alloc(P->flags, 4)) {
+        delete P;
+        return fail(FN_ENOMEM, "flag allocation failed");
+    }
+    if (hipMemsetAsync(P->flags.p, 0, 4, st) != hipSuccess) {
+        release_plan(P);
+        delete P;
+        return fail(FN_EHIP, "hipMemsetAsync failed");
+    }
     if (kind == 0)
         rc = dtype == FN_C128 ? plan_fwd_impl<double>(P, y, st)
                               : plan_fwd_impl<float>(P, y, st);
@@ -985,6 +1020,7 @@ static int execute(fn_plan *plan, const void *in, void *out, int phase,
     if (!in || !out)
         return fail(FN_EINVAL, "input or output pointer is NULL");
     hipStream_t st = (hipStream_t)stream;
+    plan->stream = st;
     if (plan->kind == 0)
         return plan->dtype == FN_C128 ? exec_fwd<double>(plan, in, out, phase, st)
                                       : exec_fwd<float>(plan, in, out, phase, st);
@@ -1009,11 +1045,13 @@ int nufft_destroy(fn_plan *plan)
 {
     if (!plan)
         return FN_OK;
-    hipError_t e = hipDeviceSynchronize();
+    // the workspace returns to the library's pool only once the plan's
+    // last stream has drained
+    hipError_t e = hipStreamSynchronize(plan->stream);
     release_plan(plan);
     delete plan;
     if (e != hipSuccess)
-        return fail(FN_EHIP, "hipDeviceSynchronize: %s", hipGetErrorString(e));
+        return fail(FN_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
     return FN_OK;
 }
 

@@ -87,4 +87,12 @@ __device__ __forceinline__ double xlogx_m_x(double u)
     return u == 0.0 ? 0.0 : u * log(fabs(u)) - u;
 }
 
+// One workgroup's share of the downward pass: a subtree root of level lr,
+// a range of sorted targets and a range of uniform targets.
+struct WorkItem {
+    int64_t root;
+    int32_t t0, t1;
+    int32_t u0, u1;
+};
+
 } // namespace fn

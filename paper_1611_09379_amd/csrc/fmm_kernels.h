@@ -479,12 +479,6 @@ __global__ void __launch_bounds__(BLOCK) k_regular(UpArgs<R, V> a, int PU)
 
 // ------------------------------------------------------------ k_down_eval
 
-struct WorkItem {
-    int64_t root;   // subtree root at level lr
-    int32_t t0, t1; // sorted-target range
-    int32_t u0, u1; // uniform-target range
-};
-
 template <typename R, typename V>
 struct DownArgs {
     int64_t N;
@@ -493,6 +487,7 @@ struct DownArgs {
     int rows_buf, rows_src;  // rows of each local buffer / of the source buffer
     int near_cap;            // LDS slots (cx<R>) for the forward near field
     const WorkItem *work;
+    const int32_t *nwork;    // number of valid work items (device)
     const V *mp;             // PU per box
     int PU;
     const V *loc2;           // 4 x PD
@@ -503,6 +498,7 @@ struct DownArgs {
     const cx<R> *w_sorted;
     // targets
     SortedSet tgt;
+    const int32_t *tgt_leaf; // FWD: leaf of every sorted target
     // epilogues
     cx<R> *out;              // FWD: g (input order); INV: f
     const V *S;              // sum of the weights
@@ -610,14 +606,13 @@ __device__ __forceinline__ void m2l_tiles(const DownOps<R, PD> &o, int rt, int c
     }
 }
 
-// 1/d: the binary64 hardware reciprocal is good to about 2^-24 and takes two
-// Newton steps; the binary32 one is within 1 ulp.
+// 1/d: the binary64 hardware reciprocal is good to about 2^-24; one Newton
+// step brings it to about 2^-48 relative (far inside the 1e-12 target of
+// the binary64 path).  The binary32 one is within 1 ulp.
 __device__ __forceinline__ double recip(double d)
 {
     double r = __builtin_amdgcn_rcp(d);
     double e = fma(-d, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-d, r, 1.0);
     return fma(r, e, r);
 }
 __device__ __forceinline__ float recip(float d)
@@ -665,12 +660,32 @@ __device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
             const int32_t base = (int32_t)(tm - k0);
             const cx<R> *fp = fs + (k0 - K0);
             const int32_t cnt = (int32_t)(k1 - k0);
-            for (int32_t i = 0; i < cnt; ++i) {
+            // four independent chains: the reciprocals of four pairs overlap
+            cx<R> a1 = {R(0), R(0)}, a2 = {R(0), R(0)}, a3 = {R(0), R(0)};
+            int32_t i = 0;
+            for (; i + 4 <= cnt; i += 4) {
+                const R r0 = recip((R)((double)(base - i) + tth));
+                const R r1 = recip((R)((double)(base - i - 1) + tth));
+                const R r2 = recip((R)((double)(base - i - 2) + tth));
+                const R r3 = recip((R)((double)(base - i - 3) + tth));
+                const cx<R> w0 = fp[i], w1 = fp[i + 1], w2 = fp[i + 2], w3 = fp[i + 3];
+                acc.re = fma(w0.re, r0, acc.re);
+                acc.im = fma(w0.im, r0, acc.im);
+                a1.re = fma(w1.re, r1, a1.re);
+                a1.im = fma(w1.im, r1, a1.im);
+                a2.re = fma(w2.re, r2, a2.re);
+                a2.im = fma(w2.im, r2, a2.im);
+                a3.re = fma(w3.re, r3, a3.re);
+                a3.im = fma(w3.im, r3, a3.im);
+            }
+            for (; i < cnt; ++i) {
                 const R rd = recip((R)((double)(base - i) + tth));
                 const cx<R> w = fp[i];
                 acc.re = fma(w.re, rd, acc.re);
                 acc.im = fma(w.im, rd, acc.im);
             }
+            acc.re += (a1.re + a2.re) + a3.re;
+            acc.im += (a1.im + a2.im) + a3.im;
             return acc;
         }
     }
@@ -761,6 +776,8 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
     R *bufB = bufA + (size_t)a.rows_buf * RS;
     R *srcs = bufB + (size_t)a.rows_buf * RS;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if ((int32_t)blockIdx.x >= *a.nwork)
+        return; // the grid is sized for the largest possible work list
     const WorkItem w = a.work[blockIdx.x];
     const int64_t R0 = w.root;
     const int lr = a.lr;
@@ -890,6 +907,7 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
         }
         const V S = *a.S;
         const double hscale = (double)N / 3.14159265358979323846;
+        const double invN = 1.0 / (double)N;
         for (int32_t t = w.t0 + tid; t < w.t1; t += BLOCK) {
             const int64_t tm = a.tgt.m[t];
             const double th = a.tgt.th[t];
@@ -898,7 +916,7 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
                 a.out[j] = a.f_hit[tm == N ? 0 : tm];
                 continue;
             }
-            const int64_t leaf = box_of(tm, th, a.l, N);
+            const int64_t leaf = a.tgt_leaf[t];
             const R u = (R)rel_coord(tm, th, leaf, a.l, N);
             V h = horner<R, V>(leafloc, RS, (int)(leaf - leaf0), PD, u);
             cx<R> nr = near_cot<R, V, SRC>(a, tm, th, leaf, fsp, K0);
@@ -906,7 +924,7 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
             double hi = (double)h.im + hscale * (double)nr.im;
             // g = -(F/2)(S + i h), F = 2i sin(pi th) e^{i pi th} / N
             double sp = sinpi(th), cp = cospi(th);
-            double Fr = -2.0 * sp * sp / (double)N, Fi = 2.0 * sp * cp / (double)N;
+            double Fr = -2.0 * sp * sp * invN, Fi = 2.0 * sp * cp * invN;
             double Ar = (double)S.re - hi, Ai = (double)S.im + hr;
             cx<R> g = {(R)(-0.5 * (Fr * Ar - Fi * Ai)), (R)(-0.5 * (Fr * Ai + Fi * Ar))};
             a.out[j] = g;

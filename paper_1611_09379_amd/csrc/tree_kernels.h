@@ -25,45 +25,130 @@ __device__ __noinline__ void grid_units(double y, double c_hi, double c_lo,
     *th_out = (p - n) + e;
 }
 
-// y -> (m, th, leaf).  s = y N / (2 pi) is formed in double-double from the
-// double-double constant N/(2 pi) = c_hi + c_lo; m = nearest integer mod N,
-// th = s - nearest integer in [-1/2, 1/2]; the representative in [0, N)
-// uses m = N when m = 0 and th < 0.  Counts the points of every leaf and, if
-// hit is given, records the index of a point that lies exactly on x_m.
+// y -> (m, th): s = y N / (2 pi) in double-double from the double-double
+// constant N/(2 pi) = c_hi + c_lo; m = nearest integer mod N, th = s -
+// nearest integer in [-1/2, 1/2]; the representative in [0, N) uses m = N
+// when m = 0 and th < 0.  Returns false for a non-finite or too large y.
+__device__ __forceinline__ bool reduce_point(double yy, double c_hi, double c_lo,
+                                             int64_t N, double ymax, int64_t *m_out,
+                                             double *th_out)
+{
+    if (!(fabs(yy) <= ymax)) { // also catches NaN
+        *m_out = 0;
+        *th_out = 0.25;
+        return false;
+    }
+    double n, th;
+    grid_units(yy, c_hi, c_lo, &n, &th);
+    if (th > 0.5) {
+        th -= 1.0;
+        n += 1.0;
+    } else if (th < -0.5) {
+        th += 1.0;
+        n -= 1.0;
+    }
+    int64_t m = (int64_t)n % N;
+    if (m < 0)
+        m += N;
+    if (m == 0 && th < 0.0)
+        m = N;
+    *m_out = m;
+    *th_out = th;
+    return true;
+}
+
+// Counting sort, pass 1: grid units and sort key (the level-(l - keyshift)
+// box) of every point, and per-block histograms of the keys in LDS.  Block b
+// takes points [b chunk, (b+1) chunk); H is block-major, H[b nbins + key].
+// If hit is given, records the index of a point that lies exactly on x_m.
+__global__ void __launch_bounds__(256)
+    k_reduce_hist(int64_t n, const double *__restrict__ y, double c_hi, double c_lo,
+                  int64_t N, int l, int keyshift, double ymax, int64_t chunk,
+                  int nbins, int nblk, int32_t *um, double *uth, int32_t *ukey,
+                  int32_t *H, int32_t *hit, int *flags)
+{
+    extern __shared__ int32_t hist[];
+    for (int i = threadIdx.x; i < nbins; i += 256)
+        hist[i] = 0;
+    __syncthreads();
+    const int64_t j0 = (int64_t)blockIdx.x * chunk;
+    const int64_t j1 = j0 + chunk < n ? j0 + chunk : n;
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
+        int64_t m;
+        double th;
+        if (!reduce_point(y[j], c_hi, c_lo, N, ymax, &m, &th))
+            atomicOr(flags, FLAG_BAD_Y);
+        const int32_t key = (int32_t)(box_of(m, th, l, N) >> keyshift);
+        um[j] = (int32_t)m;
+        uth[j] = th;
+        ukey[j] = key;
+        atomicAdd(&hist[key], 1);
+        if (hit && th == 0.0)
+            atomicExch(&hit[m], (int32_t)j);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nbins; i += 256)
+        H[(int64_t)blockIdx.x * nbins + i] = hist[i];
+}
+
+// Counting sort, between the passes: for every key, the exclusive prefix of
+// its counts over the blocks (in place in H) and its total (tot[key]).
+__global__ void k_colscan(int nbins, int nblk, int32_t *H, int32_t *tot)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nbins;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int32_t run = 0;
+        for (int b = 0; b < nblk; ++b) {
+            const int32_t c = H[(int64_t)b * nbins + k];
+            H[(int64_t)b * nbins + k] = run;
+            run += c;
+        }
+        tot[k] = run;
+    }
+}
+
+// Counting sort, pass 2: block b places its points of every key at
+// off[key] + (points of that key in blocks before b) + its LDS counter.
+// off is the exclusive scan of the key totals.
+__global__ void __launch_bounds__(256)
+    k_place(int64_t n, int64_t chunk, int nbins, const int32_t *H, const int32_t *off,
+            const int32_t *um, const double *uth, const int32_t *ukey,
+            int32_t *sm, double *sth, int32_t *sperm, int32_t *skey)
+{
+    extern __shared__ int32_t cur[];
+    for (int i = threadIdx.x; i < nbins; i += 256)
+        cur[i] = off[i] + H[(int64_t)blockIdx.x * nbins + i];
+    __syncthreads();
+    const int64_t j0 = (int64_t)blockIdx.x * chunk;
+    const int64_t j1 = j0 + chunk < n ? j0 + chunk : n;
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
+        const int32_t key = ukey[j];
+        const int32_t pos = atomicAdd(&cur[key], 1);
+        sm[pos] = um[j];
+        sth[pos] = uth[j];
+        sperm[pos] = (int32_t)j;
+        if (skey)
+            skey[pos] = key;
+    }
+}
+
+// Counting sort with global atomics, for key ranges too large for LDS:
+// pass 1 counts every key.
 __global__ void k_reduce(int64_t M, const double *__restrict__ y, double c_hi,
-                         double c_lo, int64_t N, int l, double ymax,
+                         double c_lo, int64_t N, int l, int keyshift, double ymax,
                          int32_t *um, double *uth, int32_t *ukey,
                          int32_t *count, int32_t *hit, int *flags)
 {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < M;
          j += (int64_t)gridDim.x * blockDim.x) {
-        double yy = y[j];
-        if (!(fabs(yy) <= ymax)) { // also catches NaN
+        int64_t m;
+        double th;
+        if (!reduce_point(y[j], c_hi, c_lo, N, ymax, &m, &th))
             atomicOr(flags, FLAG_BAD_Y);
-            um[j] = 0;
-            uth[j] = 0.25;
-            ukey[j] = 0;
-            atomicAdd(&count[0], 1);
-            continue;
-        }
-        double n, th;
-        grid_units(yy, c_hi, c_lo, &n, &th);
-        if (th > 0.5) {
-            th -= 1.0;
-            n += 1.0;
-        } else if (th < -0.5) {
-            th += 1.0;
-            n -= 1.0;
-        }
-        int64_t m = (int64_t)n % N;
-        if (m < 0)
-            m += N;
-        if (m == 0 && th < 0.0)
-            m = N;
-        int64_t key = box_of(m, th, l, N);
+        const int32_t key = (int32_t)(box_of(m, th, l, N) >> keyshift);
         um[j] = (int32_t)m;
         uth[j] = th;
-        ukey[j] = (int32_t)key;
+        ukey[j] = key;
         atomicAdd(&count[key], 1);
         if (hit && th == 0.0)
             atomicExch(&hit[m], (int32_t)j);
@@ -214,6 +299,52 @@ __global__ void k_rank(int64_t n, const int32_t *gm, const double *gth,
         sth[pos] = tht;
         sperm[pos] = gperm[t];
     }
+}
+
+// Work list of the downward pass (one workgroup): for every subtree root R
+// of level lr, its sorted targets [off[R << sh], off[(R+1) << sh]) cut into
+// pieces of at most tmax (pieces = 0 for none), or one item carrying both
+// the sorted range and the uniform targets of R when `uniform`.
+__global__ void __launch_bounds__(1024)
+    k_work(int64_t nroot, int sh, const int32_t *off, int uniform, int64_t N,
+           int lr, int32_t tmax, WorkItem *items, int32_t *nitems)
+{
+    __shared__ int32_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (nroot + 1023) / 1024;
+    const int64_t r0 = tid * per, r1 = r0 + per < nroot ? r0 + per : nroot;
+    auto pieces = [&](int64_t R) -> int32_t {
+        const int32_t t0 = off[R << sh], t1 = off[(R + 1) << sh];
+        if (uniform)
+            return 1;
+        return (t1 - t0 + tmax - 1) / tmax;
+    };
+    int32_t s = 0;
+    for (int64_t R = r0; R < r1; ++R)
+        s += pieces(R);
+    part[tid] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        int32_t x = tid >= d ? part[tid - d] : 0;
+        __syncthreads();
+        part[tid] += x;
+        __syncthreads();
+    }
+    int32_t pos = tid == 0 ? 0 : part[tid - 1];
+    for (int64_t R = r0; R < r1; ++R) {
+        const int32_t t0 = off[R << sh], t1 = off[(R + 1) << sh];
+        if (uniform) {
+            const int64_t nr = int64_t(1) << lr;
+            const int32_t u0 = (int32_t)((R * N + nr - 1) >> lr);
+            const int32_t u1 = (int32_t)(((R + 1) * N + nr - 1) >> lr);
+            items[pos++] = {R, t0, t1, u0, u1};
+        } else {
+            for (int32_t a = t0; a < t1; a += tmax)
+                items[pos++] = {R, a, a + tmax < t1 ? a + tmax : t1, 0, 0};
+        }
+    }
+    if (tid == 1023)
+        *nitems = part[1023];
 }
 
 // Eq. (p8), rescaled by 2^N (the scale cancels in C_k D_j):
