@@ -292,7 +292,7 @@ struct FmmSetup {
     Band band[MAX_BANDS];
     size_t reg_smem = 0;
     size_t dn_smem = 0;
-    int rows_buf = 0, rows_src = 0, near_cap = 0;
+    int rows_buf = 0, rows_src = 0, near_bytes = 0;
 };
 
 struct fn_plan {
@@ -405,7 +405,7 @@ static int choose_lr(int l, int nc, int PD, int es)
 }
 
 template <typename R, typename V>
-static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool near_stage,
+static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q,
                      FmmSetup &F, hipStream_t st)
 {
     constexpr int NC = ncomp<V>::value;
@@ -440,7 +440,7 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool near_st
     F.dn_smem = down_lds(s, P->lr, F.RSd, es, &F.rows_buf, &F.rows_src);
     if (F.dn_smem > lim)
         return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PD, F.dn_smem);
-    F.near_cap = near_stage ? (int)((size_t)F.rows_src * F.RSd * es / sizeof(cx<R>)) : 0;
+    F.near_bytes = (int)((size_t)(F.rows_buf + F.rows_src) * F.RSd * es);
     const int64_t nmp = lev_off(P->l + 1, PU);
     if (!alloc(F.mp, nmp * sizeof(V)) || !alloc(F.loc2, 4 * PD * sizeof(V)) ||
         !alloc(F.S, sizeof(V)))
@@ -478,7 +478,7 @@ static void fill_down(const fn_plan *P, const FmmSetup &F, const OpTables<R> &T,
     da.RS = F.RSd;
     da.rows_buf = F.rows_buf;
     da.rows_src = F.rows_src;
-    da.near_cap = F.near_cap;
+    da.near_bytes = F.near_bytes;
     da.work = (const WorkItem *)P->work.p;
     da.nwork = (const int32_t *)P->nwork_dev.p;
     da.mp = (const V *)F.mp.p;
@@ -579,10 +579,14 @@ static int build_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
         gm = (int32_t *)tmp_alloc(P, n * 4);
         gth = (double *)tmp_alloc(P, n * 8);
         gperm = (int32_t *)tmp_alloc(P, n * 4);
-        gkey = (int32_t *)tmp_alloc(P, n * 4);
     }
+    // every point's leaf, kept with the plan (k_rank only reorders inside a
+    // leaf, so it holds for the final order too)
+    if (!alloc(P->skey, n * 4))
+        return fail(FN_ENOMEM, "workspace allocation failed");
+    gkey = (int32_t *)P->skey.p;
     if (!um || !uth || !ukey || (lds_path && !H) || !tot || !tsum ||
-        (deterministic && (!gm || !gth || !gperm || !gkey)) ||
+        (deterministic && (!gm || !gth || !gperm)) ||
         !alloc(P->off, ((size_t)nbins + 1) * 4) || !alloc(P->sm, n * 4) ||
         !alloc(P->sth, n * 8) || !alloc(P->sperm, n * 4) ||
         (want_hit && !alloc(P->hit, P->N * 4)))
@@ -626,11 +630,6 @@ static int build_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
     int32_t *dm = deterministic ? gm : (int32_t *)P->sm.p;
     double *dth = deterministic ? gth : (double *)P->sth.p;
     int32_t *dperm = deterministic ? gperm : (int32_t *)P->sperm.p;
-    if (!deterministic) { // the forward keeps every target's leaf
-        if (!alloc(P->skey, n * 4))
-            return fail(FN_ENOMEM, "workspace allocation failed");
-        gkey = (int32_t *)P->skey.p;
-    }
     if (lds_path) {
         hipLaunchKernelGGL(k_place, dim3(nblk), dim3(256), (size_t)nbins * 4, st, n,
                            chunk, nbins, (const int32_t *)H, (const int32_t *)off,
@@ -732,7 +731,7 @@ static int plan_fwd_impl(fn_plan *P, const double *y, hipStream_t st)
     rc = build_work(P, P->l - P->lr, false, P->M, st);
     if (rc)
         return rc;
-    rc = setup_fmm<R, cx<R>>(P, KER_COT, PU, PD, P->q, true, P->cot, st);
+    rc = setup_fmm<R, cx<R>>(P, KER_COT, PU, PD, P->q, P->cot, st);
     if (rc)
         return rc;
     OpTables<R> T;
@@ -793,7 +792,7 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     if (rc)
         return rc;
     FmmSetup F;
-    rc = setup_fmm<R, V>(P, KER_LOG, PU, PD, qlog, false, F, st);
+    rc = setup_fmm<R, V>(P, KER_LOG, PU, PD, qlog, F, st);
     // the log FMM's workspace lives until the plan's synchronisation
     for (Buf *b : {&F.mp, &F.loc2, &F.S})
         if (b->p)
@@ -819,6 +818,7 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     fill_down(P, F, T, da);
     da.src = src;
     da.tgt = src;
+    da.tgt_leaf = (const int32_t *)P->skey.p;
     da.logc = logc;
     da.logd = logd;
     da.logself = std::log(2.0 * M_PI / (double)P->N);
@@ -854,7 +854,7 @@ static int plan_inv_impl(fn_plan *P, const double *y, hipStream_t st)
     rc = plan_inv_logs(P, st);
     if (rc)
         return rc;
-    rc = setup_fmm<R, cx<R>>(P, KER_COT, PU, PD, P->q, false, P->cot, st);
+    rc = setup_fmm<R, cx<R>>(P, KER_COT, PU, PD, P->q, P->cot, st);
     if (rc)
         return rc;
     OpTables<R> T;

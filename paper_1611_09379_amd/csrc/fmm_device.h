@@ -51,6 +51,14 @@ __device__ __forceinline__ double rel_coord(int64_t m, double th, int64_t b,
     return ((double)num + ldexp(th, L + 1)) / (double)N;
 }
 
+// rel_coord with the division replaced by a product with invN = 1 / N.
+__device__ __forceinline__ double rel_coord_r(int64_t m, double th, int64_t b,
+                                              int L, int64_t N, double invN)
+{
+    int64_t num = (m << (L + 1)) - (2 * b + 1) * N;
+    return ((double)num + ldexp(th, L + 1)) * invN;
+}
+
 // First uniform point k of box b at level L: ceil(b N / 2^L).
 __device__ __forceinline__ int64_t uni_start(int64_t b, int L, int64_t N)
 {

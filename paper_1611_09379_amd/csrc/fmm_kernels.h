@@ -485,7 +485,8 @@ struct DownArgs {
     int l, lr;
     int RS;                  // LDS row stride (elements of R)
     int rows_buf, rows_src;  // rows of each local buffer / of the source buffer
-    int near_cap;            // LDS slots (cx<R>) for the forward near field
+    int near_bytes;          // LDS bytes free for the near-field sources
+                             // once the leaf locals are formed
     const WorkItem *work;
     const int32_t *nwork;    // number of valid work items (device)
     const V *mp;             // PU per box
@@ -498,7 +499,7 @@ struct DownArgs {
     const cx<R> *w_sorted;
     // targets
     SortedSet tgt;
-    const int32_t *tgt_leaf; // FWD: leaf of every sorted target
+    const int32_t *tgt_leaf; // leaf of every sorted target (FWD, LOGCD)
     // epilogues
     cx<R> *out;              // FWD: g (input order); INV: f
     const V *S;              // sum of the weights
@@ -720,6 +721,112 @@ __device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
     return acc;
 }
 
+// Leaf of the uniform point k: floor(k 2^l / N), from a binary64 estimate
+// (off by at most one) corrected with exact integer box starts.
+__device__ __forceinline__ int64_t uni_leaf(int64_t k, int l, int64_t N, double scale)
+{
+    int64_t b = (int64_t)((double)k * scale);
+    if (uni_start(b + 1, l, N) <= k)
+        ++b;
+    else if (uni_start(b, l, N) > k)
+        --b;
+    return b;
+}
+
+// Sorted sources of a subtree staged in LDS: the leaves leaf0 - 1 ..
+// leaf0 + nb (unwrapped, so positions increase), as integer grid offsets
+// from a base point, fractions and (cot kernel) weights.  The sources of
+// staged leaf j occupy [off[j], off[j + 1]).
+template <typename R>
+struct NearStage {
+    int32_t *m;
+    double *th;
+    cx<R> *w;
+    int32_t *off;
+    int32_t self0; // staged index of sorted point t is t + self0 (own leaves)
+};
+
+// Distance tau - sigma in grid units for an integer offset dm and fractions
+// a, b in [-1/2, 1/2]: a - b and the sum each round once, so the relative
+// error is at most 2^-53 (1 + 1/|d|).
+__device__ __forceinline__ double near_dist(int32_t dm, double a, double b)
+{
+    return (double)dm + (a - b);
+}
+
+// Cot near field from staged sources [j0, j1): sum w / (tau - sigma).
+template <typename R>
+__device__ __forceinline__ cx<R> near_cot_staged(const NearStage<R> &ns, int32_t j0,
+                                                 int32_t j1, int32_t tmr, double tth)
+{
+    cx<R> a0 = {R(0), R(0)}, a1 = a0, a2 = a0, a3 = a0;
+    int32_t j = j0;
+    for (; j + 4 <= j1; j += 4) {
+        const R r0 = recip((R)near_dist(tmr - ns.m[j], tth, ns.th[j]));
+        const R r1 = recip((R)near_dist(tmr - ns.m[j + 1], tth, ns.th[j + 1]));
+        const R r2 = recip((R)near_dist(tmr - ns.m[j + 2], tth, ns.th[j + 2]));
+        const R r3 = recip((R)near_dist(tmr - ns.m[j + 3], tth, ns.th[j + 3]));
+        const cx<R> w0 = ns.w[j], w1 = ns.w[j + 1], w2 = ns.w[j + 2], w3 = ns.w[j + 3];
+        a0.re = fma(w0.re, r0, a0.re);
+        a0.im = fma(w0.im, r0, a0.im);
+        a1.re = fma(w1.re, r1, a1.re);
+        a1.im = fma(w1.im, r1, a1.im);
+        a2.re = fma(w2.re, r2, a2.re);
+        a2.im = fma(w2.im, r2, a2.im);
+        a3.re = fma(w3.re, r3, a3.re);
+        a3.im = fma(w3.im, r3, a3.im);
+    }
+    for (; j < j1; ++j) {
+        const R r = recip((R)near_dist(tmr - ns.m[j], tth, ns.th[j]));
+        const cx<R> w = ns.w[j];
+        a0.re = fma(w.re, r, a0.re);
+        a0.im = fma(w.im, r, a0.im);
+    }
+    return {(a0.re + a1.re) + (a2.re + a3.re), (a0.im + a1.im) + (a2.im + a3.im)};
+}
+
+// Log near field from staged sources [j0, j1) without the source `self`:
+// log prod |tau - sigma|, the product kept as mantissa x 2^exponent (every
+// factor is below 2^31 in grid units, so eight of them stay in range).
+template <typename R>
+__device__ __forceinline__ double near_log_staged(const NearStage<R> &ns, int32_t j0,
+                                                  int32_t j1, int32_t self, int32_t tmr,
+                                                  double tth)
+{
+    double prod = 1.0;
+    int expo = 0;
+    int32_t j = j0;
+    for (; j + 8 <= j1; j += 8) {
+        double d[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double dd = fabs(near_dist(tmr - ns.m[j + u], tth, ns.th[j + u]));
+            d[u] = (j + u == self) ? 1.0 : dd;
+        }
+        const double q = ((d[0] * d[1]) * (d[2] * d[3])) * ((d[4] * d[5]) * (d[6] * d[7]));
+        int e;
+        prod = frexp(prod * q, &e);
+        expo += e;
+    }
+    double q = 1.0;
+    for (; j < j1; ++j) {
+        const double dd = fabs(near_dist(tmr - ns.m[j], tth, ns.th[j]));
+        q *= (j == self) ? 1.0 : dd;
+    }
+    return log(prod * q) + (double)expo * 0.69314718055994530942;
+}
+
+// Integral of log|tau - sigma| over sigma in the leaves leaf - 1 .. leaf + 1
+// (unwrapped), tau = tm + tth: the uniform background the log FMM removed.
+__device__ __forceinline__ double near_log_background(int64_t tm, double tth, int64_t leaf,
+                                                      int l, int64_t N)
+{
+    const double sc = ldexp(1.0, -l);
+    double lo = (double)((leaf - 1) * N - (tm << l)) * sc - tth;
+    double hi = (double)((leaf + 2) * N - (tm << l)) * sc - tth;
+    return xlogx_m_x(hi) - xlogx_m_x(lo);
+}
+
 // Near field of the log kernel with the uniform background removed:
 // sum log|tau - sigma~| over the sources of leaves b-1..b+1 (skipping the
 // source `self`), minus the integral of log|tau - sigma| over those leaves.
@@ -759,11 +866,7 @@ __device__ __forceinline__ double near_log(const DownArgs<R, V> &a, int64_t tm,
         }
     }
     const double acc = log(prod) + (double)expo * 0.69314718055994530942;
-    // integral over [(leaf-1) N/2^l, (leaf+2) N/2^l) (unwrapped)
-    const double sc = ldexp(1.0, -l);
-    double lo = (double)((leaf - 1) * N - (tm << l)) * sc - tth;
-    double hi = (double)((leaf + 2) * N - (tm << l)) * sc - tth;
-    return acc - (xlogx_m_x(hi) - xlogx_m_x(lo));
+    return acc - near_log_background(tm, tth, leaf, l, N);
 }
 
 template <typename R, typename V, int KER, int SRC, int EPI, int PD>
@@ -845,7 +948,9 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
         st_coef<R, V>(bufB, RS, li, n, vscale(acc, ipow(rho2, n)));
     }
     __syncthreads();
-    R *cur = bufA, *nxt = bufB;
+    // the leaf locals end in bufA after the s levels below, which leaves
+    // bufB and the source buffer free (contiguous) for the near field
+    R *cur = (s & 1) ? bufB : bufA, *nxt = (s & 1) ? bufA : bufB;
     for (int n = tid; n < PD; n += BLOCK) {
         V acc = ld_coef<R, V>(bufB, RS, 0, n);
         for (int li = 1; li <= nA; ++li)
@@ -885,6 +990,60 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
     }
     const R *leafloc = cur;
     const int64_t leaf0 = R0 << s;
+    const double invN = 1.0 / (double)N;
+    const double lscale = ldexp(1.0, a.l) * invN;
+
+    // sorted near-field sources of the subtree and its two neighbour leaves,
+    // staged in the LDS left free by the translations when they fit
+    NearStage<R> ns{};
+    bool staged = false;
+    int64_t base = 0;
+    if constexpr (SRC == SET_SORTED) {
+        const int nb = 1 << s;
+        const int64_t nleaf = int64_t(1) << a.l;
+        const int64_t bl = leaf0 == 0 ? nleaf - 1 : leaf0 - 1;
+        const int64_t br = leaf0 + nb == nleaf ? 0 : leaf0 + nb;
+        const int32_t oL = a.src.off[bl], cL = a.src.off[bl + 1] - oL;
+        const int32_t oM = a.src.off[leaf0], cM = a.src.off[leaf0 + nb] - oM;
+        const int32_t oR = a.src.off[br], cR = a.src.off[br + 1] - oR;
+        const int32_t total = cL + cM + cR;
+        constexpr int wb = EPI == EPI_INV ? (int)sizeof(cx<R>) : 0;
+        const int32_t cap = ((a.near_bytes - 4 * (nb + 4)) / (12 + wb)) & ~1;
+        base = uni_start(leaf0, a.l, N);
+        if (total <= cap) {
+            unsigned char *fr = reinterpret_cast<unsigned char *>(bufB);
+            ns.th = reinterpret_cast<double *>(fr);
+            ns.w = reinterpret_cast<cx<R> *>(fr + 8 * (size_t)cap);
+            ns.m = reinterpret_cast<int32_t *>(fr + (8 + wb) * (size_t)cap);
+            ns.off = ns.m + cap;
+            ns.self0 = cL - oM;
+            const int64_t shL = leaf0 == 0 ? -N : 0, shR = leaf0 + nb == nleaf ? N : 0;
+            for (int32_t i = tid; i < total; i += BLOCK) {
+                int32_t t;
+                int64_t sh;
+                if (i < cL) {
+                    t = oL + i;
+                    sh = shL;
+                } else if (i < cL + cM) {
+                    t = oM + (i - cL);
+                    sh = 0;
+                } else {
+                    t = oR + (i - cL - cM);
+                    sh = shR;
+                }
+                ns.m[i] = (int32_t)(a.src.m[t] + sh - base);
+                ns.th[i] = a.src.th[t];
+                if constexpr (EPI == EPI_INV)
+                    ns.w[i] = a.w_sorted[t];
+            }
+            for (int i = tid; i <= nb + 2; i += BLOCK)
+                ns.off[i] = i == 0 ? 0
+                                   : (i == nb + 2 ? total
+                                                  : cL + (a.src.off[leaf0 + i - 1] - oM));
+            staged = true;
+        }
+        __syncthreads();
+    }
 
     if constexpr (EPI == EPI_FWD) {
         // stage the near-field sources of the subtree (uniform sources),
@@ -892,10 +1051,10 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
         const cx<R> *fsp = nullptr;
         int64_t K0 = 0;
         if constexpr (SRC == SET_UNIFORM) {
-            cx<R> *fs = reinterpret_cast<cx<R> *>(srcs);
+            cx<R> *fs = reinterpret_cast<cx<R> *>(bufB);
             K0 = uni_start_unwrapped(leaf0 - 1, a.l, N);
             const int64_t K1 = uni_start_unwrapped(leaf0 + (1 << s) + 1, a.l, N);
-            if (K1 - K0 <= a.near_cap) {
+            if (K1 - K0 <= a.near_bytes / (int)sizeof(cx<R>)) {
                 for (int64_t i = tid; i < K1 - K0; i += BLOCK) {
                     int64_t k = K0 + i;
                     k = k < 0 ? k + N : (k >= N ? k - N : k);
@@ -907,7 +1066,6 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
         }
         const V S = *a.S;
         const double hscale = (double)N / 3.14159265358979323846;
-        const double invN = 1.0 / (double)N;
         for (int32_t t = w.t0 + tid; t < w.t1; t += BLOCK) {
             const int64_t tm = a.tgt.m[t];
             const double th = a.tgt.th[t];
@@ -917,7 +1075,7 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
                 continue;
             }
             const int64_t leaf = a.tgt_leaf[t];
-            const R u = (R)rel_coord(tm, th, leaf, a.l, N);
+            const R u = (R)rel_coord_r(tm, th, leaf, a.l, N, invN);
             V h = horner<R, V>(leafloc, RS, (int)(leaf - leaf0), PD, u);
             cx<R> nr = near_cot<R, V, SRC>(a, tm, th, leaf, fsp, K0);
             double hr = (double)h.re + hscale * (double)nr.re;
@@ -938,10 +1096,13 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
                 a.out[k] = a.gin[hj];
                 continue;
             }
-            const int64_t leaf = box_of(k, 0.0, a.l, N);
-            const R u = (R)rel_coord(k, 0.0, leaf, a.l, N);
-            V h = horner<R, V>(leafloc, RS, (int)(leaf - leaf0), PD, u);
-            cx<R> nr = near_cot<R, V, SRC>(a, k, 0.0, leaf, nullptr, 0);
+            const int64_t leaf = uni_leaf(k, a.l, N, lscale);
+            const int il = (int)(leaf - leaf0);
+            const R u = (R)rel_coord_r(k, 0.0, leaf, a.l, N, invN);
+            V h = horner<R, V>(leafloc, RS, il, PD, u);
+            cx<R> nr = staged ? near_cot_staged<R>(ns, ns.off[il], ns.off[il + 3],
+                                                   (int32_t)(k - base), 0.0)
+                              : near_cot<R, V, SRC>(a, k, 0.0, leaf, nullptr, 0);
             double hr = (double)h.re + hscale * (double)nr.re;
             double hi = (double)h.im + hscale * (double)nr.im;
             // f = -(C/2)(W + i h)
@@ -951,20 +1112,32 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
         }
     } else { // EPI_LOGCD
         for (int32_t k = w.u0 + tid; k < w.u1; k += BLOCK) {
-            const int64_t leaf = box_of(k, 0.0, a.l, N);
-            const R u = (R)rel_coord(k, 0.0, leaf, a.l, N);
-            V far = horner<R, V>(leafloc, RS, (int)(leaf - leaf0), PD, u);
-            a.logc[k] = (double)far + near_log<R, V>(a, k, 0.0, leaf, -1);
+            const int64_t leaf = uni_leaf(k, a.l, N, lscale);
+            const int il = (int)(leaf - leaf0);
+            const R u = (R)rel_coord_r(k, 0.0, leaf, a.l, N, invN);
+            V far = horner<R, V>(leafloc, RS, il, PD, u);
+            const double nr =
+                staged ? near_log_staged<R>(ns, ns.off[il], ns.off[il + 3], -1,
+                                            (int32_t)(k - base), 0.0) -
+                             near_log_background(k, 0.0, leaf, a.l, N)
+                       : near_log<R, V>(a, k, 0.0, leaf, -1);
+            a.logc[k] = (double)far + nr;
         }
         for (int32_t t = w.t0 + tid; t < w.t1; t += BLOCK) {
             const int64_t tm = a.tgt.m[t];
             const double th = a.tgt.th[t];
-            const int64_t leaf = box_of(tm, th, a.l, N);
-            const R u = (R)rel_coord(tm, th, leaf, a.l, N);
-            V far = horner<R, V>(leafloc, RS, (int)(leaf - leaf0), PD, u);
+            const int64_t leaf = a.tgt_leaf ? (int64_t)a.tgt_leaf[t] : box_of(tm, th, a.l, N);
+            const int il = (int)(leaf - leaf0);
+            const R u = (R)rel_coord_r(tm, th, leaf, a.l, N, invN);
+            V far = horner<R, V>(leafloc, RS, il, PD, u);
+            const double nr =
+                staged ? near_log_staged<R>(ns, ns.off[il], ns.off[il + 3], t + ns.self0,
+                                            (int32_t)(tm - base), th) -
+                             near_log_background(tm, th, leaf, a.l, N)
+                       : near_log<R, V>(a, tm, th, leaf, t);
             // the net count of Omega_1 carried log(2 pi / N) for the point
             // itself, whose log|t| term the near field skips
-            a.logd[t] = -((double)far + near_log<R, V>(a, tm, th, leaf, t) - a.logself);
+            a.logd[t] = -((double)far + nr - a.logself);
         }
     }
 }
