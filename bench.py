@@ -3,8 +3,8 @@
 
 One step = one forward transform (problem i, N = M = 2^20, y iid uniform on
 [0, 2 pi)) plus one inverse transform (problem ii, N = M = 2^20, jittered
-grid y_j = 2 pi (j + u_j)/N, u_j ~ U(-0.4, 0.4)), each one-shot: setup of
-the data structure (Section 3.3) and evaluation.  Inputs are resident in HBM
+grid y_j = 2 pi (j + u_j)/N, u_j ~ U(-0.4, 0.4)), each one-shot (nufft_fwd,
+inufft): setup of the data structure (Section 3.3) and evaluation.  Inputs are resident in HBM
 before the timed region.  value = (N + M) / step time, i.e. points per
 second for the forward + inverse pair.  The plain FP64 path (eps 1e-12) is
 the headline; the mixed path (eps 1e-6) is timed on the same inputs.
@@ -58,18 +58,35 @@ def down_eval_flops(info, n_targets, n_sources):
 
 
 def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
-    """Times `steps` one-shot fwd + inv pairs; per-kernel events for phase 1."""
+    """Times `steps` one-shot fwd + inv pairs (nufft_fwd + inufft, one
+    synchronisation each), then the same transforms through plans with
+    events around the two kernels of each execute, and execute-only."""
     dt = f.dtype
     g = torch.empty(M, dtype=dt, device="cuda")
     fo = torch.empty(N, dtype=dt, device="cuda")
     dtc = fn.FN_C128 if dt == torch.complex128 else fn.FN_C64
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-    k_f, k_i, up_f, up_i = [], [], [], []
-    info_f = info_i = None
 
-    def one_step(record):
-        nonlocal info_f, info_i
+    def one_step():
+        fn.nufft_fwd(yu, f, eps, out=g)
+        fn.inufft(yj, gj, eps, out=fo)
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    # phases: events on the library's stream (torch's current stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    k_f, k_i, up_f, up_i, plan_f, plan_i = [], [], [], [], [], []
+    info_f = info_i = None
+    for it in range(warmup + steps):
+        t = time.perf_counter()
         pf = fn.Plan.forward(N, yu, eps, dtc)
+        tpf = time.perf_counter() - t
         ev[0].record()
         pf.execute_phase(f, g, 0)
         ev[1].record()
@@ -77,7 +94,9 @@ def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
         ev[2].record()
         info_f = pf.info()
         pf.destroy()
+        t = time.perf_counter()
         pi = fn.Plan.inverse(yj, eps, dtc)
+        tpi = time.perf_counter() - t
         ev[3].record()
         pi.execute_phase(gj, fo, 0)
         ev[4].record()
@@ -85,20 +104,13 @@ def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
         ev[5].record()
         info_i = pi.info()
         pi.destroy()
-        if record:
+        if it >= warmup:
             up_f.append(ev[0].elapsed_time(ev[1]))
             k_f.append(ev[1].elapsed_time(ev[2]))
             up_i.append(ev[3].elapsed_time(ev[4]))
             k_i.append(ev[4].elapsed_time(ev[5]))
-
-    for _ in range(warmup):
-        one_step(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        one_step(True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+            plan_f.append(tpf * 1e3)
+            plan_i.append(tpi * 1e3)
 
     # evaluation only (plan reused, Section 3.3), outside the headline
     pf = fn.Plan.forward(N, yu, eps, dtc)
@@ -115,9 +127,13 @@ def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
     exec_wall = time.perf_counter() - t1
     pf.destroy()
     pi.destroy()
+    # outputs of the timed one-shot transforms
+    one_step()
+    torch.cuda.synchronize()
     return {
         "wall_s": wall, "ms_per_step": 1e3 * wall / steps,
         "exec_ms_per_step": 1e3 * exec_wall / steps,
+        "fwd_plan_ms": float(np.median(plan_f)), "inv_plan_ms": float(np.median(plan_i)),
         "fwd_up_ms": float(np.mean(up_f)), "fwd_down_ms": float(np.mean(k_f)),
         "inv_up_ms": float(np.mean(up_i)), "inv_down_ms": float(np.mean(k_i)),
         "info_f": info_f, "info_i": info_i, "g": g, "fo": fo,
@@ -164,9 +180,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md, 'How the path would shard'); run with --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -229,7 +244,8 @@ def main():
                    "inv": {"p": info_i.p, "q": info_i.q, "lmax": info_i.lmax,
                            "nterms": info_i.nterms}},
         "phases_ms": {k: round(res[k], 4) for k in
-                      ("fwd_up_ms", "fwd_down_ms", "inv_up_ms", "inv_down_ms")},
+                      ("fwd_plan_ms", "fwd_up_ms", "fwd_down_ms", "inv_plan_ms",
+                       "inv_up_ms", "inv_down_ms")},
         "exec_only": {"ms_per_step": res["exec_ms_per_step"],
                       "value": (N + M) / (res["exec_ms_per_step"] * 1e-3)},
         "accuracy": acc,
@@ -246,7 +262,8 @@ def main():
                  "speedup_vs_f64": res["ms_per_step"] / rm["ms_per_step"],
                  "exec_only_ms_per_step": rm["exec_ms_per_step"],
                  "phases_ms": {k: round(rm[k], 4) for k in
-                               ("fwd_up_ms", "fwd_down_ms", "inv_up_ms", "inv_down_ms")},
+                               ("fwd_plan_ms", "fwd_up_ms", "fwd_down_ms", "inv_plan_ms",
+                                "inv_up_ms", "inv_down_ms")},
                  "inv_roundtrip_rel_l2": float(np.linalg.norm(fo_m - f_h) / np.linalg.norm(f_h))}
         if not args.no_cpu_baseline:
             import oracle

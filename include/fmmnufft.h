@@ -54,8 +54,9 @@ typedef enum {
     FN_ENOMEM = 2,    /* device workspace allocation failed                */
     FN_EHIP = 3,      /* a HIP runtime call failed (message has details)   */
     FN_ESINGULAR = 4, /* inverse: two y_j coincide on the circle            */
-    FN_ERANGE = 5,    /* inverse: |C_k| or |D_j| leaves the binary64 range
-                         (the point set is too ill-conditioned)            */
+    FN_ERANGE = 5,    /* inverse: |C_k| or |D_j| leaves the binary64 range,
+                         or a leaf holds over 16 times the mean number of
+                         points (the point set is too ill-conditioned)     */
     FN_EPREC = 6      /* eps below what the precision path can deliver     */
 } fn_status;
 
@@ -88,14 +89,16 @@ typedef struct {
 
 /* Forward interpolation (problem i): g_j = sum_k K_jk f_k, Eq. (p2).
  * y: M doubles; f: N complex; g: M complex (written).  N >= 1, M >= 1,
- * N, M < 2^31.  One-shot: plan + execute + destroy; synchronises the stream
- * once (to size the tree). */
+ * N, M < 2^31.  One-shot: setup and evaluation are enqueued back to back
+ * and the call synchronises the stream once, at the end, where it also
+ * reports the data-dependent errors of the setup (on such an error g holds
+ * no result). */
 int nufft_fwd(int64_t N, int64_t M, const double *y, const void *f, void *g,
               double eps, int dtype, void *stream);
 
 /* Inverse interpolation (problem ii, M = N): f = L g, Eq. (p6)/(p8).
  * y: N doubles, pairwise distinct modulo 2 pi; g: N complex; f: N complex
- * (written).  One-shot; synchronises the stream. */
+ * (written).  One-shot like nufft_fwd: one synchronisation, at the end. */
 int inufft(int64_t N, const double *y, const void *g, void *f, double eps,
            int dtype, void *stream);
 

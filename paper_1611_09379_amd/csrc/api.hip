@@ -486,6 +486,7 @@ static void fill_down(const fn_plan *P, const FmmSetup &F, const OpTables<R> &T,
     da.loc2 = (const V *)F.loc2.p;
     da.S = (const V *)F.S.p;
     da.T = T;
+    da.flags = (const int *)P->flags.p;
 }
 
 // Launches with the expansion lengths as template arguments.
@@ -550,6 +551,15 @@ static int grid_for(int64_t n, int block = 256)
 {
     int64_t g = (n + block - 1) / block;
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+
+// Largest leaf the inverse accepts: 16 times the mean occupancy (at least
+// 512).  A jittered grid stays near the mean; denser leaves mean a point set
+// far too clustered for the inverse.
+static int32_t dense_max(int64_t N, int l)
+{
+    const int64_t mean = (N + (int64_t(1) << l) - 1) >> l;
+    return (int32_t)std::min<int64_t>(INT32_MAX, std::max<int64_t>(512, 16 * mean));
 }
 
 static constexpr int SORT_LDS_BINS = 32768; // LDS histogram limit (128 KB)
@@ -645,8 +655,9 @@ static int build_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
         hipLaunchKernelGGL(k_rank, dim3(grid_for(n)), dim3(256), 0, st, n,
                            (const int32_t *)gm, (const double *)gth,
                            (const int32_t *)gperm, (const int32_t *)gkey,
-                           (const int32_t *)P->off.p, (int32_t *)P->sm.p,
-                           (double *)P->sth.p, (int32_t *)P->sperm.p, flags);
+                           (const int32_t *)P->off.p, dense_max(P->N, P->l),
+                           (int32_t *)P->sm.p, (double *)P->sth.p, (int32_t *)P->sperm.p,
+                           flags);
         HIPCHK(hipGetLastError());
     }
     return FN_OK;
@@ -687,6 +698,9 @@ static int finish_plan(fn_plan *P, hipStream_t st)
         return fail(FN_EINVAL, "y holds a non-finite value or |y| > %g", FN_Y_MAX);
     if (hflags & FLAG_DUP)
         return fail(FN_ESINGULAR, "two points y_j coincide on the circle");
+    if (hflags & FLAG_DENSE)
+        return fail(FN_ERANGE, "a leaf holds more than %d points: the point set is "
+                               "too clustered for the inverse", dense_max(P->N, P->l));
     if (hflags & FLAG_RANGE)
         return fail(FN_ERANGE, "|C_k| or |D_j| leaves the binary64 range: the "
                                "point set is too ill-conditioned for the inverse");
@@ -738,7 +752,7 @@ static int plan_fwd_impl(fn_plan *P, const double *y, hipStream_t st)
     rc = get_tables<R>(KER_COT, PU, PD, P->q, &T);
     if (rc)
         return rc;
-    return finish_plan(P, st);
+    return FN_OK;
 }
 
 template <typename R>
@@ -861,7 +875,7 @@ static int plan_inv_impl(fn_plan *P, const double *y, hipStream_t st)
     rc = get_tables<R>(KER_COT, PU, PD, P->q, &T);
     if (rc)
         return rc;
-    return finish_plan(P, st);
+    return FN_OK;
 }
 
 template <typename R>
@@ -931,9 +945,12 @@ static void choose(int64_t N, int64_t M, double eps, int dtype, int32_t p_in,
     *q = q_in > 0 ? q_in : qq;
 }
 
+// Creates a plan.  Unless `defer`, waits for the setup kernels and reports
+// their errors; a deferred plan is checked by finish_plan after its first
+// execute (the one-shot calls), which then costs a single synchronisation.
 static int plan_common(fn_plan **out, int kind, int64_t N, int64_t M,
                        const double *y, double eps, int dtype, int32_t p_in,
-                       int32_t q_in, int32_t l_in, void *stream)
+                       int32_t q_in, int32_t l_in, void *stream, bool defer = false)
 {
     if (!out)
         return fail(FN_EINVAL, "plan pointer is NULL");
@@ -975,6 +992,8 @@ static int plan_common(fn_plan **out, int kind, int64_t N, int64_t M,
     else
         rc = dtype == FN_C128 ? plan_inv_impl<double>(P, y, st)
                               : plan_inv_impl<float>(P, y, st);
+    if (!rc && !defer)
+        rc = finish_plan(P, st);
     if (rc) {
         (void)hipStreamSynchronize(st);
         release_plan(P);
@@ -983,6 +1002,17 @@ static int plan_common(fn_plan **out, int kind, int64_t N, int64_t M,
     }
     *out = P;
     return FN_OK;
+}
+
+// End of a one-shot call: one synchronisation for the setup's error flags
+// and the evaluation, then the plan goes.  A setup error takes precedence
+// (the evaluation then ran on a rejected point set and its output is void).
+static int finish_one_shot(fn_plan *P, int rc_exec)
+{
+    int rc = finish_plan(P, P->stream);
+    release_plan(P);
+    delete P;
+    return rc ? rc : rc_exec;
 }
 
 extern "C" {
@@ -1094,12 +1124,10 @@ int nufft_fwd(int64_t N, int64_t M, const double *y, const void *f, void *g,
     if (!f || !g)
         return fail(FN_EINVAL, "f or g is NULL");
     fn_plan *P = nullptr;
-    int rc = nufft_plan_fwd(&P, N, M, y, eps, dtype, stream);
+    int rc = plan_common(&P, 0, N, M, y, eps, dtype, 0, 0, 0, stream, true);
     if (rc)
         return rc;
-    rc = nufft_execute(P, f, g, stream);
-    int rc2 = nufft_destroy(P);
-    return rc ? rc : rc2;
+    return finish_one_shot(P, nufft_execute(P, f, g, stream));
 }
 
 int inufft(int64_t N, const double *y, const void *g, void *f, double eps,
@@ -1108,12 +1136,10 @@ int inufft(int64_t N, const double *y, const void *g, void *f, double eps,
     if (!f || !g)
         return fail(FN_EINVAL, "f or g is NULL");
     fn_plan *P = nullptr;
-    int rc = nufft_plan_inv(&P, N, y, eps, dtype, stream);
+    int rc = plan_common(&P, 1, N, N, y, eps, dtype, 0, 0, 0, stream, true);
     if (rc)
         return rc;
-    rc = nufft_execute(P, g, f, stream);
-    int rc2 = nufft_destroy(P);
-    return rc ? rc : rc2;
+    return finish_one_shot(P, nufft_execute(P, g, f, stream));
 }
 
 const char *nufft_last_error(void) { return g_err.c_str(); }

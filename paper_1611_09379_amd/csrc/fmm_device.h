@@ -13,6 +13,14 @@
 
 namespace fn {
 
+// Error flags the setup kernels raise (one int in device memory).
+enum {
+    FLAG_BAD_Y = 1, // non-finite or too large y
+    FLAG_DUP = 2,   // two points coincide (inverse)
+    FLAG_RANGE = 4, // |C_k| or |D_j| outside the binary64 range (inverse)
+    FLAG_DENSE = 8  // a leaf far denser than the average (inverse)
+};
+
 template <typename R>
 struct cx {
     R re, im;

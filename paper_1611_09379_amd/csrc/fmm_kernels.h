@@ -509,6 +509,9 @@ struct DownArgs {
     const cx<R> *gin;        // INV: g (input order)
     double *logc, *logd;     // LOGCD outputs
     double logself;          // LOGCD: log(2 pi / N), the excluded self term
+    const int *flags;        // setup error flags: sorted-source passes stop
+                             // at FLAG_DENSE (their near field would be
+                             // quadratic in the leaf size)
 };
 
 // Register-held operator tiles of one wave (row tile rt of PD rows).
@@ -881,6 +884,9 @@ __global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if ((int32_t)blockIdx.x >= *a.nwork)
         return; // the grid is sized for the largest possible work list
+    if constexpr (SRC == SET_SORTED)
+        if (*a.flags & FLAG_DENSE)
+            return; // the plan fails; nothing is evaluated
     const WorkItem w = a.work[blockIdx.x];
     const int64_t R0 = w.root;
     const int lr = a.lr;

@@ -8,8 +8,6 @@
 
 namespace fn {
 
-enum { FLAG_BAD_Y = 1, FLAG_DUP = 2, FLAG_RANGE = 4 };
-
 // s = y (c_hi + c_lo) in double-double, split into the nearest integer n
 // and the remainder th.  Contraction stays off: fusing p - n with
 // p = y c_hi into one fma would count the rounding error of y c_hi twice.
@@ -270,18 +268,29 @@ __global__ void k_scatter(int64_t M, const int32_t *um, const double *uth,
 
 // Orders the points of every leaf by position (so the whole set is sorted
 // along the circle); two points at the same position raise FLAG_DUP.
+// A leaf holding more than dense_max points raises FLAG_DENSE and keeps
+// its order (still a permutation): the point set is far too clustered for
+// the inverse, and ranking it would cost the square of the leaf's size.
 __global__ void k_rank(int64_t n, const int32_t *gm, const double *gth,
                        const int32_t *gperm, const int32_t *gkey,
-                       const int32_t *off, int32_t *sm, double *sth,
+                       const int32_t *off, int32_t dense_max, int32_t *sm, double *sth,
                        int32_t *sperm, int *flags)
 {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int32_t b = gkey[t];
-        const int32_t t0 = off[b], t1 = off[b + 1];
+        const int32_t t0 = off[b];
+        int32_t t1 = off[b + 1];
         const int32_t mt = gm[t];
         const double tht = gth[t];
-        int32_t rank = 0;
+        int32_t rank = (int32_t)t - t0;
+        if (t1 - t0 > dense_max) {
+            if (t == t0)
+                atomicOr(flags, FLAG_DENSE);
+            t1 = t0; // no ranking
+        } else {
+            rank = 0;
+        }
         for (int32_t u = t0; u < t1; ++u) {
             if (u == t)
                 continue;

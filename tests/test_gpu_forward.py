@@ -141,6 +141,18 @@ def test_errors():
     with pytest.raises(fn.NufftError) as e:
         fn.nufft_fwd(y, f, 1e-12)
     assert e.value.status == fn.FN_EINVAL
+    # the plan API reports it at plan creation, too; |y| beyond the limit
+    # is rejected like a non-finite value
+    with pytest.raises(fn.NufftError) as e:
+        fn.Plan.forward(8, y, 1e-12)
+    assert e.value.status == fn.FN_EINVAL
+    with pytest.raises(fn.NufftError) as e:
+        fn.nufft_fwd(dev(np.array([0.1, 2000.0])), f, 1e-12)
+    assert e.value.status == fn.FN_EINVAL
+    # the library stays usable after a rejected call
+    yok = np.array([0.1, 0.2, 0.3])
+    g = host(fn.nufft_fwd(dev(yok), f, 1e-12))
+    assert rel_l2(g, oracle.fwd(8, yok, np.ones(8, complex))) < 1e-12
     y = dev(np.array([0.1, 0.2]))
     with pytest.raises(fn.NufftError) as e:
         fn.nufft_fwd(y, f, 1e-20)

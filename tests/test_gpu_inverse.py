@@ -96,3 +96,29 @@ def test_inv_mixed():
     err = rel_l2(f, ref)
     say("mixed inv rel l2", err)
     assert err < 1e-6
+
+
+def test_inv_clustered_rejected():
+    """A clustered point set makes the inverse ill-posed (Eq. p8: the
+    products of sines leave any floating-point range): FN_ERANGE, from the
+    one-shot call and from the plan, without running the near field of the
+    dense leaves."""
+    N = 8192
+    rng = np.random.default_rng(9)
+    g = dev((rng.standard_normal(N) + 1j * rng.standard_normal(N)))
+    # every point in one leaf: far above the dense-leaf limit
+    y_one = np.pi + 1e-3 * np.sort(rng.random(N))
+    # a mixture of 8 narrow Gaussians: |D_j| overflows
+    y_mix = workloads.points_clustered(N, rng)
+    for y in (y_one, y_mix):
+        say("clustered inverse", y.min(), y.max())
+        with pytest.raises(fn.NufftError) as e:
+            fn.inufft(dev(y), g, 1e-12)
+        assert e.value.status == fn.FN_ERANGE
+        with pytest.raises(fn.NufftError) as e:
+            fn.Plan.inverse(dev(y), 1e-12)
+        assert e.value.status == fn.FN_ERANGE
+    # still usable afterwards
+    y, c = workloads.inverse_case(1024, 0.4, seed=3)
+    g1 = np.random.default_rng(4).standard_normal(1024) + 0j
+    assert rel_l2(run_inv(y, g1, 1e-12), oracle.inv(1024, y, g1)) < 1e-12
