@@ -610,9 +610,12 @@ static int build_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
     int32_t *hit = want_hit ? (int32_t *)P->hit.p : nullptr;
     int *flags = (int *)P->flags.p;
     if (lds_path) {
-        hipLaunchKernelGGL(k_reduce_hist, dim3(nblk), dim3(256), (size_t)nbins * 4, st,
-                           n, y, chi, clo, P->N, P->l, keyshift, (double)FN_Y_MAX,
-                           chunk, nbins, nblk, um, uth, ukey, H, hit, flags);
+        hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(256), 0, st, n, y, chi, clo,
+                           P->N, P->l, keyshift, (double)FN_Y_MAX, um, uth, ukey, hit,
+                           flags);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_hist, dim3(nblk), dim3(256), (size_t)nbins * 4, st, n, chunk,
+                           nbins, (const int32_t *)ukey, H);
         HIPCHK(hipGetLastError());
         hipLaunchKernelGGL(k_colscan, dim3(grid_for(nbins)), dim3(256), 0, st, nbins, nblk,
                            H, tot);
@@ -839,8 +842,8 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     rc = launch_down<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>(P, F, da, st);
     if (rc)
         return rc;
-    hipLaunchKernelGGL(k_coeffs, dim3(grid_for(P->N)), dim3(256), 0, st, P->N,
-                       (const double *)logc, (const double *)logd,
+    hipLaunchKernelGGL(k_coeffs, dim3(grid_for(P->N)), dim3(256), 0, st, P->N, P->l,
+                       (const int32_t *)P->off.p, (const double *)logc, (const double *)logd,
                        (const int32_t *)P->sm.p, (const double *)P->sth.p,
                        (const int32_t *)P->hit.p, (double *)P->chat.p,
                        (cx<double> *)P->dhat.p, (int *)P->flags.p);

@@ -55,15 +55,35 @@ __device__ __forceinline__ bool reduce_point(double yy, double c_hi, double c_lo
     return true;
 }
 
-// Counting sort, pass 1: grid units and sort key (the level-(l - keyshift)
-// box) of every point, and per-block histograms of the keys in LDS.  Block b
-// takes points [b chunk, (b+1) chunk); H is block-major, H[b nbins + key].
-// If hit is given, records the index of a point that lies exactly on x_m.
+// Grid units and sort key (the level-(l - keyshift) box) of every point,
+// one point per thread.  If hit is given, records the index of a point that
+// lies exactly on x_m.
 __global__ void __launch_bounds__(256)
-    k_reduce_hist(int64_t n, const double *__restrict__ y, double c_hi, double c_lo,
-                  int64_t N, int l, int keyshift, double ymax, int64_t chunk,
-                  int nbins, int nblk, int32_t *um, double *uth, int32_t *ukey,
-                  int32_t *H, int32_t *hit, int *flags)
+    k_keys(int64_t n, const double *__restrict__ y, double c_hi, double c_lo, int64_t N,
+           int l, int keyshift, double ymax, int32_t *__restrict__ um,
+           double *__restrict__ uth, int32_t *__restrict__ ukey, int32_t *hit, int *flags)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        int64_t m;
+        double th;
+        if (!reduce_point(y[j], c_hi, c_lo, N, ymax, &m, &th))
+            atomicOr(flags, FLAG_BAD_Y);
+        um[j] = (int32_t)m;
+        uth[j] = th;
+        ukey[j] = (int32_t)(box_of(m, th, l, N) >> keyshift);
+        if (hit && th == 0.0)
+            atomicExch(&hit[m], (int32_t)j);
+    }
+}
+
+constexpr int SORT_BATCH = 8; // points in flight per thread in the sort passes
+
+// Counting sort, pass 1: per-block histograms of the keys in LDS.  Block b
+// takes points [b chunk, (b+1) chunk); H is block-major, H[b nbins + key].
+__global__ void __launch_bounds__(256)
+    k_hist(int64_t n, int64_t chunk, int nbins, const int32_t *__restrict__ ukey,
+           int32_t *__restrict__ H)
 {
     extern __shared__ int32_t hist[];
     for (int i = threadIdx.x; i < nbins; i += 256)
@@ -71,18 +91,17 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
     const int64_t j0 = (int64_t)blockIdx.x * chunk;
     const int64_t j1 = j0 + chunk < n ? j0 + chunk : n;
-    for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
-        int64_t m;
-        double th;
-        if (!reduce_point(y[j], c_hi, c_lo, N, ymax, &m, &th))
-            atomicOr(flags, FLAG_BAD_Y);
-        const int32_t key = (int32_t)(box_of(m, th, l, N) >> keyshift);
-        um[j] = (int32_t)m;
-        uth[j] = th;
-        ukey[j] = key;
-        atomicAdd(&hist[key], 1);
-        if (hit && th == 0.0)
-            atomicExch(&hit[m], (int32_t)j);
+    for (int64_t jb = j0 + threadIdx.x; jb < j1; jb += 256 * SORT_BATCH) {
+        int32_t key[SORT_BATCH];
+#pragma unroll
+        for (int u = 0; u < SORT_BATCH; ++u) {
+            const int64_t j = jb + u * 256;
+            key[u] = j < j1 ? ukey[j] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < SORT_BATCH; ++u)
+            if (key[u] >= 0)
+                atomicAdd(&hist[key[u]], 1);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nbins; i += 256)
@@ -96,10 +115,17 @@ __global__ void k_colscan(int nbins, int nblk, int32_t *H, int32_t *tot)
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nbins;
          k += (int64_t)gridDim.x * blockDim.x) {
         int32_t run = 0;
-        for (int b = 0; b < nblk; ++b) {
-            const int32_t c = H[(int64_t)b * nbins + k];
-            H[(int64_t)b * nbins + k] = run;
-            run += c;
+        for (int b0 = 0; b0 < nblk; b0 += SORT_BATCH) {
+            int32_t c[SORT_BATCH];
+#pragma unroll
+            for (int u = 0; u < SORT_BATCH; ++u)
+                c[u] = b0 + u < nblk ? H[(int64_t)(b0 + u) * nbins + k] : 0;
+#pragma unroll
+            for (int u = 0; u < SORT_BATCH; ++u) {
+                if (b0 + u < nblk)
+                    H[(int64_t)(b0 + u) * nbins + k] = run;
+                run += c[u];
+            }
         }
         tot[k] = run;
     }
@@ -119,14 +145,32 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
     const int64_t j0 = (int64_t)blockIdx.x * chunk;
     const int64_t j1 = j0 + chunk < n ? j0 + chunk : n;
-    for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
-        const int32_t key = ukey[j];
-        const int32_t pos = atomicAdd(&cur[key], 1);
-        sm[pos] = um[j];
-        sth[pos] = uth[j];
-        sperm[pos] = (int32_t)j;
-        if (skey)
-            skey[pos] = key;
+    for (int64_t jb = j0 + threadIdx.x; jb < j1; jb += 256 * SORT_BATCH) {
+        int32_t key[SORT_BATCH], mm[SORT_BATCH], pos[SORT_BATCH];
+        double tt[SORT_BATCH];
+#pragma unroll
+        for (int u = 0; u < SORT_BATCH; ++u) {
+            const int64_t j = jb + u * 256;
+            key[u] = -1;
+            if (j < j1) {
+                key[u] = ukey[j];
+                mm[u] = um[j];
+                tt[u] = uth[j];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SORT_BATCH; ++u)
+            if (key[u] >= 0)
+                pos[u] = atomicAdd(&cur[key[u]], 1);
+#pragma unroll
+        for (int u = 0; u < SORT_BATCH; ++u)
+            if (key[u] >= 0) {
+                sm[pos[u]] = mm[u];
+                sth[pos[u]] = tt[u];
+                sperm[pos[u]] = (int32_t)(jb + u * 256);
+                if (skey)
+                    skey[pos[u]] = key[u];
+            }
     }
 }
 
@@ -291,18 +335,30 @@ __global__ void k_rank(int64_t n, const int32_t *gm, const double *gth,
         } else {
             rank = 0;
         }
-        for (int32_t u = t0; u < t1; ++u) {
-            if (u == t)
-                continue;
-            double d = grid_diff((int64_t)gm[u] - mt, gth[u], tht);
-            if (d < 0.0)
-                ++rank;
-            else if (d == 0.0) {
-                atomicOr(flags, FLAG_DUP);
-                if (u < t)
-                    ++rank;
+        bool dup = false;
+        for (int32_t u0 = t0; u0 < t1; u0 += SORT_BATCH) {
+            int32_t mu[SORT_BATCH];
+            double thu[SORT_BATCH];
+#pragma unroll
+            for (int v = 0; v < SORT_BATCH; ++v) {
+                const int32_t u = u0 + v < t1 ? u0 + v : t0;
+                mu[v] = gm[u];
+                thu[v] = gth[u];
+            }
+#pragma unroll
+            for (int v = 0; v < SORT_BATCH; ++v) {
+                const int32_t u = u0 + v;
+                if (u >= t1 || u == (int32_t)t)
+                    continue;
+                const double d = grid_diff((int64_t)mu[v] - mt, thu[v], tht);
+                // ties (duplicates) are ordered by index: the ranks stay a
+                // permutation of the leaf
+                rank += (d < 0.0 || (d == 0.0 && u < t)) ? 1 : 0;
+                dup |= d == 0.0;
             }
         }
+        if (dup)
+            atomicOr(flags, FLAG_DUP);
         const int32_t pos = t0 + rank;
         sm[pos] = mt;
         sth[pos] = tht;
@@ -362,15 +418,22 @@ __global__ void __launch_bounds__(1024)
 //   Dhat_j = i e^{-i N y_j / 2} / prod_{i != j} 2 sin((y_j - y_i)/2)
 //          = i (-1)^(m_j) e^{-i pi th_j} (-1)^(#{i: s_i > s_j}) exp(logD_j),
 // with the points sorted along the circle, so #{i: s_i > s_j} = N - 1 - rank.
-__global__ void k_coeffs(int64_t N, const double *logc, const double *logd,
-                         const int32_t *sm, const double *sth,
+__global__ void k_coeffs(int64_t N, int l, const int32_t *off, const double *logc,
+                         const double *logd, const int32_t *sm, const double *sth,
                          const int32_t *hit, double *chat, cx<double> *dhat,
                          int *flags)
 {
+    const double lscale = ldexp(1.0, l) / (double)N;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < N;
          k += (int64_t)gridDim.x * blockDim.x) {
-        // #{j : s_j <= k} by binary search over the sorted positions
-        int64_t lo = 0, hi = N;
+        // #{j : s_j <= k}: every point of the leaves before k's leaf, plus a
+        // binary search over the (sorted) points of k's leaf
+        int64_t b = (int64_t)((double)k * lscale);
+        if (uni_start(b + 1, l, N) <= k)
+            ++b;
+        else if (uni_start(b, l, N) > k)
+            --b;
+        int64_t lo = off[b], hi = off[b + 1];
         while (lo < hi) {
             int64_t mid = (lo + hi) >> 1;
             bool le = sm[mid] < k || (sm[mid] == k && sth[mid] <= 0.0);
