@@ -293,6 +293,7 @@ struct FmmSetup {
     size_t reg_smem = 0;
     size_t dn_smem = 0;
     int rows_buf = 0, rows_src = 0, near_bytes = 0;
+    int stage_cap = 0; // first upward band: sorted sources staged in LDS
 };
 
 struct fn_plan {
@@ -404,8 +405,17 @@ static int choose_lr(int l, int nc, int PD, int es)
     return l;
 }
 
+// Uniform sources: the number B of grid points in every leaf when all
+// leaves hold the same number and 4 <= B <= 64, B a multiple of 4 (the
+// matrix-core P2M, with the band's weights staged in LDS); else 0.
+static int uniform_leaf_pts(const fn_plan *P)
+{
+    const int64_t B = P->N >> P->l;
+    return ((B << P->l) == P->N && B >= 4 && B <= 64 && B % 4 == 0) ? (int)B : 0;
+}
+
 template <typename R, typename V>
-static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q,
+static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_src,
                      FmmSetup &F, hipStream_t st)
 {
     constexpr int NC = ncomp<V>::value;
@@ -429,6 +439,27 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q,
         lb -= d;
         first = false;
     } while (lb > 2);
+    // first band: LDS staging of its sources (uniform grid with an equal
+    // number B in every leaf: the weights; sorted sources: coordinates and
+    // weights of up to twice the mean count, else they are read in place)
+    {
+        const int nbot = 1 << F.band[0].d;
+        size_t bytes = 0;
+        if (!sorted_src) {
+            if (kernel == KER_COT && uniform_leaf_pts(P) > 0)
+                bytes = (size_t)nbot * uniform_leaf_pts(P) * 2 * es;
+        } else {
+            const int64_t mean = (P->N + (int64_t(1) << P->l) - 1) >> P->l;
+            const size_t per = es * (kernel == KER_COT ? 3 : 1);
+            const size_t room = lim > F.band[0].smem + 64 ? lim - F.band[0].smem - 64 : 0;
+            int64_t cap = std::min<int64_t>(2 * nbot * mean + 64, (int64_t)(room / per) - 4);
+            cap = std::min<int64_t>(cap, 4096) & ~int64_t(3);
+            F.stage_cap = cap >= 64 ? (int)cap : 0;
+            if (F.stage_cap)
+                bytes = (size_t)F.stage_cap * per;
+        }
+        F.band[0].smem += bytes;
+    }
     for (int b = 0; b < F.nbands; ++b)
         if (F.band[b].smem > lim)
             return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PU,
@@ -458,10 +489,9 @@ static void fill_up(const fn_plan *P, const FmmSetup &F, const OpTables<R> &T,
     ua.l = P->l;
     ua.RS = F.RSu;
     ua.PD = F.PD;
-    {
-        const int64_t B = P->N >> P->l;
-        ua.leaf_pts = ((B << P->l) == P->N && B >= 4 && B % 4 == 0) ? (int)B : 0;
-    }
+    ua.leaf_pts = uniform_leaf_pts(P);
+    ua.stage_cap = F.stage_cap;
+    ua.src_leaf = (const int32_t *)P->skey.p;
     ua.mp = (V *)F.mp.p;
     ua.loc2 = (V *)F.loc2.p;
     ua.S = (V *)F.S.p;
@@ -631,15 +661,21 @@ static int build_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
     int32_t *cursor = lds_path ? nullptr : (int32_t *)tmp_alloc(P, (size_t)nbins * 4);
     if (!lds_path && !cursor)
         return fail(FN_ENOMEM, "workspace allocation failed");
-    const int nt = (int)((nbins + SCAN_TILE - 1) / SCAN_TILE);
-    hipLaunchKernelGGL(k_scan_sums, dim3(nt), dim3(256), 0, st, (const int32_t *)tot,
-                       (int64_t)nbins, tsum);
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tsum, nt, off + nbins);
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(256), 0, st, (const int32_t *)tot,
-                       (int64_t)nbins, (const int32_t *)tsum, off, cursor);
-    HIPCHK(hipGetLastError());
+    if (nbins <= SCAN1_MAX) {
+        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, st, (const int32_t *)tot,
+                           nbins, off, cursor);
+        HIPCHK(hipGetLastError());
+    } else {
+        const int nt = (int)((nbins + SCAN_TILE - 1) / SCAN_TILE);
+        hipLaunchKernelGGL(k_scan_sums, dim3(nt), dim3(256), 0, st, (const int32_t *)tot,
+                           (int64_t)nbins, tsum);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tsum, nt, off + nbins);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(256), 0, st, (const int32_t *)tot,
+                           (int64_t)nbins, (const int32_t *)tsum, off, cursor);
+        HIPCHK(hipGetLastError());
+    }
     int32_t *dm = deterministic ? gm : (int32_t *)P->sm.p;
     double *dth = deterministic ? gth : (double *)P->sth.p;
     int32_t *dperm = deterministic ? gperm : (int32_t *)P->sperm.p;
@@ -748,7 +784,7 @@ static int plan_fwd_impl(fn_plan *P, const double *y, hipStream_t st)
     rc = build_work(P, P->l - P->lr, false, P->M, st);
     if (rc)
         return rc;
-    rc = setup_fmm<R, cx<R>>(P, KER_COT, PU, PD, P->q, P->cot, st);
+    rc = setup_fmm<R, cx<R>>(P, KER_COT, PU, PD, P->q, false, P->cot, st);
     if (rc)
         return rc;
     OpTables<R> T;
@@ -809,7 +845,7 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     if (rc)
         return rc;
     FmmSetup F;
-    rc = setup_fmm<R, V>(P, KER_LOG, PU, PD, qlog, F, st);
+    rc = setup_fmm<R, V>(P, KER_LOG, PU, PD, qlog, true, F, st);
     // the log FMM's workspace lives until the plan's synchronisation
     for (Buf *b : {&F.mp, &F.loc2, &F.S})
         if (b->p)
@@ -871,7 +907,7 @@ static int plan_inv_impl(fn_plan *P, const double *y, hipStream_t st)
     rc = plan_inv_logs(P, st);
     if (rc)
         return rc;
-    rc = setup_fmm<R, cx<R>>(P, KER_COT, PU, PD, P->q, P->cot, st);
+    rc = setup_fmm<R, cx<R>>(P, KER_COT, PU, PD, P->q, true, P->cot, st);
     if (rc)
         return rc;
     OpTables<R> T;

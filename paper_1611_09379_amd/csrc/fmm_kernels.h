@@ -182,6 +182,9 @@ struct UpArgs {
     int leaf_pts;   // uniform sources: points per leaf if every leaf holds
                     // the same number (N divisible by 2^l, a multiple of 4
                     // up to 64), else 0
+    int stage_cap;  // first band, sorted sources: sources of one launch's
+                    // leaves that fit in its LDS staging area
+    const int32_t *src_leaf; // sorted sources: leaf of every source
     // sources (first band)
     SortedSet src;
     const cx<R> *f_uniform;  // forward: f_k at the uniform points
@@ -263,13 +266,44 @@ __device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, int64_t b,
     }
 }
 
+// P2M from sources staged in LDS: relative coordinates sv and (cot kernel)
+// weights sw of the sources [j0, j1) of one leaf, moments m0 .. m0+CHS-1.
+template <typename R, typename V, int KER>
+__device__ __forceinline__ void p2m_staged(const R *sv, const cx<R> *sw, int j0, int j1,
+                                           int m0, double r, V *acc)
+{
+    for (int c = 0; c < CHS; ++c)
+        acc[c] = vzero<V>();
+    for (int j = j0; j < j1; ++j) {
+        const R v = sv[j];
+        R pw = ipow(v, m0);
+        V w;
+        if constexpr (KER == KER_COT)
+            w = sw[j];
+        else
+            w = R(1);
+        for (int c = 0; c < CHS; ++c) {
+            vfma(acc[c], pw, w);
+            pw *= v;
+        }
+    }
+    if constexpr (KER == KER_LOG) {
+        for (int c = 0; c < CHS; ++c) {
+            const int m = m0 + c;
+            if ((m & 1) == 0)
+                acc[c] -= (R)(2.0 * r / (double)(m + 1));
+        }
+    }
+}
+
 // P2M on the matrix cores for uniform sources with B points in every leaf:
 // a[m][(leaf, comp)] = sum_i v_i^m f[leaf B + i], v_i = (2i - B)/B, i.e. a
-// GEMM whose operator V^T (PU x B) is the same for every leaf.
+// GEMM whose operator V^T (PU x B) is the same for every leaf.  f holds the
+// launch's nbot B weights, staged in LDS.
 template <typename R, typename V, int PU>
 __device__ __forceinline__ void p2m_mfma(const UpArgs<R, V> &a, int64_t first,
                                          int nbot, R *buf, int RS, V *g,
-                                         int lane, int wave)
+                                         int lane, int wave, const R *f)
 {
     constexpr int NC = 2; // cot kernel: complex weights
     using A = typename acc_t<R>::type;
@@ -277,14 +311,13 @@ __device__ __forceinline__ void p2m_mfma(const UpArgs<R, V> &a, int64_t first,
     const int B = a.leaf_pts;
     const int nks = B / 4;
     const int ntile = nrt * ((NC * nbot + 15) / 16);
-    const R *f = reinterpret_cast<const R *>(a.f_uniform);
     for (int tile = wave; tile < ntile; tile += 4) {
         const int rt = tile % nrt, ct = tile / nrt;
         const int j = 16 * ct + (lane & 15);
         const int i = j / NC, c = j % NC;
         const bool valid = i < nbot;
         const int m = 16 * rt + (lane & 15); // A row of this lane
-        const R *fp = f + ((first + (valid ? i : 0)) * B) * NC + c;
+        const R *fp = f + ((valid ? i : 0) * B) * NC + c; // f staged in LDS
         A acc = {0, 0, 0, 0};
         for (int ks = 0; ks < nks; ++ks) {
             const int k = 4 * ks + (lane >> 4);
@@ -365,10 +398,47 @@ __global__ void __launch_bounds__(BLOCK) k_up_band(UpArgs<R, V> a)
     R *buf1 = buf0 + (size_t)nbot * RS;
     if (a.first_band) {
         V *g = a.mp + lev_off(lb, PU);
+        // staging area for the sources, after the two level buffers
+        R *stage = buf1 + (size_t)(nbot / 2 > 0 ? nbot / 2 : 1) * RS;
         bool done = false;
         if constexpr (SRC == SET_UNIFORM && KER == KER_COT) {
             if (a.leaf_pts > 0) {
-                p2m_mfma<R, V, PU>(a, first, nbot, buf0, RS, g, lane, wave);
+                const int nf = nbot * a.leaf_pts * 2;
+                const R *f = reinterpret_cast<const R *>(a.f_uniform) + first * a.leaf_pts * 2;
+                for (int i = tid; i < nf; i += BLOCK)
+                    stage[i] = f[i];
+                __syncthreads();
+                p2m_mfma<R, V, PU>(a, first, nbot, buf0, RS, g, lane, wave, stage);
+                done = true;
+            }
+        }
+        if constexpr (SRC == SET_SORTED) {
+            const int32_t t0 = a.src.off[first], t1 = a.src.off[first + nbot];
+            if (t1 - t0 <= a.stage_cap) {
+                const int cnt = t1 - t0;
+                R *sv = stage;
+                cx<R> *sw = reinterpret_cast<cx<R> *>(stage + ((a.stage_cap + 3) & ~3));
+                const double invN = 1.0 / (double)a.N;
+                for (int i = tid; i < cnt; i += BLOCK) {
+                    const int32_t t = t0 + i;
+                    sv[i] = (R)rel_coord_r(a.src.m[t], a.src.th[t], a.src_leaf[t], a.l,
+                                           a.N, invN);
+                    if constexpr (KER == KER_COT)
+                        sw[i] = a.w_sorted[t];
+                }
+                __syncthreads();
+                const double r = ldexp((double)a.N, -(a.l + 1));
+                constexpr int nch = PU / CHS;
+                for (int idx = tid; idx < nbot * nch; idx += BLOCK) {
+                    const int i = idx / nch, ch = idx - i * nch;
+                    V acc[CHS];
+                    p2m_staged<R, V, KER>(sv, sw, a.src.off[first + i] - t0,
+                                          a.src.off[first + i + 1] - t0, ch * CHS, r, acc);
+                    for (int c = 0; c < CHS; ++c) {
+                        st_coef<R, V>(buf0, RS, i, ch * CHS + c, acc[c]);
+                        g[(first + i) * PU + ch * CHS + c] = acc[c];
+                    }
+                }
                 done = true;
             }
         }

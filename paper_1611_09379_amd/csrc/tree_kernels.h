@@ -197,6 +197,48 @@ __global__ void k_reduce(int64_t M, const double *__restrict__ y, double c_hi,
     }
 }
 
+// Exclusive scan of up to SCAN1_MAX counts in one workgroup of 1024 threads:
+// thread i owns the run [32 i, 32 i + 32), loaded at once into registers.
+// off[n] = total; cursor (optional) receives a copy of the scan.
+constexpr int SCAN1_PER = 32;
+constexpr int SCAN1_MAX = 1024 * SCAN1_PER;
+__global__ void __launch_bounds__(1024)
+    k_scan_one(const int32_t *__restrict__ count, int n, int32_t *__restrict__ off,
+               int32_t *__restrict__ cursor)
+{
+    __shared__ int32_t part[1024];
+    const int i0 = threadIdx.x * SCAN1_PER;
+    int32_t v[SCAN1_PER];
+#pragma unroll
+    for (int u = 0; u < SCAN1_PER; ++u)
+        v[u] = i0 + u < n ? count[i0 + u] : 0;
+    int32_t sum = 0;
+#pragma unroll
+    for (int u = 0; u < SCAN1_PER; ++u)
+        sum += v[u];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the 1024 partial sums
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int32_t t = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+#pragma unroll
+    for (int u = 0; u < SCAN1_PER; ++u) {
+        if (i0 + u < n) {
+            off[i0 + u] = run;
+            if (cursor)
+                cursor[i0 + u] = run;
+        }
+        run += v[u];
+    }
+    if (threadIdx.x == 1023)
+        off[n] = part[1023];
+}
+
 // Exclusive scan of the leaf counts in three coalesced steps: sums of tiles
 // of SCAN_TILE counts, a scan of the tile sums (one workgroup), and the scan
 // inside every tile.
