@@ -138,14 +138,17 @@ int nufft_destroy(fn_plan *plan);
 /* Reports the parameters of a plan. */
 int nufft_plan_get_info(const fn_plan *plan, fn_plan_info *info);
 
-/* Parameters the library would choose for (N, M, eps, dtype): the
- * truncation numbers of Eq. (18.2) and the depth of Eq. (25).  Host only;
- * no GPU work.  Any output pointer may be NULL. */
+/* The paper's parameters for (N, M, eps, dtype): the truncation numbers of
+ * Eq. (18.2) and the depth of Eq. (25) with l_max = round(log2 sqrt(N M)) - 5
+ * (Section 3.2).  Plans default to a depth measured on MI355X instead, one
+ * level shallower or deeper depending on the size and the transform (their
+ * p follows Eq. (18.2) for that depth); nufft_plan_get_info reports what a
+ * plan uses.  Host only; no GPU work.  Any output pointer may be NULL. */
 int nufft_select_params(int64_t N, int64_t M, double eps, int dtype,
                         int32_t *p, int32_t *q, int32_t *lmax);
 
 /* Like nufft_plan_fwd / nufft_plan_inv with p, q and lmax given explicitly
- * (values <= 0 mean "choose as nufft_select_params").  For tuning and tests. */
+ * (values <= 0 mean "the plan's default").  For tuning and tests. */
 int nufft_plan_fwd_ex(fn_plan **plan, int64_t N, int64_t M, const double *y,
                       double eps, int dtype, int32_t p, int32_t q,
                       int32_t lmax, void *stream);

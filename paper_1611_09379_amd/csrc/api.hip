@@ -99,17 +99,28 @@ static void trunc_numbers(double eps, int lmax, int *p, int *q)
 }
 
 // Depth: Eq. (25) with the offset measured by the paper (l_max = log2 N - 5
-// for N = M, Section 3.2), generalised to N != M through log2 sqrt(N M).
-static int default_depth(int64_t N, int64_t M, int dtype)
+// for N = M, Section 3.2), generalised to N != M through lg = log2 sqrt(N M).
+static int paper_depth(int64_t N, int64_t M)
 {
-    (void)dtype;
     const double lg = 0.5 * std::log2((double)N * (double)M);
-    int l = (int)std::lround(lg) - 5;
-    if (const char *e = getenv("FN_LEAF_OFFSET"))
-        l = (int)std::lround(lg) - atoi(e);
-    return std::min(24, std::max(2, l));
+    return std::min(24, std::max(2, (int)std::lround(lg) - 5));
 }
 
+// Depth of a plan (kind 0 forward, 1 inverse): lg minus a leaf offset
+// measured on MI355X for one-shot transforms (binary64 and mixed agree).
+// Forward: 4 below lg = 14, 5 up to lg = 17, then 6 (leaves of about 64
+// targets: its near field runs on staged uniform sources and is cheap next
+// to the translations).  Inverse: 4 below lg = 17, then 5 (its sorted-source
+// and log near fields cost more per pair).  FN_LEAF_OFFSET overrides both.
+static int default_depth(int64_t N, int64_t M, int kind)
+{
+    const double lg = 0.5 * std::log2((double)N * (double)M);
+    const int r = (int)std::lround(lg);
+    int off = kind == 0 ? (r < 14 ? 4 : (r < 18 ? 5 : 6)) : (r < 17 ? 4 : 5);
+    if (const char *e = getenv("FN_LEAF_OFFSET"))
+        off = atoi(e);
+    return std::min(24, std::max(2, r - off));
+}
 
 static double eps_floor(int dtype) { return dtype == FN_C64 ? 1e-7 : 1e-15; }
 
@@ -974,10 +985,11 @@ static int check_common(int64_t N, int64_t M, double eps, int dtype)
     return FN_OK;
 }
 
-static void choose(int64_t N, int64_t M, double eps, int dtype, int32_t p_in,
+// Parameters of a plan of the given kind (-1: the paper's depth rule).
+static void choose(int64_t N, int64_t M, double eps, int kind, int32_t p_in,
                    int32_t q_in, int32_t l_in, int *p, int *q, int *l)
 {
-    *l = l_in > 0 ? l_in : default_depth(N, M, dtype);
+    *l = l_in > 0 ? l_in : (kind < 0 ? paper_depth(N, M) : default_depth(N, M, kind));
     int pp, qq;
     trunc_numbers(eps, *l, &pp, &qq);
     *p = p_in > 0 ? p_in : pp;
@@ -1007,7 +1019,7 @@ static int plan_common(fn_plan **out, int kind, int64_t N, int64_t M,
     P->N = N;
     P->M = M;
     P->eps = eps;
-    choose(N, M, eps, dtype, p_in, q_in, l_in, &P->p, &P->q, &P->l);
+    choose(N, M, eps, kind, p_in, q_in, l_in, &P->p, &P->q, &P->l);
     P->p_explicit = p_in > 0;
     if (P->p > 64 || 2 * P->q > 64) {
         const int p = P->p, q = P->q;
@@ -1147,7 +1159,7 @@ int nufft_select_params(int64_t N, int64_t M, double eps, int dtype, int32_t *p,
     if (rc)
         return rc;
     int pp, qq, ll;
-    choose(N, M, eps, dtype, 0, 0, 0, &pp, &qq, &ll);
+    choose(N, M, eps, -1, 0, 0, 0, &pp, &qq, &ll);
     if (p)
         *p = pp;
     if (q)
