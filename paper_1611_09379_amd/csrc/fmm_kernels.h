@@ -942,8 +942,10 @@ __device__ __forceinline__ double near_log(const DownArgs<R, V> &a, int64_t tm,
     return acc - near_log_background(tm, tth, leaf, l, N);
 }
 
+// Three waves per SIMD at least (at most 168 VGPRs): the binary64 variants
+// otherwise take up to 252 and run two.
 template <typename R, typename V, int KER, int SRC, int EPI, int PD>
-__global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
+__global__ void __launch_bounds__(BLOCK, 3) k_down_eval(DownArgs<R, V> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int RS = a.RS;
