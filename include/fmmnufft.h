@@ -156,6 +156,41 @@ int nufft_plan_inv_ex(fn_plan **plan, int64_t N, const double *y, double eps,
                       int dtype, int32_t p, int32_t q, int32_t lmax,
                       void *stream);
 
+/* ---- Batches of independent forward transforms (problem i) ----------
+ *
+ * count transforms of sizes N[t], M[t] (host arrays), with points y[t],
+ * inputs f[t] and outputs g[t] (host arrays of DEVICE pointers, each array
+ * laid out as for nufft_fwd).  All share eps and dtype.  Every pass of the
+ * method (the sort of the targets, the upward bands, the regular part, the
+ * downward pass with the evaluation) runs as one launch over the whole
+ * batch, each workgroup working for one transform; transforms too large for
+ * the shared sort (over 2^15 leaves) run with their own launches.  Errors
+ * name the first transform at fault (nufft_last_error). */
+typedef struct fn_batch fn_batch;
+
+/* One-shot batch: setup, evaluation and one synchronisation at the end
+ * (as nufft_fwd).  count >= 1. */
+int nufft_fwd_batched(int32_t count, const int64_t *N, const int64_t *M,
+                      const double *const *y, const void *const *f, void *const *g,
+                      double eps, int dtype, void *stream);
+
+/* Setup of a batch (the sorts), kept for repeated evaluations with new
+ * f[t], g[t] on the same points.  Synchronises the stream. */
+int nufft_plan_fwd_batched(fn_batch **batch, int32_t count, const int64_t *N,
+                           const int64_t *M, const double *const *y, double eps,
+                           int dtype, void *stream);
+
+/* Evaluation of a batch plan: g[t] = K_t f[t] for every t.  The shared
+ * launches are captured in a HIP graph on the first call and replayed on
+ * the batch's own stream, ordered after the work already enqueued on
+ * `stream` and before any work enqueued on it afterwards.  No
+ * synchronisation; calls on one batch must not run concurrently. */
+int nufft_execute_batched(fn_batch *batch, const void *const *f, void *const *g,
+                          void *stream);
+
+/* Releases a batch plan (NULL accepted).  Synchronises its streams. */
+int nufft_destroy_batched(fn_batch *batch);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *nufft_last_error(void);
 

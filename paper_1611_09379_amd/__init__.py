@@ -10,6 +10,8 @@ missing, importing the binding's functions raises: there is no fallback.
     f = inufft(y, g, eps)           # inverse, Eq. (p6), M = N
     plan = Plan.forward(N, y, eps)  # setup once per point set (Section 3.3)
     g = plan(f)                     # evaluation, repeated per input
+    gs = nufft_fwd_batched(ys, fs, eps)   # many forward transforms at once
+    batch = Batch.forward(ys, Ns, eps)    # batch setup; batch(fs) evaluates
 """
 from __future__ import annotations
 
@@ -29,7 +31,8 @@ ABI_SYMBOLS = (
     "nufft_plan_fwd_ex", "nufft_plan_inv_ex", "nufft_execute",
     "nufft_execute_phase",
     "nufft_destroy", "nufft_plan_get_info", "nufft_select_params",
-    "nufft_last_error",
+    "nufft_fwd_batched", "nufft_plan_fwd_batched", "nufft_execute_batched",
+    "nufft_destroy_batched", "nufft_last_error",
 )
 
 
@@ -75,6 +78,10 @@ def load_library(path: str = LIB_PATH):
         "nufft_destroy": [vp],
         "nufft_plan_get_info": [vp, ctypes.POINTER(PlanInfo)],
         "nufft_select_params": [i64, i64, dbl, ctypes.c_int, pi32, pi32, pi32],
+        "nufft_fwd_batched": [i32, vp, vp, vp, vp, vp, dbl, ctypes.c_int, vp],
+        "nufft_plan_fwd_batched": [pp, i32, vp, vp, vp, dbl, ctypes.c_int, vp],
+        "nufft_execute_batched": [vp, vp, vp, vp],
+        "nufft_destroy_batched": [vp],
         "nufft_last_error": [],
     }
     for name, args in sig.items():
@@ -230,3 +237,88 @@ def inufft(y, g, eps: float, out=None):
     _check(load_library().inufft(N, _dev_ptr(y, "y"), _dev_ptr(g, "g"),
                                  _dev_ptr(out, "f"), eps, dt, _stream()))
     return out
+
+
+def _ptr_array(ts, name):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = _dev_ptr(t, f"{name}[{i}]").value
+    return arr
+
+
+def _sizes(vals):
+    arr = (ctypes.c_int64 * len(vals))()
+    for i, v in enumerate(vals):
+        arr[i] = int(v)
+    return arr
+
+
+def nufft_fwd_batched(ys, fs, eps: float, outs=None):
+    """g_t = K_t f_t for every t (Eq. p2), one shot over a batch: ys and fs
+    are sequences of tensors (one transform each, same dtype)."""
+    torch = _torch()
+    if len(ys) != len(fs) or not ys:
+        raise ValueError("ys and fs must be non-empty and of equal length")
+    for y in ys:
+        _check_y(y)
+    dt = _dtype_code(fs[0])
+    if any(_dtype_code(f) != dt for f in fs):
+        raise TypeError("every f must have the same dtype")
+    if outs is None:
+        outs = [torch.empty(y.shape[0], dtype=fs[0].dtype, device=fs[0].device) for y in ys]
+    Ns = _sizes([f.shape[0] for f in fs])
+    Ms = _sizes([y.shape[0] for y in ys])
+    _check(load_library().nufft_fwd_batched(
+        len(ys), Ns, Ms, _ptr_array(ys, "y"), _ptr_array(fs, "f"),
+        _ptr_array(outs, "g"), eps, dt, _stream()))
+    return outs
+
+
+class Batch:
+    """Setup of a batch of forward transforms, evaluated repeatedly
+    (nufft_plan_fwd_batched / nufft_execute_batched)."""
+
+    def __init__(self, handle, Ns, Ms, dtype):
+        self._h = handle
+        self.Ns, self.Ms, self.dtype = list(Ns), list(Ms), dtype
+
+    @classmethod
+    def forward(cls, ys, Ns, eps: float, dtype: int = FN_C128):
+        for y in ys:
+            _check_y(y)
+        if len(ys) != len(Ns) or not ys:
+            raise ValueError("ys and Ns must be non-empty and of equal length")
+        h = ctypes.c_void_p()
+        Ms = [y.shape[0] for y in ys]
+        _check(load_library().nufft_plan_fwd_batched(
+            ctypes.byref(h), len(ys), _sizes(Ns), _sizes(Ms), _ptr_array(ys, "y"),
+            eps, dtype, _stream()))
+        return cls(h, Ns, Ms, dtype)
+
+    def execute(self, fs, outs=None):
+        torch = _torch()
+        if self._h is None:
+            raise RuntimeError("batch was destroyed")
+        if len(fs) != len(self.Ns):
+            raise ValueError("one input per transform")
+        for f, n in zip(fs, self.Ns):
+            if _dtype_code(f) != self.dtype or f.shape != (n,):
+                raise ValueError("input dtype or shape does not match the batch")
+        if outs is None:
+            outs = [torch.empty(m, dtype=fs[0].dtype, device=fs[0].device) for m in self.Ms]
+        _check(load_library().nufft_execute_batched(
+            self._h, _ptr_array(fs, "f"), _ptr_array(outs, "g"), _stream()))
+        return outs
+
+    __call__ = execute
+
+    def destroy(self):
+        if self._h is not None:
+            _check(load_library().nufft_destroy_batched(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

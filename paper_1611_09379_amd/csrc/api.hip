@@ -605,118 +605,143 @@ static int32_t dense_max(int64_t N, int l)
 
 static constexpr int SORT_LDS_BINS = 32768; // LDS histogram limit (128 KB)
 
-// Sort a point set by the level-(l - keyshift) box (the leaves for
-// keyshift = 0): a counting sort with per-block LDS histograms when the
-// keys fit in LDS, with global atomics otherwise.  deterministic: order
-// inside each leaf by position (inverse; keyshift must be 0); otherwise the
-// order inside a key is arbitrary (forward).  Fills the hit map when asked.
-// Enqueues only; errors land in P->flags.
-static int build_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
-                      bool deterministic, bool want_hit, hipStream_t st)
+// The sort of a point set by the level-(l - keyshift) box (the leaves for
+// keyshift = 0): a counting sort with per-block LDS histograms when the keys
+// fit in LDS, with global atomics otherwise.  It is split into its workspace
+// and arguments (prepare_tree) and its launches (launch_tree), so that a
+// batch of sorts can share launches.
+struct TreeJob {
+    SortArgs a{};
+    bool lds_path = true, deterministic = false;
+    int32_t *tsum = nullptr;               // tile sums of the multi-pass scan
+    int32_t *gm = nullptr, *gperm = nullptr; // deterministic: before ranking
+    double *gth = nullptr;
+};
+
+static int prepare_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
+                        bool deterministic, bool want_hit, TreeJob *J)
 {
     const int nbins = 1 << (P->l - keyshift);
-    int32_t *um = (int32_t *)tmp_alloc(P, n * 4);
-    double *uth = (double *)tmp_alloc(P, n * 8);
-    int32_t *ukey = (int32_t *)tmp_alloc(P, n * 4);
-    const bool lds_path = nbins <= SORT_LDS_BINS;
-    const int nblk = lds_path ? (int)std::max<int64_t>(1, std::min<int64_t>(128, (n + 8191) / 8192)) : 0;
-    const int64_t chunk = lds_path ? (n + nblk - 1) / nblk : 0;
-    int32_t *H = lds_path ? (int32_t *)tmp_alloc(P, (size_t)nbins * nblk * 4) : nullptr;
-    int32_t *tot = (int32_t *)tmp_alloc(P, (size_t)nbins * 4);
-    int32_t *tsum = (int32_t *)tmp_alloc(P, ((nbins + SCAN_TILE - 1) / SCAN_TILE) * 4);
-    int32_t *gm = nullptr, *gperm = nullptr, *gkey = nullptr;
-    double *gth = nullptr;
+    J->deterministic = deterministic;
+    J->lds_path = nbins <= SORT_LDS_BINS;
+    const bool lds_path = J->lds_path;
+    SortArgs &a = J->a;
+    a.n = n;
+    a.y = y;
+    n_over_2pi(P->N, &a.c_hi, &a.c_lo);
+    a.N = P->N;
+    a.l = P->l;
+    a.keyshift = keyshift;
+    a.ymax = FN_Y_MAX;
+    a.nbins = nbins;
+    a.nblk = lds_path ? (int)std::max<int64_t>(1, std::min<int64_t>(128, (n + 8191) / 8192)) : 0;
+    a.chunk = lds_path ? (n + a.nblk - 1) / a.nblk : 0;
+    a.um = (int32_t *)tmp_alloc(P, n * 4);
+    a.uth = (double *)tmp_alloc(P, n * 8);
+    a.ukey = (int32_t *)tmp_alloc(P, n * 4);
+    a.H = lds_path ? (int32_t *)tmp_alloc(P, (size_t)nbins * a.nblk * 4) : nullptr;
+    a.tot = (int32_t *)tmp_alloc(P, (size_t)nbins * 4);
+    a.cursor = lds_path ? nullptr : (int32_t *)tmp_alloc(P, (size_t)nbins * 4);
+    J->tsum = (int32_t *)tmp_alloc(P, ((nbins + SCAN_TILE - 1) / SCAN_TILE) * 4);
     if (deterministic) {
-        gm = (int32_t *)tmp_alloc(P, n * 4);
-        gth = (double *)tmp_alloc(P, n * 8);
-        gperm = (int32_t *)tmp_alloc(P, n * 4);
+        J->gm = (int32_t *)tmp_alloc(P, n * 4);
+        J->gth = (double *)tmp_alloc(P, n * 8);
+        J->gperm = (int32_t *)tmp_alloc(P, n * 4);
     }
     // every point's leaf, kept with the plan (k_rank only reorders inside a
     // leaf, so it holds for the final order too)
-    if (!alloc(P->skey, n * 4))
-        return fail(FN_ENOMEM, "workspace allocation failed");
-    gkey = (int32_t *)P->skey.p;
-    if (!um || !uth || !ukey || (lds_path && !H) || !tot || !tsum ||
-        (deterministic && (!gm || !gth || !gperm)) ||
-        !alloc(P->off, ((size_t)nbins + 1) * 4) || !alloc(P->sm, n * 4) ||
-        !alloc(P->sth, n * 8) || !alloc(P->sperm, n * 4) ||
+    if (!a.um || !a.uth || !a.ukey || (lds_path && !a.H) || !a.tot || !J->tsum ||
+        (!lds_path && !a.cursor) || (deterministic && (!J->gm || !J->gth || !J->gperm)) ||
+        !alloc(P->skey, n * 4) || !alloc(P->off, ((size_t)nbins + 1) * 4) ||
+        !alloc(P->sm, n * 4) || !alloc(P->sth, n * 8) || !alloc(P->sperm, n * 4) ||
         (want_hit && !alloc(P->hit, P->N * 4)))
         return fail(FN_ENOMEM, "workspace allocation failed (%lld points)", (long long)n);
     if ((nbins + SCAN_TILE - 1) / SCAN_TILE > 4096)
         return fail(FN_EINVAL, "tree too large for the scan (%d leaves)", nbins);
-    double chi, clo;
-    n_over_2pi(P->N, &chi, &clo);
-    if (want_hit)
-        HIPCHK(hipMemsetAsync(P->hit.p, 0xff, P->N * 4, st));
-    int32_t *hit = want_hit ? (int32_t *)P->hit.p : nullptr;
-    int *flags = (int *)P->flags.p;
-    if (lds_path) {
-        hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(256), 0, st, n, y, chi, clo,
-                           P->N, P->l, keyshift, (double)FN_Y_MAX, um, uth, ukey, hit,
-                           flags);
+    a.off = (int32_t *)P->off.p;
+    a.sm = deterministic ? J->gm : (int32_t *)P->sm.p;
+    a.sth = deterministic ? J->gth : (double *)P->sth.p;
+    a.sperm = deterministic ? J->gperm : (int32_t *)P->sperm.p;
+    a.skey = (int32_t *)P->skey.p;
+    a.hit = want_hit ? (int32_t *)P->hit.p : nullptr;
+    a.flags = (int *)P->flags.p;
+    return FN_OK;
+}
+
+// Enqueues the sort of one point set; errors land in P->flags.
+static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
+{
+    const SortArgs &a = J.a;
+    const int nbins = a.nbins;
+    if (a.hit)
+        HIPCHK(hipMemsetAsync(a.hit, 0xff, P->N * 4, st));
+    if (J.lds_path) {
+        hipLaunchKernelGGL(k_keys, dim3(grid_for(a.n)), dim3(256), 0, st, a);
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_hist, dim3(nblk), dim3(256), (size_t)nbins * 4, st, n, chunk,
-                           nbins, (const int32_t *)ukey, H);
+        hipLaunchKernelGGL(k_hist, dim3(a.nblk), dim3(256), (size_t)nbins * 4, st, a);
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_colscan, dim3(grid_for(nbins)), dim3(256), 0, st, nbins, nblk,
-                           H, tot);
+        hipLaunchKernelGGL(k_colscan, dim3(grid_for(nbins)), dim3(256), 0, st, a);
     } else {
-        HIPCHK(hipMemsetAsync(tot, 0, (size_t)nbins * 4, st));
-        hipLaunchKernelGGL(k_reduce, dim3(grid_for(n)), dim3(256), 0, st, n, y, chi,
-                           clo, P->N, P->l, keyshift, (double)FN_Y_MAX, um, uth, ukey,
-                           tot, hit, flags);
+        HIPCHK(hipMemsetAsync(a.tot, 0, (size_t)nbins * 4, st));
+        hipLaunchKernelGGL(k_reduce, dim3(grid_for(a.n)), dim3(256), 0, st, a.n, a.y,
+                           a.c_hi, a.c_lo, a.N, a.l, a.keyshift, a.ymax, a.um, a.uth,
+                           a.ukey, a.tot, a.hit, a.flags);
     }
     HIPCHK(hipGetLastError());
     // off = exclusive scan of the key totals; cursor copy for the atomic path
-    int32_t *off = (int32_t *)P->off.p;
-    int32_t *cursor = lds_path ? nullptr : (int32_t *)tmp_alloc(P, (size_t)nbins * 4);
-    if (!lds_path && !cursor)
-        return fail(FN_ENOMEM, "workspace allocation failed");
     if (nbins <= SCAN1_MAX) {
-        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, st, (const int32_t *)tot,
-                           nbins, off, cursor);
+        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, st, (const int32_t *)a.tot,
+                           nbins, a.off, a.cursor);
         HIPCHK(hipGetLastError());
     } else {
         const int nt = (int)((nbins + SCAN_TILE - 1) / SCAN_TILE);
-        hipLaunchKernelGGL(k_scan_sums, dim3(nt), dim3(256), 0, st, (const int32_t *)tot,
-                           (int64_t)nbins, tsum);
+        hipLaunchKernelGGL(k_scan_sums, dim3(nt), dim3(256), 0, st, (const int32_t *)a.tot,
+                           (int64_t)nbins, J.tsum);
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tsum, nt, off + nbins);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, J.tsum, nt, a.off + nbins);
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(256), 0, st, (const int32_t *)tot,
-                           (int64_t)nbins, (const int32_t *)tsum, off, cursor);
+        hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(256), 0, st, (const int32_t *)a.tot,
+                           (int64_t)nbins, (const int32_t *)J.tsum, a.off, a.cursor);
         HIPCHK(hipGetLastError());
     }
-    int32_t *dm = deterministic ? gm : (int32_t *)P->sm.p;
-    double *dth = deterministic ? gth : (double *)P->sth.p;
-    int32_t *dperm = deterministic ? gperm : (int32_t *)P->sperm.p;
-    if (lds_path) {
-        hipLaunchKernelGGL(k_place, dim3(nblk), dim3(256), (size_t)nbins * 4, st, n,
-                           chunk, nbins, (const int32_t *)H, (const int32_t *)off,
-                           (const int32_t *)um, (const double *)uth, (const int32_t *)ukey,
-                           dm, dth, dperm, gkey);
+    if (J.lds_path) {
+        hipLaunchKernelGGL(k_place, dim3(a.nblk), dim3(256), (size_t)nbins * 4, st, a);
     } else {
-        hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(256), 0, st, n,
-                           (const int32_t *)um, (const double *)uth, (const int32_t *)ukey,
-                           cursor, dm, dth, dperm, gkey);
+        hipLaunchKernelGGL(k_scatter, dim3(grid_for(a.n)), dim3(256), 0, st, a.n,
+                           (const int32_t *)a.um, (const double *)a.uth,
+                           (const int32_t *)a.ukey, a.cursor, a.sm, a.sth, a.sperm, a.skey);
     }
     HIPCHK(hipGetLastError());
-    if (deterministic) {
-        hipLaunchKernelGGL(k_rank, dim3(grid_for(n)), dim3(256), 0, st, n,
-                           (const int32_t *)gm, (const double *)gth,
-                           (const int32_t *)gperm, (const int32_t *)gkey,
-                           (const int32_t *)P->off.p, dense_max(P->N, P->l),
+    if (J.deterministic) {
+        hipLaunchKernelGGL(k_rank, dim3(grid_for(a.n)), dim3(256), 0, st, a.n,
+                           (const int32_t *)J.gm, (const double *)J.gth,
+                           (const int32_t *)J.gperm, (const int32_t *)a.skey,
+                           (const int32_t *)a.off, dense_max(P->N, P->l),
                            (int32_t *)P->sm.p, (double *)P->sth.p, (int32_t *)P->sperm.p,
-                           flags);
+                           a.flags);
         HIPCHK(hipGetLastError());
     }
     return FN_OK;
 }
 
+// Sort of the points into the leaves, ranked inside each leaf by position
+// (inverse; keyshift must be 0) when `deterministic`; otherwise the order
+// inside a key is arbitrary (forward).  Fills the hit map when asked.
+// Enqueues only; errors land in P->flags.
+static int build_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
+                      bool deterministic, bool want_hit, hipStream_t st)
+{
+    TreeJob J;
+    int rc = prepare_tree(P, n, y, keyshift, deterministic, want_hit, &J);
+    if (rc)
+        return rc;
+    return launch_tree(P, J, st);
+}
+
 // Work list of k_down_eval, built on the device: subtree roots of level lr;
 // P->off indexes the sorted points at level lr + sh.  The grid is sized for
 // the largest possible list.
-static int build_work(fn_plan *P, int sh, bool uniform, int64_t npts, hipStream_t st)
+static int prepare_work(fn_plan *P, int sh, bool uniform, int64_t npts, WorkArgs *w)
 {
     const int32_t tmax = 2048;
     const int64_t nroot = int64_t(1) << P->lr;
@@ -726,9 +751,18 @@ static int build_work(fn_plan *P, int sh, bool uniform, int64_t npts, hipStream_
     P->nwork = (int)maxitems;
     if (!alloc(P->work, maxitems * sizeof(WorkItem)) || !alloc(P->nwork_dev, 4))
         return fail(FN_ENOMEM, "work list allocation failed");
-    hipLaunchKernelGGL(k_work, dim3(1), dim3(1024), 0, st, nroot, sh,
-                       (const int32_t *)P->off.p, uniform ? 1 : 0, P->N, P->lr, tmax,
-                       (WorkItem *)P->work.p, (int32_t *)P->nwork_dev.p);
+    *w = {nroot, sh, (const int32_t *)P->off.p, uniform ? 1 : 0, P->N, P->lr, tmax,
+          (WorkItem *)P->work.p, (int32_t *)P->nwork_dev.p};
+    return FN_OK;
+}
+
+static int build_work(fn_plan *P, int sh, bool uniform, int64_t npts, hipStream_t st)
+{
+    WorkArgs w;
+    int rc = prepare_work(P, sh, uniform, npts, &w);
+    if (rc)
+        return rc;
+    hipLaunchKernelGGL(k_work, dim3(1), dim3(1024), 0, st, w);
     HIPCHK(hipGetLastError());
     return FN_OK;
 }
@@ -1066,6 +1100,414 @@ static int finish_one_shot(fn_plan *P, int rc_exec)
     return rc ? rc : rc_exec;
 }
 
+// ------------------------------------------------------ batched forward
+//
+// Many independent forward transforms of uneven sizes.  Every transform
+// gets its own plan (workspace, tree, work list), but each pass runs as one
+// launch over the whole batch: block b of a launch works for the transform
+// its BlockMap assigns.  The arguments of all launches sit in one device
+// blob written at plan time; the per-call inputs and outputs come from a
+// small IoPtr table, so the evaluation (upward bands, regular part,
+// downward pass) is captured once in a HIP graph and replayed.  Transforms
+// whose sort needs the global-atomic path or whose expansion lengths differ
+// from the batch's run with their own launches.
+
+struct LaunchShape {
+    size_t args = 0, map = 0; // byte offsets in the blob
+    int grid = 0, n = 0;      // blocks; problems in the launch
+    size_t smem = 0;
+};
+
+struct fn_batch {
+    int T = 0, dtype = 0;
+    double eps = 0;
+    std::vector<fn_plan *> P;
+    std::vector<int> grp, solo;
+    int PU = 0, PD = 0, q = 0, nbands = 0;
+    size_t reg_smem = 0;
+    Buf blob, io, flags;
+    std::vector<IoPtr> hio;
+    LaunchShape keys, hist, colscan, place, scan, work, reg, down, up[MAX_BANDS];
+    hipStream_t stream = nullptr;
+    hipStream_t bs = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+// Host image of the blob: argument arrays and block maps appended in turn.
+struct BlobBuilder {
+    std::vector<unsigned char> bytes;
+    size_t put(const void *p, size_t n)
+    {
+        size_t off = (bytes.size() + 15) & ~size_t(15);
+        bytes.resize(off + n);
+        memcpy(bytes.data() + off, p, n);
+        return off;
+    }
+    template <typename A>
+    void add(LaunchShape &L, const std::vector<A> &args, const std::vector<int> &blocks)
+    {
+        std::vector<int32_t> start(blocks.size() + 1, 0);
+        for (size_t i = 0; i < blocks.size(); ++i)
+            start[i + 1] = start[i] + blocks[i];
+        L.args = put(args.data(), args.size() * sizeof(A));
+        L.map = put(start.data(), start.size() * 4);
+        L.grid = start.back();
+        L.n = (int)args.size();
+    }
+};
+
+static void release_batch(fn_batch *B)
+{
+    for (fn_plan *P : B->P) {
+        if (!P)
+            continue;
+        P->flags = Buf{}; // a slot of the batch's flag array
+        release_plan(P);
+        delete P;
+    }
+    B->P.clear();
+    release(B->blob);
+    release(B->io);
+    release(B->flags);
+    if (B->gexec)
+        (void)hipGraphExecDestroy(B->gexec);
+    if (B->ev_in)
+        (void)hipEventDestroy(B->ev_in);
+    if (B->ev_out)
+        (void)hipEventDestroy(B->ev_out);
+    if (B->bs)
+        (void)hipStreamDestroy(B->bs);
+}
+
+template <typename R>
+static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
+                           const double *const *ys, hipStream_t st)
+{
+    using V = cx<R>;
+    const int T = B->T;
+    if (!alloc(B->flags, (size_t)T * 4) || !alloc(B->io, (size_t)T * sizeof(IoPtr)))
+        return fail(FN_ENOMEM, "batch allocation failed");
+    HIPCHK(hipMemsetAsync(B->flags.p, 0, (size_t)T * 4, st));
+    std::vector<SortArgs> sa;
+    std::vector<WorkArgs> wa;
+    std::vector<int> nb_keys, nb_hist, nb_col, nb_one;
+    std::vector<TreeJob> jobs(T);
+    std::vector<WorkArgs> works(T);
+    B->P.assign(T, nullptr);
+    for (int t = 0; t < T; ++t) {
+        fn_plan *P = new fn_plan();
+        B->P[t] = P;
+        P->kind = 0;
+        P->dtype = B->dtype;
+        P->N = Ns[t];
+        P->M = Ms[t];
+        P->eps = B->eps;
+        P->stream = st;
+        choose(P->N, P->M, P->eps, 0, 0, 0, 0, &P->p, &P->q, &P->l);
+        if (P->p > 64 || 2 * P->q > 64)
+            return fail(FN_EINVAL, "transform %d: truncation numbers need more than 64 terms", t);
+        P->flags.p = (int *)B->flags.p + t;
+        int PU, PD;
+        cot_lengths(P, &PU, &PD);
+        P->lr = choose_lr(P->l, 2, PD, sizeof(R));
+        int rc = prepare_tree(P, P->M, ys[t], 0, false, false, &jobs[t]);
+        if (!rc)
+            rc = prepare_work(P, P->l - P->lr, false, P->M, &works[t]);
+        if (!rc)
+            rc = setup_fmm<R, V>(P, KER_COT, PU, PD, P->q, false, P->cot, st);
+        if (rc)
+            return rc;
+        if (B->grp.empty()) {
+            B->PU = PU;
+            B->PD = PD;
+            B->q = P->q;
+        }
+        const bool shared = jobs[t].lds_path && PU == B->PU && PD == B->PD &&
+                            jobs[t].a.nbins <= SCAN1_MAX;
+        (shared ? B->grp : B->solo).push_back(t);
+    }
+    // the sorts: shared launches for the group, own launches for the rest
+    BlobBuilder bb;
+    size_t hist_smem = 0;
+    for (int t : B->grp) {
+        const SortArgs &a = jobs[t].a;
+        sa.push_back(a);
+        wa.push_back(works[t]);
+        nb_keys.push_back(grid_for(a.n));
+        nb_hist.push_back(a.nblk);
+        nb_col.push_back(grid_for(a.nbins));
+        nb_one.push_back(1);
+        hist_smem = std::max(hist_smem, (size_t)a.nbins * 4);
+    }
+    if (!B->grp.empty()) {
+        bb.add(B->keys, sa, nb_keys);
+        bb.add(B->hist, sa, nb_hist);
+        B->hist.smem = hist_smem;
+        bb.add(B->colscan, sa, nb_col);
+        bb.add(B->scan, sa, nb_one);
+        bb.add(B->place, sa, nb_hist);
+        B->place.smem = hist_smem;
+        bb.add(B->work, wa, nb_one);
+    }
+    // the evaluation: per band, the transforms that have it
+    OpTables<R> Tb;
+    int rc = get_tables<R>(KER_COT, B->PU ? B->PU : 16, B->PD ? B->PD : 16, B->q ? B->q : 1, &Tb);
+    if (rc)
+        return rc;
+    B->nbands = 0;
+    for (int t : B->grp)
+        B->nbands = std::max(B->nbands, B->P[t]->cot.nbands);
+    for (int k = 0; k < B->nbands; ++k) {
+        std::vector<UpArgs<R, V>> ua;
+        std::vector<int> nb;
+        size_t smem = 0;
+        for (int t : B->grp) {
+            const fn_plan *P = B->P[t];
+            const FmmSetup &F = P->cot;
+            if (k >= F.nbands)
+                continue;
+            UpArgs<R, V> u{};
+            fill_up(P, F, Tb, u);
+            u.lb = F.band[k].lb;
+            u.d = F.band[k].d;
+            u.first_band = F.band[k].first;
+            u.io_index = t;
+            ua.push_back(u);
+            nb.push_back(F.band[k].grid);
+            smem = std::max(smem, F.band[k].smem);
+        }
+        bb.add(B->up[k], ua, nb);
+        B->up[k].smem = smem;
+    }
+    {
+        std::vector<UpArgs<R, V>> ua;
+        std::vector<DownArgs<R, V>> da;
+        std::vector<int> nb_reg, nb_down;
+        size_t dsm = 0;
+        for (int t : B->grp) {
+            fn_plan *P = B->P[t];
+            const FmmSetup &F = P->cot;
+            UpArgs<R, V> u{};
+            fill_up(P, F, Tb, u);
+            u.io_index = t;
+            ua.push_back(u);
+            nb_reg.push_back(1);
+            B->reg_smem = std::max(B->reg_smem, F.reg_smem);
+            DownArgs<R, V> d{};
+            fill_down(P, F, Tb, d);
+            d.tgt = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
+                     (const double *)P->sth.p, (const int32_t *)P->sperm.p};
+            d.tgt_leaf = (const int32_t *)P->skey.p;
+            d.io_index = t;
+            da.push_back(d);
+            nb_down.push_back(P->nwork);
+            dsm = std::max(dsm, F.dn_smem);
+        }
+        bb.add(B->reg, ua, nb_reg);
+        B->reg.smem = B->reg_smem;
+        bb.add(B->down, da, nb_down);
+        B->down.smem = dsm;
+    }
+    if (!bb.bytes.empty()) {
+        if (!alloc(B->blob, bb.bytes.size()))
+            return fail(FN_ENOMEM, "batch argument allocation failed");
+        HIPCHK(hipMemcpyAsync(B->blob.p, bb.bytes.data(), bb.bytes.size(),
+                              hipMemcpyHostToDevice, st));
+    }
+    // enqueue the sorts
+    auto at = [&](size_t off) { return (unsigned char *)B->blob.p + off; };
+    auto map = [&](const LaunchShape &L) {
+        return BlockMap{(const int32_t *)at(L.map), L.n};
+    };
+    if (!B->grp.empty()) {
+        const SortArgs *A = (const SortArgs *)at(B->keys.args);
+        hipLaunchKernelGGL(kb_keys, dim3(B->keys.grid), dim3(256), 0, st, A, map(B->keys));
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(kb_hist, dim3(B->hist.grid), dim3(256), B->hist.smem, st,
+                           (const SortArgs *)at(B->hist.args), map(B->hist));
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(kb_colscan, dim3(B->colscan.grid), dim3(256), 0, st,
+                           (const SortArgs *)at(B->colscan.args), map(B->colscan));
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(kb_scan_one, dim3(B->scan.grid), dim3(1024), 0, st,
+                           (const SortArgs *)at(B->scan.args));
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(kb_place, dim3(B->place.grid), dim3(256), B->place.smem, st,
+                           (const SortArgs *)at(B->place.args), map(B->place));
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(kb_work, dim3(B->work.grid), dim3(1024), 0, st,
+                           (const WorkArgs *)at(B->work.args));
+        HIPCHK(hipGetLastError());
+    }
+    for (int t : B->solo) {
+        rc = launch_tree(B->P[t], jobs[t], st);
+        if (rc)
+            return rc;
+        hipLaunchKernelGGL(k_work, dim3(1), dim3(1024), 0, st, works[t]);
+        HIPCHK(hipGetLastError());
+    }
+    return FN_OK;
+}
+
+// The evaluation of the group: upward bands, regular part, downward pass.
+template <typename R>
+static int launch_batch_eval(fn_batch *B, hipStream_t st)
+{
+    using V = cx<R>;
+    if (B->grp.empty())
+        return FN_OK;
+    auto at = [&](size_t off) { return (unsigned char *)B->blob.p + off; };
+    auto map = [&](const LaunchShape &L) {
+        return BlockMap{(const int32_t *)at(L.map), L.n};
+    };
+    const IoPtr *io = (const IoPtr *)B->io.p;
+    for (int k = 0; k < B->nbands; ++k) {
+        const LaunchShape &L = B->up[k];
+        FN_DISPATCH16(B->PU, PU_,
+                      hipLaunchKernelGGL((kb_up_band<R, V, KER_COT, SET_UNIFORM, PU_>),
+                                         dim3(L.grid), dim3(BLOCK), L.smem, st,
+                                         (const UpArgs<R, V> *)at(L.args), map(L), io));
+        HIPCHK(hipGetLastError());
+    }
+    hipLaunchKernelGGL((kb_regular<R, V, KER_COT>), dim3(B->reg.grid), dim3(BLOCK),
+                       B->reg.smem, st, (const UpArgs<R, V> *)at(B->reg.args), B->PU);
+    HIPCHK(hipGetLastError());
+    FN_DISPATCH16(B->PD, PD_,
+                  hipLaunchKernelGGL((kb_down_eval<R, V, KER_COT, SET_UNIFORM, EPI_FWD, PD_>),
+                                     dim3(B->down.grid), dim3(BLOCK), B->down.smem, st,
+                                     (const DownArgs<R, V> *)at(B->down.args), map(B->down),
+                                     io));
+    HIPCHK(hipGetLastError());
+    return FN_OK;
+}
+
+static int plan_batch(fn_batch **out, int32_t count, const int64_t *Ns, const int64_t *Ms,
+                      const double *const *ys, double eps, int dtype, void *stream)
+{
+    if (!out)
+        return fail(FN_EINVAL, "batch pointer is NULL");
+    *out = nullptr;
+    if (count < 1 || !Ns || !Ms || !ys)
+        return fail(FN_EINVAL, "count must be >= 1 and the size and point arrays non-NULL");
+    for (int32_t t = 0; t < count; ++t) {
+        int rc = check_common(Ns[t], Ms[t], eps, dtype);
+        if (rc)
+            return fail(rc, "transform %d: %s", t, std::string(g_err).c_str());
+        if (!ys[t])
+            return fail(FN_EINVAL, "transform %d: y is NULL", t);
+    }
+    fn_batch *B = new fn_batch();
+    B->T = count;
+    B->dtype = dtype;
+    B->eps = eps;
+    hipStream_t st = (hipStream_t)stream;
+    B->stream = st;
+    int rc = dtype == FN_C128 ? plan_batch_impl<double>(B, Ns, Ms, ys, st)
+                              : plan_batch_impl<float>(B, Ns, Ms, ys, st);
+    if (rc) {
+        (void)hipStreamSynchronize(st);
+        release_batch(B);
+        delete B;
+        return rc;
+    }
+    *out = B;
+    return FN_OK;
+}
+
+// Waits for the batch's setup and reports its errors (first transform
+// with a flag); releases the setup temporaries.
+static int finish_batch(fn_batch *B, hipStream_t st)
+{
+    std::vector<int> hf(B->T, 0);
+    hipError_t e = hipMemcpyAsync(hf.data(), B->flags.p, (size_t)B->T * 4,
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    for (fn_plan *P : B->P)
+        release_tmp(P);
+    if (e != hipSuccess)
+        return fail(FN_EHIP, "batch setup: %s", hipGetErrorString(e));
+    for (int t = 0; t < B->T; ++t)
+        if (hf[t] & FLAG_BAD_Y)
+            return fail(FN_EINVAL, "transform %d: y holds a non-finite value or |y| > %g", t,
+                        FN_Y_MAX);
+    return FN_OK;
+}
+
+template <typename R>
+static int exec_batch_impl(fn_batch *B, const void *const *f, void *const *g, hipStream_t st,
+                           bool graph)
+{
+    for (int t = 0; t < B->T; ++t)
+        if (!f[t] || !g[t])
+            return fail(FN_EINVAL, "transform %d: f or g is NULL", t);
+    B->hio.resize(B->T);
+    for (int t = 0; t < B->T; ++t)
+        B->hio[t] = {f[t], g[t]};
+    B->stream = st;
+    if (!B->grp.empty()) {
+        if (!graph) {
+            HIPCHK(hipMemcpyAsync(B->io.p, B->hio.data(), (size_t)B->T * sizeof(IoPtr),
+                                  hipMemcpyHostToDevice, st));
+            int rc = launch_batch_eval<R>(B, st);
+            if (rc)
+                return rc;
+        } else {
+            // replay on the batch's stream, ordered after the caller's work
+            if (!B->bs) {
+                HIPCHK(hipStreamCreateWithFlags(&B->bs, hipStreamNonBlocking));
+                HIPCHK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
+                HIPCHK(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
+            }
+            HIPCHK(hipEventRecord(B->ev_in, st));
+            HIPCHK(hipStreamWaitEvent(B->bs, B->ev_in, 0));
+            HIPCHK(hipMemcpyAsync(B->io.p, B->hio.data(), (size_t)B->T * sizeof(IoPtr),
+                                  hipMemcpyHostToDevice, B->bs));
+            if (!B->gexec) {
+                hipGraph_t gr = nullptr;
+                HIPCHK(hipStreamBeginCapture(B->bs, hipStreamCaptureModeThreadLocal));
+                int rc = launch_batch_eval<R>(B, B->bs);
+                hipError_t e = hipStreamEndCapture(B->bs, &gr);
+                if (rc) {
+                    if (gr)
+                        (void)hipGraphDestroy(gr);
+                    return rc;
+                }
+                if (e != hipSuccess)
+                    return fail(FN_EHIP, "graph capture: %s", hipGetErrorString(e));
+                e = hipGraphInstantiate(&B->gexec, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                if (e != hipSuccess) {
+                    B->gexec = nullptr;
+                    return fail(FN_EHIP, "graph instantiation: %s", hipGetErrorString(e));
+                }
+            }
+            HIPCHK(hipGraphLaunch(B->gexec, B->bs));
+            HIPCHK(hipEventRecord(B->ev_out, B->bs));
+            HIPCHK(hipStreamWaitEvent(st, B->ev_out, 0));
+        }
+    }
+    for (int t : B->solo) {
+        int rc = exec_fwd<R>(B->P[t], f[t], g[t], -1, st);
+        if (rc)
+            return rc;
+    }
+    return FN_OK;
+}
+
+static int exec_batch(fn_batch *B, const void *const *f, void *const *g, void *stream,
+                      bool graph)
+{
+    if (!B)
+        return fail(FN_EINVAL, "batch is NULL");
+    if (!f || !g)
+        return fail(FN_EINVAL, "f or g pointer array is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    return B->dtype == FN_C128 ? exec_batch_impl<double>(B, f, g, st, graph)
+                               : exec_batch_impl<float>(B, f, g, st, graph);
+}
+
 extern "C" {
 
 int nufft_plan_fwd_ex(fn_plan **plan, int64_t N, int64_t M, const double *y,
@@ -1191,6 +1633,58 @@ int inufft(int64_t N, const double *y, const void *g, void *f, double eps,
     if (rc)
         return rc;
     return finish_one_shot(P, nufft_execute(P, g, f, stream));
+}
+
+int nufft_plan_fwd_batched(fn_batch **batch, int32_t count, const int64_t *N,
+                           const int64_t *M, const double *const *y, double eps, int dtype,
+                           void *stream)
+{
+    int rc = plan_batch(batch, count, N, M, y, eps, dtype, stream);
+    if (rc)
+        return rc;
+    rc = finish_batch(*batch, (hipStream_t)stream);
+    if (rc) {
+        release_batch(*batch);
+        delete *batch;
+        *batch = nullptr;
+    }
+    return rc;
+}
+
+int nufft_execute_batched(fn_batch *batch, const void *const *f, void *const *g, void *stream)
+{
+    return exec_batch(batch, f, g, stream, true);
+}
+
+int nufft_destroy_batched(fn_batch *batch)
+{
+    if (!batch)
+        return FN_OK;
+    hipError_t e = hipStreamSynchronize(batch->stream);
+    if (e == hipSuccess && batch->bs)
+        e = hipStreamSynchronize(batch->bs);
+    release_batch(batch);
+    delete batch;
+    if (e != hipSuccess)
+        return fail(FN_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    return FN_OK;
+}
+
+int nufft_fwd_batched(int32_t count, const int64_t *N, const int64_t *M,
+                      const double *const *y, const void *const *f, void *const *g,
+                      double eps, int dtype, void *stream)
+{
+    if (!f || !g)
+        return fail(FN_EINVAL, "f or g pointer array is NULL");
+    fn_batch *B = nullptr;
+    int rc = plan_batch(&B, count, N, M, y, eps, dtype, stream);
+    if (rc)
+        return rc;
+    int rc_exec = exec_batch(B, f, g, stream, false);
+    rc = finish_batch(B, (hipStream_t)stream);
+    release_batch(B);
+    delete B;
+    return rc ? rc : rc_exec;
 }
 
 const char *nufft_last_error(void) { return g_err.c_str(); }

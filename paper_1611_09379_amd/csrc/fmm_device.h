@@ -103,6 +103,36 @@ __device__ __forceinline__ double xlogx_m_x(double u)
     return u == 0.0 ? 0.0 : u * log(fabs(u)) - u;
 }
 
+// Launch of one kernel over several problems: block b of the grid belongs
+// to problem t with start[t] <= b < start[t + 1] and is its local block
+// b - start[t].
+struct BlockMap {
+    const int32_t *start; // T + 1 entries
+    int T;
+};
+
+__device__ __forceinline__ int bm_find(const BlockMap &bm, int b, int *local, int *count)
+{
+    int lo = 0, hi = bm.T; // largest t with start[t] <= b
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (bm.start[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    *local = b - bm.start[lo];
+    *count = bm.start[lo + 1] - bm.start[lo];
+    return lo;
+}
+
+// Input and output of one problem of a batch, read by the batched
+// evaluation launches (so that their arguments stay fixed from call to call).
+struct IoPtr {
+    const void *in;
+    void *out;
+};
+
 // One workgroup's share of the downward pass: a subtree root of level lr,
 // a range of sorted targets and a range of uniform targets.
 struct WorkItem {

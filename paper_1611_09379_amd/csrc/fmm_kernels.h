@@ -195,6 +195,7 @@ struct UpArgs {
     V *S;                    // sum of the weights (cot kernel)
     OpTables<R> T;
     double logc1, logc2;     // log kernel: log(2 pi / N), log 2
+    int32_t io_index;        // batched launches: entry of the IoPtr table
 };
 
 // Inverse: w_j = Dhat_j g_j in sorted order (Eq. p6: the weights of the cot
@@ -386,7 +387,7 @@ __device__ __forceinline__ void m2m_level(const R (&am)[PU / 4], int rt,
 // One launch of the upward pass: 2^d boxes of level lb (the leaves, by P2M,
 // in the first band) up to level lb - d.
 template <typename R, typename V, int KER, int SRC, int PU>
-__global__ void __launch_bounds__(BLOCK) k_up_band(UpArgs<R, V> a)
+__device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     R *buf0 = reinterpret_cast<R *>(smem_raw);
@@ -394,7 +395,7 @@ __global__ void __launch_bounds__(BLOCK) k_up_band(UpArgs<R, V> a)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lb = a.lb, d = a.d;
     const int nbot = 1 << d;
-    const int64_t first = (int64_t)blockIdx.x << d;
+    const int64_t first = (int64_t)blk << d;
     R *buf1 = buf0 + (size_t)nbot * RS;
     if (a.first_band) {
         V *g = a.mp + lev_off(lb, PU);
@@ -482,13 +483,33 @@ __global__ void __launch_bounds__(BLOCK) k_up_band(UpArgs<R, V> a)
     }
 }
 
+template <typename R, typename V, int KER, int SRC, int PU>
+__global__ void __launch_bounds__(BLOCK) k_up_band(UpArgs<R, V> a)
+{
+    up_band_body<R, V, KER, SRC, PU>(a, blockIdx.x);
+}
+
+// The same band of every problem of a batch in one launch.
+// The forward's weights come from the IoPtr table when it is given.
+template <typename R, typename V, int KER, int SRC, int PU>
+__global__ void __launch_bounds__(BLOCK) kb_up_band(const UpArgs<R, V> *aa, BlockMap bm,
+                                                    const IoPtr *io)
+{
+    int blk, nblk;
+    const int t = bm_find(bm, blockIdx.x, &blk, &nblk);
+    UpArgs<R, V> a = aa[t];
+    if (io)
+        a.f_uniform = reinterpret_cast<const cx<R> *>(io[a.io_index].in);
+    up_band_body<R, V, KER, SRC, PU>(a, blk);
+}
+
 // Level 2 (one workgroup): the regular part of Eq. (p20) as the level-2
 // local polynomial of every quarter, from the four level-2 multipoles, and
 // the sum of the weights.  A1 holds the moments of Omega_1(P_n) about the
 // centre of P_n: the three quarters unwrapped around it, (v + 2i)^t expanded
 // for i = -1, 0, +1.
 template <typename R, typename V, int KER>
-__global__ void __launch_bounds__(BLOCK) k_regular(UpArgs<R, V> a, int PU)
+__device__ __forceinline__ void regular_body(const UpArgs<R, V> &a, int PU)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int PD = a.PD;
@@ -547,6 +568,19 @@ __global__ void __launch_bounds__(BLOCK) k_regular(UpArgs<R, V> a, int PU)
     }
 }
 
+template <typename R, typename V, int KER>
+__global__ void __launch_bounds__(BLOCK) k_regular(UpArgs<R, V> a, int PU)
+{
+    regular_body<R, V, KER>(a, PU);
+}
+
+// One workgroup per problem of a batch.
+template <typename R, typename V, int KER>
+__global__ void __launch_bounds__(BLOCK) kb_regular(const UpArgs<R, V> *aa, int PU)
+{
+    regular_body<R, V, KER>(aa[blockIdx.x], PU);
+}
+
 // ------------------------------------------------------------ k_down_eval
 
 template <typename R, typename V>
@@ -582,6 +616,7 @@ struct DownArgs {
     const int *flags;        // setup error flags: sorted-source passes stop
                              // at FLAG_DENSE (their near field would be
                              // quadratic in the leaf size)
+    int32_t io_index;        // batched launches: entry of the IoPtr table
 };
 
 // Register-held operator tiles of one wave (row tile rt of PD rows).
@@ -942,10 +977,8 @@ __device__ __forceinline__ double near_log(const DownArgs<R, V> &a, int64_t tm,
     return acc - near_log_background(tm, tth, leaf, l, N);
 }
 
-// Three waves per SIMD at least (at most 168 VGPRs): the binary64 variants
-// otherwise take up to 252 and run two.
 template <typename R, typename V, int KER, int SRC, int EPI, int PD>
-__global__ void __launch_bounds__(BLOCK, 3) k_down_eval(DownArgs<R, V> a)
+__device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int RS = a.RS;
@@ -954,12 +987,12 @@ __global__ void __launch_bounds__(BLOCK, 3) k_down_eval(DownArgs<R, V> a)
     R *bufB = bufA + (size_t)a.rows_buf * RS;
     R *srcs = bufB + (size_t)a.rows_buf * RS;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if ((int32_t)blockIdx.x >= *a.nwork)
+    if (blk >= *a.nwork)
         return; // the grid is sized for the largest possible work list
     if constexpr (SRC == SET_SORTED)
         if (*a.flags & FLAG_DENSE)
             return; // the plan fails; nothing is evaluated
-    const WorkItem w = a.work[blockIdx.x];
+    const WorkItem w = a.work[blk];
     const int64_t R0 = w.root;
     const int lr = a.lr;
     const int64_t N = a.N;
@@ -1218,6 +1251,32 @@ __global__ void __launch_bounds__(BLOCK, 3) k_down_eval(DownArgs<R, V> a)
             a.logd[t] = -((double)far + nr - a.logself);
         }
     }
+}
+
+// Three waves per SIMD at least (at most 168 VGPRs): the binary64 variants
+// otherwise take up to 252 and run two.
+template <typename R, typename V, int KER, int SRC, int EPI, int PD>
+__global__ void __launch_bounds__(BLOCK, 3) k_down_eval(DownArgs<R, V> a)
+{
+    down_eval_body<R, V, KER, SRC, EPI, PD>(a, blockIdx.x);
+}
+
+// The downward pass of every problem of a batch in one launch.
+// The forward's input and output come from the IoPtr table when it is
+// given.
+template <typename R, typename V, int KER, int SRC, int EPI, int PD>
+__global__ void __launch_bounds__(BLOCK, 3) kb_down_eval(const DownArgs<R, V> *aa,
+                                                         BlockMap bm, const IoPtr *io)
+{
+    int blk, nblk;
+    const int t = bm_find(bm, blockIdx.x, &blk, &nblk);
+    DownArgs<R, V> a = aa[t];
+    if (io) {
+        a.f_uniform = reinterpret_cast<const cx<R> *>(io[a.io_index].in);
+        a.f_hit = a.f_uniform;
+        a.out = reinterpret_cast<cx<R> *>(io[a.io_index].out);
+    }
+    down_eval_body<R, V, KER, SRC, EPI, PD>(a, blk);
 }
 
 } // namespace fn

@@ -55,42 +55,70 @@ __device__ __forceinline__ bool reduce_point(double yy, double c_hi, double c_lo
     return true;
 }
 
+// Arguments of the counting sort of one point set into the leaves (all the
+// passes share them).
+struct SortArgs {
+    int64_t n;              // points
+    const double *y;        // radians
+    double c_hi, c_lo;      // N / (2 pi) in double-double
+    int64_t N;
+    int l, keyshift;        // key = level-(l - keyshift) box
+    double ymax;
+    int64_t chunk;          // points per histogram block
+    int nbins, nblk;        // keys; histogram blocks
+    int32_t *um;            // unsorted grid units and keys
+    double *uth;
+    int32_t *ukey;
+    int32_t *H;             // nblk x nbins block histograms
+    int32_t *tot;           // points per key
+    int32_t *off;           // nbins + 1 offsets
+    int32_t *cursor;        // (atomic path) placement cursors
+    int32_t *sm;            // sorted m, th, perm, key
+    double *sth;
+    int32_t *sperm;
+    int32_t *skey;
+    int32_t *hit;           // (optional) index of a point on x_m, per m
+    int *flags;
+};
+
 // Grid units and sort key (the level-(l - keyshift) box) of every point,
 // one point per thread.  If hit is given, records the index of a point that
 // lies exactly on x_m.
-__global__ void __launch_bounds__(256)
-    k_keys(int64_t n, const double *__restrict__ y, double c_hi, double c_lo, int64_t N,
-           int l, int keyshift, double ymax, int32_t *__restrict__ um,
-           double *__restrict__ uth, int32_t *__restrict__ ukey, int32_t *hit, int *flags)
+__device__ __forceinline__ void keys_body(const SortArgs &a, int blk, int nblk)
 {
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
-         j += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t j = blk * (int64_t)blockDim.x + threadIdx.x; j < a.n;
+         j += (int64_t)nblk * blockDim.x) {
         int64_t m;
         double th;
-        if (!reduce_point(y[j], c_hi, c_lo, N, ymax, &m, &th))
-            atomicOr(flags, FLAG_BAD_Y);
-        um[j] = (int32_t)m;
-        uth[j] = th;
-        ukey[j] = (int32_t)(box_of(m, th, l, N) >> keyshift);
-        if (hit && th == 0.0)
-            atomicExch(&hit[m], (int32_t)j);
+        if (!reduce_point(a.y[j], a.c_hi, a.c_lo, a.N, a.ymax, &m, &th))
+            atomicOr(a.flags, FLAG_BAD_Y);
+        a.um[j] = (int32_t)m;
+        a.uth[j] = th;
+        a.ukey[j] = (int32_t)(box_of(m, th, a.l, a.N) >> a.keyshift);
+        if (a.hit && th == 0.0)
+            atomicExch(&a.hit[m], (int32_t)j);
     }
+}
+
+__global__ void __launch_bounds__(256) k_keys(SortArgs a)
+{
+    keys_body(a, blockIdx.x, gridDim.x);
 }
 
 constexpr int SORT_BATCH = 8; // points in flight per thread in the sort passes
 
 // Counting sort, pass 1: per-block histograms of the keys in LDS.  Block b
 // takes points [b chunk, (b+1) chunk); H is block-major, H[b nbins + key].
-__global__ void __launch_bounds__(256)
-    k_hist(int64_t n, int64_t chunk, int nbins, const int32_t *__restrict__ ukey,
-           int32_t *__restrict__ H)
+__device__ __forceinline__ void hist_body(const SortArgs &a, int blk)
 {
     extern __shared__ int32_t hist[];
+    const int nbins = a.nbins;
     for (int i = threadIdx.x; i < nbins; i += 256)
         hist[i] = 0;
     __syncthreads();
-    const int64_t j0 = (int64_t)blockIdx.x * chunk;
-    const int64_t j1 = j0 + chunk < n ? j0 + chunk : n;
+    const int64_t j0 = (int64_t)blk * a.chunk;
+    const int64_t j1 = j0 + a.chunk < a.n ? j0 + a.chunk : a.n;
+    const int32_t *__restrict__ ukey = a.ukey;
     for (int64_t jb = j0 + threadIdx.x; jb < j1; jb += 256 * SORT_BATCH) {
         int32_t key[SORT_BATCH];
 #pragma unroll
@@ -105,15 +133,19 @@ __global__ void __launch_bounds__(256)
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nbins; i += 256)
-        H[(int64_t)blockIdx.x * nbins + i] = hist[i];
+        a.H[(int64_t)blk * nbins + i] = hist[i];
 }
+
+__global__ void __launch_bounds__(256) k_hist(SortArgs a) { hist_body(a, blockIdx.x); }
 
 // Counting sort, between the passes: for every key, the exclusive prefix of
 // its counts over the blocks (in place in H) and its total (tot[key]).
-__global__ void k_colscan(int nbins, int nblk, int32_t *H, int32_t *tot)
+__device__ __forceinline__ void colscan_body(const SortArgs &a, int blk, int nblocks)
 {
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nbins;
-         k += (int64_t)gridDim.x * blockDim.x) {
+    const int nbins = a.nbins, nblk = a.nblk;
+    int32_t *H = a.H;
+    for (int64_t k = blk * (int64_t)blockDim.x + threadIdx.x; k < nbins;
+         k += (int64_t)nblocks * blockDim.x) {
         int32_t run = 0;
         for (int b0 = 0; b0 < nblk; b0 += SORT_BATCH) {
             int32_t c[SORT_BATCH];
@@ -127,24 +159,24 @@ __global__ void k_colscan(int nbins, int nblk, int32_t *H, int32_t *tot)
                 run += c[u];
             }
         }
-        tot[k] = run;
+        a.tot[k] = run;
     }
 }
+
+__global__ void k_colscan(SortArgs a) { colscan_body(a, blockIdx.x, gridDim.x); }
 
 // Counting sort, pass 2: block b places its points of every key at
 // off[key] + (points of that key in blocks before b) + its LDS counter.
 // off is the exclusive scan of the key totals.
-__global__ void __launch_bounds__(256)
-    k_place(int64_t n, int64_t chunk, int nbins, const int32_t *H, const int32_t *off,
-            const int32_t *um, const double *uth, const int32_t *ukey,
-            int32_t *sm, double *sth, int32_t *sperm, int32_t *skey)
+__device__ __forceinline__ void place_body(const SortArgs &a, int blk)
 {
     extern __shared__ int32_t cur[];
+    const int nbins = a.nbins;
     for (int i = threadIdx.x; i < nbins; i += 256)
-        cur[i] = off[i] + H[(int64_t)blockIdx.x * nbins + i];
+        cur[i] = a.off[i] + a.H[(int64_t)blk * nbins + i];
     __syncthreads();
-    const int64_t j0 = (int64_t)blockIdx.x * chunk;
-    const int64_t j1 = j0 + chunk < n ? j0 + chunk : n;
+    const int64_t j0 = (int64_t)blk * a.chunk;
+    const int64_t j1 = j0 + a.chunk < a.n ? j0 + a.chunk : a.n;
     for (int64_t jb = j0 + threadIdx.x; jb < j1; jb += 256 * SORT_BATCH) {
         int32_t key[SORT_BATCH], mm[SORT_BATCH], pos[SORT_BATCH];
         double tt[SORT_BATCH];
@@ -153,9 +185,9 @@ __global__ void __launch_bounds__(256)
             const int64_t j = jb + u * 256;
             key[u] = -1;
             if (j < j1) {
-                key[u] = ukey[j];
-                mm[u] = um[j];
-                tt[u] = uth[j];
+                key[u] = a.ukey[j];
+                mm[u] = a.um[j];
+                tt[u] = a.uth[j];
             }
         }
 #pragma unroll
@@ -165,14 +197,16 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int u = 0; u < SORT_BATCH; ++u)
             if (key[u] >= 0) {
-                sm[pos[u]] = mm[u];
-                sth[pos[u]] = tt[u];
-                sperm[pos[u]] = (int32_t)(jb + u * 256);
-                if (skey)
-                    skey[pos[u]] = key[u];
+                a.sm[pos[u]] = mm[u];
+                a.sth[pos[u]] = tt[u];
+                a.sperm[pos[u]] = (int32_t)(jb + u * 256);
+                if (a.skey)
+                    a.skey[pos[u]] = key[u];
             }
     }
 }
+
+__global__ void __launch_bounds__(256) k_place(SortArgs a) { place_body(a, blockIdx.x); }
 
 // Counting sort with global atomics, for key ranges too large for LDS:
 // pass 1 counts every key.
@@ -202,9 +236,9 @@ __global__ void k_reduce(int64_t M, const double *__restrict__ y, double c_hi,
 // off[n] = total; cursor (optional) receives a copy of the scan.
 constexpr int SCAN1_PER = 32;
 constexpr int SCAN1_MAX = 1024 * SCAN1_PER;
-__global__ void __launch_bounds__(1024)
-    k_scan_one(const int32_t *__restrict__ count, int n, int32_t *__restrict__ off,
-               int32_t *__restrict__ cursor)
+__device__ __forceinline__ void scan_one_body(const int32_t *__restrict__ count, int n,
+                                              int32_t *__restrict__ off,
+                                              int32_t *__restrict__ cursor)
 {
     __shared__ int32_t part[1024];
     const int i0 = threadIdx.x * SCAN1_PER;
@@ -237,6 +271,12 @@ __global__ void __launch_bounds__(1024)
     }
     if (threadIdx.x == 1023)
         off[n] = part[1023];
+}
+
+__global__ void __launch_bounds__(1024)
+    k_scan_one(const int32_t *count, int n, int32_t *off, int32_t *cursor)
+{
+    scan_one_body(count, n, off, cursor);
 }
 
 // Exclusive scan of the leaf counts in three coalesced steps: sums of tiles
@@ -412,11 +452,26 @@ __global__ void k_rank(int64_t n, const int32_t *gm, const double *gth,
 // of level lr, its sorted targets [off[R << sh], off[(R+1) << sh]) cut into
 // pieces of at most tmax (pieces = 0 for none), or one item carrying both
 // the sorted range and the uniform targets of R when `uniform`.
-__global__ void __launch_bounds__(1024)
-    k_work(int64_t nroot, int sh, const int32_t *off, int uniform, int64_t N,
-           int lr, int32_t tmax, WorkItem *items, int32_t *nitems)
+struct WorkArgs {
+    int64_t nroot;       // subtree roots (2^lr)
+    int sh;              // off indexes level lr + sh
+    const int32_t *off;
+    int uniform;
+    int64_t N;
+    int lr;
+    int32_t tmax;
+    WorkItem *items;
+    int32_t *nitems;
+};
+
+__device__ __forceinline__ void work_body(const WorkArgs &w)
 {
     __shared__ int32_t part[1024];
+    const int64_t nroot = w.nroot, N = w.N;
+    const int sh = w.sh, lr = w.lr, uniform = w.uniform;
+    const int32_t tmax = w.tmax;
+    const int32_t *off = w.off;
+    WorkItem *items = w.items;
     const int tid = threadIdx.x;
     const int64_t per = (nroot + 1023) / 1024;
     const int64_t r0 = tid * per, r1 = r0 + per < nroot ? r0 + per : nroot;
@@ -451,8 +506,10 @@ __global__ void __launch_bounds__(1024)
         }
     }
     if (tid == 1023)
-        *nitems = part[1023];
+        *w.nitems = part[1023];
 }
+
+__global__ void __launch_bounds__(1024) k_work(WorkArgs w) { work_body(w); }
 
 // Eq. (p8), rescaled by 2^N (the scale cancels in C_k D_j):
 //   Chat_k = (-1)^k prod_j 2 sin((x_k - y_j)/2)
@@ -503,5 +560,46 @@ __global__ void k_coeffs(int64_t N, int l, const int32_t *off, const double *log
         dhat[k] = {sg * sinpi(th), sg * cospi(th)};
     }
 }
+
+// ---- the same passes over a batch of point sets: one launch each, block
+// b working for problem bm_find(b) (see BlockMap)
+
+__global__ void __launch_bounds__(256) kb_keys(const SortArgs *aa, BlockMap bm)
+{
+    int blk, nblk;
+    const int t = bm_find(bm, blockIdx.x, &blk, &nblk);
+    keys_body(aa[t], blk, nblk);
+}
+
+__global__ void __launch_bounds__(256) kb_hist(const SortArgs *aa, BlockMap bm)
+{
+    int blk, nblk;
+    const int t = bm_find(bm, blockIdx.x, &blk, &nblk);
+    hist_body(aa[t], blk);
+}
+
+__global__ void __launch_bounds__(256) kb_colscan(const SortArgs *aa, BlockMap bm)
+{
+    int blk, nblk;
+    const int t = bm_find(bm, blockIdx.x, &blk, &nblk);
+    colscan_body(aa[t], blk, nblk);
+}
+
+// one workgroup per problem
+__global__ void __launch_bounds__(1024) kb_scan_one(const SortArgs *aa)
+{
+    const SortArgs &a = aa[blockIdx.x];
+    scan_one_body(a.tot, a.nbins, a.off, a.cursor);
+}
+
+__global__ void __launch_bounds__(256) kb_place(const SortArgs *aa, BlockMap bm)
+{
+    int blk, nblk;
+    const int t = bm_find(bm, blockIdx.x, &blk, &nblk);
+    place_body(aa[t], blk);
+}
+
+// one workgroup per problem
+__global__ void __launch_bounds__(1024) kb_work(const WorkArgs *ww) { work_body(ww[blockIdx.x]); }
 
 } // namespace fn
