@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the clustered-forward and batched figures")
     return ap.parse_args()
 
 
@@ -138,6 +140,68 @@ def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
         "inv_up_ms": float(np.mean(up_i)), "inv_down_ms": float(np.mean(k_i)),
         "info_f": info_f, "info_i": info_i, "g": g, "fo": fo,
     }
+
+
+def run_batched(fn, torch, workloads, steps, warmup):
+    """512 independent forward transforms, N_i log-uniform in [2^8, 2^16],
+    M_i = rint(N_i U(0.5, 2)), uniform y: one-shot batched calls (setup and
+    evaluation) and evaluation-only graph replays of a batch plan, for both
+    precision paths.  Throughput = (sum N_i + sum M_i) / time."""
+    Ns, Ms = workloads.batched_sizes(512, seed=0)
+    ys, fs = [], []
+    for t, (N, M) in enumerate(zip(Ns, Ms)):
+        y, f, c = workloads.forward_case(int(N), int(M), "uniform", seed=t)
+        ys.append(torch.from_numpy(y).cuda())
+        fs.append(torch.from_numpy(f).cuda())
+    pts = int(Ns.sum() + Ms.sum())
+    out = {"transforms": 512, "sum_N": int(Ns.sum()), "sum_M": int(Ms.sum())}
+    for name, dt, eps in (("f64", torch.complex128, 1e-12), ("mixed", torch.complex64, 1e-6)):
+        fx = [f.to(dt) for f in fs]
+        gs = [torch.empty(y.shape[0], dtype=dt, device="cuda") for y in ys]
+        for _ in range(warmup):
+            fn.nufft_fwd_batched(ys, fx, eps, outs=gs)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn.nufft_fwd_batched(ys, fx, eps, outs=gs)
+        torch.cuda.synchronize()
+        one = (time.perf_counter() - t) / steps
+        b = fn.Batch.forward(ys, [int(n) for n in Ns], eps,
+                             fn.FN_C128 if dt == torch.complex128 else fn.FN_C64)
+        for _ in range(warmup):
+            b(fx, gs)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            b(fx, gs)
+        torch.cuda.synchronize()
+        ex = (time.perf_counter() - t) / steps
+        b.destroy()
+        out[name] = {"eps": eps, "one_shot_ms": one * 1e3, "one_shot_points_per_s": pts / one,
+                     "graph_exec_ms": ex * 1e3, "graph_exec_points_per_s": pts / ex}
+    return out
+
+
+def run_clustered(fn, torch, workloads, N, steps, warmup):
+    """Forward transform on clustered targets (wrapped mixture of 8 Gaussians,
+    sigma = 0.01), N = M, one-shot, both precision paths."""
+    y, f, c = workloads.forward_case(N, N, "clustered", seed=0)
+    yd = torch.from_numpy(y).cuda()
+    f64 = torch.from_numpy(f).cuda()
+    out = {"N": N, "M": N}
+    for name, dt, eps in (("f64", torch.complex128, 1e-12), ("mixed", torch.complex64, 1e-6)):
+        fx = f64.to(dt)
+        g = torch.empty(N, dtype=dt, device="cuda")
+        for _ in range(warmup):
+            fn.nufft_fwd(yd, fx, eps, out=g)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn.nufft_fwd(yd, fx, eps, out=g)
+        torch.cuda.synchronize()
+        dtm = (time.perf_counter() - t) / steps
+        out[name] = {"eps": eps, "ms": dtm * 1e3, "points_per_s": 2 * N / dtm}
+    return out
 
 
 def cpu_baseline(N, M, yu, f, yj, seconds):
@@ -271,6 +335,10 @@ def main():
             ref = oracle.fwd_at(N, yu_h, f32.cpu().numpy().astype(np.complex128), sel)
             mixed["fwd_rel_l2_vs_oracle_64"] = float(np.linalg.norm(gm[sel] - ref) / np.linalg.norm(ref))
         out["mixed"] = mixed
+    if not args.no_extra:
+        out["forward_clustered"] = run_clustered(fn, torch, workloads, N, args.steps,
+                                                 args.warmup)
+        out["batched_512"] = run_batched(fn, torch, workloads, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, M, yu_h, f_h, yj_h, args.cpu_seconds)
     print(json.dumps(out), flush=True)
