@@ -83,7 +83,34 @@ void pool_put(void *p, size_t bytes)
 struct Buf {
     void *p = nullptr;
     size_t n = 0;
+    bool arena = false; // carved from an Arena chunk (not returned alone)
 };
+
+// Bump allocation from large pooled chunks, for the many small workspaces
+// of a batch of transforms; the chunks go back to the pool with the batch.
+struct Arena {
+    std::vector<Buf> chunks;
+    size_t used = 0; // bytes used in the last chunk
+};
+thread_local Arena *g_arena = nullptr;
+constexpr size_t ARENA_CHUNK = size_t(64) << 20;
+
+void *arena_get(Arena &A, size_t bytes)
+{
+    bytes = round_bytes(bytes ? bytes : 1);
+    if (A.chunks.empty() || A.used + bytes > A.chunks.back().n) {
+        Buf c;
+        c.n = std::max(ARENA_CHUNK, bytes);
+        c.p = pool_get(c.n);
+        if (!c.p)
+            return nullptr;
+        A.chunks.push_back(c);
+        A.used = 0;
+    }
+    void *p = (unsigned char *)A.chunks.back().p + A.used;
+    A.used += bytes;
+    return p;
+}
 } // namespace
 
 // ------------------------------------------------- parameters (Section 2.3)
@@ -337,15 +364,16 @@ struct fn_plan {
 static bool alloc(Buf &b, size_t bytes)
 {
     b.n = bytes;
-    b.p = pool_get(bytes);
+    b.arena = g_arena != nullptr;
+    b.p = b.arena ? arena_get(*g_arena, bytes) : pool_get(bytes);
     return b.p != nullptr;
 }
 
 static void release(Buf &b)
 {
-    pool_put(b.p, b.n);
-    b.p = nullptr;
-    b.n = 0;
+    if (!b.arena)
+        pool_put(b.p, b.n);
+    b = Buf{};
 }
 
 static void release_tmp(fn_plan *P)
@@ -374,14 +402,25 @@ static void *tmp_alloc(fn_plan *P, size_t bytes)
 
 static int round16(int x) { return std::min(64, std::max(16, (x + 15) & ~15)); }
 
+// LDS per workgroup of the current device (cached per device).
 static size_t lds_limit()
 {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
-        v <= 0)
+    static std::mutex mu;
+    static std::map<int, size_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
         return 64 * 1024;
-    return (size_t)v;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end())
+        return it->second;
+    int v = 0;
+    size_t r = 64 * 1024;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        v > 0)
+        r = (size_t)v;
+    cache[dev] = r;
+    return r;
 }
 
 // LDS row stride: nc * P elements of size es, padded so that a row's start
@@ -1119,6 +1158,7 @@ struct LaunchShape {
 };
 
 struct fn_batch {
+    Arena arena; // every workspace of the batch's plans
     int T = 0, dtype = 0;
     double eps = 0;
     std::vector<fn_plan *> P;
@@ -1170,6 +1210,9 @@ static void release_batch(fn_batch *B)
     release(B->blob);
     release(B->io);
     release(B->flags);
+    for (Buf &c : B->arena.chunks)
+        release(c);
+    B->arena.chunks.clear();
     if (B->gexec)
         (void)hipGraphExecDestroy(B->gexec);
     if (B->ev_in)
@@ -1403,8 +1446,10 @@ static int plan_batch(fn_batch **out, int32_t count, const int64_t *Ns, const in
     B->eps = eps;
     hipStream_t st = (hipStream_t)stream;
     B->stream = st;
+    g_arena = &B->arena;
     int rc = dtype == FN_C128 ? plan_batch_impl<double>(B, Ns, Ms, ys, st)
                               : plan_batch_impl<float>(B, Ns, Ms, ys, st);
+    g_arena = nullptr;
     if (rc) {
         (void)hipStreamSynchronize(st);
         release_batch(B);
