@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the clustered-forward and batched figures")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain elementwise kernel that reads and "
+                         "writes 256 MiB (known byte counts for scaling "
+                         "memory-traffic counters)")
     return ap.parse_args()
 
 
@@ -256,6 +260,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     fn.load_library()
+    if args.calibrate_copy:
+        # a plain elementwise kernel: reads 256 MiB, writes 256 MiB
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     N = M = 1 << args.log2n
     yu_h, f_h, c_h = workloads.forward_case(N, M, "uniform", seed=0)
     yj_h, cj_h = workloads.inverse_case(N, 0.4, seed=1)

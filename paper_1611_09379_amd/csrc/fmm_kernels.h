@@ -1253,10 +1253,8 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
     }
 }
 
-// Three waves per SIMD at least (at most 168 VGPRs): the binary64 variants
-// otherwise take up to 252 and run two.
 template <typename R, typename V, int KER, int SRC, int EPI, int PD>
-__global__ void __launch_bounds__(BLOCK, 3) k_down_eval(DownArgs<R, V> a)
+__global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
 {
     down_eval_body<R, V, KER, SRC, EPI, PD>(a, blockIdx.x);
 }
@@ -1265,8 +1263,8 @@ __global__ void __launch_bounds__(BLOCK, 3) k_down_eval(DownArgs<R, V> a)
 // The forward's input and output come from the IoPtr table when it is
 // given.
 template <typename R, typename V, int KER, int SRC, int EPI, int PD>
-__global__ void __launch_bounds__(BLOCK, 3) kb_down_eval(const DownArgs<R, V> *aa,
-                                                         BlockMap bm, const IoPtr *io)
+__global__ void __launch_bounds__(BLOCK) kb_down_eval(const DownArgs<R, V> *aa,
+                                                      BlockMap bm, const IoPtr *io)
 {
     int blk, nblk;
     const int t = bm_find(bm, blockIdx.x, &blk, &nblk);
