@@ -344,6 +344,7 @@ struct fn_plan {
     // points sorted into the leaves (targets of the forward, sources of the
     // inverse)
     Buf off, sm, sth, sperm, skey;
+    Buf spt; // forward: sorted target records (instead of sm, sth, sperm, skey)
     Buf work, nwork_dev;
     int nwork = 0;  // grid of k_down_eval: the largest possible work list
     FmmSetup cot;
@@ -356,7 +357,7 @@ struct fn_plan {
     hipStream_t stream = nullptr; // stream of the last call
     std::vector<Buf *> all()
     {
-        return {&off, &sm, &sth, &sperm, &skey, &work, &nwork_dev, &cot.mp, &cot.loc2,
+        return {&off, &sm, &sth, &sperm, &skey, &spt, &work, &nwork_dev, &cot.mp, &cot.loc2,
                 &cot.S, &hit, &chat, &dhat, &wsorted, &flags};
     }
 };
@@ -658,7 +659,7 @@ struct TreeJob {
 };
 
 static int prepare_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
-                        bool deterministic, bool want_hit, TreeJob *J)
+                        bool deterministic, bool want_hit, bool records, TreeJob *J)
 {
     const int nbins = 1 << (P->l - keyshift);
     J->deterministic = deterministic;
@@ -687,12 +688,16 @@ static int prepare_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
         J->gth = (double *)tmp_alloc(P, n * 8);
         J->gperm = (int32_t *)tmp_alloc(P, n * 4);
     }
-    // every point's leaf, kept with the plan (k_rank only reorders inside a
-    // leaf, so it holds for the final order too)
+    // sorted points: (m, perm, th) records, or separate arrays plus every
+    // point's leaf (k_rank only reorders inside a leaf, so the leaves hold
+    // for the final order too)
+    const bool sorted_ok =
+        records ? alloc(P->spt, n * sizeof(SortedPt))
+                : (alloc(P->skey, n * 4) && alloc(P->sm, n * 4) && alloc(P->sth, n * 8) &&
+                   alloc(P->sperm, n * 4));
     if (!a.um || !a.uth || !a.ukey || (lds_path && !a.H) || !a.tot || !J->tsum ||
         (!lds_path && !a.cursor) || (deterministic && (!J->gm || !J->gth || !J->gperm)) ||
-        !alloc(P->skey, n * 4) || !alloc(P->off, ((size_t)nbins + 1) * 4) ||
-        !alloc(P->sm, n * 4) || !alloc(P->sth, n * 8) || !alloc(P->sperm, n * 4) ||
+        !sorted_ok || !alloc(P->off, ((size_t)nbins + 1) * 4) ||
         (want_hit && !alloc(P->hit, P->N * 4)))
         return fail(FN_ENOMEM, "workspace allocation failed (%lld points)", (long long)n);
     if ((nbins + SCAN_TILE - 1) / SCAN_TILE > 4096)
@@ -702,6 +707,7 @@ static int prepare_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
     a.sth = deterministic ? J->gth : (double *)P->sth.p;
     a.sperm = deterministic ? J->gperm : (int32_t *)P->sperm.p;
     a.skey = (int32_t *)P->skey.p;
+    a.spt = (SortedPt *)P->spt.p;
     a.hit = want_hit ? (int32_t *)P->hit.p : nullptr;
     a.flags = (int *)P->flags.p;
     return FN_OK;
@@ -748,7 +754,8 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
     } else {
         hipLaunchKernelGGL(k_scatter, dim3(grid_for(a.n)), dim3(256), 0, st, a.n,
                            (const int32_t *)a.um, (const double *)a.uth,
-                           (const int32_t *)a.ukey, a.cursor, a.sm, a.sth, a.sperm, a.skey);
+                           (const int32_t *)a.ukey, a.cursor, a.sm, a.sth, a.sperm, a.skey,
+                           a.spt);
     }
     HIPCHK(hipGetLastError());
     if (J.deterministic) {
@@ -768,10 +775,10 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
 // inside a key is arbitrary (forward).  Fills the hit map when asked.
 // Enqueues only; errors land in P->flags.
 static int build_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
-                      bool deterministic, bool want_hit, hipStream_t st)
+                      bool deterministic, bool want_hit, bool records, hipStream_t st)
 {
     TreeJob J;
-    int rc = prepare_tree(P, n, y, keyshift, deterministic, want_hit, &J);
+    int rc = prepare_tree(P, n, y, keyshift, deterministic, want_hit, records, &J);
     if (rc)
         return rc;
     return launch_tree(P, J, st);
@@ -862,7 +869,7 @@ static int plan_fwd_impl(fn_plan *P, const double *y, hipStream_t st)
     P->lr = choose_lr(P->l, 2, PD, sizeof(R));
     // targets grouped by leaf: the lanes of a wavefront then share the
     // leaf locals and near-field sources they read
-    int rc = build_tree(P, P->M, y, 0, false, false, st);
+    int rc = build_tree(P, P->M, y, 0, false, false, true, st);
     if (rc)
         return rc;
     rc = build_work(P, P->l - P->lr, false, P->M, st);
@@ -901,9 +908,7 @@ static int exec_fwd(fn_plan *P, const void *in, void *out, int phase,
     DownArgs<R, V> da{};
     fill_down(P, F, T, da);
     da.f_uniform = (const cx<R> *)in;
-    da.tgt = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
-              (const double *)P->sth.p, (const int32_t *)P->sperm.p};
-    da.tgt_leaf = (const int32_t *)P->skey.p;
+    da.tgt_pt = (const SortedPt *)P->spt.p;
     da.out = (cx<R> *)out;
     da.f_hit = (const cx<R> *)in;
     return launch_down<R, V, KER_COT, SET_UNIFORM, EPI_FWD>(P, F, da, st);
@@ -979,7 +984,7 @@ static int plan_inv_impl(fn_plan *P, const double *y, hipStream_t st)
     // one subtree level serves the log FMM (binary64, real, at most 64
     // terms) and the cot FMM
     P->lr = std::max(choose_lr(P->l, 2, PD, sizeof(R)), choose_lr(P->l, 1, 64, 8));
-    int rc = build_tree(P, P->N, y, 0, true, true, st);
+    int rc = build_tree(P, P->N, y, 0, true, true, false, st);
     if (rc)
         return rc;
     rc = build_work(P, P->l - P->lr, true, P->N, st);
@@ -1254,7 +1259,7 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
         int PU, PD;
         cot_lengths(P, &PU, &PD);
         P->lr = choose_lr(P->l, 2, PD, sizeof(R));
-        int rc = prepare_tree(P, P->M, ys[t], 0, false, false, &jobs[t]);
+        int rc = prepare_tree(P, P->M, ys[t], 0, false, false, true, &jobs[t]);
         if (!rc)
             rc = prepare_work(P, P->l - P->lr, false, P->M, &works[t]);
         if (!rc)
@@ -1339,9 +1344,7 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
             B->reg_smem = std::max(B->reg_smem, F.reg_smem);
             DownArgs<R, V> d{};
             fill_down(P, F, Tb, d);
-            d.tgt = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
-                     (const double *)P->sth.p, (const int32_t *)P->sperm.p};
-            d.tgt_leaf = (const int32_t *)P->skey.p;
+            d.tgt_pt = (const SortedPt *)P->spt.p;
             d.io_index = t;
             da.push_back(d);
             nb_down.push_back(P->nwork);

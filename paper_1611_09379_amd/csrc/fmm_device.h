@@ -39,17 +39,31 @@ __host__ __device__ __forceinline__ int64_t lev_off(int L, int P)
     return ((int64_t(1) << L) - 4) * (int64_t)P;
 }
 
-// floor((m + th) 2^L / N): the level-L box of the point s = m + th.
-__device__ __forceinline__ int64_t box_of(int64_t m, double th, int L,
-                                          int64_t N)
+// floor((m + th) 2^L / N), clamped to [0, 2^L): the level-L box of the
+// point s = m + th (0 <= m <= N, |th| <= 1/2).  A binary64 estimate, off by
+// at most one, is corrected by exact comparisons: b N - m 2^L is an exact
+// integer (below 2^53) and th 2^L an exact binary64 value.  The sort and
+// the evaluation both use this function, so they always agree.
+__device__ __forceinline__ int64_t box_of(int64_t m, double th, int L, int64_t N)
 {
-    int64_t A = m << L;
-    int64_t q0 = A / N;
-    double t = (double)(A - q0 * N) + ldexp(th, L);
-    q0 += (int64_t)floor(t / (double)N);
-    int64_t nb = int64_t(1) << L;
-    return q0 < 0 ? 0 : (q0 >= nb ? nb - 1 : q0);
+    const int64_t A = m << L;
+    const double tl = ldexp(th, L);
+    int64_t b = (int64_t)floor(((double)A + tl) / (double)N);
+    // s >= b N / 2^L  <=>  b N - A <= tl
+    if ((double)(b * N - A) > tl)
+        --b;
+    else if ((double)((b + 1) * N - A) <= tl)
+        ++b;
+    const int64_t nb = int64_t(1) << L;
+    return b < 0 ? 0 : (b >= nb ? nb - 1 : b);
 }
+
+// A sorted target of the forward transform: grid units and input index.
+struct alignas(16) SortedPt {
+    int32_t m;
+    int32_t perm;
+    double th;
+};
 
 // (s - c) / r for the point s = m + th and box b of level L.
 __device__ __forceinline__ double rel_coord(int64_t m, double th, int64_t b,

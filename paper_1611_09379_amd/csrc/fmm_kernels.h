@@ -603,7 +603,8 @@ struct DownArgs {
     const cx<R> *w_sorted;
     // targets
     SortedSet tgt;
-    const int32_t *tgt_leaf; // leaf of every sorted target (FWD, LOGCD)
+    const int32_t *tgt_leaf; // LOGCD: leaf of every sorted target
+    const SortedPt *tgt_pt;  // FWD: sorted targets
     // epilogues
     cx<R> *out;              // FWD: g (input order); INV: f
     const V *S;              // sum of the weights
@@ -1178,14 +1179,15 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
         const V S = *a.S;
         const double hscale = (double)N / 3.14159265358979323846;
         for (int32_t t = w.t0 + tid; t < w.t1; t += BLOCK) {
-            const int64_t tm = a.tgt.m[t];
-            const double th = a.tgt.th[t];
-            const int32_t j = a.tgt.perm[t];
+            const SortedPt pt = a.tgt_pt[t];
+            const int64_t tm = pt.m;
+            const double th = pt.th;
+            const int32_t j = pt.perm;
             if (th == 0.0) { // exact hit: K_jk is the Kronecker delta
                 a.out[j] = a.f_hit[tm == N ? 0 : tm];
                 continue;
             }
-            const int64_t leaf = a.tgt_leaf[t];
+            const int64_t leaf = box_of(tm, th, a.l, N);
             const R u = (R)rel_coord_r(tm, th, leaf, a.l, N, invN);
             V h = horner<R, V>(leafloc, RS, (int)(leaf - leaf0), PD, u);
             cx<R> nr = near_cot<R, V, SRC>(a, tm, th, leaf, fsp, K0);

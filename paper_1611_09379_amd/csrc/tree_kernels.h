@@ -77,6 +77,8 @@ struct SortArgs {
     double *sth;
     int32_t *sperm;
     int32_t *skey;
+    SortedPt *spt;          // if set: sorted (m, perm, th) records instead
+                            // of sm, sth, sperm, skey (forward targets)
     int32_t *hit;           // (optional) index of a point on x_m, per m
     int *flags;
 };
@@ -194,15 +196,22 @@ __device__ __forceinline__ void place_body(const SortArgs &a, int blk)
         for (int u = 0; u < SORT_BATCH; ++u)
             if (key[u] >= 0)
                 pos[u] = atomicAdd(&cur[key[u]], 1);
+        if (a.spt) {
 #pragma unroll
-        for (int u = 0; u < SORT_BATCH; ++u)
-            if (key[u] >= 0) {
-                a.sm[pos[u]] = mm[u];
-                a.sth[pos[u]] = tt[u];
-                a.sperm[pos[u]] = (int32_t)(jb + u * 256);
-                if (a.skey)
-                    a.skey[pos[u]] = key[u];
-            }
+            for (int u = 0; u < SORT_BATCH; ++u)
+                if (key[u] >= 0)
+                    a.spt[pos[u]] = {mm[u], (int32_t)(jb + u * 256), tt[u]};
+        } else {
+#pragma unroll
+            for (int u = 0; u < SORT_BATCH; ++u)
+                if (key[u] >= 0) {
+                    a.sm[pos[u]] = mm[u];
+                    a.sth[pos[u]] = tt[u];
+                    a.sperm[pos[u]] = (int32_t)(jb + u * 256);
+                    if (a.skey)
+                        a.skey[pos[u]] = key[u];
+                }
+        }
     }
 }
 
@@ -378,12 +387,16 @@ __global__ void __launch_bounds__(256)
 // order inside a leaf is arbitrary (the forward results do not depend on it).
 __global__ void k_scatter(int64_t M, const int32_t *um, const double *uth,
                           const int32_t *ukey, int32_t *cursor, int32_t *sm,
-                          double *sth, int32_t *sperm, int32_t *skey)
+                          double *sth, int32_t *sperm, int32_t *skey, SortedPt *spt)
 {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < M;
          j += (int64_t)gridDim.x * blockDim.x) {
         int32_t key = ukey[j];
         int32_t pos = atomicAdd(&cursor[key], 1);
+        if (spt) {
+            spt[pos] = {um[j], (int32_t)j, uth[j]};
+            continue;
+        }
         sm[pos] = um[j];
         sth[pos] = uth[j];
         sperm[pos] = (int32_t)j;
