@@ -191,6 +191,26 @@ int nufft_execute_batched(fn_batch *batch, const void *const *f, void *const *g,
 /* Releases a batch plan (NULL accepted).  Synchronises its streams. */
 int nufft_destroy_batched(fn_batch *batch);
 
+/* ---- Autotuner --------------------------------------------------------
+ *
+ * Measures transforms of kind (0 forward, 1 inverse; M is ignored for the
+ * inverse) and sizes N, M at accuracy eps on a synthetic problem of that
+ * size (uniform targets, or a jittered grid for the inverse), generated on
+ * the device: first the shortest local expansion (16, 32 or 48 terms) whose
+ * result stays within eps/4 of the 64-term result, then the fastest tree
+ * depth among round(log2 sqrt(N M)) - 4 .. - 7 for one-shot calls.  Plans
+ * (and batches) created afterwards in this process for the same kind,
+ * dtype, size class round(log2 sqrt(N M)) and accuracy class
+ * floor(-log10 eps) use the recorded values unless given explicitly.
+ * lmax, nterms (may be NULL) receive the choice (nterms 0: the default
+ * length was kept).  Synchronises the stream; allocates and frees device
+ * memory. */
+int nufft_autotune(int kind, int64_t N, int64_t M, double eps, int dtype, int32_t *lmax,
+                   int32_t *nterms, void *stream);
+
+/* Forgets every recorded choice of nufft_autotune. */
+int nufft_autotune_clear(void);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *nufft_last_error(void);
 

@@ -32,7 +32,8 @@ ABI_SYMBOLS = (
     "nufft_execute_phase",
     "nufft_destroy", "nufft_plan_get_info", "nufft_select_params",
     "nufft_fwd_batched", "nufft_plan_fwd_batched", "nufft_execute_batched",
-    "nufft_destroy_batched", "nufft_last_error",
+    "nufft_destroy_batched", "nufft_autotune", "nufft_autotune_clear",
+    "nufft_last_error",
 )
 
 
@@ -62,6 +63,11 @@ def load_library(path: str = LIB_PATH):
         raise RuntimeError(
             f"{path} is missing: build it first "
             "(python -m paper_1611_09379_amd.build); there is no fallback path")
+    # PyTorch ships its own HIP runtime under the same soname: import it
+    # first, so that the library binds to the runtime that owns the tensors
+    # and streams (loaded the other way round, the two stacks mix and the
+    # runtime finds no device)
+    _torch()
     lib = ctypes.CDLL(path)
     i64, i32, dbl, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
     pp = ctypes.POINTER(ctypes.c_void_p)
@@ -82,6 +88,8 @@ def load_library(path: str = LIB_PATH):
         "nufft_plan_fwd_batched": [pp, i32, vp, vp, vp, dbl, ctypes.c_int, vp],
         "nufft_execute_batched": [vp, vp, vp, vp],
         "nufft_destroy_batched": [vp],
+        "nufft_autotune": [ctypes.c_int, i64, i64, dbl, ctypes.c_int, pi32, pi32, vp],
+        "nufft_autotune_clear": [],
         "nufft_last_error": [],
     }
     for name, args in sig.items():
@@ -322,3 +330,19 @@ class Batch:
             self.destroy()
         except Exception:
             pass
+
+
+def autotune(kind: str, N: int, M: int, eps: float, dtype: int = FN_C128):
+    """Runs the library's autotuner for forward ("fwd") or inverse ("inv")
+    transforms of sizes N, M; later plans of that size class use its
+    choice.  Returns (lmax, nterms) (nterms 0: default length kept)."""
+    l = ctypes.c_int32()
+    p = ctypes.c_int32()
+    _check(load_library().nufft_autotune(0 if kind == "fwd" else 1, N, M, eps, dtype,
+                                         ctypes.byref(l), ctypes.byref(p), _stream()))
+    return l.value, p.value
+
+
+def autotune_clear():
+    """Forgets every choice recorded by autotune."""
+    _check(load_library().nufft_autotune_clear())

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -50,6 +51,7 @@ static int fail(int status, const char *fmt, ...)
 
 namespace {
 std::mutex g_pool_mu;
+thread_local hipError_t g_alloc_err = hipSuccess; // last failed hipMalloc
 std::multimap<size_t, void *> g_pool;
 
 size_t round_bytes(size_t n) { return (n + 255) & ~size_t(255); }
@@ -67,8 +69,11 @@ void *pool_get(size_t bytes)
         }
     }
     void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess)
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        g_alloc_err = e;
         return nullptr;
+    }
     return p;
 }
 
@@ -1064,14 +1069,44 @@ static int check_common(int64_t N, int64_t M, double eps, int dtype)
 }
 
 // Parameters of a plan of the given kind (-1: the paper's depth rule).
-static void choose(int64_t N, int64_t M, double eps, int kind, int32_t p_in,
-                   int32_t q_in, int32_t l_in, int *p, int *q, int *l)
+// Depth and expansion length recorded by nufft_autotune, per (kind,
+// dtype, size class lg = round(log2 sqrt(N M)), accuracy class
+// floor(-log10 eps)).
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tuned;
+
+static std::tuple<int, int, int, int> tune_key(int kind, int dtype, int64_t N, int64_t M,
+                                               double eps)
 {
-    *l = l_in > 0 ? l_in : (kind < 0 ? paper_depth(N, M) : default_depth(N, M, kind));
+    const int lg = (int)std::lround(0.5 * std::log2((double)N * (double)M));
+    const int ec = (int)std::floor(-std::log10(eps) + 1e-9);
+    return std::make_tuple(kind, dtype, lg, ec);
+}
+
+// Parameters of a plan of the given kind (-1: the paper's depth rule).
+// Values not given explicitly come from the autotuner's record when there
+// is one (the expansion length then counts as given), else from the
+// defaults.
+static void choose(int64_t N, int64_t M, double eps, int kind, int dtype, int32_t p_in,
+                   int32_t q_in, int32_t l_in, int *p, int *q, int *l, bool *p_given)
+{
+    int tl = 0, tp = 0;
+    if (kind >= 0 && (l_in <= 0 || p_in <= 0)) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(tune_key(kind, dtype, N, M, eps));
+        if (it != g_tuned.end()) {
+            tl = it->second.first;
+            tp = it->second.second;
+        }
+    }
+    *l = l_in > 0 ? l_in
+                  : (tl > 0 ? tl : (kind < 0 ? paper_depth(N, M) : default_depth(N, M, kind)));
     int pp, qq;
     trunc_numbers(eps, *l, &pp, &qq);
-    *p = p_in > 0 ? p_in : pp;
+    *p = p_in > 0 ? p_in : (tp > 0 ? tp : pp);
     *q = q_in > 0 ? q_in : qq;
+    if (p_given)
+        *p_given = p_in > 0 || tp > 0;
 }
 
 // Creates a plan.  Unless `defer`, waits for the setup kernels and reports
@@ -1097,8 +1132,7 @@ static int plan_common(fn_plan **out, int kind, int64_t N, int64_t M,
     P->N = N;
     P->M = M;
     P->eps = eps;
-    choose(N, M, eps, kind, p_in, q_in, l_in, &P->p, &P->q, &P->l);
-    P->p_explicit = p_in > 0;
+    choose(N, M, eps, kind, dtype, p_in, q_in, l_in, &P->p, &P->q, &P->l, &P->p_explicit);
     if (P->p > 64 || 2 * P->q > 64) {
         const int p = P->p, q = P->q;
         delete P;
@@ -1108,7 +1142,7 @@ static int plan_common(fn_plan **out, int kind, int64_t N, int64_t M,
     P->stream = st;
     if (!alloc(P->flags, 4)) {
         delete P;
-        return fail(FN_ENOMEM, "flag allocation failed");
+        return fail(FN_ENOMEM, "flag allocation failed (%s)", hipGetErrorString(g_alloc_err));
     }
     if (hipMemsetAsync(P->flags.p, 0, 4, st) != hipSuccess) {
         release_plan(P);
@@ -1252,7 +1286,7 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
         P->M = Ms[t];
         P->eps = B->eps;
         P->stream = st;
-        choose(P->N, P->M, P->eps, 0, 0, 0, 0, &P->p, &P->q, &P->l);
+        choose(P->N, P->M, P->eps, 0, P->dtype, 0, 0, 0, &P->p, &P->q, &P->l, &P->p_explicit);
         if (P->p > 64 || 2 * P->q > 64)
             return fail(FN_EINVAL, "transform %d: truncation numbers need more than 64 terms", t);
         P->flags.p = (int *)B->flags.p + t;
@@ -1556,6 +1590,144 @@ static int exec_batch(fn_batch *B, const void *const *f, void *const *g, void *s
                                : exec_batch_impl<float>(B, f, g, st, graph);
 }
 
+// ------------------------------------------------------------ autotuner
+//
+// For one kind, size and accuracy, on a synthetic problem of that size
+// (uniform targets for the forward, a jittered grid for the inverse):
+//   1. the shortest expansion length (16, 32, 48) whose output stays within
+//      eps / 4 (relative l2) of the output with 64 terms, at the default
+//      depth; else the default length;
+//   2. the fastest depth among lg - 4 .. lg - 7 (lg = round(log2 sqrt(N M)))
+//      for one-shot transforms with that length (median of three).
+// The result is recorded for later plans of that kind, dtype, size class
+// and accuracy class.
+
+static int execute(fn_plan *plan, const void *in, void *out, int phase, void *stream);
+
+// One-shot transform with explicit parameters; returns the wall time.
+static int tune_run(int kind, int64_t N, int64_t M, const double *y, const void *in,
+                    void *out, double eps, int dtype, int p, int l, hipStream_t st,
+                    double *secs)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    fn_plan *P = nullptr;
+    int rc = plan_common(&P, kind, N, M, y, eps, dtype, p, 0, l, st, true);
+    if (rc)
+        return rc;
+    rc = finish_one_shot(P, execute(P, in, out, -1, st));
+    *secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+static int tune_err(int64_t n, const void *a, const void *b, int dtype, Buf &part,
+                    hipStream_t st, double *err)
+{
+    const int nb = 256;
+    if (dtype == FN_C128)
+        hipLaunchKernelGGL(k_diff2<double>, dim3(nb), dim3(256), 0, st, n,
+                           (const cx<double> *)a, (const cx<double> *)b, (double *)part.p);
+    else
+        hipLaunchKernelGGL(k_diff2<float>, dim3(nb), dim3(256), 0, st, n,
+                           (const cx<float> *)a, (const cx<float> *)b, (double *)part.p);
+    HIPCHK(hipGetLastError());
+    std::vector<double> h(2 * nb);
+    HIPCHK(hipMemcpyAsync(h.data(), part.p, h.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double d = 0, r = 0;
+    for (int i = 0; i < nb; ++i) {
+        d += h[2 * i];
+        r += h[2 * i + 1];
+    }
+    *err = r > 0 ? std::sqrt(d / r) : std::sqrt(d);
+    return FN_OK;
+}
+
+static int autotune(int kind, int64_t N, int64_t M, double eps, int dtype, int32_t *l_out,
+                    int32_t *p_out, hipStream_t st)
+{
+    if (kind != 0 && kind != 1)
+        return fail(FN_EINVAL, "kind must be 0 (forward) or 1 (inverse)");
+    if (kind == 1)
+        M = N;
+    int rc = check_common(N, M, eps, dtype);
+    if (rc)
+        return rc;
+    const size_t es = dtype == FN_C128 ? 16 : 8;
+    const int64_t nin = N, nout = kind == 0 ? M : N;
+    Buf y, in, out, ref, part;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);
+        for (Buf *b : {&y, &in, &out, &ref, &part})
+            release(*b);
+    };
+    if (!alloc(y, (size_t)M * 8) || !alloc(in, nin * es) || !alloc(out, nout * es) ||
+        !alloc(ref, nout * es) || !alloc(part, 512 * 8)) {
+        cleanup();
+        return fail(FN_ENOMEM, "autotuner allocation failed");
+    }
+    const uint64_t seed = 0x5eed0f0e11ull;
+    hipLaunchKernelGGL(k_synth_points, dim3(grid_for(M)), dim3(256), 0, st, M, N,
+                       kind == 1 ? 0.8 : 0.0, seed, (double *)y.p);
+    if (dtype == FN_C128)
+        hipLaunchKernelGGL(k_synth_data<double>, dim3(grid_for(nin)), dim3(256), 0, st, nin,
+                           seed + 1, (cx<double> *)in.p);
+    else
+        hipLaunchKernelGGL(k_synth_data<float>, dim3(grid_for(nin)), dim3(256), 0, st, nin,
+                           seed + 1, (cx<float> *)in.p);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu); // measure without an old record
+        g_tuned.erase(tune_key(kind, dtype, N, M, eps));
+    }
+    const int l0 = default_depth(N, M, kind);
+    double secs = 0, err = 0;
+    rc = tune_run(kind, N, M, (const double *)y.p, in.p, ref.p, eps, dtype, 64, l0, st, &secs);
+    int pbest = 0;
+    for (int pc = 16; !rc && pc <= 48; pc += 16) {
+        rc = tune_run(kind, N, M, (const double *)y.p, in.p, out.p, eps, dtype, pc, l0, st,
+                      &secs);
+        if (!rc)
+            rc = tune_err(nout, out.p, ref.p, dtype, part, st, &err);
+        if (!rc && err <= 0.25 * eps) {
+            pbest = pc;
+            break;
+        }
+    }
+    const int lg = (int)std::lround(0.5 * std::log2((double)N * (double)M));
+    int lbest = l0;
+    double tbest = 1e300;
+    for (int off = 4; !rc && off <= 7; ++off) {
+        const int l = std::min(24, std::max(2, lg - off));
+        if (off > 4 && l == std::min(24, std::max(2, lg - off + 1)))
+            continue;
+        std::vector<double> ts;
+        for (int r = 0; !rc && r < 4; ++r) {
+            rc = tune_run(kind, N, M, (const double *)y.p, in.p, out.p, eps, dtype, pbest, l,
+                          st, &secs);
+            if (r > 0)
+                ts.push_back(secs); // the first run warms the caches
+        }
+        if (rc)
+            break;
+        std::sort(ts.begin(), ts.end());
+        if (ts[1] < tbest) {
+            tbest = ts[1];
+            lbest = l;
+        }
+    }
+    cleanup();
+    if (rc)
+        return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[tune_key(kind, dtype, N, M, eps)] = {lbest, pbest};
+    }
+    if (l_out)
+        *l_out = lbest;
+    if (p_out)
+        *p_out = pbest;
+    return FN_OK;
+}
+
 extern "C" {
 
 int nufft_plan_fwd_ex(fn_plan **plan, int64_t N, int64_t M, const double *y,
@@ -1649,7 +1821,7 @@ int nufft_select_params(int64_t N, int64_t M, double eps, int dtype, int32_t *p,
     if (rc)
         return rc;
     int pp, qq, ll;
-    choose(N, M, eps, -1, 0, 0, 0, &pp, &qq, &ll);
+    choose(N, M, eps, -1, dtype, 0, 0, 0, &pp, &qq, &ll, nullptr);
     if (p)
         *p = pp;
     if (q)
@@ -1733,6 +1905,19 @@ int nufft_fwd_batched(int32_t count, const int64_t *N, const int64_t *M,
     release_batch(B);
     delete B;
     return rc ? rc : rc_exec;
+}
+
+int nufft_autotune(int kind, int64_t N, int64_t M, double eps, int dtype, int32_t *lmax,
+                   int32_t *nterms, void *stream)
+{
+    return autotune(kind, N, M, eps, dtype, lmax, nterms, (hipStream_t)stream);
+}
+
+int nufft_autotune_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+    return FN_OK;
 }
 
 const char *nufft_last_error(void) { return g_err.c_str(); }

@@ -574,6 +574,74 @@ __global__ void k_coeffs(int64_t N, int l, const int32_t *off, const double *log
     }
 }
 
+// ---- synthetic problems for the autotuner (never part of a transform)
+
+// SplitMix64 (Steele, Lea and Flood, 2014): a counter-based hash.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x)
+{
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+__device__ __forceinline__ double unit_rand(uint64_t seed, uint64_t i)
+{
+    return (double)(splitmix64(seed ^ (i * 0x632be59bd9b4e019ull)) >> 11) * 0x1.0p-53;
+}
+
+// y_j uniform on [0, 2 pi) (jitter = 0) or the grid 2 pi (j + jitter (u - 1/2)) / N.
+__global__ void k_synth_points(int64_t n, int64_t N, double jitter, uint64_t seed,
+                               double *y)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const double u = unit_rand(seed, (uint64_t)j);
+        y[j] = jitter > 0.0 ? 6.283185307179586 * ((double)j + jitter * (u - 0.5)) / (double)N
+                            : 6.283185307179586 * u;
+    }
+}
+
+// Complex data with components uniform on [-1/2, 1/2).
+template <typename R>
+__global__ void k_synth_data(int64_t n, uint64_t seed, cx<R> *x)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x)
+        x[j] = {(R)(unit_rand(seed, 2 * (uint64_t)j) - 0.5),
+                (R)(unit_rand(seed, 2 * (uint64_t)j + 1) - 0.5)};
+}
+
+// Per-block sums of |a - b|^2 and |b|^2 (part[2 blk], part[2 blk + 1]).
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_diff2(int64_t n, const cx<R> *a, const cx<R> *b, double *part)
+{
+    __shared__ double sd[256], sb[256];
+    double d = 0.0, r = 0.0;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const double dr = (double)a[j].re - (double)b[j].re;
+        const double di = (double)a[j].im - (double)b[j].im;
+        d += dr * dr + di * di;
+        r += (double)b[j].re * (double)b[j].re + (double)b[j].im * (double)b[j].im;
+    }
+    sd[threadIdx.x] = d;
+    sb[threadIdx.x] = r;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) {
+            sd[threadIdx.x] += sd[threadIdx.x + k];
+            sb[threadIdx.x] += sb[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sd[0];
+        part[2 * blockIdx.x + 1] = sb[0];
+    }
+}
+
 // ---- the same passes over a batch of point sets: one launch each, block
 // b working for problem bm_find(b) (see BlockMap)
 
