@@ -150,7 +150,8 @@ def run_batched(fn, torch, workloads, steps, warmup):
     """512 independent forward transforms, N_i log-uniform in [2^8, 2^16],
     M_i = rint(N_i U(0.5, 2)), uniform y: one-shot batched calls (setup and
     evaluation) and evaluation-only graph replays of a batch plan, for both
-    precision paths.  Throughput = (sum N_i + sum M_i) / time."""
+    precision paths, with depth and expansion length autotuned per size
+    class first.  Throughput = (sum N_i + sum M_i) / time."""
     Ns, Ms = workloads.batched_sizes(512, seed=0)
     ys, fs = [], []
     for t, (N, M) in enumerate(zip(Ns, Ms)):
@@ -159,7 +160,19 @@ def run_batched(fn, torch, workloads, steps, warmup):
         fs.append(torch.from_numpy(f).cuda())
     pts = int(Ns.sum() + Ms.sum())
     out = {"transforms": 512, "sum_N": int(Ns.sum()), "sum_M": int(Ms.sum())}
+    # size classes lg = round(log2 sqrt(N M)) present, each with its median member
+    lg = np.rint(0.5 * np.log2(Ns.astype(float) * Ms.astype(float))).astype(int)
+    reps = {}
+    for c in sorted(set(lg.tolist())):
+        idx = np.nonzero(lg == c)[0]
+        i = idx[np.argsort(Ns[idx])[len(idx) // 2]]
+        reps[c] = (int(Ns[i]), int(Ms[i]))
     for name, dt, eps in (("f64", torch.complex128, 1e-12), ("mixed", torch.complex64, 1e-6)):
+        dtc = fn.FN_C128 if dt == torch.complex128 else fn.FN_C64
+        # autotuned depth and expansion length per size class (outside timing)
+        t = time.perf_counter()
+        tuned = {str(c): fn.autotune("fwd", n, m, eps, dtc) for c, (n, m) in reps.items()}
+        tune_s = time.perf_counter() - t
         fx = [f.to(dt) for f in fs]
         gs = [torch.empty(y.shape[0], dtype=dt, device="cuda") for y in ys]
         for _ in range(warmup):
@@ -170,8 +183,7 @@ def run_batched(fn, torch, workloads, steps, warmup):
             fn.nufft_fwd_batched(ys, fx, eps, outs=gs)
         torch.cuda.synchronize()
         one = (time.perf_counter() - t) / steps
-        b = fn.Batch.forward(ys, [int(n) for n in Ns], eps,
-                             fn.FN_C128 if dt == torch.complex128 else fn.FN_C64)
+        b = fn.Batch.forward(ys, [int(n) for n in Ns], eps, dtc)
         for _ in range(warmup):
             b(fx, gs)
         torch.cuda.synchronize()
@@ -181,8 +193,11 @@ def run_batched(fn, torch, workloads, steps, warmup):
         torch.cuda.synchronize()
         ex = (time.perf_counter() - t) / steps
         b.destroy()
+        fn.autotune_clear()
         out[name] = {"eps": eps, "one_shot_ms": one * 1e3, "one_shot_points_per_s": pts / one,
-                     "graph_exec_ms": ex * 1e3, "graph_exec_points_per_s": pts / ex}
+                     "graph_exec_ms": ex * 1e3, "graph_exec_points_per_s": pts / ex,
+                     "autotuned_lmax_nterms_by_size_class": tuned,
+                     "autotune_s": tune_s}
     return out
 
 
