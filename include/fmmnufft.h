@@ -198,7 +198,9 @@ int nufft_destroy_batched(fn_batch *batch);
  * size (uniform targets, or a jittered grid for the inverse), generated on
  * the device: first the shortest local expansion (16, 32 or 48 terms) whose
  * result stays within eps/4 of the 64-term result, then the fastest tree
- * depth among round(log2 sqrt(N M)) - 4 .. - 7 for one-shot calls.  Plans
+ * depth among round(log2 sqrt(N M)) - 4 .. - 7 for one-shot calls (small
+ * forward sizes timed as a batch of copies; the default depth is kept
+ * unless another is faster by over 5%).  Plans
  * (and batches) created afterwards in this process for the same kind,
  * dtype, size class round(log2 sqrt(N M)) and accuracy class
  * floor(-log10 eps) use the recorded values unless given explicitly.
