@@ -135,6 +135,14 @@ int nufft_execute_phase(fn_plan *plan, const void *in, void *out, int phase,
  * still queued on another stream must have completed before this call. */
 int nufft_destroy(fn_plan *plan);
 
+/* Inverse plans: the coefficients of Eq. (p8) the plan computed with the
+ * log-kernel FMM, rescaled as Chat_k = 2^N C_k (k = 0..N-1; 0 where a y_j
+ * falls on x_k) and Dhat_j = 2^-N D_j (in the order of y), binary64 on both
+ * precision paths.  chat: N doubles, dhat: N complex binary64 pairs, device
+ * memory owned by the caller.  Enqueues the copies on stream; FN_EINVAL
+ * for a forward plan. */
+int nufft_plan_coeffs(const fn_plan *plan, double *chat, void *dhat, void *stream);
+
 /* Reports the parameters of a plan. */
 int nufft_plan_get_info(const fn_plan *plan, fn_plan_info *info);
 

@@ -13,6 +13,7 @@ Functions (all arrays numpy; complex arrays are complex128):
   fwd_spectral(N, y, f)       -> g, Eq. (p1): c = DFT(f)/N, g_j = sum_n c_n e^{i n y_j}
   eval_series(N, y, c)        -> g, Eq. (p1) from given coefficients
   logsums(N, y, ks, js)       -> (logC, negC, logD, negD) behind Eq. (p8)
+  coeffs_at(N, y, ks, js)     -> (Chat[ks], Dhat[js]) of Eq. (p8), rescaled by 2^N
   inv(N, y, g)                -> f, Eq. (p6)/(p8) Lagrange form (M = N)
 """
 from __future__ import annotations
@@ -48,6 +49,7 @@ def _load():
     lib.or_eval_series.argtypes = [i64, i64, vp, vp, vp, ctypes.c_int]
     lib.or_logsums_at.argtypes = [i64, vp, i64, vp, vp, vp, i64, vp, vp, vp,
                                   ctypes.c_int]
+    lib.or_coeffs_at.argtypes = [i64, vp, i64, vp, vp, i64, vp, vp, ctypes.c_int]
     lib.or_inv.argtypes = [i64, vp, vp, vp, ctypes.c_int]
     lib.or_inv.restype = ctypes.c_int
     lib.or_max_threads.argtypes = [ctypes.c_int]
@@ -143,6 +145,22 @@ def logsums(N: int, y, ks=None, js=None):
                           None if js_a is None else _ptr(js_a), _ptr(logD),
                           _ptr(negD), _threads())
     return logC, negC, logD, negD
+
+
+def coeffs_at(N: int, y, ks, js):
+    """Chat_k = (-1)^(k + #{j: s_j > k}) prod_j |2 sin((x_k - y_j)/2)| and
+    Dhat_j = i e^{-i N y_j / 2} / prod_{i != j} 2 sin((y_j - y_i)/2) (Eq. p8,
+    rescaled by 2^N and 2^-N) at the selected k and j, each from O(N) direct
+    log-sums."""
+    y = _f64(y)
+    assert y.shape[0] == N
+    ks_a = np.ascontiguousarray(ks, dtype=np.int64)
+    js_a = np.ascontiguousarray(js, dtype=np.int64)
+    chat = np.empty(ks_a.shape[0])
+    dhat = np.empty(js_a.shape[0], dtype=np.complex128)
+    _load().or_coeffs_at(N, _ptr(y), ks_a.shape[0], _ptr(ks_a), _ptr(chat),
+                         js_a.shape[0], _ptr(js_a), _ptr(dhat), _threads())
+    return chat, dhat
 
 
 class OracleError(RuntimeError):

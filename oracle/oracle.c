@@ -243,13 +243,60 @@ static inline int64_t rep_int(int64_t m, double th, int64_t N)
     return (m == 0 && th < 0.0) ? N : m;
 }
 
-/* log |2 sin(pi d / N)| for a grid offset d = n + frac, n reduced first
- * (|sin| has period N in d). */
-static inline double log2sin(int64_t n, double frac_a, double frac_b,
-                             int64_t N)
+/* log |2 sin(pi d / N)| for a grid offset d = n + (fa - fb), n reduced
+ * first (|sin| has period N in d), split as E ln 2 + main + corr:
+ *   - d and x = d / N are carried as double-double pairs, and the argument
+ *     a = pi x as ah + al with pi = M_PI + PI_LO; the tail al enters to
+ *     first order as al cot(ah) (corr);
+ *   - |2 sin(ah)| = mant 2^E with mant in [1/2, 1), main = log(mant).
+ * Callers sum E exactly, main and corr apart, and combine them once: the
+ * rounding of pi alone would otherwise shift every term the same way (a
+ * drift of 3.9e-17 N ln 2 over N terms), and rounding log|2 sin| whole
+ * (terms up to ~12) costs an ulp of the term. */
+static const double PI_LO = 1.2246467991473532e-16; /* pi - M_PI */
+
+typedef struct {
+    int64_t e;   /* sum of the binary exponents */
+    nsum main;   /* sum of log(mant) */
+    nsum corr;   /* sum of the argument tails */
+} logsum;
+
+static inline void logsum_add(logsum *ls, int64_t n, double fa, double fb, int64_t N)
 {
-    double d = int_plus_diff(wrap_half(n, N), frac_a, frac_b);
-    return log(fabs(2.0 * sin(M_PI * (d / (double)N))));
+    const double nd = (double)wrap_half(n, N);
+    /* hi + lo = fa - fb exactly */
+    const double hi = fa - fb;
+    const double bb = hi - fa;
+    const double lo = (fa - (hi - bb)) + (-fb - bb);
+    /* dh + dl = nd + hi + lo */
+    const double dh = nd + hi;
+    const double bv = dh - nd;
+    const double dl = ((nd - (dh - bv)) + (hi - bv)) + lo;
+    /* q + ql = (dh + dl) / N */
+    const double Nd = (double)N;
+    const double q = dh / Nd;
+    const double ql = (fma(-q, Nd, dh) + dl) / Nd;
+    /* ah + al = pi (q + ql) */
+    const double ah = M_PI * q;
+    const double al = fma(M_PI, q, -ah) + M_PI * ql + PI_LO * q;
+    double sn, cs;
+    sincos(ah, &sn, &cs);
+    int e;
+    const double mant = frexp(fabs(2.0 * sn), &e);
+    ls->e += e;
+    nsum_add(&ls->main, log(mant));
+    nsum_add(&ls->corr, al * (cs / sn));
+}
+
+/* E ln 2 and the sum of log(mant) are each large and cancel to an O(1)
+ * result: they are combined in binary128 from the unrounded compensated
+ * pairs (s, c). */
+static inline double logsum_get(const logsum *ls)
+{
+    const __float128 v = (__float128)ls->e * M_LN2q + (__float128)ls->main.s +
+                         (__float128)ls->main.c + (__float128)ls->corr.s +
+                         (__float128)ls->corr.c;
+    return (double)v;
 }
 
 /* Sums behind the coefficients of Eq. (p8), rescaled by 2^N (the rescaling
@@ -273,7 +320,7 @@ void or_logsums_at(int64_t N, const double *y, int64_t nk, const int64_t *ks,
 #pragma omp parallel for schedule(dynamic, 8)
     for (int64_t i = 0; i < nk; ++i) {
         int64_t k = ks ? ks[i] : i;
-        nsum acc = {0, 0};
+        logsum acc = {0, {0, 0}, {0, 0}};
         int64_t neg = 0;
         int hit = 0;
         for (int64_t j = 0; j < N; ++j) {
@@ -282,17 +329,17 @@ void or_logsums_at(int64_t N, const double *y, int64_t nk, const int64_t *ks,
                 hit = 1;
                 continue;
             }
-            nsum_add(&acc, log2sin(k - m[j], 0.0, th[j], N));
+            logsum_add(&acc, k - m[j], 0.0, th[j], N);
             if (m[j] > k || (m[j] == k && th[j] > 0.0))
                 ++neg;
         }
-        logC[i] = hit ? -INFINITY : nsum_get(&acc);
+        logC[i] = hit ? -INFINITY : logsum_get(&acc);
         negC[i] = neg;
     }
 #pragma omp parallel for schedule(dynamic, 8)
     for (int64_t t = 0; t < nj; ++t) {
         int64_t j = js ? js[t] : t;
-        nsum acc = {0, 0};
+        logsum acc = {0, {0, 0}, {0, 0}};
         int64_t neg = 0;
         for (int64_t i = 0; i < N; ++i) {
             if (i == j)
@@ -301,9 +348,9 @@ void or_logsums_at(int64_t N, const double *y, int64_t nk, const int64_t *ks,
             double d = int_plus_diff(m[j] - m[i], th[j], th[i]);
             if (d < 0.0)
                 ++neg;
-            nsum_add(&acc, log2sin(m[j] - m[i], th[j], th[i], N));
+            logsum_add(&acc, m[j] - m[i], th[j], th[i], N);
         }
-        logD[t] = -nsum_get(&acc);
+        logD[t] = -logsum_get(&acc);
         negD[t] = neg;
     }
     free(m);
@@ -418,4 +465,40 @@ done:
     free(negD);
     free(w);
     return status;
+}
+
+/* Chat_k (k in ks) and Dhat_j (j in js) of Eq. (p8), rescaled by 2^N:
+ *   Chat_k = (-1)^(k + #{j: s_j > k}) exp(logC_k)       (0 at an exact hit),
+ *   Dhat_j = (-1)^(m'_j + #{i: s_i > s_j}) exp(logD_j) i e^{-i pi theta_j},
+ * from the direct log-sums above (the same composition as or_inv). */
+void or_coeffs_at(int64_t N, const double *y, int64_t nk, const int64_t *ks,
+                  double *chat, int64_t nj, const int64_t *js, double *dhat,
+                  int nthreads)
+{
+    double *logC = malloc(sizeof(double) * (size_t)(nk ? nk : 1));
+    double *logD = malloc(sizeof(double) * (size_t)(nj ? nj : 1));
+    int64_t *negC = malloc(sizeof(int64_t) * (size_t)(nk ? nk : 1));
+    int64_t *negD = malloc(sizeof(int64_t) * (size_t)(nj ? nj : 1));
+    or_logsums_at(N, y, nk, ks, logC, negC, nj, js, logD, negD, nthreads);
+    for (int64_t i = 0; i < nk; ++i) {
+        const int64_t k = ks[i];
+        chat[i] = logC[i] == -INFINITY
+                      ? 0.0
+                      : exp(logC[i]) * (((k + negC[i]) & 1) ? -1.0 : 1.0);
+    }
+    for (int64_t t = 0; t < nj; ++t) {
+        int64_t m;
+        double th;
+        or_grid_units(N, 1, y + js[t], &m, &th);
+        const int64_t mr = rep_int(m, th, N);
+        const double sgn = (((mr + negD[t]) & 1) ? -1.0 : 1.0) * exp(logD[t]);
+        double sp, cp;
+        sincos(M_PI * th, &sp, &cp);
+        dhat[2 * t] = sgn * sp;
+        dhat[2 * t + 1] = sgn * cp;
+    }
+    free(logC);
+    free(logD);
+    free(negC);
+    free(negD);
 }

@@ -30,7 +30,8 @@ ABI_SYMBOLS = (
     "nufft_fwd", "inufft", "nufft_plan_fwd", "nufft_plan_inv",
     "nufft_plan_fwd_ex", "nufft_plan_inv_ex", "nufft_execute",
     "nufft_execute_phase",
-    "nufft_destroy", "nufft_plan_get_info", "nufft_select_params",
+    "nufft_destroy", "nufft_plan_get_info", "nufft_plan_coeffs",
+    "nufft_select_params",
     "nufft_fwd_batched", "nufft_plan_fwd_batched", "nufft_execute_batched",
     "nufft_destroy_batched", "nufft_autotune", "nufft_autotune_clear",
     "nufft_last_error",
@@ -83,6 +84,7 @@ def load_library(path: str = LIB_PATH):
         "nufft_execute_phase": [vp, vp, vp, ctypes.c_int, vp],
         "nufft_destroy": [vp],
         "nufft_plan_get_info": [vp, ctypes.POINTER(PlanInfo)],
+        "nufft_plan_coeffs": [vp, vp, vp, vp],
         "nufft_select_params": [i64, i64, dbl, ctypes.c_int, pi32, pi32, pi32],
         "nufft_fwd_batched": [i32, vp, vp, vp, vp, vp, dbl, ctypes.c_int, vp],
         "nufft_plan_fwd_batched": [pp, i32, vp, vp, vp, dbl, ctypes.c_int, vp],
@@ -178,6 +180,16 @@ class Plan:
         out = PlanInfo()
         _check(load_library().nufft_plan_get_info(self._h, ctypes.byref(out)))
         return out
+
+    def coeffs(self):
+        """Inverse plans: (Chat, Dhat) of Eq. (p8), rescaled by 2^N and 2^-N
+        (Dhat in the order of y), as complex128/float64 GPU tensors."""
+        torch = _torch()
+        chat = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        dhat = torch.empty(self.N, dtype=torch.complex128, device="cuda")
+        _check(load_library().nufft_plan_coeffs(self._h, _dev_ptr(chat, "chat"),
+                                                _dev_ptr(dhat, "dhat"), _stream()))
+        return chat, dhat
 
     def execute(self, x, out=None):
         torch = _torch()

@@ -1836,6 +1836,21 @@ int nufft_destroy(fn_plan *plan)
     return FN_OK;
 }
 
+int nufft_plan_coeffs(const fn_plan *plan, double *chat, void *dhat, void *stream)
+{
+    if (!plan || !chat || !dhat)
+        return fail(FN_EINVAL, "NULL argument");
+    if (plan->kind != 1)
+        return fail(FN_EINVAL, "only inverse plans hold the coefficients of Eq. (p8)");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(chat, plan->chat.p, plan->N * 8, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_unsort_c128, dim3(grid_for(plan->N)), dim3(256), 0, st, plan->N,
+                       (const cx<double> *)plan->dhat.p, (const int32_t *)plan->sperm.p,
+                       (cx<double> *)dhat);
+    HIPCHK(hipGetLastError());
+    return FN_OK;
+}
+
 int nufft_plan_get_info(const fn_plan *plan, fn_plan_info *info)
 {
     if (!plan || !info)

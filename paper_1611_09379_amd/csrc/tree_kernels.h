@@ -574,6 +574,15 @@ __global__ void k_coeffs(int64_t N, int l, const int32_t *off, const double *log
     }
 }
 
+// Dhat in input order: out[perm[t]] = dhat[t].
+__global__ void k_unsort_c128(int64_t n, const cx<double> *dhat, const int32_t *perm,
+                              cx<double> *out)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        out[perm[t]] = dhat[t];
+}
+
 // ---- synthetic problems for the autotuner (never part of a transform)
 
 // SplitMix64 (Steele, Lea and Flood, 2014): a counter-based hash.

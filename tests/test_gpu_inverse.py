@@ -122,3 +122,23 @@ def test_inv_clustered_rejected():
     y, c = workloads.inverse_case(1024, 0.4, seed=3)
     g1 = np.random.default_rng(4).standard_normal(1024) + 0j
     assert rel_l2(run_inv(y, g1, 1e-12), oracle.inv(1024, y, g1)) < 1e-12
+
+
+@pytest.mark.parametrize("N,amp,dtype", [(1 << 20, 0.4, fn.FN_C128), (1 << 20, 0.4, fn.FN_C64),
+                                         (1 << 16, 0.4, fn.FN_C128), (4097, 0.1, fn.FN_C128)])
+def test_coeffs_sampled(N, amp, dtype):
+    """Chat_k and Dhat_j of Eq. (p8) (log-kernel FMM) against the oracle's
+    direct log-sums at sampled indices, at full size."""
+    y, c = workloads.inverse_case(N, amp, seed=0)
+    plan = fn.Plan.inverse(dev(y), 1e-12 if dtype == fn.FN_C128 else 1e-6, dtype)
+    chat, dhat = (host(t) for t in plan.coeffs())
+    plan.destroy()
+    rng = np.random.default_rng(11)
+    ks = rng.choice(N, min(N, 384), replace=False)
+    js = rng.choice(N, min(N, 384), replace=False)
+    rc, rd = oracle.coeffs_at(N, y, ks, js)
+    ec, ed = rel_l2(chat[ks], rc), rel_l2(dhat[js], rd)
+    say(f"coeffs N={N}: Chat {ec:.2e} Dhat {ed:.2e}")
+    # the log-sums are binary64 on both paths, truncated for a tenth of eps
+    tol = 1e-12 if dtype == fn.FN_C128 else 1e-6
+    assert ec < tol and ed < tol

@@ -188,3 +188,51 @@ def test_inverse_hits_and_singular():
     y2[5] = y2[9]
     with pytest.raises(oracle.OracleError):
         oracle.inv(N, y2, g)
+
+
+@pytest.mark.parametrize("N,amp", [(16, 0.3), (23, 0.45)])
+def test_coeffs_brute_force_eq_p8(N, amp):
+    """Chat_k = 2^N C_k and Dhat_j = 2^-N D_j of Eq. (p8), written as the
+    products of sines they are, in 40-digit arithmetic."""
+    y, c = workloads.inverse_case(N, amp, seed=N)
+    ks = np.arange(N)
+    chat, dhat = oracle.coeffs_at(N, y, ks, ks)
+    for k in range(N):
+        xk = 2 * mpmath.pi * k / N
+        prod = mpmath.mpf(1)
+        for v in y:
+            prod *= 2 * mpmath.sin((xk - mpmath.mpf(v)) / 2)
+        ref = (-1) ** k * prod
+        assert abs(chat[k] - float(ref)) <= 1e-13 * abs(float(ref))
+    for j in range(N):
+        yj = mpmath.mpf(y[j])
+        prod = mpmath.mpf(1)
+        for i in range(N):
+            if i != j:
+                prod *= 2 * mpmath.sin((yj - mpmath.mpf(y[i])) / 2)
+        ref = 1j * mpmath.exp(-1j * N * yj / 2) / prod
+        assert abs(dhat[j] - complex(ref)) <= 1e-13 * abs(complex(ref))
+
+
+def test_logsums_large_n_mpmath():
+    """Log-sums of Eq. (p8) at N = 2^16 against 30-digit sums.  Per-term
+    errors of about 5e-17 (random) allow some 1e-14 here; a bias common to
+    all N terms shows far above that (a rounded pi in the sine's argument:
+    3.9e-17 N ln 2 = 1.8e-12; rounding the whole logarithm of each term:
+    about 4e-13)."""
+    N = 1 << 16
+    y, c = workloads.inverse_case(N, 0.4, seed=21)
+    ks = np.array([7, 40000])
+    js = np.array([3, 51234])
+    logC, negC, logD, negD = oracle.logsums(N, y, ks, js)
+    with mpmath.workdps(30):
+        ym = [mpmath.mpf(v) for v in y]
+        for i, k in enumerate(ks):
+            xk = 2 * mpmath.pi * int(k) / N
+            ref = mpmath.fsum(mpmath.log(abs(2 * mpmath.sin((xk - v) / 2))) for v in ym)
+            assert abs(float(ref) - logC[i]) < 2e-13, (k, float(ref) - logC[i])
+        for t, j in enumerate(js):
+            yj = ym[int(j)]
+            ref = -mpmath.fsum(mpmath.log(abs(2 * mpmath.sin((yj - v) / 2)))
+                               for i, v in enumerate(ym) if i != int(j))
+            assert abs(float(ref) - logD[t]) < 2e-13, (j, float(ref) - logD[t])
