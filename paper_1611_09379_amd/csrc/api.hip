@@ -659,8 +659,7 @@ struct TreeJob {
     SortArgs a{};
     bool lds_path = true, deterministic = false;
     int32_t *tsum = nullptr;               // tile sums of the multi-pass scan
-    int32_t *gm = nullptr, *gperm = nullptr; // deterministic: before ranking
-    double *gth = nullptr;
+    SortedPt *gpt = nullptr;               // deterministic: records before ranking
 };
 
 static int prepare_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
@@ -688,11 +687,8 @@ static int prepare_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
     a.tot = (int32_t *)tmp_alloc(P, (size_t)nbins * 4);
     a.cursor = lds_path ? nullptr : (int32_t *)tmp_alloc(P, (size_t)nbins * 4);
     J->tsum = (int32_t *)tmp_alloc(P, ((nbins + SCAN_TILE - 1) / SCAN_TILE) * 4);
-    if (deterministic) {
-        J->gm = (int32_t *)tmp_alloc(P, n * 4);
-        J->gth = (double *)tmp_alloc(P, n * 8);
-        J->gperm = (int32_t *)tmp_alloc(P, n * 4);
-    }
+    if (deterministic)
+        J->gpt = (SortedPt *)tmp_alloc(P, n * sizeof(SortedPt));
     // sorted points: (m, perm, th) records, or separate arrays plus every
     // point's leaf (k_rank only reorders inside a leaf, so the leaves hold
     // for the final order too)
@@ -701,18 +697,19 @@ static int prepare_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
                 : (alloc(P->skey, n * 4) && alloc(P->sm, n * 4) && alloc(P->sth, n * 8) &&
                    alloc(P->sperm, n * 4));
     if (!a.um || !a.uth || !a.ukey || (lds_path && !a.H) || !a.tot || !J->tsum ||
-        (!lds_path && !a.cursor) || (deterministic && (!J->gm || !J->gth || !J->gperm)) ||
+        (!lds_path && !a.cursor) || (deterministic && !J->gpt) ||
         !sorted_ok || !alloc(P->off, ((size_t)nbins + 1) * 4) ||
         (want_hit && !alloc(P->hit, P->N * 4)))
         return fail(FN_ENOMEM, "workspace allocation failed (%lld points)", (long long)n);
     if ((nbins + SCAN_TILE - 1) / SCAN_TILE > 4096)
         return fail(FN_EINVAL, "tree too large for the scan (%d leaves)", nbins);
     a.off = (int32_t *)P->off.p;
-    a.sm = deterministic ? J->gm : (int32_t *)P->sm.p;
-    a.sth = deterministic ? J->gth : (double *)P->sth.p;
-    a.sperm = deterministic ? J->gperm : (int32_t *)P->sperm.p;
+    // deterministic: records first, ranked into sm, sth, sperm by k_rank
+    a.sm = (int32_t *)P->sm.p;
+    a.sth = (double *)P->sth.p;
+    a.sperm = (int32_t *)P->sperm.p;
     a.skey = (int32_t *)P->skey.p;
-    a.spt = (SortedPt *)P->spt.p;
+    a.spt = deterministic ? J->gpt : (SortedPt *)P->spt.p;
     a.hit = want_hit ? (int32_t *)P->hit.p : nullptr;
     a.flags = (int *)P->flags.p;
     return FN_OK;
@@ -728,7 +725,7 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
     if (J.lds_path) {
         hipLaunchKernelGGL(k_keys, dim3(grid_for(a.n)), dim3(256), 0, st, a);
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_hist, dim3(a.nblk), dim3(256), (size_t)nbins * 4, st, a);
+        hipLaunchKernelGGL(k_hist, dim3(a.nblk), dim3(SORT_THREADS), (size_t)nbins * 4, st, a);
         HIPCHK(hipGetLastError());
         hipLaunchKernelGGL(k_colscan, dim3(grid_for(nbins)), dim3(256), 0, st, a);
     } else {
@@ -740,8 +737,8 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
     HIPCHK(hipGetLastError());
     // off = exclusive scan of the key totals; cursor copy for the atomic path
     if (nbins <= SCAN1_MAX) {
-        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, st, (const int32_t *)a.tot,
-                           nbins, a.off, a.cursor);
+        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), SCAN1_SMEM, st,
+                           (const int32_t *)a.tot, nbins, a.off, a.cursor);
         HIPCHK(hipGetLastError());
     } else {
         const int nt = (int)((nbins + SCAN_TILE - 1) / SCAN_TILE);
@@ -755,7 +752,7 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
         HIPCHK(hipGetLastError());
     }
     if (J.lds_path) {
-        hipLaunchKernelGGL(k_place, dim3(a.nblk), dim3(256), (size_t)nbins * 4, st, a);
+        hipLaunchKernelGGL(k_place, dim3(a.nblk), dim3(SORT_THREADS), (size_t)nbins * 4, st, a);
     } else {
         hipLaunchKernelGGL(k_scatter, dim3(grid_for(a.n)), dim3(256), 0, st, a.n,
                            (const int32_t *)a.um, (const double *)a.uth,
@@ -764,9 +761,9 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
     }
     HIPCHK(hipGetLastError());
     if (J.deterministic) {
-        hipLaunchKernelGGL(k_rank, dim3(grid_for(a.n)), dim3(256), 0, st, a.n,
-                           (const int32_t *)J.gm, (const double *)J.gth,
-                           (const int32_t *)J.gperm, (const int32_t *)a.skey,
+        const int64_t nleaf = int64_t(1) << P->l;
+        hipLaunchKernelGGL(k_rank, dim3((nleaf + RANK_LEAVES - 1) / RANK_LEAVES), dim3(256),
+                           0, st, nleaf, (const SortedPt *)J.gpt, (const int32_t *)a.skey,
                            (const int32_t *)a.off, dense_max(P->N, P->l),
                            (int32_t *)P->sm.p, (double *)P->sth.p, (int32_t *)P->sperm.p,
                            a.flags);
@@ -1404,16 +1401,16 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
         const SortArgs *A = (const SortArgs *)at(B->keys.args);
         hipLaunchKernelGGL(kb_keys, dim3(B->keys.grid), dim3(256), 0, st, A, map(B->keys));
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(kb_hist, dim3(B->hist.grid), dim3(256), B->hist.smem, st,
+        hipLaunchKernelGGL(kb_hist, dim3(B->hist.grid), dim3(SORT_THREADS), B->hist.smem, st,
                            (const SortArgs *)at(B->hist.args), map(B->hist));
         HIPCHK(hipGetLastError());
         hipLaunchKernelGGL(kb_colscan, dim3(B->colscan.grid), dim3(256), 0, st,
                            (const SortArgs *)at(B->colscan.args), map(B->colscan));
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(kb_scan_one, dim3(B->scan.grid), dim3(1024), 0, st,
+        hipLaunchKernelGGL(kb_scan_one, dim3(B->scan.grid), dim3(1024), SCAN1_SMEM, st,
                            (const SortArgs *)at(B->scan.args));
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(kb_place, dim3(B->place.grid), dim3(256), B->place.smem, st,
+        hipLaunchKernelGGL(kb_place, dim3(B->place.grid), dim3(SORT_THREADS), B->place.smem, st,
                            (const SortArgs *)at(B->place.args), map(B->place));
         HIPCHK(hipGetLastError());
         hipLaunchKernelGGL(kb_work, dim3(B->work.grid), dim3(1024), 0, st,

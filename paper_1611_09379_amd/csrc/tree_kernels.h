@@ -107,38 +107,61 @@ __global__ void __launch_bounds__(256) k_keys(SortArgs a)
     keys_body(a, blockIdx.x, gridDim.x);
 }
 
-constexpr int SORT_BATCH = 8; // points in flight per thread in the sort passes
+constexpr int SORT_BATCH = 8;     // points in flight per thread in the sort passes
+constexpr int SORT_THREADS = 1024; // threads of a histogram / placement block
 
 // Counting sort, pass 1: per-block histograms of the keys in LDS.  Block b
 // takes points [b chunk, (b+1) chunk); H is block-major, H[b nbins + key].
+// Runs of equal keys in consecutive lanes of a wavefront (nearly sorted
+// input, e.g. a jittered grid, puts a wave's points into one or two keys):
+// *start = first lane of my run, *len = its length where I am its first
+// lane (0 elsewhere).  One LDS atomic per run then replaces one per lane.
+__device__ __forceinline__ void key_runs(int32_t key, int *start, int *len)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t prev = __shfl_up(key, 1);
+    const bool head = lane == 0 || key != prev;
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
+    *start = 63 - __clzll(heads & upto);
+    const unsigned long long above = heads & ~upto;
+    const int next = above ? __ffsll((long long)above) - 1 : 64;
+    *len = head ? next - lane : 0;
+}
+
 __device__ __forceinline__ void hist_body(const SortArgs &a, int blk)
 {
     extern __shared__ int32_t hist[];
     const int nbins = a.nbins;
-    for (int i = threadIdx.x; i < nbins; i += 256)
+    for (int i = threadIdx.x; i < nbins; i += SORT_THREADS)
         hist[i] = 0;
     __syncthreads();
     const int64_t j0 = (int64_t)blk * a.chunk;
     const int64_t j1 = j0 + a.chunk < a.n ? j0 + a.chunk : a.n;
     const int32_t *__restrict__ ukey = a.ukey;
-    for (int64_t jb = j0 + threadIdx.x; jb < j1; jb += 256 * SORT_BATCH) {
+    // every lane runs every iteration (key_runs works across the wavefront)
+    for (int64_t jw = j0; jw < j1; jw += SORT_THREADS * SORT_BATCH) {
+        const int64_t jb = jw + threadIdx.x;
         int32_t key[SORT_BATCH];
 #pragma unroll
         for (int u = 0; u < SORT_BATCH; ++u) {
-            const int64_t j = jb + u * 256;
+            const int64_t j = jb + u * SORT_THREADS;
             key[u] = j < j1 ? ukey[j] : -1;
         }
 #pragma unroll
-        for (int u = 0; u < SORT_BATCH; ++u)
-            if (key[u] >= 0)
-                atomicAdd(&hist[key[u]], 1);
+        for (int u = 0; u < SORT_BATCH; ++u) {
+            int start, len;
+            key_runs(key[u], &start, &len);
+            if (len && key[u] >= 0)
+                atomicAdd(&hist[key[u]], len);
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nbins; i += 256)
+    for (int i = threadIdx.x; i < nbins; i += SORT_THREADS)
         a.H[(int64_t)blk * nbins + i] = hist[i];
 }
 
-__global__ void __launch_bounds__(256) k_hist(SortArgs a) { hist_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(SORT_THREADS) k_hist(SortArgs a) { hist_body(a, blockIdx.x); }
 
 // Counting sort, between the passes: for every key, the exclusive prefix of
 // its counts over the blocks (in place in H) and its total (tot[key]).
@@ -174,17 +197,19 @@ __device__ __forceinline__ void place_body(const SortArgs &a, int blk)
 {
     extern __shared__ int32_t cur[];
     const int nbins = a.nbins;
-    for (int i = threadIdx.x; i < nbins; i += 256)
+    for (int i = threadIdx.x; i < nbins; i += SORT_THREADS)
         cur[i] = a.off[i] + a.H[(int64_t)blk * nbins + i];
     __syncthreads();
     const int64_t j0 = (int64_t)blk * a.chunk;
     const int64_t j1 = j0 + a.chunk < a.n ? j0 + a.chunk : a.n;
-    for (int64_t jb = j0 + threadIdx.x; jb < j1; jb += 256 * SORT_BATCH) {
+    // every lane runs every iteration (key_runs works across the wavefront)
+    for (int64_t jw = j0; jw < j1; jw += SORT_THREADS * SORT_BATCH) {
+        const int64_t jb = jw + threadIdx.x;
         int32_t key[SORT_BATCH], mm[SORT_BATCH], pos[SORT_BATCH];
         double tt[SORT_BATCH];
 #pragma unroll
         for (int u = 0; u < SORT_BATCH; ++u) {
-            const int64_t j = jb + u * 256;
+            const int64_t j = jb + u * SORT_THREADS;
             key[u] = -1;
             if (j < j1) {
                 key[u] = a.ukey[j];
@@ -193,21 +218,30 @@ __device__ __forceinline__ void place_body(const SortArgs &a, int blk)
             }
         }
 #pragma unroll
-        for (int u = 0; u < SORT_BATCH; ++u)
-            if (key[u] >= 0)
-                pos[u] = atomicAdd(&cur[key[u]], 1);
+        for (int u = 0; u < SORT_BATCH; ++u) {
+            int start, len;
+            key_runs(key[u], &start, &len);
+            int32_t base = 0;
+            if (len && key[u] >= 0)
+                base = atomicAdd(&cur[key[u]], len);
+            base = __shfl(base, start);
+            pos[u] = base + ((int)(threadIdx.x & 63) - start);
+        }
         if (a.spt) {
 #pragma unroll
             for (int u = 0; u < SORT_BATCH; ++u)
-                if (key[u] >= 0)
-                    a.spt[pos[u]] = {mm[u], (int32_t)(jb + u * 256), tt[u]};
+                if (key[u] >= 0) {
+                    a.spt[pos[u]] = {mm[u], (int32_t)(jb + u * SORT_THREADS), tt[u]};
+                    if (a.skey)
+                        a.skey[pos[u]] = key[u];
+                }
         } else {
 #pragma unroll
             for (int u = 0; u < SORT_BATCH; ++u)
                 if (key[u] >= 0) {
                     a.sm[pos[u]] = mm[u];
                     a.sth[pos[u]] = tt[u];
-                    a.sperm[pos[u]] = (int32_t)(jb + u * 256);
+                    a.sperm[pos[u]] = (int32_t)(jb + u * SORT_THREADS);
                     if (a.skey)
                         a.skey[pos[u]] = key[u];
                 }
@@ -215,7 +249,7 @@ __device__ __forceinline__ void place_body(const SortArgs &a, int blk)
     }
 }
 
-__global__ void __launch_bounds__(256) k_place(SortArgs a) { place_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(SORT_THREADS) k_place(SortArgs a) { place_body(a, blockIdx.x); }
 
 // Counting sort with global atomics, for key ranges too large for LDS:
 // pass 1 counts every key.
@@ -241,27 +275,31 @@ __global__ void k_reduce(int64_t M, const double *__restrict__ y, double c_hi,
 }
 
 // Exclusive scan of up to SCAN1_MAX counts in one workgroup of 1024 threads:
-// thread i owns the run [32 i, 32 i + 32), loaded at once into registers.
-// off[n] = total; cursor (optional) receives a copy of the scan.
+// the counts are loaded coalesced into LDS (skewed by one word per 32, so
+// that the per-thread runs below are free of bank conflicts), thread i scans
+// the run [32 i, 32 i + 32), the 1024 run sums are scanned, and the results
+// go out coalesced.  off[n] = total; cursor (optional) receives a copy.
 constexpr int SCAN1_PER = 32;
 constexpr int SCAN1_MAX = 1024 * SCAN1_PER;
+__device__ __forceinline__ int scan1_slot(int i) { return i + (i >> 5); }
+
 __device__ __forceinline__ void scan_one_body(const int32_t *__restrict__ count, int n,
                                               int32_t *__restrict__ off,
                                               int32_t *__restrict__ cursor)
 {
-    __shared__ int32_t part[1024];
+    extern __shared__ int32_t sv[]; // scan1_slot(SCAN1_MAX) + 1024 words
+    int32_t *part = sv + scan1_slot(SCAN1_MAX);
+    for (int i = threadIdx.x; i < SCAN1_MAX; i += 1024)
+        sv[scan1_slot(i)] = i < n ? count[i] : 0;
+    __syncthreads();
     const int i0 = threadIdx.x * SCAN1_PER;
-    int32_t v[SCAN1_PER];
-#pragma unroll
-    for (int u = 0; u < SCAN1_PER; ++u)
-        v[u] = i0 + u < n ? count[i0 + u] : 0;
     int32_t sum = 0;
-#pragma unroll
+#pragma unroll 8
     for (int u = 0; u < SCAN1_PER; ++u)
-        sum += v[u];
+        sum += sv[scan1_slot(i0 + u)];
     part[threadIdx.x] = sum;
     __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 partial sums
+    // Hillis-Steele inclusive scan of the 1024 run sums
     for (int d = 1; d < 1024; d <<= 1) {
         const int32_t t = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
         __syncthreads();
@@ -269,18 +307,26 @@ __device__ __forceinline__ void scan_one_body(const int32_t *__restrict__ count,
         __syncthreads();
     }
     int32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
-#pragma unroll
+#pragma unroll 8
     for (int u = 0; u < SCAN1_PER; ++u) {
-        if (i0 + u < n) {
-            off[i0 + u] = run;
-            if (cursor)
-                cursor[i0 + u] = run;
-        }
-        run += v[u];
+        const int k = scan1_slot(i0 + u);
+        const int32_t c = sv[k];
+        sv[k] = run;
+        run += c;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        const int32_t v = sv[scan1_slot(i)];
+        off[i] = v;
+        if (cursor)
+            cursor[i] = v;
     }
     if (threadIdx.x == 1023)
         off[n] = part[1023];
 }
+
+// dynamic LDS of k_scan_one / kb_scan_one
+constexpr size_t SCAN1_SMEM = (size_t)(SCAN1_MAX + SCAN1_MAX / 32 + 1024) * 4;
 
 __global__ void __launch_bounds__(1024)
     k_scan_one(const int32_t *count, int n, int32_t *off, int32_t *cursor)
@@ -395,6 +441,8 @@ __global__ void k_scatter(int64_t M, const int32_t *um, const double *uth,
         int32_t pos = atomicAdd(&cursor[key], 1);
         if (spt) {
             spt[pos] = {um[j], (int32_t)j, uth[j]};
+            if (skey)
+                skey[pos] = key;
             continue;
         }
         sm[pos] = um[j];
@@ -410,55 +458,132 @@ __global__ void k_scatter(int64_t M, const int32_t *um, const double *uth,
 // A leaf holding more than dense_max points raises FLAG_DENSE and keeps
 // its order (still a permutation): the point set is far too clustered for
 // the inverse, and ranking it would cost the square of the leaf's size.
-__global__ void k_rank(int64_t n, const int32_t *gm, const double *gth,
-                       const int32_t *gperm, const int32_t *gkey,
-                       const int32_t *off, int32_t dense_max, int32_t *sm, double *sth,
-                       int32_t *sperm, int *flags)
+// Positions s = m + th are compared in the canonical form th in [-1/2, 1/2)
+// (th = 1/2 becomes m + 1, -1/2): the intervals [m - 1/2, m + 1/2) are
+// disjoint, so s_u < s_t exactly when (m_u, th_u) < (m_t, th_t)
+// lexicographically.
+__device__ __forceinline__ void canon_pos(int32_t &m, double &th)
 {
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t b = gkey[t];
-        const int32_t t0 = off[b];
-        int32_t t1 = off[b + 1];
-        const int32_t mt = gm[t];
-        const double tht = gth[t];
-        int32_t rank = (int32_t)t - t0;
-        if (t1 - t0 > dense_max) {
-            if (t == t0)
-                atomicOr(flags, FLAG_DENSE);
-            t1 = t0; // no ranking
-        } else {
-            rank = 0;
-        }
-        bool dup = false;
-        for (int32_t u0 = t0; u0 < t1; u0 += SORT_BATCH) {
-            int32_t mu[SORT_BATCH];
-            double thu[SORT_BATCH];
-#pragma unroll
-            for (int v = 0; v < SORT_BATCH; ++v) {
-                const int32_t u = u0 + v < t1 ? u0 + v : t0;
-                mu[v] = gm[u];
-                thu[v] = gth[u];
-            }
-#pragma unroll
-            for (int v = 0; v < SORT_BATCH; ++v) {
-                const int32_t u = u0 + v;
-                if (u >= t1 || u == (int32_t)t)
-                    continue;
-                const double d = grid_diff((int64_t)mu[v] - mt, thu[v], tht);
-                // ties (duplicates) are ordered by index: the ranks stay a
-                // permutation of the leaf
-                rank += (d < 0.0 || (d == 0.0 && u < t)) ? 1 : 0;
-                dup |= d == 0.0;
-            }
-        }
-        if (dup)
-            atomicOr(flags, FLAG_DUP);
+    if (th == 0.5) {
+        m += 1;
+        th = -0.5;
+    }
+}
+
+// Rank of point t (of the leaf [t0, t1)) among its leaf by position, from
+// canonical grid units gm(u), gth(u); ties (duplicates) are ordered by index,
+// so that the ranks stay a permutation of the leaf.
+template <typename GetM, typename GetTh>
+__device__ __forceinline__ int32_t leaf_rank(int32_t t, int32_t t0, int32_t t1, GetM gm,
+                                             GetTh gth, int32_t mt, double tht, bool *dup)
+{
+    int32_t rank = 0;
+    bool d = false;
+#pragma unroll 4
+    for (int32_t u = t0; u < t1; ++u) {
+        const int32_t mu = gm(u);
+        const double tu = gth(u);
+        const bool lt = mu < mt || (mu == mt && tu < tht);
+        const bool eq = mu == mt && tu == tht;
+        rank += (lt || (eq && u < t)) ? 1 : 0;
+        d |= eq && u != t;
+    }
+    *dup |= d;
+    return rank;
+}
+
+constexpr int RANK_LEAVES = 32;   // leaves per workgroup of k_rank
+constexpr int RANK_CAP = 2048;    // points of those leaves staged in LDS
+
+// Orders the points of every leaf by position (so the whole set is sorted
+// along the circle); two points at the same position raise FLAG_DUP.
+// Workgroup g takes leaves [32 g, 32 g + 32).  When their points fit, they
+// are staged in LDS with the leaves' offsets, and each thread ranks one
+// point against its leaf from LDS (its leaf found by a binary search of the
+// staged offsets); else the points are read in place.  A leaf holding more
+// than dense_max points raises FLAG_DENSE and keeps its order (still a
+// permutation): the point set is far too clustered for the inverse, and
+// ranking it would cost the square of the leaf's size.
+__global__ void __launch_bounds__(256)
+    k_rank(int64_t nleaf, const SortedPt *gpt, const int32_t *gkey, const int32_t *off,
+           int32_t dense_max, int32_t *sm, double *sth, int32_t *sperm, int *flags)
+{
+    __shared__ int32_t lm[RANK_CAP], lperm[RANK_CAP]; // canonical m, input index
+    __shared__ double lth[RANK_CAP];                  // canonical th
+    __shared__ int32_t loff[RANK_LEAVES + 1];
+    const int64_t b0 = (int64_t)blockIdx.x * RANK_LEAVES;
+    const int64_t b1 = b0 + RANK_LEAVES < nleaf ? b0 + RANK_LEAVES : nleaf;
+    const int nb = (int)(b1 - b0);
+    const int32_t T0 = off[b0], T1 = off[b1];
+    bool dup = false;
+    auto finish = [&](int32_t t0, int32_t rank, int32_t mt, double tht, int32_t perm) {
         const int32_t pos = t0 + rank;
         sm[pos] = mt;
         sth[pos] = tht;
-        sperm[pos] = gperm[t];
+        sperm[pos] = perm;
+    };
+    if (T1 - T0 <= RANK_CAP) {
+        for (int32_t i = threadIdx.x; i < T1 - T0; i += 256) {
+            SortedPt q = gpt[T0 + i];
+            lperm[i] = q.perm;
+            canon_pos(q.m, q.th);
+            lm[i] = q.m;
+            lth[i] = q.th;
+        }
+        for (int i = threadIdx.x; i <= nb; i += 256)
+            loff[i] = off[b0 + i] - T0;
+        __syncthreads();
+        auto gm = [&](int32_t u) { return lm[u]; };
+        auto gth = [&](int32_t u) { return lth[u]; };
+        for (int32_t i = threadIdx.x; i < T1 - T0; i += 256) {
+            int lo = 0, hi = nb; // leaf: largest li with loff[li] <= i
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (loff[mid] <= i)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            const int32_t t0 = loff[lo], t1 = loff[lo + 1];
+            int32_t rank;
+            if (t1 - t0 > dense_max) {
+                if (i == t0)
+                    atomicOr(flags, FLAG_DENSE);
+                rank = i - t0; // no ranking
+            } else {
+                rank = leaf_rank(i, t0, t1, gm, gth, lm[i], lth[i], &dup);
+            }
+            const SortedPt q = gpt[T0 + i]; // the stored (not canonical) units
+            finish(t0 + T0, rank, q.m, q.th, lperm[i]);
+        }
+    } else {
+        auto gm = [&](int32_t u) {
+            SortedPt q = gpt[u];
+            canon_pos(q.m, q.th);
+            return q.m;
+        };
+        auto gth = [&](int32_t u) {
+            SortedPt q = gpt[u];
+            canon_pos(q.m, q.th);
+            return q.th;
+        };
+        for (int32_t t = T0 + threadIdx.x; t < T1; t += 256) {
+            const int32_t b = gkey[t];
+            const int32_t t0 = off[b], t1 = off[b + 1];
+            const SortedPt q = gpt[t];
+            int32_t rank;
+            if (t1 - t0 > dense_max) {
+                if (t == t0)
+                    atomicOr(flags, FLAG_DENSE);
+                rank = t - t0; // no ranking
+            } else {
+                rank = leaf_rank(t, t0, t1, gm, gth, gm(t), gth(t), &dup);
+            }
+            finish(t0, rank, q.m, q.th, q.perm);
+        }
     }
+    if (dup)
+        atomicOr(flags, FLAG_DUP);
 }
 
 // Work list of the downward pass (one workgroup): for every subtree root R
@@ -661,7 +786,7 @@ __global__ void __launch_bounds__(256) kb_keys(const SortArgs *aa, BlockMap bm)
     keys_body(aa[t], blk, nblk);
 }
 
-__global__ void __launch_bounds__(256) kb_hist(const SortArgs *aa, BlockMap bm)
+__global__ void __launch_bounds__(SORT_THREADS) kb_hist(const SortArgs *aa, BlockMap bm)
 {
     int blk, nblk;
     const int t = bm_find(bm, blockIdx.x, &blk, &nblk);
@@ -682,7 +807,7 @@ __global__ void __launch_bounds__(1024) kb_scan_one(const SortArgs *aa)
     scan_one_body(a.tot, a.nbins, a.off, a.cursor);
 }
 
-__global__ void __launch_bounds__(256) kb_place(const SortArgs *aa, BlockMap bm)
+__global__ void __launch_bounds__(SORT_THREADS) kb_place(const SortArgs *aa, BlockMap bm)
 {
     int blk, nblk;
     const int t = bm_find(bm, blockIdx.x, &blk, &nblk);
