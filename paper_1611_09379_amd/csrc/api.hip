@@ -331,6 +331,7 @@ struct FmmSetup {
     int PU = 0, PD = 0, q = 0;
     int RSu = 0, RSd = 0;          // LDS row strides (elements of R)
     Buf mp, loc2, S;
+    Buf locl; // leaf local expansions (between the two downward kernels)
     int nbands = 0;
     Band band[MAX_BANDS];
     size_t reg_smem = 0;
@@ -363,6 +364,7 @@ struct fn_plan {
     std::vector<Buf *> all()
     {
         return {&off, &sm, &sth, &sperm, &skey, &spt, &work, &nwork_dev, &cot.mp, &cot.loc2,
+                &cot.locl,
                 &cot.S, &hit, &chat, &dhat, &wsorted, &flags};
     }
 };
@@ -530,7 +532,7 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_
     F.near_bytes = (int)((size_t)(F.rows_buf + F.rows_src) * F.RSd * es);
     const int64_t nmp = lev_off(P->l + 1, PU);
     if (!alloc(F.mp, nmp * sizeof(V)) || !alloc(F.loc2, 4 * PD * sizeof(V)) ||
-        !alloc(F.S, sizeof(V)))
+        !alloc(F.S, sizeof(V)) || !alloc(F.locl, ((size_t)PD << P->l) * sizeof(V)))
         return fail(FN_ENOMEM, "expansion allocation failed");
     (void)kernel;
     (void)st;
@@ -573,6 +575,7 @@ static void fill_down(const fn_plan *P, const FmmSetup &F, const OpTables<R> &T,
     da.S = (const V *)F.S.p;
     da.T = T;
     da.flags = (const int *)P->flags.p;
+    da.leaf_loc = (V *)F.locl.p;
 }
 
 // Launches with the expansion lengths as template arguments.
@@ -612,6 +615,9 @@ static int launch_down(const fn_plan *P, const FmmSetup &F, const DownArgs<R, V>
     if (P->nwork == 0)
         return FN_OK;
     FN_DISPATCH16(F.PD, PD_,
+                  hipLaunchKernelGGL((k_down_trans<R, V, KER, SRC, EPI, PD_>),
+                                     dim3(P->nwork), dim3(BLOCK), F.dn_smem, st, da);
+                  HIPCHK(hipGetLastError());
                   hipLaunchKernelGGL((k_down_eval<R, V, KER, SRC, EPI, PD_>),
                                      dim3(P->nwork), dim3(BLOCK), F.dn_smem, st, da));
     HIPCHK(hipGetLastError());
@@ -938,7 +944,7 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     FmmSetup F;
     rc = setup_fmm<R, V>(P, KER_LOG, PU, PD, qlog, true, F, st);
     // the log FMM's workspace lives until the plan's synchronisation
-    for (Buf *b : {&F.mp, &F.loc2, &F.S})
+    for (Buf *b : {&F.mp, &F.loc2, &F.S, &F.locl})
         if (b->p)
             P->tmp.push_back(*b);
     if (rc)
@@ -1450,11 +1456,15 @@ static int launch_batch_eval(fn_batch *B, hipStream_t st)
     hipLaunchKernelGGL((kb_regular<R, V, KER_COT>), dim3(B->reg.grid), dim3(BLOCK),
                        B->reg.smem, st, (const UpArgs<R, V> *)at(B->reg.args), B->PU);
     HIPCHK(hipGetLastError());
-    FN_DISPATCH16(B->PD, PD_,
-                  hipLaunchKernelGGL((kb_down_eval<R, V, KER_COT, SET_UNIFORM, EPI_FWD, PD_>),
-                                     dim3(B->down.grid), dim3(BLOCK), B->down.smem, st,
-                                     (const DownArgs<R, V> *)at(B->down.args), map(B->down),
-                                     io));
+    FN_DISPATCH16(
+        B->PD, PD_,
+        hipLaunchKernelGGL((kb_down_trans<R, V, KER_COT, SET_UNIFORM, EPI_FWD, PD_>),
+                           dim3(B->down.grid), dim3(BLOCK), B->down.smem, st,
+                           (const DownArgs<R, V> *)at(B->down.args), map(B->down), io);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL((kb_down_eval<R, V, KER_COT, SET_UNIFORM, EPI_FWD, PD_>),
+                           dim3(B->down.grid), dim3(BLOCK), B->down.smem, st,
+                           (const DownArgs<R, V> *)at(B->down.args), map(B->down), io));
     HIPCHK(hipGetLastError());
     return FN_OK;
 }

@@ -153,6 +153,8 @@ struct WorkItem {
     int64_t root;
     int32_t t0, t1;
     int32_t u0, u1;
+    int32_t lead; // the first item of its root (forms the root's leaf locals)
+    int32_t pad;
 };
 
 } // namespace fn

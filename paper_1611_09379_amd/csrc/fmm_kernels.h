@@ -618,7 +618,14 @@ struct DownArgs {
                              // at FLAG_DENSE (their near field would be
                              // quadratic in the leaf size)
     int32_t io_index;        // batched launches: entry of the IoPtr table
+    V *leaf_loc;             // local expansions of the leaves, PD per leaf
 };
+
+// Phases of the downward pass: the translations down to the leaf locals
+// (written to leaf_loc), then the evaluation at the targets (reading them).
+// Split in two kernels, the evaluation runs at a much higher occupancy than
+// the translations' register-held operator tiles allow.
+enum { PH_TRANS = 1, PH_EVAL = 2 };
 
 // Register-held operator tiles of one wave (row tile rt of PD rows).
 template <typename R, int PD>
@@ -740,7 +747,7 @@ __device__ __forceinline__ V horner4(const R *base, int RS, int row, R u)
     const R u2 = u * u, u4 = u2 * u2;
     V c0 = ld_coef<R, V>(base, RS, row, P - 4), c1 = ld_coef<R, V>(base, RS, row, P - 3);
     V c2 = ld_coef<R, V>(base, RS, row, P - 2), c3 = ld_coef<R, V>(base, RS, row, P - 1);
-#pragma unroll
+#pragma unroll 2 // fully unrolled, the loads of all P coefficients get hoisted
     for (int n = P - 8; n >= 0; n -= 4) {
         V t0 = vscale(c0, u4), t1 = vscale(c1, u4), t2 = vscale(c2, u4), t3 = vscale(c3, u4);
         vadd(t0, ld_coef<R, V>(base, RS, row, n));
@@ -997,7 +1004,7 @@ __device__ __forceinline__ double near_log(const DownArgs<R, V> &a, int64_t tm,
     return acc - near_log_background(tm, tth, leaf, l, N);
 }
 
-template <typename R, typename V, int KER, int SRC, int EPI, int PD>
+template <typename R, typename V, int KER, int SRC, int EPI, int PD, int PH>
 __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1013,9 +1020,14 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
         if (*a.flags & FLAG_DENSE)
             return; // the plan fails; nothing is evaluated
     const WorkItem w = a.work[blk];
+    if constexpr (PH == PH_TRANS)
+        if (!w.lead)
+            return; // another item of the same root forms its leaf locals
     const int64_t R0 = w.root;
     const int lr = a.lr;
     const int64_t N = a.N;
+    R *cur = bufA;
+    if constexpr (PH == PH_TRANS) {
     const int PU = a.PU;
 
     constexpr int nrt = PD / 16;
@@ -1081,7 +1093,8 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
     __syncthreads();
     // the leaf locals end in bufA after the s levels below, which leaves
     // bufB and the source buffer free (contiguous) for the near field
-    R *cur = (s & 1) ? bufB : bufA, *nxt = (s & 1) ? bufA : bufB;
+    cur = (s & 1) ? bufB : bufA;
+    R *nxt = (s & 1) ? bufA : bufB;
     for (int n = tid; n < PD; n += BLOCK) {
         V acc = ld_coef<R, V>(bufB, RS, 0, n);
         for (int li = 1; li <= nA; ++li)
@@ -1119,8 +1132,20 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
         cur = nxt;
         nxt = t;
     }
-    const R *leafloc = cur;
+    } // PH_TRANS
     const int64_t leaf0 = R0 << s;
+    if constexpr (PH == PH_TRANS) { // the leaf locals (in bufA) go out
+        V *g = a.leaf_loc + leaf0 * PD;
+        for (int idx = tid; idx < (PD << s); idx += BLOCK)
+            g[idx] = ld_coef<R, V>(cur, RS, idx / PD, idx % PD);
+        return;
+    } else { // ... and come back for the evaluation
+        const V *g = a.leaf_loc + leaf0 * PD;
+        for (int idx = tid; idx < (PD << s); idx += BLOCK)
+            st_coef<R, V>(bufA, RS, idx / PD, idx % PD, g[idx]);
+        __syncthreads();
+    }
+    const R *leafloc = bufA;
     const double invN = 1.0 / (double)N;
     const double lscale = ldexp(1.0, a.l) * invN;
 
@@ -1275,17 +1300,24 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
 }
 
 template <typename R, typename V, int KER, int SRC, int EPI, int PD>
-__global__ void __launch_bounds__(BLOCK) k_down_eval(DownArgs<R, V> a)
+__global__ void __launch_bounds__(BLOCK) k_down_trans(DownArgs<R, V> a)
 {
-    down_eval_body<R, V, KER, SRC, EPI, PD>(a, blockIdx.x);
+    down_eval_body<R, V, KER, SRC, EPI, PD, PH_TRANS>(a, blockIdx.x);
 }
 
-// The downward pass of every problem of a batch in one launch.
+// at least 4 waves per SIMD (at most 128 VGPRs; the evaluation needs 64-112)
+template <typename R, typename V, int KER, int SRC, int EPI, int PD>
+__global__ void __launch_bounds__(BLOCK, 4) k_down_eval(DownArgs<R, V> a)
+{
+    down_eval_body<R, V, KER, SRC, EPI, PD, PH_EVAL>(a, blockIdx.x);
+}
+
+// The downward pass of every problem of a batch in one launch (each phase).
 // The forward's input and output come from the IoPtr table when it is
 // given.
-template <typename R, typename V, int KER, int SRC, int EPI, int PD>
-__global__ void __launch_bounds__(BLOCK) kb_down_eval(const DownArgs<R, V> *aa,
-                                                      BlockMap bm, const IoPtr *io)
+template <typename R, typename V, int KER, int SRC, int EPI, int PD, int PH>
+__device__ __forceinline__ void down_batched(const DownArgs<R, V> *aa, BlockMap bm,
+                                             const IoPtr *io)
 {
     int blk, nblk;
     const int t = bm_find(bm, blockIdx.x, &blk, &nblk);
@@ -1295,7 +1327,21 @@ __global__ void __launch_bounds__(BLOCK) kb_down_eval(const DownArgs<R, V> *aa,
         a.f_hit = a.f_uniform;
         a.out = reinterpret_cast<cx<R> *>(io[a.io_index].out);
     }
-    down_eval_body<R, V, KER, SRC, EPI, PD>(a, blk);
+    down_eval_body<R, V, KER, SRC, EPI, PD, PH>(a, blk);
+}
+
+template <typename R, typename V, int KER, int SRC, int EPI, int PD>
+__global__ void __launch_bounds__(BLOCK) kb_down_trans(const DownArgs<R, V> *aa, BlockMap bm,
+                                                       const IoPtr *io)
+{
+    down_batched<R, V, KER, SRC, EPI, PD, PH_TRANS>(aa, bm, io);
+}
+
+template <typename R, typename V, int KER, int SRC, int EPI, int PD>
+__global__ void __launch_bounds__(BLOCK, 4) kb_down_eval(const DownArgs<R, V> *aa,
+                                                         BlockMap bm, const IoPtr *io)
+{
+    down_batched<R, V, KER, SRC, EPI, PD, PH_EVAL>(aa, bm, io);
 }
 
 } // namespace fn

@@ -637,10 +637,10 @@ __device__ __forceinline__ void work_body(const WorkArgs &w)
             const int64_t nr = int64_t(1) << lr;
             const int32_t u0 = (int32_t)((R * N + nr - 1) >> lr);
             const int32_t u1 = (int32_t)(((R + 1) * N + nr - 1) >> lr);
-            items[pos++] = {R, t0, t1, u0, u1};
+            items[pos++] = {R, t0, t1, u0, u1, 1, 0};
         } else {
             for (int32_t a = t0; a < t1; a += tmax)
-                items[pos++] = {R, a, a + tmax < t1 ? a + tmax : t1, 0, 0};
+                items[pos++] = {R, a, a + tmax < t1 ? a + tmax : t1, 0, 0, a == t0 ? 1 : 0, 0};
         }
     }
     if (tid == 1023)
