@@ -28,6 +28,8 @@ METRIC = "(N+M)/s at rel-ℓ2 1e-12 (FP64) vs 1e-6 (mixed), N=M=2^20 fwd+inv"
 PEAK_FP64 = 78.6e12      # MI355X FP64 vector (and matrix) FLOP/s
 PEAK_FP32 = 157.3e12     # MI355X FP32 vector FLOP/s
 PEAK_HBM = 8.0e12        # B/s
+PHASES = ("fwd_plan_ms", "fwd_up_ms", "fwd_trans_ms", "fwd_eval_ms", "inv_plan_ms",
+          "inv_up_ms", "inv_trans_ms", "inv_eval_ms")
 
 
 def parse():
@@ -49,18 +51,23 @@ def parse():
     return ap.parse_args()
 
 
-def down_eval_flops(info, n_targets, n_sources):
-    """Algorithmic flops of one k_down_eval launch (forward or inverse cot FMM):
-    L2L (triangular) + 3 M2L per box of levels 3..lmax on complex data
-    (2 flops per real FMA), 3 N M / 2^lmax near-field pairs (Eq. 23) at 6 flops
-    (difference, reciprocal, complex-by-real FMA), and a P-term complex Horner
-    L2P (4 flops per term) per target."""
+def trans_flops(info):
+    """Algorithmic flops of one downward-translation launch (cot FMM, complex
+    data, real operators): per box of levels 3..lmax one triangular L2L
+    (P(P+1)/2 complex-by-real multiply-adds, 4 flops each) and 3 M2L
+    (P^2 each), i.e. 2P(P+1) + 12P^2."""
     P, l = info.nterms, info.lmax
     boxes = (1 << (l + 1)) - 8 if l >= 3 else 0
-    trans = boxes * (2 * P * (P + 1) + 12 * P * P)
-    p2p = 3.0 * n_targets * n_sources / (1 << l) * 6.0
-    l2p = n_targets * 4.0 * P
-    return trans + p2p + l2p
+    return boxes * (2 * P * (P + 1) + 12 * P * P)
+
+
+def eval_flops(info, n_targets, n_sources):
+    """Algorithmic flops of one evaluation launch: 3 N_t N_s / 2^lmax
+    near-field pairs (Eq. 23) at 6 flops (difference, reciprocal,
+    complex-by-real multiply-add) and a P-term complex Horner L2P (4 flops
+    per term) per target."""
+    P, l = info.nterms, info.lmax
+    return 3.0 * n_targets * n_sources / (1 << l) * 6.0 + n_targets * 4.0 * P
 
 
 def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
@@ -86,8 +93,9 @@ def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
     wall = time.perf_counter() - t0
 
     # phases: events on the library's stream (torch's current stream)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-    k_f, k_i, up_f, up_i, plan_f, plan_i = [], [], [], [], [], []
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    ph = {k: [] for k in ("fwd_up", "fwd_trans", "fwd_eval", "inv_up", "inv_trans",
+                          "inv_eval", "fwd_plan", "inv_plan")}
     info_f = info_i = None
     for it in range(warmup + steps):
         t = time.perf_counter()
@@ -98,25 +106,31 @@ def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
         ev[1].record()
         pf.execute_phase(f, g, 1)
         ev[2].record()
+        pf.execute_phase(f, g, 2)
+        ev[3].record()
         info_f = pf.info()
         pf.destroy()
         t = time.perf_counter()
         pi = fn.Plan.inverse(yj, eps, dtc)
         tpi = time.perf_counter() - t
-        ev[3].record()
-        pi.execute_phase(gj, fo, 0)
         ev[4].record()
-        pi.execute_phase(gj, fo, 1)
+        pi.execute_phase(gj, fo, 0)
         ev[5].record()
+        pi.execute_phase(gj, fo, 1)
+        ev[6].record()
+        pi.execute_phase(gj, fo, 2)
+        ev[7].record()
         info_i = pi.info()
         pi.destroy()
         if it >= warmup:
-            up_f.append(ev[0].elapsed_time(ev[1]))
-            k_f.append(ev[1].elapsed_time(ev[2]))
-            up_i.append(ev[3].elapsed_time(ev[4]))
-            k_i.append(ev[4].elapsed_time(ev[5]))
-            plan_f.append(tpf * 1e3)
-            plan_i.append(tpi * 1e3)
+            ph["fwd_up"].append(ev[0].elapsed_time(ev[1]))
+            ph["fwd_trans"].append(ev[1].elapsed_time(ev[2]))
+            ph["fwd_eval"].append(ev[2].elapsed_time(ev[3]))
+            ph["inv_up"].append(ev[4].elapsed_time(ev[5]))
+            ph["inv_trans"].append(ev[5].elapsed_time(ev[6]))
+            ph["inv_eval"].append(ev[6].elapsed_time(ev[7]))
+            ph["fwd_plan"].append(tpf * 1e3)
+            ph["inv_plan"].append(tpi * 1e3)
 
     # evaluation only (plan reused, Section 3.3), outside the headline
     pf = fn.Plan.forward(N, yu, eps, dtc)
@@ -139,9 +153,8 @@ def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
     return {
         "wall_s": wall, "ms_per_step": 1e3 * wall / steps,
         "exec_ms_per_step": 1e3 * exec_wall / steps,
-        "fwd_plan_ms": float(np.median(plan_f)), "inv_plan_ms": float(np.median(plan_i)),
-        "fwd_up_ms": float(np.mean(up_f)), "fwd_down_ms": float(np.mean(k_f)),
-        "inv_up_ms": float(np.mean(up_i)), "inv_down_ms": float(np.mean(k_i)),
+        **{k + "_ms": float(np.median(v) if k.endswith("plan") else np.mean(v))
+           for k, v in ph.items()},
         "info_f": info_f, "info_i": info_i, "g": g, "fo": fo,
     }
 
@@ -305,18 +318,26 @@ def main():
         acc["fwd_rel_l2_vs_oracle_64"] = float(np.linalg.norm(g_h[sel] - ref) / np.linalg.norm(ref))
 
     info_f, info_i = res["info_f"], res["info_i"]
-    fl_f = down_eval_flops(info_f, M, N)
-    fl_i = down_eval_flops(info_i, N, N)
-    kf = res["fwd_down_ms"] * 1e-3
-    ki = res["inv_down_ms"] * 1e-3
-    # dominant kernel: the forward or inverse downward pass, whichever is longer
-    if kf >= ki:
-        dom, fl, dur = "k_down_eval<double,cot,uniform sources,forward>", fl_f, kf
-    else:
-        dom, fl, dur = "k_down_eval<double,cot,sorted sources,inverse>", fl_i, ki
-    roof = {"bound": "alu", "achieved": fl / dur / 1e12, "peak": PEAK_FP64 / 1e12,
+    # dominant kernel: the longest of the downward translation and evaluation
+    # kernels of the two transforms (each timed alone with events)
+    cands = [
+        ("k_down_trans<double,cot,uniform sources,forward>", "mfma", trans_flops(info_f),
+         res["fwd_trans_ms"]),
+        ("k_down_eval<double,cot,uniform sources,forward>", "alu",
+         eval_flops(info_f, M, N), res["fwd_eval_ms"]),
+        ("k_down_trans<double,cot,sorted sources,inverse>", "mfma", trans_flops(info_i),
+         res["inv_trans_ms"]),
+        ("k_down_eval<double,cot,sorted sources,inverse>", "alu",
+         eval_flops(info_i, N, N), res["inv_eval_ms"]),
+    ]
+    dom, bound, fl, dur_ms = max(cands, key=lambda c: c[3])
+    dur = dur_ms * 1e-3
+    roof = {"bound": bound, "achieved": fl / dur / 1e12, "peak": PEAK_FP64 / 1e12,
             "unit": "TFLOP/s", "frac": fl / dur / PEAK_FP64, "traffic": None,
-            "kernel": dom, "flops_per_launch": fl, "avg_launch_ms": dur * 1e3}
+            "kernel": dom, "flops_per_launch": fl, "avg_launch_ms": dur_ms,
+            "others": {c[0]: {"bound": c[1], "tflops": c[2] / (c[3] * 1e-3) / 1e12,
+                              "frac": c[2] / (c[3] * 1e-3) / PEAK_FP64, "ms": c[3]}
+                       for c in cands}}
 
     out = {
         "metric": METRIC,
@@ -333,9 +354,7 @@ def main():
                            "nterms": info_f.nterms},
                    "inv": {"p": info_i.p, "q": info_i.q, "lmax": info_i.lmax,
                            "nterms": info_i.nterms}},
-        "phases_ms": {k: round(res[k], 4) for k in
-                      ("fwd_plan_ms", "fwd_up_ms", "fwd_down_ms", "inv_plan_ms",
-                       "inv_up_ms", "inv_down_ms")},
+        "phases_ms": {k: round(res[k], 4) for k in PHASES},
         "exec_only": {"ms_per_step": res["exec_ms_per_step"],
                       "value": (N + M) / (res["exec_ms_per_step"] * 1e-3)},
         "accuracy": acc,
@@ -351,9 +370,7 @@ def main():
                  "eps": 1e-6,
                  "speedup_vs_f64": res["ms_per_step"] / rm["ms_per_step"],
                  "exec_only_ms_per_step": rm["exec_ms_per_step"],
-                 "phases_ms": {k: round(rm[k], 4) for k in
-                               ("fwd_plan_ms", "fwd_up_ms", "fwd_down_ms", "inv_plan_ms",
-                                "inv_up_ms", "inv_down_ms")},
+                 "phases_ms": {k: round(rm[k], 4) for k in PHASES},
                  "inv_roundtrip_rel_l2": float(np.linalg.norm(fo_m - f_h) / np.linalg.norm(f_h))}
         if not args.no_cpu_baseline:
             import oracle

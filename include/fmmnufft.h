@@ -119,14 +119,14 @@ int nufft_plan_inv(fn_plan **plan, int64_t N, const double *y, double eps,
  * synchronisation. */
 int nufft_execute(fn_plan *plan, const void *in, void *out, void *stream);
 
-/* One kernel of nufft_execute: phase 0 is the upward pass (P2M at the leaves,
- * M2M to level 2, level-2 regular part), phase 1 the downward pass with the
- * evaluation at the targets (M2L, L2L, L2P, near field, epilogue).
- * nufft_execute is phase 0 followed by phase 1 on the same stream; calling
- * them separately lets a caller bracket each kernel with events.  Phase 1
- * reads the plan workspace phase 0 wrote, so the two must be enqueued in
- * order, with the same input, and without another execute of the same plan
- * between them. */
+/* One part of nufft_execute: phase 0 is the upward pass (P2M at the leaves,
+ * M2M to level 2, level-2 regular part), phase 1 the downward translations
+ * (M2L, L2L down to the leaf locals; one kernel), phase 2 the evaluation at
+ * the targets (L2P, near field, epilogue; one kernel).  nufft_execute is
+ * phases 0, 1, 2 in order on one stream; calling them separately lets a
+ * caller bracket each with events.  Each phase reads the plan workspace the
+ * previous one wrote, so the three must be enqueued in order, with the same
+ * input, and without another execute of the same plan between them. */
 int nufft_execute_phase(fn_plan *plan, const void *in, void *out, int phase,
                         void *stream);
 

@@ -212,8 +212,8 @@ class Plan:
     __call__ = execute
 
     def execute_phase(self, x, out, phase: int):
-        """One kernel of execute (0: upward pass, 1: downward pass and
-        evaluation); both must be enqueued in order with the same x."""
+        """One part of execute (0: upward pass, 1: downward translations,
+        2: evaluation); the three must be enqueued in order with the same x."""
         _check(load_library().nufft_execute_phase(
             self._h, _dev_ptr(x, "input"), _dev_ptr(out, "output"), phase,
             _stream()))

@@ -609,18 +609,25 @@ static int launch_up(const FmmSetup &F, UpArgs<R, V> ua, hipStream_t st)
 }
 
 template <typename R, typename V, int KER, int SRC, int EPI>
+// The downward pass: its translation kernel (which = 1), its evaluation
+// kernel (which = 2), or both (which < 0).
 static int launch_down(const fn_plan *P, const FmmSetup &F, const DownArgs<R, V> &da,
-                       hipStream_t st)
+                       hipStream_t st, int which = -1)
 {
     if (P->nwork == 0)
         return FN_OK;
-    FN_DISPATCH16(F.PD, PD_,
-                  hipLaunchKernelGGL((k_down_trans<R, V, KER, SRC, EPI, PD_>),
-                                     dim3(P->nwork), dim3(BLOCK), F.dn_smem, st, da);
-                  HIPCHK(hipGetLastError());
-                  hipLaunchKernelGGL((k_down_eval<R, V, KER, SRC, EPI, PD_>),
-                                     dim3(P->nwork), dim3(BLOCK), F.dn_smem, st, da));
-    HIPCHK(hipGetLastError());
+    if (which != 2) {
+        FN_DISPATCH16(F.PD, PD_,
+                      hipLaunchKernelGGL((k_down_trans<R, V, KER, SRC, EPI, PD_>),
+                                         dim3(P->nwork), dim3(BLOCK), F.dn_smem, st, da));
+        HIPCHK(hipGetLastError());
+    }
+    if (which != 1) {
+        FN_DISPATCH16(F.PD, PD_,
+                      hipLaunchKernelGGL((k_down_eval<R, V, KER, SRC, EPI, PD_>),
+                                         dim3(P->nwork), dim3(BLOCK), F.dn_smem, st, da));
+        HIPCHK(hipGetLastError());
+    }
     return FN_OK;
 }
 
@@ -903,7 +910,7 @@ static int exec_fwd(fn_plan *P, const void *in, void *out, int phase,
     int rc = get_tables<R>(KER_COT, F.PU, F.PD, F.q, &T);
     if (rc)
         return rc;
-    if (phase != 1) {
+    if (phase <= 0) {
         UpArgs<R, V> ua{};
         fill_up(P, F, T, ua);
         ua.f_uniform = (const cx<R> *)in;
@@ -919,7 +926,7 @@ static int exec_fwd(fn_plan *P, const void *in, void *out, int phase,
     da.tgt_pt = (const SortedPt *)P->spt.p;
     da.out = (cx<R> *)out;
     da.f_hit = (const cx<R> *)in;
-    return launch_down<R, V, KER_COT, SET_UNIFORM, EPI_FWD>(P, F, da, st);
+    return launch_down<R, V, KER_COT, SET_UNIFORM, EPI_FWD>(P, F, da, st, phase);
 }
 
 // --------------------------------------------------------- inverse plan
@@ -1026,7 +1033,7 @@ static int exec_inv(fn_plan *P, const void *in, void *out, int phase,
         return rc;
     const SortedSet src = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
                            (const double *)P->sth.p, (const int32_t *)P->sperm.p};
-    if (phase != 1) {
+    if (phase <= 0) {
         UpArgs<R, V> ua{};
         fill_up(P, F, T, ua);
         ua.src = src;
@@ -1050,7 +1057,7 @@ static int exec_inv(fn_plan *P, const void *in, void *out, int phase,
     da.chat = (const double *)P->chat.p;
     da.hit = (const int32_t *)P->hit.p;
     da.gin = (const cx<R> *)in;
-    return launch_down<R, V, KER_COT, SET_SORTED, EPI_INV>(P, F, da, st);
+    return launch_down<R, V, KER_COT, SET_SORTED, EPI_INV>(P, F, da, st, phase);
 }
 
 // ------------------------------------------------------------------ ABI
@@ -1824,8 +1831,8 @@ int nufft_execute(fn_plan *plan, const void *in, void *out, void *stream)
 int nufft_execute_phase(fn_plan *plan, const void *in, void *out, int phase,
                         void *stream)
 {
-    if (phase != 0 && phase != 1)
-        return fail(FN_EINVAL, "phase must be 0 or 1");
+    if (phase < 0 || phase > 2)
+        return fail(FN_EINVAL, "phase must be 0, 1 or 2");
     return execute(plan, in, out, phase, stream);
 }
 
