@@ -28,6 +28,16 @@ METRIC = "(N+M)/s at rel-ℓ2 1e-12 (FP64) vs 1e-6 (mixed), N=M=2^20 fwd+inv"
 PEAK_FP64 = 78.6e12      # MI355X FP64 vector (and matrix) FLOP/s
 PEAK_FP32 = 157.3e12     # MI355X FP32 vector FLOP/s
 PEAK_HBM = 8.0e12        # B/s
+# HBM bytes per launch of the dominant kernel from FETCH_SIZE and WRITE_SIZE
+# (rocprofv3 --pmc, one counter per run), each scaled by what the counter
+# reads for a plain 256 MiB elementwise kernel (fetch x2.000, write x1.000).
+# Valid only for the kernel sources they were taken on: any change to them
+# turns the figure back into null until the counters are taken again.
+TRAFFIC = {
+    "k_down_eval<double,cot,uniform sources,forward>": {
+        "src_sha256": "f4ba21dd154a69e43b64c4f3c88f3cc6ca695b116d904c60b3517934dceb0666", "fetch": 44439106, "write": 34123861,
+        "summary": "profiles/down_eval_fwd_2p20_traffic.txt"},
+}
 PHASES = ("fwd_plan_ms", "fwd_up_ms", "fwd_trans_ms", "fwd_eval_ms", "inv_plan_ms",
           "inv_up_ms", "inv_trans_ms", "inv_eval_ms")
 
@@ -49,6 +59,23 @@ def parse():
                          "writes 256 MiB (known byte counts for scaling "
                          "memory-traffic counters)")
     return ap.parse_args()
+
+
+def kernel_sources_sha256():
+    import hashlib
+    d = os.path.join(ROOT, "paper_1611_09379_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def traffic_of(kernel):
+    t = TRAFFIC.get(kernel)
+    if t is None or t["src_sha256"] != kernel_sources_sha256():
+        return None
+    return t["fetch"] + t["write"]
 
 
 def trans_flops(info):
@@ -333,7 +360,7 @@ def main():
     dom, bound, fl, dur_ms = max(cands, key=lambda c: c[3])
     dur = dur_ms * 1e-3
     roof = {"bound": bound, "achieved": fl / dur / 1e12, "peak": PEAK_FP64 / 1e12,
-            "unit": "TFLOP/s", "frac": fl / dur / PEAK_FP64, "traffic": None,
+            "unit": "TFLOP/s", "frac": fl / dur / PEAK_FP64, "traffic": traffic_of(dom), "traffic_unit": "bytes per launch",
             "kernel": dom, "flops_per_launch": fl, "avg_launch_ms": dur_ms,
             "others": {c[0]: {"bound": c[1], "tflops": c[2] / (c[3] * 1e-3) / 1e12,
                               "frac": c[2] / (c[3] * 1e-3) / PEAK_FP64, "ms": c[3]}
