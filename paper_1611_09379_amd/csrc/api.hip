@@ -493,30 +493,34 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_
     do {
         const int d = std::min(first ? 4 : 5, lb - 2);
         F.band[F.nbands++] = {lb, d, first ? 1 : 0, 1 << (lb - d),
-                              (size_t)((1 << d) + std::max((1 << d) / 2, 1)) * F.RSu * es};
+                              (size_t)(1 << d) * F.RSu * es};
         lb -= d;
         first = false;
     } while (lb > 2);
-    // first band: LDS staging of its sources (uniform grid with an equal
-    // number B in every leaf: the weights; sorted sources: coordinates and
-    // weights of up to twice the mean count, else they are read in place)
-    {
-        const int nbot = 1 << F.band[0].d;
-        size_t bytes = 0;
-        if (!sorted_src) {
+    // every band: the level buffer of its bottom level, and the buffer of
+    // the level above it, which in the first band holds the staged sources
+    // until the P2M is done (uniform grid with an equal number B in every
+    // leaf: the weights; sorted sources: coordinates and weights of up to
+    // 1.25 times the mean count plus 64, else they are read in place)
+    for (int b = 0; b < F.nbands; ++b) {
+        const int nbot = 1 << F.band[b].d;
+        size_t bytes = (size_t)std::max(nbot / 2, 1) * F.RSu * es;
+        if (b == 0 && !sorted_src) {
             if (kernel == KER_COT && uniform_leaf_pts(P) > 0)
-                bytes = (size_t)nbot * uniform_leaf_pts(P) * 2 * es;
-        } else {
+                bytes = std::max(bytes, (size_t)nbot *
+                                            uni_stage_stride(uniform_leaf_pts(P), es) * es);
+        } else if (b == 0) {
             const int64_t mean = (P->N + (int64_t(1) << P->l) - 1) >> P->l;
             const size_t per = es * (kernel == KER_COT ? 3 : 1);
             const size_t room = lim > F.band[0].smem + 64 ? lim - F.band[0].smem - 64 : 0;
-            int64_t cap = std::min<int64_t>(2 * nbot * mean + 64, (int64_t)(room / per) - 4);
+            int64_t cap = std::min<int64_t>(nbot * mean + nbot * mean / 4 + 64,
+                                            (int64_t)(room / per) - 4);
             cap = std::min<int64_t>(cap, 4096) & ~int64_t(3);
             F.stage_cap = cap >= 64 ? (int)cap : 0;
             if (F.stage_cap)
-                bytes = (size_t)F.stage_cap * per;
+                bytes = std::max(bytes, (size_t)F.stage_cap * per);
         }
-        F.band[0].smem += bytes;
+        F.band[b].smem += bytes;
     }
     for (int b = 0; b < F.nbands; ++b)
         if (F.band[b].smem > lim)
@@ -602,8 +606,9 @@ static int launch_up(const FmmSetup &F, UpArgs<R, V> ua, hipStream_t st)
                                          F.band[b].smem, st, ua));
         HIPCHK(hipGetLastError());
     }
-    hipLaunchKernelGGL((k_regular<R, V, KER>), dim3(1), dim3(BLOCK), F.reg_smem, st,
-                       ua, F.PU);
+    FN_DISPATCH16(F.PU, PU_,
+                  hipLaunchKernelGGL((k_regular<R, V, KER, PU_>), dim3(1), dim3(BLOCK),
+                                     F.reg_smem, st, ua));
     HIPCHK(hipGetLastError());
     return FN_OK;
 }
@@ -1460,8 +1465,10 @@ static int launch_batch_eval(fn_batch *B, hipStream_t st)
                                          (const UpArgs<R, V> *)at(L.args), map(L), io));
         HIPCHK(hipGetLastError());
     }
-    hipLaunchKernelGGL((kb_regular<R, V, KER_COT>), dim3(B->reg.grid), dim3(BLOCK),
-                       B->reg.smem, st, (const UpArgs<R, V> *)at(B->reg.args), B->PU);
+    FN_DISPATCH16(B->PU, PU_,
+                  hipLaunchKernelGGL((kb_regular<R, V, KER_COT, PU_>), dim3(B->reg.grid),
+                                     dim3(BLOCK), B->reg.smem, st,
+                                     (const UpArgs<R, V> *)at(B->reg.args)));
     HIPCHK(hipGetLastError());
     FN_DISPATCH16(
         B->PD, PD_,

@@ -34,6 +34,15 @@ __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b)
 
 // First multipole / local coefficient of level L in the packed per-level
 // arrays (levels 2..lmax, 2^L boxes each).
+// Leaf stride (elements) of uniform-grid weights staged in LDS for the
+// matrix-core P2M: B complex weights per leaf, padded so that consecutive
+// leaves start 8 elements apart modulo the 256-byte bank cycle.
+__host__ __device__ __forceinline__ int uni_stage_stride(int B, int es)
+{
+    const int W = 256 / es;
+    return 2 * B + (((8 - 2 * B) % W) + W) % W;
+}
+
 __host__ __device__ __forceinline__ int64_t lev_off(int L, int P)
 {
     return ((int64_t(1) << L) - 4) * (int64_t)P;

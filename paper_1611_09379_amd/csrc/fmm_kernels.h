@@ -269,13 +269,46 @@ __device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, int64_t b,
 
 // P2M from sources staged in LDS: relative coordinates sv and (cot kernel)
 // weights sw of the sources [j0, j1) of one leaf, moments m0 .. m0+CHS-1.
+// Four sources at a time, their powers v^m0 formed as independent chains;
+// each moment still sums its sources in order.
 template <typename R, typename V, int KER>
 __device__ __forceinline__ void p2m_staged(const R *sv, const cx<R> *sw, int j0, int j1,
                                            int m0, double r, V *acc)
 {
     for (int c = 0; c < CHS; ++c)
         acc[c] = vzero<V>();
-    for (int j = j0; j < j1; ++j) {
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+        R v[4], sq[4], pw[4];
+        V w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v[u] = sv[j + u];
+            sq[u] = v[u];
+            pw[u] = R(1);
+            if constexpr (KER == KER_COT)
+                w[u] = sw[j + u];
+            else
+                w[u] = R(1);
+        }
+        for (int e = m0; e; e >>= 1) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (e & 1)
+                    pw[u] *= sq[u];
+                sq[u] *= sq[u];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CHS; ++c) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                vfma(acc[c], pw[u], w[u]);
+                pw[u] *= v[u];
+            }
+        }
+    }
+    for (; j < j1; ++j) {
         const R v = sv[j];
         R pw = ipow(v, m0);
         V w;
@@ -300,34 +333,56 @@ __device__ __forceinline__ void p2m_staged(const R *sv, const cx<R> *sw, int j0,
 // P2M on the matrix cores for uniform sources with B points in every leaf:
 // a[m][(leaf, comp)] = sum_i v_i^m f[leaf B + i], v_i = (2i - B)/B, i.e. a
 // GEMM whose operator V^T (PU x B) is the same for every leaf.  f holds the
-// launch's nbot B weights, staged in LDS.
+// launch's nbot B weights, staged in LDS with leaf stride SB.  Each wave
+// keeps one 16-row tile of V^T in registers (its powers formed once, as
+// independent chains) and takes every column tile of that row tile.
+constexpr int P2M_KMAX = 16; // B <= 64
+
 template <typename R, typename V, int PU>
 __device__ __forceinline__ void p2m_mfma(const UpArgs<R, V> &a, int64_t first,
                                          int nbot, R *buf, int RS, V *g,
-                                         int lane, int wave, const R *f)
+                                         int lane, int wave, const R *f, int SB)
 {
     constexpr int NC = 2; // cot kernel: complex weights
     using A = typename acc_t<R>::type;
     constexpr int nrt = PU / 16;
+    constexpr int used = (4 / nrt) * nrt;
+    if (wave >= used)
+        return;
     const int B = a.leaf_pts;
     const int nks = B / 4;
-    const int ntile = nrt * ((NC * nbot + 15) / 16);
-    for (int tile = wave; tile < ntile; tile += 4) {
-        const int rt = tile % nrt, ct = tile / nrt;
+    const int rt = wave % nrt;
+    const int m = 16 * rt + (lane & 15); // A row of this lane
+    R av[P2M_KMAX], vv[P2M_KMAX];
+#pragma unroll
+    for (int ks = 0; ks < P2M_KMAX; ++ks) {
+        const int k = 4 * ks + (lane >> 4);
+        vv[ks] = (R)((double)(2 * k - B) / (double)B);
+        av[ks] = R(1);
+    }
+    for (int e = m; e; e >>= 1) {
+#pragma unroll
+        for (int ks = 0; ks < P2M_KMAX; ++ks) {
+            if (e & 1)
+                av[ks] *= vv[ks];
+            vv[ks] *= vv[ks];
+        }
+    }
+    const int nct = (NC * nbot + 15) / 16;
+    for (int ct = wave / nrt; ct < nct; ct += used / nrt) {
         const int j = 16 * ct + (lane & 15);
         const int i = j / NC, c = j % NC;
         const bool valid = i < nbot;
-        const int m = 16 * rt + (lane & 15); // A row of this lane
-        const R *fp = f + ((valid ? i : 0) * B) * NC + c; // f staged in LDS
+        const R *fp = f + (valid ? i : 0) * SB + c + (lane >> 4) * NC;
         A acc = {0, 0, 0, 0};
-        for (int ks = 0; ks < nks; ++ks) {
-            const int k = 4 * ks + (lane >> 4);
-            const R v = (R)((double)(2 * k - B) / (double)B);
-            const R av = ipow(v, m);
-            R bv = fp[k * NC];
-            if (!valid)
-                bv = R(0);
-            acc = mma(av, bv, acc);
+#pragma unroll
+        for (int ks = 0; ks < P2M_KMAX; ++ks) {
+            if (ks < nks) {
+                R bv = fp[4 * ks * NC];
+                if (!valid)
+                    bv = R(0);
+                acc = mma(av[ks], bv, acc);
+            }
         }
         if (valid) {
 #pragma unroll
@@ -361,16 +416,20 @@ __device__ __forceinline__ void m2m_level(const R (&am)[PU / 4], int rt,
         A al = {0, 0, 0, 0}, ar = {0, 0, 0, 0};
 #pragma unroll
         for (int ks = 0; ks < PU / 4; ++ks) {
-            const int m = 4 * ks + (lane >> 4);
-            R bl = cl[m * NC], br = cr[m * NC];
-            if (!valid) {
-                bl = R(0);
-                br = R(0);
+            // the operator is lower triangular: rows below 16 (rt + 1) take
+            // no moment of order 16 (rt + 1) or more
+            if (ks < 4 * (rt + 1)) {
+                const int m = 4 * ks + (lane >> 4);
+                R bl = cl[m * NC], br = cr[m * NC];
+                if (!valid) {
+                    bl = R(0);
+                    br = R(0);
+                }
+                if (m & 1)
+                    br = -br;
+                al = mma(am[ks], bl, al);
+                ar = mma(am[ks], br, ar);
             }
-            if (m & 1)
-                br = -br;
-            al = mma(am[ks], bl, al);
-            ar = mma(am[ks], br, ar);
         }
         if (valid) {
 #pragma unroll
@@ -399,17 +458,21 @@ __device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk)
     R *buf1 = buf0 + (size_t)nbot * RS;
     if (a.first_band) {
         V *g = a.mp + lev_off(lb, PU);
-        // staging area for the sources, after the two level buffers
-        R *stage = buf1 + (size_t)(nbot / 2 > 0 ? nbot / 2 : 1) * RS;
+        // staging area for the sources: the second level buffer, which the
+        // M2M only writes after the P2M is done with the sources
+        R *stage = buf1;
         bool done = false;
         if constexpr (SRC == SET_UNIFORM && KER == KER_COT) {
             if (a.leaf_pts > 0) {
-                const int nf = nbot * a.leaf_pts * 2;
-                const R *f = reinterpret_cast<const R *>(a.f_uniform) + first * a.leaf_pts * 2;
-                for (int i = tid; i < nf; i += BLOCK)
-                    stage[i] = f[i];
+                const int bn = a.leaf_pts * 2, SB = uni_stage_stride(a.leaf_pts, sizeof(R));
+                const int nf = nbot * bn;
+                const R *f = reinterpret_cast<const R *>(a.f_uniform) + first * bn;
+                for (int i = tid; i < nf; i += BLOCK) {
+                    const int leaf = i / bn;
+                    stage[i + (SB - bn) * leaf] = f[i];
+                }
                 __syncthreads();
-                p2m_mfma<R, V, PU>(a, first, nbot, buf0, RS, g, lane, wave, stage);
+                p2m_mfma<R, V, PU>(a, first, nbot, buf0, RS, g, lane, wave, stage, SB);
                 done = true;
             }
         }
@@ -508,25 +571,62 @@ __global__ void __launch_bounds__(BLOCK) kb_up_band(const UpArgs<R, V> *aa, Bloc
 // the sum of the weights.  A1 holds the moments of Omega_1(P_n) about the
 // centre of P_n: the three quarters unwrapped around it, (v + 2i)^t expanded
 // for i = -1, 0, +1.
-template <typename R, typename V, int KER>
-__device__ __forceinline__ void regular_body(const UpArgs<R, V> &a, int PU)
+template <typename R, typename V, int KER, int PU>
+__device__ __forceinline__ void regular_body(const UpArgs<R, V> &a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int PD = a.PD;
+    const int PD = a.PD; // at most 64
     R *tb = reinterpret_cast<R *>(smem_raw);      // PU x PU
     R *t1 = tb + PU * PU;                          // PU x PD
     R *t2 = t1 + PU * PD;                          // PU x PD
     V *a2 = reinterpret_cast<V *>(t2 + PU * PD);   // 4 x PU
     V *A1 = a2 + 4 * PU;                           // 4 x PU
     const int tid = threadIdx.x;
-    for (int i = tid; i < PU * PU; i += BLOCK)
-        tb[i] = a.T.bin[i];
-    for (int i = tid; i < PU * PD; i += BLOCK) {
-        t1[i] = a.T.reg1[i];
-        t2[i] = a.T.reg2[i];
+    // every load of a thread is issued before the first store to LDS: one
+    // round trip to memory instead of one per loop iteration
+    {
+        constexpr int NB = (PU * PU + BLOCK - 1) / BLOCK;
+        constexpr int NR = (PU * 64 + BLOCK - 1) / BLOCK;
+        constexpr int NA = (4 * PU + BLOCK - 1) / BLOCK;
+        R rb[NB], r1[NR], r2[NR];
+        V ra[NA];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const int i = tid + k * BLOCK;
+            rb[k] = i < PU * PU ? a.T.bin[i] : R(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int i = tid + k * BLOCK;
+            r1[k] = i < PU * PD ? a.T.reg1[i] : R(0);
+            r2[k] = i < PU * PD ? a.T.reg2[i] : R(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            const int i = tid + k * BLOCK;
+            ra[k] = i < 4 * PU ? a.mp[i] : vzero<V>(); // level 2 is the first level of mp
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const int i = tid + k * BLOCK;
+            if (i < PU * PU)
+                tb[i] = rb[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int i = tid + k * BLOCK;
+            if (i < PU * PD) {
+                t1[i] = r1[k];
+                t2[i] = r2[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            const int i = tid + k * BLOCK;
+            if (i < 4 * PU)
+                a2[i] = ra[k];
+        }
     }
-    for (int i = tid; i < 4 * PU; i += BLOCK)
-        a2[i] = a.mp[i]; // level 2 is the first level of mp
     __syncthreads();
     for (int idx = tid; idx < 4 * PU; idx += BLOCK) {
         const int q = idx / PU, t = idx - q * PU;
@@ -548,6 +648,7 @@ __device__ __forceinline__ void regular_body(const UpArgs<R, V> &a, int PU)
         const V *o = a2 + ((q + 2) & 3) * PU;
         const V *n1 = A1 + q * PU;
         V acc = vzero<V>();
+#pragma unroll 8
         for (int t = 0; t < PU; ++t) {
             vfma(acc, t1[t * PD + lo], n1[t]);
             vfma(acc, t2[t * PD + lo], o[t]);
@@ -568,17 +669,17 @@ __device__ __forceinline__ void regular_body(const UpArgs<R, V> &a, int PU)
     }
 }
 
-template <typename R, typename V, int KER>
-__global__ void __launch_bounds__(BLOCK) k_regular(UpArgs<R, V> a, int PU)
+template <typename R, typename V, int KER, int PU>
+__global__ void __launch_bounds__(BLOCK) k_regular(UpArgs<R, V> a)
 {
-    regular_body<R, V, KER>(a, PU);
+    regular_body<R, V, KER, PU>(a);
 }
 
 // One workgroup per problem of a batch.
-template <typename R, typename V, int KER>
-__global__ void __launch_bounds__(BLOCK) kb_regular(const UpArgs<R, V> *aa, int PU)
+template <typename R, typename V, int KER, int PU>
+__global__ void __launch_bounds__(BLOCK) kb_regular(const UpArgs<R, V> *aa)
 {
-    regular_body<R, V, KER>(aa[blockIdx.x], PU);
+    regular_body<R, V, KER, PU>(aa[blockIdx.x]);
 }
 
 // ------------------------------------------------------------ k_down_eval
