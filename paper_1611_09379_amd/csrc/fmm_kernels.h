@@ -788,12 +788,16 @@ __device__ __forceinline__ void m2l_tiles(const DownOps<R, PD> &o, int rt, int c
             n4 = mma(o.a4[ks], b2, n4);
             a6 = mma(o.a6[ks], b3, a6);
             if constexpr (WITH_L2L) {
-                R b4 = sp[m * NC];
-                if (!valid)
-                    b4 = R(0);
-                if (odd && !left)
-                    b4 = -b4;
-                al = mma(o.al[ks], b4, al);
+                // the L2L operator is triangular: output moments of row tile
+                // rt take no input moment below 16 rt
+                if (ks >= 4 * rt) {
+                    R b4 = sp[m * NC];
+                    if (!valid)
+                        b4 = R(0);
+                    if (odd && !left)
+                        b4 = -b4;
+                    al = mma(o.al[ks], b4, al);
+                }
             }
         }
         if (!valid)
@@ -897,23 +901,35 @@ __device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
             const int32_t base = (int32_t)(tm - k0);
             const cx<R> *fp = fs + (k0 - K0);
             const int32_t cnt = (int32_t)(k1 - k0);
-            // four independent chains: the reciprocals of four pairs overlap
+            // binary64: two pairs at a time, each pair over one reciprocal,
+            // w0/d0 + w1/d1 = (w0 d1 + w1 d0) / (d0 d1) (no distance is
+            // zero: exact hits never reach the near field); binary32 keeps
+            // one reciprocal per pair, whose rounding it can afford less
             cx<R> a1 = {R(0), R(0)}, a2 = {R(0), R(0)}, a3 = {R(0), R(0)};
             int32_t i = 0;
             for (; i + 4 <= cnt; i += 4) {
-                const R r0 = recip((R)((double)(base - i) + tth));
-                const R r1 = recip((R)((double)(base - i - 1) + tth));
-                const R r2 = recip((R)((double)(base - i - 2) + tth));
-                const R r3 = recip((R)((double)(base - i - 3) + tth));
+                const R d0 = (R)((double)(base - i) + tth);
+                const R d1 = (R)((double)(base - i - 1) + tth);
+                const R d2 = (R)((double)(base - i - 2) + tth);
+                const R d3 = (R)((double)(base - i - 3) + tth);
                 const cx<R> w0 = fp[i], w1 = fp[i + 1], w2 = fp[i + 2], w3 = fp[i + 3];
-                acc.re = fma(w0.re, r0, acc.re);
-                acc.im = fma(w0.im, r0, acc.im);
-                a1.re = fma(w1.re, r1, a1.re);
-                a1.im = fma(w1.im, r1, a1.im);
-                a2.re = fma(w2.re, r2, a2.re);
-                a2.im = fma(w2.im, r2, a2.im);
-                a3.re = fma(w3.re, r3, a3.re);
-                a3.im = fma(w3.im, r3, a3.im);
+                if constexpr (sizeof(R) == 8) {
+                    const R r01 = recip(d0 * d1), r23 = recip(d2 * d3);
+                    acc.re = fma(fma(w0.re, d1, w1.re * d0), r01, acc.re);
+                    acc.im = fma(fma(w0.im, d1, w1.im * d0), r01, acc.im);
+                    a1.re = fma(fma(w2.re, d3, w3.re * d2), r23, a1.re);
+                    a1.im = fma(fma(w2.im, d3, w3.im * d2), r23, a1.im);
+                } else {
+                    const R r0 = recip(d0), r1 = recip(d1), r2 = recip(d2), r3 = recip(d3);
+                    acc.re = fma(w0.re, r0, acc.re);
+                    acc.im = fma(w0.im, r0, acc.im);
+                    a1.re = fma(w1.re, r1, a1.re);
+                    a1.im = fma(w1.im, r1, a1.im);
+                    a2.re = fma(w2.re, r2, a2.re);
+                    a2.im = fma(w2.im, r2, a2.im);
+                    a3.re = fma(w3.re, r3, a3.re);
+                    a3.im = fma(w3.im, r3, a3.im);
+                }
             }
             for (; i < cnt; ++i) {
                 const R rd = recip((R)((double)(base - i) + tth));
@@ -997,20 +1013,32 @@ __device__ __forceinline__ cx<R> near_cot_staged(const NearStage<R> &ns, int32_t
 {
     cx<R> a0 = {R(0), R(0)}, a1 = a0, a2 = a0, a3 = a0;
     int32_t j = j0;
+    // binary64: two pairs at a time, each pair over one reciprocal (no
+    // distance is zero: exact hits never reach the near field); binary32
+    // keeps one reciprocal per pair
     for (; j + 4 <= j1; j += 4) {
-        const R r0 = recip((R)near_dist(tmr - ns.m[j], tth, ns.th[j]));
-        const R r1 = recip((R)near_dist(tmr - ns.m[j + 1], tth, ns.th[j + 1]));
-        const R r2 = recip((R)near_dist(tmr - ns.m[j + 2], tth, ns.th[j + 2]));
-        const R r3 = recip((R)near_dist(tmr - ns.m[j + 3], tth, ns.th[j + 3]));
+        const R d0 = (R)near_dist(tmr - ns.m[j], tth, ns.th[j]);
+        const R d1 = (R)near_dist(tmr - ns.m[j + 1], tth, ns.th[j + 1]);
+        const R d2 = (R)near_dist(tmr - ns.m[j + 2], tth, ns.th[j + 2]);
+        const R d3 = (R)near_dist(tmr - ns.m[j + 3], tth, ns.th[j + 3]);
         const cx<R> w0 = ns.w[j], w1 = ns.w[j + 1], w2 = ns.w[j + 2], w3 = ns.w[j + 3];
-        a0.re = fma(w0.re, r0, a0.re);
-        a0.im = fma(w0.im, r0, a0.im);
-        a1.re = fma(w1.re, r1, a1.re);
-        a1.im = fma(w1.im, r1, a1.im);
-        a2.re = fma(w2.re, r2, a2.re);
-        a2.im = fma(w2.im, r2, a2.im);
-        a3.re = fma(w3.re, r3, a3.re);
-        a3.im = fma(w3.im, r3, a3.im);
+        if constexpr (sizeof(R) == 8) {
+            const R r01 = recip(d0 * d1), r23 = recip(d2 * d3);
+            a0.re = fma(fma(w0.re, d1, w1.re * d0), r01, a0.re);
+            a0.im = fma(fma(w0.im, d1, w1.im * d0), r01, a0.im);
+            a1.re = fma(fma(w2.re, d3, w3.re * d2), r23, a1.re);
+            a1.im = fma(fma(w2.im, d3, w3.im * d2), r23, a1.im);
+        } else {
+            const R r0 = recip(d0), r1 = recip(d1), r2 = recip(d2), r3 = recip(d3);
+            a0.re = fma(w0.re, r0, a0.re);
+            a0.im = fma(w0.im, r0, a0.im);
+            a1.re = fma(w1.re, r1, a1.re);
+            a1.im = fma(w1.im, r1, a1.im);
+            a2.re = fma(w2.re, r2, a2.re);
+            a2.im = fma(w2.im, r2, a2.im);
+            a3.re = fma(w3.re, r3, a3.re);
+            a3.im = fma(w3.im, r3, a3.im);
+        }
     }
     for (; j < j1; ++j) {
         const R r = recip((R)near_dist(tmr - ns.m[j], tth, ns.th[j]));
@@ -1021,9 +1049,34 @@ __device__ __forceinline__ cx<R> near_cot_staged(const NearStage<R> &ns, int32_t
     return {(a0.re + a1.re) + (a2.re + a3.re), (a0.im + a1.im) + (a2.im + a3.im)};
 }
 
+// log prod |tau - sigma| over the staged sources [j, j1), folded into
+// prod x 2^expo (renormalised after every eight factors and at the end;
+// every factor is below 2^31 in grid units, so eight of them stay in range).
+template <typename R>
+__device__ __forceinline__ void log_prod_range(const NearStage<R> &ns, int32_t j, int32_t j1,
+                                               int32_t tmr, double tth, double &prod,
+                                               int &expo)
+{
+    for (; j + 8 <= j1; j += 8) {
+        double d[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            d[u] = fabs(near_dist(tmr - ns.m[j + u], tth, ns.th[j + u]));
+        const double q = ((d[0] * d[1]) * (d[2] * d[3])) * ((d[4] * d[5]) * (d[6] * d[7]));
+        int e;
+        prod = frexp(prod * q, &e);
+        expo += e;
+    }
+    double q = 1.0;
+    for (; j < j1; ++j)
+        q *= fabs(near_dist(tmr - ns.m[j], tth, ns.th[j]));
+    int e;
+    prod = frexp(prod * q, &e);
+    expo += e;
+}
+
 // Log near field from staged sources [j0, j1) without the source `self`:
-// log prod |tau - sigma|, the product kept as mantissa x 2^exponent (every
-// factor is below 2^31 in grid units, so eight of them stay in range).
+// log prod |tau - sigma|.
 template <typename R>
 __device__ __forceinline__ double near_log_staged(const NearStage<R> &ns, int32_t j0,
                                                   int32_t j1, int32_t self, int32_t tmr,
@@ -1031,25 +1084,14 @@ __device__ __forceinline__ double near_log_staged(const NearStage<R> &ns, int32_
 {
     double prod = 1.0;
     int expo = 0;
-    int32_t j = j0;
-    for (; j + 8 <= j1; j += 8) {
-        double d[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const double dd = fabs(near_dist(tmr - ns.m[j + u], tth, ns.th[j + u]));
-            d[u] = (j + u == self) ? 1.0 : dd;
-        }
-        const double q = ((d[0] * d[1]) * (d[2] * d[3])) * ((d[4] * d[5]) * (d[6] * d[7]));
-        int e;
-        prod = frexp(prod * q, &e);
-        expo += e;
+    // the source `self` (the target itself) splits the range: no test per pair
+    if (self >= j0 && self < j1) {
+        log_prod_range(ns, j0, self, tmr, tth, prod, expo);
+        log_prod_range(ns, self + 1, j1, tmr, tth, prod, expo);
+    } else {
+        log_prod_range(ns, j0, j1, tmr, tth, prod, expo);
     }
-    double q = 1.0;
-    for (; j < j1; ++j) {
-        const double dd = fabs(near_dist(tmr - ns.m[j], tth, ns.th[j]));
-        q *= (j == self) ? 1.0 : dd;
-    }
-    return log(prod * q) + (double)expo * 0.69314718055994530942;
+    return log(prod) + (double)expo * 0.69314718055994530942;
 }
 
 // Integral of log|tau - sigma| over sigma in the leaves leaf - 1 .. leaf + 1
@@ -1105,6 +1147,46 @@ __device__ __forceinline__ double near_log(const DownArgs<R, V> &a, int64_t tm,
     return acc - near_log_background(tm, tth, leaf, l, N);
 }
 
+// Rows i = 0 .. nb + 5 of the multipoles at level lev that the M2L of the
+// subtree's nb = 2^(lev - lr) boxes reads: boxes first - 3 .. first + nb + 2
+// (around the circle), their first PD moments, into registers (one batch of
+// loads, in flight while the caller works) ...
+template <typename R, typename V, int PD, int NPF>
+__device__ __forceinline__ void lev_fetch(V (&pf)[NPF], const DownArgs<R, V> &a,
+                                          int64_t R0, int lr, int lev, int tid)
+{
+    const int nb = 1 << (lev - lr);
+    const int64_t first = R0 << (lev - lr);
+    const int64_t mask = (int64_t(1) << lev) - 1;
+    const V *base = a.mp + lev_off(lev, a.PU);
+    const int n = (nb + 6) * PD;
+    // indices clamped rather than loads predicated: no control flow between
+    // the loads, so none of them waits for another
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) {
+        int e = tid + k * BLOCK;
+        e = e < n ? e : n - 1;
+        const int i = e / PD, m = e - i * PD;
+        pf[k] = base[((first - 3 + i) & mask) * a.PU + m];
+    }
+}
+
+// ... and from the registers into the LDS rows.
+template <typename R, typename V, int PD, int NPF>
+__device__ __forceinline__ void lev_stage(const V (&pf)[NPF], R *srcs, int RS, int lr,
+                                          int lev, int tid)
+{
+    const int n = ((1 << (lev - lr)) + 6) * PD;
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) {
+        const int e = tid + k * BLOCK;
+        if (e < n) {
+            const int i = e / PD, m = e - i * PD;
+            st_coef<R, V>(srcs, RS, i, m, pf[k]);
+        }
+    }
+}
+
 template <typename R, typename V, int KER, int SRC, int EPI, int PD, int PH>
 __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
 {
@@ -1134,6 +1216,12 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
     constexpr int nrt = PD / 16;
     const int used = (4 / nrt) * nrt;
     const int rt = wave % nrt, ct0 = wave / nrt, ctstep = 4 / nrt;
+    // the first level's interaction-list multipoles: in flight during the
+    // ancestors' work
+    constexpr int NPF = ((16 + 6) * PD + BLOCK - 1) / BLOCK; // subtrees of <= 4 levels
+    V pf[NPF];
+    if (lr < a.l)
+        lev_fetch<R, V, PD, NPF>(pf, a, R0, lr, lr + 1, tid);
     DownOps<R, PD> ops;
     if (wave < used) {
         load_tile<R, PD>(ops.a4, a.T.m2l4, rt, lane);
@@ -1147,15 +1235,30 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
     // R0:  u_A = rho u_R + delta,
     //      b^R_n = sum_{n' >= n} C(n', n) rho^n delta^(n'-n) b^A_n'.
     const int nA = lr - 2; // ancestors with M2L: levels 3..lr
-    // stage the three interaction-list multipoles of every ancestor
-    for (int idx = tid; idx < 3 * nA * PD; idx += BLOCK) {
-        const int row = idx / PD, m = idx - row * PD;
-        const int ai = row / 3, which = row - ai * 3;
-        const int L = ai + 3;
-        const int64_t A = R0 >> (lr - L);
-        const int o = which == 0 ? -2 : (which == 1 ? 2 : ((A & 1) ? -3 : 3));
-        const int64_t mask = (int64_t(1) << L) - 1;
-        st_coef<R, V>(srcs, RS, row, m, a.mp[lev_off(L, PU) + ((A + o) & mask) * PU + m]);
+    // stage the three interaction-list multipoles of every ancestor, every
+    // load of a thread issued before its first store
+    for (int b0 = 0; b0 < 3 * nA * PD; b0 += 4 * BLOCK) {
+        V r[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int idx = b0 + tid + k * BLOCK;
+            idx = idx < 3 * nA * PD ? idx : 3 * nA * PD - 1; // clamped: no branch
+            const int row = idx / PD, m = idx - row * PD;
+            const int ai = row / 3, which = row - ai * 3;
+            const int L = ai + 3;
+            const int64_t A = R0 >> (lr - L);
+            const int o = which == 0 ? -2 : (which == 1 ? 2 : ((A & 1) ? -3 : 3));
+            const int64_t mask = (int64_t(1) << L) - 1;
+            r[k] = a.mp[lev_off(L, PU) + ((A + o) & mask) * PU + m];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int idx = b0 + tid + k * BLOCK;
+            if (idx < 3 * nA * PD) {
+                const int row = idx / PD, m = idx - row * PD;
+                st_coef<R, V>(srcs, RS, row, m, r[k]);
+            }
+        }
     }
     // X row 0: the level-2 local of R0's quarter
     for (int n = tid; n < PD; n += BLOCK)
@@ -1185,9 +1288,15 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
         const R md2 = (R)(-2.0 * ldexp((double)((2 * R0 + 1) - ((2 * A + 1) << sh)), -sh));
         V acc = vzero<V>();
         R pw = R(1);
-        for (int np = n; np < PD; ++np) {
-            vfma(acc, a.T.l2l[np * PD + n] * pw, ld_coef<R, V>(bufA, RS, li, np));
-            pw *= md2;
+        // unrolled, with the table read unconditionally: its loads do not
+        // wait for one another
+#pragma unroll
+        for (int np = 0; np < PD; ++np) {
+            const R tv = a.T.l2l[np * PD + n];
+            if (np >= n) {
+                vfma(acc, tv * pw, ld_coef<R, V>(bufA, RS, li, np));
+                pw *= md2;
+            }
         }
         st_coef<R, V>(bufB, RS, li, n, vscale(acc, ipow(rho2, n)));
     }
@@ -1206,16 +1315,14 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
 
     // ---- the subtree's levels: L2L from the parent + M2L from the level's
     // interaction lists (sources staged in LDS, rows first - 3 ...)
+    // (the next level's sources are fetched into registers while this
+    // level's translations run)
     for (int lev = lr + 1; lev <= a.l; ++lev) {
         const int nb = 1 << (lev - lr);
-        const int64_t first = R0 << (lev - lr);
-        const int64_t mask = (int64_t(1) << lev) - 1;
-        const V *base = a.mp + lev_off(lev, PU);
-        for (int idx = tid; idx < (nb + 6) * PD; idx += BLOCK) {
-            const int i = idx / PD, m = idx - i * PD;
-            st_coef<R, V>(srcs, RS, i, m, base[((first - 3 + i) & mask) * PU + m]);
-        }
+        lev_stage<R, V, PD, NPF>(pf, srcs, RS, lr, lev, tid);
         __syncthreads();
+        if (lev < a.l)
+            lev_fetch<R, V, PD, NPF>(pf, a, R0, lr, lev + 1, tid);
         if (wave < used) {
             const R sgl = KER == KER_COT ? (R)(ldexp(2.0, lev) / 3.14159265358979323846) : R(1);
             const R lgl = (R)log(ldexp((double)N, -(lev + 1)));
