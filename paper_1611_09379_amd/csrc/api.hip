@@ -741,8 +741,8 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
     if (a.hit)
         HIPCHK(hipMemsetAsync(a.hit, 0xff, P->N * 4, st));
     if (J.lds_path) {
-        hipLaunchKernelGGL(k_keys, dim3(grid_for(a.n)), dim3(256), 0, st, a);
-        HIPCHK(hipGetLastError());
+        // grid units and keys are computed inside the histogram and
+        // placement passes
         hipLaunchKernelGGL(k_hist, dim3(a.nblk), dim3(SORT_THREADS), (size_t)nbins * 4, st, a);
         HIPCHK(hipGetLastError());
         hipLaunchKernelGGL(k_colscan, dim3(grid_for(nbins)), dim3(256), 0, st, a);
@@ -1221,7 +1221,7 @@ struct fn_batch {
     size_t reg_smem = 0;
     Buf blob, io, flags;
     std::vector<IoPtr> hio;
-    LaunchShape keys, hist, colscan, place, scan, work, reg, down, up[MAX_BANDS];
+    LaunchShape hist, colscan, place, scan, work, reg, down, up[MAX_BANDS];
     hipStream_t stream = nullptr;
     hipStream_t bs = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -1288,7 +1288,7 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
     HIPCHK(hipMemsetAsync(B->flags.p, 0, (size_t)T * 4, st));
     std::vector<SortArgs> sa;
     std::vector<WorkArgs> wa;
-    std::vector<int> nb_keys, nb_hist, nb_col, nb_one;
+    std::vector<int> nb_hist, nb_col, nb_one;
     std::vector<TreeJob> jobs(T);
     std::vector<WorkArgs> works(T);
     B->P.assign(T, nullptr);
@@ -1331,14 +1331,12 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
         const SortArgs &a = jobs[t].a;
         sa.push_back(a);
         wa.push_back(works[t]);
-        nb_keys.push_back(grid_for(a.n));
         nb_hist.push_back(a.nblk);
         nb_col.push_back(grid_for(a.nbins));
         nb_one.push_back(1);
         hist_smem = std::max(hist_smem, (size_t)a.nbins * 4);
     }
     if (!B->grp.empty()) {
-        bb.add(B->keys, sa, nb_keys);
         bb.add(B->hist, sa, nb_hist);
         B->hist.smem = hist_smem;
         bb.add(B->colscan, sa, nb_col);
@@ -1416,9 +1414,6 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
         return BlockMap{(const int32_t *)at(L.map), L.n};
     };
     if (!B->grp.empty()) {
-        const SortArgs *A = (const SortArgs *)at(B->keys.args);
-        hipLaunchKernelGGL(kb_keys, dim3(B->keys.grid), dim3(256), 0, st, A, map(B->keys));
-        HIPCHK(hipGetLastError());
         hipLaunchKernelGGL(kb_hist, dim3(B->hist.grid), dim3(SORT_THREADS), B->hist.smem, st,
                            (const SortArgs *)at(B->hist.args), map(B->hist));
         HIPCHK(hipGetLastError());

@@ -83,28 +83,18 @@ struct SortArgs {
     int *flags;
 };
 
-// Grid units and sort key (the level-(l - keyshift) box) of every point,
-// one point per thread.  If hit is given, records the index of a point that
-// lies exactly on x_m.
-__device__ __forceinline__ void keys_body(const SortArgs &a, int blk, int nblk)
+// Grid units and sort key (the level-(l - keyshift) box) of one point.  The
+// histogram and placement passes each compute them from y: cheaper than
+// writing them out once and reading them back.
+__device__ __forceinline__ int32_t point_key(const SortArgs &a, double yy, int32_t *m_out,
+                                             double *th_out, bool *ok)
 {
-    for (int64_t j = blk * (int64_t)blockDim.x + threadIdx.x; j < a.n;
-         j += (int64_t)nblk * blockDim.x) {
-        int64_t m;
-        double th;
-        if (!reduce_point(a.y[j], a.c_hi, a.c_lo, a.N, a.ymax, &m, &th))
-            atomicOr(a.flags, FLAG_BAD_Y);
-        a.um[j] = (int32_t)m;
-        a.uth[j] = th;
-        a.ukey[j] = (int32_t)(box_of(m, th, a.l, a.N) >> a.keyshift);
-        if (a.hit && th == 0.0)
-            atomicExch(&a.hit[m], (int32_t)j);
-    }
-}
-
-__global__ void __launch_bounds__(256) k_keys(SortArgs a)
-{
-    keys_body(a, blockIdx.x, gridDim.x);
+    int64_t m;
+    double th;
+    *ok = reduce_point(yy, a.c_hi, a.c_lo, a.N, a.ymax, &m, &th);
+    *m_out = (int32_t)m;
+    *th_out = th;
+    return (int32_t)(box_of(m, th, a.l, a.N) >> a.keyshift);
 }
 
 constexpr int SORT_BATCH = 8;     // points in flight per thread in the sort passes
@@ -138,15 +128,24 @@ __device__ __forceinline__ void hist_body(const SortArgs &a, int blk)
     __syncthreads();
     const int64_t j0 = (int64_t)blk * a.chunk;
     const int64_t j1 = j0 + a.chunk < a.n ? j0 + a.chunk : a.n;
-    const int32_t *__restrict__ ukey = a.ukey;
     // every lane runs every iteration (key_runs works across the wavefront)
     for (int64_t jw = j0; jw < j1; jw += SORT_THREADS * SORT_BATCH) {
         const int64_t jb = jw + threadIdx.x;
         int32_t key[SORT_BATCH];
+        double yv[SORT_BATCH];
+#pragma unroll
+        for (int u = 0; u < SORT_BATCH; ++u) { // loads clamped: all in flight
+            const int64_t j = jb + u * SORT_THREADS;
+            yv[u] = a.y[j < j1 ? j : j1 - 1];
+        }
 #pragma unroll
         for (int u = 0; u < SORT_BATCH; ++u) {
             const int64_t j = jb + u * SORT_THREADS;
-            key[u] = j < j1 ? ukey[j] : -1;
+            int32_t mm;
+            double tt;
+            bool ok;
+            const int32_t k = point_key(a, yv[u], &mm, &tt, &ok);
+            key[u] = j < j1 ? k : -1;
         }
 #pragma unroll
         for (int u = 0; u < SORT_BATCH; ++u) {
@@ -197,8 +196,24 @@ __device__ __forceinline__ void place_body(const SortArgs &a, int blk)
 {
     extern __shared__ int32_t cur[];
     const int nbins = a.nbins;
-    for (int i = threadIdx.x; i < nbins; i += SORT_THREADS)
-        cur[i] = a.off[i] + a.H[(int64_t)blk * nbins + i];
+    // the cursors: every load of a batch in flight at once (indices clamped,
+    // stores predicated)
+    const int32_t *Hb = a.H + (int64_t)blk * nbins;
+    for (int i0 = 0; i0 < nbins; i0 += 16 * SORT_THREADS) {
+        int32_t v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int i = i0 + (int)threadIdx.x + u * SORT_THREADS;
+            i = i < nbins ? i : nbins - 1;
+            v[u] = a.off[i] + Hb[i];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = i0 + (int)threadIdx.x + u * SORT_THREADS;
+            if (i < nbins)
+                cur[i] = v[u];
+        }
+    }
     __syncthreads();
     const int64_t j0 = (int64_t)blk * a.chunk;
     const int64_t j1 = j0 + a.chunk < a.n ? j0 + a.chunk : a.n;
@@ -206,15 +221,24 @@ __device__ __forceinline__ void place_body(const SortArgs &a, int blk)
     for (int64_t jw = j0; jw < j1; jw += SORT_THREADS * SORT_BATCH) {
         const int64_t jb = jw + threadIdx.x;
         int32_t key[SORT_BATCH], mm[SORT_BATCH], pos[SORT_BATCH];
-        double tt[SORT_BATCH];
+        double tt[SORT_BATCH], yv[SORT_BATCH];
+#pragma unroll
+        for (int u = 0; u < SORT_BATCH; ++u) { // loads clamped: all in flight
+            const int64_t j = jb + u * SORT_THREADS;
+            yv[u] = a.y[j < j1 ? j : j1 - 1];
+        }
 #pragma unroll
         for (int u = 0; u < SORT_BATCH; ++u) {
             const int64_t j = jb + u * SORT_THREADS;
+            bool ok;
+            const int32_t k = point_key(a, yv[u], &mm[u], &tt[u], &ok);
             key[u] = -1;
             if (j < j1) {
-                key[u] = a.ukey[j];
-                mm[u] = a.um[j];
-                tt[u] = a.uth[j];
+                key[u] = k;
+                if (!ok)
+                    atomicOr(a.flags, FLAG_BAD_Y);
+                if (a.hit && tt[u] == 0.0)
+                    atomicExch(&a.hit[mm[u]], (int32_t)j);
             }
         }
 #pragma unroll
@@ -289,8 +313,20 @@ __device__ __forceinline__ void scan_one_body(const int32_t *__restrict__ count,
 {
     extern __shared__ int32_t sv[]; // scan1_slot(SCAN1_MAX) + 1024 words
     int32_t *part = sv + scan1_slot(SCAN1_MAX);
-    for (int i = threadIdx.x; i < SCAN1_MAX; i += 1024)
-        sv[scan1_slot(i)] = i < n ? count[i] : 0;
+    // 16 loads in flight per thread (indices clamped, values masked)
+    for (int b = 0; b < SCAN1_PER; b += 16) {
+        int32_t v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = (int)threadIdx.x + (b + u) * 1024;
+            v[u] = count[i < n ? i : n - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = (int)threadIdx.x + (b + u) * 1024;
+            sv[scan1_slot(i)] = i < n ? v[u] : 0;
+        }
+    }
     __syncthreads();
     const int i0 = threadIdx.x * SCAN1_PER;
     int32_t sum = 0;
@@ -779,12 +815,6 @@ __global__ void __launch_bounds__(256)
 // ---- the same passes over a batch of point sets: one launch each, block
 // b working for problem bm_find(b) (see BlockMap)
 
-__global__ void __launch_bounds__(256) kb_keys(const SortArgs *aa, BlockMap bm)
-{
-    int blk, nblk;
-    const int t = bm_find(bm, blockIdx.x, &blk, &nblk);
-    keys_body(aa[t], blk, nblk);
-}
 
 __global__ void __launch_bounds__(SORT_THREADS) kb_hist(const SortArgs *aa, BlockMap bm)
 {
