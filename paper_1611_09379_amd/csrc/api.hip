@@ -936,8 +936,9 @@ static int exec_fwd(fn_plan *P, const void *in, void *out, int phase,
 
 // --------------------------------------------------------- inverse plan
 
-// The log-kernel FMM of the plan: logC_k at the uniform points and logD_j
-// at the sorted sources, then Chat and Dhat (Eq. p8).  Enqueues only.
+// The log-kernel FMM of the plan: log|Chat_k| at the uniform points and
+// log|Dhat_j| at the sorted sources, and from them (in the evaluation's
+// epilogue) Chat and Dhat (Eq. p8).  Enqueues only.
 static int plan_inv_logs(fn_plan *P, hipStream_t st)
 {
     using R = double;
@@ -961,10 +962,6 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
             P->tmp.push_back(*b);
     if (rc)
         return rc;
-    double *logc = (double *)tmp_alloc(P, P->N * 8);
-    double *logd = (double *)tmp_alloc(P, P->N * 8);
-    if (!logc || !logd)
-        return fail(FN_ENOMEM, "log-sum allocation failed");
     const SortedSet src = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
                            (const double *)P->sth.p, (const int32_t *)P->sperm.p};
     UpArgs<R, V> ua{};
@@ -981,19 +978,13 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     da.src = src;
     da.tgt = src;
     da.tgt_leaf = (const int32_t *)P->skey.p;
-    da.logc = logc;
-    da.logd = logd;
+    da.hit = (const int32_t *)P->hit.p;
+    da.chat_out = (double *)P->chat.p;
+    da.dhat_out = (cx<double> *)P->dhat.p;
+    da.flags_out = (int *)P->flags.p;
     da.logself = std::log(2.0 * M_PI / (double)P->N);
-    rc = launch_down<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>(P, F, da, st);
-    if (rc)
-        return rc;
-    hipLaunchKernelGGL(k_coeffs, dim3(grid_for(P->N)), dim3(256), 0, st, P->N, P->l,
-                       (const int32_t *)P->off.p, (const double *)logc, (const double *)logd,
-                       (const int32_t *)P->sm.p, (const double *)P->sth.p,
-                       (const int32_t *)P->hit.p, (double *)P->chat.p,
-                       (cx<double> *)P->dhat.p, (int *)P->flags.p);
-    HIPCHK(hipGetLastError());
-    return FN_OK;
+    // the evaluation's epilogue forms Chat and Dhat
+    return launch_down<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>(P, F, da, st);
 }
 
 template <typename R>

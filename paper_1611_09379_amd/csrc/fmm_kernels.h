@@ -713,8 +713,11 @@ struct DownArgs {
     const double *chat;      // INV: Chat_k
     const int32_t *hit;      // INV: source index j with y_j = x_k, or -1
     const cx<R> *gin;        // INV: g (input order)
-    double *logc, *logd;     // LOGCD outputs
+    double *chat_out;        // LOGCD outputs: Chat_k (uniform points) and
+    cx<double> *dhat_out;    // Dhat_j (sorted sources), Eq. (p8)
     double logself;          // LOGCD: log(2 pi / N), the excluded self term
+    int *flags_out;          // LOGCD: FLAG_RANGE when a log-sum leaves the
+                             // range of exp
     const int *flags;        // setup error flags: sorted-source passes stop
                              // at FLAG_DENSE (their near field would be
                              // quadratic in the leaf size)
@@ -1476,6 +1479,14 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
                         (R)(-0.5 * C * ((double)W.im + hr))};
         }
     } else { // EPI_LOGCD
+        // log|Chat_k| and log|Dhat_j| by the FMM; then the coefficients of
+        // Eq. (p8), rescaled by 2^N (the scale cancels in C_k D_j):
+        //   Chat_k = (-1)^k prod_j 2 sin((x_k - y_j)/2)
+        //          = (-1)^(k + #{j: s_j > k}) exp(log|Chat_k|)  (0 on a hit),
+        //   Dhat_j = i e^{-i N y_j / 2} / prod_{i != j} 2 sin((y_j - y_i)/2)
+        //          = i (-1)^(m_j) e^{-i pi th_j} (-1)^(#{i: s_i > s_j}) exp(log|Dhat_j|),
+        // with the points sorted along the circle, so #{i: s_i > s_j} =
+        // N - 1 - rank.
         for (int32_t k = w.u0 + tid; k < w.u1; k += BLOCK) {
             const int64_t leaf = uni_leaf(k, a.l, N, lscale);
             const int il = (int)(leaf - leaf0);
@@ -1486,7 +1497,43 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
                                             (int32_t)(k - base), 0.0) -
                              near_log_background(k, 0.0, leaf, a.l, N)
                        : near_log<R, V>(a, k, 0.0, leaf, -1);
-            a.logc[k] = (double)far + nr;
+            const double lc = (double)far + nr;
+            // #{j : s_j <= k}: the points of the leaves before k's leaf, plus
+            // a binary search over the (sorted) points of k's leaf
+            int32_t lo, hi;
+            if (staged) {
+                const int32_t tmr = (int32_t)(k - base);
+                lo = ns.off[il + 1];
+                hi = ns.off[il + 2];
+                const int32_t j0 = lo;
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi) >> 1;
+                    if (ns.m[mid] < tmr || (ns.m[mid] == tmr && ns.th[mid] <= 0.0))
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                lo = a.src.off[leaf] + (lo - j0);
+            } else {
+                lo = a.src.off[leaf];
+                hi = a.src.off[leaf + 1];
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi) >> 1;
+                    const int32_t mm = a.src.m[mid];
+                    if (mm < k || (mm == k && a.src.th[mid] <= 0.0))
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+            }
+            const int64_t neg = N - lo;
+            if (a.hit[k] >= 0) {
+                a.chat_out[k] = 0.0;
+            } else {
+                if (!(fabs(lc) <= 700.0))
+                    atomicOr(a.flags_out, FLAG_RANGE);
+                a.chat_out[k] = (((k + neg) & 1) ? -1.0 : 1.0) * exp(lc);
+            }
         }
         for (int32_t t = w.t0 + tid; t < w.t1; t += BLOCK) {
             const int64_t tm = a.tgt.m[t];
@@ -1502,13 +1549,18 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
                        : near_log<R, V>(a, tm, th, leaf, t);
             // the net count of Omega_1 carried log(2 pi / N) for the point
             // itself, whose log|t| term the near field skips
-            a.logd[t] = -((double)far + nr - a.logself);
+            const double ld = -((double)far + nr - a.logself);
+            if (!(fabs(ld) <= 700.0))
+                atomicOr(a.flags_out, FLAG_RANGE);
+            const double sg = (((tm + (N - 1 - t)) & 1) ? -1.0 : 1.0) * exp(ld);
+            a.dhat_out[t] = {sg * sinpi(th), sg * cospi(th)};
         }
     }
 }
 
+// at least 3 waves per SIMD (at most 168 VGPRs + AGPRs)
 template <typename R, typename V, int KER, int SRC, int EPI, int PD>
-__global__ void __launch_bounds__(BLOCK) k_down_trans(DownArgs<R, V> a)
+__global__ void __launch_bounds__(BLOCK, 3) k_down_trans(DownArgs<R, V> a)
 {
     down_eval_body<R, V, KER, SRC, EPI, PD, PH_TRANS>(a, blockIdx.x);
 }

@@ -685,56 +685,6 @@ __device__ __forceinline__ void work_body(const WorkArgs &w)
 
 __global__ void __launch_bounds__(1024) k_work(WorkArgs w) { work_body(w); }
 
-// Eq. (p8), rescaled by 2^N (the scale cancels in C_k D_j):
-//   Chat_k = (-1)^k prod_j 2 sin((x_k - y_j)/2)
-//          = (-1)^(k + #{j: s_j > k}) exp(logC_k),
-//   Dhat_j = i e^{-i N y_j / 2} / prod_{i != j} 2 sin((y_j - y_i)/2)
-//          = i (-1)^(m_j) e^{-i pi th_j} (-1)^(#{i: s_i > s_j}) exp(logD_j),
-// with the points sorted along the circle, so #{i: s_i > s_j} = N - 1 - rank.
-__global__ void k_coeffs(int64_t N, int l, const int32_t *off, const double *logc,
-                         const double *logd, const int32_t *sm, const double *sth,
-                         const int32_t *hit, double *chat, cx<double> *dhat,
-                         int *flags)
-{
-    const double lscale = ldexp(1.0, l) / (double)N;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < N;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        // #{j : s_j <= k}: every point of the leaves before k's leaf, plus a
-        // binary search over the (sorted) points of k's leaf
-        int64_t b = (int64_t)((double)k * lscale);
-        if (uni_start(b + 1, l, N) <= k)
-            ++b;
-        else if (uni_start(b, l, N) > k)
-            --b;
-        int64_t lo = off[b], hi = off[b + 1];
-        while (lo < hi) {
-            int64_t mid = (lo + hi) >> 1;
-            bool le = sm[mid] < k || (sm[mid] == k && sth[mid] <= 0.0);
-            if (le)
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
-        const int64_t neg = N - lo;
-        const double lc = logc[k];
-        if (hit[k] >= 0) {
-            chat[k] = 0.0;
-        } else {
-            if (!(fabs(lc) <= 700.0))
-                atomicOr(flags, FLAG_RANGE);
-            chat[k] = (((k + neg) & 1) ? -1.0 : 1.0) * exp(lc);
-        }
-        // Dhat for the k-th point in sorted order
-        const double ld = logd[k];
-        if (!(fabs(ld) <= 700.0))
-            atomicOr(flags, FLAG_RANGE);
-        const int64_t negd = N - 1 - k;
-        const double sg = (((sm[k] + negd) & 1) ? -1.0 : 1.0) * exp(ld);
-        const double th = sth[k];
-        dhat[k] = {sg * sinpi(th), sg * cospi(th)};
-    }
-}
-
 // Dhat in input order: out[perm[t]] = dhat[t].
 __global__ void k_unsort_c128(int64_t n, const cx<double> *dhat, const int32_t *perm,
                               cx<double> *out)
