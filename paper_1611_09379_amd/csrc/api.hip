@@ -678,6 +678,7 @@ struct TreeJob {
     bool lds_path = true, deterministic = false;
     int32_t *tsum = nullptr;               // tile sums of the multi-pass scan
     SortedPt *gpt = nullptr;               // deterministic: records before ranking
+    const WorkArgs *work = nullptr;        // work list built with the scan
 };
 
 static int prepare_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
@@ -754,7 +755,12 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
     }
     HIPCHK(hipGetLastError());
     // off = exclusive scan of the key totals; cursor copy for the atomic path
-    if (nbins <= SCAN1_MAX) {
+    if (nbins <= SCAN1_MAX && J.work) {
+        // the work list comes out of the same launch
+        hipLaunchKernelGGL(k_scan_work, dim3(1), dim3(1024), SCAN1_SMEM + 4096, st,
+                           (const int32_t *)a.tot, nbins, a.off, a.cursor, *J.work);
+        HIPCHK(hipGetLastError());
+    } else if (nbins <= SCAN1_MAX) {
         hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), SCAN1_SMEM, st,
                            (const int32_t *)a.tot, nbins, a.off, a.cursor);
         HIPCHK(hipGetLastError());
@@ -768,6 +774,10 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
         hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(256), 0, st, (const int32_t *)a.tot,
                            (int64_t)nbins, (const int32_t *)J.tsum, a.off, a.cursor);
         HIPCHK(hipGetLastError());
+        if (J.work) {
+            hipLaunchKernelGGL(k_work, dim3(1), dim3(1024), 0, st, *J.work);
+            HIPCHK(hipGetLastError());
+        }
     }
     if (J.lds_path) {
         hipLaunchKernelGGL(k_place, dim3(a.nblk), dim3(SORT_THREADS), (size_t)nbins * 4, st, a);
@@ -794,13 +804,20 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
 // (inverse; keyshift must be 0) when `deterministic`; otherwise the order
 // inside a key is arbitrary (forward).  Fills the hit map when asked.
 // Enqueues only; errors land in P->flags.
+// With w (from prepare_work), the work list of the downward pass is built
+// right after the scan of the sort.
 static int build_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
-                      bool deterministic, bool want_hit, bool records, hipStream_t st)
+                      bool deterministic, bool want_hit, bool records, hipStream_t st,
+                      WorkArgs *w = nullptr)
 {
     TreeJob J;
     int rc = prepare_tree(P, n, y, keyshift, deterministic, want_hit, records, &J);
     if (rc)
         return rc;
+    if (w) {
+        w->off = (const int32_t *)P->off.p;
+        J.work = w;
+    }
     return launch_tree(P, J, st);
 }
 
@@ -819,17 +836,6 @@ static int prepare_work(fn_plan *P, int sh, bool uniform, int64_t npts, WorkArgs
         return fail(FN_ENOMEM, "work list allocation failed");
     *w = {nroot, sh, (const int32_t *)P->off.p, uniform ? 1 : 0, P->N, P->lr, tmax,
           (WorkItem *)P->work.p, (int32_t *)P->nwork_dev.p};
-    return FN_OK;
-}
-
-static int build_work(fn_plan *P, int sh, bool uniform, int64_t npts, hipStream_t st)
-{
-    WorkArgs w;
-    int rc = prepare_work(P, sh, uniform, npts, &w);
-    if (rc)
-        return rc;
-    hipLaunchKernelGGL(k_work, dim3(1), dim3(1024), 0, st, w);
-    HIPCHK(hipGetLastError());
     return FN_OK;
 }
 
@@ -889,10 +895,11 @@ static int plan_fwd_impl(fn_plan *P, const double *y, hipStream_t st)
     P->lr = choose_lr(P->l, 2, PD, sizeof(R));
     // targets grouped by leaf: the lanes of a wavefront then share the
     // leaf locals and near-field sources they read
-    int rc = build_tree(P, P->M, y, 0, false, false, true, st);
+    WorkArgs w;
+    int rc = prepare_work(P, P->l - P->lr, false, P->M, &w);
     if (rc)
         return rc;
-    rc = build_work(P, P->l - P->lr, false, P->M, st);
+    rc = build_tree(P, P->M, y, 0, false, false, true, st, &w);
     if (rc)
         return rc;
     rc = setup_fmm<R, cx<R>>(P, KER_COT, PU, PD, P->q, false, P->cot, st);
@@ -995,10 +1002,11 @@ static int plan_inv_impl(fn_plan *P, const double *y, hipStream_t st)
     // one subtree level serves the log FMM (binary64, real, at most 64
     // terms) and the cot FMM
     P->lr = std::max(choose_lr(P->l, 2, PD, sizeof(R)), choose_lr(P->l, 1, 64, 8));
-    int rc = build_tree(P, P->N, y, 0, true, true, false, st);
+    WorkArgs w;
+    int rc = prepare_work(P, P->l - P->lr, true, P->N, &w);
     if (rc)
         return rc;
-    rc = build_work(P, P->l - P->lr, true, P->N, st);
+    rc = build_tree(P, P->N, y, 0, true, true, false, st, &w);
     if (rc)
         return rc;
     if (!alloc(P->chat, P->N * 8) || !alloc(P->dhat, P->N * 16) ||

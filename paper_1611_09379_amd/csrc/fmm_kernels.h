@@ -910,11 +910,12 @@ __device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
             // one reciprocal per pair, whose rounding it can afford less
             cx<R> a1 = {R(0), R(0)}, a2 = {R(0), R(0)}, a3 = {R(0), R(0)};
             int32_t i = 0;
-            for (; i + 4 <= cnt; i += 4) {
-                const R d0 = (R)((double)(base - i) + tth);
-                const R d1 = (R)((double)(base - i - 1) + tth);
-                const R d2 = (R)((double)(base - i - 2) + tth);
-                const R d3 = (R)((double)(base - i - 3) + tth);
+            double cb = (double)base; // base - i, exact
+            for (; i + 4 <= cnt; i += 4, cb -= 4.0) {
+                const R d0 = (R)(cb + tth);
+                const R d1 = (R)((cb - 1.0) + tth);
+                const R d2 = (R)((cb - 2.0) + tth);
+                const R d3 = (R)((cb - 3.0) + tth);
                 const cx<R> w0 = fp[i], w1 = fp[i + 1], w2 = fp[i + 2], w3 = fp[i + 3];
                 if constexpr (sizeof(R) == 8) {
                     const R r01 = recip(d0 * d1), r23 = recip(d2 * d3);
@@ -994,7 +995,10 @@ __device__ __forceinline__ int64_t uni_leaf(int64_t k, int l, int64_t N, double 
 // staged leaf j occupy [off[j], off[j + 1]).
 template <typename R>
 struct NearStage {
-    int32_t *m;
+    // integer grid offsets (held as int32: as binary64 they would spare the
+    // conversion per pair, but the wider LDS reads cost more than it)
+    using MT = int32_t;
+    MT *m;
     double *th;
     cx<R> *w;
     int32_t *off;
@@ -1009,21 +1013,27 @@ __device__ __forceinline__ double near_dist(int32_t dm, double a, double b)
     return (double)dm + (a - b);
 }
 
+__device__ __forceinline__ double near_dist(int32_t tm, int32_t m, double a, double b)
+{
+    return (double)(tm - m) + (a - b);
+}
+
 // Cot near field from staged sources [j0, j1): sum w / (tau - sigma).
 template <typename R>
 __device__ __forceinline__ cx<R> near_cot_staged(const NearStage<R> &ns, int32_t j0,
                                                  int32_t j1, int32_t tmr, double tth)
 {
     cx<R> a0 = {R(0), R(0)}, a1 = a0, a2 = a0, a3 = a0;
+    const typename NearStage<R>::MT tmd = (typename NearStage<R>::MT)tmr;
     int32_t j = j0;
     // binary64: two pairs at a time, each pair over one reciprocal (no
     // distance is zero: exact hits never reach the near field); binary32
     // keeps one reciprocal per pair
     for (; j + 4 <= j1; j += 4) {
-        const R d0 = (R)near_dist(tmr - ns.m[j], tth, ns.th[j]);
-        const R d1 = (R)near_dist(tmr - ns.m[j + 1], tth, ns.th[j + 1]);
-        const R d2 = (R)near_dist(tmr - ns.m[j + 2], tth, ns.th[j + 2]);
-        const R d3 = (R)near_dist(tmr - ns.m[j + 3], tth, ns.th[j + 3]);
+        const R d0 = (R)near_dist(tmd, ns.m[j], tth, ns.th[j]);
+        const R d1 = (R)near_dist(tmd, ns.m[j + 1], tth, ns.th[j + 1]);
+        const R d2 = (R)near_dist(tmd, ns.m[j + 2], tth, ns.th[j + 2]);
+        const R d3 = (R)near_dist(tmd, ns.m[j + 3], tth, ns.th[j + 3]);
         const cx<R> w0 = ns.w[j], w1 = ns.w[j + 1], w2 = ns.w[j + 2], w3 = ns.w[j + 3];
         if constexpr (sizeof(R) == 8) {
             const R r01 = recip(d0 * d1), r23 = recip(d2 * d3);
@@ -1044,7 +1054,7 @@ __device__ __forceinline__ cx<R> near_cot_staged(const NearStage<R> &ns, int32_t
         }
     }
     for (; j < j1; ++j) {
-        const R r = recip((R)near_dist(tmr - ns.m[j], tth, ns.th[j]));
+        const R r = recip((R)near_dist(tmd, ns.m[j], tth, ns.th[j]));
         const cx<R> w = ns.w[j];
         a0.re = fma(w.re, r, a0.re);
         a0.im = fma(w.im, r, a0.im);
@@ -1060,11 +1070,12 @@ __device__ __forceinline__ void log_prod_range(const NearStage<R> &ns, int32_t j
                                                int32_t tmr, double tth, double &prod,
                                                int &expo)
 {
+    const typename NearStage<R>::MT tmd = (typename NearStage<R>::MT)tmr;
     for (; j + 8 <= j1; j += 8) {
         double d[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            d[u] = fabs(near_dist(tmr - ns.m[j + u], tth, ns.th[j + u]));
+            d[u] = fabs(near_dist(tmd, ns.m[j + u], tth, ns.th[j + u]));
         const double q = ((d[0] * d[1]) * (d[2] * d[3])) * ((d[4] * d[5]) * (d[6] * d[7]));
         int e;
         prod = frexp(prod * q, &e);
@@ -1072,7 +1083,7 @@ __device__ __forceinline__ void log_prod_range(const NearStage<R> &ns, int32_t j
     }
     double q = 1.0;
     for (; j < j1; ++j)
-        q *= fabs(near_dist(tmr - ns.m[j], tth, ns.th[j]));
+        q *= fabs(near_dist(tmd, ns.m[j], tth, ns.th[j]));
     int e;
     prod = frexp(prod * q, &e);
     expo += e;
@@ -1350,10 +1361,22 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
         for (int idx = tid; idx < (PD << s); idx += BLOCK)
             g[idx] = ld_coef<R, V>(cur, RS, idx / PD, idx % PD);
         return;
-    } else { // ... and come back for the evaluation
+    } else { // ... and come back for the evaluation (all loads in flight)
         const V *g = a.leaf_loc + leaf0 * PD;
-        for (int idx = tid; idx < (PD << s); idx += BLOCK)
-            st_coef<R, V>(bufA, RS, idx / PD, idx % PD, g[idx]);
+        const int n = PD << s; // at most 16 PD: 4 PD / 64 per thread
+        constexpr int NL = (16 * PD + BLOCK - 1) / BLOCK;
+        V v[NL];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int idx = tid + k * BLOCK;
+            v[k] = g[idx < n ? idx : n - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int idx = tid + k * BLOCK;
+            if (idx < n)
+                st_coef<R, V>(bufA, RS, idx / PD, idx % PD, v[k]);
+        }
         __syncthreads();
     }
     const R *leafloc = bufA;
@@ -1375,33 +1398,44 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
         const int32_t oR = a.src.off[br], cR = a.src.off[br + 1] - oR;
         const int32_t total = cL + cM + cR;
         constexpr int wb = EPI == EPI_INV ? (int)sizeof(cx<R>) : 0;
-        const int32_t cap = ((a.near_bytes - 4 * (nb + 4)) / (12 + wb)) & ~1;
+        constexpr int mb = (int)sizeof(typename NearStage<R>::MT);
+        const int32_t cap = ((a.near_bytes - 4 * (nb + 4)) / (8 + mb + wb)) & ~1;
         base = uni_start(leaf0, a.l, N);
         if (total <= cap) {
             unsigned char *fr = reinterpret_cast<unsigned char *>(bufB);
             ns.th = reinterpret_cast<double *>(fr);
             ns.w = reinterpret_cast<cx<R> *>(fr + 8 * (size_t)cap);
-            ns.m = reinterpret_cast<int32_t *>(fr + (8 + wb) * (size_t)cap);
-            ns.off = ns.m + cap;
+            ns.m = reinterpret_cast<typename NearStage<R>::MT *>(fr + (8 + wb) * (size_t)cap);
+            ns.off = reinterpret_cast<int32_t *>(ns.m + cap);
             ns.self0 = cL - oM;
             const int64_t shL = leaf0 == 0 ? -N : 0, shR = leaf0 + nb == nleaf ? N : 0;
-            for (int32_t i = tid; i < total; i += BLOCK) {
-                int32_t t;
-                int64_t sh;
-                if (i < cL) {
-                    t = oL + i;
-                    sh = shL;
-                } else if (i < cL + cM) {
-                    t = oM + (i - cL);
-                    sh = 0;
-                } else {
-                    t = oR + (i - cL - cM);
-                    sh = shR;
+            // every load of a batch in flight at once (indices clamped)
+            for (int32_t i0 = 0; i0 < total; i0 += 4 * BLOCK) {
+                int32_t mv[4];
+                double tv[4];
+                cx<R> wv[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    int32_t i = i0 + tid + k * BLOCK;
+                    i = i < total ? i : total - 1;
+                    const int32_t t = i < cL ? oL + i
+                                             : (i < cL + cM ? oM + (i - cL) : oR + (i - cL - cM));
+                    mv[k] = a.src.m[t];
+                    tv[k] = a.src.th[t];
+                    if constexpr (EPI == EPI_INV)
+                        wv[k] = a.w_sorted[t];
                 }
-                ns.m[i] = (int32_t)(a.src.m[t] + sh - base);
-                ns.th[i] = a.src.th[t];
-                if constexpr (EPI == EPI_INV)
-                    ns.w[i] = a.w_sorted[t];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int32_t i = i0 + tid + k * BLOCK;
+                    if (i < total) {
+                        const int64_t sh = i < cL ? shL : (i < cL + cM ? 0 : shR);
+                        ns.m[i] = (typename NearStage<R>::MT)(mv[k] + sh - base);
+                        ns.th[i] = tv[k];
+                        if constexpr (EPI == EPI_INV)
+                            ns.w[i] = wv[k];
+                    }
+                }
             }
             for (int i = tid; i <= nb + 2; i += BLOCK)
                 ns.off[i] = i == 0 ? 0
@@ -1422,10 +1456,24 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             K0 = uni_start_unwrapped(leaf0 - 1, a.l, N);
             const int64_t K1 = uni_start_unwrapped(leaf0 + (1 << s) + 1, a.l, N);
             if (K1 - K0 <= a.near_bytes / (int)sizeof(cx<R>)) {
-                for (int64_t i = tid; i < K1 - K0; i += BLOCK) {
-                    int64_t k = K0 + i;
-                    k = k < 0 ? k + N : (k >= N ? k - N : k);
-                    fs[i] = a.f_uniform[k];
+                const int32_t nk = (int32_t)(K1 - K0);
+                // every load of a batch in flight at once (indices clamped)
+                for (int32_t i0 = 0; i0 < nk; i0 += 8 * BLOCK) {
+                    cx<R> v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        int32_t i = i0 + tid + u * BLOCK;
+                        i = i < nk ? i : nk - 1;
+                        int64_t k = K0 + i;
+                        k = k < 0 ? k + N : (k >= N ? k - N : k);
+                        v[u] = a.f_uniform[k];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int32_t i = i0 + tid + u * BLOCK;
+                        if (i < nk)
+                            fs[i] = v[u];
+                    }
                 }
                 fsp = fs;
             }
@@ -1502,7 +1550,7 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             // a binary search over the (sorted) points of k's leaf
             int32_t lo, hi;
             if (staged) {
-                const int32_t tmr = (int32_t)(k - base);
+                const typename NearStage<R>::MT tmr = (typename NearStage<R>::MT)(k - base);
                 lo = ns.off[il + 1];
                 hi = ns.off[il + 2];
                 const int32_t j0 = lo;

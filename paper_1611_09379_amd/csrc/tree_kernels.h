@@ -559,12 +559,28 @@ __global__ void __launch_bounds__(256)
         sperm[pos] = perm;
     };
     if (T1 - T0 <= RANK_CAP) {
-        for (int32_t i = threadIdx.x; i < T1 - T0; i += 256) {
-            SortedPt q = gpt[T0 + i];
-            lperm[i] = q.perm;
-            canon_pos(q.m, q.th);
-            lm[i] = q.m;
-            lth[i] = q.th;
+        // staged in canonical form; bit 31 of lperm records that th was 1/2
+        // (the stored units are then m - 1, 1/2).  Every load of a batch is
+        // in flight at once (indices clamped).
+        const int32_t cnt = T1 - T0;
+        for (int32_t i0 = 0; i0 < cnt; i0 += 4 * 256) {
+            SortedPt q[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int32_t i = i0 + (int32_t)threadIdx.x + k * 256;
+                q[k] = gpt[T0 + (i < cnt ? i : cnt - 1)];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int32_t i = i0 + (int32_t)threadIdx.x + k * 256;
+                if (i < cnt) {
+                    const bool half = q[k].th == 0.5;
+                    lperm[i] = q[k].perm | (half ? (int32_t)0x80000000u : 0);
+                    canon_pos(q[k].m, q[k].th);
+                    lm[i] = q[k].m;
+                    lth[i] = q[k].th;
+                }
+            }
         }
         for (int i = threadIdx.x; i <= nb; i += 256)
             loff[i] = off[b0 + i] - T0;
@@ -589,8 +605,10 @@ __global__ void __launch_bounds__(256)
             } else {
                 rank = leaf_rank(i, t0, t1, gm, gth, lm[i], lth[i], &dup);
             }
-            const SortedPt q = gpt[T0 + i]; // the stored (not canonical) units
-            finish(t0 + T0, rank, q.m, q.th, lperm[i]);
+            const int32_t pv = lperm[i];
+            const bool half = pv < 0; // the stored (not canonical) units
+            finish(t0 + T0, rank, half ? lm[i] - 1 : lm[i], half ? 0.5 : lth[i],
+                   pv & 0x7fffffff);
         }
     } else {
         auto gm = [&](int32_t u) {
@@ -638,19 +656,20 @@ struct WorkArgs {
     int32_t *nitems;
 };
 
-__device__ __forceinline__ void work_body(const WorkArgs &w)
+// offl(i) = off[i] for i <= nbins, from global memory or from LDS; part is
+// 1024 words of LDS.  One workgroup of 1024 threads.
+template <typename Off>
+__device__ __forceinline__ void work_from(const WorkArgs &w, Off offl, int32_t *part)
 {
-    __shared__ int32_t part[1024];
     const int64_t nroot = w.nroot, N = w.N;
     const int sh = w.sh, lr = w.lr, uniform = w.uniform;
     const int32_t tmax = w.tmax;
-    const int32_t *off = w.off;
     WorkItem *items = w.items;
     const int tid = threadIdx.x;
     const int64_t per = (nroot + 1023) / 1024;
     const int64_t r0 = tid * per, r1 = r0 + per < nroot ? r0 + per : nroot;
     auto pieces = [&](int64_t R) -> int32_t {
-        const int32_t t0 = off[R << sh], t1 = off[(R + 1) << sh];
+        const int32_t t0 = offl(R << sh), t1 = offl((R + 1) << sh);
         if (uniform)
             return 1;
         return (t1 - t0 + tmax - 1) / tmax;
@@ -668,7 +687,7 @@ __device__ __forceinline__ void work_body(const WorkArgs &w)
     }
     int32_t pos = tid == 0 ? 0 : part[tid - 1];
     for (int64_t R = r0; R < r1; ++R) {
-        const int32_t t0 = off[R << sh], t1 = off[(R + 1) << sh];
+        const int32_t t0 = offl(R << sh), t1 = offl((R + 1) << sh);
         if (uniform) {
             const int64_t nr = int64_t(1) << lr;
             const int32_t u0 = (int32_t)((R * N + nr - 1) >> lr);
@@ -683,7 +702,28 @@ __device__ __forceinline__ void work_body(const WorkArgs &w)
         *w.nitems = part[1023];
 }
 
+__device__ __forceinline__ void work_body(const WorkArgs &w)
+{
+    __shared__ int32_t part[1024];
+    work_from(w, [&](int64_t i) { return w.off[i]; }, part);
+}
+
 __global__ void __launch_bounds__(1024) k_work(WorkArgs w) { work_body(w); }
+
+// The one-block scan of the key totals followed by the work list, built from
+// the offsets while they are still in LDS (one launch and no read-back).
+// Dynamic LDS: SCAN1_SMEM + 1024 words.
+__global__ void __launch_bounds__(1024) k_scan_work(const int32_t *count, int n, int32_t *off,
+                                                    int32_t *cursor, WorkArgs w)
+{
+    extern __shared__ int32_t sv[];
+    scan_one_body(count, n, off, cursor);
+    __syncthreads();
+    int32_t *part = sv + scan1_slot(SCAN1_MAX);
+    const int32_t total = part[1023];
+    work_from(w, [&](int64_t i) { return i < n ? sv[scan1_slot((int)i)] : total; },
+              part + 1024);
+}
 
 // Dhat in input order: out[perm[t]] = dhat[t].
 __global__ void k_unsort_c128(int64_t n, const cx<double> *dhat, const int32_t *perm,
