@@ -841,12 +841,39 @@ static int prepare_work(fn_plan *P, int sh, bool uniform, int64_t npts, WorkArgs
 
 // The one synchronisation of a plan: waits for the setup, reads the error
 // flags and releases the temporaries.
+// Pinned host memory per host thread for the flag read-backs (a copy into
+// pageable memory takes a much slower, staged path): at least `bytes`,
+// grown on demand and held until the process ends; nullptr if it cannot be
+// had (the read-back then goes to pageable memory).
+static void *pinned_scratch(size_t bytes)
+{
+    static thread_local void *buf = nullptr;
+    static thread_local size_t cap = 0;
+    if (bytes > cap) {
+        if (buf)
+            (void)hipHostFree(buf);
+        buf = nullptr;
+        cap = 0;
+        const size_t want = std::max<size_t>(bytes, 256);
+        if (hipHostMalloc(&buf, want, hipHostMallocPortable) != hipSuccess) {
+            buf = nullptr;
+            return nullptr;
+        }
+        cap = want;
+    }
+    return buf;
+}
+
 static int finish_plan(fn_plan *P, hipStream_t st)
 {
-    int hflags = 0;
-    hipError_t e = hipMemcpyAsync(&hflags, P->flags.p, 4, hipMemcpyDeviceToHost, st);
+    int hstack = 0;
+    int *hw = (int *)pinned_scratch(4);
+    if (!hw)
+        hw = &hstack;
+    hipError_t e = hipMemcpyAsync(hw, P->flags.p, 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
+    const int hflags = *hw;
     release_tmp(P);
     if (e != hipSuccess)
         return fail(FN_EHIP, "plan setup: %s", hipGetErrorString(e));
@@ -1516,8 +1543,13 @@ static int plan_batch(fn_batch **out, int32_t count, const int64_t *Ns, const in
 // with a flag); releases the setup temporaries.
 static int finish_batch(fn_batch *B, hipStream_t st)
 {
-    std::vector<int> hf(B->T, 0);
-    hipError_t e = hipMemcpyAsync(hf.data(), B->flags.p, (size_t)B->T * 4,
+    std::vector<int> hv;
+    int *hf = (int *)pinned_scratch((size_t)B->T * 4);
+    if (!hf) {
+        hv.assign(B->T, 0);
+        hf = hv.data();
+    }
+    hipError_t e = hipMemcpyAsync(hf, B->flags.p, (size_t)B->T * 4,
                                   hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
