@@ -335,7 +335,8 @@ struct FmmSetup {
     int nbands = 0;
     Band band[MAX_BANDS];
     size_t reg_smem = 0;
-    size_t dn_smem = 0;
+    size_t dn_smem = 0; // evaluation kernel
+    size_t tr_smem = 0; // translation kernel
     int rows_buf = 0, rows_src = 0, near_bytes = 0;
     int stage_cap = 0; // first upward band: sorted sources staged in LDS
 };
@@ -457,7 +458,8 @@ static int choose_lr(int l, int nc, int PD, int es)
     const int RS = row_stride(nc, PD, es);
     for (int s = std::min(4, l - 2); s >= 0; --s) {
         int rb, rsrc;
-        if (down_lds(s, l - s, RS, es, &rb, &rsrc) <= lim)
+        // the translation kernel also holds the PD x PD L2L table
+        if (down_lds(s, l - s, RS, es, &rb, &rsrc) + (size_t)PD * PD * es <= lim)
             return l - s;
     }
     return l;
@@ -531,8 +533,10 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_
         return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PU, F.reg_smem);
     const int s = P->l - P->lr;
     F.dn_smem = down_lds(s, P->lr, F.RSd, es, &F.rows_buf, &F.rows_src);
-    if (F.dn_smem > lim)
-        return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PD, F.dn_smem);
+    // the translation kernel holds the L2L table as well
+    F.tr_smem = F.dn_smem + (size_t)PD * PD * es;
+    if (F.tr_smem > lim)
+        return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PD, F.tr_smem);
     F.near_bytes = (int)((size_t)(F.rows_buf + F.rows_src) * F.RSd * es);
     const int64_t nmp = lev_off(P->l + 1, PU);
     if (!alloc(F.mp, nmp * sizeof(V)) || !alloc(F.loc2, 4 * PD * sizeof(V)) ||
@@ -624,7 +628,7 @@ static int launch_down(const fn_plan *P, const FmmSetup &F, const DownArgs<R, V>
     if (which != 2) {
         FN_DISPATCH16(F.PD, PD_,
                       hipLaunchKernelGGL((k_down_trans<R, V, KER, SRC, EPI, PD_>),
-                                         dim3(P->nwork), dim3(BLOCK), F.dn_smem, st, da));
+                                         dim3(P->nwork), dim3(BLOCK), F.tr_smem, st, da));
         HIPCHK(hipGetLastError());
     }
     if (which != 1) {
@@ -1244,7 +1248,7 @@ struct fn_batch {
     std::vector<fn_plan *> P;
     std::vector<int> grp, solo;
     int PU = 0, PD = 0, q = 0, nbands = 0;
-    size_t reg_smem = 0;
+    size_t reg_smem = 0, tr_smem = 0;
     Buf blob, io, flags;
     std::vector<IoPtr> hio;
     LaunchShape hist, colscan, place, scan, work, reg, down, up[MAX_BANDS];
@@ -1419,9 +1423,11 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
             fill_down(P, F, Tb, d);
             d.tgt_pt = (const SortedPt *)P->spt.p;
             d.io_index = t;
+            d.io = (const IoPtr *)B->io.p; // f, g of every call come from the table
             da.push_back(d);
             nb_down.push_back(P->nwork);
             dsm = std::max(dsm, F.dn_smem);
+            B->tr_smem = std::max(B->tr_smem, F.tr_smem);
         }
         bb.add(B->reg, ua, nb_reg);
         B->reg.smem = B->reg_smem;
@@ -1494,7 +1500,7 @@ static int launch_batch_eval(fn_batch *B, hipStream_t st)
     FN_DISPATCH16(
         B->PD, PD_,
         hipLaunchKernelGGL((kb_down_trans<R, V, KER_COT, SET_UNIFORM, EPI_FWD, PD_>),
-                           dim3(B->down.grid), dim3(BLOCK), B->down.smem, st,
+                           dim3(B->down.grid), dim3(BLOCK), B->tr_smem, st,
                            (const DownArgs<R, V> *)at(B->down.args), map(B->down), io);
         HIPCHK(hipGetLastError());
         hipLaunchKernelGGL((kb_down_eval<R, V, KER_COT, SET_UNIFORM, EPI_FWD, PD_>),

@@ -722,6 +722,8 @@ struct DownArgs {
                              // at FLAG_DENSE (their near field would be
                              // quadratic in the leaf size)
     int32_t io_index;        // batched launches: entry of the IoPtr table
+    const IoPtr *io;         // batched launches: the table (f_uniform, f_hit
+                             // and out are then io[io_index].in / .out)
     V *leaf_loc;             // local expansions of the leaves, PD per leaf
 };
 
@@ -892,7 +894,8 @@ __device__ __forceinline__ int64_t uni_start_unwrapped(int64_t b, int l, int64_t
 template <typename R, typename V, int SRC>
 __device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
                                           double tth, int64_t leaf,
-                                          const cx<R> *fs, int64_t K0)
+                                          const cx<R> *fs, int64_t K0,
+                                          const cx<R> *f_uniform)
 {
     const int64_t N = a.N;
     const int64_t nleaf = int64_t(1) << a.l;
@@ -959,7 +962,7 @@ __device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
             const int64_t k0 = uni_start(b, a.l, N), k1 = uni_start(b + 1, a.l, N);
             for (int64_t k = k0; k < k1; ++k) {
                 const R rd = recip((R)((double)(tm - k - shift) + tth));
-                const cx<R> w = a.f_uniform[k];
+                const cx<R> w = f_uniform[k];
                 acc.re = fma(w.re, rd, acc.re);
                 acc.im = fma(w.im, rd, acc.im);
             }
@@ -1201,7 +1204,21 @@ __device__ __forceinline__ void lev_stage(const V (&pf)[NPF], R *srcs, int RS, i
     }
 }
 
-template <typename R, typename V, int KER, int SRC, int EPI, int PD, int PH>
+// Complex load and store through a pointer of any address space (the
+// batched kernels hold global-memory pointers as such).
+template <typename R, typename P>
+__device__ __forceinline__ cx<R> ld_cx(P p, int64_t i)
+{
+    return {p[i].re, p[i].im};
+}
+template <typename R, typename P>
+__device__ __forceinline__ void st_cx(P p, int64_t i, cx<R> v)
+{
+    p[i].re = v.re;
+    p[i].im = v.im;
+}
+
+template <typename R, typename V, int KER, int SRC, int EPI, int PD, int PH, bool IOT = false>
 __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1217,6 +1234,29 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
         if (*a.flags & FLAG_DENSE)
             return; // the plan fails; nothing is evaluated
     const WorkItem w = a.work[blk];
+    // per-call pointers: from the batch's table in the batched kernels (IOT);
+    // the table holds global-memory pointers, which the casts tell the
+    // compiler (as generic pointers they would take flat loads)
+    using GC = const cx<R> __attribute__((address_space(1))) *;
+    using G = cx<R> __attribute__((address_space(1))) *;
+    const auto f_uniform = [&]() {
+        if constexpr (IOT)
+            return (GC)a.io[a.io_index].in;
+        else
+            return a.f_uniform;
+    }();
+    const auto f_hit = [&]() {
+        if constexpr (IOT)
+            return (GC)a.io[a.io_index].in;
+        else
+            return a.f_hit;
+    }();
+    const auto out = [&]() {
+        if constexpr (IOT)
+            return (G)a.io[a.io_index].out;
+        else
+            return a.out;
+    }();
     if constexpr (PH == PH_TRANS)
         if (!w.lead)
             return; // another item of the same root forms its leaf locals
@@ -1274,6 +1314,18 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             }
         }
     }
+    // the L2L table, for the shift below, after the source rows
+    R *tl2l = srcs + (size_t)a.rows_src * RS; // PD x PD, [in n'][out n]
+    {
+        static_assert((PD * PD) % BLOCK == 0, "PD^2 must be a multiple of the block");
+        R rl[PD * PD / BLOCK];
+#pragma unroll
+        for (int k = 0; k < PD * PD / BLOCK; ++k)
+            rl[k] = a.T.l2l[tid + k * BLOCK];
+#pragma unroll
+        for (int k = 0; k < PD * PD / BLOCK; ++k)
+            tl2l[tid + k * BLOCK] = rl[k];
+    }
     // X row 0: the level-2 local of R0's quarter
     for (int n = tid; n < PD; n += BLOCK)
         st_coef<R, V>(bufA, RS, 0, n, a.loc2[(R0 >> (lr - 2)) * PD + n]);
@@ -1302,15 +1354,12 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
         const R md2 = (R)(-2.0 * ldexp((double)((2 * R0 + 1) - ((2 * A + 1) << sh)), -sh));
         V acc = vzero<V>();
         R pw = R(1);
-        // unrolled, with the table read unconditionally: its loads do not
-        // wait for one another
-#pragma unroll
-        for (int np = 0; np < PD; ++np) {
-            const R tv = a.T.l2l[np * PD + n];
-            if (np >= n) {
-                vfma(acc, tv * pw, ld_coef<R, V>(bufA, RS, li, np));
-                pw *= md2;
-            }
+        // the table from LDS; a partial unroll keeps several reads in flight
+        // without the register cost of a full one
+#pragma unroll 4
+        for (int np = n; np < PD; ++np) {
+            vfma(acc, tl2l[np * PD + n] * pw, ld_coef<R, V>(bufA, RS, li, np));
+            pw *= md2;
         }
         st_coef<R, V>(bufB, RS, li, n, vscale(acc, ipow(rho2, n)));
     }
@@ -1333,13 +1382,15 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
     // level's translations run)
     for (int lev = lr + 1; lev <= a.l; ++lev) {
         const int nb = 1 << (lev - lr);
+        // the level's scale factors before the prefetch is issued: computed
+        // after it, they held up the loads' registers
+        const R sgl = KER == KER_COT ? (R)(ldexp(2.0, lev) / 3.14159265358979323846) : R(1);
+        const R lgl = KER == KER_LOG ? (R)log(ldexp((double)N, -(lev + 1))) : R(0);
         lev_stage<R, V, PD, NPF>(pf, srcs, RS, lr, lev, tid);
         __syncthreads();
         if (lev < a.l)
             lev_fetch<R, V, PD, NPF>(pf, a, R0, lr, lev + 1, tid);
         if (wave < used) {
-            const R sgl = KER == KER_COT ? (R)(ldexp(2.0, lev) / 3.14159265358979323846) : R(1);
-            const R lgl = (R)log(ldexp((double)N, -(lev + 1)));
             m2l_tiles<R, V, KER, PD, true>(
                 ops, rt, ct0, ctstep, lane, nb, srcs, cur, RS,
                 [&](int i, int o) { return i + 3 + o; },
@@ -1458,6 +1509,7 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             if (K1 - K0 <= a.near_bytes / (int)sizeof(cx<R>)) {
                 const int32_t nk = (int32_t)(K1 - K0);
                 // every load of a batch in flight at once (indices clamped)
+                // every load of a batch in flight at once (indices clamped)
                 for (int32_t i0 = 0; i0 < nk; i0 += 8 * BLOCK) {
                     cx<R> v[8];
 #pragma unroll
@@ -1466,7 +1518,7 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
                         i = i < nk ? i : nk - 1;
                         int64_t k = K0 + i;
                         k = k < 0 ? k + N : (k >= N ? k - N : k);
-                        v[u] = a.f_uniform[k];
+                        v[u] = ld_cx<R>(f_uniform, k);
                     }
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
@@ -1487,13 +1539,13 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             const double th = pt.th;
             const int32_t j = pt.perm;
             if (th == 0.0) { // exact hit: K_jk is the Kronecker delta
-                a.out[j] = a.f_hit[tm == N ? 0 : tm];
+                st_cx<R>(out, j, ld_cx<R>(f_hit, tm == N ? 0 : tm));
                 continue;
             }
             const int64_t leaf = box_of(tm, th, a.l, N);
             const R u = (R)rel_coord_r(tm, th, leaf, a.l, N, invN);
             V h = horner4<R, V, PD>(leafloc, RS, (int)(leaf - leaf0), u);
-            cx<R> nr = near_cot<R, V, SRC>(a, tm, th, leaf, fsp, K0);
+            cx<R> nr = near_cot<R, V, SRC>(a, tm, th, leaf, fsp, K0, (const cx<R> *)f_uniform);
             double hr = (double)h.re + hscale * (double)nr.re;
             double hi = (double)h.im + hscale * (double)nr.im;
             // g = -(F/2)(S + i h), F = 2i sin(pi th) e^{i pi th} / N
@@ -1501,7 +1553,7 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             double Fr = -2.0 * sp * sp * invN, Fi = 2.0 * sp * cp * invN;
             double Ar = (double)S.re - hi, Ai = (double)S.im + hr;
             cx<R> g = {(R)(-0.5 * (Fr * Ar - Fi * Ai)), (R)(-0.5 * (Fr * Ai + Fi * Ar))};
-            a.out[j] = g;
+            st_cx<R>(out, j, g);
         }
     } else if constexpr (EPI == EPI_INV) {
         const V W = *a.S;
@@ -1509,7 +1561,7 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
         for (int32_t k = w.u0 + tid; k < w.u1; k += BLOCK) {
             const int32_t hj = a.hit[k];
             if (hj >= 0) { // exact hit: C_k = 0 and f_k = g_j
-                a.out[k] = a.gin[hj];
+                st_cx<R>(out, k, a.gin[hj]);
                 continue;
             }
             const int64_t leaf = uni_leaf(k, a.l, N, lscale);
@@ -1518,13 +1570,13 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             V h = horner4<R, V, PD>(leafloc, RS, il, u);
             cx<R> nr = staged ? near_cot_staged<R>(ns, ns.off[il], ns.off[il + 3],
                                                    (int32_t)(k - base), 0.0)
-                              : near_cot<R, V, SRC>(a, k, 0.0, leaf, nullptr, 0);
+                              : near_cot<R, V, SRC>(a, k, 0.0, leaf, nullptr, 0, (const cx<R> *)f_uniform);
             double hr = (double)h.re + hscale * (double)nr.re;
             double hi = (double)h.im + hscale * (double)nr.im;
             // f = -(C/2)(W + i h)
             const double C = a.chat[k];
-            a.out[k] = {(R)(-0.5 * C * ((double)W.re - hi)),
-                        (R)(-0.5 * C * ((double)W.im + hr))};
+            st_cx<R>(out, k, cx<R>{(R)(-0.5 * C * ((double)W.re - hi)),
+                                   (R)(-0.5 * C * ((double)W.im + hr))});
         }
     } else { // EPI_LOGCD
         // log|Chat_k| and log|Dhat_j| by the FMM; then the coefficients of
@@ -1606,9 +1658,10 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
     }
 }
 
-// at least 3 waves per SIMD (at most 168 VGPRs + AGPRs)
+// at least 3 waves per SIMD (at most 168 VGPRs + AGPRs) up to 32 terms; 2
+// beyond, whose operator tiles would spill under that bound
 template <typename R, typename V, int KER, int SRC, int EPI, int PD>
-__global__ void __launch_bounds__(BLOCK, 3) k_down_trans(DownArgs<R, V> a)
+__global__ void __launch_bounds__(BLOCK, (PD <= 32 ? 3 : 2)) k_down_trans(DownArgs<R, V> a)
 {
     down_eval_body<R, V, KER, SRC, EPI, PD, PH_TRANS>(a, blockIdx.x);
 }
@@ -1621,21 +1674,17 @@ __global__ void __launch_bounds__(BLOCK, 4) k_down_eval(DownArgs<R, V> a)
 }
 
 // The downward pass of every problem of a batch in one launch (each phase).
-// The forward's input and output come from the IoPtr table when it is
-// given.
+// The forward's input and output come from the IoPtr table the arguments
+// point to (io, passed as well, is the same table).
 template <typename R, typename V, int KER, int SRC, int EPI, int PD, int PH>
 __device__ __forceinline__ void down_batched(const DownArgs<R, V> *aa, BlockMap bm,
                                              const IoPtr *io)
 {
     int blk, nblk;
     const int t = bm_find(bm, blockIdx.x, &blk, &nblk);
-    DownArgs<R, V> a = aa[t];
-    if (io) {
-        a.f_uniform = reinterpret_cast<const cx<R> *>(io[a.io_index].in);
-        a.f_hit = a.f_uniform;
-        a.out = reinterpret_cast<cx<R> *>(io[a.io_index].out);
-    }
-    down_eval_body<R, V, KER, SRC, EPI, PD, PH>(a, blk);
+    // the arguments read in place (a copy of them ended up in scratch
+    // memory); the per-call pointers come from the table they point to
+    down_eval_body<R, V, KER, SRC, EPI, PD, PH, true>(aa[t], blk);
 }
 
 template <typename R, typename V, int KER, int SRC, int EPI, int PD>

@@ -11,16 +11,19 @@ namespace fn {
 // s = y (c_hi + c_lo) in double-double, split into the nearest integer n
 // and the remainder th.  Contraction stays off: fusing p - n with
 // p = y c_hi into one fma would count the rounding error of y c_hi twice.
-__device__ __noinline__ void grid_units(double y, double c_hi, double c_lo,
-                                        double *n_out, double *th_out)
+// (Returned by value: outputs through pointers would put the caller's
+// locals in scratch memory around the call.)
+struct GridUnits {
+    double n, th;
+};
+__device__ __noinline__ GridUnits grid_units(double y, double c_hi, double c_lo)
 {
 #pragma clang fp contract(off)
     double p = y * c_hi;
     double e = fma(y, c_hi, -p);
     e = fma(y, c_lo, e);
     double n = rint(p);
-    *n_out = n;
-    *th_out = (p - n) + e;
+    return {n, (p - n) + e};
 }
 
 // y -> (m, th): s = y N / (2 pi) in double-double from the double-double
@@ -36,8 +39,8 @@ __device__ __forceinline__ bool reduce_point(double yy, double c_hi, double c_lo
         *th_out = 0.25;
         return false;
     }
-    double n, th;
-    grid_units(yy, c_hi, c_lo, &n, &th);
+    const GridUnits gu = grid_units(yy, c_hi, c_lo);
+    double n = gu.n, th = gu.th;
     if (th > 0.5) {
         th -= 1.0;
         n += 1.0;
