@@ -514,13 +514,17 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_
         } else if (b == 0) {
             const int64_t mean = (P->N + (int64_t(1) << P->l) - 1) >> P->l;
             const size_t per = es * (kernel == KER_COT ? 3 : 1);
-            const size_t room = lim > F.band[0].smem + 64 ? lim - F.band[0].smem - 64 : 0;
+            const size_t room = lim > F.band[0].smem + 4 * (size_t)(nbot + 1) + 64
+                                    ? lim - F.band[0].smem - 4 * (size_t)(nbot + 1) - 64
+                                    : 0;
             int64_t cap = std::min<int64_t>(nbot * mean + nbot * mean / 4 + 64,
                                             (int64_t)(room / per) - 4);
             cap = std::min<int64_t>(cap, 4096) & ~int64_t(3);
             F.stage_cap = cap >= 64 ? (int)cap : 0;
+            // the sources (cap rounded up to 4), then the nbot + 1 leaf offsets
             if (F.stage_cap)
-                bytes = std::max(bytes, (size_t)F.stage_cap * per);
+                bytes = std::max(bytes, (size_t)((F.stage_cap + 3) & ~3) * per +
+                                            4 * (size_t)(nbot + 1));
         }
         F.band[b].smem += bytes;
     }

@@ -467,9 +467,20 @@ __device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk)
                 const int bn = a.leaf_pts * 2, SB = uni_stage_stride(a.leaf_pts, sizeof(R));
                 const int nf = nbot * bn;
                 const R *f = reinterpret_cast<const R *>(a.f_uniform) + first * bn;
-                for (int i = tid; i < nf; i += BLOCK) {
-                    const int leaf = i / bn;
-                    stage[i + (SB - bn) * leaf] = f[i];
+                // every load of a batch in flight at once (indices clamped)
+                for (int i0 = 0; i0 < nf; i0 += 8 * BLOCK) {
+                    R v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int i = i0 + tid + u * BLOCK;
+                        v[u] = f[i < nf ? i : nf - 1];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int i = i0 + tid + u * BLOCK;
+                        if (i < nf)
+                            stage[i + (SB - bn) * (i / bn)] = v[u];
+                    }
                 }
                 __syncthreads();
                 p2m_mfma<R, V, PU>(a, first, nbot, buf0, RS, g, lane, wave, stage, SB);
@@ -480,15 +491,39 @@ __device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk)
             const int32_t t0 = a.src.off[first], t1 = a.src.off[first + nbot];
             if (t1 - t0 <= a.stage_cap) {
                 const int cnt = t1 - t0;
+                const int cap4 = (a.stage_cap + 3) & ~3;
                 R *sv = stage;
-                cx<R> *sw = reinterpret_cast<cx<R> *>(stage + ((a.stage_cap + 3) & ~3));
+                cx<R> *sw = reinterpret_cast<cx<R> *>(stage + cap4);
+                // the leaves' offsets from t0, after the weights
+                int32_t *soff = reinterpret_cast<int32_t *>(
+                    stage + cap4 + (KER == KER_COT ? 2 * cap4 : 0));
                 const double invN = 1.0 / (double)a.N;
-                for (int i = tid; i < cnt; i += BLOCK) {
-                    const int32_t t = t0 + i;
-                    sv[i] = (R)rel_coord_r(a.src.m[t], a.src.th[t], a.src_leaf[t], a.l,
-                                           a.N, invN);
-                    if constexpr (KER == KER_COT)
-                        sw[i] = a.w_sorted[t];
+                if (tid <= nbot)
+                    soff[tid] = a.src.off[first + tid] - t0;
+                // every load of a batch in flight at once (indices clamped)
+                for (int i0 = 0; i0 < cnt; i0 += 4 * BLOCK) {
+                    int32_t mv[4], lv[4];
+                    double tv[4];
+                    cx<R> wv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        int i = i0 + tid + u * BLOCK;
+                        const int32_t t = t0 + (i < cnt ? i : cnt - 1);
+                        mv[u] = a.src.m[t];
+                        tv[u] = a.src.th[t];
+                        lv[u] = a.src_leaf[t];
+                        if constexpr (KER == KER_COT)
+                            wv[u] = a.w_sorted[t];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = i0 + tid + u * BLOCK;
+                        if (i < cnt) {
+                            sv[i] = (R)rel_coord_r(mv[u], tv[u], lv[u], a.l, a.N, invN);
+                            if constexpr (KER == KER_COT)
+                                sw[i] = wv[u];
+                        }
+                    }
                 }
                 __syncthreads();
                 const double r = ldexp((double)a.N, -(a.l + 1));
@@ -496,8 +531,7 @@ __device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk)
                 for (int idx = tid; idx < nbot * nch; idx += BLOCK) {
                     const int i = idx / nch, ch = idx - i * nch;
                     V acc[CHS];
-                    p2m_staged<R, V, KER>(sv, sw, a.src.off[first + i] - t0,
-                                          a.src.off[first + i + 1] - t0, ch * CHS, r, acc);
+                    p2m_staged<R, V, KER>(sv, sw, soff[i], soff[i + 1], ch * CHS, r, acc);
                     for (int c = 0; c < CHS; ++c) {
                         st_coef<R, V>(buf0, RS, i, ch * CHS + c, acc[c]);
                         g[(first + i) * PU + ch * CHS + c] = acc[c];
@@ -525,6 +559,8 @@ __device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk)
     }
     if (d == 0)
         return;
+    // (requested before the P2M, the tile held registers through it and
+    // cost occupancy)
     constexpr int nrt = PU / 16;
     const int used = (4 / nrt) * nrt;
     R am[PU / 4];
