@@ -39,7 +39,8 @@ TRAFFIC = {
         "summary": "profiles/down_eval_fwd_2p20_traffic.txt"},
 }
 PHASES = ("fwd_plan_ms", "fwd_up_ms", "fwd_trans_ms", "fwd_eval_ms", "inv_plan_ms",
-          "inv_up_ms", "inv_trans_ms", "inv_eval_ms")
+          "inv_up_ms", "inv_trans_ms", "inv_eval_ms", "log_up_ms", "log_trans_ms",
+          "log_eval_ms")
 
 
 def parse():
@@ -97,6 +98,21 @@ def eval_flops(info, n_targets, n_sources):
     return 3.0 * n_targets * n_sources / (1 << l) * 6.0 + n_targets * 4.0 * P
 
 
+def log_trans_flops(lmax, P):
+    """The translations of the log-sum FMM: real data, so half the complex
+    count of trans_flops: P(P+1) + 6P^2 per box of levels 3..lmax."""
+    boxes = (1 << (lmax + 1)) - 8 if lmax >= 3 else 0
+    return boxes * (P * (P + 1) + 6 * P * P)
+
+
+def log_eval_flops(lmax, P, n):
+    """The log-sum evaluation at its 2n targets (the n uniform points and the
+    n sources): 3 (2n) n / 2^lmax near-field pairs (Eq. 23) at 3 flops
+    (integer and fractional differences, product) and a P-term real Horner
+    L2P (2 flops per term) per target."""
+    return 3.0 * (2 * n) * n / (1 << lmax) * 3.0 + 2 * n * 2.0 * P
+
+
 def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
     """Times `steps` one-shot fwd + inv pairs (nufft_fwd + inufft, one
     synchronisation each), then the same transforms through plans with
@@ -122,7 +138,9 @@ def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
     # phases: events on the library's stream (torch's current stream)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
     ph = {k: [] for k in ("fwd_up", "fwd_trans", "fwd_eval", "inv_up", "inv_trans",
-                          "inv_eval", "fwd_plan", "inv_plan")}
+                          "inv_eval", "fwd_plan", "inv_plan", "log_up", "log_trans",
+                          "log_eval")}
+    log_terms = 0
     info_f = info_i = None
     for it in range(warmup + steps):
         t = time.perf_counter()
@@ -137,9 +155,15 @@ def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
         ev[3].record()
         info_f = pf.info()
         pf.destroy()
+        # the inverse setup's log-sum FMM is timed by the library's own
+        # events (its kernels run inside the plan)
+        fn.set_timing(True)
         t = time.perf_counter()
         pi = fn.Plan.inverse(yj, eps, dtc)
         tpi = time.perf_counter() - t
+        fn.set_timing(False)
+        tl = pi.timings()
+        log_terms = tl["log_terms"]
         ev[4].record()
         pi.execute_phase(gj, fo, 0)
         ev[5].record()
@@ -158,6 +182,9 @@ def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
             ph["inv_eval"].append(ev[6].elapsed_time(ev[7]))
             ph["fwd_plan"].append(tpf * 1e3)
             ph["inv_plan"].append(tpi * 1e3)
+            ph["log_up"].append(tl["log_up_ms"])
+            ph["log_trans"].append(tl["log_trans_ms"])
+            ph["log_eval"].append(tl["log_eval_ms"])
 
     # evaluation only (plan reused, Section 3.3), outside the headline
     pf = fn.Plan.forward(N, yu, eps, dtc)
@@ -182,7 +209,7 @@ def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
         "exec_ms_per_step": 1e3 * exec_wall / steps,
         **{k + "_ms": float(np.median(v) if k.endswith("plan") else np.mean(v))
            for k, v in ph.items()},
-        "info_f": info_f, "info_i": info_i, "g": g, "fo": fo,
+        "info_f": info_f, "info_i": info_i, "g": g, "fo": fo, "log_terms": log_terms,
     }
 
 
@@ -346,7 +373,8 @@ def main():
 
     info_f, info_i = res["info_f"], res["info_i"]
     # dominant kernel: the longest of the downward translation and evaluation
-    # kernels of the two transforms (each timed alone with events)
+    # kernels of the two transforms and of the inverse setup's log-sum FMM
+    # (each timed alone with events)
     cands = [
         ("k_down_trans<double,cot,uniform sources,forward>", "mfma", trans_flops(info_f),
          res["fwd_trans_ms"]),
@@ -356,6 +384,10 @@ def main():
          res["inv_trans_ms"]),
         ("k_down_eval<double,cot,sorted sources,inverse>", "alu",
          eval_flops(info_i, N, N), res["inv_eval_ms"]),
+        ("k_down_trans<double,log,sorted sources,log-sums>", "mfma",
+         log_trans_flops(info_i.lmax, res["log_terms"]), res["log_trans_ms"]),
+        ("k_down_eval<double,log,sorted sources,log-sums>", "alu",
+         log_eval_flops(info_i.lmax, res["log_terms"], N), res["log_eval_ms"]),
     ]
     dom, bound, fl, dur_ms = max(cands, key=lambda c: c[3])
     dur = dur_ms * 1e-3

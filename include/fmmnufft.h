@@ -146,6 +146,21 @@ int nufft_plan_coeffs(const fn_plan *plan, double *chat, void *dhat, void *strea
 /* Reports the parameters of a plan. */
 int nufft_plan_get_info(const fn_plan *plan, fn_plan_info *info);
 
+/* Measurement of the inverse setup (for benchmarks; not needed otherwise).
+ * With timing on (on != 0; it is off at load), every inverse plan created
+ * afterwards records HIP events on its stream around the three passes of its
+ * log-sum FMM (Eq. p8): the upward pass with the level-2 regular part, the
+ * downward translations, and the evaluation (which also forms Chat, Dhat).
+ * The switch is process-wide.  Always FN_OK. */
+int nufft_set_timing(int on);
+
+/* ms[0..2]: durations (milliseconds) of those three passes for this plan,
+ * read when its setup synchronised; -1 when not recorded (timing off, or a
+ * forward plan).  *log_terms (if log_terms is not NULL): the expansion
+ * length of the log-sum FMM (0 for a forward plan).  FN_EINVAL for a NULL
+ * plan or ms. */
+int nufft_plan_get_timings(const fn_plan *plan, float *ms, int32_t *log_terms);
+
 /* The paper's parameters for (N, M, eps, dtype): the truncation numbers of
  * Eq. (18.2) and the depth of Eq. (25) with l_max = round(log2 sqrt(N M)) - 5
  * (Section 3.2).  Plans default to a depth measured on MI355X instead, one

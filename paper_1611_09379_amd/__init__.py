@@ -34,6 +34,7 @@ ABI_SYMBOLS = (
     "nufft_select_params",
     "nufft_fwd_batched", "nufft_plan_fwd_batched", "nufft_execute_batched",
     "nufft_destroy_batched", "nufft_autotune", "nufft_autotune_clear",
+    "nufft_set_timing", "nufft_plan_get_timings",
     "nufft_last_error",
 )
 
@@ -92,6 +93,8 @@ def load_library(path: str = LIB_PATH):
         "nufft_destroy_batched": [vp],
         "nufft_autotune": [ctypes.c_int, i64, i64, dbl, ctypes.c_int, pi32, pi32, vp],
         "nufft_autotune_clear": [],
+        "nufft_set_timing": [ctypes.c_int],
+        "nufft_plan_get_timings": [vp, ctypes.POINTER(ctypes.c_float), pi32],
         "nufft_last_error": [],
     }
     for name, args in sig.items():
@@ -180,6 +183,16 @@ class Plan:
         out = PlanInfo()
         _check(load_library().nufft_plan_get_info(self._h, ctypes.byref(out)))
         return out
+
+    def timings(self):
+        """Inverse plans created with timing on (set_timing): milliseconds of
+        the log-sum FMM's upward pass, translations and evaluation, and its
+        expansion length; -1 entries when not recorded."""
+        ms = (ctypes.c_float * 3)()
+        terms = ctypes.c_int32()
+        _check(load_library().nufft_plan_get_timings(self._h, ms, ctypes.byref(terms)))
+        return {"log_up_ms": ms[0], "log_trans_ms": ms[1], "log_eval_ms": ms[2],
+                "log_terms": terms.value}
 
     def coeffs(self):
         """Inverse plans: (Chat, Dhat) of Eq. (p8), rescaled by 2^N and 2^-N
@@ -358,3 +371,9 @@ def autotune(kind: str, N: int, M: int, eps: float, dtype: int = FN_C128):
 def autotune_clear():
     """Forgets every choice recorded by autotune."""
     _check(load_library().nufft_autotune_clear())
+
+
+def set_timing(on: bool):
+    """Process-wide: inverse plans created while on record event timings of
+    their log-sum FMM (Plan.timings)."""
+    _check(load_library().nufft_set_timing(1 if on else 0))

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -359,6 +360,11 @@ struct fn_plan {
     Buf hit, chat, dhat, wsorted;
     // error flags of the setup kernels, read once at the end of the plan
     Buf flags;
+    // (measurement) events around the inverse setup's log-sum FMM passes,
+    // recorded when timing is on, and their durations (ms; -1 if not taken)
+    hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
+    float tms[3] = {-1.f, -1.f, -1.f};
+    int log_terms = 0;
     // temporaries of the setup, released after its synchronisation
     std::vector<Buf> tmp;
     hipStream_t stream = nullptr; // stream of the last call
@@ -392,11 +398,21 @@ static void release_tmp(fn_plan *P)
     P->tmp.clear();
 }
 
+static void drop_events(fn_plan *P)
+{
+    for (hipEvent_t &e : P->tev)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+}
+
 static void release_plan(fn_plan *P)
 {
     for (Buf *b : P->all())
         release(*b);
     release_tmp(P);
+    drop_events(P);
 }
 
 // A temporary of the setup: kept until the plan's synchronisation.
@@ -882,6 +898,12 @@ static int finish_plan(fn_plan *P, hipStream_t st)
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
     const int hflags = *hw;
+    if (e == hipSuccess && P->tev[0]) {
+        for (int i = 0; i < 3; ++i)
+            if (hipEventElapsedTime(&P->tms[i], P->tev[i], P->tev[i + 1]) != hipSuccess)
+                P->tms[i] = -1.f;
+    }
+    drop_events(P);
     release_tmp(P);
     if (e != hipSuccess)
         return fail(FN_EHIP, "plan setup: %s", hipGetErrorString(e));
@@ -978,6 +1000,10 @@ static int exec_fwd(fn_plan *P, const void *in, void *out, int phase,
 
 // --------------------------------------------------------- inverse plan
 
+// Event timing of the inverse setup's log-sum FMM (measurement only; off
+// unless nufft_set_timing turns it on).
+static std::atomic<int> g_timing{0};
+
 // The log-kernel FMM of the plan: log|Chat_k| at the uniform points and
 // log|Dhat_j| at the sorted sources, and from them (in the evaluation's
 // epilogue) Chat and Dhat (Eq. p8).  Enqueues only.
@@ -1012,9 +1038,21 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     ua.leaf_pts = 0;
     ua.logc1 = std::log(2.0 * M_PI / (double)P->N);
     ua.logc2 = std::log(2.0);
+    P->log_terms = PD;
+    const bool timed = g_timing.load() != 0;
+    if (timed)
+        for (hipEvent_t &e : P->tev)
+            if (hipEventCreate(&e) != hipSuccess) {
+                drop_events(P);
+                return fail(FN_EHIP, "event creation failed");
+            }
+    if (timed)
+        HIPCHK(hipEventRecord(P->tev[0], st));
     rc = launch_up<R, V, KER_LOG, SET_SORTED>(F, ua, st);
     if (rc)
         return rc;
+    if (timed)
+        HIPCHK(hipEventRecord(P->tev[1], st));
     DownArgs<R, V> da{};
     fill_down(P, F, T, da);
     da.src = src;
@@ -1026,7 +1064,17 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     da.flags_out = (int *)P->flags.p;
     da.logself = std::log(2.0 * M_PI / (double)P->N);
     // the evaluation's epilogue forms Chat and Dhat
-    return launch_down<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>(P, F, da, st);
+    rc = launch_down<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>(P, F, da, st, 1);
+    if (rc)
+        return rc;
+    if (timed)
+        HIPCHK(hipEventRecord(P->tev[2], st));
+    rc = launch_down<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>(P, F, da, st, 2);
+    if (rc)
+        return rc;
+    if (timed)
+        HIPCHK(hipEventRecord(P->tev[3], st));
+    return FN_OK;
 }
 
 template <typename R>
@@ -1921,6 +1969,23 @@ int nufft_plan_get_info(const fn_plan *plan, fn_plan_info *info)
     info->lmax = plan->l;
     info->nterms = plan->cot.PD;
     info->eps = plan->eps;
+    return FN_OK;
+}
+
+int nufft_set_timing(int on)
+{
+    g_timing.store(on ? 1 : 0);
+    return FN_OK;
+}
+
+int nufft_plan_get_timings(const fn_plan *plan, float *ms, int32_t *log_terms)
+{
+    if (!plan || !ms)
+        return fail(FN_EINVAL, "plan or ms is NULL");
+    for (int i = 0; i < 3; ++i)
+        ms[i] = plan->tms[i];
+    if (log_terms)
+        *log_terms = plan->log_terms;
     return FN_OK;
 }
 

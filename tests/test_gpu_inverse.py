@@ -142,3 +142,32 @@ def test_coeffs_sampled(N, amp, dtype):
     # the log-sums are binary64 on both paths, truncated for a tenth of eps
     tol = 1e-12 if dtype == fn.FN_C128 else 1e-6
     assert ec < tol and ed < tol
+
+
+def test_setup_timings():
+    """Event timings of the log-sum FMM: recorded only while timing is on,
+    and leaving the coefficients unchanged."""
+    N = 1 << 14
+    y, c = workloads.inverse_case(N, 0.4, seed=3)
+    yd = dev(y)
+    say(f"timings N={N}")
+    p0 = fn.Plan.inverse(yd, 1e-12, fn.FN_C128)
+    t0 = p0.timings()
+    ch0, dh0 = (host(x) for x in p0.coeffs())
+    p0.destroy()
+    assert t0["log_up_ms"] == -1 and t0["log_trans_ms"] == -1 and t0["log_eval_ms"] == -1
+    assert t0["log_terms"] > 0
+    fn.set_timing(True)
+    try:
+        p1 = fn.Plan.inverse(yd, 1e-12, fn.FN_C128)
+    finally:
+        fn.set_timing(False)
+    t1 = p1.timings()
+    ch1, dh1 = (host(x) for x in p1.coeffs())
+    p1.destroy()
+    say("timings", t1)
+    assert t1["log_up_ms"] > 0 and t1["log_trans_ms"] > 0 and t1["log_eval_ms"] > 0
+    assert np.array_equal(ch0, ch1) and np.array_equal(dh0, dh1)
+    pf = fn.Plan.forward(N, yd, 1e-12, fn.FN_C128)
+    assert pf.timings()["log_terms"] == 0
+    pf.destroy()
