@@ -34,9 +34,12 @@ PEAK_HBM = 8.0e12        # B/s
 # Valid only for the kernel sources they were taken on: any change to them
 # turns the figure back into null until the counters are taken again.
 TRAFFIC = {
+    "k_down_eval<double,log,sorted sources,log-sums>": {
+        "src_sha256": "6272ead49903f6f8e022d685e6f7b3a37b9e16a0b4d47e2873525e723621c588", "fetch": 32940300, "write": 25199379,
+        "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_eval<double,cot,uniform sources,forward>": {
-        "src_sha256": "f4ba21dd154a69e43b64c4f3c88f3cc6ca695b116d904c60b3517934dceb0666", "fetch": 44439106, "write": 34123861,
-        "summary": "profiles/down_eval_fwd_2p20_traffic.txt"},
+        "src_sha256": "6272ead49903f6f8e022d685e6f7b3a37b9e16a0b4d47e2873525e723621c588", "fetch": 44486726, "write": 34099093,
+        "summary": "profiles/bench_kernels_2p20_traffic.txt"},
 }
 PHASES = ("fwd_plan_ms", "fwd_up_ms", "fwd_trans_ms", "fwd_eval_ms", "inv_plan_ms",
           "inv_up_ms", "inv_trans_ms", "inv_eval_ms", "log_up_ms", "log_trans_ms",
