@@ -57,3 +57,11 @@ def test_truncation_numbers_eq_18_2():
     for row in load_golden("eq18_params.txt"):
         eps, N, q, p, l = float(row[0]), int(row[1]), int(row[2]), int(row[3]), int(row[4])
         assert fn.select_params(N, N, eps) == (p, q, l), row
+
+
+def test_timing_switch_host_only():
+    lib = fn.load_library()
+    assert lib.nufft_set_timing(1) == fn.FN_OK
+    assert lib.nufft_set_timing(0) == fn.FN_OK
+    ms = (ctypes.c_float * 3)()
+    assert lib.nufft_plan_get_timings(None, ms, None) == fn.FN_EINVAL
