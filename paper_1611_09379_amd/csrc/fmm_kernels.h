@@ -1057,8 +1057,20 @@ __device__ __forceinline__ double near_dist(int32_t tm, int32_t m, double a, dou
     return (double)(tm - m) + (a - b);
 }
 
-// Cot near field from staged sources [j0, j1): sum w / (tau - sigma).
-template <typename R>
+// The same with GT (the target on the grid, a = 0): a - b is then -b
+// exactly, so one subtraction gives the same value.
+template <bool GT>
+__device__ __forceinline__ double near_dist_t(int32_t tm, int32_t m, double a, double b)
+{
+    if constexpr (GT)
+        return (double)(tm - m) - b;
+    else
+        return (double)(tm - m) + (a - b);
+}
+
+// Cot near field from staged sources [j0, j1): sum w / (tau - sigma)
+// (GT: the target is on the grid, tth = 0).
+template <typename R, bool GT>
 __device__ __forceinline__ cx<R> near_cot_staged(const NearStage<R> &ns, int32_t j0,
                                                  int32_t j1, int32_t tmr, double tth)
 {
@@ -1069,10 +1081,10 @@ __device__ __forceinline__ cx<R> near_cot_staged(const NearStage<R> &ns, int32_t
     // distance is zero: exact hits never reach the near field); binary32
     // keeps one reciprocal per pair
     for (; j + 4 <= j1; j += 4) {
-        const R d0 = (R)near_dist(tmd, ns.m[j], tth, ns.th[j]);
-        const R d1 = (R)near_dist(tmd, ns.m[j + 1], tth, ns.th[j + 1]);
-        const R d2 = (R)near_dist(tmd, ns.m[j + 2], tth, ns.th[j + 2]);
-        const R d3 = (R)near_dist(tmd, ns.m[j + 3], tth, ns.th[j + 3]);
+        const R d0 = (R)near_dist_t<GT>(tmd, ns.m[j], tth, ns.th[j]);
+        const R d1 = (R)near_dist_t<GT>(tmd, ns.m[j + 1], tth, ns.th[j + 1]);
+        const R d2 = (R)near_dist_t<GT>(tmd, ns.m[j + 2], tth, ns.th[j + 2]);
+        const R d3 = (R)near_dist_t<GT>(tmd, ns.m[j + 3], tth, ns.th[j + 3]);
         const cx<R> w0 = ns.w[j], w1 = ns.w[j + 1], w2 = ns.w[j + 2], w3 = ns.w[j + 3];
         if constexpr (sizeof(R) == 8) {
             const R r01 = recip(d0 * d1), r23 = recip(d2 * d3);
@@ -1093,7 +1105,7 @@ __device__ __forceinline__ cx<R> near_cot_staged(const NearStage<R> &ns, int32_t
         }
     }
     for (; j < j1; ++j) {
-        const R r = recip((R)near_dist(tmd, ns.m[j], tth, ns.th[j]));
+        const R r = recip((R)near_dist_t<GT>(tmd, ns.m[j], tth, ns.th[j]));
         const cx<R> w = ns.w[j];
         a0.re = fma(w.re, r, a0.re);
         a0.im = fma(w.im, r, a0.im);
@@ -1104,7 +1116,7 @@ __device__ __forceinline__ cx<R> near_cot_staged(const NearStage<R> &ns, int32_t
 // log prod |tau - sigma| over the staged sources [j, j1), folded into
 // prod x 2^expo (renormalised after every eight factors and at the end;
 // every factor is below 2^31 in grid units, so eight of them stay in range).
-template <typename R>
+template <typename R, bool GT>
 __device__ __forceinline__ void log_prod_range(const NearStage<R> &ns, int32_t j, int32_t j1,
                                                int32_t tmr, double tth, double &prod,
                                                int &expo)
@@ -1114,7 +1126,7 @@ __device__ __forceinline__ void log_prod_range(const NearStage<R> &ns, int32_t j
         double d[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            d[u] = fabs(near_dist(tmd, ns.m[j + u], tth, ns.th[j + u]));
+            d[u] = fabs(near_dist_t<GT>(tmd, ns.m[j + u], tth, ns.th[j + u]));
         const double q = ((d[0] * d[1]) * (d[2] * d[3])) * ((d[4] * d[5]) * (d[6] * d[7]));
         int e;
         prod = frexp(prod * q, &e);
@@ -1122,15 +1134,15 @@ __device__ __forceinline__ void log_prod_range(const NearStage<R> &ns, int32_t j
     }
     double q = 1.0;
     for (; j < j1; ++j)
-        q *= fabs(near_dist(tmd, ns.m[j], tth, ns.th[j]));
+        q *= fabs(near_dist_t<GT>(tmd, ns.m[j], tth, ns.th[j]));
     int e;
     prod = frexp(prod * q, &e);
     expo += e;
 }
 
 // Log near field from staged sources [j0, j1) without the source `self`:
-// log prod |tau - sigma|.
-template <typename R>
+// log prod |tau - sigma| (GT: the target is on the grid, tth = 0).
+template <typename R, bool GT>
 __device__ __forceinline__ double near_log_staged(const NearStage<R> &ns, int32_t j0,
                                                   int32_t j1, int32_t self, int32_t tmr,
                                                   double tth)
@@ -1139,10 +1151,10 @@ __device__ __forceinline__ double near_log_staged(const NearStage<R> &ns, int32_
     int expo = 0;
     // the source `self` (the target itself) splits the range: no test per pair
     if (self >= j0 && self < j1) {
-        log_prod_range(ns, j0, self, tmr, tth, prod, expo);
-        log_prod_range(ns, self + 1, j1, tmr, tth, prod, expo);
+        log_prod_range<R, GT>(ns, j0, self, tmr, tth, prod, expo);
+        log_prod_range<R, GT>(ns, self + 1, j1, tmr, tth, prod, expo);
     } else {
-        log_prod_range(ns, j0, j1, tmr, tth, prod, expo);
+        log_prod_range<R, GT>(ns, j0, j1, tmr, tth, prod, expo);
     }
     return log(prod) + (double)expo * 0.69314718055994530942;
 }
@@ -1604,8 +1616,8 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             const int il = (int)(leaf - leaf0);
             const R u = (R)rel_coord_r(k, 0.0, leaf, a.l, N, invN);
             V h = horner4<R, V, PD>(leafloc, RS, il, u);
-            cx<R> nr = staged ? near_cot_staged<R>(ns, ns.off[il], ns.off[il + 3],
-                                                   (int32_t)(k - base), 0.0)
+            cx<R> nr = staged ? near_cot_staged<R, true>(ns, ns.off[il], ns.off[il + 3],
+                                                         (int32_t)(k - base), 0.0)
                               : near_cot<R, V, SRC>(a, k, 0.0, leaf, nullptr, 0, (const cx<R> *)f_uniform);
             double hr = (double)h.re + hscale * (double)nr.re;
             double hi = (double)h.im + hscale * (double)nr.im;
@@ -1629,7 +1641,7 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             const R u = (R)rel_coord_r(k, 0.0, leaf, a.l, N, invN);
             V far = horner4<R, V, PD>(leafloc, RS, il, u);
             const double nr =
-                staged ? near_log_staged<R>(ns, ns.off[il], ns.off[il + 3], -1,
+                staged ? near_log_staged<R, true>(ns, ns.off[il], ns.off[il + 3], -1,
                                             (int32_t)(k - base), 0.0) -
                              near_log_background(k, 0.0, leaf, a.l, N)
                        : near_log<R, V>(a, k, 0.0, leaf, -1);
@@ -1679,7 +1691,7 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             const R u = (R)rel_coord_r(tm, th, leaf, a.l, N, invN);
             V far = horner4<R, V, PD>(leafloc, RS, il, u);
             const double nr =
-                staged ? near_log_staged<R>(ns, ns.off[il], ns.off[il + 3], t + ns.self0,
+                staged ? near_log_staged<R, false>(ns, ns.off[il], ns.off[il + 3], t + ns.self0,
                                             (int32_t)(tm - base), th) -
                              near_log_background(tm, th, leaf, a.l, N)
                        : near_log<R, V>(a, tm, th, leaf, t);
