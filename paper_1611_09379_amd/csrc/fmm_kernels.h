@@ -1391,9 +1391,11 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             [&](int i) { return i + 1; }, bufA);
     }
     __syncthreads();
-    // shift every row of X to the root (bufB rows), then sum
+    // shift every row of X to the root (bufB rows), then sum; consecutive
+    // threads take the rows of one coefficient n, so that a wavefront's
+    // sums (PD - n terms) have nearly the same length
     for (int idx = tid; idx < (nA + 1) * PD; idx += BLOCK) {
-        const int li = idx / PD, n = idx - li * PD;
+        const int n = idx / (nA + 1), li = idx - n * (nA + 1);
         const int sh = nA - li; // lr - L
         const int64_t A = R0 >> sh;
         // 2 rho = 2^(1 - sh); -2 delta with delta = ((2 R0 + 1) - (2A + 1) 2^sh) / 2^sh;
