@@ -28,18 +28,30 @@ METRIC = "(N+M)/s at rel-ℓ2 1e-12 (FP64) vs 1e-6 (mixed), N=M=2^20 fwd+inv"
 PEAK_FP64 = 78.6e12      # MI355X FP64 vector (and matrix) FLOP/s
 PEAK_FP32 = 157.3e12     # MI355X FP32 vector FLOP/s
 PEAK_HBM = 8.0e12        # B/s
-# HBM bytes per launch of the dominant kernel from FETCH_SIZE and WRITE_SIZE
+# HBM bytes per launch of the downward kernels from FETCH_SIZE and WRITE_SIZE
 # (rocprofv3 --pmc, one counter per run), each scaled by what the counter
 # reads for a plain 256 MiB elementwise kernel (fetch x2.000, write x1.000).
 # Valid only for the kernel sources they were taken on: any change to them
 # turns the figure back into null until the counters are taken again.
 TRAFFIC = {
-    "k_down_eval<double,log,sorted sources,log-sums>": {
-        "src_sha256": "6272ead49903f6f8e022d685e6f7b3a37b9e16a0b4d47e2873525e723621c588", "fetch": 32940300, "write": 25199379,
-        "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+    "k_down_trans<double,cot,uniform sources,forward>": {
+        "src_sha256": "9f42b2de92a77771e4a4526f7ea1abbd32208e2e9120a8d0bbdc80141ab023fe",
+        "fetch": 33620757, "write": 8388608, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_eval<double,cot,uniform sources,forward>": {
-        "src_sha256": "6272ead49903f6f8e022d685e6f7b3a37b9e16a0b4d47e2873525e723621c588", "fetch": 44486726, "write": 34099093,
-        "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "9f42b2de92a77771e4a4526f7ea1abbd32208e2e9120a8d0bbdc80141ab023fe",
+        "fetch": 44491712, "write": 34098365, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+    "k_down_trans<double,cot,sorted sources,inverse>": {
+        "src_sha256": "9f42b2de92a77771e4a4526f7ea1abbd32208e2e9120a8d0bbdc80141ab023fe",
+        "fetch": 66982679, "write": 16777216, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+    "k_down_eval<double,cot,sorted sources,inverse>": {
+        "src_sha256": "9f42b2de92a77771e4a4526f7ea1abbd32208e2e9120a8d0bbdc80141ab023fe",
+        "fetch": 64071238, "write": 16777216, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+    "k_down_trans<double,log,sorted sources,log-sums>": {
+        "src_sha256": "9f42b2de92a77771e4a4526f7ea1abbd32208e2e9120a8d0bbdc80141ab023fe",
+        "fetch": 33859264, "write": 8388608, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+    "k_down_eval<double,log,sorted sources,log-sums>": {
+        "src_sha256": "9f42b2de92a77771e4a4526f7ea1abbd32208e2e9120a8d0bbdc80141ab023fe",
+        "fetch": 32892480, "write": 25199612, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
 }
 PHASES = ("fwd_plan_ms", "fwd_up_ms", "fwd_trans_ms", "fwd_eval_ms", "inv_plan_ms",
           "inv_up_ms", "inv_trans_ms", "inv_eval_ms", "log_up_ms", "log_trans_ms",
@@ -398,7 +410,8 @@ def main():
             "unit": "TFLOP/s", "frac": fl / dur / PEAK_FP64, "traffic": traffic_of(dom), "traffic_unit": "bytes per launch",
             "kernel": dom, "flops_per_launch": fl, "avg_launch_ms": dur_ms,
             "others": {c[0]: {"bound": c[1], "tflops": c[2] / (c[3] * 1e-3) / 1e12,
-                              "frac": c[2] / (c[3] * 1e-3) / PEAK_FP64, "ms": c[3]}
+                              "frac": c[2] / (c[3] * 1e-3) / PEAK_FP64, "ms": c[3],
+                              "traffic": traffic_of(c[0])}
                        for c in cands}}
 
     out = {
