@@ -529,7 +529,8 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_
                                             uni_stage_stride(uniform_leaf_pts(P), es) * es);
         } else if (b == 0) {
             const int64_t mean = (P->N + (int64_t(1) << P->l) - 1) >> P->l;
-            const size_t per = es * (kernel == KER_COT ? 3 : 1);
+            // coordinate, its fourth power, and (cot) the complex weight
+            const size_t per = es * (kernel == KER_COT ? 4 : 2);
             const size_t room = lim > F.band[0].smem + 4 * (size_t)(nbot + 1) + 64
                                     ? lim - F.band[0].smem - 4 * (size_t)(nbot + 1) - 64
                                     : 0;

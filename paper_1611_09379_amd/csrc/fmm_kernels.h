@@ -267,14 +267,17 @@ __device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, int64_t b,
     }
 }
 
-// P2M from sources staged in LDS: relative coordinates sv and (cot kernel)
-// weights sw of the sources [j0, j1) of one leaf, moments m0 .. m0+CHS-1.
-// Four sources at a time, their powers v^m0 formed as independent chains;
-// each moment still sums its sources in order.
+// P2M from sources staged in LDS: relative coordinates sv, their fourth
+// powers sv4 and (cot kernel) weights sw of the sources [j0, j1) of one
+// leaf, moments m0 .. m0+CHS-1 (m0 a multiple of 4).  Four sources at a
+// time, their powers v^m0 = (v^4)^(m0/4) formed as independent chains (two
+// squarings fewer than from v); each moment still sums its sources in
+// order.
 template <typename R, typename V, int KER>
-__device__ __forceinline__ void p2m_staged(const R *sv, const cx<R> *sw, int j0, int j1,
-                                           int m0, double r, V *acc)
+__device__ __forceinline__ void p2m_staged(const R *sv, const R *sv4, const cx<R> *sw, int j0,
+                                           int j1, int m0, double r, V *acc)
 {
+    static_assert(CHS % 4 == 0, "chunks start at multiples of 4");
     for (int c = 0; c < CHS; ++c)
         acc[c] = vzero<V>();
     int j = j0;
@@ -284,14 +287,14 @@ __device__ __forceinline__ void p2m_staged(const R *sv, const cx<R> *sw, int j0,
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             v[u] = sv[j + u];
-            sq[u] = v[u];
+            sq[u] = sv4[j + u];
             pw[u] = R(1);
             if constexpr (KER == KER_COT)
                 w[u] = sw[j + u];
             else
                 w[u] = R(1);
         }
-        for (int e = m0; e; e >>= 1) {
+        for (int e = m0 >> 2; e; e >>= 1) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (e & 1)
@@ -310,7 +313,7 @@ __device__ __forceinline__ void p2m_staged(const R *sv, const cx<R> *sw, int j0,
     }
     for (; j < j1; ++j) {
         const R v = sv[j];
-        R pw = ipow(v, m0);
+        R pw = ipow(sv4[j], m0 >> 2);
         V w;
         if constexpr (KER == KER_COT)
             w = sw[j];
@@ -494,9 +497,10 @@ __device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk)
                 const int cap4 = (a.stage_cap + 3) & ~3;
                 R *sv = stage;
                 cx<R> *sw = reinterpret_cast<cx<R> *>(stage + cap4);
-                // the leaves' offsets from t0, after the weights
-                int32_t *soff = reinterpret_cast<int32_t *>(
-                    stage + cap4 + (KER == KER_COT ? 2 * cap4 : 0));
+                // the fourth powers after the weights, then the leaves'
+                // offsets from t0
+                R *sv4 = stage + cap4 + (KER == KER_COT ? 2 * cap4 : 0);
+                int32_t *soff = reinterpret_cast<int32_t *>(sv4 + cap4);
                 const double invN = 1.0 / (double)a.N;
                 if (tid <= nbot)
                     soff[tid] = a.src.off[first + tid] - t0;
@@ -519,7 +523,10 @@ __device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk)
                     for (int u = 0; u < 4; ++u) {
                         const int i = i0 + tid + u * BLOCK;
                         if (i < cnt) {
-                            sv[i] = (R)rel_coord_r(mv[u], tv[u], lv[u], a.l, a.N, invN);
+                            const R v = (R)rel_coord_r(mv[u], tv[u], lv[u], a.l, a.N, invN);
+                            const R v2 = v * v;
+                            sv[i] = v;
+                            sv4[i] = v2 * v2;
                             if constexpr (KER == KER_COT)
                                 sw[i] = wv[u];
                         }
@@ -531,7 +538,7 @@ __device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk)
                 for (int idx = tid; idx < nbot * nch; idx += BLOCK) {
                     const int i = idx / nch, ch = idx - i * nch;
                     V acc[CHS];
-                    p2m_staged<R, V, KER>(sv, sw, soff[i], soff[i + 1], ch * CHS, r, acc);
+                    p2m_staged<R, V, KER>(sv, sv4, sw, soff[i], soff[i + 1], ch * CHS, r, acc);
                     for (int c = 0; c < CHS; ++c) {
                         st_coef<R, V>(buf0, RS, i, ch * CHS + c, acc[c]);
                         g[(first + i) * PU + ch * CHS + c] = acc[c];
