@@ -35,23 +35,23 @@ PEAK_HBM = 8.0e12        # B/s
 # turns the figure back into null until the counters are taken again.
 TRAFFIC = {
     "k_down_trans<double,cot,uniform sources,forward>": {
-        "src_sha256": "9f42b2de92a77771e4a4526f7ea1abbd32208e2e9120a8d0bbdc80141ab023fe",
-        "fetch": 33620757, "write": 8388608, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "2f00f1f05ac56f486de7c5131824b452cbb568e99bf3ec04a8d26fa2d83f07f9",
+        "fetch": 33609525, "write": 8388456, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_eval<double,cot,uniform sources,forward>": {
-        "src_sha256": "9f42b2de92a77771e4a4526f7ea1abbd32208e2e9120a8d0bbdc80141ab023fe",
-        "fetch": 44491712, "write": 34098365, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "2f00f1f05ac56f486de7c5131824b452cbb568e99bf3ec04a8d26fa2d83f07f9",
+        "fetch": 44497914, "write": 34098011, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_trans<double,cot,sorted sources,inverse>": {
-        "src_sha256": "9f42b2de92a77771e4a4526f7ea1abbd32208e2e9120a8d0bbdc80141ab023fe",
-        "fetch": 66982679, "write": 16777216, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "2f00f1f05ac56f486de7c5131824b452cbb568e99bf3ec04a8d26fa2d83f07f9",
+        "fetch": 66979275, "write": 16776912, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_eval<double,cot,sorted sources,inverse>": {
-        "src_sha256": "9f42b2de92a77771e4a4526f7ea1abbd32208e2e9120a8d0bbdc80141ab023fe",
-        "fetch": 64071238, "write": 16777216, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "2f00f1f05ac56f486de7c5131824b452cbb568e99bf3ec04a8d26fa2d83f07f9",
+        "fetch": 64053957, "write": 16776912, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_trans<double,log,sorted sources,log-sums>": {
-        "src_sha256": "9f42b2de92a77771e4a4526f7ea1abbd32208e2e9120a8d0bbdc80141ab023fe",
-        "fetch": 33859264, "write": 8388608, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "2f00f1f05ac56f486de7c5131824b452cbb568e99bf3ec04a8d26fa2d83f07f9",
+        "fetch": 33859511, "write": 8388456, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_eval<double,log,sorted sources,log-sums>": {
-        "src_sha256": "9f42b2de92a77771e4a4526f7ea1abbd32208e2e9120a8d0bbdc80141ab023fe",
-        "fetch": 32892480, "write": 25199612, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "2f00f1f05ac56f486de7c5131824b452cbb568e99bf3ec04a8d26fa2d83f07f9",
+        "fetch": 32921029, "write": 25199145, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
 }
 PHASES = ("fwd_plan_ms", "fwd_up_ms", "fwd_trans_ms", "fwd_eval_ms", "inv_plan_ms",
           "inv_up_ms", "inv_trans_ms", "inv_eval_ms", "log_up_ms", "log_trans_ms",
