@@ -145,14 +145,22 @@ static int paper_depth(int64_t N, int64_t M)
 // targets: its near field runs on staged uniform sources and is cheap next
 // to the translations).  Inverse: 4 below lg = 17, then 5 (its sorted-source
 // and log near fields cost more per pair).  FN_LEAF_OFFSET overrides both.
-static int default_depth(int64_t N, int64_t M, int kind)
+// The mixed path also keeps at most 128 sources per leaf: its moments sum a
+// leaf's sources and its near field three leaves' sources in binary32, and
+// with few targets (a shallow tree) those sums ran to thousands of terms,
+// whose rounding took single targets past 1e-6.
+static int default_depth(int64_t N, int64_t M, int kind, int dtype)
 {
     const double lg = 0.5 * std::log2((double)N * (double)M);
     const int r = (int)std::lround(lg);
     int off = kind == 0 ? (r < 14 ? 4 : (r < 18 ? 5 : 6)) : (r < 17 ? 4 : 5);
     if (const char *e = getenv("FN_LEAF_OFFSET"))
         off = atoi(e);
-    return std::min(24, std::max(2, r - off));
+    int l = std::min(24, std::max(2, r - off));
+    if (dtype == FN_C64)
+        while (l < 24 && (N >> l) > 128)
+            ++l;
+    return l;
 }
 
 static double eps_floor(int dtype) { return dtype == FN_C64 ? 1e-7 : 1e-15; }
@@ -1198,7 +1206,7 @@ static void choose(int64_t N, int64_t M, double eps, int kind, int dtype, int32_
         }
     }
     *l = l_in > 0 ? l_in
-                  : (tl > 0 ? tl : (kind < 0 ? paper_depth(N, M) : default_depth(N, M, kind)));
+                  : (tl > 0 ? tl : (kind < 0 ? paper_depth(N, M) : default_depth(N, M, kind, dtype)));
     int pp, qq;
     trunc_numbers(eps, *l, &pp, &qq);
     *p = p_in > 0 ? p_in : (tp > 0 ? tp : pp);
@@ -1787,7 +1795,7 @@ static int autotune(int kind, int64_t N, int64_t M, double eps, int dtype, int32
         std::lock_guard<std::mutex> lk(g_tune_mu); // measure without an old record
         g_tuned.erase(tune_key(kind, dtype, N, M, eps));
     }
-    const int l0 = default_depth(N, M, kind);
+    const int l0 = default_depth(N, M, kind, dtype);
     double secs = 0, err = 0;
     rc = tune_run(kind, N, M, (const double *)y.p, in.p, ref.p, eps, dtype, 64, l0, st, &secs);
     int pbest = 0;

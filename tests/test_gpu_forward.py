@@ -98,6 +98,27 @@ def test_fwd_mixed(N, M, dist):
     assert err < 1e-6
 
 
+@pytest.mark.parametrize("N,M,dist", [(15226, 8, "uniform"), (2596, 2, "clustered"),
+                                      (5162, 11, "uniform")])
+def test_fwd_mixed_few_targets(N, M, dist):
+    """Few targets and many sources: the cost model alone picks a shallow
+    tree, whose binary32 moments and near-field sums ran to thousands of
+    terms and took single targets past 1e-6.  The mixed path's default depth
+    keeps at most 128 sources per leaf; every seed meets the target."""
+    worst = 0.0
+    for seed in range(8):
+        y, f, c = workloads.forward_case(N, M, dist, seed=seed)
+        f32 = f.astype(np.complex64)
+        say(f"fwd mixed N={N} M={M} {dist} seed={seed}")
+        plan = fn.Plan.forward(N, dev(y), 1e-6, fn.FN_C64)
+        assert (N >> plan.info().lmax) <= 128
+        g = host(plan(dev(f32)))
+        plan.destroy()
+        worst = max(worst, rel_l2(g, oracle.fwd(N, y, f32.astype(np.complex128))))
+    say("worst rel l2", worst)
+    assert worst < 1e-6
+
+
 def test_plan_reuse():
     N, M = 5000, 6000
     y, f, c = workloads.forward_case(N, M, "uniform", seed=2)
