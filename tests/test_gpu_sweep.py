@@ -1,0 +1,101 @@
+"""Seeded randomized sweep of the HIP path against the oracle.
+
+Random sizes (log-uniform, ragged), point distributions, whole-period
+shifts of y, exact hits, explicit depths (binary64), and both precision
+paths, for the forward (Eq. p2), the inverse (Eq. p6, p8) and the batched
+forward.  Tolerances are the stated relative l2 targets: 1e-12 (binary64)
+and 1e-6 (mixed, against the oracle on the same binary32 input)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import dev, host, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+fn = pytest.importorskip("paper_1611_09379_amd")
+
+
+def log_uniform(rng, lo, hi):
+    return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_forward_sweep(seed):
+    rng = np.random.default_rng(seed)
+    for case in range(60):
+        N, M = log_uniform(rng, 1, 12000), log_uniform(rng, 1, 12000)
+        dist = "clustered" if rng.random() < 0.3 else "uniform"
+        y, f, c = workloads.forward_case(N, M, dist, seed=int(rng.integers(1 << 30)))
+        y = y + 2 * math.pi * int(rng.integers(-3, 4))
+        if rng.random() < 0.2:
+            y[: min(2, M)] = 0.0  # exact hits
+        mixed = rng.random() < 0.4
+        lmax = 0
+        if not mixed and rng.random() < 0.25:
+            lmax = int(rng.integers(2, max(3, int(math.log2(max(N, M))) + 1)))
+        say(f"case {case}: N={N} M={M} {dist} mixed={mixed} lmax={lmax}")
+        if mixed:
+            f = f.astype(np.complex64)
+            plan = fn.Plan.forward(N, dev(y), 1e-6, fn.FN_C64)
+        else:
+            plan = fn.Plan.forward(N, dev(y), 1e-12, fn.FN_C128, lmax=lmax)
+        g = host(plan(dev(f)))
+        plan.destroy()
+        err = rel_l2(g, oracle.fwd(N, y, f.astype(np.complex128)))
+        assert err < (1e-6 if mixed else 1e-12), (case, N, M, dist, mixed, lmax, err)
+
+
+@pytest.mark.parametrize("seed", [21])
+def test_inverse_sweep(seed):
+    rng = np.random.default_rng(seed)
+    for case in range(50):
+        N = log_uniform(rng, 2, 6000)
+        amp = float(rng.uniform(0.05, 0.45))
+        y, c = workloads.inverse_case(N, amp, seed=int(rng.integers(1 << 30)))
+        if rng.random() < 0.3:
+            y[int(rng.integers(N))] = 0.0 if N > 1 else y[0]  # an exact hit
+        g = workloads.samples_from_coefficients(c)
+        mixed = rng.random() < 0.4
+        say(f"case {case}: N={N} amp={amp:.3f} mixed={mixed}")
+        if mixed:
+            g = g.astype(np.complex64)
+            f = host(fn.inufft(dev(y), dev(g), 1e-6))
+        else:
+            f = host(fn.inufft(dev(y), dev(g), 1e-12))
+        try:
+            ref = oracle.inv(N, y, g.astype(np.complex128))
+        except oracle.OracleError:
+            continue  # the hit coincided with another point: singular, not a case
+        err = rel_l2(f, ref)
+        assert err < (1e-6 if mixed else 1e-12), (case, N, amp, mixed, err)
+
+
+@pytest.mark.parametrize("seed", [31])
+def test_batched_sweep(seed):
+    rng = np.random.default_rng(seed)
+    for case in range(12):
+        T = int(rng.integers(1, 40))
+        mixed = bool(rng.random() < 0.5)
+        eps, dt, cdt = (1e-6, fn.FN_C64, np.complex64) if mixed else (1e-12, fn.FN_C128, np.complex128)
+        Ns = [log_uniform(rng, 1, 5000) for _ in range(T)]
+        Ms = [log_uniform(rng, 1, 5000) for _ in range(T)]
+        ys, fs, refs = [], [], []
+        for t in range(T):
+            y, f, c = workloads.forward_case(Ns[t], Ms[t], "uniform", seed=int(rng.integers(1 << 30)))
+            f = f.astype(cdt)
+            ys.append(dev(y))
+            fs.append(dev(f))
+            refs.append(oracle.fwd(Ns[t], y, f.astype(np.complex128)))
+        say(f"case {case}: T={T} mixed={mixed}")
+        if case % 2:
+            outs = fn.nufft_fwd_batched(ys, fs, eps)
+        else:
+            b = fn.Batch.forward(ys, Ns, eps, dt)
+            outs = b.execute(fs)
+            b.destroy()
+        err = max(rel_l2(host(o), r) for o, r in zip(outs, refs))
+        assert err < (1e-6 if mixed else 1e-12), (case, T, mixed, err)
