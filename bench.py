@@ -35,23 +35,23 @@ PEAK_HBM = 8.0e12        # B/s
 # turns the figure back into null until the counters are taken again.
 TRAFFIC = {
     "k_down_trans<double,cot,uniform sources,forward>": {
-        "src_sha256": "2f00f1f05ac56f486de7c5131824b452cbb568e99bf3ec04a8d26fa2d83f07f9",
-        "fetch": 33609525, "write": 8388456, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "a6fbfec11cfe4885a3dd562babf32f12df41cee96d86e4eea29ad8db21ec63b5",
+        "fetch": 33608378, "write": 8388472, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_eval<double,cot,uniform sources,forward>": {
-        "src_sha256": "2f00f1f05ac56f486de7c5131824b452cbb568e99bf3ec04a8d26fa2d83f07f9",
-        "fetch": 44497914, "write": 34098011, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "a6fbfec11cfe4885a3dd562babf32f12df41cee96d86e4eea29ad8db21ec63b5",
+        "fetch": 44498342, "write": 34096903, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_trans<double,cot,sorted sources,inverse>": {
-        "src_sha256": "2f00f1f05ac56f486de7c5131824b452cbb568e99bf3ec04a8d26fa2d83f07f9",
-        "fetch": 66979275, "write": 16776912, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "a6fbfec11cfe4885a3dd562babf32f12df41cee96d86e4eea29ad8db21ec63b5",
+        "fetch": 66980721, "write": 16776944, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_eval<double,cot,sorted sources,inverse>": {
-        "src_sha256": "2f00f1f05ac56f486de7c5131824b452cbb568e99bf3ec04a8d26fa2d83f07f9",
-        "fetch": 64053957, "write": 16776912, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "a6fbfec11cfe4885a3dd562babf32f12df41cee96d86e4eea29ad8db21ec63b5",
+        "fetch": 64053810, "write": 16776944, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_trans<double,log,sorted sources,log-sums>": {
-        "src_sha256": "2f00f1f05ac56f486de7c5131824b452cbb568e99bf3ec04a8d26fa2d83f07f9",
-        "fetch": 33859511, "write": 8388456, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "a6fbfec11cfe4885a3dd562babf32f12df41cee96d86e4eea29ad8db21ec63b5",
+        "fetch": 33860021, "write": 8388472, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_eval<double,log,sorted sources,log-sums>": {
-        "src_sha256": "2f00f1f05ac56f486de7c5131824b452cbb568e99bf3ec04a8d26fa2d83f07f9",
-        "fetch": 32921029, "write": 25199145, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "a6fbfec11cfe4885a3dd562babf32f12df41cee96d86e4eea29ad8db21ec63b5",
+        "fetch": 32914809, "write": 25199199, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
 }
 PHASES = ("fwd_plan_ms", "fwd_up_ms", "fwd_trans_ms", "fwd_eval_ms", "inv_plan_ms",
           "inv_up_ms", "inv_trans_ms", "inv_eval_ms", "log_up_ms", "log_trans_ms",
