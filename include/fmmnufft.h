@@ -37,6 +37,11 @@
  *     status nufft_last_error() returns a message (thread-local, valid until
  *     the next call on the same thread).  Scalar argument errors are
  *     reported before any GPU work is enqueued.
+ *   - Host threads: calls from several threads may overlap (the library's
+ *     shared state -- workspace pool, operator tables, autotune records --
+ *     is locked).  A plan or batch holds one workspace: its executes must
+ *     not overlap in time, whether from two threads or on two streams that
+ *     do not wait for each other.
  */
 #ifndef FMMNUFFT_H
 #define FMMNUFFT_H
