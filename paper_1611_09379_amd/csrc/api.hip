@@ -510,14 +510,19 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_
     F.RSu = row_stride(NC, PU, es);
     F.RSd = row_stride(NC, PD, es);
     const size_t lim = lds_limit();
-    // bands of the upward pass: the leaves' band (at most 4 levels), then
-    // bands of at most 5 levels down to level 2 (the last one has 4
-    // workgroups, one per quarter)
+    // bands of the upward pass: the leaves' band, then bands of at most 5
+    // levels down to level 2 (the last one has 4 workgroups, one per
+    // quarter).  The leaves' band spans 5 levels, except for the cot
+    // kernel's sorted sources (the inverse), whose staged coordinates,
+    // powers and complex weights for 32 leaves would cost occupancy: 4
+    // there (measured at 2^20: 5 levels take 3 us off the forward's pass
+    // and 7 us off the log-sums', and add 2 us to the inverse's)
+    const int d_first = (kernel == KER_COT && sorted_src) ? 4 : 5;
     F.nbands = 0;
     int lb = P->l;
     bool first = true;
     do {
-        const int d = std::min(first ? 4 : 5, lb - 2);
+        const int d = std::min(first ? d_first : 5, lb - 2);
         F.band[F.nbands++] = {lb, d, first ? 1 : 0, 1 << (lb - d),
                               (size_t)(1 << d) * F.RSu * es};
         lb -= d;
