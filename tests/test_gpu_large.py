@@ -54,3 +54,48 @@ def test_inv_2p22_round_trip(dtype, eps):
     err = rel_l2(f2, f)
     say("round trip rel l2", err)
     assert err < 10 * eps
+
+
+@pytest.mark.parametrize("dtype,eps", [(np.complex128, 1e-12), (np.complex64, 1e-6)])
+def test_fwd_prime_sizes_sampled(dtype, eps):
+    """N and M prime near 2^20: leaves of unequal grid counts (the vector
+    P2M in place of the matrix-core one, ragged leaf boundaries) at full
+    scale, on sampled targets."""
+    N, M = 1000003, 999983
+    y, f, c = workloads.forward_case(N, M, "uniform", seed=3)
+    fq = f.astype(dtype)
+    say(f"fwd N={N} M={M} {np.dtype(dtype).name} eps={eps}")
+    g = host(fn.nufft_fwd(dev(y), dev(fq), eps))
+    sel = np.random.default_rng(7).choice(M, 256, replace=False)
+    err = rel_l2(g[sel], oracle.fwd_at(N, y, fq.astype(np.complex128), sel))
+    say("sampled rel l2", err)
+    assert err < eps
+
+
+@pytest.mark.parametrize("dtype,eps", [(np.complex128, 1e-12), (np.complex64, 1e-6)])
+def test_inv_prime_size_round_trip(dtype, eps):
+    """The inverse at N = 1000003 (prime) on a jittered grid: its coefficients
+    Chat_k, Dhat_j against the oracle's direct log-sums at sampled indices,
+    and the round trip forward then inverse."""
+    N = 1000003
+    y, c = workloads.inverse_case(N, 0.4, seed=4)
+    f = workloads.samples_from_coefficients(c).astype(dtype)
+    yd, fd = dev(y), dev(f)
+    say(f"inverse N={N} {np.dtype(dtype).name}")
+    plan = fn.Plan.inverse(yd, eps, fn.FN_C128 if dtype == np.complex128 else fn.FN_C64)
+    chat, dhat = plan.coeffs()
+    rng = np.random.default_rng(8)
+    ks = rng.choice(N, 64, replace=False)
+    js = rng.choice(N, 64, replace=False)
+    rc, rd = oracle.coeffs_at(N, y, ks, js)
+    ec = rel_l2(host(chat)[ks], rc)
+    ed = rel_l2(host(dhat)[js], rd)
+    plan.destroy()
+    say("coefficients rel l2", ec, ed)
+    tol = 1e-12 if dtype == np.complex128 else 1e-6
+    assert ec < tol and ed < tol
+    g = fn.nufft_fwd(yd, fd, eps)
+    f2 = host(fn.inufft(yd, g, eps))
+    err = rel_l2(f2, f)
+    say("round trip rel l2", err)
+    assert err < 10 * eps
