@@ -512,12 +512,15 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_
     const size_t lim = lds_limit();
     // bands of the upward pass: the leaves' band, then bands of at most 5
     // levels down to level 2 (the last one has 4 workgroups, one per
-    // quarter).  The leaves' band spans 5 levels, except for the cot
-    // kernel's sorted sources (the inverse), whose staged coordinates,
-    // powers and complex weights for 32 leaves would cost occupancy: 4
-    // there (measured at 2^20: 5 levels take 3 us off the forward's pass
-    // and 7 us off the log-sums', and add 2 us to the inverse's)
-    const int d_first = (kernel == KER_COT && sorted_src) ? 4 : 5;
+    // quarter).  The leaves' band spans 5 levels, except where the cot
+    // kernel stages coordinates, powers and complex weights (sorted sources,
+    // and a uniform grid with unequal leaves), which for 32 leaves would
+    // cost occupancy: 4 there (measured at 2^20: 5 levels take 3 us off the
+    // forward's pass and 7 us off the log-sums', and add 2 us to the
+    // inverse's)
+    // a uniform grid with unequal leaves is staged like sorted sources
+    const bool uni_staged = !sorted_src && kernel == KER_COT && uniform_leaf_pts(P) == 0;
+    const int d_first = (kernel == KER_COT && (sorted_src || uni_staged)) ? 4 : 5;
     F.nbands = 0;
     int lb = P->l;
     bool first = true;
@@ -532,23 +535,24 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_
     // the level above it, which in the first band holds the staged sources
     // until the P2M is done (uniform grid with an equal number B in every
     // leaf: the weights; sorted sources: coordinates and weights of up to
-    // 1.25 times the mean count plus 64, else they are read in place)
+    // 1.25 times the mean count plus 64; a uniform grid with unequal
+    // leaves: coordinates and weights of its at most ceil(N / 2^l) points
+    // per leaf; else they are read in place)
     for (int b = 0; b < F.nbands; ++b) {
         const int nbot = 1 << F.band[b].d;
         size_t bytes = (size_t)std::max(nbot / 2, 1) * F.RSu * es;
-        if (b == 0 && !sorted_src) {
-            if (kernel == KER_COT && uniform_leaf_pts(P) > 0)
-                bytes = std::max(bytes, (size_t)nbot *
-                                            uni_stage_stride(uniform_leaf_pts(P), es) * es);
-        } else if (b == 0) {
+        if (b == 0 && !sorted_src && kernel == KER_COT && uniform_leaf_pts(P) > 0) {
+            bytes = std::max(bytes, (size_t)nbot *
+                                        uni_stage_stride(uniform_leaf_pts(P), es) * es);
+        } else if (b == 0 && (sorted_src || uni_staged)) {
             const int64_t mean = (P->N + (int64_t(1) << P->l) - 1) >> P->l;
             // coordinate, its fourth power, and (cot) the complex weight
             const size_t per = es * (kernel == KER_COT ? 4 : 2);
             const size_t room = lim > F.band[0].smem + 4 * (size_t)(nbot + 1) + 64
                                     ? lim - F.band[0].smem - 4 * (size_t)(nbot + 1) - 64
                                     : 0;
-            int64_t cap = std::min<int64_t>(nbot * mean + nbot * mean / 4 + 64,
-                                            (int64_t)(room / per) - 4);
+            const int64_t want = sorted_src ? nbot * mean + nbot * mean / 4 + 64 : nbot * mean + 4;
+            int64_t cap = std::min<int64_t>(want, (int64_t)(room / per) - 4);
             cap = std::min<int64_t>(cap, 4096) & ~int64_t(3);
             F.stage_cap = cap >= 64 ? (int)cap : 0;
             // the sources (cap rounded up to 4), then the nbot + 1 leaf offsets

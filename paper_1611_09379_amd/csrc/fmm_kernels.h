@@ -215,11 +215,24 @@ __global__ void k_weights(int64_t n, const cx<double> *dhat, const int32_t *perm
 
 constexpr int CHS = 4; // moments per thread in the vector P2M
 
+// Leaf of the uniform point k: floor(k 2^l / N), from a binary64 estimate
+// (off by at most one) corrected with exact integer box starts.
+__device__ __forceinline__ int64_t uni_leaf(int64_t k, int l, int64_t N, double scale)
+{
+    int64_t b = (int64_t)((double)k * scale);
+    if (uni_start(b + 1, l, N) <= k)
+        ++b;
+    else if (uni_start(b, l, N) > k)
+        --b;
+    return b;
+}
+
+
 // P2M at leaf b for CHS consecutive moments m0..: a_m = sum w v^m with
 // v = (sigma - c)/r.  The log kernel takes unit weights minus the uniform
 // density of one point per grid unit (moments 2r/(m+1) for even m).
 template <typename R, typename V, int KER, int SRC>
-__device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, int64_t b,
+__device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, const cx<R> *fu, int64_t b,
                                           int m0, V *acc)
 {
     const int l = a.l;
@@ -233,7 +246,7 @@ __device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, int64_t b,
             R pw = ipow(v, m0);
             V w;
             if constexpr (KER == KER_COT)
-                w = a.f_uniform[k];
+                w = fu[k];
             else
                 w = R(1);
             for (int c = 0; c < CHS; ++c) {
@@ -448,8 +461,9 @@ __device__ __forceinline__ void m2m_level(const R (&am)[PU / 4], int rt,
 
 // One launch of the upward pass: 2^d boxes of level lb (the leaves, by P2M,
 // in the first band) up to level lb - d.
+// fu: the uniform sources' weights (the forward's input).
 template <typename R, typename V, int KER, int SRC, int PU>
-__device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk)
+__device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk, const cx<R> *fu)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     R *buf0 = reinterpret_cast<R *>(smem_raw);
@@ -469,7 +483,7 @@ __device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk)
             if (a.leaf_pts > 0) {
                 const int bn = a.leaf_pts * 2, SB = uni_stage_stride(a.leaf_pts, sizeof(R));
                 const int nf = nbot * bn;
-                const R *f = reinterpret_cast<const R *>(a.f_uniform) + first * bn;
+                const R *f = reinterpret_cast<const R *>(fu) + first * bn;
                 // every load of a batch in flight at once (indices clamped)
                 for (int i0 = 0; i0 < nf; i0 += 8 * BLOCK) {
                     R v[8];
@@ -547,12 +561,66 @@ __device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk)
                 done = true;
             }
         }
+        if constexpr (SRC == SET_UNIFORM && KER == KER_COT) {
+            // a grid whose leaves hold unequal numbers of points (N not a
+            // multiple of the leaf count): the band's points staged with
+            // their coordinates, as sorted sources are
+            const int64_t K0 = uni_start(first, a.l, a.N);
+            const int64_t K1 = uni_start(first + nbot, a.l, a.N);
+            if (!done && a.stage_cap > 0 && K1 - K0 <= a.stage_cap) {
+                const int cnt = (int)(K1 - K0);
+                const int cap4 = (a.stage_cap + 3) & ~3;
+                R *sv = stage;
+                cx<R> *sw = reinterpret_cast<cx<R> *>(stage + cap4);
+                R *sv4 = stage + 3 * cap4;
+                int32_t *soff = reinterpret_cast<int32_t *>(sv4 + cap4);
+                const double invN = 1.0 / (double)a.N;
+                const double lscale = ldexp(1.0, a.l) * invN;
+                if (tid <= nbot)
+                    soff[tid] = (int32_t)(uni_start(first + tid, a.l, a.N) - K0);
+                // a point's coordinate and weight into the staging area
+                const auto put = [&](int i, cx<R> w) {
+                    const int64_t k = K0 + i;
+                    const int64_t leaf = uni_leaf(k, a.l, a.N, lscale);
+                    const R v = (R)rel_coord_r(k, 0.0, leaf, a.l, a.N, invN);
+                    const R v2 = v * v;
+                    sv[i] = v;
+                    sv4[i] = v2 * v2;
+                    sw[i] = w;
+                };
+                // two loads in flight at once (indices clamped); named
+                // values, not an array (which the batched kernel kept in
+                // scratch memory)
+                for (int i0 = 0; i0 < cnt; i0 += 2 * BLOCK) {
+                    const int ia = i0 + tid, ib = ia + BLOCK;
+                    const cx<R> wa = fu[K0 + (ia < cnt ? ia : cnt - 1)];
+                    const cx<R> wb = fu[K0 + (ib < cnt ? ib : cnt - 1)];
+                    if (ia < cnt)
+                        put(ia, wa);
+                    if (ib < cnt)
+                        put(ib, wb);
+                }
+                __syncthreads();
+                const double r = ldexp((double)a.N, -(a.l + 1));
+                constexpr int nch = PU / CHS;
+                for (int idx = tid; idx < nbot * nch; idx += BLOCK) {
+                    const int i = idx / nch, ch = idx - i * nch;
+                    V acc[CHS];
+                    p2m_staged<R, V, KER>(sv, sv4, sw, soff[i], soff[i + 1], ch * CHS, r, acc);
+                    for (int c = 0; c < CHS; ++c) {
+                        st_coef<R, V>(buf0, RS, i, ch * CHS + c, acc[c]);
+                        g[(first + i) * PU + ch * CHS + c] = acc[c];
+                    }
+                }
+                done = true;
+            }
+        }
         if (!done) {
             constexpr int nch = PU / CHS;
             for (int idx = tid; idx < nbot * nch; idx += BLOCK) {
                 const int i = idx / nch, ch = idx - i * nch;
                 V acc[CHS];
-                p2m_chunk<R, V, KER, SRC>(a, first + i, ch * CHS, acc);
+                p2m_chunk<R, V, KER, SRC>(a, fu, first + i, ch * CHS, acc);
                 for (int c = 0; c < CHS; ++c) {
                     st_coef<R, V>(buf0, RS, i, ch * CHS + c, acc[c]);
                     g[(first + i) * PU + ch * CHS + c] = acc[c];
@@ -592,7 +660,7 @@ __device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk)
 template <typename R, typename V, int KER, int SRC, int PU>
 __global__ void __launch_bounds__(BLOCK) k_up_band(UpArgs<R, V> a)
 {
-    up_band_body<R, V, KER, SRC, PU>(a, blockIdx.x);
+    up_band_body<R, V, KER, SRC, PU>(a, blockIdx.x, a.f_uniform);
 }
 
 // The same band of every problem of a batch in one launch.
@@ -603,10 +671,10 @@ __global__ void __launch_bounds__(BLOCK) kb_up_band(const UpArgs<R, V> *aa, Bloc
 {
     int blk, nblk;
     const int t = bm_find(bm, blockIdx.x, &blk, &nblk);
-    UpArgs<R, V> a = aa[t];
-    if (io)
-        a.f_uniform = reinterpret_cast<const cx<R> *>(io[a.io_index].in);
-    up_band_body<R, V, KER, SRC, PU>(a, blk);
+    // the arguments read in place (a copy took scratch memory)
+    const UpArgs<R, V> &a = aa[t];
+    const cx<R> *fu = io ? reinterpret_cast<const cx<R> *>(io[a.io_index].in) : a.f_uniform;
+    up_band_body<R, V, KER, SRC, PU>(a, blk, fu);
 }
 
 // Level 2 (one workgroup): the regular part of Eq. (p20) as the level-2
@@ -1021,18 +1089,6 @@ __device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
         }
     }
     return acc;
-}
-
-// Leaf of the uniform point k: floor(k 2^l / N), from a binary64 estimate
-// (off by at most one) corrected with exact integer box starts.
-__device__ __forceinline__ int64_t uni_leaf(int64_t k, int l, int64_t N, double scale)
-{
-    int64_t b = (int64_t)((double)k * scale);
-    if (uni_start(b + 1, l, N) <= k)
-        ++b;
-    else if (uni_start(b, l, N) > k)
-        --b;
-    return b;
 }
 
 // Sorted sources of a subtree staged in LDS: the leaves leaf0 - 1 ..
