@@ -35,23 +35,23 @@ PEAK_HBM = 8.0e12        # B/s
 # turns the figure back into null until the counters are taken again.
 TRAFFIC = {
     "k_down_trans<double,cot,uniform sources,forward>": {
-        "src_sha256": "18d576d99bf8fb7fb271422385ce776996df294b74887fdbd1c77456678b835b",
-        "fetch": 33609562, "write": 8388552, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "813c8cdda1b43705f052e8d12d159b483bae82577d2b0f8752f7dc988c2d4398",
+        "fetch": 33628461, "write": 8388600, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_eval<double,cot,uniform sources,forward>": {
-        "src_sha256": "18d576d99bf8fb7fb271422385ce776996df294b74887fdbd1c77456678b835b",
-        "fetch": 44497564, "write": 34096138, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "813c8cdda1b43705f052e8d12d159b483bae82577d2b0f8752f7dc988c2d4398",
+        "fetch": 44498491, "write": 34097133, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_trans<double,cot,sorted sources,inverse>": {
-        "src_sha256": "18d576d99bf8fb7fb271422385ce776996df294b74887fdbd1c77456678b835b",
-        "fetch": 66980215, "write": 16777104, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "813c8cdda1b43705f052e8d12d159b483bae82577d2b0f8752f7dc988c2d4398",
+        "fetch": 66970646, "write": 16777200, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_eval<double,cot,sorted sources,inverse>": {
-        "src_sha256": "18d576d99bf8fb7fb271422385ce776996df294b74887fdbd1c77456678b835b",
-        "fetch": 64053633, "write": 16777104, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "813c8cdda1b43705f052e8d12d159b483bae82577d2b0f8752f7dc988c2d4398",
+        "fetch": 64063607, "write": 16777200, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_trans<double,log,sorted sources,log-sums>": {
-        "src_sha256": "18d576d99bf8fb7fb271422385ce776996df294b74887fdbd1c77456678b835b",
-        "fetch": 33864692, "write": 8388552, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "813c8cdda1b43705f052e8d12d159b483bae82577d2b0f8752f7dc988c2d4398",
+        "fetch": 33863829, "write": 8388600, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
     "k_down_eval<double,log,sorted sources,log-sums>": {
-        "src_sha256": "18d576d99bf8fb7fb271422385ce776996df294b74887fdbd1c77456678b835b",
-        "fetch": 32915129, "write": 25199456, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
+        "src_sha256": "813c8cdda1b43705f052e8d12d159b483bae82577d2b0f8752f7dc988c2d4398",
+        "fetch": 32920440, "write": 25199584, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
 }
 PHASES = ("fwd_plan_ms", "fwd_up_ms", "fwd_trans_ms", "fwd_eval_ms", "inv_plan_ms",
           "inv_up_ms", "inv_trans_ms", "inv_eval_ms", "log_up_ms", "log_trans_ms",
