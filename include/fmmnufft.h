@@ -176,7 +176,11 @@ int nufft_select_params(int64_t N, int64_t M, double eps, int dtype,
                         int32_t *p, int32_t *q, int32_t *lmax);
 
 /* Like nufft_plan_fwd / nufft_plan_inv with p, q and lmax given explicitly
- * (values <= 0 mean "the plan's default").  For tuning and tests. */
+ * (values <= 0 mean "the plan's default").  For tuning and tests.  Explicit
+ * values are used as given: eps then sets only what is not given, and the
+ * result need not meet it (on the FN_C64 path, a depth that leaves more
+ * than about 128 sources per leaf sums them in binary32 and can miss 1e-6;
+ * the default depth never does). */
 int nufft_plan_fwd_ex(fn_plan **plan, int64_t N, int64_t M, const double *y,
                       double eps, int dtype, int32_t p, int32_t q,
                       int32_t lmax, void *stream);
