@@ -236,3 +236,37 @@ def test_logsums_large_n_mpmath():
             ref = -mpmath.fsum(mpmath.log(abs(2 * mpmath.sin((yj - v) / 2)))
                                for i, v in enumerate(ym) if i != int(j))
             assert abs(float(ref) - logD[t]) < 2e-13, (j, float(ref) - logD[t])
+
+
+@pytest.mark.parametrize("N", [1, 7, 1000, 4096])
+def test_fwd_at_selects_fwd(N):
+    """fwd_at(N, y, f, sel) is fwd(N, y, f)[sel] bit for bit (Eq. p2 through
+    p4): the selection keeps duplicates and order, and exact hits (y = 0,
+    y = 2 pi, y = -2 pi) go through the same per-target sum."""
+    rng = np.random.default_rng(31 + N)
+    M = 300
+    y = workloads.points_uniform(M, rng)
+    y[:3] = [0.0, 2 * np.pi, -2 * np.pi]
+    y[3] = 2 * np.pi * (N // 2) / N
+    f = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    g = oracle.fwd(N, y, f)
+    sel = np.concatenate([[M - 1, 0, 5, 5, 1, 2, 3, 0], rng.permutation(M)[:50],
+                          rng.integers(0, M, 20)])
+    gs = oracle.fwd_at(N, y, f, sel)
+    assert gs.shape == sel.shape
+    assert np.array_equal(gs.view(np.float64), g[sel].view(np.float64))
+    assert np.array_equal(oracle.fwd_at(N, y, f, sel[:0]), g[:0])
+
+
+@pytest.mark.parametrize("N", [5, 13])
+def test_fwd_at_brute_force_eq_p2(N):
+    """fwd_at against Eq. (p2) summed literally over n in 40 digits, at
+    targets picked out of order."""
+    rng = np.random.default_rng(200 + N)
+    f = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    y = np.concatenate([rng.random(5) * 2 * np.pi, [0.0, 2 * np.pi * 3 / N]])
+    sel = np.array([4, 6, 0, 5, 2, 2])
+    g = oracle.fwd_at(N, y, f, sel)
+    for i, j in enumerate(sel):
+        ref = sum(mp_K(N, y[j], k) * mpmath.mpc(f[k]) for k in range(N))
+        assert abs(complex(ref) - g[i]) <= 1e-14 * (1 + abs(complex(ref)))
