@@ -10,6 +10,7 @@ Functions (all arrays numpy; complex arrays are complex128):
   grid_units(N, y)            -> (m, theta): N y / 2 pi = m + theta, exact reduction
   fwd(N, y, f)                -> g, Eq. (p2) via its closed form (p4)-(p5)
   fwd_at(N, y, f, sel)        -> g[sel]
+  adj(N, y, g, ks=None)       -> f_k = sum_j conj(K_jk) g_j (adjoint of Eq. p2), at ks
   fwd_spectral(N, y, f)       -> g, Eq. (p1): c = DFT(f)/N, g_j = sum_n c_n e^{i n y_j}
   eval_series(N, y, c)        -> g, Eq. (p1) from given coefficients
   logsums(N, y, ks, js)       -> (logC, negC, logD, negD) behind Eq. (p8)
@@ -46,6 +47,7 @@ def _load():
     lib.or_grid_units.argtypes = [i64, i64, vp, vp, vp]
     lib.or_fwd_kernel.argtypes = [i64, i64, vp, vp, vp, ctypes.c_int]
     lib.or_fwd_kernel_at.argtypes = [i64, i64, vp, vp, i64, vp, vp, ctypes.c_int]
+    lib.or_adj_at.argtypes = [i64, i64, vp, vp, i64, vp, vp, ctypes.c_int]
     lib.or_eval_series.argtypes = [i64, i64, vp, vp, vp, ctypes.c_int]
     lib.or_logsums_at.argtypes = [i64, vp, i64, vp, vp, vp, i64, vp, vp, vp,
                                   ctypes.c_int]
@@ -108,6 +110,19 @@ def fwd_at(N: int, y, f, sel):
     _load().or_fwd_kernel_at(N, y.shape[0], _ptr(y), _ptr(f), sel.shape[0],
                              _ptr(sel), _ptr(g), _threads())
     return g
+
+
+def adj(N: int, y, g, ks=None):
+    """f_k = sum_j conj(K_jk) g_j (the adjoint of Eq. p2, K in its closed
+    form p4-p5) for k in ks (default: k = 0..N-1)."""
+    y, g = _f64(y), _c128(g)
+    assert g.shape[0] == y.shape[0]
+    ks_a = None if ks is None else np.ascontiguousarray(ks, dtype=np.int64)
+    nk = N if ks_a is None else ks_a.shape[0]
+    f = np.empty(nk, dtype=np.complex128)
+    _load().or_adj_at(N, y.shape[0], _ptr(y), _ptr(g), nk,
+                      None if ks_a is None else _ptr(ks_a), _ptr(f), _threads())
+    return f
 
 
 def eval_series(N: int, y, c):

@@ -180,6 +180,61 @@ void or_fwd_kernel_at(int64_t N, int64_t M, const double *y, const double *f,
     }
 }
 
+/* Adjoint of Eq. (p2): f_k = sum_j conj(K_jk) g_j at the grid points
+ * k = ks[i] (all k = 0..N-1 when ks is NULL; nk outputs), with K_jk in
+ * its closed form (p4)-(p5), K_jk = F_j G(y_j - x_k): the conjugate of the
+ * same product fwd_one forms, term by term over j.  A point on the grid
+ * (theta_j == 0, y_j = x_{m_j}) has K_jk = delta(k, m_j). */
+void or_adj_at(int64_t N, int64_t M, const double *y, const double *g, int64_t nk,
+               const int64_t *ks, double *f, int nthreads)
+{
+    int64_t *m = malloc(sizeof(int64_t) * (size_t)(M ? M : 1));
+    double *th = malloc(sizeof(double) * (size_t)(M ? M : 1));
+    double *F = malloc(sizeof(double) * 2 * (size_t)(M ? M : 1));
+    or_grid_units(N, M, y, m, th);
+    const double dN = (double)N;
+    for (int64_t j = 0; j < M; ++j) {
+        double sp, cp;
+        sincos(M_PI * th[j], &sp, &cp);
+        F[2 * j] = -2.0 * sp * sp / dN;   /* F_j = 2i sin(pi th) e^{i pi th} / N */
+        F[2 * j + 1] = 2.0 * sp * cp / dN;
+    }
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < nk; ++i) {
+        const int64_t k = ks ? ks[i] : i;
+        nsum ar = {0, 0}, ai = {0, 0};
+        for (int64_t j = 0; j < M; ++j) {
+            const double gr = g[2 * j], gi = g[2 * j + 1];
+            if (th[j] == 0.0) {
+                if (m[j] == k) {
+                    nsum_add(&ar, gr);
+                    nsum_add(&ai, gi);
+                }
+                continue;
+            }
+            /* G(y_j - x_k) = -(1 + i cot(pi d / N)) / 2, d = (m_j - k) + th_j */
+            const double d = (double)wrap_half(m[j] - k, N) + th[j];
+            double sn, cs;
+            sincos(M_PI * (d / dN), &sn, &cs);
+            const double ct = cs / sn;
+            const double Gr = -0.5, Gi = -0.5 * ct;
+            const double Kr = F[2 * j] * Gr - F[2 * j + 1] * Gi;
+            const double Ki = F[2 * j] * Gi + F[2 * j + 1] * Gr;
+            /* conj(K) g */
+            nsum_add(&ar, Kr * gr);
+            nsum_add(&ar, Ki * gi);
+            nsum_add(&ai, Kr * gi);
+            nsum_add(&ai, -Ki * gr);
+        }
+        f[2 * i] = nsum_get(&ar);
+        f[2 * i + 1] = nsum_get(&ai);
+    }
+    free(m);
+    free(th);
+    free(F);
+}
+
 /* Eq. (p1): g_j = f(y_j) = sum_{n=0}^{N-1} c_n e^{i n y_j}, the band-limited
  * interpolant evaluated term by term.  e^{i n y_j} = e^{2 pi i n s_j / N} is
  * split into the exact root of unity e^{2 pi i ((n m_j) mod N) / N} (table

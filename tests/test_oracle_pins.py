@@ -270,3 +270,46 @@ def test_fwd_at_brute_force_eq_p2(N):
     for i, j in enumerate(sel):
         ref = sum(mp_K(N, y[j], k) * mpmath.mpc(f[k]) for k in range(N))
         assert abs(complex(ref) - g[i]) <= 1e-14 * (1 + abs(complex(ref)))
+
+
+@pytest.mark.parametrize("N,M", [(64, 100), (127, 50), (256, 256)])
+def test_adj_matches_dense_conjugate_transpose(N, M):
+    """adj is K^H g with K of Eq. (p2) as an explicit matrix (numpy sum over
+    n), including points on the grid and repeated points."""
+    rng = np.random.default_rng(N + M)
+    y = workloads.points_uniform(M, rng)
+    y[:4] = [0.0, 2 * np.pi * 5 / N, y[10], 0.0]     # hits, repeats
+    g = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    f = oracle.adj(N, y, g)
+    ref = dense_K(N, y).conj().T @ g
+    assert np.linalg.norm(f - ref) / np.linalg.norm(ref) < 1e-12
+
+
+@pytest.mark.parametrize("N,M,dist", [(1000, 1500, "uniform"), (1024, 700, "clustered"),
+                                      (4097, 4097, "uniform")])
+def test_adj_inner_product_identity(N, M, dist):
+    """<K f, g> = <f, K^H g> with the oracle's forward sum (Eq. p2-p5): a
+    dropped conjugate, a sign of the cot term or a swapped index fails it."""
+    y, f, c = workloads.forward_case(N, M, dist, seed=11)
+    rng = np.random.default_rng(12)
+    g = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    lhs = np.vdot(g, oracle.fwd(N, y, f))
+    rhs = np.vdot(oracle.adj(N, y, g), f)
+    assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(f) * np.linalg.norm(g) * np.sqrt(N)
+
+
+@pytest.mark.parametrize("N", [1, 3, 8, 13])
+def test_adj_brute_force_eq_p2(N):
+    """f_k = sum_j conj(K_jk) g_j with K_jk of Eq. (p2) summed literally over
+    n in 40 digits; points on the grid and a repeated point included, and a
+    selection of k out of order."""
+    rng = np.random.default_rng(300 + N)
+    y = np.concatenate([rng.random(5) * 2 * np.pi, [0.0, 2 * np.pi * (N - 1) / N, 0.0]])
+    M = y.size
+    g = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    ks = np.array([N - 1, 0, N // 2, 0])
+    f = oracle.adj(N, y, g, ks)
+    for i, k in enumerate(ks):
+        ref = sum(mpmath.conj(mp_K(N, y[j], int(k))) * mpmath.mpc(g[j]) for j in range(M))
+        assert abs(complex(ref) - f[i]) <= 1e-14 * (1 + abs(complex(ref)))
+    assert np.array_equal(oracle.adj(N, y, g)[ks], f)
