@@ -90,7 +90,13 @@ int or_max_threads(int nthreads)
 
 /* s_j = N y_j / (2 pi) in binary128; m_j = nearest integer mod N,
  * theta_j = s_j - nearest integer (binary64).  Problem statement of
- * Section 2: x_k = 2 pi k / N, y_j arbitrary. */
+ * Section 2: x_k = 2 pi k / N, y_j arbitrary.
+ *
+ * |theta_j| < 1e-200 is returned as 0, an exact hit.  The kernel of
+ * Eq. (p2) is smooth in y (every entry moves by at most 2 pi |theta_j|, far
+ * below the rounding of any binary64 result), while its closed form (p4)
+ * divides a vanishing F_j by a vanishing sine there, which underflows to
+ * 0/0 for subnormal theta_j. */
 void or_grid_units(int64_t N, int64_t M, const double *y, int64_t *m,
                    double *theta)
 {
@@ -99,6 +105,8 @@ void or_grid_units(int64_t N, int64_t M, const double *y, int64_t *m,
         __float128 s = (__float128)y[j] * scale;
         __float128 n = floorq(s + 0.5Q);
         theta[j] = (double)(s - n);
+        if (fabs(theta[j]) < 1e-200)
+            theta[j] = 0.0;
         int64_t ni = (int64_t)fmodq(n, (__float128)N);
         if (ni < 0)
             ni += N;

@@ -313,3 +313,20 @@ def test_adj_brute_force_eq_p2(N):
         ref = sum(mpmath.conj(mp_K(N, y[j], int(k))) * mpmath.mpc(g[j]) for j in range(M))
         assert abs(complex(ref) - f[i]) <= 1e-14 * (1 + abs(complex(ref)))
     assert np.array_equal(oracle.adj(N, y, g)[ks], f)
+
+
+def test_fwd_tiny_fractions_brute_force_eq_p2():
+    """Points a subnormal or tiny distance from a grid point: the oracle's
+    value is finite and equals the literal sum of Eq. (p2) (40 digits), i.e.
+    f_m up to a term of order theta."""
+    N = 13
+    rng = np.random.default_rng(77)
+    f = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    y = np.array([5e-324, -5e-324, 1e-250, -1e-210, 1e-190, 2 * np.pi * 3 / N + 1e-300])
+    g = oracle.fwd(N, y, f)
+    assert np.all(np.isfinite(g))
+    for j in range(y.size):
+        ref = sum(mp_K(N, y[j], k) * mpmath.mpc(f[k]) for k in range(N))
+        assert abs(complex(ref) - g[j]) <= 1e-14 * (1 + abs(complex(ref)))
+    gi = oracle.inv(N, np.concatenate([[1e-250], 2 * np.pi * (np.arange(1, N) + 0.3) / N]), f)
+    assert np.all(np.isfinite(gi)) and gi[0] == f[0]
