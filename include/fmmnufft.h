@@ -33,10 +33,13 @@
  *   - stream is a hipStream_t passed as void* (NULL = the null stream).
  *     Work is enqueued on it; a call returns when the work is enqueued,
  *     except where noted ("synchronises").
- *   - Every function returns an fn_status.  Nothing throws.  On a non-OK
- *     status nufft_last_error() returns a message (thread-local, valid until
- *     the next call on the same thread).  Scalar argument errors are
- *     reported before any GPU work is enqueued.
+ *   - Every function returns an fn_status.  Nothing throws: a C++
+ *     exception inside the library (a failed host allocation) becomes
+ *     FN_ENOMEM (FN_EHIP for any other), after the call has released what
+ *     it allocated.  On a non-OK status nufft_last_error() returns a
+ *     message (thread-local, valid until the next call on the same
+ *     thread).  Scalar argument errors are reported before any GPU work is
+ *     enqueued.
  *   - Host threads: calls from several threads may overlap (the library's
  *     shared state -- workspace pool, operator tables, autotune records --
  *     is locked).  A plan or batch holds one workspace: its executes must
@@ -59,9 +62,12 @@ typedef enum {
     FN_ENOMEM = 2,    /* device workspace allocation failed                */
     FN_EHIP = 3,      /* a HIP runtime call failed (message has details)   */
     FN_ESINGULAR = 4, /* inverse: two y_j coincide on the circle            */
-    FN_ERANGE = 5,    /* inverse: |C_k| or |D_j| leaves the binary64 range,
-                         or a leaf holds over 16 times the mean number of
-                         points (the point set is too ill-conditioned)     */
+    FN_ERANGE = 5,    /* inverse: |log|C_k|| or |log|D_j|| (rescaled as
+                         for nufft_plan_coeffs) exceeds 700 (FN_C128) or 60
+                         (FN_C64, whose binary32 weights D_j g_j must stay
+                         in range), or a leaf holds over 16 times the mean
+                         number of points (the point set is too
+                         ill-conditioned)                                  */
     FN_EPREC = 6      /* eps below what the precision path can deliver     */
 } fn_status;
 
@@ -135,9 +141,11 @@ int nufft_execute(fn_plan *plan, const void *in, void *out, void *stream);
 int nufft_execute_phase(fn_plan *plan, const void *in, void *out, int phase,
                         void *stream);
 
-/* Releases the plan and its workspace (NULL is accepted).  Synchronises the
- * stream of the plan's last call (creation or execute); work of the plan
- * still queued on another stream must have completed before this call. */
+/* Releases the plan and its workspace (NULL is accepted): the workspace
+ * goes back to the library's cache of device blocks (see
+ * nufft_release_cache).  Synchronises the stream of the plan's last call
+ * (creation or execute); work of the plan still queued on another stream
+ * must have completed before this call. */
 int nufft_destroy(fn_plan *plan);
 
 /* Inverse plans: the coefficients of Eq. (p8) the plan computed with the
@@ -177,10 +185,12 @@ int nufft_select_params(int64_t N, int64_t M, double eps, int dtype,
 
 /* Like nufft_plan_fwd / nufft_plan_inv with p, q and lmax given explicitly
  * (values <= 0 mean "the plan's default").  For tuning and tests.  Explicit
- * values are used as given: eps then sets only what is not given, and the
- * result need not meet it (on the FN_C64 path, a depth that leaves more
- * than about 128 sources per leaf sums them in binary32 and can miss 1e-6;
- * the default depth never does). */
+ * values are used as given: eps then sets only what is not given, and a p
+ * or q below what eps needs gives a result that need not meet it.  Any
+ * depth keeps the rounding of the FN_C64 path within its 1e-6 target: its
+ * binary32 moment and near-field sums run in blocks of at most 64 and 256
+ * terms whose partials are added in binary64, however many sources a leaf
+ * holds. */
 int nufft_plan_fwd_ex(fn_plan **plan, int64_t N, int64_t M, const double *y,
                       double eps, int dtype, int32_t p, int32_t q,
                       int32_t lmax, void *stream);
@@ -207,16 +217,20 @@ int nufft_fwd_batched(int32_t count, const int64_t *N, const int64_t *M,
                       double eps, int dtype, void *stream);
 
 /* Setup of a batch (the sorts), kept for repeated evaluations with new
- * f[t], g[t] on the same points.  Synchronises the stream. */
+ * f[t], g[t] on the same points.  Also captures the shared evaluation
+ * launches in a HIP graph and allocates what its replays need (a stream,
+ * events, a pinned table of the f[t], g[t] pointers).  Synchronises the
+ * stream. */
 int nufft_plan_fwd_batched(fn_batch **batch, int32_t count, const int64_t *N,
                            const int64_t *M, const double *const *y, double eps,
                            int dtype, void *stream);
 
-/* Evaluation of a batch plan: g[t] = K_t f[t] for every t.  The shared
- * launches are captured in a HIP graph on the first call and replayed on
- * the batch's own stream, ordered after the work already enqueued on
- * `stream` and before any work enqueued on it afterwards.  No
- * synchronisation; calls on one batch must not run concurrently. */
+/* Evaluation of a batch plan: g[t] = K_t f[t] for every t.  The captured
+ * graph is replayed on the batch's own stream, ordered after the work
+ * already enqueued on `stream` and before any work enqueued on it
+ * afterwards.  No allocation and no stream synchronisation; the host waits
+ * only until the previous call's copy of the pointer table has run, before
+ * it rewrites that table.  Calls on one batch must not run concurrently. */
 int nufft_execute_batched(fn_batch *batch, const void *const *f, void *const *g,
                           void *stream);
 
@@ -235,7 +249,10 @@ int nufft_destroy_batched(fn_batch *batch);
  * unless another is faster by over 5%).  Plans
  * (and batches) created afterwards in this process for the same kind,
  * dtype, size class round(log2 sqrt(N M)) and accuracy class
- * floor(-log10 eps) use the recorded values unless given explicitly.
+ * floor(-log10 eps) use the recorded values unless given explicitly; on
+ * FN_C64 the depth is then raised where needed to keep at most 128 sources
+ * per leaf (N and M may be skewed within a size class), and the candidate
+ * depths tried here respect the same bound.
  * lmax, nterms (may be NULL) receive the choice (nterms 0: the default
  * length was kept).  Synchronises the stream; allocates and frees device
  * memory. */
@@ -244,6 +261,19 @@ int nufft_autotune(int kind, int64_t N, int64_t M, double eps, int dtype, int32_
 
 /* Forgets every recorded choice of nufft_autotune. */
 int nufft_autotune_clear(void);
+
+/* ---- Device memory ----------------------------------------------------
+ *
+ * Plan and batch workspaces come from a cache of device blocks: a released
+ * workspace (nufft_destroy, nufft_destroy_batched, the end of a one-shot
+ * call) returns its blocks to the cache, which hands a block of the same
+ * size to a later plan without hipMalloc.  The cache keeps at most 8 GiB of
+ * free blocks (beyond that a released block is freed at once), and a
+ * failing hipMalloc first frees every cached block and tries again.
+ * nufft_release_cache frees every cached block now (hipFree, which waits
+ * for the device); blocks in use by live plans are not affected.  Always
+ * FN_OK. */
+int nufft_release_cache(void);
 
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *nufft_last_error(void);

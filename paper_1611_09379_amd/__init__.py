@@ -35,7 +35,7 @@ ABI_SYMBOLS = (
     "nufft_fwd_batched", "nufft_plan_fwd_batched", "nufft_execute_batched",
     "nufft_destroy_batched", "nufft_autotune", "nufft_autotune_clear",
     "nufft_set_timing", "nufft_plan_get_timings",
-    "nufft_last_error",
+    "nufft_release_cache", "nufft_last_error",
 )
 
 
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
         "nufft_autotune_clear": [],
         "nufft_set_timing": [ctypes.c_int],
         "nufft_plan_get_timings": [vp, ctypes.POINTER(ctypes.c_float), pi32],
+        "nufft_release_cache": [],
         "nufft_last_error": [],
     }
     for name, args in sig.items():
@@ -377,3 +378,8 @@ def set_timing(on: bool):
     """Process-wide: inverse plans created while on record event timings of
     their log-sum FMM (Plan.timings)."""
     _check(load_library().nufft_set_timing(1 if on else 0))
+
+
+def release_cache():
+    """Frees the device blocks the library keeps cached for later plans."""
+    _check(load_library().nufft_release_cache())

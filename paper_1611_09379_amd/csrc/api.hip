@@ -32,7 +32,10 @@ static int fail(int status, const char *fmt, ...)
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    g_err = buf;
+    try { // never throws: callers may have released resources already
+        g_err = buf;
+    } catch (...) {
+    }
     return status;
 }
 
@@ -44,18 +47,66 @@ static int fail(int status, const char *fmt, ...)
                         hipGetErrorString(e_), __FILE__, __LINE__);            \
     } while (0)
 
+// No C++ exception crosses the C ABI: every entry point's body runs inside
+// FN_API_BEGIN / FN_API_END, which turn a failed host allocation into
+// FN_ENOMEM and anything else into FN_EHIP.
+static int fail_nothrow(int status, const char *msg) noexcept
+{
+    try {
+        g_err = msg;
+    } catch (...) {
+    }
+    return status;
+}
+
+#define FN_API_BEGIN try {
+#define FN_API_END                                                             \
+    }                                                                          \
+    catch (const std::bad_alloc &)                                             \
+    {                                                                          \
+        return fail_nothrow(FN_ENOMEM, "host memory allocation failed");       \
+    }                                                                          \
+    catch (...)                                                                \
+    {                                                                          \
+        return fail_nothrow(FN_EHIP, "unexpected C++ exception in the library"); \
+    }
+
 // ---------------------------------------------------- caching device memory
 //
 // Plans are created and destroyed per one-shot call; freed blocks are kept
 // per size and handed out again so that repeated calls do not pay for
-// hipMalloc / hipFree.
+// hipMalloc / hipFree.  The pool holds at most POOL_CAP bytes of free
+// blocks (a block returned beyond that is freed at once), and a failed
+// hipMalloc first frees every cached block and tries again, so the cache
+// never starves the caller's own allocations.  nufft_release_cache frees
+// the cached blocks on demand.
 
 namespace {
 std::mutex g_pool_mu;
 thread_local hipError_t g_alloc_err = hipSuccess; // last failed hipMalloc
 std::multimap<size_t, void *> g_pool;
+size_t g_pool_bytes = 0;                           // free bytes held
+constexpr size_t POOL_CAP = size_t(8) << 30;
 
 size_t round_bytes(size_t n) { return (n + 255) & ~size_t(255); }
+
+// Frees every cached block; returns the bytes released.  hipFree waits for
+// the device, and a cached block is in no plan's use.
+size_t pool_trim()
+{
+    std::multimap<size_t, void *> blocks;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        blocks.swap(g_pool);
+        g_pool_bytes = 0;
+    }
+    size_t n = 0;
+    for (auto &b : blocks) {
+        (void)hipFree(b.second);
+        n += b.first;
+    }
+    return n;
+}
 
 void *pool_get(size_t bytes)
 {
@@ -66,12 +117,19 @@ void *pool_get(size_t bytes)
         if (it != g_pool.end()) {
             void *p = it->second;
             g_pool.erase(it);
+            g_pool_bytes -= bytes;
             return p;
         }
     }
     void *p = nullptr;
-    const hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError(); // clear it before the retry
+        if (pool_trim() > 0)
+            e = hipMalloc(&p, bytes);
+    }
     if (e != hipSuccess) {
+        (void)hipGetLastError();
         g_alloc_err = e;
         return nullptr;
     }
@@ -82,8 +140,16 @@ void pool_put(void *p, size_t bytes)
 {
     if (!p)
         return;
-    std::lock_guard<std::mutex> lk(g_pool_mu);
-    g_pool.emplace(round_bytes(bytes ? bytes : 1), p);
+    bytes = round_bytes(bytes ? bytes : 1);
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        if (g_pool_bytes + bytes <= POOL_CAP) {
+            g_pool.emplace(bytes, p);
+            g_pool_bytes += bytes;
+            return;
+        }
+    }
+    (void)hipFree(p);
 }
 
 struct Buf {
@@ -145,10 +211,21 @@ static int paper_depth(int64_t N, int64_t M)
 // targets: its near field runs on staged uniform sources and is cheap next
 // to the translations).  Inverse: 4 below lg = 17, then 5 (its sorted-source
 // and log near fields cost more per pair).  FN_LEAF_OFFSET overrides both.
-// The mixed path also keeps at most 128 sources per leaf: its moments sum a
-// leaf's sources and its near field three leaves' sources in binary32, and
-// with few targets (a shallow tree) those sums ran to thousands of terms,
-// whose rounding took single targets past 1e-6.
+// The mixed path also keeps at most 128 sources per leaf (defaults and
+// autotuned depths alike).  Its moment and near-field sums are blocked with
+// binary64 totals, so deeper leaves stay accurate too, but with few targets
+// the cost model alone would pick trees of thousands of sources per leaf.
+// Smallest depth that keeps at most 128 sources per leaf on the mixed path
+// (2 on the binary64 path).
+static int mixed_min_depth(int64_t N, int dtype)
+{
+    int l = 2;
+    if (dtype == FN_C64)
+        while (l < 24 && (N >> l) > 128)
+            ++l;
+    return l;
+}
+
 static int default_depth(int64_t N, int64_t M, int kind, int dtype)
 {
     const double lg = 0.5 * std::log2((double)N * (double)M);
@@ -156,12 +233,13 @@ static int default_depth(int64_t N, int64_t M, int kind, int dtype)
     int off = kind == 0 ? (r < 14 ? 4 : (r < 18 ? 5 : 6)) : (r < 17 ? 4 : 5);
     if (const char *e = getenv("FN_LEAF_OFFSET"))
         off = atoi(e);
-    int l = std::min(24, std::max(2, r - off));
-    if (dtype == FN_C64)
-        while (l < 24 && (N >> l) > 128)
-            ++l;
-    return l;
+    const int l = std::min(24, std::max(2, r - off));
+    return std::max(l, mixed_min_depth(N, dtype));
 }
+
+// Largest |log|Chat_k|| and |log|Dhat_j|| an inverse plan accepts on the
+// mixed path (FN_ERANGE beyond).
+static constexpr double LOG_MAX_C64 = 60.0;
 
 static double eps_floor(int dtype) { return dtype == FN_C64 ? 1e-7 : 1e-15; }
 
@@ -887,23 +965,26 @@ static int prepare_work(fn_plan *P, int sh, bool uniform, int64_t npts, WorkArgs
 // pageable memory takes a much slower, staged path): at least `bytes`,
 // grown on demand and held until the process ends; nullptr if it cannot be
 // had (the read-back then goes to pageable memory).
-static void *pinned_scratch(size_t bytes)
+// Slot 0 serves the flag read-backs, slot 1 the I/O tables of one-shot
+// batches (each call synchronises before it returns, so the next call on
+// the thread may reuse the memory).
+static void *pinned_scratch(size_t bytes, int slot = 0)
 {
-    static thread_local void *buf = nullptr;
-    static thread_local size_t cap = 0;
-    if (bytes > cap) {
-        if (buf)
-            (void)hipHostFree(buf);
-        buf = nullptr;
-        cap = 0;
+    static thread_local void *buf[2] = {nullptr, nullptr};
+    static thread_local size_t cap[2] = {0, 0};
+    if (bytes > cap[slot]) {
+        if (buf[slot])
+            (void)hipHostFree(buf[slot]);
+        buf[slot] = nullptr;
+        cap[slot] = 0;
         const size_t want = std::max<size_t>(bytes, 256);
-        if (hipHostMalloc(&buf, want, hipHostMallocPortable) != hipSuccess) {
-            buf = nullptr;
+        if (hipHostMalloc(&buf[slot], want, hipHostMallocPortable) != hipSuccess) {
+            buf[slot] = nullptr;
             return nullptr;
         }
-        cap = want;
+        cap[slot] = want;
     }
-    return buf;
+    return buf[slot];
 }
 
 static int finish_plan(fn_plan *P, hipStream_t st)
@@ -933,8 +1014,10 @@ static int finish_plan(fn_plan *P, hipStream_t st)
         return fail(FN_ERANGE, "a leaf holds more than %d points: the point set is "
                                "too clustered for the inverse", dense_max(P->N, P->l));
     if (hflags & FLAG_RANGE)
-        return fail(FN_ERANGE, "|C_k| or |D_j| leaves the binary64 range: the "
-                               "point set is too ill-conditioned for the inverse");
+        return fail(FN_ERANGE, "|C_k| or |D_j| leaves the range of %s: the point set "
+                               "is too ill-conditioned for the inverse%s",
+                    P->dtype == FN_C64 ? "the mixed path (exp(+-60))" : "binary64",
+                    P->dtype == FN_C64 ? " on this path (FN_C128 has exp(+-700))" : "");
     return FN_OK;
 }
 
@@ -1081,6 +1164,9 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     da.dhat_out = (cx<double> *)P->dhat.p;
     da.flags_out = (int *)P->flags.p;
     da.logself = std::log(2.0 * M_PI / (double)P->N);
+    // binary64 holds exp(+-700); the mixed path stores w_j = Dhat_j g_j in
+    // binary32 (about exp(+-87)), which leaves |g_j| a range of exp(+-27)
+    da.log_max = P->dtype == FN_C64 ? LOG_MAX_C64 : 700.0;
     // the evaluation's epilogue forms Chat and Dhat
     rc = launch_down<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>(P, F, da, st, 1);
     if (rc)
@@ -1214,8 +1300,12 @@ static void choose(int64_t N, int64_t M, double eps, int kind, int dtype, int32_
             tp = it->second.second;
         }
     }
+    // a recorded depth was tuned for its size class lg = round(log2 sqrt(N M));
+    // N and M can be skewed within the class, so the mixed path's leaf
+    // bound applies to it again
     *l = l_in > 0 ? l_in
-                  : (tl > 0 ? tl : (kind < 0 ? paper_depth(N, M) : default_depth(N, M, kind, dtype)));
+                  : (tl > 0 ? std::max(tl, mixed_min_depth(N, dtype))
+                            : (kind < 0 ? paper_depth(N, M) : default_depth(N, M, kind, dtype)));
     int pp, qq;
     trunc_numbers(eps, *l, &pp, &qq);
     *p = p_in > 0 ? p_in : (tp > 0 ? tp : pp);
@@ -1223,6 +1313,10 @@ static void choose(int64_t N, int64_t M, double eps, int kind, int dtype, int32_
     if (p_given)
         *p_given = p_in > 0 || tp > 0;
 }
+
+static int plan_body(fn_plan *P, int kind, int64_t N, int64_t M, const double *y,
+                     double eps, int dtype, int32_t p_in, int32_t q_in, int32_t l_in,
+                     void *stream, bool defer);
 
 // Creates a plan.  Unless `defer`, waits for the setup kernels and reports
 // their errors; a deferred plan is checked by finish_plan after its first
@@ -1242,6 +1336,25 @@ static int plan_common(fn_plan **out, int kind, int64_t N, int64_t M,
     if (l_in > 24 || p_in > 64 || q_in > 30)
         return fail(FN_EINVAL, "explicit parameters out of range (lmax <= 24, p <= 64, q <= 30)");
     fn_plan *P = new fn_plan();
+    try {
+        rc = plan_body(P, kind, N, M, y, eps, dtype, p_in, q_in, l_in, stream, defer);
+    } catch (...) { // a failed host allocation: release the plan, then report
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        release_plan(P);
+        delete P;
+        throw;
+    }
+    if (rc)
+        return rc; // plan_body released the plan
+    *out = P;
+    return FN_OK;
+}
+
+static int plan_body(fn_plan *P, int kind, int64_t N, int64_t M, const double *y,
+                     double eps, int dtype, int32_t p_in, int32_t q_in, int32_t l_in,
+                     void *stream, bool defer)
+{
+    int rc = FN_OK;
     P->kind = kind;
     P->dtype = dtype;
     P->N = N;
@@ -1278,7 +1391,6 @@ static int plan_common(fn_plan **out, int kind, int64_t N, int64_t M,
         delete P;
         return rc;
     }
-    *out = P;
     return FN_OK;
 }
 
@@ -1320,7 +1432,14 @@ struct fn_batch {
     int PU = 0, PD = 0, q = 0, nbands = 0;
     size_t reg_smem = 0, tr_smem = 0;
     Buf blob, io, flags;
-    std::vector<IoPtr> hio;
+    // host images of the argument blob and of the I/O table, kept unchanged
+    // until the copies that read them have run: the blob's until the batch
+    // is released, the table's until ev_io (recorded after its last copy)
+    std::vector<unsigned char> blob_host;
+    IoPtr *hio = nullptr; // pinned, T entries (graph replays)
+    hipEvent_t ev_io = nullptr;
+    bool io_pending = false;
+    std::vector<IoPtr> hio_pageable; // one-shot fallback without pinned memory
     LaunchShape hist, colscan, place, scan, work, reg, down, up[MAX_BANDS];
     hipStream_t stream = nullptr;
     hipStream_t bs = nullptr;
@@ -1373,6 +1492,11 @@ static void release_batch(fn_batch *B)
         (void)hipEventDestroy(B->ev_in);
     if (B->ev_out)
         (void)hipEventDestroy(B->ev_out);
+    if (B->ev_io)
+        (void)hipEventDestroy(B->ev_io);
+    if (B->hio)
+        (void)hipHostFree(B->hio);
+    B->hio = nullptr;
     if (B->bs)
         (void)hipStreamDestroy(B->bs);
 }
@@ -1383,15 +1507,17 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
 {
     using V = cx<R>;
     const int T = B->T;
-    if (!alloc(B->flags, (size_t)T * 4) || !alloc(B->io, (size_t)T * sizeof(IoPtr)))
-        return fail(FN_ENOMEM, "batch allocation failed");
-    HIPCHK(hipMemsetAsync(B->flags.p, 0, (size_t)T * 4, st));
+    // host bookkeeping first: a failed host allocation then surfaces before
+    // any device work
     std::vector<SortArgs> sa;
     std::vector<WorkArgs> wa;
     std::vector<int> nb_hist, nb_col, nb_one;
     std::vector<TreeJob> jobs(T);
     std::vector<WorkArgs> works(T);
     B->P.assign(T, nullptr);
+    if (!alloc(B->flags, (size_t)T * 4) || !alloc(B->io, (size_t)T * sizeof(IoPtr)))
+        return fail(FN_ENOMEM, "batch allocation failed");
+    HIPCHK(hipMemsetAsync(B->flags.p, 0, (size_t)T * 4, st));
     for (int t = 0; t < T; ++t) {
         fn_plan *P = new fn_plan();
         B->P[t] = P;
@@ -1507,7 +1633,8 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
     if (!bb.bytes.empty()) {
         if (!alloc(B->blob, bb.bytes.size()))
             return fail(FN_ENOMEM, "batch argument allocation failed");
-        HIPCHK(hipMemcpyAsync(B->blob.p, bb.bytes.data(), bb.bytes.size(),
+        B->blob_host = std::move(bb.bytes);
+        HIPCHK(hipMemcpyAsync(B->blob.p, B->blob_host.data(), B->blob_host.size(),
                               hipMemcpyHostToDevice, st));
     }
     // enqueue the sorts
@@ -1602,8 +1729,17 @@ static int plan_batch(fn_batch **out, int32_t count, const int64_t *Ns, const in
     hipStream_t st = (hipStream_t)stream;
     B->stream = st;
     g_arena = &B->arena;
-    int rc = dtype == FN_C128 ? plan_batch_impl<double>(B, Ns, Ms, ys, st)
+    int rc;
+    try {
+        rc = dtype == FN_C128 ? plan_batch_impl<double>(B, Ns, Ms, ys, st)
                               : plan_batch_impl<float>(B, Ns, Ms, ys, st);
+    } catch (...) { // a failed host allocation: release the batch, then report
+        g_arena = nullptr;
+        (void)hipStreamSynchronize(st);
+        release_batch(B);
+        delete B;
+        throw;
+    }
     g_arena = nullptr;
     if (rc) {
         (void)hipStreamSynchronize(st);
@@ -1640,6 +1776,44 @@ static int finish_batch(fn_batch *B, hipStream_t st)
     return FN_OK;
 }
 
+// Replay resources of a batch plan, made once at plan time so that its
+// executes allocate nothing: the batch's stream, its events, the pinned I/O
+// table, and the evaluation captured as a graph (it reads f, g through the
+// device I/O table, so one capture serves every call).
+template <typename R>
+static int prepare_replay(fn_batch *B)
+{
+    if (B->grp.empty())
+        return FN_OK;
+    HIPCHK(hipStreamCreateWithFlags(&B->bs, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&B->ev_io, hipEventDisableTiming));
+    if (hipHostMalloc((void **)&B->hio, (size_t)B->T * sizeof(IoPtr),
+                      hipHostMallocPortable) != hipSuccess) {
+        B->hio = nullptr;
+        return fail(FN_ENOMEM, "pinned host allocation of the I/O table failed");
+    }
+    hipGraph_t gr = nullptr;
+    HIPCHK(hipStreamBeginCapture(B->bs, hipStreamCaptureModeThreadLocal));
+    int rc = launch_batch_eval<R>(B, B->bs);
+    hipError_t e = hipStreamEndCapture(B->bs, &gr);
+    if (rc) {
+        if (gr)
+            (void)hipGraphDestroy(gr);
+        return rc;
+    }
+    if (e != hipSuccess)
+        return fail(FN_EHIP, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&B->gexec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) {
+        B->gexec = nullptr;
+        return fail(FN_EHIP, "graph instantiation: %s", hipGetErrorString(e));
+    }
+    return FN_OK;
+}
+
 template <typename R>
 static int exec_batch_impl(fn_batch *B, const void *const *f, void *const *g, hipStream_t st,
                            bool graph)
@@ -1647,51 +1821,41 @@ static int exec_batch_impl(fn_batch *B, const void *const *f, void *const *g, hi
     for (int t = 0; t < B->T; ++t)
         if (!f[t] || !g[t])
             return fail(FN_EINVAL, "transform %d: f or g is NULL", t);
-    B->hio.resize(B->T);
-    for (int t = 0; t < B->T; ++t)
-        B->hio[t] = {f[t], g[t]};
     B->stream = st;
-    if (!B->grp.empty()) {
-        if (!graph) {
-            HIPCHK(hipMemcpyAsync(B->io.p, B->hio.data(), (size_t)B->T * sizeof(IoPtr),
-                                  hipMemcpyHostToDevice, st));
-            int rc = launch_batch_eval<R>(B, st);
-            if (rc)
-                return rc;
-        } else {
-            // replay on the batch's stream, ordered after the caller's work
-            if (!B->bs) {
-                HIPCHK(hipStreamCreateWithFlags(&B->bs, hipStreamNonBlocking));
-                HIPCHK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
-                HIPCHK(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
-            }
-            HIPCHK(hipEventRecord(B->ev_in, st));
-            HIPCHK(hipStreamWaitEvent(B->bs, B->ev_in, 0));
-            HIPCHK(hipMemcpyAsync(B->io.p, B->hio.data(), (size_t)B->T * sizeof(IoPtr),
-                                  hipMemcpyHostToDevice, B->bs));
-            if (!B->gexec) {
-                hipGraph_t gr = nullptr;
-                HIPCHK(hipStreamBeginCapture(B->bs, hipStreamCaptureModeThreadLocal));
-                int rc = launch_batch_eval<R>(B, B->bs);
-                hipError_t e = hipStreamEndCapture(B->bs, &gr);
-                if (rc) {
-                    if (gr)
-                        (void)hipGraphDestroy(gr);
-                    return rc;
-                }
-                if (e != hipSuccess)
-                    return fail(FN_EHIP, "graph capture: %s", hipGetErrorString(e));
-                e = hipGraphInstantiate(&B->gexec, gr, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(gr);
-                if (e != hipSuccess) {
-                    B->gexec = nullptr;
-                    return fail(FN_EHIP, "graph instantiation: %s", hipGetErrorString(e));
-                }
-            }
-            HIPCHK(hipGraphLaunch(B->gexec, B->bs));
-            HIPCHK(hipEventRecord(B->ev_out, B->bs));
-            HIPCHK(hipStreamWaitEvent(st, B->ev_out, 0));
+    if (!B->grp.empty() && !graph) {
+        // one-shot: the call synchronises before it returns, so the
+        // thread's pinned table (or the batch's own) stays put until then
+        IoPtr *h = (IoPtr *)pinned_scratch((size_t)B->T * sizeof(IoPtr), 1);
+        if (!h) {
+            B->hio_pageable.resize(B->T);
+            h = B->hio_pageable.data();
         }
+        for (int t = 0; t < B->T; ++t)
+            h[t] = {f[t], g[t]};
+        HIPCHK(hipMemcpyAsync(B->io.p, h, (size_t)B->T * sizeof(IoPtr),
+                              hipMemcpyHostToDevice, st));
+        int rc = launch_batch_eval<R>(B, st);
+        if (rc)
+            return rc;
+    } else if (!B->grp.empty()) {
+        if (!B->gexec)
+            return fail(FN_EINVAL, "batch plan has no captured evaluation");
+        // the pinned I/O table is rewritten only once its last copy has run
+        if (B->io_pending)
+            HIPCHK(hipEventSynchronize(B->ev_io));
+        B->io_pending = false;
+        for (int t = 0; t < B->T; ++t)
+            B->hio[t] = {f[t], g[t]};
+        // replay on the batch's stream, ordered after the caller's work
+        HIPCHK(hipEventRecord(B->ev_in, st));
+        HIPCHK(hipStreamWaitEvent(B->bs, B->ev_in, 0));
+        HIPCHK(hipMemcpyAsync(B->io.p, B->hio, (size_t)B->T * sizeof(IoPtr),
+                              hipMemcpyHostToDevice, B->bs));
+        HIPCHK(hipEventRecord(B->ev_io, B->bs));
+        B->io_pending = true;
+        HIPCHK(hipGraphLaunch(B->gexec, B->bs));
+        HIPCHK(hipEventRecord(B->ev_out, B->bs));
+        HIPCHK(hipStreamWaitEvent(st, B->ev_out, 0));
     }
     for (int t : B->solo) {
         int rc = exec_fwd<R>(B->P[t], f[t], g[t], -1, st);
@@ -1834,9 +1998,10 @@ static int autotune(int kind, int64_t N, int64_t M, double eps, int dtype, int32
     const auto key = tune_key(kind, dtype, N, M, eps);
     int lbest = l0;
     double tbest = 1e300;
+    const int lmin = mixed_min_depth(N, dtype);
     for (int off = 4; !rc && off <= 7; ++off) {
-        const int l = std::min(24, std::max(2, lg - off));
-        if (off > 4 && l == std::min(24, std::max(2, lg - off + 1)))
+        const int l = std::max(lmin, std::min(24, std::max(2, lg - off)));
+        if (off > 4 && l == std::max(lmin, std::min(24, std::max(2, lg - off + 1))))
             continue;
         std::vector<double> ts;
         for (int r = 0; !rc && r < 4; ++r) {
@@ -1895,25 +2060,33 @@ int nufft_plan_fwd_ex(fn_plan **plan, int64_t N, int64_t M, const double *y,
                       double eps, int dtype, int32_t p, int32_t q, int32_t lmax,
                       void *stream)
 {
+    FN_API_BEGIN
     return plan_common(plan, 0, N, M, y, eps, dtype, p, q, lmax, stream);
+    FN_API_END
 }
 
 int nufft_plan_inv_ex(fn_plan **plan, int64_t N, const double *y, double eps,
                       int dtype, int32_t p, int32_t q, int32_t lmax, void *stream)
 {
+    FN_API_BEGIN
     return plan_common(plan, 1, N, N, y, eps, dtype, p, q, lmax, stream);
+    FN_API_END
 }
 
 int nufft_plan_fwd(fn_plan **plan, int64_t N, int64_t M, const double *y,
                    double eps, int dtype, void *stream)
 {
+    FN_API_BEGIN
     return plan_common(plan, 0, N, M, y, eps, dtype, 0, 0, 0, stream);
+    FN_API_END
 }
 
 int nufft_plan_inv(fn_plan **plan, int64_t N, const double *y, double eps,
                    int dtype, void *stream)
 {
+    FN_API_BEGIN
     return plan_common(plan, 1, N, N, y, eps, dtype, 0, 0, 0, stream);
+    FN_API_END
 }
 
 static int execute(fn_plan *plan, const void *in, void *out, int phase,
@@ -1934,19 +2107,24 @@ static int execute(fn_plan *plan, const void *in, void *out, int phase,
 
 int nufft_execute(fn_plan *plan, const void *in, void *out, void *stream)
 {
+    FN_API_BEGIN
     return execute(plan, in, out, -1, stream);
+    FN_API_END
 }
 
 int nufft_execute_phase(fn_plan *plan, const void *in, void *out, int phase,
                         void *stream)
 {
+    FN_API_BEGIN
     if (phase < 0 || phase > 2)
         return fail(FN_EINVAL, "phase must be 0, 1 or 2");
     return execute(plan, in, out, phase, stream);
+    FN_API_END
 }
 
 int nufft_destroy(fn_plan *plan)
 {
+    FN_API_BEGIN
     if (!plan)
         return FN_OK;
     // the workspace returns to the library's pool only once the plan's
@@ -1957,10 +2135,12 @@ int nufft_destroy(fn_plan *plan)
     if (e != hipSuccess)
         return fail(FN_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
     return FN_OK;
+    FN_API_END
 }
 
 int nufft_plan_coeffs(const fn_plan *plan, double *chat, void *dhat, void *stream)
 {
+    FN_API_BEGIN
     if (!plan || !chat || !dhat)
         return fail(FN_EINVAL, "NULL argument");
     if (plan->kind != 1)
@@ -1972,10 +2152,12 @@ int nufft_plan_coeffs(const fn_plan *plan, double *chat, void *dhat, void *strea
                        (cx<double> *)dhat);
     HIPCHK(hipGetLastError());
     return FN_OK;
+    FN_API_END
 }
 
 int nufft_plan_get_info(const fn_plan *plan, fn_plan_info *info)
 {
+    FN_API_BEGIN
     if (!plan || !info)
         return fail(FN_EINVAL, "NULL argument");
     info->N = plan->N;
@@ -1988,16 +2170,20 @@ int nufft_plan_get_info(const fn_plan *plan, fn_plan_info *info)
     info->nterms = plan->cot.PD;
     info->eps = plan->eps;
     return FN_OK;
+    FN_API_END
 }
 
 int nufft_set_timing(int on)
 {
+    FN_API_BEGIN
     g_timing.store(on ? 1 : 0);
     return FN_OK;
+    FN_API_END
 }
 
 int nufft_plan_get_timings(const fn_plan *plan, float *ms, int32_t *log_terms)
 {
+    FN_API_BEGIN
     if (!plan || !ms)
         return fail(FN_EINVAL, "plan or ms is NULL");
     for (int i = 0; i < 3; ++i)
@@ -2005,11 +2191,13 @@ int nufft_plan_get_timings(const fn_plan *plan, float *ms, int32_t *log_terms)
     if (log_terms)
         *log_terms = plan->log_terms;
     return FN_OK;
+    FN_API_END
 }
 
 int nufft_select_params(int64_t N, int64_t M, double eps, int dtype, int32_t *p,
                         int32_t *q, int32_t *lmax)
 {
+    FN_API_BEGIN
     int rc = check_common(N, M, eps, dtype);
     if (rc)
         return rc;
@@ -2022,55 +2210,90 @@ int nufft_select_params(int64_t N, int64_t M, double eps, int dtype, int32_t *p,
     if (lmax)
         *lmax = ll;
     return FN_OK;
+    FN_API_END
 }
 
 int nufft_fwd(int64_t N, int64_t M, const double *y, const void *f, void *g,
               double eps, int dtype, void *stream)
 {
+    FN_API_BEGIN
     if (!f || !g)
         return fail(FN_EINVAL, "f or g is NULL");
     fn_plan *P = nullptr;
     int rc = plan_common(&P, 0, N, M, y, eps, dtype, 0, 0, 0, stream, true);
     if (rc)
         return rc;
-    return finish_one_shot(P, nufft_execute(P, f, g, stream));
+    try {
+        return finish_one_shot(P, execute(P, f, g, -1, stream));
+    } catch (...) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        release_plan(P);
+        delete P;
+        throw;
+    }
+    FN_API_END
 }
 
 int inufft(int64_t N, const double *y, const void *g, void *f, double eps,
            int dtype, void *stream)
 {
+    FN_API_BEGIN
     if (!f || !g)
         return fail(FN_EINVAL, "f or g is NULL");
     fn_plan *P = nullptr;
     int rc = plan_common(&P, 1, N, N, y, eps, dtype, 0, 0, 0, stream, true);
     if (rc)
         return rc;
-    return finish_one_shot(P, nufft_execute(P, g, f, stream));
+    try {
+        return finish_one_shot(P, execute(P, g, f, -1, stream));
+    } catch (...) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        release_plan(P);
+        delete P;
+        throw;
+    }
+    FN_API_END
 }
 
 int nufft_plan_fwd_batched(fn_batch **batch, int32_t count, const int64_t *N,
                            const int64_t *M, const double *const *y, double eps, int dtype,
                            void *stream)
 {
+    FN_API_BEGIN
     int rc = plan_batch(batch, count, N, M, y, eps, dtype, stream);
     if (rc)
         return rc;
-    rc = finish_batch(*batch, (hipStream_t)stream);
+    try {
+        rc = finish_batch(*batch, (hipStream_t)stream);
+        if (!rc)
+            rc = dtype == FN_C128 ? prepare_replay<double>(*batch)
+                                  : prepare_replay<float>(*batch);
+    } catch (...) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        release_batch(*batch);
+        delete *batch;
+        *batch = nullptr;
+        throw;
+    }
     if (rc) {
         release_batch(*batch);
         delete *batch;
         *batch = nullptr;
     }
     return rc;
+    FN_API_END
 }
 
 int nufft_execute_batched(fn_batch *batch, const void *const *f, void *const *g, void *stream)
 {
+    FN_API_BEGIN
     return exec_batch(batch, f, g, stream, true);
+    FN_API_END
 }
 
 int nufft_destroy_batched(fn_batch *batch)
 {
+    FN_API_BEGIN
     if (!batch)
         return FN_OK;
     hipError_t e = hipStreamSynchronize(batch->stream);
@@ -2081,36 +2304,59 @@ int nufft_destroy_batched(fn_batch *batch)
     if (e != hipSuccess)
         return fail(FN_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
     return FN_OK;
+    FN_API_END
 }
 
 int nufft_fwd_batched(int32_t count, const int64_t *N, const int64_t *M,
                       const double *const *y, const void *const *f, void *const *g,
                       double eps, int dtype, void *stream)
 {
+    FN_API_BEGIN
     if (!f || !g)
         return fail(FN_EINVAL, "f or g pointer array is NULL");
     fn_batch *B = nullptr;
     int rc = plan_batch(&B, count, N, M, y, eps, dtype, stream);
     if (rc)
         return rc;
-    int rc_exec = exec_batch(B, f, g, stream, false);
-    rc = finish_batch(B, (hipStream_t)stream);
+    try {
+        int rc_exec = exec_batch(B, f, g, stream, false);
+        rc = finish_batch(B, (hipStream_t)stream);
+        rc = rc ? rc : rc_exec;
+    } catch (...) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        release_batch(B);
+        delete B;
+        throw;
+    }
     release_batch(B);
     delete B;
-    return rc ? rc : rc_exec;
+    return rc;
+    FN_API_END
 }
 
 int nufft_autotune(int kind, int64_t N, int64_t M, double eps, int dtype, int32_t *lmax,
                    int32_t *nterms, void *stream)
 {
+    FN_API_BEGIN
     return autotune(kind, N, M, eps, dtype, lmax, nterms, (hipStream_t)stream);
+    FN_API_END
 }
 
 int nufft_autotune_clear(void)
 {
+    FN_API_BEGIN
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned.clear();
     return FN_OK;
+    FN_API_END
+}
+
+int nufft_release_cache(void)
+{
+    FN_API_BEGIN
+    (void)pool_trim();
+    return FN_OK;
+    FN_API_END
 }
 
 const char *nufft_last_error(void) { return g_err.c_str(); }

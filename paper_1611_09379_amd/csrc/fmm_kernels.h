@@ -41,6 +41,17 @@ enum { EPI_FWD = 0, EPI_INV = 1, EPI_LOGCD = 2 };
 
 constexpr int BLOCK = 256; // 4 wavefronts of 64
 
+// Binary32 sums of the near field and of the vector P2M run over blocks of
+// at most this many terms; each block's partial is added into a binary64
+// total.  The rounding error of a sum then stays at that of a block,
+// whatever the number of sources in a leaf.  Binary64 sums are not split.
+template <typename R>
+__host__ __device__ constexpr int32_t fold_len()
+{
+    return sizeof(R) == 8 ? INT32_MAX : 256;
+}
+constexpr int P2M_FOLD = 64; // sources per binary32 block of the vector P2M
+
 // Points sorted by leaf: off[b]..off[b+1] index the points of leaf b.
 struct SortedSet {
     const int32_t *off;
@@ -228,17 +239,44 @@ __device__ __forceinline__ int64_t uni_leaf(int64_t k, int l, int64_t N, double 
 }
 
 
+// Binary64 accumulator of a binary32 moment (the vector P2M's blocks).
+template <typename V>
+struct wide { typedef V type; };
+template <>
+struct wide<cx<float>> { typedef cx<double> type; };
+template <>
+struct wide<float> { typedef double type; };
+
+__device__ __forceinline__ void vacc(cx<double> &t, cx<float> v)
+{
+    t.re += (double)v.re;
+    t.im += (double)v.im;
+}
+__device__ __forceinline__ void vacc(double &t, float v) { t += (double)v; }
+template <typename V>
+__device__ __forceinline__ V vnarrow(typename wide<V>::type t)
+{
+    if constexpr (ncomp<V>::value == 2)
+        return {(decltype(V::re))t.re, (decltype(V::re))t.im};
+    else
+        return (V)t;
+}
+
 // P2M at leaf b for CHS consecutive moments m0..: a_m = sum w v^m with
 // v = (sigma - c)/r.  The log kernel takes unit weights minus the uniform
-// density of one point per grid unit (moments 2r/(m+1) for even m).
+// density of one point per grid unit (moments 2r/(m+1) for even m).  The
+// sources are read in place (they did not fit in LDS); binary32 terms are
+// summed in binary64.
 template <typename R, typename V, int KER, int SRC>
 __device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, const cx<R> *fu, int64_t b,
                                           int m0, V *acc)
 {
+    using W = typename wide<V>::type;
     const int l = a.l;
     const int64_t N = a.N;
+    W tot[CHS];
     for (int c = 0; c < CHS; ++c)
-        acc[c] = vzero<V>();
+        tot[c] = vzero<W>();
     if constexpr (SRC == SET_UNIFORM) {
         const int64_t k0 = uni_start(b, l, N), k1 = uni_start(b + 1, l, N);
         for (int64_t k = k0; k < k1; ++k) {
@@ -250,7 +288,10 @@ __device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, const cx<R> *fu
             else
                 w = R(1);
             for (int c = 0; c < CHS; ++c) {
-                vfma(acc[c], pw, w);
+                if constexpr (sizeof(R) == 8)
+                    vfma(tot[c], pw, w);
+                else
+                    vacc(tot[c], vscale(w, pw));
                 pw *= v;
             }
         }
@@ -265,11 +306,16 @@ __device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, const cx<R> *fu
             else
                 w = R(1);
             for (int c = 0; c < CHS; ++c) {
-                vfma(acc[c], pw, w);
+                if constexpr (sizeof(R) == 8)
+                    vfma(tot[c], pw, w);
+                else
+                    vacc(tot[c], vscale(w, pw));
                 pw *= v;
             }
         }
     }
+    for (int c = 0; c < CHS; ++c)
+        acc[c] = vnarrow<V>(tot[c]);
     if constexpr (KER == KER_LOG) {
         const double r = ldexp((double)N, -(l + 1));
         for (int c = 0; c < CHS; ++c) {
@@ -285,57 +331,79 @@ __device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, const cx<R> *fu
 // leaf, moments m0 .. m0+CHS-1 (m0 a multiple of 4).  Four sources at a
 // time, their powers v^m0 = (v^4)^(m0/4) formed as independent chains (two
 // squarings fewer than from v); each moment still sums its sources in
-// order.
+// order.  Binary32 sums run over blocks of P2M_FOLD sources, each block
+// added into a binary64 total.
 template <typename R, typename V, int KER>
 __device__ __forceinline__ void p2m_staged(const R *sv, const R *sv4, const cx<R> *sw, int j0,
                                            int j1, int m0, double r, V *acc)
 {
     static_assert(CHS % 4 == 0, "chunks start at multiples of 4");
-    for (int c = 0; c < CHS; ++c)
-        acc[c] = vzero<V>();
-    int j = j0;
-    for (; j + 4 <= j1; j += 4) {
-        R v[4], sq[4], pw[4];
-        V w[4];
+    using W = typename wide<V>::type;
+    constexpr int FOLD = sizeof(R) == 8 ? INT32_MAX : P2M_FOLD;
+    W tot[CHS];
+    for (int jb = j0; jb < j1;) {
+        const int je = (j1 - jb > FOLD) ? jb + FOLD : j1;
+        for (int c = 0; c < CHS; ++c)
+            acc[c] = vzero<V>();
+        int j = jb;
+        for (; j + 4 <= je; j += 4) {
+            R v[4], sq[4], pw[4];
+            V w[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            v[u] = sv[j + u];
-            sq[u] = sv4[j + u];
-            pw[u] = R(1);
+            for (int u = 0; u < 4; ++u) {
+                v[u] = sv[j + u];
+                sq[u] = sv4[j + u];
+                pw[u] = R(1);
+                if constexpr (KER == KER_COT)
+                    w[u] = sw[j + u];
+                else
+                    w[u] = R(1);
+            }
+            for (int e = m0 >> 2; e; e >>= 1) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (e & 1)
+                        pw[u] *= sq[u];
+                    sq[u] *= sq[u];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CHS; ++c) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    vfma(acc[c], pw[u], w[u]);
+                    pw[u] *= v[u];
+                }
+            }
+        }
+        for (; j < je; ++j) {
+            const R v = sv[j];
+            R pw = ipow(sv4[j], m0 >> 2);
+            V w;
             if constexpr (KER == KER_COT)
-                w[u] = sw[j + u];
+                w = sw[j];
             else
-                w[u] = R(1);
-        }
-        for (int e = m0 >> 2; e; e >>= 1) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (e & 1)
-                    pw[u] *= sq[u];
-                sq[u] *= sq[u];
+                w = R(1);
+            for (int c = 0; c < CHS; ++c) {
+                vfma(acc[c], pw, w);
+                pw *= v;
             }
         }
-#pragma unroll
-        for (int c = 0; c < CHS; ++c) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                vfma(acc[c], pw[u], w[u]);
-                pw[u] *= v[u];
+        if constexpr (sizeof(R) != 8) {
+            for (int c = 0; c < CHS; ++c) {
+                if (jb == j0)
+                    tot[c] = vzero<W>();
+                vacc(tot[c], acc[c]);
             }
         }
+        jb = je;
     }
-    for (; j < j1; ++j) {
-        const R v = sv[j];
-        R pw = ipow(sv4[j], m0 >> 2);
-        V w;
-        if constexpr (KER == KER_COT)
-            w = sw[j];
-        else
-            w = R(1);
-        for (int c = 0; c < CHS; ++c) {
-            vfma(acc[c], pw, w);
-            pw *= v;
-        }
+    if (j1 <= j0) {
+        for (int c = 0; c < CHS; ++c)
+            acc[c] = vzero<V>();
+    } else if constexpr (sizeof(R) != 8) {
+        for (int c = 0; c < CHS; ++c)
+            acc[c] = vnarrow<V>(tot[c]);
     }
     if constexpr (KER == KER_LOG) {
         for (int c = 0; c < CHS; ++c) {
@@ -827,8 +895,10 @@ struct DownArgs {
     double *chat_out;        // LOGCD outputs: Chat_k (uniform points) and
     cx<double> *dhat_out;    // Dhat_j (sorted sources), Eq. (p8)
     double logself;          // LOGCD: log(2 pi / N), the excluded self term
-    int *flags_out;          // LOGCD: FLAG_RANGE when a log-sum leaves the
-                             // range of exp
+    int *flags_out;          // LOGCD: FLAG_RANGE when a log-sum leaves
+    double log_max;          // [-log_max, log_max] (the range of exp in
+                             // binary64, or what the binary32 weights
+                             // D_j g_j of the mixed path can hold)
     const int *flags;        // setup error flags: sorted-source passes stop
                              // at FLAG_DENSE (their near field would be
                              // quadratic in the leaf size)
@@ -1001,16 +1071,17 @@ __device__ __forceinline__ int64_t uni_start_unwrapped(int64_t b, int l, int64_t
 }
 
 // Near field of the cot kernel: sum over the sources of leaves b-1, b, b+1
-// (unwrapped around the circle) of w / (tau - sigma~).
+// (unwrapped around the circle) of w / (tau - sigma~).  Binary32 terms are
+// summed in blocks (fold_len) or straight into binary64.
 template <typename R, typename V, int SRC>
-__device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
-                                          double tth, int64_t leaf,
-                                          const cx<R> *fs, int64_t K0,
-                                          const cx<R> *f_uniform)
+__device__ __forceinline__ cx<double> near_cot(const DownArgs<R, V> &a, int64_t tm,
+                                               double tth, int64_t leaf,
+                                               const cx<R> *fs, int64_t K0,
+                                               const cx<R> *f_uniform)
 {
     const int64_t N = a.N;
     const int64_t nleaf = int64_t(1) << a.l;
-    cx<R> acc = {R(0), R(0)};
+    cx<double> tot = {0.0, 0.0};
     if constexpr (SRC == SET_UNIFORM) {
         if (fs) { // sources staged in LDS from unwrapped index K0 on
             const int64_t k0 = uni_start_unwrapped(leaf - 1, a.l, N);
@@ -1018,48 +1089,57 @@ __device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
             const int32_t base = (int32_t)(tm - k0);
             const cx<R> *fp = fs + (k0 - K0);
             const int32_t cnt = (int32_t)(k1 - k0);
-            // binary64: two pairs at a time, each pair over one reciprocal,
-            // w0/d0 + w1/d1 = (w0 d1 + w1 d0) / (d0 d1) (no distance is
-            // zero: exact hits never reach the near field); binary32 keeps
-            // one reciprocal per pair, whose rounding it can afford less
-            cx<R> a1 = {R(0), R(0)}, a2 = {R(0), R(0)}, a3 = {R(0), R(0)};
-            int32_t i = 0;
-            double cb = (double)base; // base - i, exact
-            for (; i + 4 <= cnt; i += 4, cb -= 4.0) {
-                const R d0 = (R)(cb + tth);
-                const R d1 = (R)((cb - 1.0) + tth);
-                const R d2 = (R)((cb - 2.0) + tth);
-                const R d3 = (R)((cb - 3.0) + tth);
-                const cx<R> w0 = fp[i], w1 = fp[i + 1], w2 = fp[i + 2], w3 = fp[i + 3];
-                if constexpr (sizeof(R) == 8) {
-                    const R r01 = recip(d0 * d1), r23 = recip(d2 * d3);
-                    acc.re = fma(fma(w0.re, d1, w1.re * d0), r01, acc.re);
-                    acc.im = fma(fma(w0.im, d1, w1.im * d0), r01, acc.im);
-                    a1.re = fma(fma(w2.re, d3, w3.re * d2), r23, a1.re);
-                    a1.im = fma(fma(w2.im, d3, w3.im * d2), r23, a1.im);
-                } else {
-                    const R r0 = recip(d0), r1 = recip(d1), r2 = recip(d2), r3 = recip(d3);
-                    acc.re = fma(w0.re, r0, acc.re);
-                    acc.im = fma(w0.im, r0, acc.im);
-                    a1.re = fma(w1.re, r1, a1.re);
-                    a1.im = fma(w1.im, r1, a1.im);
-                    a2.re = fma(w2.re, r2, a2.re);
-                    a2.im = fma(w2.im, r2, a2.im);
-                    a3.re = fma(w3.re, r3, a3.re);
-                    a3.im = fma(w3.im, r3, a3.im);
+            for (int32_t ib = 0; ib < cnt;) {
+                const int32_t ie = (cnt - ib > fold_len<R>()) ? ib + fold_len<R>() : cnt;
+                // binary64: two pairs at a time, each pair over one
+                // reciprocal, w0/d0 + w1/d1 = (w0 d1 + w1 d0) / (d0 d1) (no
+                // distance is zero: exact hits never reach the near field);
+                // binary32 keeps one reciprocal per pair, whose rounding it
+                // can afford less
+                cx<R> acc = {R(0), R(0)}, a1 = acc, a2 = acc, a3 = acc;
+                int32_t i = ib;
+                double cb = (double)(base - ib); // base - i, exact
+                for (; i + 4 <= ie; i += 4, cb -= 4.0) {
+                    const R d0 = (R)(cb + tth);
+                    const R d1 = (R)((cb - 1.0) + tth);
+                    const R d2 = (R)((cb - 2.0) + tth);
+                    const R d3 = (R)((cb - 3.0) + tth);
+                    const cx<R> w0 = fp[i], w1 = fp[i + 1], w2 = fp[i + 2], w3 = fp[i + 3];
+                    if constexpr (sizeof(R) == 8) {
+                        const R r01 = recip(d0 * d1), r23 = recip(d2 * d3);
+                        acc.re = fma(fma(w0.re, d1, w1.re * d0), r01, acc.re);
+                        acc.im = fma(fma(w0.im, d1, w1.im * d0), r01, acc.im);
+                        a1.re = fma(fma(w2.re, d3, w3.re * d2), r23, a1.re);
+                        a1.im = fma(fma(w2.im, d3, w3.im * d2), r23, a1.im);
+                    } else {
+                        const R r0 = recip(d0), r1 = recip(d1), r2 = recip(d2), r3 = recip(d3);
+                        acc.re = fma(w0.re, r0, acc.re);
+                        acc.im = fma(w0.im, r0, acc.im);
+                        a1.re = fma(w1.re, r1, a1.re);
+                        a1.im = fma(w1.im, r1, a1.im);
+                        a2.re = fma(w2.re, r2, a2.re);
+                        a2.im = fma(w2.im, r2, a2.im);
+                        a3.re = fma(w3.re, r3, a3.re);
+                        a3.im = fma(w3.im, r3, a3.im);
+                    }
                 }
+                for (; i < ie; ++i) {
+                    const R rd = recip((R)((double)(base - i) + tth));
+                    const cx<R> w = fp[i];
+                    acc.re = fma(w.re, rd, acc.re);
+                    acc.im = fma(w.im, rd, acc.im);
+                }
+                acc.re += (a1.re + a2.re) + a3.re;
+                acc.im += (a1.im + a2.im) + a3.im;
+                tot.re += (double)acc.re;
+                tot.im += (double)acc.im;
+                ib = ie;
             }
-            for (; i < cnt; ++i) {
-                const R rd = recip((R)((double)(base - i) + tth));
-                const cx<R> w = fp[i];
-                acc.re = fma(w.re, rd, acc.re);
-                acc.im = fma(w.im, rd, acc.im);
-            }
-            acc.re += (a1.re + a2.re) + a3.re;
-            acc.im += (a1.im + a2.im) + a3.im;
-            return acc;
+            return tot;
         }
     }
+    // sources read in place (they did not fit in LDS): each term rounded in
+    // R, the sum kept in binary64
     for (int dl = -1; dl <= 1; ++dl) {
         int64_t b = leaf + dl, shift = 0;
         if (b < 0) {
@@ -1074,8 +1154,8 @@ __device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
             for (int64_t k = k0; k < k1; ++k) {
                 const R rd = recip((R)((double)(tm - k - shift) + tth));
                 const cx<R> w = f_uniform[k];
-                acc.re = fma(w.re, rd, acc.re);
-                acc.im = fma(w.im, rd, acc.im);
+                tot.re = fma((double)w.re, (double)rd, tot.re);
+                tot.im = fma((double)w.im, (double)rd, tot.im);
             }
         } else {
             const int32_t t0 = a.src.off[b], t1 = a.src.off[b + 1];
@@ -1083,12 +1163,12 @@ __device__ __forceinline__ cx<R> near_cot(const DownArgs<R, V> &a, int64_t tm,
                 const double dd = grid_diff(tm - a.src.m[t] - shift, tth, a.src.th[t]);
                 const R rd = recip((R)dd);
                 const cx<R> w = a.w_sorted[t];
-                acc.re = fma(w.re, rd, acc.re);
-                acc.im = fma(w.im, rd, acc.im);
+                tot.re = fma((double)w.re, (double)rd, tot.re);
+                tot.im = fma((double)w.im, (double)rd, tot.im);
             }
         }
     }
-    return acc;
+    return tot;
 }
 
 // Sorted sources of a subtree staged in LDS: the leaves leaf0 - 1 ..
@@ -1132,48 +1212,57 @@ __device__ __forceinline__ double near_dist_t(int32_t tm, int32_t m, double a, d
 }
 
 // Cot near field from staged sources [j0, j1): sum w / (tau - sigma)
-// (GT: the target is on the grid, tth = 0).
+// (GT: the target is on the grid, tth = 0).  Binary32 sums run over blocks
+// of NEAR_FOLD pairs, each block's partial added into a binary64 total, so
+// the rounding of the sum does not grow with the number of sources.
 template <typename R, bool GT>
-__device__ __forceinline__ cx<R> near_cot_staged(const NearStage<R> &ns, int32_t j0,
-                                                 int32_t j1, int32_t tmr, double tth)
+__device__ __forceinline__ cx<double> near_cot_staged(const NearStage<R> &ns, int32_t j0,
+                                                      int32_t j1, int32_t tmr, double tth)
 {
-    cx<R> a0 = {R(0), R(0)}, a1 = a0, a2 = a0, a3 = a0;
     const typename NearStage<R>::MT tmd = (typename NearStage<R>::MT)tmr;
-    int32_t j = j0;
-    // binary64: two pairs at a time, each pair over one reciprocal (no
-    // distance is zero: exact hits never reach the near field); binary32
-    // keeps one reciprocal per pair
-    for (; j + 4 <= j1; j += 4) {
-        const R d0 = (R)near_dist_t<GT>(tmd, ns.m[j], tth, ns.th[j]);
-        const R d1 = (R)near_dist_t<GT>(tmd, ns.m[j + 1], tth, ns.th[j + 1]);
-        const R d2 = (R)near_dist_t<GT>(tmd, ns.m[j + 2], tth, ns.th[j + 2]);
-        const R d3 = (R)near_dist_t<GT>(tmd, ns.m[j + 3], tth, ns.th[j + 3]);
-        const cx<R> w0 = ns.w[j], w1 = ns.w[j + 1], w2 = ns.w[j + 2], w3 = ns.w[j + 3];
-        if constexpr (sizeof(R) == 8) {
-            const R r01 = recip(d0 * d1), r23 = recip(d2 * d3);
-            a0.re = fma(fma(w0.re, d1, w1.re * d0), r01, a0.re);
-            a0.im = fma(fma(w0.im, d1, w1.im * d0), r01, a0.im);
-            a1.re = fma(fma(w2.re, d3, w3.re * d2), r23, a1.re);
-            a1.im = fma(fma(w2.im, d3, w3.im * d2), r23, a1.im);
-        } else {
-            const R r0 = recip(d0), r1 = recip(d1), r2 = recip(d2), r3 = recip(d3);
-            a0.re = fma(w0.re, r0, a0.re);
-            a0.im = fma(w0.im, r0, a0.im);
-            a1.re = fma(w1.re, r1, a1.re);
-            a1.im = fma(w1.im, r1, a1.im);
-            a2.re = fma(w2.re, r2, a2.re);
-            a2.im = fma(w2.im, r2, a2.im);
-            a3.re = fma(w3.re, r3, a3.re);
-            a3.im = fma(w3.im, r3, a3.im);
+    cx<double> tot = {0.0, 0.0};
+    for (int32_t jb = j0; jb < j1;) {
+        const int32_t je = (j1 - jb > fold_len<R>()) ? jb + fold_len<R>() : j1;
+        cx<R> a0 = {R(0), R(0)}, a1 = a0, a2 = a0, a3 = a0;
+        int32_t j = jb;
+        // binary64: two pairs at a time, each pair over one reciprocal (no
+        // distance is zero: exact hits never reach the near field); binary32
+        // keeps one reciprocal per pair
+        for (; j + 4 <= je; j += 4) {
+            const R d0 = (R)near_dist_t<GT>(tmd, ns.m[j], tth, ns.th[j]);
+            const R d1 = (R)near_dist_t<GT>(tmd, ns.m[j + 1], tth, ns.th[j + 1]);
+            const R d2 = (R)near_dist_t<GT>(tmd, ns.m[j + 2], tth, ns.th[j + 2]);
+            const R d3 = (R)near_dist_t<GT>(tmd, ns.m[j + 3], tth, ns.th[j + 3]);
+            const cx<R> w0 = ns.w[j], w1 = ns.w[j + 1], w2 = ns.w[j + 2], w3 = ns.w[j + 3];
+            if constexpr (sizeof(R) == 8) {
+                const R r01 = recip(d0 * d1), r23 = recip(d2 * d3);
+                a0.re = fma(fma(w0.re, d1, w1.re * d0), r01, a0.re);
+                a0.im = fma(fma(w0.im, d1, w1.im * d0), r01, a0.im);
+                a1.re = fma(fma(w2.re, d3, w3.re * d2), r23, a1.re);
+                a1.im = fma(fma(w2.im, d3, w3.im * d2), r23, a1.im);
+            } else {
+                const R r0 = recip(d0), r1 = recip(d1), r2 = recip(d2), r3 = recip(d3);
+                a0.re = fma(w0.re, r0, a0.re);
+                a0.im = fma(w0.im, r0, a0.im);
+                a1.re = fma(w1.re, r1, a1.re);
+                a1.im = fma(w1.im, r1, a1.im);
+                a2.re = fma(w2.re, r2, a2.re);
+                a2.im = fma(w2.im, r2, a2.im);
+                a3.re = fma(w3.re, r3, a3.re);
+                a3.im = fma(w3.im, r3, a3.im);
+            }
         }
+        for (; j < je; ++j) {
+            const R r = recip((R)near_dist_t<GT>(tmd, ns.m[j], tth, ns.th[j]));
+            const cx<R> w = ns.w[j];
+            a0.re = fma(w.re, r, a0.re);
+            a0.im = fma(w.im, r, a0.im);
+        }
+        tot.re += (double)((a0.re + a1.re) + (a2.re + a3.re));
+        tot.im += (double)((a0.im + a1.im) + (a2.im + a3.im));
+        jb = je;
     }
-    for (; j < j1; ++j) {
-        const R r = recip((R)near_dist_t<GT>(tmd, ns.m[j], tth, ns.th[j]));
-        const cx<R> w = ns.w[j];
-        a0.re = fma(w.re, r, a0.re);
-        a0.im = fma(w.im, r, a0.im);
-    }
-    return {(a0.re + a1.re) + (a2.re + a3.re), (a0.im + a1.im) + (a2.im + a3.im)};
+    return tot;
 }
 
 // log prod |tau - sigma| over the staged sources [j, j1), folded into
@@ -1658,9 +1747,10 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             const int64_t leaf = box_of(tm, th, a.l, N);
             const R u = (R)rel_coord_r(tm, th, leaf, a.l, N, invN);
             V h = horner4<R, V, PD>(leafloc, RS, (int)(leaf - leaf0), u);
-            cx<R> nr = near_cot<R, V, SRC>(a, tm, th, leaf, fsp, K0, (const cx<R> *)f_uniform);
-            double hr = (double)h.re + hscale * (double)nr.re;
-            double hi = (double)h.im + hscale * (double)nr.im;
+            const cx<double> nr =
+                near_cot<R, V, SRC>(a, tm, th, leaf, fsp, K0, (const cx<R> *)f_uniform);
+            double hr = (double)h.re + hscale * nr.re;
+            double hi = (double)h.im + hscale * nr.im;
             // g = -(F/2)(S + i h), F = 2i sin(pi th) e^{i pi th} / N
             double sp = sinpi(th), cp = cospi(th);
             double Fr = -2.0 * sp * sp * invN, Fi = 2.0 * sp * cp * invN;
@@ -1681,11 +1771,13 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             const int il = (int)(leaf - leaf0);
             const R u = (R)rel_coord_r(k, 0.0, leaf, a.l, N, invN);
             V h = horner4<R, V, PD>(leafloc, RS, il, u);
-            cx<R> nr = staged ? near_cot_staged<R, true>(ns, ns.off[il], ns.off[il + 3],
-                                                         (int32_t)(k - base), 0.0)
-                              : near_cot<R, V, SRC>(a, k, 0.0, leaf, nullptr, 0, (const cx<R> *)f_uniform);
-            double hr = (double)h.re + hscale * (double)nr.re;
-            double hi = (double)h.im + hscale * (double)nr.im;
+            const cx<double> nr =
+                staged ? near_cot_staged<R, true>(ns, ns.off[il], ns.off[il + 3],
+                                                  (int32_t)(k - base), 0.0)
+                       : near_cot<R, V, SRC>(a, k, 0.0, leaf, nullptr, 0,
+                                             (const cx<R> *)f_uniform);
+            double hr = (double)h.re + hscale * nr.re;
+            double hi = (double)h.im + hscale * nr.im;
             // f = -(C/2)(W + i h)
             const double C = a.chat[k];
             st_cx<R>(out, k, cx<R>{(R)(-0.5 * C * ((double)W.re - hi)),
@@ -1743,7 +1835,7 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             if (a.hit[k] >= 0) {
                 a.chat_out[k] = 0.0;
             } else {
-                if (!(fabs(lc) <= 700.0))
+                if (!(fabs(lc) <= a.log_max))
                     atomicOr(a.flags_out, FLAG_RANGE);
                 a.chat_out[k] = (((k + neg) & 1) ? -1.0 : 1.0) * exp(lc);
             }
@@ -1763,7 +1855,7 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             // the net count of Omega_1 carried log(2 pi / N) for the point
             // itself, whose log|t| term the near field skips
             const double ld = -((double)far + nr - a.logself);
-            if (!(fabs(ld) <= 700.0))
+            if (!(fabs(ld) <= a.log_max))
                 atomicOr(a.flags_out, FLAG_RANGE);
             const double sg = (((tm + (N - 1 - t)) & 1) ? -1.0 : 1.0) * exp(ld);
             a.dhat_out[t] = {sg * sinpi(th), sg * cospi(th)};

@@ -13,6 +13,8 @@ namespace fn {
 // p = y c_hi into one fma would count the rounding error of y c_hi twice.
 // (Returned by value: outputs through pointers would put the caller's
 // locals in scratch memory around the call.)
+constexpr double HIT_SNAP = 0x1p-100; // grid units
+
 struct GridUnits {
     double n, th;
 };
@@ -29,7 +31,11 @@ __device__ __noinline__ GridUnits grid_units(double y, double c_hi, double c_lo)
 // y -> (m, th): s = y N / (2 pi) in double-double from the double-double
 // constant N/(2 pi) = c_hi + c_lo; m = nearest integer mod N, th = s -
 // nearest integer in [-1/2, 1/2]; the representative in [0, N) uses m = N
-// when m = 0 and th < 0.  Returns false for a non-finite or too large y.
+// when m = 0 and th < 0.  A fraction below HIT_SNAP in magnitude becomes 0:
+// such a point is an exact hit (Eq. p2 then gives g_j = f_m up to a term of
+// order th, far below any tolerance), where 1/th would leave the binary32
+// (and near 1e-308 the binary64) range.  Returns false for a non-finite or
+// too large y.
 __device__ __forceinline__ bool reduce_point(double yy, double c_hi, double c_lo,
                                              int64_t N, double ymax, int64_t *m_out,
                                              double *th_out)
@@ -48,6 +54,8 @@ __device__ __forceinline__ bool reduce_point(double yy, double c_hi, double c_lo
         th += 1.0;
         n -= 1.0;
     }
+    if (fabs(th) < HIT_SNAP)
+        th = 0.0;
     int64_t m = (int64_t)n % N;
     if (m < 0)
         m += N;

@@ -65,3 +65,41 @@ def test_timing_switch_host_only():
     assert lib.nufft_set_timing(0) == fn.FN_OK
     ms = (ctypes.c_float * 3)()
     assert lib.nufft_plan_get_timings(None, ms, None) == fn.FN_EINVAL
+
+
+HOST_OOM_SCRIPT = r"""
+import ctypes, resource, sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import paper_1611_09379_amd as fn
+lib = fn.load_library()
+T = 1 << 24
+Ns = np.full(T, 1000, np.int64)
+Ms = np.full(T, 1000, np.int64)
+ys = np.full(T, 4096, np.uint64)        # non-NULL, never read on the host
+one = (ctypes.c_void_p * 1)(4096)
+vm = [int(l.split()[1]) for l in open("/proc/self/status") if l.startswith("VmSize")][0]
+lim = vm * 1024 + (1 << 30)              # 1 GiB of address space to spare
+resource.setrlimit(resource.RLIMIT_AS, (lim, lim))
+st = lib.nufft_fwd_batched(T, Ns.ctypes.data_as(ctypes.c_void_p),
+                           Ms.ctypes.data_as(ctypes.c_void_p),
+                           ys.ctypes.data_as(ctypes.c_void_p), one, one, 1e-12, 0, None)
+print(st, lib.nufft_last_error().decode())
+"""
+
+
+def test_host_allocation_failure_is_a_status():
+    """A batch of 2^24 transforms needs several GB of host bookkeeping; under
+    an address-space limit its allocation throws inside the library, and the
+    C ABI returns FN_ENOMEM (the exception does not reach the caller)."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, "-c", HOST_OOM_SCRIPT, ROOT], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    st, msg = r.stdout.strip().splitlines()[-1].split(" ", 1)
+    assert int(st) == fn.FN_ENOMEM and "host memory" in msg, r.stdout
+
+
+def test_release_cache_host_only():
+    assert fn.load_library().nufft_release_cache() == fn.FN_OK

@@ -43,6 +43,25 @@ def test_autotune_forward(dtype, eps):
     assert fn.Plan.forward(N, dev(y), eps, dtype).info().lmax == plain.lmax
 
 
+def test_autotune_mixed_skewed():
+    """A depth tuned on the mixed path at N = M is reused for a skewed
+    N >> M of the same size class (round(log2 sqrt(N M)) = 12): the plan
+    still keeps at most 128 sources per leaf and meets 1e-6."""
+    l, p = fn.autotune("fwd", 4096, 4096, 1e-6, fn.FN_C64)
+    N, M = 1 << 16, 1 << 8
+    y, f, c = workloads.forward_case(N, M, "uniform", seed=12)
+    f = f.astype(np.complex64)
+    plan = fn.Plan.forward(N, dev(y), 1e-6, fn.FN_C64)
+    info = plan.info()
+    say("tuned", l, p, "skewed plan depth", info.lmax)
+    assert (N >> info.lmax) <= 128
+    g = host(plan(dev(f)))
+    plan.destroy()
+    err = rel_l2(g, oracle.fwd(N, y, f.astype(np.complex128)))
+    say("skewed rel l2", err)
+    assert err < 1e-6
+
+
 def test_autotune_inverse():
     N = 4096
     y, c = workloads.inverse_case(N, 0.4, seed=9)

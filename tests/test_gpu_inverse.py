@@ -171,3 +171,57 @@ def test_setup_timings():
     pf = fn.Plan.forward(N, yd, 1e-12, fn.FN_C128)
     assert pf.timings()["log_terms"] == 0
     pf.destroy()
+
+
+def test_inv_mixed_range():
+    """A grid compressed into 95% of the circle (N = 1024): log|Dhat_j|
+    reaches about -120 (oracle), beyond what the mixed path's binary32
+    weights Dhat_j g_j hold (and the problem's condition number is about
+    7e15).  FN_C64 reports FN_ERANGE instead of a wrong result; FN_C128
+    (range exp(+-700)) accepts it, with Chat_k and Dhat_j equal to the
+    oracle's log-sums."""
+    N = 1024
+    y = 2 * np.pi * np.arange(N) / N * 0.95 + 1e-3
+    lC, _, lD, _ = oracle.logsums(N, y)
+    assert np.abs(lD).max() > 100 and np.abs(lD).max() < 700
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    with pytest.raises(fn.NufftError) as e:
+        fn.inufft(dev(y), dev(g.astype(np.complex64)), 1e-6)
+    assert e.value.status == fn.FN_ERANGE
+    with pytest.raises(fn.NufftError) as e:
+        fn.Plan.inverse(dev(y), 1e-6, fn.FN_C64)
+    assert e.value.status == fn.FN_ERANGE
+    plan = fn.Plan.inverse(dev(y), 1e-12, fn.FN_C128)
+    chat, dhat = (host(t) for t in plan.coeffs())
+    assert np.all(np.isfinite(host(plan(dev(g)))))
+    plan.destroy()
+    ks = np.arange(1, N, 7)
+    js = np.arange(0, N, 5)
+    rc, rd = oracle.coeffs_at(N, y, ks, js)
+    ec, ed = rel_l2(chat[ks], rc), rel_l2(dhat[js], rd)
+    say(f"compressed grid, binary64 coefficients: Chat {ec:.2e} Dhat {ed:.2e}")
+    assert ec < 1e-12 and ed < 1e-12
+
+
+@pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
+def test_tiny_fractions_are_hits(dtype):
+    """Points within 2^-100 grid units of a grid point (|theta| as small as
+    1e-42 and subnormal) are exact hits: no overflowing reciprocal, and the
+    result matches the oracle's exact sums (which differ from f_m by a term
+    of order theta)."""
+    N, M = 256, 64
+    y, f, c = workloads.forward_case(N, M, "uniform", seed=6)
+    y[:4] = [1e-42, -1e-42, 2 * np.pi * 5 / N, 5e-324]
+    f = f.astype(dtype)
+    eps = 1e-12 if dtype == np.complex128 else 1e-6
+    g = host(fn.nufft_fwd(dev(y), dev(f), eps))
+    assert np.all(np.isfinite(g))
+    ref = oracle.fwd(N, y, f.astype(np.complex128))
+    assert rel_l2(g, ref) < eps
+    yi, ci = workloads.inverse_case(N, 0.3, seed=6)
+    yi[0] = 1e-42
+    gi = (np.random.default_rng(6).standard_normal(N) + 0j).astype(dtype)
+    fi = host(fn.inufft(dev(yi), dev(gi), eps))
+    assert np.all(np.isfinite(fi))
+    assert rel_l2(fi, oracle.inv(N, yi, gi.astype(np.complex128))) < eps

@@ -99,3 +99,56 @@ def test_batched_sweep(seed):
             b.destroy()
         err = max(rel_l2(host(o), r) for o, r in zip(outs, refs))
         assert err < (1e-6 if mixed else 1e-12), (case, T, mixed, err)
+
+
+# Forward cases that missed 1e-6 on the mixed path when its binary32 moment
+# and near-field sums ran over thousands of sources per leaf: (N, M, depth).
+SHALLOW_MIXED = [(163215, 168, 5), (9568, 2, 2), (12857, 40, 3), (127473, 60, 6),
+                 (65536, 16, 2), (40000, 3000, 4)]
+
+
+@pytest.mark.parametrize("N,M,lmax", SHALLOW_MIXED)
+def test_mixed_shallow_depths(N, M, lmax):
+    """Explicit shallow depths on the mixed path (up to ~40 000 sources per
+    leaf) stay within 1e-6 of the oracle on the same binary32 input."""
+    y, f, c = workloads.forward_case(N, M, "uniform", seed=N + M)
+    f = f.astype(np.complex64)
+    plan = fn.Plan.forward(N, dev(y), 1e-6, fn.FN_C64, lmax=lmax)
+    assert plan.info().lmax == lmax
+    g = host(plan(dev(f)))
+    plan.destroy()
+    err = rel_l2(g, oracle.fwd(N, y, f.astype(np.complex128)))
+    say(f"N={N} M={M} lmax={lmax} ({N >> lmax} sources per leaf): {err:.3e}")
+    assert err < 1e-6, (N, M, lmax, err)
+
+
+@pytest.mark.parametrize("seed", [13])
+def test_mixed_depth_sweep(seed):
+    """Mixed path at random explicit depths 2 .. log2 N, including N >> M
+    (few targets, many sources per leaf), forward and inverse."""
+    rng = np.random.default_rng(seed)
+    for case in range(40):
+        N = log_uniform(rng, 64, 60000)
+        M = log_uniform(rng, 1, max(2, 4e6 // N))
+        lmax = int(rng.integers(2, max(3, int(math.log2(N)) + 1)))
+        dist = "clustered" if rng.random() < 0.3 else "uniform"
+        y, f, c = workloads.forward_case(N, M, dist, seed=int(rng.integers(1 << 30)))
+        f = f.astype(np.complex64)
+        say(f"case {case}: N={N} M={M} {dist} lmax={lmax}")
+        plan = fn.Plan.forward(N, dev(y), 1e-6, fn.FN_C64, lmax=lmax)
+        g = host(plan(dev(f)))
+        plan.destroy()
+        err = rel_l2(g, oracle.fwd(N, y, f.astype(np.complex128)))
+        assert err < 1e-6, (case, N, M, dist, lmax, err)
+    for case in range(12):
+        N = log_uniform(rng, 64, 3000)
+        lmax = int(rng.integers(2, max(3, int(math.log2(N)))))
+        y, c = workloads.inverse_case(N, float(rng.uniform(0.1, 0.4)),
+                                      seed=int(rng.integers(1 << 30)))
+        g = workloads.samples_from_coefficients(c).astype(np.complex64)
+        say(f"inverse case {case}: N={N} lmax={lmax}")
+        plan = fn.Plan.inverse(dev(y), 1e-6, fn.FN_C64, lmax=lmax)
+        f = host(plan(dev(g)))
+        plan.destroy()
+        err = rel_l2(f, oracle.inv(N, y, g.astype(np.complex128)))
+        assert err < 1e-6, (case, N, lmax, err)
