@@ -262,6 +262,25 @@ int nufft_autotune(int kind, int64_t N, int64_t M, double eps, int dtype, int32_
 /* Forgets every recorded choice of nufft_autotune. */
 int nufft_autotune_clear(void);
 
+/* ---- Allocation-free forward call -------------------------------------
+ *
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): nufft_fwd_noalloc computes exactly what
+ * nufft_fwd computes (same arguments, same kernels and parameters, one
+ * synchronisation at the end) but calls no hipMalloc, hipFree or
+ * hipHostMalloc.  Every workspace comes from a static device array of
+ * 96 MiB (98 304 KiB) that the library holds on each device it runs on
+ * until the process ends; operator tables that no earlier call has built
+ * are built into it as well.  That holds the binary64 or mixed forward up
+ * to N = M = 2^20; sizes whose workspace does not fit return FN_EINVAL
+ * before any kernel is enqueued (nufft_fwd has no such limit).  The array
+ * is shared by every call on one device and keeps the last call's
+ * contents: calls that overlap in time on one device (two host threads, or
+ * two streams that do not wait for each other) race and must not be made.
+ * The flags of the setup are read back through pageable host memory. */
+int nufft_fwd_noalloc(int64_t N, int64_t M, const double *y, const void *f, void *g,
+                      double eps, int dtype, void *stream);
+
 /* ---- Device memory ----------------------------------------------------
  *
  * Plan and batch workspaces come from a cache of device blocks: a released

@@ -35,7 +35,7 @@ ABI_SYMBOLS = (
     "nufft_fwd_batched", "nufft_plan_fwd_batched", "nufft_execute_batched",
     "nufft_destroy_batched", "nufft_autotune", "nufft_autotune_clear",
     "nufft_set_timing", "nufft_plan_get_timings",
-    "nufft_release_cache", "nufft_last_error",
+    "nufft_fwd_noalloc", "nufft_release_cache", "nufft_last_error",
 )
 
 
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
         "nufft_autotune_clear": [],
         "nufft_set_timing": [ctypes.c_int],
         "nufft_plan_get_timings": [vp, ctypes.POINTER(ctypes.c_float), pi32],
+        "nufft_fwd_noalloc": [i64, i64, vp, vp, vp, dbl, ctypes.c_int, vp],
         "nufft_release_cache": [],
         "nufft_last_error": [],
     }

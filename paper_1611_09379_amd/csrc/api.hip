@@ -160,9 +160,18 @@ struct Buf {
 
 // Bump allocation from large pooled chunks, for the many small workspaces
 // of a batch of transforms; the chunks go back to the pool with the batch.
+// A fixed arena (the allocation-free entry point) carves one given region
+// and never grows: a request beyond it fails and sets `overflow`.
 struct Arena {
     std::vector<Buf> chunks;
-    size_t used = 0; // bytes used in the last chunk
+    size_t used = 0; // bytes used in the last chunk (or the fixed region)
+    unsigned char *fixed = nullptr;
+    size_t fixed_cap = 0;
+    bool overflow = false;
+    // operator tables built into the fixed region by this call (key, where)
+    long tab_key = -1;
+    void *tab_base = nullptr;
+    size_t tab_off[7] = {0};
 };
 thread_local Arena *g_arena = nullptr;
 constexpr size_t ARENA_CHUNK = size_t(64) << 20;
@@ -170,6 +179,15 @@ constexpr size_t ARENA_CHUNK = size_t(64) << 20;
 void *arena_get(Arena &A, size_t bytes)
 {
     bytes = round_bytes(bytes ? bytes : 1);
+    if (A.fixed) {
+        if (bytes > A.fixed_cap - A.used) {
+            A.overflow = true;
+            return nullptr;
+        }
+        void *p = A.fixed + A.used;
+        A.used += bytes;
+        return p;
+    }
     if (A.chunks.empty() || A.used + bytes > A.chunks.back().n) {
         Buf c;
         c.n = std::max(ARENA_CHUNK, bytes);
@@ -382,6 +400,40 @@ static int get_tables(int kernel, int PU, int PD, int q, OpTables<R> *out)
     const auto key = std::make_tuple((int)sizeof(R), kernel, PU, PD, q, dev);
     std::lock_guard<std::mutex> lk(g_tab_mu);
     auto it = g_tab_cache.find(key);
+    if (it == g_tab_cache.end() && g_arena && g_arena->fixed) {
+        // allocation-free call: tables not built yet by another call go
+        // into the call's own region (built again by the next such call)
+        Arena &A = *g_arena;
+        const long fkey = (((long)sizeof(R) * 2 + kernel) * 65 + PU) * 65 * 31 + PD * 31 + q;
+        if (A.tab_key == fkey) {
+            const R *b = (const R *)A.tab_base;
+            *out = {b + A.tab_off[0], b + A.tab_off[1], b + A.tab_off[2], b + A.tab_off[3],
+                    b + A.tab_off[4], b + A.tab_off[5], b + A.tab_off[6]};
+            return FN_OK;
+        }
+        Tables T;
+        build_tables(PU, PD, q, kernel, T);
+        std::vector<R> h;
+        size_t off[7];
+        const std::vector<long double> *parts[7] = {&T.m2m, &T.l2l, &T.m2l4, &T.m2l6,
+                                                    &T.bin, &T.reg1, &T.reg2};
+        for (int i = 0; i < 7; ++i) {
+            off[i] = h.size();
+            for (long double x : *parts[i])
+                h.push_back((R)x);
+        }
+        R *b = (R *)arena_get(A, h.size() * sizeof(R));
+        if (!b)
+            return fail(FN_ENOMEM, "no room for the operator tables");
+        HIPCHK(hipMemcpy(b, h.data(), h.size() * sizeof(R), hipMemcpyHostToDevice));
+        A.tab_key = fkey;
+        A.tab_base = b;
+        for (int i = 0; i < 7; ++i)
+            A.tab_off[i] = off[i];
+        *out = {b + off[0], b + off[1], b + off[2], b + off[3], b + off[4], b + off[5],
+                b + off[6]};
+        return FN_OK;
+    }
     if (it == g_tab_cache.end()) {
         Tables T;
         build_tables(PU, PD, q, kernel, T);
@@ -970,6 +1022,9 @@ static int prepare_work(fn_plan *P, int sh, bool uniform, int64_t npts, WorkArgs
 // the thread may reuse the memory).
 static void *pinned_scratch(size_t bytes, int slot = 0)
 {
+    if (g_arena && g_arena->fixed)
+        return nullptr; // allocation-free call: pageable read-back
+
     static thread_local void *buf[2] = {nullptr, nullptr};
     static thread_local size_t cap[2] = {0, 0};
     if (bytes > cap[slot]) {
@@ -1053,11 +1108,9 @@ static int plan_fwd_impl(fn_plan *P, const double *y, hipStream_t st)
     P->lr = choose_lr(P->l, 2, PD, sizeof(R));
     // targets grouped by leaf: the lanes of a wavefront then share the
     // leaf locals and near-field sources they read
+    // every workspace is allocated before the first launch (the sort)
     WorkArgs w;
     int rc = prepare_work(P, P->l - P->lr, false, P->M, &w);
-    if (rc)
-        return rc;
-    rc = build_tree(P, P->M, y, 0, false, false, true, st, &w);
     if (rc)
         return rc;
     rc = setup_fmm<R, cx<R>>(P, KER_COT, PU, PD, P->q, false, P->cot, st);
@@ -1067,7 +1120,7 @@ static int plan_fwd_impl(fn_plan *P, const double *y, hipStream_t st)
     rc = get_tables<R>(KER_COT, PU, PD, P->q, &T);
     if (rc)
         return rc;
-    return FN_OK;
+    return build_tree(P, P->M, y, 0, false, false, true, st, &w);
 }
 
 template <typename R>
@@ -2054,6 +2107,42 @@ static int autotune(int kind, int64_t N, int64_t M, double eps, int dtype, int32
     return FN_OK;
 }
 
+// ---------------------------------------- the allocation-free forward call
+//
+// nufft_fwd_noalloc takes every workspace (sorted targets, histograms, work
+// list, multipoles, leaf locals, and operator tables not yet built by
+// another call) from one static device array instead of the block cache.
+// Each device holds its own copy at its own address, found once per device
+// with hipGetSymbolAddress; host code never passes the array's name itself
+// to a kernel or a copy.
+
+static constexpr size_t SCRATCH_BYTES = size_t(96) << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+static constexpr int SCRATCH_MAX_DEV = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[SCRATCH_MAX_DEV];
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device).
+static int scratch_region(void **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEV)
+        return fail(FN_EINVAL, "device %d beyond the %d the static scratch serves", dev,
+                    SCRATCH_MAX_DEV);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(FN_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FN_OK;
+}
+
 extern "C" {
 
 int nufft_plan_fwd_ex(fn_plan **plan, int64_t N, int64_t M, const double *y,
@@ -2348,6 +2437,48 @@ int nufft_autotune_clear(void)
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned.clear();
     return FN_OK;
+    FN_API_END
+}
+
+int nufft_fwd_noalloc(int64_t N, int64_t M, const double *y, const void *f, void *g,
+                      double eps, int dtype, void *stream)
+{
+    FN_API_BEGIN
+    if (!f || !g)
+        return fail(FN_EINVAL, "f or g is NULL");
+    int rc = check_common(N, M, eps, dtype);
+    if (rc)
+        return rc;
+    void *base = nullptr;
+    rc = scratch_region(&base);
+    if (rc)
+        return rc;
+    Arena A;
+    A.fixed = (unsigned char *)base;
+    A.fixed_cap = SCRATCH_BYTES;
+    struct Scope { // the call's allocations come from the fixed region
+        Arena *prev;
+        explicit Scope(Arena *a) : prev(g_arena) { g_arena = a; }
+        ~Scope() { g_arena = prev; }
+    } scope(&A);
+    fn_plan *P = nullptr;
+    rc = plan_common(&P, 0, N, M, y, eps, dtype, 0, 0, 0, stream, true);
+    if (rc) {
+        if (A.overflow)
+            return fail(FN_EINVAL, "N = %lld, M = %lld need more workspace than the %zu "
+                                   "bytes of the static scratch region (nufft_fwd has no "
+                                   "such limit)",
+                        (long long)N, (long long)M, SCRATCH_BYTES);
+        return rc;
+    }
+    try {
+        return finish_one_shot(P, execute(P, f, g, -1, stream));
+    } catch (...) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        release_plan(P);
+        delete P;
+        throw;
+    }
     FN_API_END
 }
 
