@@ -86,7 +86,7 @@ typedef struct fn_plan fn_plan;
 /* Parameters a plan uses (for reporting and tests). */
 typedef struct {
     int64_t N, M;
-    int32_t kind;  /* 0 forward, 1 inverse                                */
+    int32_t kind;  /* 0 forward, 1 inverse, 2 adjoint                     */
     int32_t dtype; /* fn_dtype                                            */
     int32_t p;     /* truncation number of the 1/t MLFMM from Eq. (18.2)
                       (or as given)                                      */
@@ -113,6 +113,22 @@ int nufft_fwd(int64_t N, int64_t M, const double *y, const void *f, void *g,
 int inufft(int64_t N, const double *y, const void *g, void *f, double eps,
            int dtype, void *stream);
 
+/* Adjoint of the forward transform: f = K^H g, i.e.
+ *     f_k = sum_j conj(K_jk) g_j,  k = 0..N-1,  K of Eq. (p2).
+ * Since conj(G(t)) = G(-t), conj(K_jk) = conj(F_j) G(x_k - y_j): the
+ * cot-kernel FMM with the roles of the grid and the points swapped, the
+ * same evaluation the inverse uses (Section 2), with weights conj(F_j) g_j
+ * and without its C_k factor.  It is the type-1 (nonuniform to uniform)
+ * direction; with the forward it gives the normal equations of a
+ * least-squares fit for M != N.  y: M doubles (any points; coincident
+ * points are allowed); g: M complex; f: N complex (written).  A point on a
+ * grid point x_m (theta_j = 0) contributes g_j to f_m alone.  One-shot like
+ * nufft_fwd: one synchronisation, at the end.  The summation order inside
+ * a leaf follows the sort's placement, which can differ from run to run;
+ * results then differ in the last bits only. */
+int nufft_adj(int64_t N, int64_t M, const double *y, const void *g, void *f,
+              double eps, int dtype, void *stream);
+
 /* Setup step of Section 3.3 ("setting the data structure"): everything that
  * depends on the points only.  Forward plan: reduction of y to grid units
  * and the sort of the targets into the leaves of the tree.  Inverse plan:
@@ -123,11 +139,14 @@ int nufft_plan_fwd(fn_plan **plan, int64_t N, int64_t M, const double *y,
                    double eps, int dtype, void *stream);
 int nufft_plan_inv(fn_plan **plan, int64_t N, const double *y, double eps,
                    int dtype, void *stream);
+/* Adjoint plan (the sort of the M points y into the leaves). */
+int nufft_plan_adj(fn_plan **plan, int64_t N, int64_t M, const double *y,
+                   double eps, int dtype, void *stream);
 
-/* Evaluation step of Section 3.3: out = K in (forward plan) or out = L in
- * (inverse plan).  in/out sizes: forward N -> M, inverse N -> N, complex of
- * the plan's dtype.  Enqueues kernels only: no allocation, no
- * synchronisation. */
+/* Evaluation step of Section 3.3: out = K in (forward plan), out = L in
+ * (inverse plan) or out = K^H in (adjoint plan).  in/out sizes: forward
+ * N -> M, inverse N -> N, adjoint M -> N, complex of the plan's dtype.
+ * Enqueues kernels only: no allocation, no synchronisation. */
 int nufft_execute(fn_plan *plan, const void *in, void *out, void *stream);
 
 /* One part of nufft_execute: phase 0 is the upward pass (P2M at the leaves,
@@ -197,6 +216,9 @@ int nufft_plan_fwd_ex(fn_plan **plan, int64_t N, int64_t M, const double *y,
 int nufft_plan_inv_ex(fn_plan **plan, int64_t N, const double *y, double eps,
                       int dtype, int32_t p, int32_t q, int32_t lmax,
                       void *stream);
+int nufft_plan_adj_ex(fn_plan **plan, int64_t N, int64_t M, const double *y,
+                      double eps, int dtype, int32_t p, int32_t q, int32_t lmax,
+                      void *stream);
 
 /* ---- Batches of independent forward transforms (problem i) ----------
  *
@@ -239,9 +261,10 @@ int nufft_destroy_batched(fn_batch *batch);
 
 /* ---- Autotuner --------------------------------------------------------
  *
- * Measures transforms of kind (0 forward, 1 inverse; M is ignored for the
- * inverse) and sizes N, M at accuracy eps on a synthetic problem of that
- * size (uniform targets, or a jittered grid for the inverse), generated on
+ * Measures transforms of kind (0 forward, 1 inverse, 2 adjoint; M is
+ * ignored for the inverse) and sizes N, M at accuracy eps on a synthetic
+ * problem of that size (uniform points, or a jittered grid for the
+ * inverse), generated on
  * the device: first the shortest local expansion (16, 32 or 48 terms) whose
  * result stays within eps/4 of the 64-term result, then the fastest tree
  * depth among round(log2 sqrt(N M)) - 4 .. - 7 for one-shot calls (small

@@ -8,6 +8,7 @@ missing, importing the binding's functions raises: there is no fallback.
 
     g = nufft_fwd(y, f, eps)        # forward, Eq. (p2): g_j = f(y_j)
     f = inufft(y, g, eps)           # inverse, Eq. (p6), M = N
+    f = nufft_adj(y, g, N, eps)     # adjoint of Eq. (p2): f = K^H g
     plan = Plan.forward(N, y, eps)  # setup once per point set (Section 3.3)
     g = plan(f)                     # evaluation, repeated per input
     gs = nufft_fwd_batched(ys, fs, eps)   # many forward transforms at once
@@ -27,8 +28,9 @@ STATUS_NAMES = {0: "FN_OK", 1: "FN_EINVAL", 2: "FN_ENOMEM", 3: "FN_EHIP",
                 4: "FN_ESINGULAR", 5: "FN_ERANGE", 6: "FN_EPREC"}
 
 ABI_SYMBOLS = (
-    "nufft_fwd", "inufft", "nufft_plan_fwd", "nufft_plan_inv",
-    "nufft_plan_fwd_ex", "nufft_plan_inv_ex", "nufft_execute",
+    "nufft_fwd", "inufft", "nufft_adj", "nufft_plan_fwd", "nufft_plan_inv",
+    "nufft_plan_adj", "nufft_plan_fwd_ex", "nufft_plan_inv_ex",
+    "nufft_plan_adj_ex", "nufft_execute",
     "nufft_execute_phase",
     "nufft_destroy", "nufft_plan_get_info", "nufft_plan_coeffs",
     "nufft_select_params",
@@ -77,6 +79,9 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "nufft_fwd": [i64, i64, vp, vp, vp, dbl, ctypes.c_int, vp],
         "inufft": [i64, vp, vp, vp, dbl, ctypes.c_int, vp],
+        "nufft_adj": [i64, i64, vp, vp, vp, dbl, ctypes.c_int, vp],
+        "nufft_plan_adj": [pp, i64, i64, vp, dbl, ctypes.c_int, vp],
+        "nufft_plan_adj_ex": [pp, i64, i64, vp, dbl, ctypes.c_int, i32, i32, i32, vp],
         "nufft_plan_fwd": [pp, i64, i64, vp, dbl, ctypes.c_int, vp],
         "nufft_plan_inv": [pp, i64, vp, dbl, ctypes.c_int, vp],
         "nufft_plan_fwd_ex": [pp, i64, i64, vp, dbl, ctypes.c_int, i32, i32, i32, vp],
@@ -181,6 +186,17 @@ class Plan:
             _stream()))
         return cls(h, 1, N, N, dtype)
 
+    @classmethod
+    def adjoint(cls, N: int, y, eps: float, dtype: int = FN_C128, p: int = 0,
+                q: int = 0, lmax: int = 0):
+        """Adjoint plan: f = K^H g (M points y -> N grid values)."""
+        _check_y(y)
+        h = ctypes.c_void_p()
+        _check(load_library().nufft_plan_adj_ex(
+            ctypes.byref(h), N, y.shape[0], _dev_ptr(y, "y"), eps, dtype, p, q, lmax,
+            _stream()))
+        return cls(h, 2, N, y.shape[0], dtype)
+
     def info(self) -> PlanInfo:
         out = PlanInfo()
         _check(load_library().nufft_plan_get_info(self._h, ctypes.byref(out)))
@@ -212,7 +228,7 @@ class Plan:
             raise RuntimeError("plan was destroyed")
         if _dtype_code(x) != self.dtype:
             raise TypeError("input dtype does not match the plan")
-        n_in = self.N
+        n_in = self.M if self.kind == 2 else self.N
         n_out = self.M if self.kind == 0 else self.N
         if x.shape != (n_in,):
             raise ValueError(f"input must have shape ({n_in},)")
@@ -271,6 +287,22 @@ def inufft(y, g, eps: float, out=None):
         out = torch.empty(N, dtype=g.dtype, device=g.device)
     _check(load_library().inufft(N, _dev_ptr(y, "y"), _dev_ptr(g, "g"),
                                  _dev_ptr(out, "f"), eps, dt, _stream()))
+    return out
+
+
+def nufft_adj(y, g, N: int, eps: float, out=None):
+    """f_k = sum_j conj(K_jk) g_j (the adjoint of Eq. p2), k = 0..N-1, one
+    shot."""
+    torch = _torch()
+    _check_y(y)
+    dt = _dtype_code(g)
+    M = y.shape[0]
+    if g.shape != (M,):
+        raise ValueError("g must have the shape of y")
+    if out is None:
+        out = torch.empty(N, dtype=g.dtype, device=g.device)
+    _check(load_library().nufft_adj(N, M, _dev_ptr(y, "y"), _dev_ptr(g, "g"),
+                                    _dev_ptr(out, "f"), eps, dt, _stream()))
     return out
 
 
@@ -360,12 +392,12 @@ class Batch:
 
 
 def autotune(kind: str, N: int, M: int, eps: float, dtype: int = FN_C128):
-    """Runs the library's autotuner for forward ("fwd") or inverse ("inv")
-    transforms of sizes N, M; later plans of that size class use its
+    """Runs the library's autotuner for forward ("fwd"), inverse ("inv") or
+    adjoint ("adj") transforms of sizes N, M; later plans of that size class use its
     choice.  Returns (lmax, nterms) (nterms 0: default length kept)."""
     l = ctypes.c_int32()
     p = ctypes.c_int32()
-    _check(load_library().nufft_autotune(0 if kind == "fwd" else 1, N, M, eps, dtype,
+    _check(load_library().nufft_autotune({"fwd": 0, "inv": 1, "adj": 2}[kind], N, M, eps, dtype,
                                          ctypes.byref(l), ctypes.byref(p), _stream()))
     return l.value, p.value
 

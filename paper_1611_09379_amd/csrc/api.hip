@@ -223,7 +223,8 @@ static int paper_depth(int64_t N, int64_t M)
     return std::min(24, std::max(2, (int)std::lround(lg) - 5));
 }
 
-// Depth of a plan (kind 0 forward, 1 inverse): lg minus a leaf offset
+// Depth of a plan (kind 0 forward, 1 inverse, 2 adjoint, whose sources are
+// the M points and whose tree is the inverse's): lg minus a leaf offset
 // measured on MI355X for one-shot transforms (binary64 and mixed agree).
 // Forward: 4 below lg = 14, 5 up to lg = 17, then 6 (leaves of about 64
 // targets: its near field runs on staged uniform sources and is cheap next
@@ -252,7 +253,7 @@ static int default_depth(int64_t N, int64_t M, int kind, int dtype)
     if (const char *e = getenv("FN_LEAF_OFFSET"))
         off = atoi(e);
     const int l = std::min(24, std::max(2, r - off));
-    return std::max(l, mixed_min_depth(N, dtype));
+    return std::max(l, mixed_min_depth(kind == 2 ? M : N, dtype));
 }
 
 // Largest |log|Chat_k|| and |log|Dhat_j|| an inverse plan accepts on the
@@ -481,14 +482,14 @@ struct FmmSetup {
 };
 
 struct fn_plan {
-    int kind = 0, dtype = 0;
+    int kind = 0, dtype = 0; // kind 0 forward, 1 inverse, 2 adjoint
     int64_t N = 0, M = 0;
     int p = 0, q = 0, l = 0;
     bool p_explicit = false;
     double eps = 0;
     int lr = 2; // subtree root level of k_down_eval
     // points sorted into the leaves (targets of the forward, sources of the
-    // inverse)
+    // inverse and of the adjoint)
     Buf off, sm, sth, sperm, skey;
     Buf spt; // forward: sorted target records (instead of sm, sth, sperm, skey)
     Buf work, nwork_dev;
@@ -675,7 +676,8 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_
             bytes = std::max(bytes, (size_t)nbot *
                                         uni_stage_stride(uniform_leaf_pts(P), es) * es);
         } else if (b == 0 && (sorted_src || uni_staged)) {
-            const int64_t mean = (P->N + (int64_t(1) << P->l) - 1) >> P->l;
+            const int64_t nsrc = P->kind == 2 ? P->M : P->N; // the adjoint's are y
+            const int64_t mean = (nsrc + (int64_t(1) << P->l) - 1) >> P->l;
             // coordinate, its fourth power, and (cot) the complex weight
             const size_t per = es * (kernel == KER_COT ? 4 : 2);
             const size_t room = lim > F.band[0].smem + 4 * (size_t)(nbot + 1) + 64
@@ -1304,6 +1306,81 @@ static int exec_inv(fn_plan *P, const void *in, void *out, int phase,
     return launch_down<R, V, KER_COT, SET_SORTED, EPI_INV>(P, F, da, st, phase);
 }
 
+// --------------------------------------------------------- adjoint plan
+//
+// f_k = sum_j conj(K_jk) g_j (k = 0..N-1, j = 0..M-1), the adjoint of
+// Eq. (p2).  conj(K_jk) = conj(F_j) G(x_k - y_j), since conj(G(t)) = G(-t):
+// the cot FMM of the inverse (Section 2, roles of x and y swapped) with
+// weights conj(F_j) g_j and no C_k factor, f_k = -(W + i h_k) / 2.  The M
+// points are sorted into the leaves like the inverse's sources, without the
+// inverse's ranking (no signs are needed, and coincident points are
+// allowed).
+
+template <typename R>
+static int plan_adj_impl(fn_plan *P, const double *y, hipStream_t st)
+{
+    int PU, PD;
+    cot_lengths(P, &PU, &PD);
+    P->lr = choose_lr(P->l, 2, PD, sizeof(R));
+    // every workspace is allocated before the first launch (the sort)
+    WorkArgs w;
+    int rc = prepare_work(P, P->l - P->lr, true, P->N, &w);
+    if (rc)
+        return rc;
+    rc = setup_fmm<R, cx<R>>(P, KER_COT, PU, PD, P->q, true, P->cot, st);
+    if (rc)
+        return rc;
+    if (!alloc(P->wsorted, P->M * 2 * sizeof(R)))
+        return fail(FN_ENOMEM, "adjoint weight allocation failed");
+    OpTables<R> T;
+    rc = get_tables<R>(KER_COT, PU, PD, P->q, &T);
+    if (rc)
+        return rc;
+    return build_tree(P, P->M, y, 0, false, false, false, st, &w);
+}
+
+template <typename R>
+static int exec_adj(fn_plan *P, const void *in, void *out, int phase, hipStream_t st)
+{
+    using V = cx<R>;
+    const FmmSetup &F = P->cot;
+    OpTables<R> T;
+    int rc = get_tables<R>(KER_COT, F.PU, F.PD, F.q, &T);
+    if (rc)
+        return rc;
+    const SortedSet src = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
+                           (const double *)P->sth.p, (const int32_t *)P->sperm.p};
+    if (phase <= 0) {
+        UpArgs<R, V> ua{};
+        fill_up(P, F, T, ua);
+        ua.src = src;
+        ua.leaf_pts = 0;
+        ua.w_sorted = (const cx<R> *)P->wsorted.p;
+        hipLaunchKernelGGL((k_adj_weights<R>), dim3(grid_for(P->M)), dim3(256), 0, st, P->M,
+                           P->N, (const double *)P->sth.p, (const int32_t *)P->sperm.p,
+                           (const cx<R> *)in, (cx<R> *)P->wsorted.p);
+        HIPCHK(hipGetLastError());
+        rc = launch_up<R, V, KER_COT, SET_SORTED>(F, ua, st);
+        if (rc)
+            return rc;
+    }
+    if (phase == 0)
+        return FN_OK;
+    DownArgs<R, V> da{};
+    fill_down(P, F, T, da);
+    da.src = src;
+    da.w_sorted = (const cx<R> *)P->wsorted.p;
+    da.out = (cx<R> *)out;
+    rc = launch_down<R, V, KER_COT, SET_SORTED, EPI_ADJ>(P, F, da, st, phase);
+    if (rc || phase == 1)
+        return rc;
+    hipLaunchKernelGGL((k_adj_hits<R>), dim3(grid_for(P->M)), dim3(256), 0, st, P->M,
+                       (const int32_t *)P->sm.p, (const double *)P->sth.p,
+                       (const int32_t *)P->sperm.p, (const cx<R> *)in, (cx<R> *)out);
+    HIPCHK(hipGetLastError());
+    return FN_OK;
+}
+
 // ------------------------------------------------------------------ ABI
 
 static int check_common(int64_t N, int64_t M, double eps, int dtype)
@@ -1357,7 +1434,7 @@ static void choose(int64_t N, int64_t M, double eps, int kind, int dtype, int32_
     // N and M can be skewed within the class, so the mixed path's leaf
     // bound applies to it again
     *l = l_in > 0 ? l_in
-                  : (tl > 0 ? std::max(tl, mixed_min_depth(N, dtype))
+                  : (tl > 0 ? std::max(tl, mixed_min_depth(kind == 2 ? M : N, dtype))
                             : (kind < 0 ? paper_depth(N, M) : default_depth(N, M, kind, dtype)));
     int pp, qq;
     trunc_numbers(eps, *l, &pp, &qq);
@@ -1433,9 +1510,12 @@ static int plan_body(fn_plan *P, int kind, int64_t N, int64_t M, const double *y
     if (kind == 0)
         rc = dtype == FN_C128 ? plan_fwd_impl<double>(P, y, st)
                               : plan_fwd_impl<float>(P, y, st);
-    else
+    else if (kind == 1)
         rc = dtype == FN_C128 ? plan_inv_impl<double>(P, y, st)
                               : plan_inv_impl<float>(P, y, st);
+    else
+        rc = dtype == FN_C128 ? plan_adj_impl<double>(P, y, st)
+                              : plan_adj_impl<float>(P, y, st);
     if (!rc && !defer)
         rc = finish_plan(P, st);
     if (rc) {
@@ -1988,15 +2068,15 @@ static int tune_err(int64_t n, const void *a, const void *b, int dtype, Buf &par
 static int autotune(int kind, int64_t N, int64_t M, double eps, int dtype, int32_t *l_out,
                     int32_t *p_out, hipStream_t st)
 {
-    if (kind != 0 && kind != 1)
-        return fail(FN_EINVAL, "kind must be 0 (forward) or 1 (inverse)");
+    if (kind < 0 || kind > 2)
+        return fail(FN_EINVAL, "kind must be 0 (forward), 1 (inverse) or 2 (adjoint)");
     if (kind == 1)
         M = N;
     int rc = check_common(N, M, eps, dtype);
     if (rc)
         return rc;
     const size_t es = dtype == FN_C128 ? 16 : 8;
-    const int64_t nin = N, nout = kind == 0 ? M : N;
+    const int64_t nin = kind == 2 ? M : N, nout = kind == 0 ? M : N;
     Buf y, in, out, ref, part;
     auto cleanup = [&]() {
         (void)hipStreamSynchronize(st);
@@ -2170,6 +2250,44 @@ int nufft_plan_fwd(fn_plan **plan, int64_t N, int64_t M, const double *y,
     FN_API_END
 }
 
+int nufft_plan_adj_ex(fn_plan **plan, int64_t N, int64_t M, const double *y,
+                      double eps, int dtype, int32_t p, int32_t q, int32_t lmax,
+                      void *stream)
+{
+    FN_API_BEGIN
+    return plan_common(plan, 2, N, M, y, eps, dtype, p, q, lmax, stream);
+    FN_API_END
+}
+
+int nufft_plan_adj(fn_plan **plan, int64_t N, int64_t M, const double *y,
+                   double eps, int dtype, void *stream)
+{
+    FN_API_BEGIN
+    return plan_common(plan, 2, N, M, y, eps, dtype, 0, 0, 0, stream);
+    FN_API_END
+}
+
+int nufft_adj(int64_t N, int64_t M, const double *y, const void *g, void *f,
+              double eps, int dtype, void *stream)
+{
+    FN_API_BEGIN
+    if (!f || !g)
+        return fail(FN_EINVAL, "f or g is NULL");
+    fn_plan *P = nullptr;
+    int rc = plan_common(&P, 2, N, M, y, eps, dtype, 0, 0, 0, stream, true);
+    if (rc)
+        return rc;
+    try {
+        return finish_one_shot(P, execute(P, g, f, -1, stream));
+    } catch (...) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        release_plan(P);
+        delete P;
+        throw;
+    }
+    FN_API_END
+}
+
 int nufft_plan_inv(fn_plan **plan, int64_t N, const double *y, double eps,
                    int dtype, void *stream)
 {
@@ -2190,6 +2308,9 @@ static int execute(fn_plan *plan, const void *in, void *out, int phase,
     if (plan->kind == 0)
         return plan->dtype == FN_C128 ? exec_fwd<double>(plan, in, out, phase, st)
                                       : exec_fwd<float>(plan, in, out, phase, st);
+    if (plan->kind == 2)
+        return plan->dtype == FN_C128 ? exec_adj<double>(plan, in, out, phase, st)
+                                      : exec_adj<float>(plan, in, out, phase, st);
     return plan->dtype == FN_C128 ? exec_inv<double>(plan, in, out, phase, st)
                                   : exec_inv<float>(plan, in, out, phase, st);
 }

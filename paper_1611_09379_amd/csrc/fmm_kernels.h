@@ -37,7 +37,7 @@ namespace fn {
 
 enum { KER_COT = 0, KER_LOG = 1 };
 enum { SET_UNIFORM = 0, SET_SORTED = 1 };
-enum { EPI_FWD = 0, EPI_INV = 1, EPI_LOGCD = 2 };
+enum { EPI_FWD = 0, EPI_INV = 1, EPI_LOGCD = 2, EPI_ADJ = 3 };
 
 constexpr int BLOCK = 256; // 4 wavefronts of 64
 
@@ -222,6 +222,40 @@ __global__ void k_weights(int64_t n, const cx<double> *dhat, const int32_t *perm
         w[t] = {(R)(d.re * (double)x.re - d.im * (double)x.im),
                 (R)(d.re * (double)x.im + d.im * (double)x.re)};
     }
+}
+
+// Adjoint weights in sorted order: w_t = conj(F_t) g_perm(t), with
+// F = (e^{i N y} - 1) / N = 2i sin(pi th) e^{i pi th} / N (Eq. p4-p5), so
+// conj(F) = -(2 / N) sin(pi th) (sin(pi th) + i cos(pi th)).
+template <typename R>
+__global__ void k_adj_weights(int64_t n, int64_t N, const double *sth, const int32_t *perm,
+                              const cx<R> *g, cx<R> *w)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n)
+        return;
+    const double th = sth[t];
+    const double sp = sinpi(th), cp = cospi(th);
+    const double a = -2.0 * sp / (double)N;
+    const double Fr = a * sp, Fi = a * cp; // conj(F)
+    const cx<R> gv = g[perm[t]];
+    w[t] = {(R)(Fr * (double)gv.re - Fi * (double)gv.im),
+            (R)(Fr * (double)gv.im + Fi * (double)gv.re)};
+}
+
+// Adjoint, sources on grid points: conj(K_jk) = delta(k, m_j), so f_m gets
+// g_j (after the evaluation wrote f; several sources may share a point).
+template <typename R>
+__global__ void k_adj_hits(int64_t n, const int32_t *sm, const double *sth,
+                           const int32_t *perm, const cx<R> *g, cx<R> *f)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n || sth[t] != 0.0)
+        return;
+    const cx<R> gv = g[perm[t]];
+    R *fp = reinterpret_cast<R *>(f + sm[t]);
+    atomicAdd(fp, gv.re);
+    atomicAdd(fp + 1, gv.im);
 }
 
 constexpr int CHS = 4; // moments per thread in the vector P2M
@@ -1161,6 +1195,8 @@ __device__ __forceinline__ cx<double> near_cot(const DownArgs<R, V> &a, int64_t 
             const int32_t t0 = a.src.off[b], t1 = a.src.off[b + 1];
             for (int32_t t = t0; t < t1; ++t) {
                 const double dd = grid_diff(tm - a.src.m[t] - shift, tth, a.src.th[t]);
+                if (dd == 0.0)
+                    continue; // a source on this grid point (weight 0, adjoint)
                 const R rd = recip((R)dd);
                 const cx<R> w = a.w_sorted[t];
                 tot.re = fma((double)w.re, (double)rd, tot.re);
@@ -1650,7 +1686,8 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
         const int32_t oM = a.src.off[leaf0], cM = a.src.off[leaf0 + nb] - oM;
         const int32_t oR = a.src.off[br], cR = a.src.off[br + 1] - oR;
         const int32_t total = cL + cM + cR;
-        constexpr int wb = EPI == EPI_INV ? (int)sizeof(cx<R>) : 0;
+        constexpr bool WS = EPI == EPI_INV || EPI == EPI_ADJ; // weights staged
+        constexpr int wb = WS ? (int)sizeof(cx<R>) : 0;
         constexpr int mb = (int)sizeof(typename NearStage<R>::MT);
         const int32_t cap = ((a.near_bytes - 4 * (nb + 4)) / (8 + mb + wb)) & ~1;
         base = uni_start(leaf0, a.l, N);
@@ -1675,7 +1712,7 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
                                              : (i < cL + cM ? oM + (i - cL) : oR + (i - cL - cM));
                     mv[k] = a.src.m[t];
                     tv[k] = a.src.th[t];
-                    if constexpr (EPI == EPI_INV)
+                    if constexpr (WS)
                         wv[k] = a.w_sorted[t];
                 }
 #pragma unroll
@@ -1684,8 +1721,11 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
                     if (i < total) {
                         const int64_t sh = i < cL ? shL : (i < cL + cM ? 0 : shR);
                         ns.m[i] = (typename NearStage<R>::MT)(mv[k] + sh - base);
-                        ns.th[i] = tv[k];
-                        if constexpr (EPI == EPI_INV)
+                        // adjoint: a source on a grid point has weight 0
+                        // (F_j = 0); it is staged a quarter unit away, so
+                        // that its own grid point never divides by 0
+                        ns.th[i] = (EPI == EPI_ADJ && tv[k] == 0.0) ? 0.25 : tv[k];
+                        if constexpr (WS)
                             ns.w[i] = wv[k];
                     }
                 }
@@ -1782,6 +1822,27 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             const double C = a.chat[k];
             st_cx<R>(out, k, cx<R>{(R)(-0.5 * C * ((double)W.re - hi)),
                                    (R)(-0.5 * C * ((double)W.im + hr))});
+        }
+    } else if constexpr (EPI == EPI_ADJ) {
+        // adjoint of Eq. (p2): f_k = sum_j G(x_k - y_j) conj(F_j) g_j
+        //                          = -(W + i h_k) / 2 with the weights
+        // w_j = conj(F_j) g_j (sources on grid points add g_j afterwards)
+        const V W = *a.S;
+        const double hscale = (double)N / 3.14159265358979323846;
+        for (int32_t k = w.u0 + tid; k < w.u1; k += BLOCK) {
+            const int64_t leaf = uni_leaf(k, a.l, N, lscale);
+            const int il = (int)(leaf - leaf0);
+            const R u = (R)rel_coord_r(k, 0.0, leaf, a.l, N, invN);
+            V h = horner4<R, V, PD>(leafloc, RS, il, u);
+            const cx<double> nr =
+                staged ? near_cot_staged<R, true>(ns, ns.off[il], ns.off[il + 3],
+                                                  (int32_t)(k - base), 0.0)
+                       : near_cot<R, V, SRC>(a, k, 0.0, leaf, nullptr, 0,
+                                             (const cx<R> *)f_uniform);
+            const double hr = (double)h.re + hscale * nr.re;
+            const double hi = (double)h.im + hscale * nr.im;
+            st_cx<R>(out, k, cx<R>{(R)(-0.5 * ((double)W.re - hi)),
+                                   (R)(-0.5 * ((double)W.im + hr))});
         }
     } else { // EPI_LOGCD
         // log|Chat_k| and log|Dhat_j| by the FMM; then the coefficients of

@@ -1,0 +1,139 @@
+"""Adjoint transform f = K^H g (f_k = sum_j conj(K_jk) g_j, K of Eq. p2) on
+the GPU against the oracle's direct sum, element by element: ragged and
+tiny sizes with M != N, uniform and clustered points, points on grid
+points (also coincident ones), explicit depths, plan reuse, and 2^20 on
+sampled outputs plus the inner-product identity <K f, g> = <f, K^H g> with
+the GPU forward at full size.  Tolerances: rel-l2 1e-12 (binary64) and 1e-6
+(mixed, against the oracle on the same binary32 input)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import dev, host, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+fn = pytest.importorskip("paper_1611_09379_amd")
+
+PATHS = [(np.complex128, 1e-12), (np.complex64, 1e-6)]
+
+
+def adj_case(N, M, dist, seed):
+    rng = np.random.default_rng(seed)
+    if dist == "uniform":
+        y = workloads.points_uniform(M, rng)
+    else:
+        y = workloads.points_clustered(M, rng)
+    g = (rng.standard_normal(M) + 1j * rng.standard_normal(M)) / math.sqrt(2)
+    return y, g
+
+
+@pytest.mark.parametrize("dtype,eps", PATHS)
+@pytest.mark.parametrize("N,M,dist", [(1024, 1024, "uniform"), (1000, 3001, "uniform"),
+                                      (4096, 777, "clustered"), (8192, 8192, "uniform"),
+                                      (6000, 12000, "clustered"), (1, 5, "uniform"),
+                                      (7, 1, "uniform"), (13, 40, "clustered")])
+def test_adjoint_full(N, M, dist, dtype, eps):
+    y, g = adj_case(N, M, dist, seed=N + 3 * M)
+    g = g.astype(dtype)
+    say(f"adj N={N} M={M} {dist} {np.dtype(dtype).name}")
+    f = host(fn.nufft_adj(dev(y), dev(g), N, eps))
+    ref = oracle.adj(N, y, g.astype(np.complex128))
+    err = rel_l2(f, ref)
+    say(f"  rel l2 {err:.3e}")
+    assert err < eps
+
+
+@pytest.mark.parametrize("dtype,eps", PATHS)
+def test_adjoint_grid_points_and_duplicates(dtype, eps):
+    """Points on grid points contribute g_j to f_m alone (conj(K_jk) =
+    delta(k, m)); several points may coincide, on and off the grid."""
+    N, M = 512, 700
+    y, g = adj_case(N, M, "uniform", seed=5)
+    # two points at x_0, two at fl(x_7) (one ulp off the grid point, not a
+    # hit), two coincident off-grid points, two more at x_0 via a period
+    y[:8] = [0.0, 0.0, 2 * np.pi * 7 / N, 2 * np.pi * 7 / N, y[10], y[10], 2 * np.pi,
+             -2 * np.pi]
+    g = g.astype(dtype)
+    f = host(fn.nufft_adj(dev(y), dev(g), N, eps))
+    assert np.all(np.isfinite(f))
+    ref = oracle.adj(N, y, g.astype(np.complex128))
+    assert rel_l2(f, ref) < eps
+
+
+@pytest.mark.parametrize("dtype,eps", PATHS)
+def test_adjoint_plan_reuse_and_phases(dtype, eps):
+    N, M = 3000, 2500
+    y, g = adj_case(N, M, "clustered", seed=8)
+    rng = np.random.default_rng(9)
+    g2 = (rng.standard_normal(M) + 1j * rng.standard_normal(M)).astype(dtype)
+    g = g.astype(dtype)
+    plan = fn.Plan.adjoint(N, dev(y), eps, dtype=fn.FN_C128 if dtype == np.complex128 else fn.FN_C64)
+    assert plan.info().kind == 2
+    f1 = host(plan(dev(g)))
+    f2 = host(plan(dev(g2)))
+    import torch
+    out = torch.empty(N, dtype=torch.complex128 if dtype == np.complex128 else torch.complex64,
+                      device="cuda")
+    gd = dev(g)
+    for ph in (0, 1, 2):
+        plan.execute_phase(gd, out, ph)
+    f3 = host(out)
+    plan.destroy()
+    assert np.array_equal(f1, f3)
+    assert rel_l2(f1, oracle.adj(N, y, g.astype(np.complex128))) < eps
+    assert rel_l2(f2, oracle.adj(N, y, g2.astype(np.complex128))) < eps
+
+
+@pytest.mark.parametrize("seed", [41])
+def test_adjoint_sweep(seed):
+    """Random sizes, distributions, whole-period shifts, exact grid points
+    and explicit depths, both paths."""
+    rng = np.random.default_rng(seed)
+    for case in range(40):
+        N, M = workloads_log_uniform(rng, 1, 10000), workloads_log_uniform(rng, 1, 10000)
+        dist = "clustered" if rng.random() < 0.3 else "uniform"
+        y, g = adj_case(N, M, dist, seed=int(rng.integers(1 << 30)))
+        y = y + 2 * math.pi * int(rng.integers(-3, 4))
+        if rng.random() < 0.2:
+            y[: min(2, M)] = 0.0
+        mixed = rng.random() < 0.4
+        lmax = int(rng.integers(2, max(3, int(math.log2(max(N, M))) + 1))) if rng.random() < 0.3 else 0
+        dt, eps, cdt = (fn.FN_C64, 1e-6, np.complex64) if mixed else (fn.FN_C128, 1e-12, np.complex128)
+        say(f"case {case}: N={N} M={M} {dist} mixed={mixed} lmax={lmax}")
+        g = g.astype(cdt)
+        plan = fn.Plan.adjoint(N, dev(y), eps, dt, lmax=lmax)
+        f = host(plan(dev(g)))
+        plan.destroy()
+        err = rel_l2(f, oracle.adj(N, y, g.astype(np.complex128)))
+        assert err < eps, (case, N, M, dist, mixed, lmax, err)
+
+
+def workloads_log_uniform(rng, lo, hi):
+    return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+
+
+@pytest.mark.parametrize("dtype,eps", PATHS)
+def test_adjoint_2p20(dtype, eps):
+    """N = M = 2^20: 512 sampled outputs against the oracle, and the
+    inner-product identity <K f, g> = <f, K^H g> over all outputs with the
+    GPU forward (a property of the pair that holds at any size)."""
+    N = M = 1 << 20
+    y, g = adj_case(N, M, "uniform", seed=20)
+    yf, f, c = workloads.forward_case(N, M, "uniform", seed=21)
+    g, f = g.astype(dtype), f.astype(dtype)
+    yd = dev(y)
+    fa = host(fn.nufft_adj(yd, dev(g), N, eps))
+    ks = np.random.default_rng(3).choice(N, 512, replace=False)
+    ref = oracle.adj(N, y, g.astype(np.complex128), ks)
+    err = rel_l2(fa[ks], ref)
+    gf = host(fn.nufft_fwd(yd, dev(f), eps))
+    lhs = np.vdot(g.astype(np.complex128), gf.astype(np.complex128))   # <g, K f>
+    rhs = np.vdot(fa.astype(np.complex128), f.astype(np.complex128))   # <K^H g, f>
+    ident = abs(lhs - rhs) / (np.linalg.norm(g) * np.linalg.norm(gf))
+    say(f"adj 2^20 {np.dtype(dtype).name}: sampled {err:.3e}, identity {ident:.3e}")
+    assert err < eps
+    assert ident < eps
