@@ -707,7 +707,21 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_
     F.tr_smem = F.dn_smem + (size_t)PD * PD * es;
     if (F.tr_smem > lim)
         return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PD, F.tr_smem);
-    F.near_bytes = (int)((size_t)(F.rows_buf + F.rows_src) * F.RSd * es);
+    // the evaluation stages its near-field sources after the leaf locals:
+    // for sorted sources, room for 1.25 times the mean count of the
+    // subtree's leaves and its two neighbours (16 bytes of position, plus
+    // the weight for the cot kernel), within 48 KiB (four workgroups per
+    // compute unit); a subtree beyond it reads its sources in place
+    const size_t loc_bytes = (size_t)F.rows_buf * F.RSd * es;
+    if (sorted_src) {
+        const int64_t nsrc = P->kind == 2 ? P->M : P->N;
+        const int64_t mean = (nsrc + (int64_t(1) << P->l) - 1) >> P->l;
+        const int64_t want = (((int64_t(1) << s) + 2) * mean * 5) / 4 + 64;
+        const size_t per = 16 + (kernel == KER_COT ? 2 * (size_t)es : 0);
+        const size_t need = loc_bytes + (size_t)want * per + 4 * (((size_t)1 << s) + 4);
+        F.dn_smem = std::max(F.dn_smem, std::min(need, std::min(lim, (size_t)48 << 10)));
+    }
+    F.near_bytes = (int)(F.dn_smem - loc_bytes);
     const int64_t nmp = lev_off(P->l + 1, PU);
     if (!alloc(F.mp, nmp * sizeof(V)) || !alloc(F.loc2, 4 * PD * sizeof(V)) ||
         !alloc(F.S, sizeof(V)) || !alloc(F.locl, ((size_t)PD << P->l) * sizeof(V)))

@@ -1208,43 +1208,31 @@ __device__ __forceinline__ cx<double> near_cot(const DownArgs<R, V> &a, int64_t 
 }
 
 // Sorted sources of a subtree staged in LDS: the leaves leaf0 - 1 ..
-// leaf0 + nb (unwrapped, so positions increase), as integer grid offsets
-// from a base point, fractions and (cot kernel) weights.  The sources of
-// staged leaf j occupy [off[j], off[j + 1]).
+// leaf0 + nb (unwrapped, so positions increase), as (integer grid offset
+// from a base point, fraction) pairs and (cot kernel) weights.  The sources
+// of staged leaf j occupy [off[j], off[j + 1]).  The offset is held as a
+// binary64 value (an exact integer), interleaved with the fraction, so that
+// a pair takes one 16-byte LDS read and no integer-to-binary64 conversion.
 template <typename R>
 struct NearStage {
-    // integer grid offsets (held as int32: as binary64 they would spare the
-    // conversion per pair, but the wider LDS reads cost more than it)
-    using MT = int32_t;
-    MT *m;
-    double *th;
+    double2 *p; // {offset, fraction}
     cx<R> *w;
     int32_t *off;
     int32_t self0; // staged index of sorted point t is t + self0 (own leaves)
 };
 
-// Distance tau - sigma in grid units for an integer offset dm and fractions
-// a, b in [-1/2, 1/2]: a - b and the sum each round once, so the relative
-// error is at most 2^-53 (1 + 1/|d|).
-__device__ __forceinline__ double near_dist(int32_t dm, double a, double b)
-{
-    return (double)dm + (a - b);
-}
-
-__device__ __forceinline__ double near_dist(int32_t tm, int32_t m, double a, double b)
-{
-    return (double)(tm - m) + (a - b);
-}
-
-// The same with GT (the target on the grid, a = 0): a - b is then -b
-// exactly, so one subtraction gives the same value.
+// Distance tau - sigma in grid units for integer parts tm, m (binary64,
+// |tm - m| < 2^31, so their difference is exact) and fractions a, b in
+// [-1/2, 1/2]: a - b and the sum each round once, so the relative error is
+// at most 2^-53 (1 + 1/|d|).  GT: the target is on the grid (a = 0), and
+// a - b is -b exactly, so one subtraction gives the same value.
 template <bool GT>
-__device__ __forceinline__ double near_dist_t(int32_t tm, int32_t m, double a, double b)
+__device__ __forceinline__ double near_dist_p(double tm, double2 p, double a)
 {
     if constexpr (GT)
-        return (double)(tm - m) - b;
+        return (tm - p.x) - p.y;
     else
-        return (double)(tm - m) + (a - b);
+        return (tm - p.x) + (a - p.y);
 }
 
 // Cot near field from staged sources [j0, j1): sum w / (tau - sigma)
@@ -1255,7 +1243,7 @@ template <typename R, bool GT>
 __device__ __forceinline__ cx<double> near_cot_staged(const NearStage<R> &ns, int32_t j0,
                                                       int32_t j1, int32_t tmr, double tth)
 {
-    const typename NearStage<R>::MT tmd = (typename NearStage<R>::MT)tmr;
+    const double tmd = (double)tmr;
     cx<double> tot = {0.0, 0.0};
     for (int32_t jb = j0; jb < j1;) {
         const int32_t je = (j1 - jb > fold_len<R>()) ? jb + fold_len<R>() : j1;
@@ -1265,10 +1253,10 @@ __device__ __forceinline__ cx<double> near_cot_staged(const NearStage<R> &ns, in
         // distance is zero: exact hits never reach the near field); binary32
         // keeps one reciprocal per pair
         for (; j + 4 <= je; j += 4) {
-            const R d0 = (R)near_dist_t<GT>(tmd, ns.m[j], tth, ns.th[j]);
-            const R d1 = (R)near_dist_t<GT>(tmd, ns.m[j + 1], tth, ns.th[j + 1]);
-            const R d2 = (R)near_dist_t<GT>(tmd, ns.m[j + 2], tth, ns.th[j + 2]);
-            const R d3 = (R)near_dist_t<GT>(tmd, ns.m[j + 3], tth, ns.th[j + 3]);
+            const R d0 = (R)near_dist_p<GT>(tmd, ns.p[j], tth);
+            const R d1 = (R)near_dist_p<GT>(tmd, ns.p[j + 1], tth);
+            const R d2 = (R)near_dist_p<GT>(tmd, ns.p[j + 2], tth);
+            const R d3 = (R)near_dist_p<GT>(tmd, ns.p[j + 3], tth);
             const cx<R> w0 = ns.w[j], w1 = ns.w[j + 1], w2 = ns.w[j + 2], w3 = ns.w[j + 3];
             if constexpr (sizeof(R) == 8) {
                 const R r01 = recip(d0 * d1), r23 = recip(d2 * d3);
@@ -1289,7 +1277,7 @@ __device__ __forceinline__ cx<double> near_cot_staged(const NearStage<R> &ns, in
             }
         }
         for (; j < je; ++j) {
-            const R r = recip((R)near_dist_t<GT>(tmd, ns.m[j], tth, ns.th[j]));
+            const R r = recip((R)near_dist_p<GT>(tmd, ns.p[j], tth));
             const cx<R> w = ns.w[j];
             a0.re = fma(w.re, r, a0.re);
             a0.im = fma(w.im, r, a0.im);
@@ -1309,12 +1297,12 @@ __device__ __forceinline__ void log_prod_range(const NearStage<R> &ns, int32_t j
                                                int32_t tmr, double tth, double &prod,
                                                int &expo)
 {
-    const typename NearStage<R>::MT tmd = (typename NearStage<R>::MT)tmr;
+    const double tmd = (double)tmr;
     for (; j + 8 <= j1; j += 8) {
         double d[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            d[u] = fabs(near_dist_t<GT>(tmd, ns.m[j + u], tth, ns.th[j + u]));
+            d[u] = fabs(near_dist_p<GT>(tmd, ns.p[j + u], tth));
         const double q = ((d[0] * d[1]) * (d[2] * d[3])) * ((d[4] * d[5]) * (d[6] * d[7]));
         int e;
         prod = frexp(prod * q, &e);
@@ -1322,7 +1310,7 @@ __device__ __forceinline__ void log_prod_range(const NearStage<R> &ns, int32_t j
     }
     double q = 1.0;
     for (; j < j1; ++j)
-        q *= fabs(near_dist_t<GT>(tmd, ns.m[j], tth, ns.th[j]));
+        q *= fabs(near_dist_p<GT>(tmd, ns.p[j], tth));
     int e;
     prod = frexp(prod * q, &e);
     expo += e;
@@ -1688,15 +1676,13 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
         const int32_t total = cL + cM + cR;
         constexpr bool WS = EPI == EPI_INV || EPI == EPI_ADJ; // weights staged
         constexpr int wb = WS ? (int)sizeof(cx<R>) : 0;
-        constexpr int mb = (int)sizeof(typename NearStage<R>::MT);
-        const int32_t cap = ((a.near_bytes - 4 * (nb + 4)) / (8 + mb + wb)) & ~1;
+        const int32_t cap = ((a.near_bytes - 4 * (nb + 4)) / (16 + wb)) & ~1;
         base = uni_start(leaf0, a.l, N);
         if (total <= cap) {
-            unsigned char *fr = reinterpret_cast<unsigned char *>(bufB);
-            ns.th = reinterpret_cast<double *>(fr);
-            ns.w = reinterpret_cast<cx<R> *>(fr + 8 * (size_t)cap);
-            ns.m = reinterpret_cast<typename NearStage<R>::MT *>(fr + (8 + wb) * (size_t)cap);
-            ns.off = reinterpret_cast<int32_t *>(ns.m + cap);
+            unsigned char *fr = reinterpret_cast<unsigned char *>(bufB); // 16-byte aligned
+            ns.p = reinterpret_cast<double2 *>(fr);
+            ns.w = reinterpret_cast<cx<R> *>(fr + 16 * (size_t)cap);
+            ns.off = reinterpret_cast<int32_t *>(fr + (16 + wb) * (size_t)cap);
             ns.self0 = cL - oM;
             const int64_t shL = leaf0 == 0 ? -N : 0, shR = leaf0 + nb == nleaf ? N : 0;
             // every load of a batch in flight at once (indices clamped)
@@ -1720,11 +1706,11 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
                     const int32_t i = i0 + tid + k * BLOCK;
                     if (i < total) {
                         const int64_t sh = i < cL ? shL : (i < cL + cM ? 0 : shR);
-                        ns.m[i] = (typename NearStage<R>::MT)(mv[k] + sh - base);
                         // adjoint: a source on a grid point has weight 0
                         // (F_j = 0); it is staged a quarter unit away, so
                         // that its own grid point never divides by 0
-                        ns.th[i] = (EPI == EPI_ADJ && tv[k] == 0.0) ? 0.25 : tv[k];
+                        ns.p[i] = make_double2((double)(mv[k] + sh - base),
+                                               (EPI == EPI_ADJ && tv[k] == 0.0) ? 0.25 : tv[k]);
                         if constexpr (WS)
                             ns.w[i] = wv[k];
                     }
@@ -1868,13 +1854,14 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             // a binary search over the (sorted) points of k's leaf
             int32_t lo, hi;
             if (staged) {
-                const typename NearStage<R>::MT tmr = (typename NearStage<R>::MT)(k - base);
+                const double tmr = (double)(k - base);
                 lo = ns.off[il + 1];
                 hi = ns.off[il + 2];
                 const int32_t j0 = lo;
                 while (lo < hi) {
                     const int32_t mid = (lo + hi) >> 1;
-                    if (ns.m[mid] < tmr || (ns.m[mid] == tmr && ns.th[mid] <= 0.0))
+                    const double2 pm = ns.p[mid];
+                    if (pm.x < tmr || (pm.x == tmr && pm.y <= 0.0))
                         lo = mid + 1;
                     else
                         hi = mid;
