@@ -471,10 +471,12 @@ struct FmmSetup {
     int PU = 0, PD = 0, q = 0;
     int RSu = 0, RSd = 0;          // LDS row strides (elements of R)
     Buf mp, loc2, S;
-    Buf locl; // leaf local expansions (between the two downward kernels)
+    // M2L results of every box of levels 3..l (PD per box, packed per
+    // level); the leaf level becomes the leaf locals (read by the evaluation)
+    Buf pre;
     int nbands = 0;
     Band band[MAX_BANDS];
-    size_t reg_smem = 0;
+    size_t m2l_smem = 0; // M2L kernel (with the level-2 regular part)
     size_t dn_smem = 0; // evaluation kernel
     size_t tr_smem = 0; // translation kernel
     int rows_buf = 0, rows_src = 0, near_bytes = 0;
@@ -510,8 +512,7 @@ struct fn_plan {
     std::vector<Buf *> all()
     {
         return {&off, &sm, &sth, &sperm, &skey, &spt, &work, &nwork_dev, &cot.mp, &cot.loc2,
-                &cot.locl,
-                &cot.S, &hit, &chat, &dhat, &wsorted, &flags};
+                &cot.pre, &cot.S, &hit, &chat, &dhat, &wsorted, &flags};
     }
 };
 
@@ -698,15 +699,15 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_
         if (F.band[b].smem > lim)
             return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PU,
                         F.band[b].smem);
-    F.reg_smem = (size_t)(PU * PU + 2 * PU * PD) * es + 8 * (size_t)PU * sizeof(V);
-    if (F.reg_smem > lim)
-        return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PU, F.reg_smem);
     const int s = P->l - P->lr;
     F.dn_smem = down_lds(s, P->lr, F.RSd, es, &F.rows_buf, &F.rows_src);
-    // the translation kernel holds the L2L table as well
-    F.tr_smem = F.dn_smem + (size_t)PD * PD * es;
-    if (F.tr_smem > lim)
-        return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PD, F.tr_smem);
+    // the translation kernel: its two level buffers and the L2L table; the
+    // M2L kernel: the source rows and the output rows of its boxes
+    F.tr_smem = (size_t)2 * F.rows_buf * F.RSd * es + (size_t)PD * PD * es;
+    F.m2l_smem = std::max((size_t)(M2L_BOXES + 6) * F.RSd * es, 8 * (size_t)PU * sizeof(V));
+    if (F.tr_smem > lim || F.m2l_smem > lim)
+        return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PD,
+                    std::max(F.tr_smem, F.m2l_smem));
     // the evaluation stages its near-field sources after the leaf locals:
     // for sorted sources, room for 1.25 times the mean count of the
     // subtree's leaves and its two neighbours (16 bytes of position, plus
@@ -724,7 +725,7 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_
     F.near_bytes = (int)(F.dn_smem - loc_bytes);
     const int64_t nmp = lev_off(P->l + 1, PU);
     if (!alloc(F.mp, nmp * sizeof(V)) || !alloc(F.loc2, 4 * PD * sizeof(V)) ||
-        !alloc(F.S, sizeof(V)) || !alloc(F.locl, ((size_t)PD << P->l) * sizeof(V)))
+        !alloc(F.S, sizeof(V)) || !alloc(F.pre, lev_off(P->l + 1, PD) * sizeof(V)))
         return fail(FN_ENOMEM, "expansion allocation failed");
     (void)kernel;
     (void)st;
@@ -767,7 +768,8 @@ static void fill_down(const fn_plan *P, const FmmSetup &F, const OpTables<R> &T,
     da.S = (const V *)F.S.p;
     da.T = T;
     da.flags = (const int *)P->flags.p;
-    da.leaf_loc = (V *)F.locl.p;
+    da.pre = (V *)F.pre.p;
+    da.leaf_loc = (V *)F.pre.p + lev_off(P->l, F.PD);
 }
 
 // Launches with the expansion lengths as template arguments.
@@ -779,8 +781,9 @@ static void fill_down(const fn_plan *P, const FmmSetup &F, const OpTables<R> &T,
     default: { constexpr int NAME = 64; __VA_ARGS__; } break;                  \
     }
 
-// The upward pass: the bands, then the level-2 regular part.  ua must be
-// filled except for the band fields.
+// The upward pass: the bands (the level-2 regular part runs with the M2L
+// kernel of the downward pass).  ua must be filled except for the band
+// fields.
 template <typename R, typename V, int KER, int SRC>
 static int launch_up(const FmmSetup &F, UpArgs<R, V> ua, hipStream_t st)
 {
@@ -794,19 +797,22 @@ static int launch_up(const FmmSetup &F, UpArgs<R, V> ua, hipStream_t st)
                                          F.band[b].smem, st, ua));
         HIPCHK(hipGetLastError());
     }
-    FN_DISPATCH16(F.PU, PU_,
-                  hipLaunchKernelGGL((k_regular<R, V, KER, PU_>), dim3(1), dim3(BLOCK),
-                                     F.reg_smem, st, ua));
-    HIPCHK(hipGetLastError());
     return FN_OK;
 }
 
 template <typename R, typename V, int KER, int SRC, int EPI>
-// The downward pass: its translation kernel (which = 1), its evaluation
-// kernel (which = 2), or both (which < 0).
+// The downward pass: its translations (which = 1: the M2L of every box with
+// the level-2 regular part, then the subtrees' L2L), its evaluation kernel
+// (which = 2), or both (which < 0).  ua: the regular part's arguments.
 static int launch_down(const fn_plan *P, const FmmSetup &F, const DownArgs<R, V> &da,
-                       hipStream_t st, int which = -1)
+                       const UpArgs<R, V> &ua, hipStream_t st, int which = -1)
 {
+    if (which != 2) {
+        FN_DISPATCH16(F.PD, PD_,
+                      hipLaunchKernelGGL((k_m2l<R, V, KER, PD_>), dim3(m2l_blocks(P->l) + 1),
+                                         dim3(BLOCK), F.m2l_smem, st, da, ua));
+        HIPCHK(hipGetLastError());
+    }
     if (P->nwork == 0)
         return FN_OK;
     if (which != 2) {
@@ -1149,10 +1155,10 @@ static int exec_fwd(fn_plan *P, const void *in, void *out, int phase,
     int rc = get_tables<R>(KER_COT, F.PU, F.PD, F.q, &T);
     if (rc)
         return rc;
+    UpArgs<R, V> ua{};
+    fill_up(P, F, T, ua);
+    ua.f_uniform = (const cx<R> *)in;
     if (phase <= 0) {
-        UpArgs<R, V> ua{};
-        fill_up(P, F, T, ua);
-        ua.f_uniform = (const cx<R> *)in;
         rc = launch_up<R, V, KER_COT, SET_UNIFORM>(F, ua, st);
         if (rc)
             return rc;
@@ -1165,7 +1171,7 @@ static int exec_fwd(fn_plan *P, const void *in, void *out, int phase,
     da.tgt_pt = (const SortedPt *)P->spt.p;
     da.out = (cx<R> *)out;
     da.f_hit = (const cx<R> *)in;
-    return launch_down<R, V, KER_COT, SET_UNIFORM, EPI_FWD>(P, F, da, st, phase);
+    return launch_down<R, V, KER_COT, SET_UNIFORM, EPI_FWD>(P, F, da, ua, st, phase);
 }
 
 // --------------------------------------------------------- inverse plan
@@ -1195,7 +1201,7 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     FmmSetup F;
     rc = setup_fmm<R, V>(P, KER_LOG, PU, PD, qlog, true, F, st);
     // the log FMM's workspace lives until the plan's synchronisation
-    for (Buf *b : {&F.mp, &F.loc2, &F.S, &F.locl})
+    for (Buf *b : {&F.mp, &F.loc2, &F.S, &F.pre})
         if (b->p)
             P->tmp.push_back(*b);
     if (rc)
@@ -1237,12 +1243,12 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     // binary32 (about exp(+-87)), which leaves |g_j| a range of exp(+-27)
     da.log_max = P->dtype == FN_C64 ? LOG_MAX_C64 : 700.0;
     // the evaluation's epilogue forms Chat and Dhat
-    rc = launch_down<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>(P, F, da, st, 1);
+    rc = launch_down<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>(P, F, da, ua, st, 1);
     if (rc)
         return rc;
     if (timed)
         HIPCHK(hipEventRecord(P->tev[2], st));
-    rc = launch_down<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>(P, F, da, st, 2);
+    rc = launch_down<R, V, KER_LOG, SET_SORTED, EPI_LOGCD>(P, F, da, ua, st, 2);
     if (rc)
         return rc;
     if (timed)
@@ -1293,12 +1299,12 @@ static int exec_inv(fn_plan *P, const void *in, void *out, int phase,
         return rc;
     const SortedSet src = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
                            (const double *)P->sth.p, (const int32_t *)P->sperm.p};
+    UpArgs<R, V> ua{};
+    fill_up(P, F, T, ua);
+    ua.src = src;
+    ua.leaf_pts = 0;
+    ua.w_sorted = (const cx<R> *)P->wsorted.p;
     if (phase <= 0) {
-        UpArgs<R, V> ua{};
-        fill_up(P, F, T, ua);
-        ua.src = src;
-        ua.leaf_pts = 0;
-        ua.w_sorted = (const cx<R> *)P->wsorted.p;
         hipLaunchKernelGGL((k_weights<R>), dim3(grid_for(P->N)), dim3(256), 0, st, P->N,
                            (const cx<double> *)P->dhat.p, (const int32_t *)P->sperm.p,
                            (const cx<R> *)in, (cx<R> *)P->wsorted.p);
@@ -1317,7 +1323,7 @@ static int exec_inv(fn_plan *P, const void *in, void *out, int phase,
     da.chat = (const double *)P->chat.p;
     da.hit = (const int32_t *)P->hit.p;
     da.gin = (const cx<R> *)in;
-    return launch_down<R, V, KER_COT, SET_SORTED, EPI_INV>(P, F, da, st, phase);
+    return launch_down<R, V, KER_COT, SET_SORTED, EPI_INV>(P, F, da, ua, st, phase);
 }
 
 // --------------------------------------------------------- adjoint plan
@@ -1364,12 +1370,12 @@ static int exec_adj(fn_plan *P, const void *in, void *out, int phase, hipStream_
         return rc;
     const SortedSet src = {(const int32_t *)P->off.p, (const int32_t *)P->sm.p,
                            (const double *)P->sth.p, (const int32_t *)P->sperm.p};
+    UpArgs<R, V> ua{};
+    fill_up(P, F, T, ua);
+    ua.src = src;
+    ua.leaf_pts = 0;
+    ua.w_sorted = (const cx<R> *)P->wsorted.p;
     if (phase <= 0) {
-        UpArgs<R, V> ua{};
-        fill_up(P, F, T, ua);
-        ua.src = src;
-        ua.leaf_pts = 0;
-        ua.w_sorted = (const cx<R> *)P->wsorted.p;
         hipLaunchKernelGGL((k_adj_weights<R>), dim3(grid_for(P->M)), dim3(256), 0, st, P->M,
                            P->N, (const double *)P->sth.p, (const int32_t *)P->sperm.p,
                            (const cx<R> *)in, (cx<R> *)P->wsorted.p);
@@ -1385,7 +1391,7 @@ static int exec_adj(fn_plan *P, const void *in, void *out, int phase, hipStream_
     da.src = src;
     da.w_sorted = (const cx<R> *)P->wsorted.p;
     da.out = (cx<R> *)out;
-    rc = launch_down<R, V, KER_COT, SET_SORTED, EPI_ADJ>(P, F, da, st, phase);
+    rc = launch_down<R, V, KER_COT, SET_SORTED, EPI_ADJ>(P, F, da, ua, st, phase);
     if (rc || phase == 1)
         return rc;
     hipLaunchKernelGGL((k_adj_hits<R>), dim3(grid_for(P->M)), dim3(256), 0, st, P->M,
@@ -1577,7 +1583,7 @@ struct fn_batch {
     std::vector<fn_plan *> P;
     std::vector<int> grp, solo;
     int PU = 0, PD = 0, q = 0, nbands = 0;
-    size_t reg_smem = 0, tr_smem = 0;
+    size_t tr_smem = 0;
     Buf blob, io, flags;
     // host images of the argument blob and of the I/O table, kept unchanged
     // until the copies that read them have run: the blob's until the batch
@@ -1587,7 +1593,7 @@ struct fn_batch {
     hipEvent_t ev_io = nullptr;
     bool io_pending = false;
     std::vector<IoPtr> hio_pageable; // one-shot fallback without pinned memory
-    LaunchShape hist, colscan, place, scan, work, reg, down, up[MAX_BANDS];
+    LaunchShape hist, colscan, place, scan, work, reg, m2l, down, up[MAX_BANDS];
     hipStream_t stream = nullptr;
     hipStream_t bs = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -1751,8 +1757,8 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
     {
         std::vector<UpArgs<R, V>> ua;
         std::vector<DownArgs<R, V>> da;
-        std::vector<int> nb_reg, nb_down;
-        size_t dsm = 0;
+        std::vector<int> nb_reg, nb_down, nb_m2l;
+        size_t dsm = 0, msm = 0;
         for (int t : B->grp) {
             fn_plan *P = B->P[t];
             const FmmSetup &F = P->cot;
@@ -1761,7 +1767,6 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
             u.io_index = t;
             ua.push_back(u);
             nb_reg.push_back(1);
-            B->reg_smem = std::max(B->reg_smem, F.reg_smem);
             DownArgs<R, V> d{};
             fill_down(P, F, Tb, d);
             d.tgt_pt = (const SortedPt *)P->spt.p;
@@ -1769,13 +1774,16 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
             d.io = (const IoPtr *)B->io.p; // f, g of every call come from the table
             da.push_back(d);
             nb_down.push_back(P->nwork);
+            nb_m2l.push_back(m2l_blocks(P->l) + 1); // + the regular part
             dsm = std::max(dsm, F.dn_smem);
+            msm = std::max(msm, F.m2l_smem);
             B->tr_smem = std::max(B->tr_smem, F.tr_smem);
         }
-        bb.add(B->reg, ua, nb_reg);
-        B->reg.smem = B->reg_smem;
+        bb.add(B->reg, ua, nb_reg); // the regular part's arguments (read by kb_m2l)
         bb.add(B->down, da, nb_down);
         B->down.smem = dsm;
+        bb.add(B->m2l, da, nb_m2l);
+        B->m2l.smem = msm;
     }
     if (!bb.bytes.empty()) {
         if (!alloc(B->blob, bb.bytes.size()))
@@ -1836,9 +1844,10 @@ static int launch_batch_eval(fn_batch *B, hipStream_t st)
                                          (const UpArgs<R, V> *)at(L.args), map(L), io));
         HIPCHK(hipGetLastError());
     }
-    FN_DISPATCH16(B->PU, PU_,
-                  hipLaunchKernelGGL((kb_regular<R, V, KER_COT, PU_>), dim3(B->reg.grid),
-                                     dim3(BLOCK), B->reg.smem, st,
+    FN_DISPATCH16(B->PD, PD_,
+                  hipLaunchKernelGGL((kb_m2l<R, V, KER_COT, PD_>), dim3(B->m2l.grid),
+                                     dim3(BLOCK), B->m2l.smem, st,
+                                     (const DownArgs<R, V> *)at(B->m2l.args), map(B->m2l),
                                      (const UpArgs<R, V> *)at(B->reg.args)));
     HIPCHK(hipGetLastError());
     FN_DISPATCH16(

@@ -23,12 +23,16 @@
 //   k_up_band    P2M at the leaves (first band) or a load of the band's
 //                bottom multipoles, then M2M up the band (matrix cores); the
 //                last band ends at level 2.
-//   k_regular    one workgroup: the level-2 local polynomial of the regular
+//   k_m2l        the M2L of every box of levels 3..l (matrix cores), and in
+//                one workgroup the level-2 local polynomial of the regular
 //                part (Eq. p20) from the four level-2 multipoles.
-//   k_down_eval  one subtree of the finest levels: the local of its root as
+//   k_down_trans one subtree of the finest levels: the local of its root as
 //                the sum of the ancestors' M2L results shifted straight to
-//                the root, the subtree's L2L + M2L (matrix cores), then every
-//                target in it: L2P + near-field P2P + the transform epilogue.
+//                the root, then the subtree's levels, each box's M2L result
+//                plus the L2L of its parent (matrix cores), down to the leaf
+//                locals.
+//   k_down_eval  every target of a subtree: L2P + near-field P2P + the
+//                transform epilogue.
 #pragma once
 
 #include "fmm_device.h"
@@ -784,74 +788,43 @@ __global__ void __launch_bounds__(BLOCK) kb_up_band(const UpArgs<R, V> *aa, Bloc
 // the sum of the weights.  A1 holds the moments of Omega_1(P_n) about the
 // centre of P_n: the three quarters unwrapped around it, (v + 2i)^t expanded
 // for i = -1, 0, +1.
-template <typename R, typename V, int KER, int PU>
-__device__ __forceinline__ void regular_body(const UpArgs<R, V> &a)
+// The level-2 regular part (Eq. p20) and S, by one workgroup: the local
+// polynomial of each level-2 box from the four level-2 multipoles (its own
+// quarter's and its neighbours' moments alpha1, the opposite quarter's
+// alpha2), with the binomial and regular-part tables read from memory
+// (cached; each is read by a few hundred threads).  a2, A1: 4 PU values of
+// LDS each.
+template <typename R, typename V, int KER>
+__device__ __forceinline__ void regular_part(const UpArgs<R, V> &a, int PU, V *a2, V *A1)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int PD = a.PD; // at most 64
-    R *tb = reinterpret_cast<R *>(smem_raw);      // PU x PU
-    R *t1 = tb + PU * PU;                          // PU x PD
-    R *t2 = t1 + PU * PD;                          // PU x PD
-    V *a2 = reinterpret_cast<V *>(t2 + PU * PD);   // 4 x PU
-    V *A1 = a2 + 4 * PU;                           // 4 x PU
     const int tid = threadIdx.x;
-    // every load of a thread is issued before the first store to LDS: one
-    // round trip to memory instead of one per loop iteration
-    {
-        constexpr int NB = (PU * PU + BLOCK - 1) / BLOCK;
-        constexpr int NR = (PU * 64 + BLOCK - 1) / BLOCK;
-        constexpr int NA = (4 * PU + BLOCK - 1) / BLOCK;
-        R rb[NB], r1[NR], r2[NR];
-        V ra[NA];
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            const int i = tid + k * BLOCK;
-            rb[k] = i < PU * PU ? a.T.bin[i] : R(0);
-        }
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            const int i = tid + k * BLOCK;
-            r1[k] = i < PU * PD ? a.T.reg1[i] : R(0);
-            r2[k] = i < PU * PD ? a.T.reg2[i] : R(0);
-        }
-#pragma unroll
-        for (int k = 0; k < NA; ++k) {
-            const int i = tid + k * BLOCK;
-            ra[k] = i < 4 * PU ? a.mp[i] : vzero<V>(); // level 2 is the first level of mp
-        }
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            const int i = tid + k * BLOCK;
-            if (i < PU * PU)
-                tb[i] = rb[k];
-        }
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            const int i = tid + k * BLOCK;
-            if (i < PU * PD) {
-                t1[i] = r1[k];
-                t2[i] = r2[k];
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < NA; ++k) {
-            const int i = tid + k * BLOCK;
-            if (i < 4 * PU)
-                a2[i] = ra[k];
-        }
-    }
+    for (int i = tid; i < 4 * PU; i += BLOCK)
+        a2[i] = a.mp[i]; // level 2 is the first level of mp
     __syncthreads();
     for (int idx = tid; idx < 4 * PU; idx += BLOCK) {
         const int q = idx / PU, t = idx - q * PU;
         V acc = a2[q * PU + t];
         const V *lft = a2 + ((q + 3) & 3) * PU;
         const V *rgt = a2 + ((q + 1) & 3) * PU;
+        const R *brow = a.T.bin + t * PU;
         R pw = R(1);
-        for (int j = t; j >= 0; --j) {
-            const R cb = tb[t * PU + j] * pw;
-            vfma(acc, cb, rgt[j]);
-            vfma(acc, ((t - j) & 1) ? -cb : cb, lft[j]);
-            pw *= R(2);
+        // the table row in batches of 8 loads in flight (indices clamped)
+        for (int j0 = t; j0 >= 0; j0 -= 8) {
+            R tb[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                tb[u] = brow[j0 - u >= 0 ? j0 - u : 0];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = j0 - u;
+                if (j >= 0) {
+                    const R cb = tb[u] * pw;
+                    vfma(acc, cb, rgt[j]);
+                    vfma(acc, ((t - j) & 1) ? -cb : cb, lft[j]);
+                    pw *= R(2);
+                }
+            }
         }
         A1[idx] = acc;
     }
@@ -863,8 +836,8 @@ __device__ __forceinline__ void regular_body(const UpArgs<R, V> &a)
         V acc = vzero<V>();
 #pragma unroll 8
         for (int t = 0; t < PU; ++t) {
-            vfma(acc, t1[t * PD + lo], n1[t]);
-            vfma(acc, t2[t * PD + lo], o[t]);
+            vfma(acc, a.T.reg1[t * PD + lo], n1[t]);
+            vfma(acc, a.T.reg2[t * PD + lo], o[t]);
         }
         if constexpr (KER == KER_LOG) {
             if (lo == 0)
@@ -874,25 +847,12 @@ __device__ __forceinline__ void regular_body(const UpArgs<R, V> &a)
     }
     if constexpr (KER == KER_COT) {
         if (tid == 0) {
-            V s = a2[0];
+            V sm = a2[0];
             for (int q = 1; q < 4; ++q)
-                vadd(s, a2[q * PU]);
-            *a.S = s;
+                vadd(sm, a2[q * PU]);
+            *a.S = sm;
         }
     }
-}
-
-template <typename R, typename V, int KER, int PU>
-__global__ void __launch_bounds__(BLOCK) k_regular(UpArgs<R, V> a)
-{
-    regular_body<R, V, KER, PU>(a);
-}
-
-// One workgroup per problem of a batch.
-template <typename R, typename V, int KER, int PU>
-__global__ void __launch_bounds__(BLOCK) kb_regular(const UpArgs<R, V> *aa)
-{
-    regular_body<R, V, KER, PU>(aa[blockIdx.x]);
 }
 
 // ------------------------------------------------------------ k_down_eval
@@ -940,6 +900,10 @@ struct DownArgs {
     const IoPtr *io;         // batched launches: the table (f_uniform, f_hit
                              // and out are then io[io_index].in / .out)
     V *leaf_loc;             // local expansions of the leaves, PD per leaf
+    V *pre;                  // M2L results of every box of levels 3..l, PD
+                             // per box packed per level (the leaf level is
+                             // leaf_loc itself: each subtree turns its
+                             // leaves' M2L results into their locals)
 };
 
 // Phases of the downward pass: the translations down to the leaf locals
@@ -962,16 +926,17 @@ struct DownOps {
 // patterns (-1)^m on the input (applied to the B operand) and a per-row
 // sign on the output.  srcrow(i, o) -> LDS row of box i's neighbour at
 // offset o; parrow(i) -> LDS row of the parent local; isleft(i), sig(i),
-// lgr(i) per box; outrow(i) -> output row in outbase.
+// lgr(i) per box; outrow(i) -> output row in outbase (rows RSo apart; LDS
+// or global memory).
 template <typename R, typename V, int KER, int PD, bool WITH_L2L, typename SrcRow,
           typename ParRow, typename IsLeft, typename Sigma, typename LogR,
-          typename OutRow>
+          typename OutRow, typename OutPtr>
 __device__ __forceinline__ void m2l_tiles(const DownOps<R, PD> &o, int rt, int ct0,
                                           int ctstep, int lane, int nb,
                                           const R *lds, const R *parbase, int RS,
                                           SrcRow srcrow, ParRow parrow,
                                           IsLeft isleft, Sigma sig,
-                                          LogR lgr, OutRow outrow, R *outbase)
+                                          LogR lgr, OutRow outrow, OutPtr outbase, int RSo)
 {
     constexpr int NC = ncomp<V>::value;
     using A = typename acc_t<R>::type;
@@ -1028,7 +993,7 @@ __device__ __forceinline__ void m2l_tiles(const DownOps<R, PD> &o, int rt, int c
             a0 = sp4[0] + sm4[0] + s6[0];
             lr0 = lgr(ic);
         }
-        R *dst = outbase + (size_t)outrow(ic) * RS + c;
+        const auto dst = outbase + (size_t)outrow(ic) * RSo + c;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int n = 16 * rt + out_row<R>(lane, r);
@@ -1388,44 +1353,164 @@ __device__ __forceinline__ double near_log(const DownArgs<R, V> &a, int64_t tm,
     return acc - near_log_background(tm, tth, leaf, l, N);
 }
 
-// Rows i = 0 .. nb + 5 of the multipoles at level lev that the M2L of the
-// subtree's nb = 2^(lev - lr) boxes reads: boxes first - 3 .. first + nb + 2
-// (around the circle), their first PD moments, into registers (one batch of
-// loads, in flight while the caller works) ...
+// The M2L results of the nb boxes of level lev below the subtree root R0
+// (PD per box), loaded into registers (no control flow between the loads,
+// so that none of them waits for another) ...
 template <typename R, typename V, int PD, int NPF>
-__device__ __forceinline__ void lev_fetch(V (&pf)[NPF], const DownArgs<R, V> &a,
-                                          int64_t R0, int lr, int lev, int tid)
+__device__ __forceinline__ void pre_fetch(V (&pf)[NPF], const V *pre, int64_t R0, int lr,
+                                          int lev, int tid)
 {
     const int nb = 1 << (lev - lr);
-    const int64_t first = R0 << (lev - lr);
-    const int64_t mask = (int64_t(1) << lev) - 1;
-    const V *base = a.mp + lev_off(lev, a.PU);
-    const int n = (nb + 6) * PD;
-    // indices clamped rather than loads predicated: no control flow between
-    // the loads, so none of them waits for another
+    const V *base = pre + lev_off(lev, PD) + (R0 << (lev - lr)) * PD;
+    const int n = nb * PD;
 #pragma unroll
     for (int k = 0; k < NPF; ++k) {
         int e = tid + k * BLOCK;
         e = e < n ? e : n - 1;
-        const int i = e / PD, m = e - i * PD;
-        pf[k] = base[((first - 3 + i) & mask) * a.PU + m];
+        pf[k] = base[e];
     }
 }
 
-// ... and from the registers into the LDS rows.
+// ... and from the registers into the LDS rows 0..nb-1.
 template <typename R, typename V, int PD, int NPF>
-__device__ __forceinline__ void lev_stage(const V (&pf)[NPF], R *srcs, int RS, int lr,
-                                          int lev, int tid)
+__device__ __forceinline__ void pre_stage(const V (&pf)[NPF], R *rows, int RS, int nb, int tid)
 {
-    const int n = ((1 << (lev - lr)) + 6) * PD;
+    const int n = nb * PD;
 #pragma unroll
     for (int k = 0; k < NPF; ++k) {
         const int e = tid + k * BLOCK;
         if (e < n) {
             const int i = e / PD, m = e - i * PD;
-            st_coef<R, V>(srcs, RS, i, m, pf[k]);
+            st_coef<R, V>(rows, RS, i, m, pf[k]);
         }
     }
+}
+
+// L2L of one level with matrix cores: out row i (child i of parent row
+// i >> 1 of par) += L2L(par row) for nb children.  The right child's
+// operator follows from the left one by the signs (-1)^m on the input and
+// (-1)^n on the output; the operator is triangular, so row tile rt takes no
+// input moment below 16 rt.
+template <typename R, typename V, int PD>
+__device__ __forceinline__ void l2l_tiles(const R (&al)[PD / 4], int rt, int ct0, int ctstep,
+                                          int lane, int nb, const R *par, R *out, int RS)
+{
+    constexpr int NC = ncomp<V>::value;
+    using A = typename acc_t<R>::type;
+    const int nct = (NC * nb + 15) / 16;
+    for (int ct = ct0; ct < nct; ct += ctstep) {
+        const int j = 16 * ct + (lane & 15);
+        const int i = j / NC, c = j % NC;
+        const bool valid = i < nb;
+        const int ic = valid ? i : 0;
+        const bool left = (ic & 1) == 0;
+        const R *sp = par + (size_t)(ic >> 1) * RS + c;
+        A acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < PD / 4; ++ks) {
+            if (ks >= 4 * rt) {
+                const int m = 4 * ks + (lane >> 4);
+                R b = sp[m * NC];
+                if (!valid)
+                    b = R(0);
+                if ((m & 1) && !left)
+                    b = -b;
+                acc = mma(al[ks], b, acc);
+            }
+        }
+        if (!valid)
+            continue;
+        R *dst = out + (size_t)ic * RS + c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * rt + out_row<R>(lane, r);
+            dst[n * NC] += (!left && (n & 1)) ? -acc[r] : acc[r];
+        }
+    }
+}
+
+// M2L of every box of levels 3..l (the interaction lists of Section 2.1:
+// the boxes at offsets -2, +2 and +-3 of the same level, whose parents
+// neighbour the box's parent), written to pre (PD per box, packed per
+// level like the multipoles).  Block 0 forms the level-2 regular part
+// instead (it needs only the level-2 multipoles, and runs beside the M2L
+// blocks).  Block 1 + k takes up to M2L_BOXES consecutive boxes of one
+// level: k = 0, 1 levels 3, 4; then level 5 + j has 2^j blocks.
+constexpr int M2L_BOXES = 32;
+
+__host__ __device__ __forceinline__ int m2l_blocks(int l)
+{
+    return l < 3 ? 0 : (l == 3 ? 1 : (l == 4 ? 2 : 2 + (1 << (l - 4)) - 1));
+}
+
+template <typename R, typename V, int KER, int PD>
+__device__ __forceinline__ void m2l_body(const DownArgs<R, V> &a, const UpArgs<R, V> &ua,
+                                         int blk)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    if (blk == 0) {
+        V *a2 = reinterpret_cast<V *>(smem_raw);
+        regular_part<R, V, KER>(ua, a.PU, a2, a2 + 4 * a.PU);
+        return;
+    }
+    blk -= 1;
+    const int RS = a.RS;
+    R *srcs = reinterpret_cast<R *>(smem_raw); // M2L_BOXES + 6 rows
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int L;
+    int64_t b0;
+    if (blk < 2) {
+        L = 3 + blk;
+        b0 = 0;
+    } else {
+        const int k = 31 - __clz(blk - 1); // blk - 1 in [2^k, 2^(k+1))
+        L = 5 + k;
+        b0 = (int64_t)(blk - 1 - (1 << k)) * M2L_BOXES;
+    }
+    const int nb = (1 << L) < M2L_BOXES ? (1 << L) : M2L_BOXES;
+    const int64_t mask = (int64_t(1) << L) - 1;
+    constexpr int nrt = PD / 16;
+    const int used = (4 / nrt) * nrt;
+    const int rt = wave % nrt, ct0 = wave / nrt, ctstep = 4 / nrt;
+    DownOps<R, PD> ops;
+    if (wave < used) {
+        load_tile<R, PD>(ops.a4, a.T.m2l4, rt, lane);
+        load_tile<R, PD>(ops.a6, a.T.m2l6, rt, lane);
+    }
+    // the multipoles of boxes b0 - 3 .. b0 + nb + 2 (around the circle),
+    // first PD coefficients (every load of a thread issued first)
+    const V *mpl = a.mp + lev_off(L, a.PU);
+    const int n = (nb + 6) * PD;
+    for (int e0 = 0; e0 < n; e0 += 4 * BLOCK) {
+        V r[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int e = e0 + tid + k * BLOCK;
+            e = e < n ? e : n - 1;
+            const int i = e / PD, m = e - i * PD;
+            r[k] = mpl[((b0 - 3 + i) & mask) * a.PU + m];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e = e0 + tid + k * BLOCK;
+            if (e < n) {
+                const int i = e / PD, m = e - i * PD;
+                st_coef<R, V>(srcs, RS, i, m, r[k]);
+            }
+        }
+    }
+    __syncthreads();
+    const R sgl = KER == KER_COT ? (R)(ldexp(2.0, L) / 3.14159265358979323846) : R(1);
+    const R lgl = KER == KER_LOG ? (R)log(ldexp((double)a.N, -(L + 1))) : R(0);
+    constexpr int NC = ncomp<V>::value;
+    // results straight to memory (each box's row: PD coefficients)
+    R *dst = reinterpret_cast<R *>(a.pre + lev_off(L, PD) + b0 * PD);
+    if (wave < used)
+        m2l_tiles<R, V, KER, PD, false>(
+            ops, rt, ct0, ctstep, lane, nb, srcs, srcs, RS,
+            [&](int i, int o) { return i + 3 + o; }, [&](int) { return 0; },
+            [&](int i) { return ((b0 + i) & 1) == 0; }, [&](int) { return sgl; },
+            [&](int) { return lgl; }, [&](int i) { return i; }, dst, PD * NC);
 }
 
 // Complex load and store through a pointer of any address space (the
@@ -1489,23 +1574,18 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
     const int64_t N = a.N;
     R *cur = bufA;
     if constexpr (PH == PH_TRANS) {
-    const int PU = a.PU;
-
     constexpr int nrt = PD / 16;
     const int used = (4 / nrt) * nrt;
     const int rt = wave % nrt, ct0 = wave / nrt, ctstep = 4 / nrt;
-    // the first level's interaction-list multipoles: in flight during the
+    // the first subtree level's M2L results: in flight during the
     // ancestors' work
-    constexpr int NPF = ((16 + 6) * PD + BLOCK - 1) / BLOCK; // subtrees of <= 4 levels
+    constexpr int NPF = (16 * PD + BLOCK - 1) / BLOCK; // subtrees of <= 4 levels
     V pf[NPF];
     if (lr < a.l)
-        lev_fetch<R, V, PD, NPF>(pf, a, R0, lr, lr + 1, tid);
-    DownOps<R, PD> ops;
-    if (wave < used) {
-        load_tile<R, PD>(ops.a4, a.T.m2l4, rt, lane);
-        load_tile<R, PD>(ops.a6, a.T.m2l6, rt, lane);
-        load_tile<R, PD>(ops.al, a.T.l2l, rt, lane);
-    }
+        pre_fetch<R, V, PD, NPF>(pf, a.pre, R0, lr, lr + 1, tid);
+    R al[PD / 4];
+    if (wave < used)
+        load_tile<R, PD>(al, a.T.l2l, rt, lane);
 
     // ---- local expansion of the subtree root R0 (level lr): the sum over
     // its ancestors A_L (L = 2..lr) of the M2L result at A_L (the regular-
@@ -1513,33 +1593,29 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
     // R0:  u_A = rho u_R + delta,
     //      b^R_n = sum_{n' >= n} C(n', n) rho^n delta^(n'-n) b^A_n'.
     const int nA = lr - 2; // ancestors with M2L: levels 3..lr
-    // stage the three interaction-list multipoles of every ancestor, every
-    // load of a thread issued before its first store
-    for (int b0 = 0; b0 < 3 * nA * PD; b0 += 4 * BLOCK) {
+    // X row 0: the level-2 local of R0's quarter; row li (1..nA): the M2L
+    // result of the ancestor at level li + 2 (all loads issued first)
+    for (int b0 = 0; b0 < (nA + 1) * PD; b0 += 4 * BLOCK) {
         V r[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             int idx = b0 + tid + k * BLOCK;
-            idx = idx < 3 * nA * PD ? idx : 3 * nA * PD - 1; // clamped: no branch
-            const int row = idx / PD, m = idx - row * PD;
-            const int ai = row / 3, which = row - ai * 3;
-            const int L = ai + 3;
-            const int64_t A = R0 >> (lr - L);
-            const int o = which == 0 ? -2 : (which == 1 ? 2 : ((A & 1) ? -3 : 3));
-            const int64_t mask = (int64_t(1) << L) - 1;
-            r[k] = a.mp[lev_off(L, PU) + ((A + o) & mask) * PU + m];
+            idx = idx < (nA + 1) * PD ? idx : (nA + 1) * PD - 1; // clamped: no branch
+            const int li = idx / PD, n = idx - li * PD;
+            r[k] = li == 0 ? a.loc2[(R0 >> (lr - 2)) * PD + n]
+                           : a.pre[lev_off(li + 2, PD) + (R0 >> (lr - 2 - li)) * PD + n];
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int idx = b0 + tid + k * BLOCK;
-            if (idx < 3 * nA * PD) {
-                const int row = idx / PD, m = idx - row * PD;
-                st_coef<R, V>(srcs, RS, row, m, r[k]);
+            if (idx < (nA + 1) * PD) {
+                const int li = idx / PD, n = idx - li * PD;
+                st_coef<R, V>(bufA, RS, li, n, r[k]);
             }
         }
     }
-    // the L2L table, for the shift below, after the source rows
-    R *tl2l = srcs + (size_t)a.rows_src * RS; // PD x PD, [in n'][out n]
+    // the L2L table, for the shift below (after the two level buffers)
+    R *tl2l = srcs; // PD x PD, [in n'][out n]
     {
         static_assert((PD * PD) % BLOCK == 0, "PD^2 must be a multiple of the block");
         R rl[PD * PD / BLOCK];
@@ -1549,22 +1625,6 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
 #pragma unroll
         for (int k = 0; k < PD * PD / BLOCK; ++k)
             tl2l[tid + k * BLOCK] = rl[k];
-    }
-    // X row 0: the level-2 local of R0's quarter
-    for (int n = tid; n < PD; n += BLOCK)
-        st_coef<R, V>(bufA, RS, 0, n, a.loc2[(R0 >> (lr - 2)) * PD + n]);
-    __syncthreads();
-    if (nA > 0 && wave < used) {
-        m2l_tiles<R, V, KER, PD, false>(
-            ops, rt, ct0, ctstep, lane, nA, srcs, srcs, RS,
-            [&](int i, int o) { return 3 * i + (o == -2 ? 0 : (o == 2 ? 1 : 2)); },
-            [&](int) { return 0; },
-            [&](int i) { return ((R0 >> (lr - (i + 3))) & 1) == 0; },
-            [&](int i) {
-                return KER == KER_COT ? (R)(ldexp(2.0, i + 3) / 3.14159265358979323846) : R(1);
-            },
-            [&](int i) { return (R)log(ldexp((double)N, -(i + 4))); },
-            [&](int i) { return i + 1; }, bufA);
     }
     __syncthreads();
     // shift every row of X to the root (bufB rows), then sum; consecutive
@@ -1590,8 +1650,7 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
         st_coef<R, V>(bufB, RS, li, n, vscale(acc, ipow(rho2, n)));
     }
     __syncthreads();
-    // the leaf locals end in bufA after the s levels below, which leaves
-    // bufB and the source buffer free (contiguous) for the near field
+    // the leaf locals end in bufA after the s levels below
     cur = (s & 1) ? bufB : bufA;
     R *nxt = (s & 1) ? bufA : bufB;
     for (int n = tid; n < PD; n += BLOCK) {
@@ -1602,30 +1661,17 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
     }
     __syncthreads();
 
-    // ---- the subtree's levels: L2L from the parent + M2L from the level's
-    // interaction lists (sources staged in LDS, rows first - 3 ...)
-    // (the next level's sources are fetched into registers while this
-    // level's translations run)
+    // ---- the subtree's levels: each box's local is its M2L result (staged
+    // in the output rows) plus the L2L of its parent's local (matrix cores;
+    // the next level's M2L results are fetched while this level runs)
     for (int lev = lr + 1; lev <= a.l; ++lev) {
         const int nb = 1 << (lev - lr);
-        // the level's scale factors before the prefetch is issued: computed
-        // after it, they held up the loads' registers
-        const R sgl = KER == KER_COT ? (R)(ldexp(2.0, lev) / 3.14159265358979323846) : R(1);
-        const R lgl = KER == KER_LOG ? (R)log(ldexp((double)N, -(lev + 1))) : R(0);
-        lev_stage<R, V, PD, NPF>(pf, srcs, RS, lr, lev, tid);
+        pre_stage<R, V, PD, NPF>(pf, nxt, RS, nb, tid);
         __syncthreads();
         if (lev < a.l)
-            lev_fetch<R, V, PD, NPF>(pf, a, R0, lr, lev + 1, tid);
-        if (wave < used) {
-            m2l_tiles<R, V, KER, PD, true>(
-                ops, rt, ct0, ctstep, lane, nb, srcs, cur, RS,
-                [&](int i, int o) { return i + 3 + o; },
-                [&](int i) { return i >> 1; },
-                [&](int i) { return (i & 1) == 0; },
-                [&](int) { return sgl; },
-                [&](int) { return lgl; },
-                [&](int i) { return i; }, nxt);
-        }
+            pre_fetch<R, V, PD, NPF>(pf, a.pre, R0, lr, lev + 1, tid);
+        if (wave < used)
+            l2l_tiles<R, V, PD>(al, rt, ct0, ctstep, lane, nb, cur, nxt, RS);
         __syncthreads();
         R *t = cur;
         cur = nxt;
@@ -1911,10 +1957,17 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
     }
 }
 
-// at least 3 waves per SIMD (at most 168 VGPRs + AGPRs) up to 32 terms; 2
-// beyond, whose operator tiles would spill under that bound
+// The M2L of every box (levels 3..l), one launch.
+template <typename R, typename V, int KER, int PD>
+__global__ void __launch_bounds__(BLOCK) k_m2l(DownArgs<R, V> a, UpArgs<R, V> ua)
+{
+    m2l_body<R, V, KER, PD>(a, ua, blockIdx.x);
+}
+
+// at least 4 waves per SIMD (at most 128 VGPRs) up to 32 terms (the L2L
+// tile is the only operator held in registers); 2 beyond
 template <typename R, typename V, int KER, int SRC, int EPI, int PD>
-__global__ void __launch_bounds__(BLOCK, (PD <= 32 ? 3 : 2)) k_down_trans(DownArgs<R, V> a)
+__global__ void __launch_bounds__(BLOCK, (PD <= 32 ? 4 : 2)) k_down_trans(DownArgs<R, V> a)
 {
     down_eval_body<R, V, KER, SRC, EPI, PD, PH_TRANS>(a, blockIdx.x);
 }
@@ -1938,6 +1991,15 @@ __device__ __forceinline__ void down_batched(const DownArgs<R, V> *aa, BlockMap 
     // the arguments read in place (a copy of them ended up in scratch
     // memory); the per-call pointers come from the table they point to
     down_eval_body<R, V, KER, SRC, EPI, PD, PH, true>(aa[t], blk);
+}
+
+template <typename R, typename V, int KER, int PD>
+__global__ void __launch_bounds__(BLOCK) kb_m2l(const DownArgs<R, V> *aa, BlockMap bm,
+                                                const UpArgs<R, V> *uu)
+{
+    int blk, nblk;
+    const int t = bm_find(bm, blockIdx.x, &blk, &nblk);
+    m2l_body<R, V, KER, PD>(aa[t], uu[t], blk);
 }
 
 template <typename R, typename V, int KER, int SRC, int EPI, int PD>
