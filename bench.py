@@ -25,37 +25,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "(N+M)/s at rel-ℓ2 1e-12 (FP64) vs 1e-6 (mixed), N=M=2^20 fwd+inv"
-PEAK_FP64 = 78.6e12      # MI355X FP64 vector (and matrix) FLOP/s
-PEAK_FP32 = 157.3e12     # MI355X FP32 vector FLOP/s
+PEAK_FP64 = 78.6e12      # MI355X FP64 vector and matrix FLOP/s
+PEAK_FP32 = 157.3e12     # MI355X FP32 vector and matrix FLOP/s
 PEAK_HBM = 8.0e12        # B/s
-# HBM bytes per launch of the downward kernels from FETCH_SIZE and WRITE_SIZE
-# (rocprofv3 --pmc, one counter per run), each scaled by what the counter
-# reads for a plain 256 MiB elementwise kernel (fetch x2.000, write x1.000).
-# Valid only for the kernel sources they were taken on: any change to them
-# turns the figure back into null until the counters are taken again.
-TRAFFIC = {
-    "k_down_trans<double,cot,uniform sources,forward>": {
-        "src_sha256": "813c8cdda1b43705f052e8d12d159b483bae82577d2b0f8752f7dc988c2d4398",
-        "fetch": 33628461, "write": 8388600, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
-    "k_down_eval<double,cot,uniform sources,forward>": {
-        "src_sha256": "813c8cdda1b43705f052e8d12d159b483bae82577d2b0f8752f7dc988c2d4398",
-        "fetch": 44498491, "write": 34097133, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
-    "k_down_trans<double,cot,sorted sources,inverse>": {
-        "src_sha256": "813c8cdda1b43705f052e8d12d159b483bae82577d2b0f8752f7dc988c2d4398",
-        "fetch": 66970646, "write": 16777200, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
-    "k_down_eval<double,cot,sorted sources,inverse>": {
-        "src_sha256": "813c8cdda1b43705f052e8d12d159b483bae82577d2b0f8752f7dc988c2d4398",
-        "fetch": 64063607, "write": 16777200, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
-    "k_down_trans<double,log,sorted sources,log-sums>": {
-        "src_sha256": "813c8cdda1b43705f052e8d12d159b483bae82577d2b0f8752f7dc988c2d4398",
-        "fetch": 33863829, "write": 8388600, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
-    "k_down_eval<double,log,sorted sources,log-sums>": {
-        "src_sha256": "813c8cdda1b43705f052e8d12d159b483bae82577d2b0f8752f7dc988c2d4398",
-        "fetch": 32920440, "write": 25199584, "summary": "profiles/bench_kernels_2p20_traffic.txt"},
-}
-PHASES = ("fwd_plan_ms", "fwd_up_ms", "fwd_trans_ms", "fwd_eval_ms", "inv_plan_ms",
-          "inv_up_ms", "inv_trans_ms", "inv_eval_ms", "log_up_ms", "log_trans_ms",
-          "log_eval_ms")
+# HBM bytes per launch of each phase, from FETCH_SIZE and WRITE_SIZE
+# (rocprofv3 --pmc, one counter per run) summed over the phase's kernels,
+# each scaled by what the counter reads for a plain 256 MiB elementwise
+# kernel (fetch x2.000, write x1.000).  Valid only for the kernel sources
+# they were taken on: any change to them turns the figure back into null
+# until the counters are taken again.
+TRAFFIC_SRC_SHA256 = None
+TRAFFIC = {}
+# phase keys of one step (ms): plan wall time, then each measured phase
+PHASES = ("fwd_plan_ms", "fwd_sort_ms", "fwd_up_ms", "fwd_trans_ms", "fwd_eval_ms",
+          "inv_plan_ms", "inv_sort_ms", "log_up_ms", "log_trans_ms", "log_eval_ms",
+          "inv_up_ms", "inv_trans_ms", "inv_eval_ms")
 
 
 def parse():
@@ -87,45 +71,55 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def traffic_of(kernel):
-    t = TRAFFIC.get(kernel)
-    if t is None or t["src_sha256"] != kernel_sources_sha256():
+def traffic_of(phase):
+    t = TRAFFIC.get(phase)
+    if t is None or TRAFFIC_SRC_SHA256 != kernel_sources_sha256():
         return None
-    return t["fetch"] + t["write"]
+    return t
 
 
-def trans_flops(info):
-    """Algorithmic flops of one downward-translation launch (cot FMM, complex
-    data, real operators): per box of levels 3..lmax one triangular L2L
-    (P(P+1)/2 complex-by-real multiply-adds, 4 flops each) and 3 M2L
-    (P^2 each), i.e. 2P(P+1) + 12P^2."""
-    P, l = info.nterms, info.lmax
-    boxes = (1 << (l + 1)) - 8 if l >= 3 else 0
-    return boxes * (2 * P * (P + 1) + 12 * P * P)
+def boxes(l, lo=3):
+    """Boxes of levels lo..l of the binary tree (2^lo + ... + 2^l)."""
+    return (1 << (l + 1)) - (1 << lo) if l >= lo else 0
 
 
-def eval_flops(info, n_targets, n_sources):
-    """Algorithmic flops of one evaluation launch: 3 N_t N_s / 2^lmax
-    near-field pairs (Eq. 23) at 6 flops (difference, reciprocal,
-    complex-by-real multiply-add) and a P-term complex Horner L2P (4 flops
-    per term) per target."""
-    P, l = info.nterms, info.lmax
+def trans_flops(l, P, complex_data=True):
+    """Algorithmic flops of the downward translations: per box of levels
+    3..l three M2L (P^2 multiply-adds each) and one triangular L2L
+    (P(P+1)/2), 4 flops per multiply-add of a complex by a real, 2 for real
+    data: 12 P^2 + 2 P(P+1) per box (complex), half that for the log-sums."""
+    f = boxes(l) * (12 * P * P + 2 * P * (P + 1))
+    return f if complex_data else f // 2
+
+
+def eval_flops(l, P, n_targets, n_sources):
+    """Algorithmic flops of one cot evaluation: 3 N_t N_s / 2^l near-field
+    pairs (Eq. 23) at 6 flops (difference, reciprocal, complex-by-real
+    multiply-add) and a P-term complex Horner L2P (4 flops per term) per
+    target."""
     return 3.0 * n_targets * n_sources / (1 << l) * 6.0 + n_targets * 4.0 * P
 
 
-def log_trans_flops(lmax, P):
-    """The translations of the log-sum FMM: real data, so half the complex
-    count of trans_flops: P(P+1) + 6P^2 per box of levels 3..lmax."""
-    boxes = (1 << (lmax + 1)) - 8 if lmax >= 3 else 0
-    return boxes * (P * (P + 1) + 6 * P * P)
-
-
-def log_eval_flops(lmax, P, n):
+def log_eval_flops(l, P, n):
     """The log-sum evaluation at its 2n targets (the n uniform points and the
-    n sources): 3 (2n) n / 2^lmax near-field pairs (Eq. 23) at 3 flops
+    n sources): 3 (2n) n / 2^l near-field pairs (Eq. 23) at 3 flops
     (integer and fractional differences, product) and a P-term real Horner
     L2P (2 flops per term) per target."""
-    return 3.0 * (2 * n) * n / (1 << lmax) * 3.0 + 2 * n * 2.0 * P
+    return 3.0 * (2 * n) * n / (1 << l) * 3.0 + 2 * n * 2.0 * P
+
+
+def up_bytes(l, PU, n, src_bytes, coef_bytes):
+    """Algorithmic HBM bytes of an upward pass: the sources read once
+    (src_bytes each: weights and, for sorted sources, grid units and leaf)
+    and every multipole of levels 2..l written once (PU coefficients of
+    coef_bytes per box)."""
+    return n * src_bytes + boxes(l, 2) * PU * coef_bytes
+
+
+def sort_bytes(n):
+    """Algorithmic HBM bytes of a sort: y read once (8 B per point), the
+    sorted point (grid units and index, 16 B) written once."""
+    return 24.0 * n
 
 
 def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
@@ -154,13 +148,16 @@ def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
     ph = {k: [] for k in ("fwd_up", "fwd_trans", "fwd_eval", "inv_up", "inv_trans",
                           "inv_eval", "fwd_plan", "inv_plan", "log_up", "log_trans",
-                          "log_eval")}
+                          "log_eval", "fwd_sort", "inv_sort")}
     log_terms = 0
     info_f = info_i = None
     for it in range(warmup + steps):
+        fn.set_timing(True)   # events around the sort (and the log-sum FMM)
         t = time.perf_counter()
         pf = fn.Plan.forward(N, yu, eps, dtc)
         tpf = time.perf_counter() - t
+        fn.set_timing(False)
+        sort_f = pf.timings()["sort_ms"]
         ev[0].record()
         pf.execute_phase(f, g, 0)
         ev[1].record()
@@ -179,6 +176,7 @@ def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
         fn.set_timing(False)
         tl = pi.timings()
         log_terms = tl["log_terms"]
+        sort_i = tl["sort_ms"]
         ev[4].record()
         pi.execute_phase(gj, fo, 0)
         ev[5].record()
@@ -197,6 +195,8 @@ def run_path(fn, torch, N, M, yu, f, yj, gj, eps, steps, warmup):
             ph["inv_eval"].append(ev[6].elapsed_time(ev[7]))
             ph["fwd_plan"].append(tpf * 1e3)
             ph["inv_plan"].append(tpi * 1e3)
+            ph["fwd_sort"].append(sort_f)
+            ph["inv_sort"].append(sort_i)
             ph["log_up"].append(tl["log_up_ms"])
             ph["log_trans"].append(tl["log_trans_ms"])
             ph["log_eval"].append(tl["log_eval_ms"])
@@ -305,6 +305,28 @@ def run_clustered(fn, torch, workloads, N, steps, warmup):
     return out
 
 
+def run_adjoint(fn, torch, workloads, N, steps, warmup):
+    """Adjoint transform f = K^H g (the type-1 direction), N = M, uniform y,
+    one-shot, both precision paths."""
+    y, f, c = workloads.forward_case(N, N, "uniform", seed=5)
+    yd = torch.from_numpy(y).cuda()
+    g64 = torch.from_numpy(f).cuda()      # any M values serve as the input
+    out = {"N": N, "M": N}
+    for name, dt, eps in (("f64", torch.complex128, 1e-12), ("mixed", torch.complex64, 1e-6)):
+        gx = g64.to(dt)
+        fo = torch.empty(N, dtype=dt, device="cuda")
+        for _ in range(warmup):
+            fn.nufft_adj(yd, gx, N, eps, out=fo)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn.nufft_adj(yd, gx, N, eps, out=fo)
+        torch.cuda.synchronize()
+        dtm = (time.perf_counter() - t) / steps
+        out[name] = {"eps": eps, "ms": dtm * 1e3, "points_per_s": 2 * N / dtm}
+    return out
+
+
 def cpu_baseline(N, M, yu, f, yj, seconds):
     """The oracle (direct sums, unchanged) on a bounded sample of the same
     workload, extrapolated to the full transforms: forward cost per target
@@ -339,6 +361,60 @@ def cpu_baseline(N, M, yu, f, yj, seconds):
                       f"and cot sum) of the N=M=2^{int(np.log2(N))} workload, "
                       f"{tf + ti:.1f} s measured, extrapolated linearly to all "
                       f"N + M outputs ({t_pair:.0f} s per fwd+inv pair)"}
+
+
+def phase_table(res, N, M, mixed):
+    """Every measured phase of one step: (key, kernels, bound, work, unit,
+    peak).  Work is algorithmic: flops for the matrix-core translations
+    and the vector evaluations, HBM bytes for the sorts, upward passes and
+    weights (the kernels and their counts are listed in the design notes).
+    The mixed path's cot translations and evaluations are priced against
+    the binary32 peaks, everything in binary64 against the binary64 ones."""
+    fi, ii = res["info_f"], res["info_i"]
+    cb = 8 if mixed else 16                  # bytes of one complex value
+    pk = PEAK_FP32 if mixed else PEAK_FP64
+    lf, li = fi.lmax, ii.lmax
+    T = "TFLOP/s"
+    return [
+        ("fwd_sort", "k_hist k_colscan k_scan_work k_place", "hbm", sort_bytes(M), "GB/s", PEAK_HBM),
+        ("fwd_up", "k_up_band (P2M, M2M)", "hbm", up_bytes(lf, fi.mterms, N, cb, cb), "GB/s", PEAK_HBM),
+        ("fwd_trans", "k_m2l k_down_trans", "mfma", trans_flops(lf, fi.nterms), T, pk),
+        ("fwd_eval", "k_down_eval (forward)", "alu", eval_flops(lf, fi.nterms, M, N), T, pk),
+        ("inv_sort", "k_hist k_colscan k_scan_work k_place k_rank", "hbm", sort_bytes(N), "GB/s", PEAK_HBM),
+        ("log_up", "k_up_band (log-sums)", "hbm", up_bytes(li, ii.log_mterms, N, 16, 8), "GB/s", PEAK_HBM),
+        ("log_trans", "k_m2l k_down_trans (log-sums)", "mfma",
+         trans_flops(li, ii.log_nterms, complex_data=False), T, PEAK_FP64),
+        ("log_eval", "k_down_eval (log-sums, Chat, Dhat)", "alu",
+         log_eval_flops(li, ii.log_nterms, N), T, PEAK_FP64),
+        ("inv_up", "k_weights k_up_band (inverse)", "hbm",
+         N * (16 + 2 * cb + 4) + up_bytes(li, ii.mterms, N, cb + 16, cb), "GB/s", PEAK_HBM),
+        ("inv_trans", "k_m2l k_down_trans (inverse)", "mfma", trans_flops(li, ii.nterms), T, pk),
+        ("inv_eval", "k_down_eval (inverse)", "alu", eval_flops(li, ii.nterms, N, N), T, pk),
+    ]
+
+
+def roofline(res, N, M, mixed):
+    """The dominant kernel (the longest phase that is a single kernel; the
+    sorts, upward passes and translations take several launches) with its
+    fraction of the roof that bounds it, and every phase under `others`."""
+    rows = {}
+    for key, kern, bound, work, unit, peak in phase_table(res, N, M, mixed):
+        ms = res[key + "_ms"]
+        rate = work / (ms * 1e-3)
+        scale = 1e9 if unit == "GB/s" else 1e12
+        rows[key] = {"kernels": kern, "bound": bound, "ms": ms,
+                     "achieved": rate / scale, "peak": peak / scale, "unit": unit,
+                     "frac": rate / peak, "work": work,
+                     "work_unit": "bytes" if unit == "GB/s" else "flops",
+                     "traffic": traffic_of(key)}
+    dom = max((k for k in rows if len(rows[k]["kernels"].split()) == 1 or
+               rows[k]["kernels"].startswith("k_down_eval")),
+              key=lambda k: rows[k]["ms"])
+    d = rows[dom]
+    return {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
+            "unit": d["unit"], "frac": d["frac"], "traffic": d["traffic"],
+            "traffic_unit": "bytes per launch", "kernel": dom + ": " + d["kernels"],
+            "work_per_launch": d["work"], "avg_launch_ms": d["ms"], "others": rows}
 
 
 def main():
@@ -387,32 +463,7 @@ def main():
         acc["fwd_rel_l2_vs_oracle_64"] = float(np.linalg.norm(g_h[sel] - ref) / np.linalg.norm(ref))
 
     info_f, info_i = res["info_f"], res["info_i"]
-    # dominant kernel: the longest of the downward translation and evaluation
-    # kernels of the two transforms and of the inverse setup's log-sum FMM
-    # (each timed alone with events)
-    cands = [
-        ("k_down_trans<double,cot,uniform sources,forward>", "mfma", trans_flops(info_f),
-         res["fwd_trans_ms"]),
-        ("k_down_eval<double,cot,uniform sources,forward>", "alu",
-         eval_flops(info_f, M, N), res["fwd_eval_ms"]),
-        ("k_down_trans<double,cot,sorted sources,inverse>", "mfma", trans_flops(info_i),
-         res["inv_trans_ms"]),
-        ("k_down_eval<double,cot,sorted sources,inverse>", "alu",
-         eval_flops(info_i, N, N), res["inv_eval_ms"]),
-        ("k_down_trans<double,log,sorted sources,log-sums>", "mfma",
-         log_trans_flops(info_i.lmax, res["log_terms"]), res["log_trans_ms"]),
-        ("k_down_eval<double,log,sorted sources,log-sums>", "alu",
-         log_eval_flops(info_i.lmax, res["log_terms"], N), res["log_eval_ms"]),
-    ]
-    dom, bound, fl, dur_ms = max(cands, key=lambda c: c[3])
-    dur = dur_ms * 1e-3
-    roof = {"bound": bound, "achieved": fl / dur / 1e12, "peak": PEAK_FP64 / 1e12,
-            "unit": "TFLOP/s", "frac": fl / dur / PEAK_FP64, "traffic": traffic_of(dom), "traffic_unit": "bytes per launch",
-            "kernel": dom, "flops_per_launch": fl, "avg_launch_ms": dur_ms,
-            "others": {c[0]: {"bound": c[1], "tflops": c[2] / (c[3] * 1e-3) / 1e12,
-                              "frac": c[2] / (c[3] * 1e-3) / PEAK_FP64, "ms": c[3],
-                              "traffic": traffic_of(c[0])}
-                       for c in cands}}
+    roof = roofline(res, N, M, mixed=False)
 
     out = {
         "metric": METRIC,
@@ -446,6 +497,7 @@ def main():
                  "speedup_vs_f64": res["ms_per_step"] / rm["ms_per_step"],
                  "exec_only_ms_per_step": rm["exec_ms_per_step"],
                  "phases_ms": {k: round(rm[k], 4) for k in PHASES},
+                 "roofline": roofline(rm, N, M, mixed=True),
                  "inv_roundtrip_rel_l2": float(np.linalg.norm(fo_m - f_h) / np.linalg.norm(f_h))}
         if not args.no_cpu_baseline:
             import oracle
@@ -456,6 +508,7 @@ def main():
     if not args.no_extra:
         out["forward_clustered"] = run_clustered(fn, torch, workloads, N, args.steps,
                                                  args.warmup)
+        out["adjoint"] = run_adjoint(fn, torch, workloads, N, args.steps, args.warmup)
         out["batched_512"] = run_batched(fn, torch, workloads, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, M, yu_h, f_h, yj_h, args.cpu_seconds)

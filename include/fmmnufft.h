@@ -96,6 +96,10 @@ typedef struct {
                       or a smaller value calibrated for the relative l2
                       target when p was not given, rounded up to 16       */
     double eps;
+    int32_t mterms;     /* terms of the multipole expansions (>= nterms and
+                           >= 2q, rounded up to 16)                        */
+    int32_t log_nterms; /* inverse plans: local and multipole terms of the */
+    int32_t log_mterms; /* log-sum FMM (0 for other plans)                */
 } fn_plan_info;
 
 /* Forward interpolation (problem i): g_j = sum_k K_jk f_k, Eq. (p2).
@@ -150,9 +154,10 @@ int nufft_plan_adj(fn_plan **plan, int64_t N, int64_t M, const double *y,
 int nufft_execute(fn_plan *plan, const void *in, void *out, void *stream);
 
 /* One part of nufft_execute: phase 0 is the upward pass (P2M at the leaves,
- * M2M to level 2, level-2 regular part), phase 1 the downward translations
- * (M2L, L2L down to the leaf locals; one kernel), phase 2 the evaluation at
- * the targets (L2P, near field, epilogue; one kernel).  nufft_execute is
+ * M2M to level 2), phase 1 the downward translations (the M2L of every box
+ * with the level-2 regular part, then L2L down to the leaf locals; two
+ * kernels), phase 2 the evaluation at the targets (L2P, near field,
+ * epilogue; one kernel).  nufft_execute is
  * phases 0, 1, 2 in order on one stream; calling them separately lets a
  * caller bracket each with events.  Each phase reads the plan workspace the
  * previous one wrote, so the three must be enqueued in order, with the same
@@ -178,19 +183,20 @@ int nufft_plan_coeffs(const fn_plan *plan, double *chat, void *dhat, void *strea
 /* Reports the parameters of a plan. */
 int nufft_plan_get_info(const fn_plan *plan, fn_plan_info *info);
 
-/* Measurement of the inverse setup (for benchmarks; not needed otherwise).
- * With timing on (on != 0; it is off at load), every inverse plan created
- * afterwards records HIP events on its stream around the three passes of its
- * log-sum FMM (Eq. p8): the upward pass with the level-2 regular part, the
- * downward translations, and the evaluation (which also forms Chat, Dhat).
- * The switch is process-wide.  Always FN_OK. */
+/* Measurement of the setup (for benchmarks; not needed otherwise).  With
+ * timing on (on != 0; it is off at load), every plan created afterwards
+ * records HIP events on its stream around the sort of its points, and an
+ * inverse plan also around the three passes of its log-sum FMM (Eq. p8):
+ * the upward pass, the downward translations (with the level-2 regular
+ * part), and the evaluation (which also forms Chat, Dhat).  The switch is
+ * process-wide.  Always FN_OK. */
 int nufft_set_timing(int on);
 
-/* ms[0..2]: durations (milliseconds) of those three passes for this plan,
- * read when its setup synchronised; -1 when not recorded (timing off, or a
- * forward plan).  *log_terms (if log_terms is not NULL): the expansion
- * length of the log-sum FMM (0 for a forward plan).  FN_EINVAL for a NULL
- * plan or ms. */
+/* ms[0..3]: durations (milliseconds) of those three passes (ms[0..2]) and
+ * of the sort (ms[3]) for this plan, read when its setup synchronised; -1
+ * when not recorded (timing off, or no log-sum FMM in a forward or adjoint
+ * plan).  *log_terms (if log_terms is not NULL): the expansion length of
+ * the log-sum FMM (0 without one).  FN_EINVAL for a NULL plan or ms. */
 int nufft_plan_get_timings(const fn_plan *plan, float *ms, int32_t *log_terms);
 
 /* The paper's parameters for (N, M, eps, dtype): the truncation numbers of

@@ -52,7 +52,8 @@ class PlanInfo(ctypes.Structure):
                 ("kind", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("p", ctypes.c_int32), ("q", ctypes.c_int32),
                 ("lmax", ctypes.c_int32), ("nterms", ctypes.c_int32),
-                ("eps", ctypes.c_double)]
+                ("eps", ctypes.c_double), ("mterms", ctypes.c_int32),
+                ("log_nterms", ctypes.c_int32), ("log_mterms", ctypes.c_int32)]
 
 
 _lib = None
@@ -203,14 +204,14 @@ class Plan:
         return out
 
     def timings(self):
-        """Inverse plans created with timing on (set_timing): milliseconds of
-        the log-sum FMM's upward pass, translations and evaluation, and its
-        expansion length; -1 entries when not recorded."""
-        ms = (ctypes.c_float * 3)()
+        """Plans created with timing on (set_timing): milliseconds of the sort
+        and (inverse plans) of the log-sum FMM's upward pass, translations and
+        evaluation, and its expansion length; -1 entries when not recorded."""
+        ms = (ctypes.c_float * 4)()
         terms = ctypes.c_int32()
         _check(load_library().nufft_plan_get_timings(self._h, ms, ctypes.byref(terms)))
         return {"log_up_ms": ms[0], "log_trans_ms": ms[1], "log_eval_ms": ms[2],
-                "log_terms": terms.value}
+                "sort_ms": ms[3], "log_terms": terms.value}
 
     def coeffs(self):
         """Inverse plans: (Chat, Dhat) of Eq. (p8), rescaled by 2^N and 2^-N

@@ -479,7 +479,7 @@ struct FmmSetup {
     size_t m2l_smem = 0; // M2L kernel (with the level-2 regular part)
     size_t dn_smem = 0; // evaluation kernel
     size_t tr_smem = 0; // translation kernel
-    int rows_buf = 0, rows_src = 0, near_bytes = 0;
+    int rows_buf = 0, rows_src = 0, near_bytes = 0, grp_lds = 0;
     int stage_cap = 0; // first upward band: sorted sources staged in LDS
 };
 
@@ -503,9 +503,10 @@ struct fn_plan {
     Buf flags;
     // (measurement) events around the inverse setup's log-sum FMM passes,
     // recorded when timing is on, and their durations (ms; -1 if not taken)
-    hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
-    float tms[3] = {-1.f, -1.f, -1.f};
-    int log_terms = 0;
+    // (tev 0..3: the inverse setup's log-sum FMM; 4, 5: the sort of the plan)
+    hipEvent_t tev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    float tms[4] = {-1.f, -1.f, -1.f, -1.f};
+    int log_terms = 0, log_mterms = 0; // log-sum FMM expansion lengths
     // temporaries of the setup, released after its synchronisation
     std::vector<Buf> tmp;
     hipStream_t stream = nullptr; // stream of the last call
@@ -723,6 +724,10 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_
         F.dn_smem = std::max(F.dn_smem, std::min(need, std::min(lim, (size_t)48 << 10)));
     }
     F.near_bytes = (int)(F.dn_smem - loc_bytes);
+    // the forward evaluation's grouping of targets by leaf, after the rest
+    F.grp_lds = (int)F.dn_smem;
+    if (!sorted_src && kernel == KER_COT)
+        F.dn_smem += 4 * (((size_t)1 << s) + 1 + FWD_TMAX);
     const int64_t nmp = lev_off(P->l + 1, PU);
     if (!alloc(F.mp, nmp * sizeof(V)) || !alloc(F.loc2, 4 * PD * sizeof(V)) ||
         !alloc(F.S, sizeof(V)) || !alloc(F.pre, lev_off(P->l + 1, PD) * sizeof(V)))
@@ -760,6 +765,7 @@ static void fill_down(const fn_plan *P, const FmmSetup &F, const OpTables<R> &T,
     da.rows_buf = F.rows_buf;
     da.rows_src = F.rows_src;
     da.near_bytes = F.near_bytes;
+    da.grp_lds = F.grp_lds;
     da.work = (const WorkItem *)P->work.p;
     da.nwork = (const int32_t *)P->nwork_dev.p;
     da.mp = (const V *)F.mp.p;
@@ -887,11 +893,17 @@ static int prepare_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
     a.y = y;
     n_over_2pi(P->N, &a.c_hi, &a.c_lo);
     a.N = P->N;
+    a.invN = 1.0 / (double)P->N;
     a.l = P->l;
     a.keyshift = keyshift;
     a.ymax = FN_Y_MAX;
     a.nbins = nbins;
-    a.nblk = lds_path ? (int)std::max<int64_t>(1, std::min<int64_t>(128, (n + 8191) / 8192)) : 0;
+    // histogram blocks: more of them (fuller chip) when the histograms are
+    // small; the column scan takes at most 256
+    a.nblk = !lds_path ? 0
+             : nbins <= 4096
+                 ? (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + 4095) / 4096))
+                 : (int)std::max<int64_t>(1, std::min<int64_t>(128, (n + 8191) / 8192));
     a.chunk = lds_path ? (n + a.nblk - 1) / a.nblk : 0;
     a.um = (int32_t *)tmp_alloc(P, n * 4);
     a.uth = (double *)tmp_alloc(P, n * 8);
@@ -940,7 +952,8 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
         // placement passes
         hipLaunchKernelGGL(k_hist, dim3(a.nblk), dim3(SORT_THREADS), (size_t)nbins * 4, st, a);
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_colscan, dim3(grid_for(nbins)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_colscan, dim3((nbins + CS_COLS - 1) / CS_COLS), dim3(CS_THREADS),
+                           0, st, a);
     } else {
         HIPCHK(hipMemsetAsync(a.tot, 0, (size_t)nbins * 4, st));
         hipLaunchKernelGGL(k_reduce, dim3(grid_for(a.n)), dim3(256), 0, st, a.n, a.y,
@@ -1000,6 +1013,10 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
 // Enqueues only; errors land in P->flags.
 // With w (from prepare_work), the work list of the downward pass is built
 // right after the scan of the sort.
+// Measurement switch (nufft_set_timing): plans created while it is on record
+// events around their sort and the inverse setup's log-sum FMM passes.
+static std::atomic<int> g_timing{0};
+
 static int build_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
                       bool deterministic, bool want_hit, bool records, hipStream_t st,
                       WorkArgs *w = nullptr)
@@ -1012,7 +1029,19 @@ static int build_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
         w->off = (const int32_t *)P->off.p;
         J.work = w;
     }
-    return launch_tree(P, J, st);
+    const bool timed = g_timing.load() != 0;
+    if (timed) {
+        for (int i = 4; i < 6; ++i)
+            if (!P->tev[i] && hipEventCreate(&P->tev[i]) != hipSuccess) {
+                P->tev[i] = nullptr;
+                return fail(FN_EHIP, "event creation failed");
+            }
+        HIPCHK(hipEventRecord(P->tev[4], st));
+    }
+    rc = launch_tree(P, J, st);
+    if (!rc && timed)
+        HIPCHK(hipEventRecord(P->tev[5], st));
+    return rc;
 }
 
 // Work list of k_down_eval, built on the device: subtree roots of level lr;
@@ -1020,7 +1049,7 @@ static int build_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
 // the largest possible list.
 static int prepare_work(fn_plan *P, int sh, bool uniform, int64_t npts, WorkArgs *w)
 {
-    const int32_t tmax = 2048;
+    const int32_t tmax = FWD_TMAX;
     const int64_t nroot = int64_t(1) << P->lr;
     const int64_t maxitems = uniform ? nroot : nroot + npts / tmax + 1;
     if (maxitems > INT32_MAX)
@@ -1079,6 +1108,9 @@ static int finish_plan(fn_plan *P, hipStream_t st)
             if (hipEventElapsedTime(&P->tms[i], P->tev[i], P->tev[i + 1]) != hipSuccess)
                 P->tms[i] = -1.f;
     }
+    if (e == hipSuccess && P->tev[4] &&
+        hipEventElapsedTime(&P->tms[3], P->tev[4], P->tev[5]) != hipSuccess)
+        P->tms[3] = -1.f;
     drop_events(P);
     release_tmp(P);
     if (e != hipSuccess)
@@ -1130,9 +1162,11 @@ static int plan_fwd_impl(fn_plan *P, const double *y, hipStream_t st)
     P->lr = choose_lr(P->l, 2, PD, sizeof(R));
     // targets grouped by leaf: the lanes of a wavefront then share the
     // leaf locals and near-field sources they read
-    // every workspace is allocated before the first launch (the sort)
+    // every workspace is allocated before the first launch (the sort); the
+    // targets are sorted by subtree (the evaluation groups each work item's
+    // targets by leaf in LDS)
     WorkArgs w;
-    int rc = prepare_work(P, P->l - P->lr, false, P->M, &w);
+    int rc = prepare_work(P, 0, false, P->M, &w);
     if (rc)
         return rc;
     rc = setup_fmm<R, cx<R>>(P, KER_COT, PU, PD, P->q, false, P->cot, st);
@@ -1142,7 +1176,7 @@ static int plan_fwd_impl(fn_plan *P, const double *y, hipStream_t st)
     rc = get_tables<R>(KER_COT, PU, PD, P->q, &T);
     if (rc)
         return rc;
-    return build_tree(P, P->M, y, 0, false, false, true, st, &w);
+    return build_tree(P, P->M, y, P->l - P->lr, false, false, true, st, &w);
 }
 
 template <typename R>
@@ -1178,7 +1212,6 @@ static int exec_fwd(fn_plan *P, const void *in, void *out, int phase,
 
 // Event timing of the inverse setup's log-sum FMM (measurement only; off
 // unless nufft_set_timing turns it on).
-static std::atomic<int> g_timing{0};
 
 // The log-kernel FMM of the plan: log|Chat_k| at the uniform points and
 // log|Dhat_j| at the sorted sources, and from them (in the evaluation's
@@ -1215,10 +1248,11 @@ static int plan_inv_logs(fn_plan *P, hipStream_t st)
     ua.logc1 = std::log(2.0 * M_PI / (double)P->N);
     ua.logc2 = std::log(2.0);
     P->log_terms = PD;
+    P->log_mterms = PU;
     const bool timed = g_timing.load() != 0;
     if (timed)
-        for (hipEvent_t &e : P->tev)
-            if (hipEventCreate(&e) != hipSuccess) {
+        for (int i = 0; i < 4; ++i)
+            if (hipEventCreate(&P->tev[i]) != hipSuccess) {
                 drop_events(P);
                 return fail(FN_EHIP, "event creation failed");
             }
@@ -1687,9 +1721,9 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
         int PU, PD;
         cot_lengths(P, &PU, &PD);
         P->lr = choose_lr(P->l, 2, PD, sizeof(R));
-        int rc = prepare_tree(P, P->M, ys[t], 0, false, false, true, &jobs[t]);
+        int rc = prepare_tree(P, P->M, ys[t], P->l - P->lr, false, false, true, &jobs[t]);
         if (!rc)
-            rc = prepare_work(P, P->l - P->lr, false, P->M, &works[t]);
+            rc = prepare_work(P, 0, false, P->M, &works[t]);
         if (!rc)
             rc = setup_fmm<R, V>(P, KER_COT, PU, PD, P->q, false, P->cot, st);
         if (rc)
@@ -1711,7 +1745,7 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
         sa.push_back(a);
         wa.push_back(works[t]);
         nb_hist.push_back(a.nblk);
-        nb_col.push_back(grid_for(a.nbins));
+        nb_col.push_back((a.nbins + CS_COLS - 1) / CS_COLS);
         nb_one.push_back(1);
         hist_smem = std::max(hist_smem, (size_t)a.nbins * 4);
     }
@@ -1801,7 +1835,7 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
         hipLaunchKernelGGL(kb_hist, dim3(B->hist.grid), dim3(SORT_THREADS), B->hist.smem, st,
                            (const SortArgs *)at(B->hist.args), map(B->hist));
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(kb_colscan, dim3(B->colscan.grid), dim3(256), 0, st,
+        hipLaunchKernelGGL(kb_colscan, dim3(B->colscan.grid), dim3(CS_THREADS), 0, st,
                            (const SortArgs *)at(B->colscan.args), map(B->colscan));
         HIPCHK(hipGetLastError());
         hipLaunchKernelGGL(kb_scan_one, dim3(B->scan.grid), dim3(1024), SCAN1_SMEM, st,
@@ -2402,6 +2436,9 @@ int nufft_plan_get_info(const fn_plan *plan, fn_plan_info *info)
     info->lmax = plan->l;
     info->nterms = plan->cot.PD;
     info->eps = plan->eps;
+    info->mterms = plan->cot.PU;
+    info->log_nterms = plan->log_terms;
+    info->log_mterms = plan->log_mterms;
     return FN_OK;
     FN_API_END
 }
@@ -2419,7 +2456,7 @@ int nufft_plan_get_timings(const fn_plan *plan, float *ms, int32_t *log_terms)
     FN_API_BEGIN
     if (!plan || !ms)
         return fail(FN_EINVAL, "plan or ms is NULL");
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 4; ++i)
         ms[i] = plan->tms[i];
     if (log_terms)
         *log_terms = plan->log_terms;

@@ -49,15 +49,16 @@ __host__ __device__ __forceinline__ int64_t lev_off(int L, int P)
 }
 
 // floor((m + th) 2^L / N), clamped to [0, 2^L): the level-L box of the
-// point s = m + th (0 <= m <= N, |th| <= 1/2).  A binary64 estimate, off by
-// at most one, is corrected by exact comparisons: b N - m 2^L is an exact
-// integer (below 2^53) and th 2^L an exact binary64 value.  The sort and
-// the evaluation both use this function, so they always agree.
-__device__ __forceinline__ int64_t box_of(int64_t m, double th, int L, int64_t N)
+// point s = m + th (0 <= m <= N, |th| <= 1/2).  A binary64 estimate (with
+// invN = 1/N rounded, off by at most one) is corrected by exact comparisons:
+// b N - m 2^L is an exact integer (below 2^53) and th 2^L an exact binary64
+// value.  The sort and the evaluation both use this function, so they always
+// agree.
+__device__ __forceinline__ int64_t box_of(int64_t m, double th, int L, int64_t N, double invN)
 {
     const int64_t A = m << L;
     const double tl = ldexp(th, L);
-    int64_t b = (int64_t)floor(((double)A + tl) / (double)N);
+    int64_t b = (int64_t)floor(((double)A + tl) * invN);
     // s >= b N / 2^L  <=>  b N - A <= tl
     if ((double)(b * N - A) > tl)
         --b;

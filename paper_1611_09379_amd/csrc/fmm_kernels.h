@@ -44,6 +44,7 @@ enum { SET_UNIFORM = 0, SET_SORTED = 1 };
 enum { EPI_FWD = 0, EPI_INV = 1, EPI_LOGCD = 2, EPI_ADJ = 3 };
 
 constexpr int BLOCK = 256; // 4 wavefronts of 64
+constexpr int FWD_TMAX = 2048; // forward: most targets of one work item
 
 // Binary32 sums of the near field and of the vector P2M run over blocks of
 // at most this many terms; each block's partial is added into a binary64
@@ -865,6 +866,8 @@ struct DownArgs {
     int rows_buf, rows_src;  // rows of each local buffer / of the source buffer
     int near_bytes;          // LDS bytes free for the near-field sources
                              // once the leaf locals are formed
+    int grp_lds;             // forward evaluation: LDS byte offset of the
+                             // grouping of a work item's targets by leaf
     const WorkItem *work;
     const int32_t *nwork;    // number of valid work items (device)
     const V *mp;             // PU per box
@@ -877,7 +880,7 @@ struct DownArgs {
     const cx<R> *w_sorted;
     // targets
     SortedSet tgt;
-    const int32_t *tgt_leaf; // LOGCD: leaf of every sorted target
+    const int32_t *tgt_leaf; // LOGCD: leaf of every sorted target (required)
     const SortedPt *tgt_pt;  // FWD: sorted targets
     // epilogues
     cx<R> *out;              // FWD: g (input order); INV: f
@@ -1807,7 +1810,42 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
         }
         const V S = *a.S;
         const double hscale = (double)N / 3.14159265358979323846;
-        for (int32_t t = w.t0 + tid; t < w.t1; t += BLOCK) {
+        // the targets arrive sorted by subtree only: group the item's
+        // targets by leaf in LDS (a counting sort of their indices), so that
+        // the lanes of a wavefront share the leaf local and the near-field
+        // sources they read
+        const int nb = 1 << s;
+        const int32_t nt = w.t1 - w.t0; // at most FWD_TMAX
+        int32_t *cnt = reinterpret_cast<int32_t *>(smem_raw + a.grp_lds); // nb + 1
+        int32_t *ord = cnt + (nb + 1);                                     // nt
+        for (int i = tid; i <= nb; i += BLOCK)
+            cnt[i] = 0;
+        __syncthreads();
+        constexpr int GPT = FWD_TMAX / BLOCK; // targets per thread
+        int32_t gl[GPT], gr[GPT];
+#pragma unroll
+        for (int u = 0; u < GPT; ++u) {
+            const int32_t i = tid + u * BLOCK;
+            const SortedPt pt = a.tgt_pt[w.t0 + (i < nt ? i : nt - 1)];
+            gl[u] = (int32_t)(box_of(pt.m, pt.th, a.l, N, invN) - leaf0);
+        }
+#pragma unroll
+        for (int u = 0; u < GPT; ++u)
+            gr[u] = tid + u * BLOCK < nt ? atomicAdd(&cnt[gl[u] + 1], 1) : 0;
+        __syncthreads();
+        if (tid == 0)
+            for (int i = 1; i <= nb; ++i)
+                cnt[i] += cnt[i - 1];
+        __syncthreads();
+        // (index in the item) + (leaf in the subtree) * 2^16
+#pragma unroll
+        for (int u = 0; u < GPT; ++u)
+            if (tid + u * BLOCK < nt)
+                ord[cnt[gl[u]] + gr[u]] = (tid + u * BLOCK) | (gl[u] << 16);
+        __syncthreads();
+        for (int32_t q = tid; q < nt; q += BLOCK) {
+            const int32_t oq = ord[q];
+            const int32_t t = w.t0 + (oq & 0xffff);
             const SortedPt pt = a.tgt_pt[t];
             const int64_t tm = pt.m;
             const double th = pt.th;
@@ -1816,7 +1854,7 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
                 st_cx<R>(out, j, ld_cx<R>(f_hit, tm == N ? 0 : tm));
                 continue;
             }
-            const int64_t leaf = box_of(tm, th, a.l, N);
+            const int64_t leaf = leaf0 + (oq >> 16);
             const R u = (R)rel_coord_r(tm, th, leaf, a.l, N, invN);
             V h = horner4<R, V, PD>(leafloc, RS, (int)(leaf - leaf0), u);
             const cx<double> nr =
@@ -1937,7 +1975,7 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
         for (int32_t t = w.t0 + tid; t < w.t1; t += BLOCK) {
             const int64_t tm = a.tgt.m[t];
             const double th = a.tgt.th[t];
-            const int64_t leaf = a.tgt_leaf ? (int64_t)a.tgt_leaf[t] : box_of(tm, th, a.l, N);
+            const int64_t leaf = a.tgt_leaf[t]; // the sort's key of every point
             const int il = (int)(leaf - leaf0);
             const R u = (R)rel_coord_r(tm, th, leaf, a.l, N, invN);
             V far = horner4<R, V, PD>(leafloc, RS, il, u);

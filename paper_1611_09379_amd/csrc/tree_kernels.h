@@ -37,8 +37,8 @@ __device__ __noinline__ GridUnits grid_units(double y, double c_hi, double c_lo)
 // (and near 1e-308 the binary64) range.  Returns false for a non-finite or
 // too large y.
 __device__ __forceinline__ bool reduce_point(double yy, double c_hi, double c_lo,
-                                             int64_t N, double ymax, int64_t *m_out,
-                                             double *th_out)
+                                             int64_t N, double invN, double ymax,
+                                             int64_t *m_out, double *th_out)
 {
     if (!(fabs(yy) <= ymax)) { // also catches NaN
         *m_out = 0;
@@ -56,9 +56,15 @@ __device__ __forceinline__ bool reduce_point(double yy, double c_hi, double c_lo
     }
     if (fabs(th) < HIT_SNAP)
         th = 0.0;
-    int64_t m = (int64_t)n % N;
-    if (m < 0)
-        m += N;
+    // m = n mod N in binary64: n and q N are integers below 2^53, so the
+    // difference is exact; the quotient estimate is off by at most one
+    const double dN = (double)N;
+    double mr = n - floor(n * invN) * dN;
+    if (mr < 0.0)
+        mr += dN;
+    else if (mr >= dN)
+        mr -= dN;
+    int64_t m = (int64_t)mr;
     if (m == 0 && th < 0.0)
         m = N;
     *m_out = m;
@@ -73,6 +79,7 @@ struct SortArgs {
     const double *y;        // radians
     double c_hi, c_lo;      // N / (2 pi) in double-double
     int64_t N;
+    double invN;            // 1 / N
     int l, keyshift;        // key = level-(l - keyshift) box
     double ymax;
     int64_t chunk;          // points per histogram block
@@ -102,10 +109,10 @@ __device__ __forceinline__ int32_t point_key(const SortArgs &a, double yy, int32
 {
     int64_t m;
     double th;
-    *ok = reduce_point(yy, a.c_hi, a.c_lo, a.N, a.ymax, &m, &th);
+    *ok = reduce_point(yy, a.c_hi, a.c_lo, a.N, a.invN, a.ymax, &m, &th);
     *m_out = (int32_t)m;
     *th_out = th;
-    return (int32_t)(box_of(m, th, a.l, a.N) >> a.keyshift);
+    return (int32_t)(box_of(m, th, a.l, a.N, a.invN) >> a.keyshift);
 }
 
 constexpr int SORT_BATCH = 8;     // points in flight per thread in the sort passes
@@ -173,32 +180,66 @@ __device__ __forceinline__ void hist_body(const SortArgs &a, int blk)
 
 __global__ void __launch_bounds__(SORT_THREADS) k_hist(SortArgs a) { hist_body(a, blockIdx.x); }
 
+
+
 // Counting sort, between the passes: for every key, the exclusive prefix of
-// its counts over the blocks (in place in H) and its total (tot[key]).
-__device__ __forceinline__ void colscan_body(const SortArgs &a, int blk, int nblocks)
+// its counts over the blocks (in place in H) and its total (tot[key]).  A
+// workgroup of 256 threads takes CS_COLS consecutive keys; its threads split
+// the blocks into CS_ROWG row groups, each scanning its rows of a key in
+// registers (every load issued first), then the row groups' totals are
+// scanned in LDS.  Column-parallel alone, a key's blocks would be one
+// dependent chain.
+constexpr int CS_COLS = 32, CS_ROWG = 8, CS_MAXR = 32; // nblk <= ROWG * MAXR
+constexpr int CS_THREADS = CS_COLS * CS_ROWG;
+__device__ __forceinline__ void colscan_body(const SortArgs &a, int blk)
 {
+    __shared__ int32_t part[CS_ROWG][CS_COLS];
     const int nbins = a.nbins, nblk = a.nblk;
     int32_t *H = a.H;
-    for (int64_t k = blk * (int64_t)blockDim.x + threadIdx.x; k < nbins;
-         k += (int64_t)nblocks * blockDim.x) {
-        int32_t run = 0;
-        for (int b0 = 0; b0 < nblk; b0 += SORT_BATCH) {
-            int32_t c[SORT_BATCH];
+    const int c = threadIdx.x % CS_COLS, g = threadIdx.x / CS_COLS;
+    const int64_t k = (int64_t)blk * CS_COLS + c;
+    const int per = (nblk + CS_ROWG - 1) / CS_ROWG; // rows of one group
+    const int r0 = g * per;
+    const bool kv = k < nbins;
+    // rows of this thread: r0 .. r0 + nr - 1, addressed by a running
+    // pointer (per-row offsets held as scalars would spill)
+    const int nr = kv ? max(0, min(per, nblk - r0)) : 0;
+    int32_t *col = H + (int64_t)r0 * nbins + (kv ? k : 0);
+    int32_t v[CS_MAXR];
+    {
+        const int32_t *q = col;
 #pragma unroll
-            for (int u = 0; u < SORT_BATCH; ++u)
-                c[u] = b0 + u < nblk ? H[(int64_t)(b0 + u) * nbins + k] : 0;
-#pragma unroll
-            for (int u = 0; u < SORT_BATCH; ++u) {
-                if (b0 + u < nblk)
-                    H[(int64_t)(b0 + u) * nbins + k] = run;
-                run += c[u];
-            }
+        for (int u = 0; u < CS_MAXR; ++u) {
+            v[u] = u < nr ? *q : 0;
+            q += nbins;
         }
-        a.tot[k] = run;
+    }
+    int32_t run = 0;
+#pragma unroll
+    for (int u = 0; u < CS_MAXR; ++u) {
+        const int32_t x = v[u];
+        v[u] = run;
+        run += x;
+    }
+    part[g][c] = run;
+    __syncthreads();
+    int32_t base = 0;
+    for (int h = 0; h < g; ++h)
+        base += part[h][c];
+    if (kv) {
+        int32_t *q = col;
+#pragma unroll
+        for (int u = 0; u < CS_MAXR; ++u) {
+            if (u < nr)
+                *q = base + v[u];
+            q += nbins;
+        }
+        if (g == CS_ROWG - 1)
+            a.tot[k] = base + run;
     }
 }
 
-__global__ void k_colscan(SortArgs a) { colscan_body(a, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(CS_THREADS) k_colscan(SortArgs a) { colscan_body(a, blockIdx.x); }
 
 // Counting sort, pass 2: block b places its points of every key at
 // off[key] + (points of that key in blocks before b) + its LDS counter.
@@ -297,9 +338,10 @@ __global__ void k_reduce(int64_t M, const double *__restrict__ y, double c_hi,
          j += (int64_t)gridDim.x * blockDim.x) {
         int64_t m;
         double th;
-        if (!reduce_point(y[j], c_hi, c_lo, N, ymax, &m, &th))
+        const double invN = 1.0 / (double)N;
+        if (!reduce_point(y[j], c_hi, c_lo, N, invN, ymax, &m, &th))
             atomicOr(flags, FLAG_BAD_Y);
-        const int32_t key = (int32_t)(box_of(m, th, l, N) >> keyshift);
+        const int32_t key = (int32_t)(box_of(m, th, l, N, invN) >> keyshift);
         um[j] = (int32_t)m;
         uth[j] = th;
         ukey[j] = key;
@@ -309,6 +351,39 @@ __global__ void k_reduce(int64_t M, const double *__restrict__ y, double c_hi,
     }
 }
 
+// Exclusive scan of one value per thread over a workgroup of 1024 threads:
+// wavefront scans by shuffles, then one scan of the 16 wavefront totals
+// (ws: 16 words of LDS).  Two barriers instead of the twenty of a
+// Hillis-Steele scan over LDS.  *total: the sum of all 1024 values.
+__device__ __forceinline__ int32_t block_scan1024(int32_t x, int32_t *ws, int32_t *total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t v = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t t = __shfl_up(v, d);
+        if (lane >= d)
+            v += t;
+    }
+    if (lane == 63)
+        ws[wv] = v;
+    __syncthreads();
+    if (wv == 0) {
+        int32_t u = lane < 16 ? ws[lane] : 0;
+#pragma unroll
+        for (int d = 1; d < 16; d <<= 1) {
+            const int32_t t = __shfl_up(u, d);
+            if (lane >= d)
+                u += t;
+        }
+        if (lane < 16)
+            ws[16 + lane] = u; // inclusive scan of the wavefront totals
+    }
+    __syncthreads();
+    *total = ws[31];
+    return (wv ? ws[16 + wv - 1] : 0) + v - x;
+}
+
 // Exclusive scan of up to SCAN1_MAX counts in one workgroup of 1024 threads:
 // the counts are loaded coalesced into LDS (skewed by one word per 32, so
 // that the per-thread runs below are free of bank conflicts), thread i scans
@@ -316,16 +391,18 @@ __global__ void k_reduce(int64_t M, const double *__restrict__ y, double c_hi,
 // go out coalesced.  off[n] = total; cursor (optional) receives a copy.
 constexpr int SCAN1_PER = 32;
 constexpr int SCAN1_MAX = 1024 * SCAN1_PER;
-__device__ __forceinline__ int scan1_slot(int i) { return i + (i >> 5); }
+__host__ __device__ __forceinline__ int scan1_slot(int i) { return i + (i >> 5); }
 
-__device__ __forceinline__ void scan_one_body(const int32_t *__restrict__ count, int n,
-                                              int32_t *__restrict__ off,
-                                              int32_t *__restrict__ cursor)
+// The scan itself, with the counts staged in sv (scan1_slot(n) + 1 words of
+// LDS) and part (64 words) for the block scan; thread i scans a run of
+// ceil(n / 1024) consecutive counts.  part[63] receives the total.
+__device__ __forceinline__ void scan_block(const int32_t *count, int n,
+                                           int32_t *__restrict__ off,
+                                           int32_t *__restrict__ cursor, int32_t *sv,
+                                           int32_t *part)
 {
-    extern __shared__ int32_t sv[]; // scan1_slot(SCAN1_MAX) + 1024 words
-    int32_t *part = sv + scan1_slot(SCAN1_MAX);
     // 16 loads in flight per thread (indices clamped, values masked)
-    for (int b = 0; b < SCAN1_PER; b += 16) {
+    for (int b = 0; b * 1024 < n; b += 16) {
         int32_t v[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
@@ -335,31 +412,26 @@ __device__ __forceinline__ void scan_one_body(const int32_t *__restrict__ count,
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int i = (int)threadIdx.x + (b + u) * 1024;
-            sv[scan1_slot(i)] = i < n ? v[u] : 0;
+            if (i < n)
+                sv[scan1_slot(i)] = v[u];
         }
     }
     __syncthreads();
-    const int i0 = threadIdx.x * SCAN1_PER;
+    const int per = (n + 1023) / 1024;
+    const int i0 = threadIdx.x * per;
     int32_t sum = 0;
-#pragma unroll 8
-    for (int u = 0; u < SCAN1_PER; ++u)
-        sum += sv[scan1_slot(i0 + u)];
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 run sums
-    for (int d = 1; d < 1024; d <<= 1) {
-        const int32_t t = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
-        __syncthreads();
-        part[threadIdx.x] += t;
-        __syncthreads();
-    }
-    int32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
-#pragma unroll 8
-    for (int u = 0; u < SCAN1_PER; ++u) {
-        const int k = scan1_slot(i0 + u);
-        const int32_t c = sv[k];
-        sv[k] = run;
-        run += c;
+    for (int u = 0; u < per; ++u)
+        if (i0 + u < n)
+            sum += sv[scan1_slot(i0 + u)];
+    int32_t total;
+    int32_t run = block_scan1024(sum, part, &total);
+    for (int u = 0; u < per; ++u) {
+        if (i0 + u < n) {
+            const int k = scan1_slot(i0 + u);
+            const int32_t c = sv[k];
+            sv[k] = run;
+            run += c;
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += 1024) {
@@ -368,8 +440,18 @@ __device__ __forceinline__ void scan_one_body(const int32_t *__restrict__ count,
         if (cursor)
             cursor[i] = v;
     }
-    if (threadIdx.x == 1023)
-        off[n] = part[1023];
+    if (threadIdx.x == 1023) {
+        off[n] = total;
+        part[63] = total; // (after the block scan's 32 words) for callers that go on
+    }
+}
+
+__device__ __forceinline__ void scan_one_body(const int32_t *__restrict__ count, int n,
+                                              int32_t *__restrict__ off,
+                                              int32_t *__restrict__ cursor)
+{
+    extern __shared__ int32_t sv[]; // scan1_slot(SCAN1_MAX) + 1024 words
+    scan_block(count, n, off, cursor, sv, sv + scan1_slot(SCAN1_MAX));
 }
 
 // dynamic LDS of k_scan_one / kb_scan_one
@@ -421,21 +503,14 @@ __global__ void __launch_bounds__(1024)
         v[i - b0] = tsum[i];
         s += v[i - b0];
     }
-    part[tid] = s;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        int32_t x = tid >= d ? part[tid - d] : 0;
-        __syncthreads();
-        part[tid] += x;
-        __syncthreads();
-    }
-    int32_t run = tid == 0 ? 0 : part[tid - 1];
+    int32_t all;
+    int32_t run = block_scan1024(s, part, &all);
     for (int i = b0; i < b1; ++i) {
         tsum[i] = run;
         run += v[i - b0];
     }
     if (tid == 1023)
-        *total = part[1023];
+        *total = all;
 }
 
 __global__ void __launch_bounds__(256)
@@ -688,15 +763,8 @@ __device__ __forceinline__ void work_from(const WorkArgs &w, Off offl, int32_t *
     int32_t s = 0;
     for (int64_t R = r0; R < r1; ++R)
         s += pieces(R);
-    part[tid] = s;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        int32_t x = tid >= d ? part[tid - d] : 0;
-        __syncthreads();
-        part[tid] += x;
-        __syncthreads();
-    }
-    int32_t pos = tid == 0 ? 0 : part[tid - 1];
+    int32_t nall;
+    int32_t pos = block_scan1024(s, part, &nall);
     for (int64_t R = r0; R < r1; ++R) {
         const int32_t t0 = offl(R << sh), t1 = offl((R + 1) << sh);
         if (uniform) {
@@ -710,7 +778,7 @@ __device__ __forceinline__ void work_from(const WorkArgs &w, Off offl, int32_t *
         }
     }
     if (tid == 1023)
-        *w.nitems = part[1023];
+        *w.nitems = nall;
 }
 
 __device__ __forceinline__ void work_body(const WorkArgs &w)
@@ -720,6 +788,8 @@ __device__ __forceinline__ void work_body(const WorkArgs &w)
 }
 
 __global__ void __launch_bounds__(1024) k_work(WorkArgs w) { work_body(w); }
+
+
 
 // The one-block scan of the key totals followed by the work list, built from
 // the offsets while they are still in LDS (one launch and no read-back).
@@ -731,7 +801,7 @@ __global__ void __launch_bounds__(1024) k_scan_work(const int32_t *count, int n,
     scan_one_body(count, n, off, cursor);
     __syncthreads();
     int32_t *part = sv + scan1_slot(SCAN1_MAX);
-    const int32_t total = part[1023];
+    const int32_t total = part[63];
     work_from(w, [&](int64_t i) { return i < n ? sv[scan1_slot((int)i)] : total; },
               part + 1024);
 }
@@ -824,11 +894,11 @@ __global__ void __launch_bounds__(SORT_THREADS) kb_hist(const SortArgs *aa, Bloc
     hist_body(aa[t], blk);
 }
 
-__global__ void __launch_bounds__(256) kb_colscan(const SortArgs *aa, BlockMap bm)
+__global__ void __launch_bounds__(CS_THREADS) kb_colscan(const SortArgs *aa, BlockMap bm)
 {
     int blk, nblk;
     const int t = bm_find(bm, blockIdx.x, &blk, &nblk);
-    colscan_body(aa[t], blk, nblk);
+    colscan_body(aa[t], blk);
 }
 
 // one workgroup per problem

@@ -63,7 +63,7 @@ def test_timing_switch_host_only():
     lib = fn.load_library()
     assert lib.nufft_set_timing(1) == fn.FN_OK
     assert lib.nufft_set_timing(0) == fn.FN_OK
-    ms = (ctypes.c_float * 3)()
+    ms = (ctypes.c_float * 4)()
     assert lib.nufft_plan_get_timings(None, ms, None) == fn.FN_EINVAL
 
 

@@ -167,10 +167,19 @@ def test_setup_timings():
     p1.destroy()
     say("timings", t1)
     assert t1["log_up_ms"] > 0 and t1["log_trans_ms"] > 0 and t1["log_eval_ms"] > 0
+    assert t1["sort_ms"] > 0 and t0["sort_ms"] == -1
     assert np.array_equal(ch0, ch1) and np.array_equal(dh0, dh1)
     pf = fn.Plan.forward(N, yd, 1e-12, fn.FN_C128)
-    assert pf.timings()["log_terms"] == 0
+    assert pf.timings()["log_terms"] == 0 and pf.timings()["sort_ms"] == -1
     pf.destroy()
+    fn.set_timing(True)
+    try:
+        pf = fn.Plan.forward(N, yd, 1e-12, fn.FN_C128)
+    finally:
+        fn.set_timing(False)
+    tf = pf.timings()
+    pf.destroy()
+    assert tf["sort_ms"] > 0 and tf["log_up_ms"] == -1
 
 
 def test_inv_mixed_range():
