@@ -327,6 +327,59 @@ def run_adjoint(fn, torch, workloads, N, steps, warmup):
     return out
 
 
+def run_spectral(fn, torch, workloads, N, steps, warmup):
+    """Spectral transforms (Eq. p1): coefficients -> values at uniform y
+    (forward) and values at a jittered grid -> coefficients (inverse),
+    N = M, both precision paths.  One-shot times, and the uniform DFT's
+    share (rocFFT) as the difference between spectral and plain plan
+    executes on the same points, timed with events."""
+    y, f, c = workloads.forward_case(N, N, "uniform", seed=7)
+    yj, cj = workloads.inverse_case(N, 0.4, seed=8)
+    yd, yjd = torch.from_numpy(y).cuda(), torch.from_numpy(yj).cuda()
+    c64 = torch.from_numpy(c).cuda()
+    out = {"N": N, "M": N}
+    for name, dt, eps in (("f64", torch.complex128, 1e-12), ("mixed", torch.complex64, 1e-6)):
+        dtc = fn.FN_C128 if dt == torch.complex128 else fn.FN_C64
+        cx = c64.to(dt)
+        g = torch.empty(N, dtype=dt, device="cuda")
+        co = torch.empty(N, dtype=dt, device="cuda")
+        fn.nufft_spec_fwd(yd, cx, eps, out=g)
+        gj = fn.nufft_spec_fwd(yjd, cx, eps)
+        for _ in range(warmup):
+            fn.nufft_spec_fwd(yd, cx, eps, out=g)
+            fn.inufft_spec(yjd, gj, eps, out=co)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn.nufft_spec_fwd(yd, cx, eps, out=g)
+            fn.inufft_spec(yjd, gj, eps, out=co)
+        torch.cuda.synchronize()
+        one = (time.perf_counter() - t) / steps
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+        def timed(plan, x, o):
+            for _ in range(2):
+                plan(x, o)
+            ev[0].record()
+            for _ in range(steps):
+                plan(x, o)
+            ev[1].record()
+            torch.cuda.synchronize()
+            return ev[0].elapsed_time(ev[1]) / steps
+
+        pf, psf = fn.Plan.forward(N, yd, eps, dtc), fn.Plan.spectral_forward(N, yd, eps, dtc)
+        pi, psi = fn.Plan.inverse(yjd, eps, dtc), fn.Plan.spectral_inverse(yjd, eps, dtc)
+        tf, tsf = timed(pf, cx, g), timed(psf, cx, g)
+        ti, tsi = timed(pi, gj, co), timed(psi, gj, co)
+        for p_ in (pf, psf, pi, psi):
+            p_.destroy()
+        out[name] = {"eps": eps, "one_shot_fwd_plus_inv_ms": one * 1e3,
+                     "points_per_s": 2 * N / one,
+                     "exec_fwd_ms": tsf, "exec_inv_ms": tsi,
+                     "dft_fwd_ms": tsf - tf, "dft_inv_ms": tsi - ti}
+    return out
+
+
 def cpu_baseline(N, M, yu, f, yj, seconds):
     """The oracle (direct sums, unchanged) on a bounded sample of the same
     workload, extrapolated to the full transforms: forward cost per target
@@ -509,6 +562,7 @@ def main():
         out["forward_clustered"] = run_clustered(fn, torch, workloads, N, args.steps,
                                                  args.warmup)
         out["adjoint"] = run_adjoint(fn, torch, workloads, N, args.steps, args.warmup)
+        out["spectral"] = run_spectral(fn, torch, workloads, N, args.steps, args.warmup)
         out["batched_512"] = run_batched(fn, torch, workloads, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, M, yu_h, f_h, yj_h, args.cpu_seconds)

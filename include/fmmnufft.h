@@ -133,6 +133,21 @@ int inufft(int64_t N, const double *y, const void *g, void *f, double eps,
 int nufft_adj(int64_t N, int64_t M, const double *y, const void *g, void *f,
               double eps, int dtype, void *stream);
 
+/* Spectral transforms (Eq. p1, f(x) = sum_{n=0}^{N-1} c_n e^{inx}), with the
+ * uniform DFT by rocFFT beside the FMM:
+ *   nufft_spec_fwd: g_j = f(y_j) from the coefficients c (N complex):
+ *       f_k = sum_n c_n e^{2 pi i n k / N} (unscaled backward DFT), g = K f;
+ *   inufft_spec (M = N): the coefficients c (N complex, written) of the
+ *       band-limited interpolant through the values g_j: f = L g, then
+ *       c_n = (1/N) sum_k f_k e^{-2 pi i n k / N}.
+ * Arguments, precision paths and errors as nufft_fwd / inufft; the DFT runs
+ * in the dtype's precision.  One-shot: one synchronisation at the end.  A
+ * rocFFT failure returns FN_EHIP. */
+int nufft_spec_fwd(int64_t N, int64_t M, const double *y, const void *c, void *g,
+                   double eps, int dtype, void *stream);
+int inufft_spec(int64_t N, const double *y, const void *g, void *c, double eps,
+                int dtype, void *stream);
+
 /* Setup step of Section 3.3 ("setting the data structure"): everything that
  * depends on the points only.  Forward plan: reduction of y to grid units
  * and the sort of the targets into the leaves of the tree.  Inverse plan:
@@ -146,6 +161,15 @@ int nufft_plan_inv(fn_plan **plan, int64_t N, const double *y, double eps,
 /* Adjoint plan (the sort of the M points y into the leaves). */
 int nufft_plan_adj(fn_plan **plan, int64_t N, int64_t M, const double *y,
                    double eps, int dtype, void *stream);
+/* Spectral plans: a forward or inverse plan plus its rocFFT plan and an
+ * N-value workspace; nufft_execute then maps c -> g (forward) or g -> c
+ * (inverse), reusing the setup for any number of inputs on the same points
+ * (Section 3.3).  nufft_execute_phase: the forward's DFT runs at the start
+ * of phase 0, the inverse's at the end of phase 2. */
+int nufft_plan_spec_fwd(fn_plan **plan, int64_t N, int64_t M, const double *y,
+                        double eps, int dtype, void *stream);
+int nufft_plan_spec_inv(fn_plan **plan, int64_t N, const double *y, double eps,
+                        int dtype, void *stream);
 
 /* Evaluation step of Section 3.3: out = K in (forward plan), out = L in
  * (inverse plan) or out = K^H in (adjoint plan).  in/out sizes: forward

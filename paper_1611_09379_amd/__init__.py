@@ -28,8 +28,9 @@ STATUS_NAMES = {0: "FN_OK", 1: "FN_EINVAL", 2: "FN_ENOMEM", 3: "FN_EHIP",
                 4: "FN_ESINGULAR", 5: "FN_ERANGE", 6: "FN_EPREC"}
 
 ABI_SYMBOLS = (
-    "nufft_fwd", "inufft", "nufft_adj", "nufft_plan_fwd", "nufft_plan_inv",
-    "nufft_plan_adj", "nufft_plan_fwd_ex", "nufft_plan_inv_ex",
+    "nufft_fwd", "inufft", "nufft_adj", "nufft_spec_fwd", "inufft_spec",
+    "nufft_plan_fwd", "nufft_plan_inv", "nufft_plan_adj", "nufft_plan_spec_fwd",
+    "nufft_plan_spec_inv", "nufft_plan_fwd_ex", "nufft_plan_inv_ex",
     "nufft_plan_adj_ex", "nufft_execute",
     "nufft_execute_phase",
     "nufft_destroy", "nufft_plan_get_info", "nufft_plan_coeffs",
@@ -81,6 +82,10 @@ def load_library(path: str = LIB_PATH):
         "nufft_fwd": [i64, i64, vp, vp, vp, dbl, ctypes.c_int, vp],
         "inufft": [i64, vp, vp, vp, dbl, ctypes.c_int, vp],
         "nufft_adj": [i64, i64, vp, vp, vp, dbl, ctypes.c_int, vp],
+        "nufft_spec_fwd": [i64, i64, vp, vp, vp, dbl, ctypes.c_int, vp],
+        "inufft_spec": [i64, vp, vp, vp, dbl, ctypes.c_int, vp],
+        "nufft_plan_spec_fwd": [pp, i64, i64, vp, dbl, ctypes.c_int, vp],
+        "nufft_plan_spec_inv": [pp, i64, vp, dbl, ctypes.c_int, vp],
         "nufft_plan_adj": [pp, i64, i64, vp, dbl, ctypes.c_int, vp],
         "nufft_plan_adj_ex": [pp, i64, i64, vp, dbl, ctypes.c_int, i32, i32, i32, vp],
         "nufft_plan_fwd": [pp, i64, i64, vp, dbl, ctypes.c_int, vp],
@@ -198,6 +203,26 @@ class Plan:
             _stream()))
         return cls(h, 2, N, y.shape[0], dtype)
 
+    @classmethod
+    def spectral_forward(cls, N: int, y, eps: float, dtype: int = FN_C128):
+        """Spectral forward plan: coefficients c (N) -> values g_j = f(y_j)
+        (Eq. p1), the uniform DFT by rocFFT, then the forward FMM."""
+        _check_y(y)
+        h = ctypes.c_void_p()
+        _check(load_library().nufft_plan_spec_fwd(
+            ctypes.byref(h), N, y.shape[0], _dev_ptr(y, "y"), eps, dtype, _stream()))
+        return cls(h, 0, N, y.shape[0], dtype)
+
+    @classmethod
+    def spectral_inverse(cls, y, eps: float, dtype: int = FN_C128):
+        """Spectral inverse plan (M = N): values g_j -> coefficients c."""
+        _check_y(y)
+        h = ctypes.c_void_p()
+        N = y.shape[0]
+        _check(load_library().nufft_plan_spec_inv(
+            ctypes.byref(h), N, _dev_ptr(y, "y"), eps, dtype, _stream()))
+        return cls(h, 1, N, N, dtype)
+
     def info(self) -> PlanInfo:
         out = PlanInfo()
         _check(load_library().nufft_plan_get_info(self._h, ctypes.byref(out)))
@@ -288,6 +313,36 @@ def inufft(y, g, eps: float, out=None):
         out = torch.empty(N, dtype=g.dtype, device=g.device)
     _check(load_library().inufft(N, _dev_ptr(y, "y"), _dev_ptr(g, "g"),
                                  _dev_ptr(out, "f"), eps, dt, _stream()))
+    return out
+
+
+def nufft_spec_fwd(y, c, eps: float, out=None):
+    """g_j = sum_n c_n e^{i n y_j} (Eq. p1) from the coefficients c, one shot
+    (rocFFT for the uniform DFT, then the forward FMM)."""
+    torch = _torch()
+    _check_y(y)
+    dt = _dtype_code(c)
+    N, M = c.shape[0], y.shape[0]
+    if out is None:
+        out = torch.empty(M, dtype=c.dtype, device=c.device)
+    _check(load_library().nufft_spec_fwd(N, M, _dev_ptr(y, "y"), _dev_ptr(c, "c"),
+                                         _dev_ptr(out, "g"), eps, dt, _stream()))
+    return out
+
+
+def inufft_spec(y, g, eps: float, out=None):
+    """The coefficients c of the band-limited interpolant through the values
+    g_j at the points y (M = N), one shot (inverse FMM, then rocFFT)."""
+    torch = _torch()
+    _check_y(y)
+    dt = _dtype_code(g)
+    N = y.shape[0]
+    if g.shape != (N,):
+        raise ValueError("g must have the shape of y (M = N)")
+    if out is None:
+        out = torch.empty(N, dtype=g.dtype, device=g.device)
+    _check(load_library().inufft_spec(N, _dev_ptr(y, "y"), _dev_ptr(g, "g"),
+                                      _dev_ptr(out, "c"), eps, dt, _stream()))
     return out
 
 

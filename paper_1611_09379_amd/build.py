@@ -25,7 +25,7 @@ FLAGS = [
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, "-o", tmp, SRC]
+    cmd = [hipcc, *FLAGS, "-o", tmp, SRC, "-lrocfft"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1,6 +1,7 @@
 // Host side of the FMM-based NUFFT / INUFFT: parameter selection, operator
 // tables, plans, launches and the C ABI declared in include/fmmnufft.h.
 #include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
 
 #include <algorithm>
 #include <atomic>
@@ -507,13 +508,18 @@ struct fn_plan {
     hipEvent_t tev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     float tms[4] = {-1.f, -1.f, -1.f, -1.f};
     int log_terms = 0, log_mterms = 0; // log-sum FMM expansion lengths
+    // spectral plans (Eq. p1): the uniform DFT by rocFFT around the FMM
+    bool spec = false;
+    rocfft_plan fft = nullptr;
+    rocfft_execution_info fft_info = nullptr;
+    Buf fft_work, spec_buf; // rocFFT's work buffer; the N grid values f_k
     // temporaries of the setup, released after its synchronisation
     std::vector<Buf> tmp;
     hipStream_t stream = nullptr; // stream of the last call
     std::vector<Buf *> all()
     {
         return {&off, &sm, &sth, &sperm, &skey, &spt, &work, &nwork_dev, &cot.mp, &cot.loc2,
-                &cot.pre, &cot.S, &hit, &chat, &dhat, &wsorted, &flags};
+                &cot.pre, &cot.S, &hit, &chat, &dhat, &wsorted, &flags, &fft_work, &spec_buf};
     }
 };
 
@@ -554,6 +560,12 @@ static void release_plan(fn_plan *P)
         release(*b);
     release_tmp(P);
     drop_events(P);
+    if (P->fft_info)
+        (void)rocfft_execution_info_destroy(P->fft_info);
+    if (P->fft)
+        (void)rocfft_plan_destroy(P->fft);
+    P->fft_info = nullptr;
+    P->fft = nullptr;
 }
 
 // A temporary of the setup: kept until the plan's synchronisation.
@@ -1432,6 +1444,71 @@ static int exec_adj(fn_plan *P, const void *in, void *out, int phase, hipStream_
                        (const int32_t *)P->sm.p, (const double *)P->sth.p,
                        (const int32_t *)P->sperm.p, (const cx<R> *)in, (cx<R> *)out);
     HIPCHK(hipGetLastError());
+    return FN_OK;
+}
+
+// ------------------------------------------------------- spectral plans
+//
+// Eq. (p1): f(x) = sum_{n<N} c_n e^{inx}.  The spectral forward evaluates
+// g_j = f(y_j) from the coefficients: f_k = sum_n c_n e^{2 pi i n k / N} on
+// the grid (rocFFT's unscaled backward DFT), then g = K f.  The spectral
+// inverse (M = N) returns the coefficients of the interpolant through the
+// g_j: f = L g, then c_n = (1/N) sum_k f_k e^{-2 pi i n k / N} (rocFFT's
+// forward DFT with the scale 1/N).  The uniform DFT is a library step: the
+// paper puts it beside the FMM, which is the part it accelerates.
+
+static std::once_flag g_fft_once;
+static rocfft_status g_fft_setup = rocfft_status_success;
+
+#define FFTCHK(expr)                                                           \
+    do {                                                                       \
+        const rocfft_status e_ = (expr);                                       \
+        if (e_ != rocfft_status_success)                                       \
+            return fail(FN_EHIP, "%s: rocFFT status %d", #expr, (int)e_);      \
+    } while (0)
+
+// rocFFT plan of a spectral plan; the work buffer and the grid values are
+// allocated with the plan's workspace.
+static int setup_spec(fn_plan *P)
+{
+    std::call_once(g_fft_once, [] { g_fft_setup = rocfft_setup(); });
+    FFTCHK(g_fft_setup);
+    const size_t len = (size_t)P->N;
+    const rocfft_precision prec =
+        P->dtype == FN_C128 ? rocfft_precision_double : rocfft_precision_single;
+    if (P->kind == 0) {
+        // c -> f in place in spec_buf, unscaled e^{+2 pi i n k / N}
+        FFTCHK(rocfft_plan_create(&P->fft, rocfft_placement_inplace,
+                                  rocfft_transform_type_complex_inverse, prec, 1, &len, 1,
+                                  nullptr));
+    } else {
+        // f (spec_buf) -> c, e^{-2 pi i n k / N} / N
+        rocfft_plan_description d = nullptr;
+        FFTCHK(rocfft_plan_description_create(&d));
+        rocfft_status e = rocfft_plan_description_set_scale_factor(d, 1.0 / (double)P->N);
+        if (e == rocfft_status_success)
+            e = rocfft_plan_create(&P->fft, rocfft_placement_notinplace,
+                                   rocfft_transform_type_complex_forward, prec, 1, &len, 1, d);
+        (void)rocfft_plan_description_destroy(d);
+        FFTCHK(e);
+    }
+    size_t wbytes = 0;
+    FFTCHK(rocfft_plan_get_work_buffer_size(P->fft, &wbytes));
+    FFTCHK(rocfft_execution_info_create(&P->fft_info));
+    const size_t es = P->dtype == FN_C128 ? 16 : 8;
+    if (!alloc(P->spec_buf, (size_t)P->N * es) || (wbytes && !alloc(P->fft_work, wbytes)))
+        return fail(FN_ENOMEM, "spectral workspace allocation failed");
+    if (wbytes)
+        FFTCHK(rocfft_execution_info_set_work_buffer(P->fft_info, P->fft_work.p, wbytes));
+    P->spec = true;
+    return FN_OK;
+}
+
+static int run_fft(fn_plan *P, void *in, void *out, hipStream_t st)
+{
+    FFTCHK(rocfft_execution_info_set_stream(P->fft_info, st));
+    void *ib[1] = {in}, *ob[1] = {out};
+    FFTCHK(rocfft_execute(P->fft, ib, out ? ob : nullptr, P->fft_info));
     return FN_OK;
 }
 
@@ -2345,6 +2422,88 @@ int nufft_adj(int64_t N, int64_t M, const double *y, const void *g, void *f,
     FN_API_END
 }
 
+static int plan_spec_common(fn_plan **plan, int kind, int64_t N, int64_t M, const double *y,
+                            double eps, int dtype, void *stream, bool defer)
+{
+    int rc = plan_common(plan, kind, N, M, y, eps, dtype, 0, 0, 0, stream, defer);
+    if (rc)
+        return rc;
+    try {
+        rc = setup_spec(*plan);
+    } catch (...) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        release_plan(*plan);
+        delete *plan;
+        *plan = nullptr;
+        throw;
+    }
+    if (rc) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        release_plan(*plan);
+        delete *plan;
+        *plan = nullptr;
+    }
+    return rc;
+}
+
+int nufft_plan_spec_fwd(fn_plan **plan, int64_t N, int64_t M, const double *y, double eps,
+                        int dtype, void *stream)
+{
+    FN_API_BEGIN
+    return plan_spec_common(plan, 0, N, M, y, eps, dtype, stream, false);
+    FN_API_END
+}
+
+int nufft_plan_spec_inv(fn_plan **plan, int64_t N, const double *y, double eps, int dtype,
+                        void *stream)
+{
+    FN_API_BEGIN
+    return plan_spec_common(plan, 1, N, N, y, eps, dtype, stream, false);
+    FN_API_END
+}
+
+int nufft_spec_fwd(int64_t N, int64_t M, const double *y, const void *c, void *g,
+                   double eps, int dtype, void *stream)
+{
+    FN_API_BEGIN
+    if (!c || !g)
+        return fail(FN_EINVAL, "c or g is NULL");
+    fn_plan *P = nullptr;
+    int rc = plan_spec_common(&P, 0, N, M, y, eps, dtype, stream, true);
+    if (rc)
+        return rc;
+    try {
+        return finish_one_shot(P, execute(P, c, g, -1, stream));
+    } catch (...) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        release_plan(P);
+        delete P;
+        throw;
+    }
+    FN_API_END
+}
+
+int inufft_spec(int64_t N, const double *y, const void *g, void *c, double eps, int dtype,
+                void *stream)
+{
+    FN_API_BEGIN
+    if (!c || !g)
+        return fail(FN_EINVAL, "c or g is NULL");
+    fn_plan *P = nullptr;
+    int rc = plan_spec_common(&P, 1, N, N, y, eps, dtype, stream, true);
+    if (rc)
+        return rc;
+    try {
+        return finish_one_shot(P, execute(P, g, c, -1, stream));
+    } catch (...) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        release_plan(P);
+        delete P;
+        throw;
+    }
+    FN_API_END
+}
+
 int nufft_plan_inv(fn_plan **plan, int64_t N, const double *y, double eps,
                    int dtype, void *stream)
 {
@@ -2352,6 +2511,8 @@ int nufft_plan_inv(fn_plan **plan, int64_t N, const double *y, double eps,
     return plan_common(plan, 1, N, N, y, eps, dtype, 0, 0, 0, stream);
     FN_API_END
 }
+
+static int execute_fmm(fn_plan *plan, const void *in, void *out, int phase, hipStream_t st);
 
 static int execute(fn_plan *plan, const void *in, void *out, int phase,
                    void *stream)
@@ -2362,6 +2523,27 @@ static int execute(fn_plan *plan, const void *in, void *out, int phase,
         return fail(FN_EINVAL, "input or output pointer is NULL");
     hipStream_t st = (hipStream_t)stream;
     plan->stream = st;
+    if (!plan->spec)
+        return execute_fmm(plan, in, out, phase, st);
+    const size_t bytes = (size_t)plan->N * (plan->dtype == FN_C128 ? 16 : 8);
+    if (plan->kind == 0) { // c -> f (phase 0 starts with it) -> g
+        if (phase <= 0) {
+            HIPCHK(hipMemcpyAsync(plan->spec_buf.p, in, bytes, hipMemcpyDeviceToDevice, st));
+            int rc = run_fft(plan, plan->spec_buf.p, nullptr, st);
+            if (rc)
+                return rc;
+        }
+        return execute_fmm(plan, plan->spec_buf.p, out, phase, st);
+    }
+    // g -> f -> c (phase 2 ends with it)
+    int rc = execute_fmm(plan, in, plan->spec_buf.p, phase, st);
+    if (rc || (phase >= 0 && phase < 2))
+        return rc;
+    return run_fft(plan, plan->spec_buf.p, out, st);
+}
+
+static int execute_fmm(fn_plan *plan, const void *in, void *out, int phase, hipStream_t st)
+{
     if (plan->kind == 0)
         return plan->dtype == FN_C128 ? exec_fwd<double>(plan, in, out, phase, st)
                                       : exec_fwd<float>(plan, in, out, phase, st);
