@@ -11,6 +11,8 @@ Functions (all arrays numpy; complex arrays are complex128):
   fwd(N, y, f)                -> g, Eq. (p2) via its closed form (p4)-(p5)
   fwd_at(N, y, f, sel)        -> g[sel]
   adj(N, y, g, ks=None)       -> f_k = sum_j conj(K_jk) g_j (adjoint of Eq. p2), at ks
+  kmatrix(N, y)               -> the M x N matrix K of Eq. (p2), closed form per entry
+  lsq(N, y, g)                -> argmin ||K f - g||_2 (dense K, LAPACK least squares)
   fwd_spectral(N, y, f)       -> g, Eq. (p1): c = DFT(f)/N, g_j = sum_n c_n e^{i n y_j}
   eval_series(N, y, c)        -> g, Eq. (p1) from given coefficients
   logsums(N, y, ks, js)       -> (logC, negC, logD, negD) behind Eq. (p8)
@@ -48,6 +50,7 @@ def _load():
     lib.or_fwd_kernel.argtypes = [i64, i64, vp, vp, vp, ctypes.c_int]
     lib.or_fwd_kernel_at.argtypes = [i64, i64, vp, vp, i64, vp, vp, ctypes.c_int]
     lib.or_adj_at.argtypes = [i64, i64, vp, vp, i64, vp, vp, ctypes.c_int]
+    lib.or_kmatrix.argtypes = [i64, i64, vp, vp, ctypes.c_int]
     lib.or_eval_series.argtypes = [i64, i64, vp, vp, vp, ctypes.c_int]
     lib.or_logsums_at.argtypes = [i64, vp, i64, vp, vp, vp, i64, vp, vp, vp,
                                   ctypes.c_int]
@@ -123,6 +126,22 @@ def adj(N: int, y, g, ks=None):
     _load().or_adj_at(N, y.shape[0], _ptr(y), _ptr(g), nk,
                       None if ks_a is None else _ptr(ks_a), _ptr(f), _threads())
     return f
+
+
+def kmatrix(N: int, y):
+    """The M x N matrix K of Eq. (p2), every entry in the closed form
+    (p4)-(p5) (a Kronecker delta row for a point on the grid)."""
+    y = _f64(y)
+    K = np.empty((y.shape[0], N), dtype=np.complex128)
+    _load().or_kmatrix(N, y.shape[0], _ptr(y), _ptr(K), _threads())
+    return K
+
+
+def lsq(N: int, y, g):
+    """argmin_f ||K f - g||_2 with the dense K of Eq. (p2) (numpy's LAPACK
+    least squares, a library step; the minimum-norm solution when K has
+    deficient rank).  For small N only."""
+    return np.linalg.lstsq(kmatrix(N, y), _c128(g), rcond=None)[0]
 
 
 def eval_series(N: int, y, c):

@@ -188,6 +188,44 @@ void or_fwd_kernel_at(int64_t N, int64_t M, const double *y, const double *f,
     }
 }
 
+/* The matrix K of Eq. (p2) itself, K[j][k] (row-major, M x N complex), each
+ * entry in the closed form (p4)-(p5) the forward sums: F_j G(y_j - x_k),
+ * with F_j = 2i sin(pi theta_j) e^{i pi theta_j} / N and
+ * G(t) = -(1 + i cot(t/2)) / 2; a point on the grid (theta_j == 0) gives
+ * the Kronecker delta. */
+void or_kmatrix(int64_t N, int64_t M, const double *y, double *K, int nthreads)
+{
+    int64_t *m = malloc(sizeof(int64_t) * (size_t)(M ? M : 1));
+    double *th = malloc(sizeof(double) * (size_t)(M ? M : 1));
+    or_grid_units(N, M, y, m, th);
+    const double dN = (double)N;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < M; ++j) {
+        double *row = K + 2 * (size_t)j * (size_t)N;
+        if (th[j] == 0.0) {
+            for (int64_t k = 0; k < N; ++k) {
+                row[2 * k] = k == m[j] ? 1.0 : 0.0;
+                row[2 * k + 1] = 0.0;
+            }
+            continue;
+        }
+        double sp, cp;
+        sincos(M_PI * th[j], &sp, &cp);
+        const double Fr = -2.0 * sp * sp / dN, Fi = 2.0 * sp * cp / dN;
+        for (int64_t k = 0; k < N; ++k) {
+            const double d = (double)wrap_half(m[j] - k, N) + th[j];
+            double sn, cs;
+            sincos(M_PI * (d / dN), &sn, &cs);
+            const double Gr = -0.5, Gi = -0.5 * (cs / sn);
+            row[2 * k] = Fr * Gr - Fi * Gi;
+            row[2 * k + 1] = Fr * Gi + Fi * Gr;
+        }
+    }
+    free(m);
+    free(th);
+}
+
 /* Adjoint of Eq. (p2): f_k = sum_j conj(K_jk) g_j at the grid points
  * k = ks[i] (all k = 0..N-1 when ks is NULL; nk outputs), with K_jk in
  * its closed form (p4)-(p5), K_jk = F_j G(y_j - x_k): the conjugate of the

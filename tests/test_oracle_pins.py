@@ -330,3 +330,35 @@ def test_fwd_tiny_fractions_brute_force_eq_p2():
         assert abs(complex(ref) - g[j]) <= 1e-14 * (1 + abs(complex(ref)))
     gi = oracle.inv(N, np.concatenate([[1e-250], 2 * np.pi * (np.arange(1, N) + 0.3) / N]), f)
     assert np.all(np.isfinite(gi)) and gi[0] == f[0]
+
+
+@pytest.mark.parametrize("N,M", [(1, 3), (8, 5), (64, 100), (257, 300)])
+def test_kmatrix_matches_eq_p2_and_forward(N, M):
+    """The closed-form matrix equals Eq. (p2) summed over n (numpy), and its
+    product with f is the oracle's forward sum; a grid point gives a delta
+    row."""
+    rng = np.random.default_rng(N + M)
+    y = rng.random(M) * 2 * np.pi
+    y[0] = 2 * np.pi * (N // 2) / N if N > 1 else 0.0
+    y[-1] = 0.0
+    K = oracle.kmatrix(N, y)
+    Kd = dense_K(N, y)
+    assert np.abs(K - Kd).max() < 1e-13 * max(1, N)
+    assert np.array_equal(K[-1], np.eye(N)[0])
+    f = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    assert np.linalg.norm(K @ f - oracle.fwd(N, y, f)) <= 1e-13 * np.linalg.norm(K @ f)
+
+
+def test_lsq_normal_equations_and_consistent_data():
+    """oracle.lsq: for consistent data g = K f it returns f (K has full
+    column rank for M = 2N uniform points); for inconsistent data its
+    residual is orthogonal to the range of K (the normal equations)."""
+    rng = np.random.default_rng(9)
+    N, M = 64, 128
+    y = rng.random(M) * 2 * np.pi
+    f = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    K = oracle.kmatrix(N, y)
+    assert np.linalg.norm(oracle.lsq(N, y, K @ f) - f) < 1e-9 * np.linalg.norm(f)
+    g = K @ f + 0.1 * (rng.standard_normal(M) + 1j * rng.standard_normal(M))
+    fl = oracle.lsq(N, y, g)
+    assert np.linalg.norm(K.conj().T @ (K @ fl - g)) < 1e-10 * np.linalg.norm(K.conj().T @ g)
