@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the clustered-forward and batched figures")
+    ap.add_argument("--study", choices=("cond", "eps_th"), default=None,
+                    help="instead of the benchmark: the inverse's conditioning "
+                         "study (cond) or the precision floor eps_th(N) study")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain elementwise kernel that reads and "
                          "writes 256 MiB (known byte counts for scaling "
@@ -470,6 +473,104 @@ def roofline(res, N, M, mixed):
             "work_per_launch": d["work"], "avg_launch_ms": d["ms"], "others": rows}
 
 
+def study_cond(fn, torch, workloads):
+    """The inverse across point distributions (Section 3: its error depends on
+    the distribution of the points), N = 1024: the condition number of K
+    (numpy), the range of the log-sums of Eq. (p8), the square inverse on
+    both precision paths (status and error against the band-limited
+    function whose exact values it inverts), and the least-squares inverse
+    (CG on the normal equations) with M = N and with M = 4N points of the
+    same distribution."""
+    import oracle
+    N = 1024
+    rng = np.random.default_rng(0)
+    c = workloads.coefficients(N, rng)
+    f = workloads.samples_from_coefficients(c)
+
+    def pts(kind, par, M, seed):
+        r = np.random.default_rng(seed)
+        if kind == "jitter":
+            k = M // N
+            base = np.concatenate([workloads.points_jittered(N, par, r) + 2 * np.pi * i / (k * N)
+                                   for i in range(k)]) if k > 1 else workloads.points_jittered(N, par, r)
+            return np.mod(base, 2 * np.pi)
+        if kind == "uniform":
+            return workloads.points_uniform(M, r)
+        if kind == "gap":
+            return 2 * np.pi * par * (np.arange(M) + r.uniform(-0.3, 0.3, M)) / M + 1e-3
+        return workloads.points_clustered(M, r, sigma=par)
+
+    cases = [("jitter", a) for a in (0.1, 0.25, 0.3, 0.4, 0.45, 0.49)] + [("uniform", 0)] + \
+            [("gap", a) for a in (0.97, 0.9)] + [("clustered", s_) for s_ in (0.3, 0.1, 0.01)]
+    rows = []
+    for kind, par in cases:
+        y = pts(kind, par, N, 1)
+        g = oracle.fwd(N, y, f)
+        row = {"points": kind, "param": par, "N": N}
+        try:
+            row["cond_K"] = float(np.linalg.cond(oracle.kmatrix(N, y)))
+        except Exception:
+            row["cond_K"] = None
+        lC, _, lD, _ = oracle.logsums(N, y)
+        row["max_abs_log_C_D"] = float(max(np.abs(lC[np.isfinite(lC)]).max(), np.abs(lD).max()))
+        try:
+            row["oracle_inv_err"] = float(np.linalg.norm(oracle.inv(N, y, g) - f) / np.linalg.norm(f))
+        except oracle.OracleError as e:
+            row["oracle_inv_err"] = str(e)
+        for name, dt, eps in (("f64", torch.complex128, 1e-12), ("mixed", torch.complex64, 1e-6)):
+            try:
+                fo = fn.inufft(torch.from_numpy(y).cuda(), torch.from_numpy(g).cuda().to(dt), eps)
+                row[f"inv_{name}_err"] = float(np.linalg.norm(fo.cpu().numpy() - f) / np.linalg.norm(f))
+            except fn.NufftError as e:
+                row[f"inv_{name}_err"] = fn.STATUS_NAMES[e.status]
+        for mult in (1, 4):
+            ym = pts(kind, par, mult * N, 2) if mult > 1 else y
+            gm = oracle.fwd(N, ym, f)
+            out, it, res = fn.nufft_lsq(torch.from_numpy(ym).cuda(), torch.from_numpy(gm).cuda(),
+                                        N, 1e-12, tol=1e-12, maxiter=1000)
+            row[f"lsq_M{mult}N"] = {"iters": it, "resid": res,
+                                    "err": float(np.linalg.norm(out.cpu().numpy() - f) / np.linalg.norm(f))}
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+    return rows
+
+
+def study_eps_th(fn, torch, workloads):
+    """The precision floor of the binary64 path, eps_th(N) (Section 3.1): for
+    f = 1 (exact g = 1) and for random f (against the oracle on sampled
+    targets), the error at requested eps = 1e-8 ... 1e-15; eps_th(N) is the
+    smallest error reached, and p_th, q_th the truncation numbers of
+    Eq. (18.2) at eps = eps_th(N) (nufft_select_params)."""
+    import oracle
+    rows = []
+    for L in (3, 6, 8, 10, 12, 14, 16, 18, 20):
+        N = M = 1 << L
+        rng = np.random.default_rng(L)
+        y = workloads.points_uniform(M, rng)
+        yd = torch.from_numpy(y).cuda()
+        ones = torch.ones(N, dtype=torch.complex128, device="cuda")
+        c = workloads.coefficients(N, rng)
+        f = workloads.samples_from_coefficients(c)
+        fd = torch.from_numpy(f).cuda()
+        sel = rng.choice(M, min(M, 256), replace=False)
+        ref = oracle.fwd_at(N, y, f, sel)
+        row = {"N": N, "by_eps": {}}
+        best_one, best_rand = 1.0, 1.0
+        for e in (1e-8, 1e-10, 1e-12, 1e-13, 1e-14, 1e-15):
+            g1 = fn.nufft_fwd(yd, ones, e).cpu().numpy()
+            gr = fn.nufft_fwd(yd, fd, e).cpu().numpy()
+            ea = float(np.abs(g1 - 1).max())
+            er = float(np.linalg.norm(gr[sel] - ref) / np.linalg.norm(ref))
+            row["by_eps"][f"{e:g}"] = {"max_abs_err_f1": ea, "rel_l2_random": er}
+            best_one, best_rand = min(best_one, ea), min(best_rand, er)
+        p, q, l = fn.select_params(N, M, max(best_one, 1e-15))
+        row.update({"eps_th_max_abs_f1": best_one, "eps_th_rel_l2_random": best_rand,
+                    "p_th": p, "q_th": q})
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+    return rows
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -486,6 +587,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     fn.load_library()
+    if args.study:
+        rows = (study_cond if args.study == "cond" else study_eps_th)(fn, torch, workloads)
+        print(json.dumps({"study": args.study, "rows": rows}), flush=True)
+        return
     if args.calibrate_copy:
         # a plain elementwise kernel: reads 256 MiB, writes 256 MiB
         src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")

@@ -315,6 +315,26 @@ int nufft_autotune(int kind, int64_t N, int64_t M, double eps, int dtype, int32_
 /* Forgets every recorded choice of nufft_autotune. */
 int nufft_autotune_clear(void);
 
+/* ---- Least squares ----------------------------------------------------
+ *
+ * The square inverse (inufft) needs M = N and a point set for which the
+ * products of Eq. (p8) stay in range; the paper notes that the inverse's
+ * error depends on the distribution of the points (Section 3).  For any M
+ * (oversampled sets M > N, clustered or gapped points), nufft_lsq returns
+ *     f = argmin ||K f - g||_2,   K of Eq. (p2) (M x N),
+ * by conjugate gradients on the normal equations K^H K f = K^H g (CGNR),
+ * starting from f = 0.  Each iteration runs one forward and one adjoint
+ * transform at accuracy eps and reads two squared norms back (the stream is
+ * synchronised every iteration).  It stops when ||K^H (g - K f)|| <= tol
+ * ||K^H g|| or after maxiter iterations (an ill-conditioned K converges
+ * slowly; the iterate is still the CG approximation).  y: M doubles; g: M
+ * complex; f: N complex (written).  iters, resid (may be NULL): the
+ * iterations done and the final relative normal-equation residual.
+ * Allocates and frees device memory (two plans and four vectors). */
+int nufft_lsq(int64_t N, int64_t M, const double *y, const void *g, void *f, double eps,
+              double tol, int32_t maxiter, int dtype, int32_t *iters, double *resid,
+              void *stream);
+
 /* ---- Allocation-free forward call -------------------------------------
  *
  * For callers that cannot allocate device memory (tight serving loops,

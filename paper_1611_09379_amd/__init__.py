@@ -38,7 +38,7 @@ ABI_SYMBOLS = (
     "nufft_fwd_batched", "nufft_plan_fwd_batched", "nufft_execute_batched",
     "nufft_destroy_batched", "nufft_autotune", "nufft_autotune_clear",
     "nufft_set_timing", "nufft_plan_get_timings",
-    "nufft_fwd_noalloc", "nufft_release_cache", "nufft_last_error",
+    "nufft_lsq", "nufft_fwd_noalloc", "nufft_release_cache", "nufft_last_error",
 )
 
 
@@ -107,6 +107,8 @@ def load_library(path: str = LIB_PATH):
         "nufft_set_timing": [ctypes.c_int],
         "nufft_plan_get_timings": [vp, ctypes.POINTER(ctypes.c_float), pi32],
         "nufft_fwd_noalloc": [i64, i64, vp, vp, vp, dbl, ctypes.c_int, vp],
+        "nufft_lsq": [i64, i64, vp, vp, vp, dbl, dbl, i32, ctypes.c_int, pi32,
+                      ctypes.POINTER(ctypes.c_double), vp],
         "nufft_release_cache": [],
         "nufft_last_error": [],
     }
@@ -360,6 +362,26 @@ def nufft_adj(y, g, N: int, eps: float, out=None):
     _check(load_library().nufft_adj(N, M, _dev_ptr(y, "y"), _dev_ptr(g, "g"),
                                     _dev_ptr(out, "f"), eps, dt, _stream()))
     return out
+
+
+def nufft_lsq(y, g, N: int, eps: float, tol: float = 1e-12, maxiter: int = 100, out=None):
+    """f = argmin ||K f - g|| (K of Eq. p2, M = len(y) points) by conjugate
+    gradients on the normal equations, each step a forward and an adjoint
+    transform.  Returns (f, iterations, relative normal-equation residual)."""
+    torch = _torch()
+    _check_y(y)
+    dt = _dtype_code(g)
+    M = y.shape[0]
+    if g.shape != (M,):
+        raise ValueError("g must have the shape of y")
+    if out is None:
+        out = torch.empty(N, dtype=g.dtype, device=g.device)
+    it = ctypes.c_int32()
+    res = ctypes.c_double()
+    _check(load_library().nufft_lsq(N, M, _dev_ptr(y, "y"), _dev_ptr(g, "g"),
+                                    _dev_ptr(out, "f"), eps, tol, maxiter, dt,
+                                    ctypes.byref(it), ctypes.byref(res), _stream()))
+    return out, it.value, res.value
 
 
 def _ptr_array(ts, name):

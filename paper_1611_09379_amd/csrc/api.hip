@@ -18,6 +18,7 @@
 
 #include "../../include/fmmnufft.h"
 #include "fmm_kernels.h"
+#include "solver_kernels.h"
 #include "tree_kernels.h"
 
 using namespace fn;
@@ -1512,6 +1513,96 @@ static int run_fft(fn_plan *P, void *in, void *out, hipStream_t st)
     return FN_OK;
 }
 
+// ------------------------------------------------------ least squares
+//
+// f = argmin ||K f - g||_2 for M points and any M (the square inverse of
+// Eq. p6 needs M = N and a well-conditioned point set): conjugate gradients
+// on the normal equations K^H K f = K^H g (CGNR), each iteration one forward
+// and one adjoint transform, the norms summed in binary64 on the device and
+// read back once per iteration.
+
+static int execute(fn_plan *plan, const void *in, void *out, int phase, void *stream);
+
+struct Lsq {
+    Buf r, s, p, q, part;
+    double *hpart = nullptr; // pinned read-back of the partial sums
+};
+
+template <typename R>
+static int lsq_sqnorm(const void *x, int64_t n, Lsq &L, hipStream_t st, double *out)
+{
+    hipLaunchKernelGGL((k_sqnorm<R>), dim3(SOLVE_BLOCKS), dim3(256), 0, st, n,
+                       (const cx<R> *)x, (double *)L.part.p);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(L.hpart, L.part.p, SOLVE_BLOCKS * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double sum = 0.0;
+    for (int b = 0; b < SOLVE_BLOCKS; ++b)
+        sum += L.hpart[b];
+    *out = sum;
+    return FN_OK;
+}
+
+template <typename R>
+static int lsq_run(fn_plan *Pf, fn_plan *Pa, const void *g, void *f, double tol,
+                   int32_t maxiter, Lsq &L, hipStream_t st, int32_t *iters, double *resid)
+{
+    const int64_t N = Pf->N, M = Pf->M;
+    const size_t es = sizeof(cx<R>);
+    // f = 0, r = g, s = K^H r, p = s
+    HIPCHK(hipMemsetAsync(f, 0, (size_t)N * es, st));
+    HIPCHK(hipMemcpyAsync(L.r.p, g, (size_t)M * es, hipMemcpyDeviceToDevice, st));
+    int rc = execute(Pa, L.r.p, L.s.p, -1, st);
+    if (rc)
+        return rc;
+    HIPCHK(hipMemcpyAsync(L.p.p, L.s.p, (size_t)N * es, hipMemcpyDeviceToDevice, st));
+    double gamma = 0.0, gamma0 = 0.0;
+    rc = lsq_sqnorm<R>(L.s.p, N, L, st, &gamma);
+    if (rc)
+        return rc;
+    gamma0 = gamma;
+    int32_t k = 0;
+    double res = gamma0 > 0.0 ? 1.0 : 0.0;
+    const int gN = grid_for(N), gM = grid_for(M);
+    while (k < maxiter && res > tol) {
+        rc = execute(Pf, L.p.p, L.q.p, -1, st); // q = K p
+        if (rc)
+            return rc;
+        double qq = 0.0;
+        rc = lsq_sqnorm<R>(L.q.p, M, L, st, &qq);
+        if (rc)
+            return rc;
+        if (!(qq > 0.0))
+            break;
+        const double alpha = gamma / qq;
+        hipLaunchKernelGGL((k_axpy<R>), dim3(gN), dim3(256), 0, st, N, alpha,
+                           (const cx<R> *)L.p.p, (cx<R> *)f);
+        hipLaunchKernelGGL((k_axpy<R>), dim3(gM), dim3(256), 0, st, M, -alpha,
+                           (const cx<R> *)L.q.p, (cx<R> *)L.r.p);
+        HIPCHK(hipGetLastError());
+        rc = execute(Pa, L.r.p, L.s.p, -1, st); // s = K^H r
+        if (rc)
+            return rc;
+        double gnew = 0.0;
+        rc = lsq_sqnorm<R>(L.s.p, N, L, st, &gnew);
+        if (rc)
+            return rc;
+        ++k;
+        res = std::sqrt(gnew / gamma0);
+        hipLaunchKernelGGL((k_xpby<R>), dim3(gN), dim3(256), 0, st, N,
+                           (const cx<R> *)L.s.p, gnew / gamma, (cx<R> *)L.p.p);
+        HIPCHK(hipGetLastError());
+        gamma = gnew;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (iters)
+        *iters = k;
+    if (resid)
+        *resid = res;
+    return FN_OK;
+}
+
 // ------------------------------------------------------------------ ABI
 
 static int check_common(int64_t N, int64_t M, double eps, int dtype)
@@ -2842,6 +2933,56 @@ int nufft_fwd_noalloc(int64_t N, int64_t M, const double *y, const void *f, void
         delete P;
         throw;
     }
+    FN_API_END
+}
+
+int nufft_lsq(int64_t N, int64_t M, const double *y, const void *g, void *f, double eps,
+              double tol, int32_t maxiter, int dtype, int32_t *iters, double *resid,
+              void *stream)
+{
+    FN_API_BEGIN
+    if (!f || !g)
+        return fail(FN_EINVAL, "f or g is NULL");
+    if (!(tol >= 0.0) || !std::isfinite(tol) || maxiter < 0)
+        return fail(FN_EINVAL, "tol must be finite and >= 0, maxiter >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    fn_plan *Pf = nullptr, *Pa = nullptr;
+    int rc = plan_common(&Pf, 0, N, M, y, eps, dtype, 0, 0, 0, stream);
+    if (rc)
+        return rc;
+    rc = plan_common(&Pa, 2, N, M, y, eps, dtype, 0, 0, 0, stream);
+    if (rc) {
+        release_plan(Pf);
+        delete Pf;
+        return rc;
+    }
+    Lsq L;
+    const size_t es = dtype == FN_C128 ? 16 : 8;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);
+        for (Buf *b : {&L.r, &L.s, &L.p, &L.q, &L.part})
+            release(*b);
+        release_plan(Pf);
+        delete Pf;
+        release_plan(Pa);
+        delete Pa;
+    };
+    try {
+        L.hpart = (double *)pinned_scratch(SOLVE_BLOCKS * sizeof(double));
+        if (!alloc(L.r, (size_t)M * es) || !alloc(L.q, (size_t)M * es) ||
+            !alloc(L.s, (size_t)N * es) || !alloc(L.p, (size_t)N * es) ||
+            !alloc(L.part, SOLVE_BLOCKS * sizeof(double)) || !L.hpart)
+            rc = fail(FN_ENOMEM, "least-squares workspace allocation failed");
+        else
+            rc = dtype == FN_C128
+                     ? lsq_run<double>(Pf, Pa, g, f, tol, maxiter, L, st, iters, resid)
+                     : lsq_run<float>(Pf, Pa, g, f, tol, maxiter, L, st, iters, resid);
+    } catch (...) {
+        cleanup();
+        throw;
+    }
+    cleanup();
+    return rc;
     FN_API_END
 }
 
