@@ -30,6 +30,14 @@
  *     for k = 0..N-1).
  *   - eps is the target relative l2 error ||out - exact|| / ||exact||.  It
  *     sets the truncation numbers p, q and the tree depth (Eq. 18, 18.2, 25).
+ *     eps = FN_EPS_MACHINE (0) asks for the precision path's own floor
+ *     eps_th(N) (Section 3.1, the machine-precision setting of Section
+ *     3.2), which the plan reports in fn_plan_info.eps.  Binary64: the
+ *     measured maximum error for f = 1, 1.4e-16 log2 sqrt(N M) (at least
+ *     5.6e-16; the relative l2 error of random data stays near 5e-16),
+ *     reached with p_th = 32 expansion terms and q_th = 22 Bernoulli terms
+ *     at every size measured (2^6 ... 2^20), the depth being that of
+ *     eps = eps_th(N).  FN_C64: the parameters of eps = 2e-7.
  *   - stream is a hipStream_t passed as void* (NULL = the null stream).
  *     Work is enqueued on it; a call returns when the work is enqueued,
  *     except where noted ("synchronises").
@@ -54,6 +62,9 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+
+/* eps value that requests the precision floor eps_th(N) of the path. */
+#define FN_EPS_MACHINE 0.0
 
 typedef enum {
     FN_OK = 0,

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(HERE, "libfmmnufft.so")
 
 FN_OK, FN_EINVAL, FN_ENOMEM, FN_EHIP, FN_ESINGULAR, FN_ERANGE, FN_EPREC = range(7)
 FN_C128, FN_C64 = 0, 1
+FN_EPS_MACHINE = 0.0   # eps that requests the path's precision floor eps_th(N)
 STATUS_NAMES = {0: "FN_OK", 1: "FN_EINVAL", 2: "FN_ENOMEM", 3: "FN_EHIP",
                 4: "FN_ESINGULAR", 5: "FN_ERANGE", 6: "FN_EPREC"}
 

@@ -264,6 +264,20 @@ static constexpr double LOG_MAX_C64 = 60.0;
 
 static double eps_floor(int dtype) { return dtype == FN_C64 ? 1e-7 : 1e-15; }
 
+// The precision floor eps_th of a path (Section 3.1), the accuracy that
+// eps = FN_EPS_MACHINE requests.  Binary64: the maximum error for f = 1
+// grows with the size through the rounding of the grid-unit reduction and
+// of the sums; measured on MI355X at N = M = 2^3 ... 2^20 (uniform y, 5.6e-16
+// ... 2.8e-15), it follows 1.4e-16 log2 sqrt(N M) within 25 %.  Binary32
+// data: the relative l2 floor of the mixed path, 2e-7 at 2^20.
+static double eps_th(int64_t N, int64_t M, int dtype)
+{
+    if (dtype == FN_C64)
+        return 2e-7;
+    const double lg = 0.5 * std::log2((double)N * (double)M);
+    return 1.4e-16 * std::max(4.0, lg);
+}
+
 // ------------------------------------------------------ operator tables
 
 // |B_2m| = 2 (2m)! zeta(2m) / (2 pi)^(2m)  (m >= 1), zeta by direct
@@ -1605,7 +1619,25 @@ static int lsq_run(fn_plan *Pf, fn_plan *Pa, const void *g, void *f, double tol,
 
 // ------------------------------------------------------------------ ABI
 
-static int check_common(int64_t N, int64_t M, double eps, int dtype)
+// Machine precision (eps = FN_EPS_MACHINE) on binary64: the expansion length
+// p_th and regular-part truncation q_th measured on MI355X to reach eps_th(N)
+// at every N = M = 2^6 ... 2^20 (uniform y; one term fewer of either leaves
+// 4x its error).  Eq. (18.2) at eps_th(N) asks for p = 34 ... 42, q = 25.
+// Values given explicitly are kept.
+static constexpr int P_TH = 32, Q_TH = 22;
+static void machine_params(double eps_in, int dtype, int32_t *p_in, int32_t *q_in)
+{
+    if (eps_in != 0.0 || dtype != FN_C128)
+        return;
+    if (*p_in <= 0)
+        *p_in = P_TH;
+    if (*q_in <= 0)
+        *q_in = Q_TH;
+}
+
+// Checks the scalar arguments; eps = FN_EPS_MACHINE (0) becomes the path's
+// floor eps_th(N, M).
+static int check_common(int64_t N, int64_t M, double &eps, int dtype)
 {
     if (N < 1 || N > INT32_MAX - 1)
         return fail(FN_EINVAL, "N = %lld out of range [1, 2^31 - 2]", (long long)N);
@@ -1613,8 +1645,13 @@ static int check_common(int64_t N, int64_t M, double eps, int dtype)
         return fail(FN_EINVAL, "M = %lld out of range [1, 2^31 - 2]", (long long)M);
     if (dtype != FN_C128 && dtype != FN_C64)
         return fail(FN_EINVAL, "unknown dtype %d", dtype);
+    if (eps == 0.0) {
+        eps = eps_th(N, M, dtype);
+        return FN_OK;
+    }
     if (!(eps > 0.0) || !std::isfinite(eps) || eps >= 1.0)
-        return fail(FN_EINVAL, "eps = %g must be finite and in (0, 1)", eps);
+        return fail(FN_EINVAL, "eps = %g must be 0 (the precision floor) or finite and "
+                               "in (0, 1)", eps);
     if (eps < eps_floor(dtype))
         return fail(FN_EPREC, "eps = %g is below the floor %g of this precision path",
                     eps, eps_floor(dtype));
@@ -1680,6 +1717,7 @@ static int plan_common(fn_plan **out, int kind, int64_t N, int64_t M,
     if (!out)
         return fail(FN_EINVAL, "plan pointer is NULL");
     *out = nullptr;
+    machine_params(eps, dtype, &p_in, &q_in);
     int rc = check_common(N, M, eps, dtype);
     if (rc)
         return rc;
@@ -1782,6 +1820,7 @@ struct fn_batch {
     Arena arena; // every workspace of the batch's plans
     int T = 0, dtype = 0;
     double eps = 0;
+    bool machine = false; // eps = FN_EPS_MACHINE: each transform at its eps_th
     std::vector<fn_plan *> P;
     std::vector<int> grp, solo;
     int PU = 0, PD = 0, q = 0, nbands = 0;
@@ -1880,9 +1919,12 @@ static int plan_batch_impl(fn_batch *B, const int64_t *Ns, const int64_t *Ms,
         P->dtype = B->dtype;
         P->N = Ns[t];
         P->M = Ms[t];
-        P->eps = B->eps;
+        P->eps = B->machine ? eps_th(P->N, P->M, P->dtype) : B->eps;
         P->stream = st;
-        choose(P->N, P->M, P->eps, 0, P->dtype, 0, 0, 0, &P->p, &P->q, &P->l, &P->p_explicit);
+        int32_t p_in = 0, q_in = 0;
+        machine_params(B->machine ? 0.0 : B->eps, P->dtype, &p_in, &q_in);
+        choose(P->N, P->M, P->eps, 0, P->dtype, p_in, q_in, 0, &P->p, &P->q, &P->l,
+               &P->p_explicit);
         if (P->p > 64 || 2 * P->q > 64)
             return fail(FN_EINVAL, "transform %d: truncation numbers need more than 64 terms", t);
         P->flags.p = (int *)B->flags.p + t;
@@ -2073,17 +2115,25 @@ static int plan_batch(fn_batch **out, int32_t count, const int64_t *Ns, const in
     *out = nullptr;
     if (count < 1 || !Ns || !Ms || !ys)
         return fail(FN_EINVAL, "count must be >= 1 and the size and point arrays non-NULL");
+    // FN_EPS_MACHINE: each transform at its own floor; the batch records
+    // the smallest
+    const bool machine = eps == 0.0;
+    double eps_b = machine ? 1.0 : eps;
     for (int32_t t = 0; t < count; ++t) {
-        int rc = check_common(Ns[t], Ms[t], eps, dtype);
+        double e = eps;
+        int rc = check_common(Ns[t], Ms[t], e, dtype);
         if (rc)
             return fail(rc, "transform %d: %s", t, std::string(g_err).c_str());
         if (!ys[t])
             return fail(FN_EINVAL, "transform %d: y is NULL", t);
+        eps_b = std::min(eps_b, e);
     }
+    eps = eps_b;
     fn_batch *B = new fn_batch();
     B->T = count;
     B->dtype = dtype;
     B->eps = eps;
+    B->machine = machine;
     hipStream_t st = (hipStream_t)stream;
     B->stream = st;
     g_arena = &B->arena;
@@ -2741,11 +2791,13 @@ int nufft_select_params(int64_t N, int64_t M, double eps, int dtype, int32_t *p,
                         int32_t *q, int32_t *lmax)
 {
     FN_API_BEGIN
+    int32_t p_in = 0, q_in = 0;
+    machine_params(eps, dtype, &p_in, &q_in);
     int rc = check_common(N, M, eps, dtype);
     if (rc)
         return rc;
     int pp, qq, ll;
-    choose(N, M, eps, -1, dtype, 0, 0, 0, &pp, &qq, &ll, nullptr);
+    choose(N, M, eps, -1, dtype, p_in, q_in, 0, &pp, &qq, &ll, nullptr);
     if (p)
         *p = pp;
     if (q)
@@ -2900,6 +2952,7 @@ int nufft_fwd_noalloc(int64_t N, int64_t M, const double *y, const void *f, void
     FN_API_BEGIN
     if (!f || !g)
         return fail(FN_EINVAL, "f or g is NULL");
+    const double eps_in = eps; // FN_EPS_MACHINE stays visible to the plan
     int rc = check_common(N, M, eps, dtype);
     if (rc)
         return rc;
@@ -2916,7 +2969,7 @@ int nufft_fwd_noalloc(int64_t N, int64_t M, const double *y, const void *f, void
         ~Scope() { g_arena = prev; }
     } scope(&A);
     fn_plan *P = nullptr;
-    rc = plan_common(&P, 0, N, M, y, eps, dtype, 0, 0, 0, stream, true);
+    rc = plan_common(&P, 0, N, M, y, eps_in, dtype, 0, 0, 0, stream, true);
     if (rc) {
         if (A.overflow)
             return fail(FN_EINVAL, "N = %lld, M = %lld need more workspace than the %zu "

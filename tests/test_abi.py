@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_1611_09379_amd as fn
@@ -103,3 +104,19 @@ def test_host_allocation_failure_is_a_status():
 
 def test_release_cache_host_only():
     assert fn.load_library().nufft_release_cache() == fn.FN_OK
+
+
+def test_machine_precision_eps_host_only():
+    """eps = FN_EPS_MACHINE: binary64 plans take the measured p_th = 32,
+    q_th = 22 and the depth of eps = eps_th(N) = 1.4e-16 log2 sqrt(N M);
+    FN_C64 plans the parameters of eps = 2e-7."""
+    for N, M in ((1 << 20, 1 << 20), (1 << 10, 1 << 16), (1 << 14, 1 << 14)):
+        e = 1.4e-16 * 0.5 * np.log2(float(N) * M)
+        assert fn.select_params(N, M, fn.FN_EPS_MACHINE) == \
+            (32, 22, fn.select_params(N, M, e)[2])
+        assert fn.select_params(N, M, fn.FN_EPS_MACHINE, fn.FN_C64) == \
+            fn.select_params(N, M, 2e-7, fn.FN_C64)
+    assert fn.select_params(8, 8, fn.FN_EPS_MACHINE)[:2] == (32, 22)
+    with pytest.raises(fn.NufftError) as err:
+        fn.select_params(64, 64, -1e-12)
+    assert err.value.status == fn.FN_EINVAL
