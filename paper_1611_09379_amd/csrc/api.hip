@@ -515,8 +515,11 @@ struct fn_plan {
     FmmSetup cot;
     // inverse
     Buf hit, chat, dhat, wsorted;
-    // error flags of the setup kernels, read once at the end of the plan
+    // error flags of the setup kernels, read once at the end of the plan;
+    // set to 0 by the first launch of the sort unless flags_ready (a slot
+    // of a batch's flag array, cleared by the batch)
     Buf flags;
+    bool flags_ready = false;
     // (measurement) events around the inverse setup's log-sum FMM passes,
     // recorded when timing is on, and their durations (ms; -1 if not taken)
     // (tev 0..3: the inverse setup's log-sum FMM; 4, 5: the sort of the plan)
@@ -681,11 +684,12 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_
     // a uniform grid with unequal leaves is staged like sorted sources
     const bool uni_staged = !sorted_src && kernel == KER_COT && uniform_leaf_pts(P) == 0;
     const int d_first = (kernel == KER_COT && (sorted_src || uni_staged)) ? 4 : 5;
+    const int d_rest = 5;
     F.nbands = 0;
     int lb = P->l;
     bool first = true;
     do {
-        const int d = std::min(first ? d_first : 5, lb - 2);
+        const int d = std::min(first ? d_first : d_rest, lb - 2);
         F.band[F.nbands++] = {lb, d, first ? 1 : 0, 1 << (lb - d),
                               (size_t)(1 << d) * F.RSu * es};
         lb -= d;
@@ -972,12 +976,24 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
 {
     const SortArgs &a = J.a;
     const int nbins = a.nbins;
-    if (a.hit)
-        HIPCHK(hipMemsetAsync(a.hit, 0xff, P->N * 4, st));
+    // the flags cleared and the hit table filled before the first kernel
+    // that writes them (k_place, k_reduce): by k_hist, else by one launch
+    // (either is cheaper on the host than a memset each)
+    const bool need_init = a.hit || !P->flags_ready;
+    if (need_init && !J.lds_path) {
+        const int64_t nhit = a.hit ? P->N : 0;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (nhit + 255) / 256));
+        hipLaunchKernelGGL(k_init, dim3(grid), dim3(256), 0, st,
+                           P->flags_ready ? nullptr : (int *)P->flags.p, 1, a.hit, nhit);
+        HIPCHK(hipGetLastError());
+    }
     if (J.lds_path) {
         // grid units and keys are computed inside the histogram and
         // placement passes
-        hipLaunchKernelGGL(k_hist, dim3(a.nblk), dim3(SORT_THREADS), (size_t)nbins * 4, st, a);
+        SortArgs ha = a;
+        ha.init_flags = P->flags_ready ? 0 : 1;
+        ha.nhit = a.hit ? P->N : 0;
+        hipLaunchKernelGGL(k_hist, dim3(a.nblk), dim3(SORT_THREADS), (size_t)nbins * 4, st, ha);
         HIPCHK(hipGetLastError());
         hipLaunchKernelGGL(k_colscan, dim3((nbins + CS_COLS - 1) / CS_COLS), dim3(CS_THREADS),
                            0, st, a);
@@ -1013,6 +1029,7 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
             HIPCHK(hipGetLastError());
         }
     }
+    P->flags_ready = true;
     if (J.lds_path) {
         hipLaunchKernelGGL(k_place, dim3(a.nblk), dim3(SORT_THREADS), (size_t)nbins * 4, st, a);
     } else {
@@ -1120,16 +1137,53 @@ static void *pinned_scratch(size_t bytes, int slot = 0)
     return buf[slot];
 }
 
+// Fine-grained (coherent) pinned host words per host thread that a kernel
+// writes the error flags into, with their device address; allocated once
+// and held until the process ends.  nullptr if they cannot be had (the
+// flags are then copied).
+static int *flag_mirror(int **dev)
+{
+    if (g_arena && g_arena->fixed)
+        return nullptr; // allocation-free call
+    static thread_local int *host = nullptr, *devp = nullptr;
+    static thread_local bool tried = false;
+    if (!tried) {
+        tried = true;
+        void *h = nullptr, *d = nullptr;
+        if (hipHostMalloc(&h, 256, hipHostMallocCoherent | hipHostMallocPortable |
+                                       hipHostMallocMapped) == hipSuccess) {
+            if (hipHostGetDevicePointer(&d, h, 0) == hipSuccess) {
+                host = (int *)h;
+                devp = (int *)d;
+            } else {
+                (void)hipHostFree(h);
+            }
+        }
+    }
+    *dev = devp;
+    return host;
+}
+
 static int finish_plan(fn_plan *P, hipStream_t st)
 {
     int hstack = 0;
-    int *hw = (int *)pinned_scratch(4);
-    if (!hw)
-        hw = &hstack;
-    hipError_t e = hipMemcpyAsync(hw, P->flags.p, 4, hipMemcpyDeviceToHost, st);
+    int *dmirror = nullptr;
+    int *hw = flag_mirror(&dmirror);
+    hipError_t e;
+    if (hw) {
+        *hw = -1; // overwritten by the kernel
+        hipLaunchKernelGGL(k_flags_out, dim3(1), dim3(64), 0, st, (const int *)P->flags.p, 1,
+                           dmirror);
+        e = hipGetLastError();
+    } else {
+        hw = (int *)pinned_scratch(4);
+        if (!hw)
+            hw = &hstack;
+        e = hipMemcpyAsync(hw, P->flags.p, 4, hipMemcpyDeviceToHost, st);
+    }
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
-    const int hflags = *hw;
+    const int hflags = *(volatile int *)hw;
     if (e == hipSuccess && P->tev[0]) {
         for (int i = 0; i < 3; ++i)
             if (hipEventElapsedTime(&P->tms[i], P->tev[i], P->tev[i + 1]) != hipSuccess)
@@ -1762,11 +1816,7 @@ static int plan_body(fn_plan *P, int kind, int64_t N, int64_t M, const double *y
         delete P;
         return fail(FN_ENOMEM, "flag allocation failed (%s)", hipGetErrorString(g_alloc_err));
     }
-    if (hipMemsetAsync(P->flags.p, 0, 4, st) != hipSuccess) {
-        release_plan(P);
-        delete P;
-        return fail(FN_EHIP, "hipMemsetAsync failed");
-    }
+    // (the flags are cleared by the first launch of the plan's sort)
     if (kind == 0)
         rc = dtype == FN_C128 ? plan_fwd_impl<double>(P, y, st)
                               : plan_fwd_impl<float>(P, y, st);
@@ -1870,6 +1920,7 @@ static void release_batch(fn_batch *B)
         if (!P)
             continue;
         P->flags = Buf{}; // a slot of the batch's flag array
+        P->flags_ready = true;
         release_plan(P);
         delete P;
     }

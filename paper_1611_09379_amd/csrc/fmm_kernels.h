@@ -480,7 +480,9 @@ __device__ __forceinline__ void p2m_mfma(const UpArgs<R, V> &a, int64_t first,
 #pragma unroll
     for (int ks = 0; ks < P2M_KMAX; ++ks) {
         const int k = 4 * ks + (lane >> 4);
-        vv[ks] = (R)((double)(2 * k - B) / (double)B);
+        // (steps past the leaf's points: a zero coordinate, so that their
+        // powers stay finite)
+        vv[ks] = ks < nks ? (R)((double)(2 * k - B) / (double)B) : R(0);
         av[ks] = R(1);
     }
     for (int e = m; e; e >>= 1) {
@@ -497,16 +499,25 @@ __device__ __forceinline__ void p2m_mfma(const UpArgs<R, V> &a, int64_t first,
         const int i = j / NC, c = j % NC;
         const bool valid = i < nbot;
         const R *fp = f + (valid ? i : 0) * SB + c + (lane >> 4) * NC;
-        A acc = {0, 0, 0, 0};
+        // every operand load issued before the first matrix instruction
+        // (steps past the leaf's points read its last step and add zero),
+        // two accumulator chains in flight
+        R bv[P2M_KMAX];
+#pragma unroll
+        for (int ks = 0; ks < P2M_KMAX; ++ks)
+            bv[ks] = fp[4 * (ks < nks ? ks : nks - 1) * NC];
+        A acc = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
 #pragma unroll
         for (int ks = 0; ks < P2M_KMAX; ++ks) {
-            if (ks < nks) {
-                R bv = fp[4 * ks * NC];
-                if (!valid)
-                    bv = R(0);
-                acc = mma(av[ks], bv, acc);
-            }
+            const R v = (valid && ks < nks) ? bv[ks] : R(0);
+            if (ks & 1)
+                acc1 = mma(av[ks], v, acc1);
+            else
+                acc = mma(av[ks], v, acc);
         }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            acc[r] += acc1[r];
         if (valid) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -520,11 +531,15 @@ __device__ __forceinline__ void p2m_mfma(const UpArgs<R, V> &a, int64_t first,
 
 // M2M of one level inside LDS: np parents from 2 np children (rows of cur),
 // written to nxt (LDS) and g (global, PU per box).  Each wave takes 16-row
-// tiles of the parents' moments; its operator tile sits in registers.
-template <typename R, typename V, int PU>
-__device__ __forceinline__ void m2m_level(const R (&am)[PU / 4], int rt,
-                                          int ct0, int ctstep, int lane, int np,
-                                          const R *cur, R *nxt, int RS, V *g)
+// tiles of the parents' moments; its operator tile sits in registers.  The
+// operator is lower triangular: row tile rt takes no moment of order
+// 16 (rt + 1) or more, so its loop has KE = 4 (rt + 1) steps, a constant of
+// the instantiation: every operand load of a column tile is then issued
+// before the first matrix instruction (with a bound known only at run time
+// each step waited for its own load).
+template <typename R, typename V, int PU, int KE>
+__device__ __forceinline__ void m2m_tile(const R (&am)[PU / 4], int rt, int ct0, int ctstep,
+                                         int lane, int np, const R *cur, R *nxt, int RS, V *g)
 {
     constexpr int NC = ncomp<V>::value;
     using A = typename acc_t<R>::type;
@@ -536,23 +551,22 @@ __device__ __forceinline__ void m2m_level(const R (&am)[PU / 4], int rt,
         const int pc = valid ? p : 0;
         const R *cl = cur + (size_t)(2 * pc) * RS + c;
         const R *cr = cl + RS;
+        R bl[KE], br[KE];
+#pragma unroll
+        for (int ks = 0; ks < KE; ++ks) {
+            const int m = 4 * ks + (lane >> 4);
+            bl[ks] = cl[m * NC];
+            br[ks] = cr[m * NC];
+        }
         A al = {0, 0, 0, 0}, ar = {0, 0, 0, 0};
 #pragma unroll
-        for (int ks = 0; ks < PU / 4; ++ks) {
-            // the operator is lower triangular: rows below 16 (rt + 1) take
-            // no moment of order 16 (rt + 1) or more
-            if (ks < 4 * (rt + 1)) {
-                const int m = 4 * ks + (lane >> 4);
-                R bl = cl[m * NC], br = cr[m * NC];
-                if (!valid) {
-                    bl = R(0);
-                    br = R(0);
-                }
-                if (m & 1)
-                    br = -br;
-                al = mma(am[ks], bl, al);
-                ar = mma(am[ks], br, ar);
-            }
+        for (int ks = 0; ks < KE; ++ks) {
+            const int m = 4 * ks + (lane >> 4);
+            R vl = valid ? bl[ks] : R(0), vr = valid ? br[ks] : R(0);
+            if (m & 1)
+                vr = -vr;
+            al = mma(am[ks], vl, al);
+            ar = mma(am[ks], vr, ar);
         }
         if (valid) {
 #pragma unroll
@@ -563,6 +577,31 @@ __device__ __forceinline__ void m2m_level(const R (&am)[PU / 4], int rt,
                 reinterpret_cast<R *>(g)[((size_t)p * PU + n) * NC + c] = v;
             }
         }
+    }
+}
+
+template <typename R, typename V, int PU>
+__device__ __forceinline__ void m2m_level(const R (&am)[PU / 4], int rt,
+                                          int ct0, int ctstep, int lane, int np,
+                                          const R *cur, R *nxt, int RS, V *g)
+{
+    static_assert(PU % 16 == 0 && PU <= 64, "multipole length: 16, 32, 48 or 64");
+    switch (rt) {
+    case 0:
+        m2m_tile<R, V, PU, 4>(am, rt, ct0, ctstep, lane, np, cur, nxt, RS, g);
+        break;
+    case 1:
+        if constexpr (PU >= 32)
+            m2m_tile<R, V, PU, 8>(am, rt, ct0, ctstep, lane, np, cur, nxt, RS, g);
+        break;
+    case 2:
+        if constexpr (PU >= 48)
+            m2m_tile<R, V, PU, 12>(am, rt, ct0, ctstep, lane, np, cur, nxt, RS, g);
+        break;
+    default:
+        if constexpr (PU >= 64)
+            m2m_tile<R, V, PU, 16>(am, rt, ct0, ctstep, lane, np, cur, nxt, RS, g);
+        break;
     }
 }
 
@@ -1393,12 +1432,16 @@ __device__ __forceinline__ void pre_stage(const V (&pf)[NPF], R *rows, int RS, i
 // i >> 1 of par) += L2L(par row) for nb children.  The right child's
 // operator follows from the left one by the signs (-1)^m on the input and
 // (-1)^n on the output; the operator is triangular, so row tile rt takes no
-// input moment below 16 rt.
-template <typename R, typename V, int PD>
-__device__ __forceinline__ void l2l_tiles(const R (&al)[PD / 4], int rt, int ct0, int ctstep,
-                                          int lane, int nb, const R *par, R *out, int RS)
+// input moment below 16 rt: its loop runs over steps KB = 4 rt .. PD / 4 - 1,
+// KB a constant of the instantiation, with every operand load issued before
+// the first matrix instruction and two accumulator chains (even and odd
+// steps) in flight.
+template <typename R, typename V, int PD, int KB>
+__device__ __forceinline__ void l2l_tile(const R (&al)[PD / 4], int rt, int ct0, int ctstep,
+                                         int lane, int nb, const R *par, R *out, int RS)
 {
     constexpr int NC = ncomp<V>::value;
+    constexpr int KN = PD / 4 - KB;
     using A = typename acc_t<R>::type;
     const int nct = (NC * nb + 15) / 16;
     for (int ct = ct0; ct < nct; ct += ctstep) {
@@ -1408,18 +1451,21 @@ __device__ __forceinline__ void l2l_tiles(const R (&al)[PD / 4], int rt, int ct0
         const int ic = valid ? i : 0;
         const bool left = (ic & 1) == 0;
         const R *sp = par + (size_t)(ic >> 1) * RS + c;
-        A acc = {0, 0, 0, 0};
+        R b[KN];
 #pragma unroll
-        for (int ks = 0; ks < PD / 4; ++ks) {
-            if (ks >= 4 * rt) {
-                const int m = 4 * ks + (lane >> 4);
-                R b = sp[m * NC];
-                if (!valid)
-                    b = R(0);
-                if ((m & 1) && !left)
-                    b = -b;
-                acc = mma(al[ks], b, acc);
-            }
+        for (int k = 0; k < KN; ++k)
+            b[k] = sp[(4 * (KB + k) + (lane >> 4)) * NC];
+        A acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < KN; ++k) {
+            const int m = 4 * (KB + k) + (lane >> 4);
+            R v = valid ? b[k] : R(0);
+            if ((m & 1) && !left)
+                v = -v;
+            if (k & 1)
+                acc1 = mma(al[KB + k], v, acc1);
+            else
+                acc0 = mma(al[KB + k], v, acc0);
         }
         if (!valid)
             continue;
@@ -1427,8 +1473,33 @@ __device__ __forceinline__ void l2l_tiles(const R (&al)[PD / 4], int rt, int ct0
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int n = 16 * rt + out_row<R>(lane, r);
-            dst[n * NC] += (!left && (n & 1)) ? -acc[r] : acc[r];
+            const R v = acc0[r] + acc1[r];
+            dst[n * NC] += (!left && (n & 1)) ? -v : v;
         }
+    }
+}
+
+template <typename R, typename V, int PD>
+__device__ __forceinline__ void l2l_tiles(const R (&al)[PD / 4], int rt, int ct0, int ctstep,
+                                          int lane, int nb, const R *par, R *out, int RS)
+{
+    static_assert(PD % 16 == 0 && PD <= 64, "local length: 16, 32, 48 or 64");
+    switch (rt) {
+    case 0:
+        l2l_tile<R, V, PD, 0>(al, rt, ct0, ctstep, lane, nb, par, out, RS);
+        break;
+    case 1:
+        if constexpr (PD >= 32)
+            l2l_tile<R, V, PD, 4>(al, rt, ct0, ctstep, lane, nb, par, out, RS);
+        break;
+    case 2:
+        if constexpr (PD >= 48)
+            l2l_tile<R, V, PD, 8>(al, rt, ct0, ctstep, lane, nb, par, out, RS);
+        break;
+    default:
+        if constexpr (PD >= 64)
+            l2l_tile<R, V, PD, 12>(al, rt, ct0, ctstep, lane, nb, par, out, RS);
+        break;
     }
 }
 

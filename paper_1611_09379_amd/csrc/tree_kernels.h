@@ -99,6 +99,11 @@ struct SortArgs {
                             // of sm, sth, sperm, skey (forward targets)
     int32_t *hit;           // (optional) index of a point on x_m, per m
     int *flags;
+    // k_hist also prepares the plan's device state (nothing of it is read
+    // before k_place): init_flags clears the flags, and a non-zero nhit fills
+    // hit[0 .. nhit) with -1 (no grid point is hit)
+    int init_flags;
+    int64_t nhit;
 };
 
 // Grid units and sort key (the level-(l - keyshift) box) of one point.  The
@@ -141,6 +146,11 @@ __device__ __forceinline__ void hist_body(const SortArgs &a, int blk)
 {
     extern __shared__ int32_t hist[];
     const int nbins = a.nbins;
+    if (a.init_flags && blk == 0 && threadIdx.x == 0)
+        *a.flags = 0;
+    for (int64_t i = (int64_t)blk * SORT_THREADS + threadIdx.x; i < a.nhit;
+         i += (int64_t)a.nblk * SORT_THREADS)
+        a.hit[i] = -1;
     for (int i = threadIdx.x; i < nbins; i += SORT_THREADS)
         hist[i] = 0;
     __syncthreads();
@@ -179,6 +189,32 @@ __device__ __forceinline__ void hist_body(const SortArgs &a, int blk)
 }
 
 __global__ void __launch_bounds__(SORT_THREADS) k_hist(SortArgs a) { hist_body(a, blockIdx.x); }
+
+// A plan's device state before its sort, in one launch: the error flags
+// (nflags words, when flags is given) to 0 and the hit table (nhit entries,
+// when hit is given) to -1 (no grid point is hit).
+__global__ void __launch_bounds__(256) k_init(int *flags, int nflags, int32_t *hit,
+                                              int64_t nhit)
+{
+    const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (flags && i0 < nflags)
+        flags[i0] = 0;
+    if (hit)
+        for (int64_t i = i0; i < nhit; i += (int64_t)gridDim.x * blockDim.x)
+            hit[i] = -1;
+}
+
+// Copies the n error flags into host memory mapped into the device's address
+// space (fine-grained pinned memory: the stores reach the host before the
+// kernel ends), so that a synchronisation is the only host call needed to
+// read them.
+__global__ void k_flags_out(const int *flags, int n, int *host)
+{
+    const int i = threadIdx.x;
+    if (i < n)
+        __hip_atomic_store(host + i, flags[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __threadfence_system();
+}
 
 
 
