@@ -326,6 +326,19 @@ int nufft_autotune(int kind, int64_t N, int64_t M, double eps, int dtype, int32_
 /* Forgets every recorded choice of nufft_autotune. */
 int nufft_autotune_clear(void);
 
+/* Writes every recorded choice of nufft_autotune to a text file (a header
+ * line, then one line per record: kind, dtype, size class, accuracy class,
+ * lmax, nterms), so that a later process can start from them.  Host only.
+ * FN_EINVAL for a NULL path or a file that cannot be written. */
+int nufft_autotune_save(const char *path);
+
+/* Adds the records of a file written by nufft_autotune_save (a record of
+ * the same kind, dtype, size and accuracy class is replaced).  Host only.
+ * FN_EINVAL for a NULL path, a file that cannot be read, or one that is not
+ * such a file (wrong header, a malformed line or a value out of range):
+ * then no record is added. */
+int nufft_autotune_load(const char *path);
+
 /* ---- Least squares ----------------------------------------------------
  *
  * The square inverse (inufft) needs M = N and a point set for which the

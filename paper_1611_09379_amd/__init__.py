@@ -37,7 +37,7 @@ ABI_SYMBOLS = (
     "nufft_destroy", "nufft_plan_get_info", "nufft_plan_coeffs",
     "nufft_select_params",
     "nufft_fwd_batched", "nufft_plan_fwd_batched", "nufft_execute_batched",
-    "nufft_destroy_batched", "nufft_autotune", "nufft_autotune_clear",
+    "nufft_destroy_batched", "nufft_autotune", "nufft_autotune_clear", "nufft_autotune_save", "nufft_autotune_load",
     "nufft_set_timing", "nufft_plan_get_timings",
     "nufft_lsq", "nufft_fwd_noalloc", "nufft_release_cache", "nufft_last_error",
 )
@@ -105,6 +105,8 @@ def load_library(path: str = LIB_PATH):
         "nufft_destroy_batched": [vp],
         "nufft_autotune": [ctypes.c_int, i64, i64, dbl, ctypes.c_int, pi32, pi32, vp],
         "nufft_autotune_clear": [],
+        "nufft_autotune_save": [ctypes.c_char_p],
+        "nufft_autotune_load": [ctypes.c_char_p],
         "nufft_set_timing": [ctypes.c_int],
         "nufft_plan_get_timings": [vp, ctypes.POINTER(ctypes.c_float), pi32],
         "nufft_fwd_noalloc": [i64, i64, vp, vp, vp, dbl, ctypes.c_int, vp],
@@ -484,6 +486,16 @@ def autotune(kind: str, N: int, M: int, eps: float, dtype: int = FN_C128):
 def autotune_clear():
     """Forgets every choice recorded by autotune."""
     _check(load_library().nufft_autotune_clear())
+
+
+def autotune_save(path: str):
+    """Writes the recorded autotune choices to a text file."""
+    _check(load_library().nufft_autotune_save(os.fsencode(path)))
+
+
+def autotune_load(path: str):
+    """Adds the autotune choices of a file written by autotune_save."""
+    _check(load_library().nufft_autotune_load(os.fsencode(path)))
 
 
 def set_timing(on: bool):

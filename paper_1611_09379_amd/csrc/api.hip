@@ -2997,6 +2997,75 @@ int nufft_autotune_clear(void)
     FN_API_END
 }
 
+// Autotune records as text: a header line, then one record per line,
+// "kind dtype size_class accuracy_class lmax nterms".
+static const char *const TUNE_HEADER = "# fmmnufft autotune records v1";
+
+int nufft_autotune_save(const char *path)
+{
+    FN_API_BEGIN
+    if (!path)
+        return fail(FN_EINVAL, "path is NULL");
+    std::vector<std::pair<std::tuple<int, int, int, int>, std::pair<int, int>>> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        recs.assign(g_tuned.begin(), g_tuned.end());
+    }
+    FILE *fp = fopen(path, "w");
+    if (!fp)
+        return fail(FN_EINVAL, "cannot write %s", path);
+    bool ok = fprintf(fp, "%s\n", TUNE_HEADER) > 0;
+    for (const auto &r : recs)
+        ok = ok && fprintf(fp, "%d %d %d %d %d %d\n", std::get<0>(r.first), std::get<1>(r.first),
+                           std::get<2>(r.first), std::get<3>(r.first), r.second.first,
+                           r.second.second) > 0;
+    ok = (fclose(fp) == 0) && ok;
+    if (!ok)
+        return fail(FN_EINVAL, "cannot write %s", path);
+    return FN_OK;
+    FN_API_END
+}
+
+int nufft_autotune_load(const char *path)
+{
+    FN_API_BEGIN
+    if (!path)
+        return fail(FN_EINVAL, "path is NULL");
+    FILE *fp = fopen(path, "r");
+    if (!fp)
+        return fail(FN_EINVAL, "cannot read %s", path);
+    std::vector<std::pair<std::tuple<int, int, int, int>, std::pair<int, int>>> recs;
+    char line[256];
+    int lineno = 0;
+    bool header = false;
+    while (fgets(line, sizeof line, fp)) {
+        ++lineno;
+        if (lineno == 1) {
+            header = strncmp(line, TUNE_HEADER, strlen(TUNE_HEADER)) == 0;
+            if (!header)
+                break;
+            continue;
+        }
+        int kind, dtype, lg, ec, l, p;
+        char extra;
+        if (sscanf(line, "%d %d %d %d %d %d %c", &kind, &dtype, &lg, &ec, &l, &p, &extra) != 6 ||
+            kind < 0 || kind > 2 || (dtype != FN_C128 && dtype != FN_C64) || lg < 0 ||
+            lg > 62 || ec < 0 || ec > 20 || l < 2 || l > 24 || p < 0 || p > 64 || p % 16) {
+            fclose(fp);
+            return fail(FN_EINVAL, "%s line %d: not an autotune record", path, lineno);
+        }
+        recs.push_back({std::make_tuple(kind, dtype, lg, ec), {l, p}});
+    }
+    fclose(fp);
+    if (!header)
+        return fail(FN_EINVAL, "%s: not an autotune record file", path);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &r : recs)
+        g_tuned[r.first] = r.second;
+    return FN_OK;
+    FN_API_END
+}
+
 int nufft_fwd_noalloc(int64_t N, int64_t M, const double *y, const void *f, void *g,
                       double eps, int dtype, void *stream)
 {

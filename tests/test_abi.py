@@ -120,3 +120,31 @@ def test_machine_precision_eps_host_only():
     with pytest.raises(fn.NufftError) as err:
         fn.select_params(64, 64, -1e-12)
     assert err.value.status == fn.FN_EINVAL
+
+
+def test_autotune_records_file_host_only(tmp_path):
+    """nufft_autotune_save / _load: a round trip of records, the load of a
+    malformed file adds nothing, and clear empties the table."""
+    fn.autotune_clear()
+    good = tmp_path / "tune.txt"
+    good.write_text("# fmmnufft autotune records v1\n0 0 20 12 14 32\n1 1 16 6 11 0\n")
+    fn.autotune_load(str(good))
+    out = tmp_path / "out.txt"
+    fn.autotune_save(str(out))
+    assert out.read_text().splitlines() == good.read_text().splitlines()
+    bad = tmp_path / "bad.txt"
+    for text in ("# fmmnufft autotune records v1\n0 0 20 12 14 33\n",   # nterms
+                 "# fmmnufft autotune records v1\n3 0 20 12 14 32\n",   # kind
+                 "# fmmnufft autotune records v1\n0 0 20 12\n",         # short
+                 "0 0 20 12 14 32\n"):                                  # header
+        bad.write_text(text)
+        with pytest.raises(fn.NufftError) as e:
+            fn.autotune_load(str(bad))
+        assert e.value.status == fn.FN_EINVAL
+    fn.autotune_save(str(out))
+    assert out.read_text().splitlines() == good.read_text().splitlines()
+    with pytest.raises(fn.NufftError):
+        fn.autotune_load(str(tmp_path / "missing.txt"))
+    fn.autotune_clear()
+    fn.autotune_save(str(out))
+    assert out.read_text().splitlines() == ["# fmmnufft autotune records v1"]

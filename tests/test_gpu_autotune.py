@@ -83,3 +83,18 @@ def test_autotune_errors():
     with pytest.raises(fn.NufftError) as e:
         fn.autotune("fwd", 100, 100, 1e-20)
     assert e.value.status == fn.FN_EPREC
+
+
+def test_autotune_records_survive_a_file(tmp_path):
+    """A tuned record saved, cleared and loaded again sets the depth of
+    later plans."""
+    N, M = 4096, 4096
+    l, p = fn.autotune("fwd", N, M, 1e-12)
+    path = str(tmp_path / "tune.txt")
+    fn.autotune_save(path)
+    fn.autotune_clear()
+    fn.autotune_load(path)
+    y, f, c = workloads.forward_case(N, M, "uniform", seed=13)
+    info = fn.Plan.forward(N, dev(y), 1e-12).info()
+    say("tuned", l, p, "after reload", info.lmax, info.nterms)
+    assert info.lmax == l and (p == 0 or info.nterms == p)
