@@ -169,11 +169,15 @@ __device__ __forceinline__ void hist_body(const SortArgs &a, int blk)
 #pragma unroll
         for (int u = 0; u < SORT_BATCH; ++u) {
             const int64_t j = jb + u * SORT_THREADS;
-            int32_t mm;
-            double tt;
-            bool ok;
-            const int32_t k = point_key(a, yv[u], &mm, &tt, &ok);
-            key[u] = j < j1 ? k : -1;
+            // (a slot past the chunk for every lane of the wave costs no
+            // key computation: small chunks fill half the batch)
+            key[u] = -1;
+            if (j < j1) {
+                int32_t mm;
+                double tt;
+                bool ok;
+                key[u] = point_key(a, yv[u], &mm, &tt, &ok);
+            }
         }
 #pragma unroll
         for (int u = 0; u < SORT_BATCH; ++u) {
@@ -318,11 +322,12 @@ __device__ __forceinline__ void place_body(const SortArgs &a, int blk)
 #pragma unroll
         for (int u = 0; u < SORT_BATCH; ++u) {
             const int64_t j = jb + u * SORT_THREADS;
-            bool ok;
-            const int32_t k = point_key(a, yv[u], &mm[u], &tt[u], &ok);
             key[u] = -1;
+            mm[u] = 0;
+            tt[u] = 0.0;
             if (j < j1) {
-                key[u] = k;
+                bool ok;
+                key[u] = point_key(a, yv[u], &mm[u], &tt[u], &ok);
                 if (!ok)
                     atomicOr(a.flags, FLAG_BAD_Y);
                 if (a.hit && tt[u] == 0.0)
