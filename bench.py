@@ -34,8 +34,27 @@ PEAK_HBM = 8.0e12        # B/s
 # kernel (fetch x2.000, write x1.000).  Valid only for the kernel sources
 # they were taken on: any change to them turns the figure back into null
 # until the counters are taken again.
-TRAFFIC_SRC_SHA256 = None
-TRAFFIC = {}
+TRAFFIC_SRC_SHA256 = "b92404218cca11e7e780fd0fa5197daa400690d6b6840a4861664c3057529886"
+TRAFFIC = {
+    "fwd_eval": 97725903,
+    "fwd_eval_mixed": 83556471,
+    "fwd_sort": 53714100,
+    "fwd_trans": 64076512,
+    "fwd_trans_mixed": 16150363,
+    "fwd_up": 43013095,
+    "fwd_up_mixed": 17198586,
+    "inv_eval": 80839898,
+    "inv_eval_mixed": 50438178,
+    "inv_sort": 145102962,
+    "inv_trans": 127748641,
+    "inv_trans_mixed": 32141833,
+    "inv_up": 142043284,
+    "inv_up_mixed": 81890034,
+    "log_eval": 58178407,
+    "log_trans": 64365604,
+    "log_up": 43729975,
+    "log_up_mixed": 34963864,
+}
 # phase keys of one step (ms): plan wall time, then each measured phase
 PHASES = ("fwd_plan_ms", "fwd_sort_ms", "fwd_up_ms", "fwd_trans_ms", "fwd_eval_ms",
           "inv_plan_ms", "inv_sort_ms", "log_up_ms", "log_trans_ms", "log_eval_ms",
@@ -74,11 +93,18 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def traffic_of(phase):
-    t = TRAFFIC.get(phase)
-    if t is None or TRAFFIC_SRC_SHA256 != kernel_sources_sha256():
+def traffic_of(phase, mixed=False):
+    """Calibrated HBM bytes of one launch of the phase's kernels (null when
+    not taken on the current kernel sources).  The mixed path's entries end
+    in _mixed; its sorts and log-sums run the binary64 kernels."""
+    if TRAFFIC_SRC_SHA256 != kernel_sources_sha256():
         return None
-    return t
+    if mixed:
+        t = TRAFFIC.get(phase + "_mixed")
+        if t is None and phase.startswith(("log_", "fwd_sort", "inv_sort")):
+            t = TRAFFIC.get(phase)
+        return t
+    return TRAFFIC.get(phase)
 
 
 def boxes(l, lo=3):
@@ -462,7 +488,7 @@ def roofline(res, N, M, mixed):
                      "achieved": rate / scale, "peak": peak / scale, "unit": unit,
                      "frac": rate / peak, "work": work,
                      "work_unit": "bytes" if unit == "GB/s" else "flops",
-                     "traffic": traffic_of(key)}
+                     "traffic": traffic_of(key, mixed)}
     dom = max((k for k in rows if len(rows[k]["kernels"].split()) == 1 or
                rows[k]["kernels"].startswith("k_down_eval")),
               key=lambda k: rows[k]["ms"])

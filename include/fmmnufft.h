@@ -153,7 +153,10 @@ int nufft_adj(int64_t N, int64_t M, const double *y, const void *g, void *f,
  *       c_n = (1/N) sum_k f_k e^{-2 pi i n k / N}.
  * Arguments, precision paths and errors as nufft_fwd / inufft; the DFT runs
  * in the dtype's precision.  One-shot: one synchronisation at the end.  A
- * rocFFT failure returns FN_EHIP. */
+ * rocFFT failure returns FN_EHIP.  The rocFFT plans (one per device, N,
+ * dtype and direction; up to 64) are created on first use and kept until
+ * the process ends: later calls and spectral plans of that size share them,
+ * each with its own work buffer. */
 int nufft_spec_fwd(int64_t N, int64_t M, const double *y, const void *c, void *g,
                    double eps, int dtype, void *stream);
 int inufft_spec(int64_t N, const double *y, const void *g, void *c, double eps,

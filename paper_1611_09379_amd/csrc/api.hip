@@ -528,7 +528,8 @@ struct fn_plan {
     int log_terms = 0, log_mterms = 0; // log-sum FMM expansion lengths
     // spectral plans (Eq. p1): the uniform DFT by rocFFT around the FMM
     bool spec = false;
-    rocfft_plan fft = nullptr;
+    rocfft_plan fft = nullptr; // owned unless it came from the plan cache
+    bool fft_cached = false;
     rocfft_execution_info fft_info = nullptr;
     Buf fft_work, spec_buf; // rocFFT's work buffer; the N grid values f_k
     // temporaries of the setup, released after its synchronisation
@@ -580,10 +581,11 @@ static void release_plan(fn_plan *P)
     drop_events(P);
     if (P->fft_info)
         (void)rocfft_execution_info_destroy(P->fft_info);
-    if (P->fft)
+    if (P->fft && !P->fft_cached)
         (void)rocfft_plan_destroy(P->fft);
     P->fft_info = nullptr;
     P->fft = nullptr;
+    P->fft_cached = false;
 }
 
 // A temporary of the setup: kept until the plan's synchronisation.
@@ -1536,30 +1538,59 @@ static rocfft_status g_fft_setup = rocfft_status_success;
             return fail(FN_EHIP, "%s: rocFFT status %d", #expr, (int)e_);      \
     } while (0)
 
+// rocFFT plans by (device, N, dtype, direction), created once and shared by
+// every spectral plan and one-shot call (creating one takes milliseconds;
+// each user keeps its own execution info and work buffer, so shared plans
+// may run at once on different streams).  At most FFT_CACHE_MAX are kept;
+// beyond that a spectral plan owns its rocFFT plan.
+static std::mutex g_fft_mu;
+static std::map<std::tuple<int, int64_t, int, int>, rocfft_plan> g_fft_cache;
+static constexpr size_t FFT_CACHE_MAX = 64;
+
+static rocfft_status create_fft(int64_t N, int dtype, int kind, rocfft_plan *out)
+{
+    const size_t len = (size_t)N;
+    const rocfft_precision prec =
+        dtype == FN_C128 ? rocfft_precision_double : rocfft_precision_single;
+    if (kind == 0) // c -> f in place in spec_buf, unscaled e^{+2 pi i n k / N}
+        return rocfft_plan_create(out, rocfft_placement_inplace,
+                                  rocfft_transform_type_complex_inverse, prec, 1, &len, 1,
+                                  nullptr);
+    // f (spec_buf) -> c, e^{-2 pi i n k / N} / N
+    rocfft_plan_description d = nullptr;
+    rocfft_status e = rocfft_plan_description_create(&d);
+    if (e != rocfft_status_success)
+        return e;
+    e = rocfft_plan_description_set_scale_factor(d, 1.0 / (double)N);
+    if (e == rocfft_status_success)
+        e = rocfft_plan_create(out, rocfft_placement_notinplace,
+                               rocfft_transform_type_complex_forward, prec, 1, &len, 1, d);
+    (void)rocfft_plan_description_destroy(d);
+    return e;
+}
+
 // rocFFT plan of a spectral plan; the work buffer and the grid values are
 // allocated with the plan's workspace.
 static int setup_spec(fn_plan *P)
 {
     std::call_once(g_fft_once, [] { g_fft_setup = rocfft_setup(); });
     FFTCHK(g_fft_setup);
-    const size_t len = (size_t)P->N;
-    const rocfft_precision prec =
-        P->dtype == FN_C128 ? rocfft_precision_double : rocfft_precision_single;
-    if (P->kind == 0) {
-        // c -> f in place in spec_buf, unscaled e^{+2 pi i n k / N}
-        FFTCHK(rocfft_plan_create(&P->fft, rocfft_placement_inplace,
-                                  rocfft_transform_type_complex_inverse, prec, 1, &len, 1,
-                                  nullptr));
-    } else {
-        // f (spec_buf) -> c, e^{-2 pi i n k / N} / N
-        rocfft_plan_description d = nullptr;
-        FFTCHK(rocfft_plan_description_create(&d));
-        rocfft_status e = rocfft_plan_description_set_scale_factor(d, 1.0 / (double)P->N);
-        if (e == rocfft_status_success)
-            e = rocfft_plan_create(&P->fft, rocfft_placement_notinplace,
-                                   rocfft_transform_type_complex_forward, prec, 1, &len, 1, d);
-        (void)rocfft_plan_description_destroy(d);
-        FFTCHK(e);
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    const auto key = std::make_tuple(dev, P->N, P->dtype, P->kind == 0 ? 0 : 1);
+    {
+        std::lock_guard<std::mutex> lk(g_fft_mu);
+        auto it = g_fft_cache.find(key);
+        if (it != g_fft_cache.end()) {
+            P->fft = it->second;
+            P->fft_cached = true;
+        } else {
+            FFTCHK(create_fft(P->N, P->dtype, P->kind, &P->fft));
+            if (g_fft_cache.size() < FFT_CACHE_MAX) {
+                g_fft_cache[key] = P->fft;
+                P->fft_cached = true;
+            }
+        }
     }
     size_t wbytes = 0;
     FFTCHK(rocfft_plan_get_work_buffer_size(P->fft, &wbytes));
