@@ -1323,23 +1323,26 @@ __device__ __forceinline__ void log_prod_range(const NearStage<R> &ns, int32_t j
     expo += e;
 }
 
-// Log near field from staged sources [j0, j1) without the source `self`:
-// log prod |tau - sigma| (GT: the target is on the grid, tth = 0).
+// Log near field from staged sources [j0, j1) without the source `self`
+// (GT: the target is on the grid, tth = 0): the product of the distances
+// |tau - sigma| as mantissa and exponent, *prod x 2^*expo with *prod in
+// [1/2, 1) (1 for an empty range).  The source `self` (the target itself)
+// splits the range: no test per pair.
 template <typename R, bool GT>
-__device__ __forceinline__ double near_log_staged(const NearStage<R> &ns, int32_t j0,
-                                                  int32_t j1, int32_t self, int32_t tmr,
-                                                  double tth)
+__device__ __forceinline__ void near_prod_staged(const NearStage<R> &ns, int32_t j0, int32_t j1,
+                                                 int32_t self, int32_t tmr, double tth,
+                                                 double *prod, int *expo)
 {
-    double prod = 1.0;
-    int expo = 0;
-    // the source `self` (the target itself) splits the range: no test per pair
+    double p = 1.0;
+    int e = 0;
     if (self >= j0 && self < j1) {
-        log_prod_range<R, GT>(ns, j0, self, tmr, tth, prod, expo);
-        log_prod_range<R, GT>(ns, self + 1, j1, tmr, tth, prod, expo);
+        log_prod_range<R, GT>(ns, j0, self, tmr, tth, p, e);
+        log_prod_range<R, GT>(ns, self + 1, j1, tmr, tth, p, e);
     } else {
-        log_prod_range<R, GT>(ns, j0, j1, tmr, tth, prod, expo);
+        log_prod_range<R, GT>(ns, j0, j1, tmr, tth, p, e);
     }
-    return log(prod) + (double)expo * 0.69314718055994530942;
+    *prod = p;
+    *expo = e;
 }
 
 // Integral of log|tau - sigma| over sigma in the leaves leaf - 1 .. leaf + 1
@@ -1999,12 +2002,20 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             const int il = (int)(leaf - leaf0);
             const R u = (R)rel_coord_r(k, 0.0, leaf, a.l, N, invN);
             V far = horner4<R, V, PD>(leafloc, RS, il, u);
-            const double nr =
-                staged ? near_log_staged<R, true>(ns, ns.off[il], ns.off[il + 3], -1,
-                                            (int32_t)(k - base), 0.0) -
-                             near_log_background(k, 0.0, leaf, a.l, N)
-                       : near_log<R, V>(a, k, 0.0, leaf, -1);
-            const double lc = (double)far + nr;
+            // log|Chat_k| = lt + log(prod), prod in [1/2, 1]: |Chat_k| =
+            // prod exp(lt) without the logarithm of the product (lt is at
+            // most 0.7 above log|Chat_k|, and the range test below uses
+            // that bound)
+            double prod = 1.0, lt;
+            if (staged) {
+                int expo;
+                near_prod_staged<R, true>(ns, ns.off[il], ns.off[il + 3], -1,
+                                          (int32_t)(k - base), 0.0, &prod, &expo);
+                lt = ((double)far - near_log_background(k, 0.0, leaf, a.l, N)) +
+                     (double)expo * 0.69314718055994530942;
+            } else {
+                lt = (double)far + near_log<R, V>(a, k, 0.0, leaf, -1);
+            }
             // #{j : s_j <= k}: the points of the leaves before k's leaf, plus
             // a binary search over the (sorted) points of k's leaf
             int32_t lo, hi;
@@ -2038,9 +2049,10 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             if (a.hit[k] >= 0) {
                 a.chat_out[k] = 0.0;
             } else {
-                if (!(fabs(lc) <= a.log_max))
+                // |log|Chat_k|| <= log_max for lt - 0.7 ... lt
+                if (!(lt <= a.log_max && lt - 0.69314718055994530942 >= -a.log_max))
                     atomicOr(a.flags_out, FLAG_RANGE);
-                a.chat_out[k] = (((k + neg) & 1) ? -1.0 : 1.0) * exp(lc);
+                a.chat_out[k] = (((k + neg) & 1) ? -prod : prod) * exp(lt);
             }
         }
         for (int32_t t = w.t0 + tid; t < w.t1; t += BLOCK) {
@@ -2050,18 +2062,26 @@ __device__ __forceinline__ void down_eval_body(const DownArgs<R, V> &a, int blk)
             const int il = (int)(leaf - leaf0);
             const R u = (R)rel_coord_r(tm, th, leaf, a.l, N, invN);
             V far = horner4<R, V, PD>(leafloc, RS, il, u);
-            const double nr =
-                staged ? near_log_staged<R, false>(ns, ns.off[il], ns.off[il + 3], t + ns.self0,
-                                            (int32_t)(tm - base), th) -
-                             near_log_background(tm, th, leaf, a.l, N)
-                       : near_log<R, V>(a, tm, th, leaf, t);
             // the net count of Omega_1 carried log(2 pi / N) for the point
-            // itself, whose log|t| term the near field skips
-            const double ld = -((double)far + nr - a.logself);
-            if (!(fabs(ld) <= a.log_max))
+            // itself, whose log|t| term the near field skips:
+            // log|Dhat_j| = lt - log(prod), prod in [1/2, 1], so |Dhat_j| =
+            // exp(lt) / prod (lt is at most 0.7 below log|Dhat_j|)
+            double prod = 1.0, lt;
+            if (staged) {
+                int expo;
+                near_prod_staged<R, false>(ns, ns.off[il], ns.off[il + 3], t + ns.self0,
+                                           (int32_t)(tm - base), th, &prod, &expo);
+                lt = -(((double)far - near_log_background(tm, th, leaf, a.l, N)) +
+                       (double)expo * 0.69314718055994530942 - a.logself);
+            } else {
+                lt = -((double)far + near_log<R, V>(a, tm, th, leaf, t) - a.logself);
+            }
+            if (!(lt >= -a.log_max && lt + 0.69314718055994530942 <= a.log_max))
                 atomicOr(a.flags_out, FLAG_RANGE);
-            const double sg = (((tm + (N - 1 - t)) & 1) ? -1.0 : 1.0) * exp(ld);
-            a.dhat_out[t] = {sg * sinpi(th), sg * cospi(th)};
+            const double sg = (((tm + (N - 1 - t)) & 1) ? -1.0 : 1.0) * exp(lt) / prod;
+            double sp, cp;
+            sincospi(th, &sp, &cp);
+            a.dhat_out[t] = {sg * sp, sg * cp};
         }
     }
 }
