@@ -655,15 +655,15 @@ __device__ __forceinline__ int32_t leaf_rank(int32_t t, int32_t t0, int32_t t1, 
     return rank;
 }
 
-constexpr int RANK_LEAVES = 32;   // leaves per workgroup of k_rank
-constexpr int RANK_CAP = 2048;    // points of those leaves staged in LDS
+constexpr int RANK_LEAVES = 16;   // leaves per workgroup of k_rank
+constexpr int RANK_CAP = 1024;    // points of those leaves staged in LDS
 
 // Orders the points of every leaf by position (so the whole set is sorted
 // along the circle); two points at the same position raise FLAG_DUP.
-// Workgroup g takes leaves [32 g, 32 g + 32).  When their points fit, they
+// Workgroup g takes leaves [16 g, 16 g + 16).  When their points fit, they
 // are staged in LDS with the leaves' offsets, and each thread ranks one
-// point against its leaf from LDS (its leaf found by a binary search of the
-// staged offsets); else the points are read in place.  A leaf holding more
+// point against its leaf from LDS (its leaf read from the sorted keys); else
+// the points are read in place.  A leaf holding more
 // than dense_max points raises FLAG_DENSE and keeps its order (still a
 // permutation): the point set is far too clustered for the inverse, and
 // ranking it would cost the square of the leaf's size.
@@ -715,14 +715,7 @@ __global__ void __launch_bounds__(256)
         auto gm = [&](int32_t u) { return lm[u]; };
         auto gth = [&](int32_t u) { return lth[u]; };
         for (int32_t i = threadIdx.x; i < T1 - T0; i += 256) {
-            int lo = 0, hi = nb; // leaf: largest li with loff[li] <= i
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (loff[mid] <= i)
-                    lo = mid;
-                else
-                    hi = mid;
-            }
+            const int lo = (int)(gkey[T0 + i] - b0); // the point's leaf in the group
             const int32_t t0 = loff[lo], t1 = loff[lo + 1];
             int32_t rank;
             if (t1 - t0 > dense_max) {
