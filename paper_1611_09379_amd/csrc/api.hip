@@ -173,7 +173,7 @@ struct Arena {
     // operator tables built into the fixed region by this call (key, where)
     long tab_key = -1;
     void *tab_base = nullptr;
-    size_t tab_off[7] = {0};
+    size_t tab_off[8] = {0};
 };
 thread_local Arena *g_arena = nullptr;
 constexpr size_t ARENA_CHUNK = size_t(64) << 20;
@@ -307,7 +307,7 @@ static long double bernoulli_abs(int m)
 }
 
 struct Tables {
-    std::vector<long double> m2m, l2l, m2l4, m2l6, bin, reg1, reg2;
+    std::vector<long double> m2m, l2l, m2l4, m2l6, regR, regL, reg1, reg2;
 };
 
 // M2M (child at c_p + s r_p/2 -> parent):  a^P_n = sum_{m<=n} C(n,m) 2^-n s^(n-m) a^C_m
@@ -327,7 +327,8 @@ struct Tables {
 static void build_tables(int PU, int PD, int q, int kernel, Tables &T)
 {
     T.m2m.assign(PU * PU, 0);
-    T.bin.assign(PU * PU, 0);
+    T.regR.assign(PU * PD, 0);
+    T.regL.assign(PU * PD, 0);
     T.l2l.assign(PD * PD, 0);
     T.m2l4.assign(PD * PD, 0);
     T.m2l6.assign(PD * PD, 0);
@@ -375,9 +376,6 @@ static void build_tables(int PU, int PD, int q, int kernel, Tables &T)
                 Mt[m * PD + n] = v;
             }
     }
-    for (int t = 0; t < PU; ++t)
-        for (int j = 0; j <= t; ++j)
-            T.bin[t * PU + j] = binom(t, j);
     const long double qpi = 0.785398163397448309615660845819875721L; // pi/4
     std::vector<long double> fac(2 * PU + 4, 1);
     for (int i = 1; i < (int)fac.size(); ++i)
@@ -397,13 +395,27 @@ static void build_tables(int PU, int PD, int q, int kernel, Tables &T)
             T.reg2[t * PD + lo] = kap * four_m;
         }
     }
+    // the neighbours' moments about the quarter's centre: a quarter's
+    // moments shifted by +-2 half-widths, (v +- 2)^t = sum_j C(t,j) (+-2)^(t-j) v^j,
+    // composed with reg1 (right neighbour: +2; left: -2)
+    for (int j = 0; j < PU; ++j)
+        for (int lo = 0; lo < PD; ++lo) {
+            long double r = 0, l = 0;
+            for (int t = j; t < PU; ++t) {
+                const long double c = T.reg1[t * PD + lo] * binom(t, j) * ldexpl(1.0L, t - j);
+                r += c;
+                l += ((t - j) & 1) ? -c : c;
+            }
+            T.regR[j * PD + lo] = r;
+            T.regL[j * PD + lo] = l;
+        }
 }
 
 // Device copies of the tables, built once per (precision, kernel, PU, PD,
 // q, device) and kept for the life of the process.
 struct TableSet {
     void *base = nullptr;
-    size_t off[7] = {0};
+    size_t off[8] = {0};
 };
 
 static std::mutex g_tab_mu;
@@ -425,16 +437,16 @@ static int get_tables(int kernel, int PU, int PD, int q, OpTables<R> *out)
         if (A.tab_key == fkey) {
             const R *b = (const R *)A.tab_base;
             *out = {b + A.tab_off[0], b + A.tab_off[1], b + A.tab_off[2], b + A.tab_off[3],
-                    b + A.tab_off[4], b + A.tab_off[5], b + A.tab_off[6]};
+                    b + A.tab_off[4], b + A.tab_off[5], b + A.tab_off[6], b + A.tab_off[7]};
             return FN_OK;
         }
         Tables T;
         build_tables(PU, PD, q, kernel, T);
         std::vector<R> h;
-        size_t off[7];
-        const std::vector<long double> *parts[7] = {&T.m2m, &T.l2l, &T.m2l4, &T.m2l6,
-                                                    &T.bin, &T.reg1, &T.reg2};
-        for (int i = 0; i < 7; ++i) {
+        size_t off[8];
+        const std::vector<long double> *parts[8] = {&T.m2m, &T.l2l,  &T.m2l4, &T.m2l6,
+                                                    &T.regR, &T.regL, &T.reg1, &T.reg2};
+        for (int i = 0; i < 8; ++i) {
             off[i] = h.size();
             for (long double x : *parts[i])
                 h.push_back((R)x);
@@ -445,10 +457,10 @@ static int get_tables(int kernel, int PU, int PD, int q, OpTables<R> *out)
         HIPCHK(hipMemcpy(b, h.data(), h.size() * sizeof(R), hipMemcpyHostToDevice));
         A.tab_key = fkey;
         A.tab_base = b;
-        for (int i = 0; i < 7; ++i)
+        for (int i = 0; i < 8; ++i)
             A.tab_off[i] = off[i];
         *out = {b + off[0], b + off[1], b + off[2], b + off[3], b + off[4], b + off[5],
-                b + off[6]};
+                b + off[6], b + off[7]};
         return FN_OK;
     }
     if (it == g_tab_cache.end()) {
@@ -456,9 +468,9 @@ static int get_tables(int kernel, int PU, int PD, int q, OpTables<R> *out)
         build_tables(PU, PD, q, kernel, T);
         std::vector<R> h;
         TableSet ts;
-        const std::vector<long double> *parts[7] = {&T.m2m, &T.l2l, &T.m2l4, &T.m2l6,
-                                                    &T.bin, &T.reg1, &T.reg2};
-        for (int i = 0; i < 7; ++i) {
+        const std::vector<long double> *parts[8] = {&T.m2m, &T.l2l,  &T.m2l4, &T.m2l6,
+                                                    &T.regR, &T.regL, &T.reg1, &T.reg2};
+        for (int i = 0; i < 8; ++i) {
             ts.off[i] = h.size();
             for (long double x : *parts[i])
                 h.push_back((R)x);
@@ -469,7 +481,7 @@ static int get_tables(int kernel, int PU, int PD, int q, OpTables<R> *out)
     }
     const R *b = (const R *)it->second.base;
     const size_t *o = it->second.off;
-    *out = {b + o[0], b + o[1], b + o[2], b + o[3], b + o[4], b + o[5], b + o[6]};
+    *out = {b + o[0], b + o[1], b + o[2], b + o[3], b + o[4], b + o[5], b + o[6], b + o[7]};
     return FN_OK;
 }
 
@@ -738,7 +750,10 @@ static int setup_fmm(fn_plan *P, int kernel, int PU, int PD, int q, bool sorted_
     // the translation kernel: its two level buffers and the L2L table; the
     // M2L kernel: the source rows and the output rows of its boxes
     F.tr_smem = (size_t)2 * F.rows_buf * F.RSd * es + (size_t)PD * PD * es;
-    F.m2l_smem = std::max((size_t)(M2L_BOXES + 6) * F.RSd * es, 8 * (size_t)PU * sizeof(V));
+    // (block 0: the four level-2 multipoles and the regular part's partial
+    // sums, 4 PU + 4 BLOCK values)
+    F.m2l_smem = std::max((size_t)(M2L_BOXES + 6) * F.RSd * es,
+                          (4 * (size_t)PU + 4 * BLOCK) * sizeof(V));
     if (F.tr_smem > lim || F.m2l_smem > lim)
         return fail(FN_EINVAL, "expansion length %d needs %zu bytes of LDS", PD,
                     std::max(F.tr_smem, F.m2l_smem));

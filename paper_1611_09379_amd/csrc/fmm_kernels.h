@@ -166,11 +166,16 @@ __device__ __forceinline__ int out_row(int lane, int r)
 //   l2l  PD x PD   L2L to the left child, same coefficients
 //   m2l4, m2l6 PD x PD  M2L for delta = (c_t - c_s)/r = +4, +6; delta = -4, -6
 //                  differ by (-1)^(m+n+1) (cot kernel) or (-1)^(m+n) (log)
-//   bin  PU x PU   C(t, j) at [t][j]
-//   reg1, reg2 PU x PD  level-2 regular part (Eq. p20 and its log analogue)
+//   reg1, reg2 PU x PD  level-2 regular part (Eq. p20 and its log analogue):
+//                  the weights of the moments of Omega_1 and of the opposite
+//                  quarter about the quarter's centre
+//   regR, regL PU x PD  reg1 composed with the shift of the right (left)
+//                  neighbour's moments to the quarter's centre,
+//                  regR[j][lo] = sum_{t>=j} reg1[t][lo] C(t,j) 2^(t-j), regL
+//                  the same with the sign (-1)^(t-j)
 template <typename R>
 struct OpTables {
-    const R *m2m, *l2l, *m2l4, *m2l6, *bin, *reg1, *reg2;
+    const R *m2m, *l2l, *m2l4, *m2l6, *regR, *regL, *reg1, *reg2;
 };
 
 // A-operands of one 16-row tile of a square operator, held in registers:
@@ -825,65 +830,76 @@ __global__ void __launch_bounds__(BLOCK) kb_up_band(const UpArgs<R, V> *aa, Bloc
 
 // Level 2 (one workgroup): the regular part of Eq. (p20) as the level-2
 // local polynomial of every quarter, from the four level-2 multipoles, and
-// the sum of the weights.  A1 holds the moments of Omega_1(P_n) about the
-// centre of P_n: the three quarters unwrapped around it, (v + 2i)^t expanded
-// for i = -1, 0, +1.
-// The level-2 regular part (Eq. p20) and S, by one workgroup: the local
-// polynomial of each level-2 box from the four level-2 multipoles (its own
-// quarter's and its neighbours' moments alpha1, the opposite quarter's
-// alpha2), with the binomial and regular-part tables read from memory
-// (cached; each is read by a few hundred threads).  a2, A1: 4 PU values of
-// LDS each.
+// the sum of the weights.  The moments of Omega_1(P_q) about the centre of
+// P_q are quarter q's own plus its neighbours' shifted by -+2 half-widths
+// ((v -+ 2)^t expanded); with that shift folded into the tables regR and
+// regL, local coefficient lo of quarter q is one sum over t of
+//   reg1 a_q + regR a_{q+1} + regL a_{q-1} + reg2 a_{q+2}.
+// Thread (lo, c) sums the t of chunk c for all four quarters, its table
+// values loaded at once (one round trip); the chunks' partial sums are then
+// added in LDS.  a2: 4 PU values of LDS; part: 4 PD x (BLOCK / PD) values.
 template <typename R, typename V, int KER>
-__device__ __forceinline__ void regular_part(const UpArgs<R, V> &a, int PU, V *a2, V *A1)
+__device__ __forceinline__ void regular_part(const UpArgs<R, V> &a, int PU, V *a2, V *part)
 {
-    const int PD = a.PD; // at most 64
+    const int PD = a.PD; // 16, 32, 48 or 64; PU a multiple of 16
     const int tid = threadIdx.x;
     for (int i = tid; i < 4 * PU; i += BLOCK)
         a2[i] = a.mp[i]; // level 2 is the first level of mp
+    const int nch = BLOCK / PD;                 // chunks of t (4 .. 16)
+    const int tlen = (PU + nch - 1) / nch;      // t values per chunk (<= 16)
+    const int lo = tid % PD, ch = tid / PD;
+    const int t0 = ch * tlen;
+    constexpr int TMAX = 16;
     __syncthreads();
-    for (int idx = tid; idx < 4 * PU; idx += BLOCK) {
-        const int q = idx / PU, t = idx - q * PU;
-        V acc = a2[q * PU + t];
-        const V *lft = a2 + ((q + 3) & 3) * PU;
-        const V *rgt = a2 + ((q + 1) & 3) * PU;
-        const R *brow = a.T.bin + t * PU;
-        R pw = R(1);
-        // the table row in batches of 8 loads in flight (indices clamped)
-        for (int j0 = t; j0 >= 0; j0 -= 8) {
-            R tb[8];
+    V acc[4] = {vzero<V>(), vzero<V>(), vzero<V>(), vzero<V>()};
+    // one table a pass (its loads in flight at once), so that the table
+    // values take few registers: the M2L workgroups of the same kernel
+    // keep their occupancy
+#pragma unroll 1
+    for (int pass = 0; pass < 4; ++pass) {
+        const R *tab = pass == 0   ? a.T.reg1
+                       : pass == 1 ? a.T.regR
+                       : pass == 2 ? a.T.regL
+                                   : a.T.reg2;
+        // the moments the table weighs: quarter q's own, its right and its
+        // left neighbour's, the opposite quarter's
+        const int qs = pass == 0 ? 0 : (pass == 1 ? 1 : (pass == 2 ? 3 : 2));
+        R w[TMAX];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                tb[u] = brow[j0 - u >= 0 ? j0 - u : 0];
+        for (int k = 0; k < TMAX; ++k) {
+            const int t = t0 + k < PU ? t0 + k : PU - 1; // clamped
+            w[k] = tab[t * PD + lo];
+        }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int j = j0 - u;
-                if (j >= 0) {
-                    const R cb = tb[u] * pw;
-                    vfma(acc, cb, rgt[j]);
-                    vfma(acc, ((t - j) & 1) ? -cb : cb, lft[j]);
-                    pw *= R(2);
-                }
+        for (int k = 0; k < TMAX; ++k) {
+            const int t = t0 + k;
+            if (k < tlen && t < PU) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    vfma(acc[q], w[k], a2[((q + qs) & 3) * PU + t]);
             }
         }
-        A1[idx] = acc;
     }
+    if (ch < nch) // (PD = 48: 240 threads in 5 chunks)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            part[(q * PD + lo) * nch + ch] = acc[q];
     __syncthreads();
     for (int idx = tid; idx < 4 * PD; idx += BLOCK) {
-        const int q = idx / PD, lo = idx - q * PD;
-        const V *o = a2 + ((q + 2) & 3) * PU;
-        const V *n1 = A1 + q * PU;
-        V acc = vzero<V>();
-#pragma unroll 8
-        for (int t = 0; t < PU; ++t) {
-            vfma(acc, a.T.reg1[t * PD + lo], n1[t]);
-            vfma(acc, a.T.reg2[t * PD + lo], o[t]);
-        }
+        const int q = idx / PD, l = idx - q * PD;
+        V sum = part[idx * nch];
+        for (int c = 1; c < nch; ++c)
+            vadd(sum, part[idx * nch + c]);
         if constexpr (KER == KER_LOG) {
-            if (lo == 0)
-                acc += (R)(a.logc1 * (double)n1[0] + a.logc2 * (double)o[0]);
+            if (l == 0) {
+                // the log kernel's monopoles: Omega_1 (the quarter and its
+                // neighbours) and the opposite quarter
+                const double m1 = (double)a2[q * PU] + (double)a2[((q + 1) & 3) * PU] +
+                                  (double)a2[((q + 3) & 3) * PU];
+                sum += (R)(a.logc1 * m1 + a.logc2 * (double)a2[((q + 2) & 3) * PU]);
+            }
         }
-        a.loc2[idx] = acc;
+        a.loc2[idx] = sum;
     }
     if constexpr (KER == KER_COT) {
         if (tid == 0) {
