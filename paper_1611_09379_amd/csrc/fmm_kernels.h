@@ -1574,17 +1574,17 @@ __device__ __forceinline__ void m2l_body(const DownArgs<R, V> &a, const UpArgs<R
     // first PD coefficients (every load of a thread issued first)
     const V *mpl = a.mp + lev_off(L, a.PU);
     const int n = (nb + 6) * PD;
-    for (int e0 = 0; e0 < n; e0 += 4 * BLOCK) {
-        V r[4];
+    for (int e0 = 0; e0 < n; e0 += 8 * BLOCK) {
+        V r[8];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 8; ++k) {
             int e = e0 + tid + k * BLOCK;
             e = e < n ? e : n - 1;
             const int i = e / PD, m = e - i * PD;
             r[k] = mpl[((b0 - 3 + i) & mask) * a.PU + m];
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 8; ++k) {
             const int e = e0 + tid + k * BLOCK;
             if (e < n) {
                 const int i = e / PD, m = e - i * PD;
