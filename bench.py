@@ -34,26 +34,26 @@ PEAK_HBM = 8.0e12        # B/s
 # kernel (fetch x2.000, write x1.000).  Valid only for the kernel sources
 # they were taken on: any change to them turns the figure back into null
 # until the counters are taken again.
-TRAFFIC_SRC_SHA256 = "b92404218cca11e7e780fd0fa5197daa400690d6b6840a4861664c3057529886"
+TRAFFIC_SRC_SHA256 = "5a3e18b5525927d3af1738fa10d90f0eb1010aaab91832379286abe1edfbb81a"
 TRAFFIC = {
-    "fwd_eval": 97725903,
-    "fwd_eval_mixed": 83556471,
-    "fwd_sort": 53714100,
-    "fwd_trans": 64076512,
-    "fwd_trans_mixed": 16150363,
-    "fwd_up": 43013095,
-    "fwd_up_mixed": 17198586,
-    "inv_eval": 80839898,
-    "inv_eval_mixed": 50438178,
-    "inv_sort": 145102962,
-    "inv_trans": 127748641,
-    "inv_trans_mixed": 32141833,
-    "inv_up": 142043284,
-    "inv_up_mixed": 81890034,
-    "log_eval": 58178407,
-    "log_trans": 64365604,
-    "log_up": 43729975,
-    "log_up_mixed": 34963864,
+    "fwd_eval": 97751101,
+    "fwd_eval_mixed": 83526757,
+    "fwd_sort": 53737615,
+    "fwd_trans": 64106845,
+    "fwd_trans_mixed": 16169173,
+    "fwd_up": 43038469,
+    "fwd_up_mixed": 17198533,
+    "inv_eval": 80840602,
+    "inv_eval_mixed": 50424981,
+    "inv_sort": 149815518,
+    "inv_trans": 127791826,
+    "inv_trans_mixed": 32144201,
+    "inv_up": 142024306,
+    "inv_up_mixed": 81883188,
+    "log_eval": 58129341,
+    "log_trans": 64394485,
+    "log_up": 43730137,
+    "log_up_mixed": 34963917,
 }
 # phase keys of one step (ms): plan wall time, then each measured phase
 PHASES = ("fwd_plan_ms", "fwd_sort_ms", "fwd_up_ms", "fwd_trans_ms", "fwd_eval_ms",
