@@ -356,6 +356,55 @@ def run_adjoint(fn, torch, workloads, N, steps, warmup):
     return out
 
 
+def run_large(fn, torch, workloads, warmup=1, steps=3):
+    """The large configuration: a forward transform at N = M = 2^24 (uniform
+    y) and an inverse at N = 2^22 (jittered grid, u ~ U(-0.3, 0.3)), eps
+    1e-10 (binary64) and 1e-6 (mixed): one-shot times and execute-only
+    times (plans reused)."""
+    out = {}
+    Nf, Ni = 1 << 24, 1 << 22
+    y, f, c = workloads.forward_case(Nf, Nf, "uniform", seed=11)
+    yi, ci = workloads.inverse_case(Ni, 0.3, seed=12)
+    rng = np.random.default_rng(13)
+    gi = rng.standard_normal(Ni) + 1j * rng.standard_normal(Ni)
+    yd, yid = torch.from_numpy(y).cuda(), torch.from_numpy(yi).cuda()
+    f64, gi64 = torch.from_numpy(f).cuda(), torch.from_numpy(gi).cuda()
+    del y, f, c, yi, ci, gi
+
+    def timed(fun):
+        for _ in range(warmup):
+            fun()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fun()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    for name, dt, eps in (("f64", torch.complex128, 1e-10), ("mixed", torch.complex64, 1e-6)):
+        fx, gx = f64.to(dt), gi64.to(dt)
+        g = torch.empty(Nf, dtype=dt, device="cuda")
+        fo = torch.empty(Ni, dtype=dt, device="cuda")
+        tf = timed(lambda: fn.nufft_fwd(yd, fx, eps, out=g))
+        ti = timed(lambda: fn.inufft(yid, gx, eps, out=fo))
+        pf = fn.Plan.forward(Nf, yd, eps, fn.FN_C128 if dt == torch.complex128 else fn.FN_C64)
+        pi = fn.Plan.inverse(yid, eps, fn.FN_C128 if dt == torch.complex128 else fn.FN_C64)
+        ef = timed(lambda: pf.execute(fx, out=g))
+        ei = timed(lambda: pi.execute(gx, out=fo))
+        info_f, info_i = pf.info(), pi.info()
+        pf.destroy()
+        pi.destroy()
+        out[name] = {"eps": eps,
+                     "fwd_2p24": {"one_shot_ms": tf * 1e3, "points_per_s": 2 * Nf / tf,
+                                  "exec_ms": ef * 1e3, "lmax": info_f.lmax,
+                                  "nterms": info_f.nterms},
+                     "inv_2p22": {"one_shot_ms": ti * 1e3, "points_per_s": 2 * Ni / ti,
+                                  "exec_ms": ei * 1e3, "lmax": info_i.lmax,
+                                  "nterms": info_i.nterms}}
+        del fx, gx, g, fo
+    return out
+
+
 def run_spectral(fn, torch, workloads, N, steps, warmup):
     """Spectral transforms (Eq. p1): coefficients -> values at uniform y
     (forward) and values at a jittered grid -> coefficients (inverse),
@@ -722,6 +771,7 @@ def main():
         out["adjoint"] = run_adjoint(fn, torch, workloads, N, args.steps, args.warmup)
         out["spectral"] = run_spectral(fn, torch, workloads, N, args.steps, args.warmup)
         out["batched_512"] = run_batched(fn, torch, workloads, args.steps, args.warmup)
+        out["large"] = run_large(fn, torch, workloads)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, M, yu_h, f_h, yj_h, args.cpu_seconds)
     print(json.dumps(out), flush=True)
