@@ -1047,7 +1047,13 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
         }
     }
     P->flags_ready = true;
-    if (J.lds_path) {
+    if (J.lds_path && a.spt && !a.skey && nbins <= 4 * SORT_THREADS &&
+        a.chunk <= PLACE_REC_MAX) {
+        // records staged in LDS in their destination order, then written
+        const size_t smem = (size_t)PLACE_REC_MAX * (sizeof(SortedPt) + 4) +
+                            (3 * (size_t)nbins + 32) * 4;
+        hipLaunchKernelGGL(k_place_rec, dim3(a.nblk), dim3(SORT_THREADS), smem, st, a);
+    } else if (J.lds_path) {
         hipLaunchKernelGGL(k_place, dim3(a.nblk), dim3(SORT_THREADS), (size_t)nbins * 4, st, a);
     } else {
         hipLaunchKernelGGL(k_scatter, dim3(grid_for(a.n)), dim3(256), 0, st, a.n,

@@ -425,6 +425,107 @@ __device__ __forceinline__ int32_t block_scan1024(int32_t x, int32_t *ws, int32_
     return (wv ? ws[16 + wv - 1] : 0) + v - x;
 }
 
+// Placement of sorted records (the forward's targets) for small blocks:
+// k_place with the block's records staged in LDS in their destination
+// order before they are written.  A block's points of one key go to
+// consecutive positions, so the write-out covers each run of positions
+// with consecutive lanes instead of single 16-byte stores scattered over
+// the output (which the memory system writes as whole sectors).  Needs the
+// whole chunk in one pass (chunk <= PLACE_REC_MAX), nbins <= 4096 and no
+// key array.
+// LDS: cur, cur0, lbase (3 nbins words), 32 scan words, PLACE_REC_MAX
+// records and their positions.
+constexpr int PLACE_REC_MAX = 4096;
+
+__device__ __forceinline__ void place_rec_body(const SortArgs &a, int blk)
+{
+    extern __shared__ __align__(16) int32_t lds_place[];
+    const int nbins = a.nbins;
+    SortedPt *rec = reinterpret_cast<SortedPt *>(lds_place); // PLACE_REC_MAX
+    int32_t *gpos = lds_place + 4 * PLACE_REC_MAX;            // PLACE_REC_MAX
+    int32_t *cur = gpos + PLACE_REC_MAX;                      // nbins
+    int32_t *cur0 = cur + nbins;                              // nbins
+    int32_t *lbase = cur0 + nbins;                            // nbins
+    int32_t *ws = lbase + nbins;                              // 32
+    const int32_t *Hb = a.H + (int64_t)blk * nbins;
+    const bool last = blk + 1 == a.nblk;
+    // cursors, and this block's count of every key: the next block's
+    // exclusive prefix (or the key's total) minus this block's
+    constexpr int KPT = 4; // keys per thread (nbins <= 4096)
+    int32_t cnt[KPT], sum = 0;
+#pragma unroll
+    for (int u = 0; u < KPT; ++u) {
+        const int k = (int)threadIdx.x * KPT + u;
+        cnt[u] = 0;
+        if (k < nbins) {
+            const int32_t c0 = a.off[k] + Hb[k];
+            const int32_t c1 = last ? a.off[k + 1] : a.off[k] + Hb[nbins + k];
+            cur[k] = c0;
+            cur0[k] = c0;
+            cnt[u] = c1 - c0;
+        }
+        sum += cnt[u];
+    }
+    int32_t total;
+    int32_t run = block_scan1024(sum, ws, &total);
+#pragma unroll
+    for (int u = 0; u < KPT; ++u) {
+        const int k = (int)threadIdx.x * KPT + u;
+        if (k < nbins)
+            lbase[k] = run;
+        run += cnt[u];
+    }
+    __syncthreads();
+    const int64_t j0 = (int64_t)blk * a.chunk;
+    const int64_t j1 = j0 + a.chunk < a.n ? j0 + a.chunk : a.n;
+    const int64_t jb = j0 + threadIdx.x;
+    int32_t key[SORT_BATCH], mm[SORT_BATCH];
+    double tt[SORT_BATCH], yv[SORT_BATCH];
+#pragma unroll
+    for (int u = 0; u < SORT_BATCH; ++u) { // loads clamped: all in flight
+        const int64_t j = jb + u * SORT_THREADS;
+        yv[u] = a.y[j < j1 ? j : j1 - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < SORT_BATCH; ++u) {
+        const int64_t j = jb + u * SORT_THREADS;
+        key[u] = -1;
+        mm[u] = 0;
+        tt[u] = 0.0;
+        if (j < j1) {
+            bool ok;
+            key[u] = point_key(a, yv[u], &mm[u], &tt[u], &ok);
+            if (!ok)
+                atomicOr(a.flags, FLAG_BAD_Y);
+            if (a.hit && tt[u] == 0.0)
+                atomicExch(&a.hit[mm[u]], (int32_t)j);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < SORT_BATCH; ++u) {
+        int start, len;
+        key_runs(key[u], &start, &len);
+        int32_t base = 0;
+        if (len && key[u] >= 0)
+            base = atomicAdd(&cur[key[u]], len);
+        base = __shfl(base, start);
+        if (key[u] >= 0) {
+            const int32_t pos = base + ((int)(threadIdx.x & 63) - start);
+            const int32_t slot = lbase[key[u]] + (pos - cur0[key[u]]);
+            rec[slot] = {mm[u], (int32_t)(jb + u * SORT_THREADS), tt[u]};
+            gpos[slot] = pos;
+        }
+    }
+    __syncthreads();
+    for (int32_t q = threadIdx.x; q < total; q += SORT_THREADS)
+        a.spt[gpos[q]] = rec[q];
+}
+
+__global__ void __launch_bounds__(SORT_THREADS) k_place_rec(SortArgs a)
+{
+    place_rec_body(a, blockIdx.x);
+}
+
 // Exclusive scan of up to SCAN1_MAX counts in one workgroup of 1024 threads:
 // the counts are loaded coalesced into LDS (skewed by one word per 32, so
 // that the per-thread runs below are free of bank conflicts), thread i scans
