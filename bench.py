@@ -34,26 +34,26 @@ PEAK_HBM = 8.0e12        # B/s
 # kernel (fetch x2.000, write x1.000).  Valid only for the kernel sources
 # they were taken on: any change to them turns the figure back into null
 # until the counters are taken again.
-TRAFFIC_SRC_SHA256 = "5a3e18b5525927d3af1738fa10d90f0eb1010aaab91832379286abe1edfbb81a"
+TRAFFIC_SRC_SHA256 = "df6dc466dba19088f794a68c1ca0ef34fe50c2cbed3c830414ecbf56d44a0136"
 TRAFFIC = {
-    "fwd_eval": 97751101,
-    "fwd_eval_mixed": 83526757,
-    "fwd_sort": 53737615,
-    "fwd_trans": 64106845,
-    "fwd_trans_mixed": 16169173,
-    "fwd_up": 43038469,
-    "fwd_up_mixed": 17198533,
-    "inv_eval": 80840602,
-    "inv_eval_mixed": 50424981,
-    "inv_sort": 149815518,
-    "inv_trans": 127791826,
-    "inv_trans_mixed": 32144201,
-    "inv_up": 142024306,
-    "inv_up_mixed": 81883188,
-    "log_eval": 58129341,
-    "log_trans": 64394485,
-    "log_up": 43730137,
-    "log_up_mixed": 34963917,
+    "fwd_eval": 97701201,
+    "fwd_eval_mixed": 83459977,
+    "fwd_sort": 43260992,
+    "fwd_trans": 64102565,
+    "fwd_trans_mixed": 16168591,
+    "fwd_up": 43046109,
+    "fwd_up_mixed": 17252203,
+    "inv_eval": 80840633,
+    "inv_eval_mixed": 50438177,
+    "inv_sort": 149824525,
+    "inv_trans": 127785659,
+    "inv_trans_mixed": 32159989,
+    "inv_up": 142010895,
+    "inv_up_mixed": 81897854,
+    "log_eval": 58137232,
+    "log_trans": 64386671,
+    "log_up": 43733339,
+    "log_up_mixed": 34945256,
 }
 # phase keys of one step (ms): plan wall time, then each measured phase
 PHASES = ("fwd_plan_ms", "fwd_sort_ms", "fwd_up_ms", "fwd_trans_ms", "fwd_eval_ms",
