@@ -507,11 +507,11 @@ def phase_table(res, N, M, mixed):
     lf, li = fi.lmax, ii.lmax
     T = "TFLOP/s"
     return [
-        ("fwd_sort", "k_hist k_colscan k_scan_work k_place", "hbm", sort_bytes(M), "GB/s", PEAK_HBM),
+        ("fwd_sort", "k_hist k_colscan k_scan_work k_place_rec", "hbm", sort_bytes(M), "GB/s", PEAK_HBM),
         ("fwd_up", "k_up_band (P2M, M2M)", "hbm", up_bytes(lf, fi.mterms, N, cb, cb), "GB/s", PEAK_HBM),
         ("fwd_trans", "k_m2l k_down_trans", "mfma", trans_flops(lf, fi.nterms), T, pk),
         ("fwd_eval", "k_down_eval (forward)", "alu", eval_flops(lf, fi.nterms, M, N), T, pk),
-        ("inv_sort", "k_hist k_colscan k_scan_work k_place k_rank", "hbm", sort_bytes(N), "GB/s", PEAK_HBM),
+        ("inv_sort", "k_hist k_colscan k_scan_work k_place_rec k_leaf_order", "hbm", sort_bytes(N), "GB/s", PEAK_HBM),
         ("log_up", "k_up_band (log-sums)", "hbm", up_bytes(li, ii.log_mterms, N, 16, 8), "GB/s", PEAK_HBM),
         ("log_trans", "k_m2l k_down_trans (log-sums)", "mfma",
          trans_flops(li, ii.log_nterms, complex_data=False), T, PEAK_FP64),

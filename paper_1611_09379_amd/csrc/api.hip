@@ -923,17 +923,26 @@ static constexpr int SORT_LDS_BINS = 32768; // LDS histogram limit (128 KB)
 // batch of sorts can share launches.
 struct TreeJob {
     SortArgs a{};
-    bool lds_path = true, deterministic = false;
+    bool lds_path = true;
+    bool leaf_order = false;               // k_leaf_order after the placement
+    bool rank = false;                     // ... ordering every leaf (inverse)
+    OrderArgs ord{};
     int32_t *tsum = nullptr;               // tile sums of the multi-pass scan
-    SortedPt *gpt = nullptr;               // deterministic: records before ranking
     const WorkArgs *work = nullptr;        // work list built with the scan
 };
 
 static int prepare_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
                         bool deterministic, bool want_hit, bool records, TreeJob *J)
 {
+    // Sorted arrays by leaf (!records): the counting sort runs on the boxes
+    // of level l - ks (at most 2^ORDER_MAX_SHIFT leaves each, never below
+    // the subtree roots of level lr), with a small key range and one
+    // k_leaf_order workgroup per key for the leaves
+    J->leaf_order = !records;
+    J->rank = deterministic;
+    if (!records)
+        keyshift = std::max(0, std::min(P->l - P->lr, ORDER_MAX_SHIFT));
     const int nbins = 1 << (P->l - keyshift);
-    J->deterministic = deterministic;
     J->lds_path = nbins <= SORT_LDS_BINS;
     const bool lds_path = J->lds_path;
     SortArgs &a = J->a;
@@ -953,38 +962,62 @@ static int prepare_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
                  ? (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + 4095) / 4096))
                  : (int)std::max<int64_t>(1, std::min<int64_t>(128, (n + 8191) / 8192));
     a.chunk = lds_path ? (n + a.nblk - 1) / a.nblk : 0;
-    a.um = (int32_t *)tmp_alloc(P, n * 4);
-    a.uth = (double *)tmp_alloc(P, n * 8);
-    a.ukey = (int32_t *)tmp_alloc(P, n * 4);
+    // unsorted grid units and keys: only the global-atomic path stores them
+    a.um = lds_path ? nullptr : (int32_t *)tmp_alloc(P, n * 4);
+    a.uth = lds_path ? nullptr : (double *)tmp_alloc(P, n * 8);
+    a.ukey = lds_path ? nullptr : (int32_t *)tmp_alloc(P, n * 4);
     a.H = lds_path ? (int32_t *)tmp_alloc(P, (size_t)nbins * a.nblk * 4) : nullptr;
     a.tot = (int32_t *)tmp_alloc(P, (size_t)nbins * 4);
     a.cursor = lds_path ? nullptr : (int32_t *)tmp_alloc(P, (size_t)nbins * 4);
     J->tsum = (int32_t *)tmp_alloc(P, ((nbins + SCAN_TILE - 1) / SCAN_TILE) * 4);
-    if (deterministic)
-        J->gpt = (SortedPt *)tmp_alloc(P, n * sizeof(SortedPt));
-    // sorted points: (m, perm, th) records, or separate arrays plus every
-    // point's leaf (k_rank only reorders inside a leaf, so the leaves hold
-    // for the final order too)
+    // sorted points: (m, perm, th) records by key; or, by leaf, separate
+    // arrays plus every point's leaf, from records by key and their offsets
+    // (workspace) and a scratch copy for keys too large for LDS
+    const int64_t nleaf = int64_t(1) << P->l;
+    SortedPt *grec = nullptr, *gtmp = nullptr;
+    int32_t *koff = nullptr;
+    if (!records) {
+        grec = (SortedPt *)tmp_alloc(P, n * sizeof(SortedPt));
+        gtmp = (SortedPt *)tmp_alloc(P, n * sizeof(SortedPt));
+        koff = (int32_t *)tmp_alloc(P, ((size_t)nbins + 1) * 4);
+    }
     const bool sorted_ok =
         records ? alloc(P->spt, n * sizeof(SortedPt))
-                : (alloc(P->skey, n * 4) && alloc(P->sm, n * 4) && alloc(P->sth, n * 8) &&
-                   alloc(P->sperm, n * 4));
-    if (!a.um || !a.uth || !a.ukey || (lds_path && !a.H) || !a.tot || !J->tsum ||
-        (!lds_path && !a.cursor) || (deterministic && !J->gpt) ||
-        !sorted_ok || !alloc(P->off, ((size_t)nbins + 1) * 4) ||
+                : (grec && gtmp && koff && alloc(P->skey, n * 4) && alloc(P->sm, n * 4) &&
+                   alloc(P->sth, n * 8) && alloc(P->sperm, n * 4));
+    if ((!lds_path && (!a.um || !a.uth || !a.ukey || !a.cursor)) || (lds_path && !a.H) ||
+        !a.tot || !J->tsum || !sorted_ok ||
+        !alloc(P->off, ((size_t)(records ? nbins : nleaf) + 1) * 4) ||
         (want_hit && !alloc(P->hit, P->N * 4)))
         return fail(FN_ENOMEM, "workspace allocation failed (%lld points)", (long long)n);
     if ((nbins + SCAN_TILE - 1) / SCAN_TILE > 4096)
         return fail(FN_EINVAL, "tree too large for the scan (%d leaves)", nbins);
-    a.off = (int32_t *)P->off.p;
-    // deterministic: records first, ranked into sm, sth, sperm by k_rank
-    a.sm = (int32_t *)P->sm.p;
-    a.sth = (double *)P->sth.p;
-    a.sperm = (int32_t *)P->sperm.p;
-    a.skey = (int32_t *)P->skey.p;
-    a.spt = deterministic ? J->gpt : (SortedPt *)P->spt.p;
+    a.off = records ? (int32_t *)P->off.p : koff;
+    a.sm = nullptr;
+    a.sth = nullptr;
+    a.sperm = nullptr;
+    a.skey = nullptr;
+    a.spt = records ? (SortedPt *)P->spt.p : grec;
     a.hit = want_hit ? (int32_t *)P->hit.p : nullptr;
     a.flags = (int *)P->flags.p;
+    if (!records) {
+        OrderArgs &o = J->ord;
+        o.nkey = nbins;
+        o.ks = keyshift;
+        o.l = P->l;
+        o.N = P->N;
+        o.invN = 1.0 / (double)P->N;
+        o.rec = grec;
+        o.tmp = gtmp;
+        o.koff = koff;
+        o.off = (int32_t *)P->off.p;
+        o.dense_max = deterministic ? dense_max(P->N, P->l) : INT32_MAX;
+        o.sm = (int32_t *)P->sm.p;
+        o.sth = (double *)P->sth.p;
+        o.sperm = (int32_t *)P->sperm.p;
+        o.skey = (int32_t *)P->skey.p;
+        o.flags = (int *)P->flags.p;
+    }
     return FN_OK;
 }
 
@@ -1062,13 +1095,13 @@ static int launch_tree(fn_plan *P, const TreeJob &J, hipStream_t st)
                            a.spt);
     }
     HIPCHK(hipGetLastError());
-    if (J.deterministic) {
-        const int64_t nleaf = int64_t(1) << P->l;
-        hipLaunchKernelGGL(k_rank, dim3((nleaf + RANK_LEAVES - 1) / RANK_LEAVES), dim3(256),
-                           0, st, nleaf, (const SortedPt *)J.gpt, (const int32_t *)a.skey,
-                           (const int32_t *)a.off, dense_max(P->N, P->l),
-                           (int32_t *)P->sm.p, (double *)P->sth.p, (int32_t *)P->sperm.p,
-                           a.flags);
+    if (J.leaf_order) {
+        if (J.rank)
+            hipLaunchKernelGGL(k_leaf_order<true>, dim3((unsigned)J.ord.nkey),
+                               dim3(ORDER_THREADS), 0, st, J.ord);
+        else
+            hipLaunchKernelGGL(k_leaf_order<false>, dim3((unsigned)J.ord.nkey),
+                               dim3(ORDER_THREADS), 0, st, J.ord);
         HIPCHK(hipGetLastError());
     }
     return FN_OK;
@@ -1093,7 +1126,10 @@ static int build_tree(fn_plan *P, int64_t n, const double *y, int keyshift,
     if (rc)
         return rc;
     if (w) {
-        w->off = (const int32_t *)P->off.p;
+        // the work list reads the offsets of the sort's keys (level
+        // l - keyshift, at or below the subtree roots)
+        w->off = (const int32_t *)J.a.off;
+        w->sh = P->l - J.a.keyshift - P->lr;
         J.work = w;
     }
     const bool timed = g_timing.load() != 0;

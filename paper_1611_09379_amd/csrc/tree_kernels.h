@@ -737,13 +737,13 @@ __device__ __forceinline__ void canon_pos(int32_t &m, double &th)
 // Rank of point t (of the leaf [t0, t1)) among its leaf by position, from
 // canonical grid units gm(u), gth(u); ties (duplicates) are ordered by index,
 // so that the ranks stay a permutation of the leaf.
-template <typename GetM, typename GetTh>
+template <int UNROLL = 4, typename GetM, typename GetTh>
 __device__ __forceinline__ int32_t leaf_rank(int32_t t, int32_t t0, int32_t t1, GetM gm,
                                              GetTh gth, int32_t mt, double tht, bool *dup)
 {
     int32_t rank = 0;
     bool d = false;
-#pragma unroll 4
+#pragma unroll UNROLL
     for (int32_t u = t0; u < t1; ++u) {
         const int32_t mu = gm(u);
         const double tu = gth(u);
@@ -756,109 +756,192 @@ __device__ __forceinline__ int32_t leaf_rank(int32_t t, int32_t t0, int32_t t1, 
     return rank;
 }
 
-constexpr int RANK_LEAVES = 16;   // leaves per workgroup of k_rank
-constexpr int RANK_CAP = 1024;    // points of those leaves staged in LDS
+// Leaf order of the points of every key (a box of level l - ks, 2^ks
+// leaves): the placement of the counting sort leaves the records of a key
+// together in arbitrary order; one workgroup per key groups them by leaf,
+// writes the leaves' offsets and, with RANK, orders every leaf along the
+// circle (FLAG_DUP on two points at one position).  Outputs: sm, sth, sperm (grid units and input index
+// as placed) and skey (the leaf) in the final order, and off[0 .. 2^l].
+// A key of at most ORDER_CAP points is held in registers, grouped by LDS
+// cursors and ranked against its leaf staged in LDS; a larger key (a
+// clustered set) takes the same steps through `tmp` in global memory.
+constexpr int ORDER_THREADS = 512;
+constexpr int ORDER_PER = 4;                           // points per thread
+constexpr int ORDER_CAP = ORDER_THREADS * ORDER_PER;   // points of a key in LDS
+constexpr int ORDER_MAX_SHIFT = 6;                     // at most 64 leaves per key
 
-// Orders the points of every leaf by position (so the whole set is sorted
-// along the circle); two points at the same position raise FLAG_DUP.
-// Workgroup g takes leaves [16 g, 16 g + 16).  When their points fit, they
-// are staged in LDS with the leaves' offsets, and each thread ranks one
-// point against its leaf from LDS (its leaf read from the sorted keys); else
-// the points are read in place.  A leaf holding more
-// than dense_max points raises FLAG_DENSE and keeps its order (still a
-// permutation): the point set is far too clustered for the inverse, and
-// ranking it would cost the square of the leaf's size.
-__global__ void __launch_bounds__(256)
-    k_rank(int64_t nleaf, const SortedPt *gpt, const int32_t *gkey, const int32_t *off,
-           int32_t dense_max, int32_t *sm, double *sth, int32_t *sperm, int *flags)
+struct OrderArgs {
+    int64_t nkey;          // keys
+    int ks;                // leaves per key: 2^ks (ks <= ORDER_MAX_SHIFT)
+    int l;                 // leaves: 2^l = nkey 2^ks
+    int64_t N;
+    double invN;
+    const SortedPt *rec;   // records grouped by key, as placed
+    SortedPt *tmp;         // as many records of scratch (keys over ORDER_CAP)
+    const int32_t *koff;   // nkey + 1 key offsets
+    int32_t *off;          // out: 2^l + 1 leaf offsets
+    int32_t dense_max;     // larger leaves raise FLAG_DENSE and stay unranked
+    int32_t *sm;
+    double *sth;
+    int32_t *sperm;
+    int32_t *skey;
+    int *flags;
+};
+
+__device__ __forceinline__ int order_leaf(const OrderArgs &a, const SortedPt &q, int64_t leaf0)
 {
-    __shared__ int32_t lm[RANK_CAP], lperm[RANK_CAP]; // canonical m, input index
-    __shared__ double lth[RANK_CAP];                  // canonical th
-    __shared__ int32_t loff[RANK_LEAVES + 1];
-    const int64_t b0 = (int64_t)blockIdx.x * RANK_LEAVES;
-    const int64_t b1 = b0 + RANK_LEAVES < nleaf ? b0 + RANK_LEAVES : nleaf;
-    const int nb = (int)(b1 - b0);
-    const int32_t T0 = off[b0], T1 = off[b1];
-    bool dup = false;
-    auto finish = [&](int32_t t0, int32_t rank, int32_t mt, double tht, int32_t perm) {
-        const int32_t pos = t0 + rank;
-        sm[pos] = mt;
-        sth[pos] = tht;
-        sperm[pos] = perm;
-    };
-    if (T1 - T0 <= RANK_CAP) {
-        // staged in canonical form; bit 31 of lperm records that th was 1/2
-        // (the stored units are then m - 1, 1/2).  Every load of a batch is
-        // in flight at once (indices clamped).
-        const int32_t cnt = T1 - T0;
-        for (int32_t i0 = 0; i0 < cnt; i0 += 4 * 256) {
-            SortedPt q[4];
+    const int64_t b = box_of(q.m, q.th, a.l, a.N, a.invN) - leaf0;
+    const int nl = 1 << a.ks;
+    return b < 0 ? 0 : (b >= nl ? nl - 1 : (int)b); // (in range by construction)
+}
+
+template <bool RANK>
+__global__ void __launch_bounds__(ORDER_THREADS) k_leaf_order(OrderArgs a)
+{
+    __shared__ int32_t lm[ORDER_CAP]; // canonical grid units of the key's
+    __shared__ double lth[ORDER_CAP]; // points in leaf order
+    __shared__ int32_t lcnt[1 << ORDER_MAX_SHIFT], lbase[1 << ORDER_MAX_SHIFT],
+        lcur[1 << ORDER_MAX_SHIFT];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t k = blockIdx.x;
+    const int nl = 1 << a.ks;
+    const int64_t leaf0 = k << a.ks;
+    const int32_t S0 = a.koff[k], S1 = a.koff[k + 1], cnt = S1 - S0;
+    const bool fast = cnt <= ORDER_CAP;
+    if (tid < nl)
+        lcnt[tid] = 0;
+    __syncthreads();
+    SortedPt q[ORDER_PER];
+    int lf[ORDER_PER], c[ORDER_PER];
+    if (fast) {
+        // all loads in flight (indices clamped), then one LDS atomic per run
+        // of equal leaves in consecutive lanes; c = place inside the leaf
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int32_t i = i0 + (int32_t)threadIdx.x + k * 256;
-                q[k] = gpt[T0 + (i < cnt ? i : cnt - 1)];
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int32_t i = i0 + (int32_t)threadIdx.x + k * 256;
-                if (i < cnt) {
-                    const bool half = q[k].th == 0.5;
-                    lperm[i] = q[k].perm | (half ? (int32_t)0x80000000u : 0);
-                    canon_pos(q[k].m, q[k].th);
-                    lm[i] = q[k].m;
-                    lth[i] = q[k].th;
-                }
-            }
+        for (int u = 0; u < ORDER_PER; ++u) {
+            const int i = tid + u * ORDER_THREADS;
+            if (u * ORDER_THREADS < cnt)
+                q[u] = a.rec[S0 + (i < cnt ? i : cnt - 1)];
         }
-        for (int i = threadIdx.x; i <= nb; i += 256)
-            loff[i] = off[b0 + i] - T0;
-        __syncthreads();
-        auto gm = [&](int32_t u) { return lm[u]; };
-        auto gth = [&](int32_t u) { return lth[u]; };
-        for (int32_t i = threadIdx.x; i < T1 - T0; i += 256) {
-            const int lo = (int)(gkey[T0 + i] - b0); // the point's leaf in the group
-            const int32_t t0 = loff[lo], t1 = loff[lo + 1];
-            int32_t rank;
-            if (t1 - t0 > dense_max) {
-                if (i == t0)
-                    atomicOr(flags, FLAG_DENSE);
-                rank = i - t0; // no ranking
-            } else {
-                rank = leaf_rank(i, t0, t1, gm, gth, lm[i], lth[i], &dup);
+#pragma unroll
+        for (int u = 0; u < ORDER_PER; ++u) {
+            const int i = tid + u * ORDER_THREADS;
+            lf[u] = -1;
+            c[u] = 0;
+            if (u * ORDER_THREADS < cnt) { // uniform over the workgroup
+                lf[u] = i < cnt ? order_leaf(a, q[u], leaf0) : -1;
+                int start, len;
+                key_runs(lf[u], &start, &len);
+                int32_t base = 0;
+                if (len && lf[u] >= 0)
+                    base = atomicAdd(&lcnt[lf[u]], len);
+                base = __shfl(base, start);
+                c[u] = base + (lane - start);
             }
-            const int32_t pv = lperm[i];
-            const bool half = pv < 0; // the stored (not canonical) units
-            finish(t0 + T0, rank, half ? lm[i] - 1 : lm[i], half ? 0.5 : lth[i],
-                   pv & 0x7fffffff);
         }
     } else {
-        auto gm = [&](int32_t u) {
-            SortedPt q = gpt[u];
-            canon_pos(q.m, q.th);
-            return q.m;
-        };
-        auto gth = [&](int32_t u) {
-            SortedPt q = gpt[u];
-            canon_pos(q.m, q.th);
-            return q.th;
-        };
-        for (int32_t t = T0 + threadIdx.x; t < T1; t += 256) {
-            const int32_t b = gkey[t];
-            const int32_t t0 = off[b], t1 = off[b + 1];
-            const SortedPt q = gpt[t];
-            int32_t rank;
-            if (t1 - t0 > dense_max) {
-                if (t == t0)
-                    atomicOr(flags, FLAG_DENSE);
-                rank = t - t0; // no ranking
-            } else {
-                rank = leaf_rank(t, t0, t1, gm, gth, gm(t), gth(t), &dup);
+        for (int32_t i = tid; i < cnt; i += ORDER_THREADS)
+            atomicAdd(&lcnt[order_leaf(a, a.rec[S0 + i], leaf0)], 1);
+    }
+    __syncthreads();
+    // leaf offsets: one wavefront scans the (at most 64) leaf counts
+    if (tid < 64) {
+        const int32_t v = tid < nl ? lcnt[tid] : 0;
+        int32_t x = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t t = __shfl_up(x, d);
+            if (lane >= d)
+                x += t;
+        }
+        if (tid < nl) {
+            lbase[tid] = x - v;
+            lcur[tid] = x - v;
+            a.off[leaf0 + tid] = S0 + x - v;
+            if (v > a.dense_max)
+                atomicOr(a.flags, FLAG_DENSE);
+        }
+        if (tid == 0 && k == a.nkey - 1)
+            a.off[(int64_t)a.nkey << a.ks] = S1;
+    }
+    __syncthreads();
+    bool dup = false;
+    auto emit = [&](const SortedPt &p, int32_t pos, int f) {
+        a.sm[pos] = p.m;
+        a.sth[pos] = p.th;
+        a.sperm[pos] = p.perm;
+        a.skey[pos] = (int32_t)(leaf0 + f);
+    };
+    if (fast) {
+        if (RANK) {
+#pragma unroll
+            for (int u = 0; u < ORDER_PER; ++u)
+                if (lf[u] >= 0) {
+                    int32_t m = q[u].m;
+                    double th = q[u].th;
+                    canon_pos(m, th);
+                    lm[lbase[lf[u]] + c[u]] = m;
+                    lth[lbase[lf[u]] + c[u]] = th;
+                }
+            __syncthreads();
+        }
+        auto gm = [&](int32_t s) { return lm[s]; };
+        auto gth = [&](int32_t s) { return lth[s]; };
+#pragma unroll
+        for (int u = 0; u < ORDER_PER; ++u)
+            if (lf[u] >= 0) {
+                const int32_t t0 = lbase[lf[u]], t1 = t0 + lcnt[lf[u]];
+                int32_t rank = c[u];
+                if (RANK && t1 - t0 <= a.dense_max) {
+                    int32_t m = q[u].m;
+                    double th = q[u].th;
+                    canon_pos(m, th);
+                    rank = leaf_rank(t0 + c[u], t0, t1, gm, gth, m, th, &dup);
+                }
+                emit(q[u], S0 + t0 + rank, lf[u]);
             }
-            finish(t0, rank, q.m, q.th, q.perm);
+    } else {
+        // grouped by leaf into tmp (or straight to the output when no
+        // ranking is asked for), then ranked from tmp
+        for (int32_t i = tid; i < cnt; i += ORDER_THREADS) {
+            const SortedPt p = a.rec[S0 + i];
+            const int f = order_leaf(a, p, leaf0);
+            const int32_t slot = atomicAdd(&lcur[f], 1);
+            if (RANK)
+                a.tmp[S0 + slot] = p;
+            else
+                emit(p, S0 + slot, f);
+        }
+        if (RANK) {
+            __threadfence_block();
+            __syncthreads();
+            const SortedPt *g = a.tmp + S0;
+            auto gm = [&](int32_t s) {
+                SortedPt p = g[s];
+                canon_pos(p.m, p.th);
+                return p.m;
+            };
+            auto gth = [&](int32_t s) {
+                SortedPt p = g[s];
+                canon_pos(p.m, p.th);
+                return p.th;
+            };
+            for (int32_t t = tid; t < cnt; t += ORDER_THREADS) {
+                const SortedPt p = g[t];
+                const int f = order_leaf(a, p, leaf0);
+                const int32_t t0 = lbase[f], t1 = t0 + lcnt[f];
+                int32_t rank = t - t0;
+                if (t1 - t0 <= a.dense_max) {
+                    int32_t m = p.m;
+                    double th = p.th;
+                    canon_pos(m, th);
+                    rank = leaf_rank<1>(t, t0, t1, gm, gth, m, th, &dup);
+                }
+                emit(p, S0 + t0 + rank, f);
+            }
         }
     }
     if (dup)
-        atomicOr(flags, FLAG_DUP);
+        atomicOr(a.flags, FLAG_DUP);
 }
 
 // Work list of the downward pass (one workgroup): for every subtree root R

@@ -29,6 +29,26 @@ def test_inv_fp64_full(N, amp):
     assert err < 1e-12
 
 
+@pytest.mark.parametrize("lmax", [6, 7, 8])
+def test_inv_explicit_depths(lmax):
+    """Shallow trees put more points in one sort key (a box of 16 leaves):
+    4096 at depth 6, about 2048 at depth 7 (on both sides of the limit),
+    1024 at depth 8.  Above 2048 points the leaf order goes through global
+    memory instead of LDS, and the ranks it forms still have to give the
+    oracle's f (Eq. p8 signs and self-exclusion)."""
+    N = 1 << 14
+    y, c = workloads.inverse_case(N, 0.35, seed=4)
+    rng = np.random.default_rng(2)
+    g = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    plan = fn.Plan.inverse(dev(y), 1e-12, fn.FN_C128, lmax=lmax)
+    assert plan.info().lmax == lmax
+    f = host(plan(dev(g)))
+    plan.destroy()
+    err = rel_l2(f, oracle.inv(N, y, g))
+    say("lmax", lmax, "rel l2", err)
+    assert err < 1e-12
+
+
 @pytest.mark.parametrize("N", [1, 2, 3, 5, 16, 100])
 def test_inv_tiny(N):
     y, c = workloads.inverse_case(N, 0.3, seed=N)
