@@ -377,17 +377,17 @@ __device__ __forceinline__ void p2m_chunk(const UpArgs<R, V> &a, const cx<R> *fu
 // squarings fewer than from v); each moment still sums its sources in
 // order.  Binary32 sums run over blocks of P2M_FOLD sources, each block
 // added into a binary64 total.
-template <typename R, typename V, int KER>
+template <typename R, typename V, int KER, int CH>
 __device__ __forceinline__ void p2m_staged(const R *sv, const R *sv4, const cx<R> *sw, int j0,
                                            int j1, int m0, double r, V *acc)
 {
-    static_assert(CHS % 4 == 0, "chunks start at multiples of 4");
+    static_assert(CH % 4 == 0, "chunks start at multiples of 4");
     using W = typename wide<V>::type;
     constexpr int FOLD = sizeof(R) == 8 ? INT32_MAX : P2M_FOLD;
-    W tot[CHS];
+    W tot[CH];
     for (int jb = j0; jb < j1;) {
         const int je = (j1 - jb > FOLD) ? jb + FOLD : j1;
-        for (int c = 0; c < CHS; ++c)
+        for (int c = 0; c < CH; ++c)
             acc[c] = vzero<V>();
         int j = jb;
         for (; j + 4 <= je; j += 4) {
@@ -412,7 +412,7 @@ __device__ __forceinline__ void p2m_staged(const R *sv, const R *sv4, const cx<R
                 }
             }
 #pragma unroll
-            for (int c = 0; c < CHS; ++c) {
+            for (int c = 0; c < CH; ++c) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     vfma(acc[c], pw[u], w[u]);
@@ -428,13 +428,13 @@ __device__ __forceinline__ void p2m_staged(const R *sv, const R *sv4, const cx<R
                 w = sw[j];
             else
                 w = R(1);
-            for (int c = 0; c < CHS; ++c) {
+            for (int c = 0; c < CH; ++c) {
                 vfma(acc[c], pw, w);
                 pw *= v;
             }
         }
         if constexpr (sizeof(R) != 8) {
-            for (int c = 0; c < CHS; ++c) {
+            for (int c = 0; c < CH; ++c) {
                 if (jb == j0)
                     tot[c] = vzero<W>();
                 vacc(tot[c], acc[c]);
@@ -443,19 +443,52 @@ __device__ __forceinline__ void p2m_staged(const R *sv, const R *sv4, const cx<R
         jb = je;
     }
     if (j1 <= j0) {
-        for (int c = 0; c < CHS; ++c)
+        for (int c = 0; c < CH; ++c)
             acc[c] = vzero<V>();
     } else if constexpr (sizeof(R) != 8) {
-        for (int c = 0; c < CHS; ++c)
+        for (int c = 0; c < CH; ++c)
             acc[c] = vnarrow<V>(tot[c]);
     }
     if constexpr (KER == KER_LOG) {
-        for (int c = 0; c < CHS; ++c) {
+        for (int c = 0; c < CH; ++c) {
             const int m = m0 + c;
             if ((m & 1) == 0)
                 acc[c] -= (R)(2.0 * r / (double)(m + 1));
         }
     }
+}
+
+// The staged P2M of a band's nbot leaves, written to the band's first level
+// buffer and to the multipoles g: work items (leaf, CH consecutive
+// moments).  CH = 8 when the items still fill three quarters of the
+// workgroup (a source's starting power then serves 8 moments instead of 4),
+// else 4.
+template <typename R, typename V, int KER, int PU, int CH>
+__device__ __forceinline__ void p2m_staged_items(const R *sv, const R *sv4, const cx<R> *sw,
+                                                 const int32_t *soff, int nbot, double r,
+                                                 R *buf0, int RS, V *g, int64_t first)
+{
+    constexpr int nch = PU / CH;
+    for (int idx = threadIdx.x; idx < nbot * nch; idx += BLOCK) {
+        const int i = idx / nch, ch = idx - i * nch;
+        V acc[CH];
+        p2m_staged<R, V, KER, CH>(sv, sv4, sw, soff[i], soff[i + 1], ch * CH, r, acc);
+        for (int c = 0; c < CH; ++c) {
+            st_coef<R, V>(buf0, RS, i, ch * CH + c, acc[c]);
+            g[(first + i) * PU + ch * CH + c] = acc[c];
+        }
+    }
+}
+
+template <typename R, typename V, int KER, int PU>
+__device__ __forceinline__ void p2m_staged_band(const R *sv, const R *sv4, const cx<R> *sw,
+                                                const int32_t *soff, int nbot, double r,
+                                                R *buf0, int RS, V *g, int64_t first)
+{
+    if (PU % 8 == 0 && nbot * (PU / 8) >= 3 * BLOCK / 4)
+        p2m_staged_items<R, V, KER, PU, 8>(sv, sv4, sw, soff, nbot, r, buf0, RS, g, first);
+    else
+        p2m_staged_items<R, V, KER, PU, 4>(sv, sv4, sw, soff, nbot, r, buf0, RS, g, first);
 }
 
 // P2M on the matrix cores for uniform sources with B points in every leaf:
@@ -698,17 +731,9 @@ __device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk, con
                     }
                 }
                 __syncthreads();
-                const double r = ldexp((double)a.N, -(a.l + 1));
-                constexpr int nch = PU / CHS;
-                for (int idx = tid; idx < nbot * nch; idx += BLOCK) {
-                    const int i = idx / nch, ch = idx - i * nch;
-                    V acc[CHS];
-                    p2m_staged<R, V, KER>(sv, sv4, sw, soff[i], soff[i + 1], ch * CHS, r, acc);
-                    for (int c = 0; c < CHS; ++c) {
-                        st_coef<R, V>(buf0, RS, i, ch * CHS + c, acc[c]);
-                        g[(first + i) * PU + ch * CHS + c] = acc[c];
-                    }
-                }
+                p2m_staged_band<R, V, KER, PU>(sv, sv4, sw, soff, nbot,
+                                               ldexp((double)a.N, -(a.l + 1)), buf0, RS, g,
+                                               first);
                 done = true;
             }
         }
@@ -752,17 +777,9 @@ __device__ __forceinline__ void up_band_body(const UpArgs<R, V> &a, int blk, con
                         put(ib, wb);
                 }
                 __syncthreads();
-                const double r = ldexp((double)a.N, -(a.l + 1));
-                constexpr int nch = PU / CHS;
-                for (int idx = tid; idx < nbot * nch; idx += BLOCK) {
-                    const int i = idx / nch, ch = idx - i * nch;
-                    V acc[CHS];
-                    p2m_staged<R, V, KER>(sv, sv4, sw, soff[i], soff[i + 1], ch * CHS, r, acc);
-                    for (int c = 0; c < CHS; ++c) {
-                        st_coef<R, V>(buf0, RS, i, ch * CHS + c, acc[c]);
-                        g[(first + i) * PU + ch * CHS + c] = acc[c];
-                    }
-                }
+                p2m_staged_band<R, V, KER, PU>(sv, sv4, sw, soff, nbot,
+                                               ldexp((double)a.N, -(a.l + 1)), buf0, RS, g,
+                                               first);
                 done = true;
             }
         }

@@ -760,14 +760,22 @@ __device__ __forceinline__ int32_t leaf_rank(int32_t t, int32_t t0, int32_t t1, 
 // leaves): the placement of the counting sort leaves the records of a key
 // together in arbitrary order; one workgroup per key groups them by leaf,
 // writes the leaves' offsets and, with RANK, orders every leaf along the
-// circle (FLAG_DUP on two points at one position).  Outputs: sm, sth, sperm (grid units and input index
-// as placed) and skey (the leaf) in the final order, and off[0 .. 2^l].
-// A key of at most ORDER_CAP points is held in registers, grouped by LDS
-// cursors and ranked against its leaf staged in LDS; a larger key (a
-// clustered set) takes the same steps through `tmp` in global memory.
+// circle (FLAG_DUP on two points at one position).  Outputs: sm, sth,
+// sperm (grid units and input index as placed) and skey (the leaf) in the
+// final order, and off[0 .. 2^l].
+// A key of at most ORDER_CAP points is held in registers.  Its order along
+// the circle is a counting sort by canonical grid cell m (at most
+// ORDER_CELLS cells: a jittered grid puts about one point in each), then
+// the order by th inside a cell; the leaves, whose boundaries are
+// positions, come out contiguous in that order.  A key spanning more cells
+// ranks each point against its leaf staged in LDS, and a key of more
+// points (a clustered set) takes those steps through `tmp` in global
+// memory.
 constexpr int ORDER_THREADS = 512;
+constexpr int ORDER_WAVES = ORDER_THREADS / 64;
 constexpr int ORDER_PER = 4;                           // points per thread
 constexpr int ORDER_CAP = ORDER_THREADS * ORDER_PER;   // points of a key in LDS
+constexpr int ORDER_CELLS = 2048;                      // grid cells of a key in LDS
 constexpr int ORDER_MAX_SHIFT = 6;                     // at most 64 leaves per key
 
 struct OrderArgs {
@@ -795,13 +803,47 @@ __device__ __forceinline__ int order_leaf(const OrderArgs &a, const SortedPt &q,
     return b < 0 ? 0 : (b >= nl ? nl - 1 : (int)b); // (in range by construction)
 }
 
+// Exclusive scan of one value per thread over a workgroup of NW wavefronts
+// (ws: 2 NW words of LDS); *total: the sum of all values.
+template <int NW>
+__device__ __forceinline__ int32_t block_scan_waves(int32_t x, int32_t *ws, int32_t *total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t v = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t t = __shfl_up(v, d);
+        if (lane >= d)
+            v += t;
+    }
+    if (lane == 63)
+        ws[wv] = v;
+    __syncthreads();
+    if (wv == 0) {
+        int32_t u = lane < NW ? ws[lane] : 0;
+#pragma unroll
+        for (int d = 1; d < NW; d <<= 1) {
+            const int32_t t = __shfl_up(u, d);
+            if (lane >= d)
+                u += t;
+        }
+        if (lane < NW)
+            ws[NW + lane] = u;
+    }
+    __syncthreads();
+    *total = ws[2 * NW - 1];
+    return (wv ? ws[NW + wv - 1] : 0) + v - x;
+}
+
 template <bool RANK>
 __global__ void __launch_bounds__(ORDER_THREADS) k_leaf_order(OrderArgs a)
 {
-    __shared__ int32_t lm[ORDER_CAP]; // canonical grid units of the key's
-    __shared__ double lth[ORDER_CAP]; // points in leaf order
+    __shared__ int32_t lm[ORDER_CAP]; // canonical grid units (by leaf) or
+    __shared__ double lth[ORDER_CAP]; // th (by cell) of the key's points
+    __shared__ int32_t ccnt[ORDER_CELLS + 1]; // points per cell, then offsets
     __shared__ int32_t lcnt[1 << ORDER_MAX_SHIFT], lbase[1 << ORDER_MAX_SHIFT],
         lcur[1 << ORDER_MAX_SHIFT];
+    __shared__ int32_t ws[2 * ORDER_WAVES], mrange[2];
     const int tid = threadIdx.x, lane = tid & 63;
     const int64_t k = blockIdx.x;
     const int nl = 1 << a.ks;
@@ -810,6 +852,14 @@ __global__ void __launch_bounds__(ORDER_THREADS) k_leaf_order(OrderArgs a)
     const bool fast = cnt <= ORDER_CAP;
     if (tid < nl)
         lcnt[tid] = 0;
+    if (RANK) {
+        for (int i = tid; i <= ORDER_CELLS; i += ORDER_THREADS)
+            ccnt[i] = 0;
+        if (tid == 0) {
+            mrange[0] = INT32_MAX;
+            mrange[1] = INT32_MIN;
+        }
+    }
     __syncthreads();
     SortedPt q[ORDER_PER];
     int lf[ORDER_PER], c[ORDER_PER];
@@ -822,6 +872,7 @@ __global__ void __launch_bounds__(ORDER_THREADS) k_leaf_order(OrderArgs a)
             if (u * ORDER_THREADS < cnt)
                 q[u] = a.rec[S0 + (i < cnt ? i : cnt - 1)];
         }
+        int32_t mlo = INT32_MAX, mhi = INT32_MIN;
 #pragma unroll
         for (int u = 0; u < ORDER_PER; ++u) {
             const int i = tid + u * ORDER_THREADS;
@@ -836,6 +887,25 @@ __global__ void __launch_bounds__(ORDER_THREADS) k_leaf_order(OrderArgs a)
                     base = atomicAdd(&lcnt[lf[u]], len);
                 base = __shfl(base, start);
                 c[u] = base + (lane - start);
+                if (RANK && lf[u] >= 0) {
+                    int32_t m = q[u].m;
+                    double th = q[u].th;
+                    canon_pos(m, th);
+                    mlo = m < mlo ? m : mlo;
+                    mhi = m > mhi ? m : mhi;
+                }
+            }
+        }
+        if (RANK) { // the key's range of canonical cells
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) {
+                const int32_t lo = __shfl_xor(mlo, d), hi = __shfl_xor(mhi, d);
+                mlo = lo < mlo ? lo : mlo;
+                mhi = hi > mhi ? hi : mhi;
+            }
+            if (lane == 0 && mlo <= mhi) {
+                atomicMin(&mrange[0], mlo);
+                atomicMax(&mrange[1], mhi);
             }
         }
     } else {
@@ -863,6 +933,20 @@ __global__ void __launch_bounds__(ORDER_THREADS) k_leaf_order(OrderArgs a)
         if (tid == 0 && k == a.nkey - 1)
             a.off[(int64_t)a.nkey << a.ks] = S1;
     }
+    const int32_t m0 = RANK ? mrange[0] : 0;
+    const int64_t ncell = RANK ? (int64_t)mrange[1] - mrange[0] + 1 : 0;
+    const bool cells = RANK && fast && cnt > 0 && ncell <= ORDER_CELLS;
+    int cc[ORDER_PER];
+    if (cells) {
+#pragma unroll
+        for (int u = 0; u < ORDER_PER; ++u)
+            if (lf[u] >= 0) {
+                int32_t m = q[u].m;
+                double th = q[u].th;
+                canon_pos(m, th);
+                cc[u] = atomicAdd(&ccnt[m - m0], 1);
+            }
+    }
     __syncthreads();
     bool dup = false;
     auto emit = [&](const SortedPt &p, int32_t pos, int f) {
@@ -871,7 +955,56 @@ __global__ void __launch_bounds__(ORDER_THREADS) k_leaf_order(OrderArgs a)
         a.sperm[pos] = p.perm;
         a.skey[pos] = (int32_t)(leaf0 + f);
     };
-    if (fast) {
+    if (cells) {
+        // the cells' offsets (exclusive scan), the points' th staged by
+        // cell, then each point's order inside its cell
+        constexpr int CPT = (ORDER_CELLS + ORDER_THREADS - 1) / ORDER_THREADS;
+        int32_t v[CPT], sum = 0;
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            const int i = tid * CPT + e;
+            v[e] = i < ncell ? ccnt[i] : 0;
+            sum += v[e];
+        }
+        int32_t total;
+        int32_t run = block_scan_waves<ORDER_WAVES>(sum, ws, &total);
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            const int i = tid * CPT + e;
+            if (i < ncell)
+                ccnt[i] = run;
+            run += v[e];
+        }
+        if (tid == 0)
+            ccnt[ncell] = total;
+        __syncthreads();
+        int32_t slot[ORDER_PER];
+#pragma unroll
+        for (int u = 0; u < ORDER_PER; ++u)
+            if (lf[u] >= 0) {
+                int32_t m = q[u].m;
+                double th = q[u].th;
+                canon_pos(m, th);
+                slot[u] = ccnt[m - m0] + cc[u];
+                lth[slot[u]] = th;
+            }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < ORDER_PER; ++u)
+            if (lf[u] >= 0) {
+                int32_t m = q[u].m;
+                double th = q[u].th;
+                canon_pos(m, th);
+                const int32_t b0 = ccnt[m - m0], b1 = ccnt[m - m0 + 1];
+                int32_t rank = 0;
+                for (int32_t s = b0; s < b1; ++s) {
+                    const double ts = lth[s];
+                    rank += (ts < th || (ts == th && s < slot[u])) ? 1 : 0;
+                    dup |= ts == th && s != slot[u];
+                }
+                emit(q[u], S0 + b0 + rank, lf[u]);
+            }
+    } else if (fast) {
         if (RANK) {
 #pragma unroll
             for (int u = 0; u < ORDER_PER; ++u)
