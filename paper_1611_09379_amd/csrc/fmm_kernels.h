@@ -570,47 +570,55 @@ __device__ __forceinline__ void p2m_mfma(const UpArgs<R, V> &a, int64_t first,
 // M2M of one level inside LDS: np parents from 2 np children (rows of cur),
 // written to nxt (LDS) and g (global, PU per box).  Each wave takes 16-row
 // tiles of the parents' moments; its operator tile sits in registers.  The
-// operator is lower triangular: row tile rt takes no moment of order
-// 16 (rt + 1) or more, so its loop has KE = 4 (rt + 1) steps, a constant of
-// the instantiation: every operand load of a column tile is then issued
-// before the first matrix instruction (with a bound known only at run time
-// each step waited for its own load).
+// columns are (child, component): the right child's operator follows from
+// the left one by the signs (-1)^m on the input and (-1)^n on the output,
+// so both children go through one product and meet in the left child's
+// lane (the right child's column is NC lanes up).  A level of few parents
+// then fills twice as many columns of a tile as with one product per
+// child.  The operator is lower triangular: row tile rt takes no moment of
+// order 16 (rt + 1) or more, so its loop has KE = 4 (rt + 1) steps, a
+// constant of the instantiation: every operand load of a column tile is
+// issued before the first matrix instruction, and even and odd steps feed
+// two accumulator chains.
 template <typename R, typename V, int PU, int KE>
 __device__ __forceinline__ void m2m_tile(const R (&am)[PU / 4], int rt, int ct0, int ctstep,
                                          int lane, int np, const R *cur, R *nxt, int RS, V *g)
 {
     constexpr int NC = ncomp<V>::value;
     using A = typename acc_t<R>::type;
-    const int nct = (NC * np + 15) / 16;
+    const int nq = 2 * np;
+    const int nct = (NC * nq + 15) / 16;
     for (int ct = ct0; ct < nct; ct += ctstep) {
         const int j = 16 * ct + (lane & 15);
-        const int p = j / NC, c = j % NC;
-        const bool valid = p < np;
-        const int pc = valid ? p : 0;
-        const R *cl = cur + (size_t)(2 * pc) * RS + c;
-        const R *cr = cl + RS;
-        R bl[KE], br[KE];
+        const int q = j / NC, c = j % NC;
+        const bool valid = q < nq, right = (q & 1) != 0;
+        const R *cq = cur + (size_t)(valid ? q : 0) * RS + c;
+        R b[KE];
 #pragma unroll
         for (int ks = 0; ks < KE; ++ks) {
             const int m = 4 * ks + (lane >> 4);
-            bl[ks] = cl[m * NC];
-            br[ks] = cr[m * NC];
+            b[ks] = cq[m * NC];
         }
-        A al = {0, 0, 0, 0}, ar = {0, 0, 0, 0};
+        A acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
 #pragma unroll
         for (int ks = 0; ks < KE; ++ks) {
             const int m = 4 * ks + (lane >> 4);
-            R vl = valid ? bl[ks] : R(0), vr = valid ? br[ks] : R(0);
-            if (m & 1)
-                vr = -vr;
-            al = mma(am[ks], vl, al);
-            ar = mma(am[ks], vr, ar);
+            R v = valid ? b[ks] : R(0);
+            if (right && (m & 1))
+                v = -v;
+            if (ks & 1)
+                acc1 = mma(am[ks], v, acc1);
+            else
+                acc0 = mma(am[ks], v, acc0);
         }
-        if (valid) {
+        const int p = q >> 1;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < 4; ++r) {
+            const R sl = acc0[r] + acc1[r];
+            const R sr = __shfl_down(sl, NC);
+            if (valid && !right) {
                 const int n = 16 * rt + out_row<R>(lane, r);
-                const R v = al[r] + ((n & 1) ? -ar[r] : ar[r]);
+                const R v = sl + ((n & 1) ? -sr : sr);
                 nxt[(size_t)p * RS + n * NC + c] = v;
                 reinterpret_cast<R *>(g)[((size_t)p * PU + n) * NC + c] = v;
             }
