@@ -34,26 +34,26 @@ PEAK_HBM = 8.0e12        # B/s
 # kernel (fetch x2.000, write x1.000).  Valid only for the kernel sources
 # they were taken on: any change to them turns the figure back into null
 # until the counters are taken again.
-TRAFFIC_SRC_SHA256 = "df6dc466dba19088f794a68c1ca0ef34fe50c2cbed3c830414ecbf56d44a0136"
+TRAFFIC_SRC_SHA256 = "f35be2b6c8f3d3a231acca288d5c7c6e026458b280fb51e9b0b49460062dc89c"
 TRAFFIC = {
-    "fwd_eval": 97701201,
-    "fwd_eval_mixed": 83459977,
-    "fwd_sort": 43260992,
-    "fwd_trans": 64102565,
-    "fwd_trans_mixed": 16168591,
-    "fwd_up": 43046109,
-    "fwd_up_mixed": 17252203,
-    "inv_eval": 80840633,
-    "inv_eval_mixed": 50438177,
-    "inv_sort": 149824525,
-    "inv_trans": 127785659,
-    "inv_trans_mixed": 32159989,
-    "inv_up": 142010895,
-    "inv_up_mixed": 81897854,
-    "log_eval": 58137232,
-    "log_trans": 64386671,
-    "log_up": 43733339,
-    "log_up_mixed": 34945256,
+    "fwd_eval": 98108347,
+    "fwd_eval_mixed": 83496503,
+    "fwd_sort": 43198233,
+    "fwd_trans": 64106987,
+    "fwd_trans_mixed": 16169026,
+    "fwd_up": 43069235,
+    "fwd_up_mixed": 17254794,
+    "inv_eval": 80831641,
+    "inv_eval_mixed": 50438550,
+    "inv_sort": 87198624,
+    "inv_trans": 127789969,
+    "inv_trans_mixed": 32160461,
+    "inv_up": 142067037,
+    "inv_up_mixed": 81920039,
+    "log_eval": 58107486,
+    "log_trans": 64382847,
+    "log_up": 43753418,
+    "log_up_mixed": 34979643,
 }
 # phase keys of one step (ms): plan wall time, then each measured phase
 PHASES = ("fwd_plan_ms", "fwd_sort_ms", "fwd_up_ms", "fwd_trans_ms", "fwd_eval_ms",
