@@ -47,6 +47,23 @@ def test_adjoint_full(N, M, dist, dtype, eps):
     assert err < eps
 
 
+@pytest.mark.parametrize("lmax", [5, 8])
+def test_adjoint_large_keys(lmax):
+    """At depth 5 the sort's keys (boxes of 8 leaves) hold 4096 points each,
+    above the 2048 that the leaf grouping keeps in registers: it then runs
+    through global memory.  Depth 8 keeps them in registers.  Both against
+    the oracle at the binary64 tolerance."""
+    N, M = 4096, 1 << 14
+    y, g = adj_case(N, M, "uniform", seed=17)
+    plan = fn.Plan.adjoint(N, dev(y), 1e-12, fn.FN_C128, lmax=lmax)
+    assert plan.info().lmax == lmax
+    f = host(plan(dev(g)))
+    plan.destroy()
+    err = rel_l2(f, oracle.adj(N, y, g))
+    say("lmax", lmax, "rel l2", err)
+    assert err < 1e-12
+
+
 @pytest.mark.parametrize("dtype,eps", PATHS)
 def test_adjoint_grid_points_and_duplicates(dtype, eps):
     """Points on grid points contribute g_j to f_m alone (conj(K_jk) =
