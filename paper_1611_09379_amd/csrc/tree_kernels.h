@@ -717,15 +717,11 @@ __global__ void k_scatter(int64_t M, const int32_t *um, const double *uth,
     }
 }
 
-// Orders the points of every leaf by position (so the whole set is sorted
-// along the circle); two points at the same position raise FLAG_DUP.
-// A leaf holding more than dense_max points raises FLAG_DENSE and keeps
-// its order (still a permutation): the point set is far too clustered for
-// the inverse, and ranking it would cost the square of the leaf's size.
-// Positions s = m + th are compared in the canonical form th in [-1/2, 1/2)
-// (th = 1/2 becomes m + 1, -1/2): the intervals [m - 1/2, m + 1/2) are
-// disjoint, so s_u < s_t exactly when (m_u, th_u) < (m_t, th_t)
-// lexicographically.
+// The order along the circle inside each leaf (the inverse): positions
+// s = m + th are compared in the canonical form th in [-1/2, 1/2) (th = 1/2
+// becomes m + 1, -1/2): the intervals [m - 1/2, m + 1/2) are disjoint, so
+// s_u < s_t exactly when (m_u, th_u) < (m_t, th_t) lexicographically.  Two
+// points at the same position raise FLAG_DUP.
 __device__ __forceinline__ void canon_pos(int32_t &m, double &th)
 {
     if (th == 0.5) {
@@ -736,7 +732,10 @@ __device__ __forceinline__ void canon_pos(int32_t &m, double &th)
 
 // Rank of point t (of the leaf [t0, t1)) among its leaf by position, from
 // canonical grid units gm(u), gth(u); ties (duplicates) are ordered by index,
-// so that the ranks stay a permutation of the leaf.
+// so that the ranks stay a permutation of the leaf.  (Used where a key's
+// points do not fit the counting sort by cell; a leaf of more than the
+// dense limit is left unranked there: the point set is far too clustered
+// for the inverse, which reports FLAG_DENSE.)
 template <int UNROLL = 4, typename GetM, typename GetTh>
 __device__ __forceinline__ int32_t leaf_rank(int32_t t, int32_t t0, int32_t t1, GetM gm,
                                              GetTh gth, int32_t mt, double tht, bool *dup)
